@@ -1,0 +1,175 @@
+/*
+ * otf.h -- C ABI of the octree TV-L1 range-data fusion library (libotf.so,
+ * HIP for gfx950 / MI355X).
+ *
+ * Method: Kehl, Holl, Tombari, Ilic, Navab, "An Octree-Based Approach towards
+ * Efficient Variational Range Data Fusion", BMVC 2016. Range maps become
+ * per-view truncated signed distance octrees (Sec. 3.1, Eq. 1-2); their union
+ * seeds one fused octree whose leaf values minimise the normalised TV-L1
+ * energy (Sec. 3.2, Eq. 3 and Eq. 5) while leaves split and join as the
+ * solution evolves (Sec. 3.2, split and join rules). The minimiser is the
+ * primal-dual scheme the paper names as an alternative solver (Sec. 5):
+ * dual ascent with projection onto the unit ball, divergence, and a per-leaf
+ * generalised shrinkage (weighted median) over the leaf's observations.
+ *
+ * Conventions for every entry point:
+ *   - returns otf_status; no C++ exception ever crosses this boundary;
+ *   - arguments are validated before any device work (OTF_E_INVALID);
+ *   - pointers marked "host" are plain host memory owned by the caller and only
+ *     read or written during the call; pointers marked "device" are device
+ *     memory on the context's device, owned by the caller;
+ *   - the context owns every device buffer it allocates and frees them in
+ *     otf_destroy; all device work is issued on the stream given at creation;
+ *   - after a failure other than OTF_E_INVALID the fused state is unspecified
+ *     and OTF_E_STATE is returned by fuse/extract/energy/export until the next
+ *     successful build or import; the context can always be destroyed;
+ *   - one context per host thread; contexts share no mutable state.
+ *
+ * Geometry: the reconstruction domain is the unit cube [0,1]^3 split into
+ * G^3 finest voxels, G = 2^max_depth. A leaf at level L has side
+ * s = 2^(max_depth - L) finest voxels; its key is the Morton code of its
+ * minimum-corner finest voxel with x in bit 0, y in bit 1, z in bit 2 of each
+ * bit triple. Leaves are always kept sorted by key.
+ */
+#ifndef OTF_H
+#define OTF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct otf_ctx otf_ctx;
+
+typedef enum {
+    OTF_OK = 0,
+    OTF_E_INVALID = 1,  /* bad argument; nothing was changed */
+    OTF_E_NOMEM = 2,    /* a device or host allocation failed */
+    OTF_E_CAPACITY = 3, /* leaf count would exceed max_leaves, or a caller buffer is too small */
+    OTF_E_DEVICE = 4,   /* a HIP call failed */
+    OTF_E_STATE = 5     /* no valid fused state (not built, or a previous call failed) */
+} otf_status;
+
+/* Pinhole camera of one range map (Sec. 3.1: the projection pi_i and centre
+ * C_i). OpenCV axes: x right, y down, z forward. Pixel (i, j) covers
+ * [i, i+1) x [j, j+1); a point with camera coordinates (X, Y, Z), Z > 0,
+ * projects to u = fx X/Z + cx, v = fy Y/Z + cy. 72 bytes. */
+typedef struct {
+    float fx, fy, cx, cy;
+    int32_t width, height;
+    float R_cw[9]; /* row-major camera->world rotation; columns are the camera axes in world space */
+    float C[3];    /* projection centre in world coordinates */
+} otf_camera;
+
+/* Construction and restructuring parameters. 40 bytes. */
+typedef struct {
+    int32_t max_depth;         /* D_max (Sec. 3.1), 1..10 */
+    float delta;               /* truncation band of Eq. 1, world units, > 0 */
+    float eta;                 /* observation cut-off (Sec. 3.1: voxels with phi < -eta are unseen), >= delta */
+    float spread_tau;          /* spread threshold of the construction (Sec. 3.1, 0.1 in the paper);
+                                  < 0 refines every observed node to max_depth */
+    float gamma;               /* normaliser offset of Eq. 5, > 0 */
+    float split_tau, join_tau; /* tau_s, tau_j of the split and join rules (Sec. 3.2); split_tau <= join_tau;
+                                  split_tau = 0 never splits, join_tau > 1 never joins (Sec. 4.2) */
+    int32_t restructure_every; /* restructure after iteration t when t % restructure_every == 0; 0 = never */
+    int64_t max_leaves;        /* leaf capacity limit; 0 = no limit beyond device memory */
+} otf_params;
+
+/* Create a context on HIP device `device`. `hip_stream` is a hipStream_t
+ * borrowed for the context's lifetime (NULL = the null stream). */
+otf_status otf_create(int device, void *hip_stream, otf_ctx **out);
+otf_status otf_destroy(otf_ctx *ctx);
+
+/* Build the fused octree from n_views range maps (Sec. 3.1 and the initial
+ * structure of Fig. 1).
+ *   depth: n_views * H * W floats, row-major per view, the radial range along
+ *          each pixel-centre ray (Eq. 1 subtracts the Euclidean distance to
+ *          C_i); 0, negative, NaN or infinite = no measurement. Host memory
+ *          if depth_is_device == 0, else device memory.
+ *   cams:  n_views cameras (host), all of the same width and height.
+ *   prm:   parameters (host).
+ * Per view: the TSDF of Eq. 1 at every finest voxel centre, observed iff the
+ * voxel is in front of the camera, inside the image, the pixel is valid and
+ * phi >= -eta; the view octree keeps a node's children iff it is above
+ * max_depth, some voxel below is observed and the spread of Eq. 2 over the
+ * observed voxels exceeds spread_tau; every stored node keeps the sum and
+ * count of its observed voxels (the upward means). The fused octree starts as
+ * the union of the view structures; each leaf gathers, per view, the node at
+ * its own level or else the deepest view leaf containing it (Fig. 4):
+ * F = sum/count, W = count/volume; W = 0 observations are dropped. The start
+ * value is sum W F / (sum W + gamma), the dual variable starts at 0.
+ * 1 <= n_views <= 64. Replaces any previous state. */
+otf_status otf_build_octree(otf_ctx *ctx, const float *depth, int32_t depth_is_device, int32_t n_views,
+                            const otf_camera *cams, const otf_params *prm);
+
+/* Run `iterations` primal-dual iterations (Sec. 3.2 energy, Sec. 5 solver):
+ *   p  <- P_unit( p + sigma * G ubar )          (forward differences, Sec. 3.2)
+ *   u' =  u + tau * div p                        (div = -G^T, volume weighted)
+ *   u+ =  argmin_v (v-u')^2/(2 tau) + lambda/(sum W + gamma) * sum_i W_i |v - F_i|
+ *   ubar = 2 u+ - u,  u = u+
+ * then split and join (Sec. 3.2) when the iteration count says so.
+ * lambda >= 0 weights the normalised data term; tau > 0, sigma > 0 are the
+ * primal and dual steps (tau * sigma * 12 <= 1 guarantees convergence on a
+ * fixed structure). All finite. */
+otf_status otf_fuse(otf_ctx *ctx, int32_t iterations, float lambda, float tau, float sigma);
+
+/* Number of leaves of the fused octree. */
+otf_status otf_num_leaves(const otf_ctx *ctx, int64_t *n);
+
+/* Copy the leaves, in key order, into host buffers of `capacity` entries
+ * (p_xyz: 3 floats per leaf, x y z). Any output pointer may be NULL. If
+ * capacity is too small returns OTF_E_CAPACITY with *n_written = leaf count. */
+otf_status otf_extract(const otf_ctx *ctx, int64_t capacity, uint32_t *keys, uint8_t *levels, float *u, float *ubar,
+                       float *p_xyz, int64_t *n_written);
+
+/* Inspection: every leaf's observations (Fig. 4 fetch), host buffers.
+ * M[i], wtot[i] = sum W, inv[i] = 1/(sum W + gamma) per leaf (cap_leaves
+ * entries); F and W concatenated in leaf order, each leaf's sorted by
+ * (F, view) (cap_obs entries). *n_obs receives the total; OTF_E_CAPACITY if
+ * a buffer is too small. */
+otf_status otf_extract_obs(const otf_ctx *ctx, int64_t cap_leaves, int32_t *M, float *wtot, float *inv,
+                           int64_t cap_obs, float *F, float *W, int64_t *n_obs);
+
+/* Inspection: face adjacency. counts: 6 per leaf for faces +x,+y,+z,-x,-y,-z;
+ * idx: neighbour leaf indices concatenated in that order, ascending key
+ * within a face. Host buffers; OTF_E_CAPACITY if idx is too small. */
+otf_status otf_extract_neighbours(const otf_ctx *ctx, int64_t cap_leaves, int32_t *counts, int64_t cap_idx,
+                                  int64_t *idx, int64_t *n_idx);
+
+/* Energy of Eq. 3 with the normaliser of Eq. 5 (lambda on the data term):
+ * tv = sum_n vol_n |(G u)_n|, data = sum_n vol_n/(sum W + gamma) sum_i W_i |u_n - F_i|;
+ * E = tv + lambda * data. Accumulated in double. */
+otf_status otf_energy(otf_ctx *ctx, double *tv, double *data);
+
+/* Splits and joins made by the last restructuring step of the last fuse. */
+otf_status otf_last_counts(const otf_ctx *ctx, int64_t *splits, int64_t *joins);
+
+/* State blob (little-endian, version 1): "OTF1", u32 version, otf_params,
+ * i64 iteration, i32 n_views, i32 0; per view i64 n_nodes then n_nodes records
+ * {u32 key, u8 level, u8 is_leaf, u16 0, f32 sum, u32 count} in (level, key)
+ * order; i64 n_leaves then records {u32 key, u8 level, u8[3] 0, f32 u, ubar,
+ * px, py, pz} in key order. Export writes at most cap bytes into host memory
+ * and always sets *n_bytes to the size needed (buf may be NULL to query). */
+otf_status otf_export_state(const otf_ctx *ctx, void *buf, int64_t cap, int64_t *n_bytes);
+otf_status otf_import_state(otf_ctx *ctx, const void *buf, int64_t n_bytes);
+
+/* Per-kernel timing with HIP events recorded on the context's stream around
+ * every launch of the solver kernels while enabled (adds event overhead).
+ * Kinds: 0 dual sweep, 1 primal sweep, 2 restructure (all its kernels,
+ * including the observation gather and the adjacency rebuild), 3 energy.
+ * otf_profile_read fills ms[4] (summed milliseconds) and launches[4], and
+ * leaf_updates (sum over iterations of the leaf count) and bytes[2]
+ * (algorithmic bytes of the dual and primal sweeps, summed). */
+otf_status otf_profile(otf_ctx *ctx, int32_t enable);
+otf_status otf_profile_read(otf_ctx *ctx, double *ms, int64_t *launches, int64_t *leaf_updates, double *bytes);
+
+/* Message of the last failure on this context (empty if none). Valid until the
+ * next call on the context. */
+const char *otf_last_error(const otf_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OTF_H */

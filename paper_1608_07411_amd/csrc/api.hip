@@ -1,0 +1,676 @@
+// C ABI of libotf: argument validation, context and buffer management, the
+// state blob, inspection copies, and the iteration driver.
+#include <cmath>
+#include <new>
+
+#include "otf_internal.h"
+
+struct otf_ctx {
+    otf::Ctx c;
+};
+
+namespace otf {
+
+void fail(otf_status st, const std::string &msg) { throw Failure{st, msg}; }
+
+void hip_check(hipError_t e, const char *what) {
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Failure{OTF_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e)};
+    }
+}
+
+Coef make_coef(int D) {
+    Coef cf;
+    for (int a = 0; a <= kMaxDepth; ++a)
+        for (int b = 0; b <= kMaxDepth; ++b) {
+            cf.c[a][b] = 0.0f;
+            cf.cp[a][b] = 0.0f;
+            if (a > D || b > D) continue;
+            // gradient of n (level a) toward its + neighbour k (level b)
+            float sn = (float)(1u << (D - a)), sk = (float)(1u << (D - b));
+            float m = sn < sk ? sn : sk;
+            float r = (m / sn) * (m / sn);
+            float h = (sn + sk) * 0.5f;
+            cf.c[a][b] = r / h;
+            // divergence of n (level b) from its - neighbour m (level a)
+            float sm = (float)(1u << (D - a));
+            float sn2 = (float)(1u << (D - b));
+            float mm = sm < sn2 ? sm : sn2;
+            float h2 = (sm + sn2) * 0.5f;
+            cf.cp[a][b] = (sm * mm * mm) / (h2 * sn2 * sn2 * sn2);
+        }
+    return cf;
+}
+
+void LeafStore::reserve(int64_t n) {
+    if (n <= cap && key.p) return;
+    int64_t c = n < 1024 ? 1024 : n;
+    key.reserve(c);
+    level.reserve(c);
+    u.reserve(c);
+    ubar.reserve(c);
+    p.reserve(3 * c);
+    ds.reserve(c);
+    obs_off.reserve(c);
+    obs_m.reserve(c);
+    obs_unit.reserve(c);
+    inv.reserve(c);
+    wtot.reserve(c);
+    nbp_off.reserve(c + 1);
+    nbm_off.reserve(c + 1);
+    flag.reserve(c);
+    uprime.reserve(c);
+    uold.reserve(c);
+    cap = c;
+}
+
+void ObsPool::reserve(int64_t n) {
+    if (n <= cap && F.p) return;
+    int64_t c = n < 1024 ? 1024 : n;
+    F.reserve(c);
+    W.reserve(c);
+    cap = c;
+}
+
+void prof_begin(Ctx &c) {
+    if (!c.prof) return;
+    OTF_HIP(hipEventRecord(c.ev[0], c.stream));
+}
+
+void prof_end(Ctx &c, ProfKind k) {
+    if (!c.prof) return;
+    OTF_HIP(hipEventRecord(c.ev[1], c.stream));
+    OTF_HIP(hipEventSynchronize(c.ev[1]));
+    float ms = 0.0f;
+    OTF_HIP(hipEventElapsedTime(&ms, c.ev[0], c.ev[1]));
+    c.prof_ms[k] += ms;
+    c.prof_n[k] += 1;
+}
+
+namespace {
+
+__global__ void k_zero_u32(uint32_t *p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+}
+
+bool finite(float v) { return std::isfinite(v); }
+
+void check_params(const otf_params *p) {
+    if (!p) fail(OTF_E_INVALID, "params is null");
+    if (p->max_depth < 1 || p->max_depth > kMaxDepth) fail(OTF_E_INVALID, "max_depth must be in 1..10");
+    if (!finite(p->delta) || !finite(p->eta) || !finite(p->gamma) || !finite(p->split_tau) ||
+        !finite(p->join_tau) || std::isnan(p->spread_tau))
+        fail(OTF_E_INVALID, "non-finite parameter");
+    if (!(p->delta > 0.0f) || !(p->eta >= p->delta)) fail(OTF_E_INVALID, "need eta >= delta > 0");
+    if (!(p->gamma > 0.0f)) fail(OTF_E_INVALID, "need gamma > 0");
+    if (!(p->split_tau <= p->join_tau)) fail(OTF_E_INVALID, "need split_tau <= join_tau");
+    if (p->restructure_every < 0) fail(OTF_E_INVALID, "restructure_every < 0");
+    if (p->max_leaves < 0) fail(OTF_E_INVALID, "max_leaves < 0");
+}
+
+void init_state_values(Ctx &c) {
+    LeafStore &s = c.lv();
+    OTF_HIP(hipMemcpyAsync(s.ubar.p, s.u.p, c.L * sizeof(float), hipMemcpyDeviceToDevice, c.stream));
+    for (int d = 0; d < 3; ++d) OTF_HIP(hipMemsetAsync(s.p.p + d * s.cap, 0, c.L * sizeof(float), c.stream));
+}
+
+template <class T>
+std::vector<T> download(Ctx &c, const T *src, int64_t n) {
+    std::vector<T> h((size_t)(n > 0 ? n : 0));
+    if (n > 0) OTF_HIP(hipMemcpyAsync(h.data(), src, n * sizeof(T), hipMemcpyDeviceToHost, c.stream));
+    return h;
+}
+
+template <class T>
+void upload(Ctx &c, T *dst, const std::vector<T> &h) {
+    if (!h.empty()) OTF_HIP(hipMemcpyAsync(dst, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, c.stream));
+}
+
+struct Writer {
+    uint8_t *p;
+    int64_t cap, n = 0;
+    void put(const void *src, int64_t k) {
+        if (p && n + k <= cap) std::memcpy(p + n, src, (size_t)k);
+        n += k;
+    }
+};
+
+struct Reader {
+    const uint8_t *p;
+    int64_t n, at = 0;
+    void get(void *dst, int64_t k) {
+        if (at + k > n) fail(OTF_E_INVALID, "state blob truncated");
+        std::memcpy(dst, p + at, (size_t)k);
+        at += k;
+    }
+};
+
+#pragma pack(push, 1)
+struct NodeRec {
+    uint32_t key;
+    uint8_t level, leaf;
+    uint16_t zero;
+    float S;
+    uint32_t cnt;
+};
+struct LeafRec {
+    uint32_t key;
+    uint8_t level, pad[3];
+    float v[5];
+};
+#pragma pack(pop)
+static_assert(sizeof(NodeRec) == 16, "node record");
+static_assert(sizeof(LeafRec) == 28, "leaf record");
+static_assert(sizeof(otf_params) == 40, "params record");
+static_assert(sizeof(otf_camera) == 72, "camera record");
+
+void setup_after_structure(Ctx &c, bool init_values) {
+    gather_all_leaves(c, init_values);
+    if (init_values) init_state_values(c);
+    build_neighbours(c);
+    OTF_HIP(hipStreamSynchronize(c.stream));
+}
+
+}  // namespace
+}  // namespace otf
+
+using namespace otf;
+
+namespace {
+
+template <class F>
+otf_status guard(otf_ctx *ctx, bool invalidates, F &&f) {
+    if (ctx) {
+        if (hipSetDevice(ctx->c.device) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->c.err = "hipSetDevice failed";
+            return OTF_E_DEVICE;
+        }
+    }
+    try {
+        f();
+        if (ctx) ctx->c.err.clear();
+        return OTF_OK;
+    } catch (const Failure &e) {
+        if (ctx) {
+            ctx->c.err = e.msg;
+            if (invalidates && e.st != OTF_E_INVALID) ctx->c.valid = false;
+        }
+        return e.st;
+    } catch (const std::bad_alloc &) {
+        if (ctx) {
+            ctx->c.err = "host allocation failed";
+            if (invalidates) ctx->c.valid = false;
+        }
+        return OTF_E_NOMEM;
+    } catch (...) {
+        if (ctx) {
+            ctx->c.err = "unexpected failure";
+            if (invalidates) ctx->c.valid = false;
+        }
+        return OTF_E_DEVICE;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+otf_status otf_create(int device, void *hip_stream, otf_ctx **out) {
+    if (!out) return OTF_E_INVALID;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+        (void)hipGetLastError();
+        return OTF_E_INVALID;
+    }
+    otf_ctx *ctx = new (std::nothrow) otf_ctx();
+    if (!ctx) return OTF_E_NOMEM;
+    ctx->c.device = device;
+    ctx->c.stream = (hipStream_t)hip_stream;
+    otf_status st = guard(ctx, false, [&] {
+        ctx->c.counters.reserve(16);
+        void *h = nullptr;
+        OTF_HIP(hipHostMalloc(&h, 16 * sizeof(uint32_t), hipHostMallocDefault));
+        ctx->c.h_counters = (uint32_t *)h;
+        OTF_HIP(hipEventCreate(&ctx->c.ev[0]));
+        OTF_HIP(hipEventCreate(&ctx->c.ev[1]));
+    });
+    if (st != OTF_OK) {
+        otf_destroy(ctx);
+        return st;
+    }
+    *out = ctx;
+    return OTF_OK;
+}
+
+otf_status otf_destroy(otf_ctx *ctx) {
+    if (!ctx) return OTF_E_INVALID;
+    (void)hipSetDevice(ctx->c.device);
+    (void)hipStreamSynchronize(ctx->c.stream);
+    if (ctx->c.h_counters) (void)hipHostFree(ctx->c.h_counters);
+    for (auto &e : ctx->c.ev)
+        if (e) (void)hipEventDestroy(e);
+    delete ctx;
+    return OTF_OK;
+}
+
+const char *otf_last_error(const otf_ctx *ctx) { return ctx ? ctx->c.err.c_str() : "null context"; }
+
+otf_status otf_build_octree(otf_ctx *ctx, const float *depth, int32_t depth_is_device, int32_t n_views,
+                            const otf_camera *cams, const otf_params *prm) {
+    if (!ctx) return OTF_E_INVALID;
+    return guard(ctx, true, [&] {
+        Ctx &c = ctx->c;
+        check_params(prm);
+        if (!depth || !cams) fail(OTF_E_INVALID, "depth or cams is null");
+        if (n_views < 1 || n_views > kMaxViews) fail(OTF_E_INVALID, "n_views must be in 1..64");
+        std::vector<CamDev> cd(n_views);
+        for (int v = 0; v < n_views; ++v) {
+            const otf_camera &k = cams[v];
+            if (k.width <= 0 || k.height <= 0 || k.width != cams[0].width || k.height != cams[0].height)
+                fail(OTF_E_INVALID, "cameras must share one positive image size");
+            const float *vals[] = {&k.fx, &k.fy, &k.cx, &k.cy};
+            for (const float *q : vals)
+                if (!std::isfinite(*q)) fail(OTF_E_INVALID, "non-finite intrinsics");
+            for (int r = 0; r < 9; ++r)
+                if (!std::isfinite(k.R_cw[r])) fail(OTF_E_INVALID, "non-finite rotation");
+            for (int r = 0; r < 3; ++r)
+                if (!std::isfinite(k.C[r])) fail(OTF_E_INVALID, "non-finite camera centre");
+            cd[v] = CamDev{k.fx, k.fy, k.cx, k.cy, k.width, k.height, {}, {}};
+            std::memcpy(cd[v].R, k.R_cw, sizeof(cd[v].R));
+            std::memcpy(cd[v].C, k.C, sizeof(cd[v].C));
+        }
+        c.valid = false;
+        c.prm = *prm;
+        c.n_views = n_views;
+        c.iteration = 0;
+        c.coef = make_coef(prm->max_depth);
+        c.last_splits = c.last_joins = 0;
+        const size_t npix = (size_t)n_views * cams[0].width * cams[0].height;
+        DBuf<float> dtmp;
+        const float *ddev = depth;
+        if (!depth_is_device) {
+            dtmp.reserve(npix);
+            OTF_HIP(hipMemcpyAsync(dtmp.p, depth, npix * sizeof(float), hipMemcpyHostToDevice, c.stream));
+            ddev = dtmp.p;
+        }
+        build_views_and_union(c, ddev, cd);
+        setup_after_structure(c, true);
+        c.valid = true;
+    });
+}
+
+otf_status otf_fuse(otf_ctx *ctx, int32_t iterations, float lambda, float tau, float sigma) {
+    if (!ctx) return OTF_E_INVALID;
+    if (iterations < 0 || !std::isfinite(lambda) || !std::isfinite(tau) || !std::isfinite(sigma) || lambda < 0.0f ||
+        !(tau > 0.0f) || !(sigma > 0.0f)) {
+        ctx->c.err = "bad fuse arguments";
+        return OTF_E_INVALID;
+    }
+    if (!ctx->c.valid) {
+        ctx->c.err = "no valid state";
+        return OTF_E_STATE;
+    }
+    return guard(ctx, true, [&] {
+        Ctx &c = ctx->c;
+        const float tl = tau * lambda;
+        for (int it = 0; it < iterations; ++it) {
+            c.iteration++;
+            prof_begin(c);
+            launch_dual(c, sigma);
+            prof_end(c, kProfDual);
+            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, c.stream, c.counters.p, 2);
+            prof_begin(c);
+            launch_primal(c, tau, tl);
+            prof_end(c, kProfPrimal);
+            c.prof_leaf_updates += c.L;
+            if (c.prof) {
+                const double E = (double)c.n_nbp, Em = (double)c.n_nbm;
+                // dual: ubar own + gathered, p r/w, ds w, + entries and offsets
+                c.prof_bytes[0] += 4.0 * c.L * (1 + 6 + 1 + 1) + 4.0 * E * 2 + 1.0 * c.L;
+                // primal: ds, u r/w, ubar w, p gathers, - entries and offsets, obs header and data
+                c.prof_bytes[1] += 4.0 * c.L * (1 + 2 + 1 + 1) + 4.0 * Em * 2 + c.L * (4.0 + 1 + 1 + 4 + 4 + 1) +
+                                   4.0 * (double)c.op().used;
+            }
+            c.last_splits = c.last_joins = 0;
+            if (c.prm.restructure_every > 0 && c.iteration % c.prm.restructure_every == 0) {
+                prof_begin(c);
+                restructure(c, tl);
+                prof_end(c, kProfRestructure);
+            }
+        }
+        OTF_HIP(hipStreamSynchronize(c.stream));
+    });
+}
+
+otf_status otf_num_leaves(const otf_ctx *ctx, int64_t *n) {
+    if (!ctx || !n) return OTF_E_INVALID;
+    if (!ctx->c.valid) return OTF_E_STATE;
+    *n = ctx->c.L;
+    return OTF_OK;
+}
+
+otf_status otf_last_counts(const otf_ctx *ctx, int64_t *splits, int64_t *joins) {
+    if (!ctx || !splits || !joins) return OTF_E_INVALID;
+    *splits = ctx->c.last_splits;
+    *joins = ctx->c.last_joins;
+    return OTF_OK;
+}
+
+otf_status otf_extract(const otf_ctx *cctx, int64_t capacity, uint32_t *keys, uint8_t *levels, float *u, float *ubar,
+                       float *p_xyz, int64_t *n_written) {
+    otf_ctx *ctx = const_cast<otf_ctx *>(cctx);
+    if (!ctx || !n_written || capacity < 0) return OTF_E_INVALID;
+    if (!ctx->c.valid) return OTF_E_STATE;
+    *n_written = ctx->c.L;
+    if (capacity < ctx->c.L) return OTF_E_CAPACITY;
+    return guard(ctx, false, [&] {
+        Ctx &c = ctx->c;
+        LeafStore &s = c.lv();
+        const int64_t L = c.L;
+        if (keys) OTF_HIP(hipMemcpyAsync(keys, s.key.p, L * 4, hipMemcpyDeviceToHost, c.stream));
+        if (levels) OTF_HIP(hipMemcpyAsync(levels, s.level.p, L, hipMemcpyDeviceToHost, c.stream));
+        if (u) OTF_HIP(hipMemcpyAsync(u, s.u.p, L * 4, hipMemcpyDeviceToHost, c.stream));
+        if (ubar) OTF_HIP(hipMemcpyAsync(ubar, s.ubar.p, L * 4, hipMemcpyDeviceToHost, c.stream));
+        if (p_xyz) {
+            std::vector<float> h = download(c, s.p.p, 3 * s.cap);
+            OTF_HIP(hipStreamSynchronize(c.stream));
+            for (int64_t i = 0; i < L; ++i)
+                for (int d = 0; d < 3; ++d) p_xyz[3 * i + d] = h[(size_t)d * s.cap + i];
+        }
+        OTF_HIP(hipStreamSynchronize(c.stream));
+    });
+}
+
+otf_status otf_extract_obs(const otf_ctx *cctx, int64_t cap_leaves, int32_t *M, float *wtot, float *inv,
+                           int64_t cap_obs, float *F, float *W, int64_t *n_obs) {
+    otf_ctx *ctx = const_cast<otf_ctx *>(cctx);
+    if (!ctx || !n_obs) return OTF_E_INVALID;
+    if (!ctx->c.valid) return OTF_E_STATE;
+    if (cap_leaves < ctx->c.L) return OTF_E_CAPACITY;
+    otf_status cap_st = OTF_OK;
+    otf_status st = guard(ctx, false, [&] {
+        Ctx &c = ctx->c;
+        LeafStore &s = c.lv();
+        const int64_t L = c.L;
+        auto hm = download(c, s.obs_m.p, L);
+        auto hoff = download(c, s.obs_off.p, L);
+        auto hw = download(c, s.wtot.p, L);
+        auto hi = download(c, s.inv.p, L);
+        auto hF = download(c, c.op().F.p, c.op().used);
+        auto hW = download(c, c.op().W.p, c.op().used);
+        OTF_HIP(hipStreamSynchronize(c.stream));
+        int64_t tot = 0;
+        for (int64_t i = 0; i < L; ++i) tot += hm[i];
+        *n_obs = tot;
+        if (tot > cap_obs) {
+            cap_st = OTF_E_CAPACITY;
+            return;
+        }
+        int64_t j = 0;
+        for (int64_t i = 0; i < L; ++i) {
+            if (M) M[i] = hm[i];
+            if (wtot) wtot[i] = hw[i];
+            if (inv) inv[i] = hi[i];
+            for (int k = 0; k < hm[i]; ++k, ++j) {
+                if (F) F[j] = hF[hoff[i] + k];
+                if (W) W[j] = hW[hoff[i] + k];
+            }
+        }
+    });
+    return st != OTF_OK ? st : cap_st;
+}
+
+otf_status otf_extract_neighbours(const otf_ctx *cctx, int64_t cap_leaves, int32_t *counts, int64_t cap_idx,
+                                  int64_t *idx, int64_t *n_idx) {
+    otf_ctx *ctx = const_cast<otf_ctx *>(cctx);
+    if (!ctx || !n_idx) return OTF_E_INVALID;
+    if (!ctx->c.valid) return OTF_E_STATE;
+    if (cap_leaves < ctx->c.L) return OTF_E_CAPACITY;
+    otf_status cap_st = OTF_OK;
+    otf_status st = guard(ctx, false, [&] {
+        Ctx &c = ctx->c;
+        LeafStore &s = c.lv();
+        const int64_t L = c.L;
+        auto op = download(c, s.nbp_off.p, L + 1);
+        auto om = download(c, s.nbm_off.p, L + 1);
+        auto ep = download(c, c.nbp.p, c.n_nbp);
+        auto em = download(c, c.nbm.p, c.n_nbm);
+        OTF_HIP(hipStreamSynchronize(c.stream));
+        *n_idx = c.n_nbp + c.n_nbm;
+        if (*n_idx > cap_idx) {
+            cap_st = OTF_E_CAPACITY;
+            return;
+        }
+        int64_t j = 0;
+        for (int64_t i = 0; i < L; ++i) {
+            int32_t cnt[6] = {0, 0, 0, 0, 0, 0};
+            for (int side = 0; side < 2; ++side) {
+                const auto &off = side ? om : op;
+                const auto &ent = side ? em : ep;
+                for (int d = 0; d < 3; ++d)
+                    for (uint32_t e = off[i]; e < off[i + 1]; ++e)
+                        if ((int)((ent[e] >> kIdxBits) & 3u) == d) {
+                            cnt[3 * side + d]++;
+                            if (idx) idx[j] = ent[e] & kIdxMask;
+                            ++j;
+                        }
+            }
+            if (counts)
+                for (int f = 0; f < 6; ++f) counts[6 * i + f] = cnt[f];
+        }
+    });
+    return st != OTF_OK ? st : cap_st;
+}
+
+otf_status otf_energy(otf_ctx *ctx, double *tv, double *data) {
+    if (!ctx || !tv || !data) return OTF_E_INVALID;
+    if (!ctx->c.valid) return OTF_E_STATE;
+    return guard(ctx, false, [&] {
+        prof_begin(ctx->c);
+        energy(ctx->c, tv, data);
+        prof_end(ctx->c, kProfEnergy);
+    });
+}
+
+otf_status otf_export_state(const otf_ctx *cctx, void *buf, int64_t cap, int64_t *n_bytes) {
+    otf_ctx *ctx = const_cast<otf_ctx *>(cctx);
+    if (!ctx || !n_bytes || cap < 0) return OTF_E_INVALID;
+    if (!ctx->c.valid) return OTF_E_STATE;
+    otf_status cap_st = OTF_OK;
+    otf_status st = guard(ctx, false, [&] {
+        Ctx &c = ctx->c;
+        const ViewStore &vs = c.views;
+        auto hk = download(c, vs.key.p, vs.n_nodes);
+        auto hl = download(c, vs.level.p, vs.n_nodes);
+        auto hS = download(c, vs.S.p, vs.n_nodes);
+        auto hc = download(c, vs.cnt.p, vs.n_nodes);
+        auto hch = download(c, vs.child.p, vs.n_nodes);
+        LeafStore &s = c.lv();
+        const int64_t L = c.L;
+        auto lk = download(c, s.key.p, L);
+        auto ll = download(c, s.level.p, L);
+        auto lu = download(c, s.u.p, L);
+        auto lb = download(c, s.ubar.p, L);
+        auto lp = download(c, s.p.p, 3 * s.cap);
+        OTF_HIP(hipStreamSynchronize(c.stream));
+        Writer w{(uint8_t *)buf, cap};
+        w.put("OTF1", 4);
+        uint32_t ver = 1;
+        w.put(&ver, 4);
+        w.put(&c.prm, sizeof(otf_params));
+        w.put(&c.iteration, 8);
+        int32_t nv = c.n_views, zero = 0;
+        w.put(&nv, 4);
+        w.put(&zero, 4);
+        for (int v = 0; v < c.n_views; ++v) {
+            int64_t nn = vs.count[v];
+            w.put(&nn, 8);
+            for (int64_t q = 0; q < nn; ++q) {
+                const int64_t i = vs.base[v] + q;
+                NodeRec r{hk[i], hl[i], (uint8_t)(hch[i] == kNone ? 1 : 0), 0, hS[i], hc[i]};
+                w.put(&r, sizeof r);
+            }
+        }
+        w.put(&L, 8);
+        for (int64_t i = 0; i < L; ++i) {
+            LeafRec r{lk[i], ll[i], {0, 0, 0}, {lu[i], lb[i], lp[i], lp[s.cap + i], lp[2 * s.cap + i]}};
+            w.put(&r, sizeof r);
+        }
+        *n_bytes = w.n;
+        if (buf && w.n > cap) cap_st = OTF_E_CAPACITY;
+    });
+    return st != OTF_OK ? st : cap_st;
+}
+
+otf_status otf_import_state(otf_ctx *ctx, const void *buf, int64_t n_bytes) {
+    if (!ctx || !buf || n_bytes < 0) return OTF_E_INVALID;
+    return guard(ctx, true, [&] {
+        Ctx &c = ctx->c;
+        Reader r{(const uint8_t *)buf, n_bytes};
+        char magic[4];
+        uint32_t ver;
+        otf_params prm;
+        int64_t iter;
+        int32_t nv, zero;
+        r.get(magic, 4);
+        r.get(&ver, 4);
+        r.get(&prm, sizeof prm);
+        r.get(&iter, 8);
+        r.get(&nv, 4);
+        r.get(&zero, 4);
+        if (std::memcmp(magic, "OTF1", 4) != 0 || ver != 1) fail(OTF_E_INVALID, "bad blob header");
+        check_params(&prm);
+        if (nv < 1 || nv > kMaxViews) fail(OTF_E_INVALID, "bad view count");
+        const int D = prm.max_depth;
+        // view trees: rebuild child links from (level, key) order
+        std::vector<uint32_t> key, cnt, child;
+        std::vector<uint8_t> level;
+        std::vector<float> S;
+        std::vector<int64_t> count(nv), base(nv);
+        for (int v = 0; v < nv; ++v) {
+            int64_t nn;
+            r.get(&nn, 8);
+            if (nn < 1 || nn > (int64_t)0x7FFFFFFF) fail(OTF_E_INVALID, "bad view node count");
+            base[v] = (int64_t)key.size();
+            count[v] = nn;
+            std::vector<NodeRec> recs((size_t)nn);
+            r.get(recs.data(), nn * (int64_t)sizeof(NodeRec));
+            int64_t next_child = 1;  // position (within the view) of the next unassigned child group
+            for (int64_t q = 0; q < nn; ++q) {
+                const NodeRec &nr = recs[q];
+                if (q == 0 && (nr.level != 0 || nr.key != 0)) fail(OTF_E_INVALID, "view root");
+                if (nr.level > D) fail(OTF_E_INVALID, "view node level");
+                uint32_t ch = kNone;
+                if (!nr.leaf) {
+                    if (nr.level >= D || next_child + 8 > nn) fail(OTF_E_INVALID, "inconsistent view tree");
+                    const int sh = 3 * (D - nr.level - 1);
+                    for (int k = 0; k < 8; ++k) {
+                        const NodeRec &cr = recs[next_child + k];
+                        if (cr.level != nr.level + 1 || cr.key != (nr.key | ((uint32_t)k << sh)))
+                            fail(OTF_E_INVALID, "inconsistent view tree");
+                    }
+                    ch = (uint32_t)(base[v] + next_child);
+                    next_child += 8;
+                }
+                key.push_back(nr.key);
+                level.push_back(nr.level);
+                S.push_back(nr.S);
+                cnt.push_back(nr.cnt);
+                child.push_back(ch);
+            }
+            if (next_child != nn) fail(OTF_E_INVALID, "inconsistent view tree");
+        }
+        int64_t nl;
+        r.get(&nl, 8);
+        if (nl < 1 || nl >= kLeafLimit) fail(OTF_E_INVALID, "bad leaf count");
+        if (prm.max_leaves > 0 && nl > prm.max_leaves) fail(OTF_E_CAPACITY, "leaves exceed max_leaves");
+        std::vector<LeafRec> lr((size_t)nl);
+        r.get(lr.data(), nl * (int64_t)sizeof(LeafRec));
+        uint64_t next = 0;
+        for (int64_t i = 0; i < nl; ++i) {
+            if (lr[i].level > D) fail(OTF_E_INVALID, "leaf level");
+            const uint64_t size = uint64_t(1) << (3 * (D - lr[i].level));
+            if (lr[i].key != next || (lr[i].key & (size - 1)) != 0) fail(OTF_E_INVALID, "leaves do not tile the domain");
+            next = (uint64_t)lr[i].key + size;
+        }
+        if (next != (uint64_t(1) << (3 * D))) fail(OTF_E_INVALID, "leaves do not tile the domain");
+        // commit
+        c.valid = false;
+        c.prm = prm;
+        c.n_views = nv;
+        c.iteration = iter;
+        c.coef = make_coef(D);
+        c.last_splits = c.last_joins = 0;
+        ViewStore &vs = c.views;
+        vs.n_nodes = (int64_t)key.size();
+        vs.count = count;
+        vs.base = base;
+        vs.S.reserve(vs.n_nodes);
+        vs.cnt.reserve(vs.n_nodes);
+        vs.child.reserve(vs.n_nodes);
+        vs.key.reserve(vs.n_nodes);
+        vs.level.reserve(vs.n_nodes);
+        upload(c, vs.S.p, S);
+        upload(c, vs.cnt.p, cnt);
+        upload(c, vs.child.p, child);
+        upload(c, vs.key.p, key);
+        upload(c, vs.level.p, level);
+        std::vector<uint32_t> roots(nv);
+        for (int v = 0; v < nv; ++v) roots[v] = (uint32_t)base[v];
+        vs.root.reserve(nv);
+        upload(c, vs.root.p, roots);
+        c.cur = 0;
+        c.L = nl;
+        LeafStore &s = c.lv();
+        s.reserve(nl);
+        std::vector<uint32_t> lk(nl);
+        std::vector<uint8_t> ll(nl);
+        std::vector<float> lu(nl), lb(nl), lp(3 * s.cap, 0.0f);
+        for (int64_t i = 0; i < nl; ++i) {
+            lk[i] = lr[i].key;
+            ll[i] = lr[i].level;
+            lu[i] = lr[i].v[0];
+            lb[i] = lr[i].v[1];
+            for (int d = 0; d < 3; ++d) lp[(size_t)d * s.cap + i] = lr[i].v[2 + d];
+        }
+        upload(c, s.key.p, lk);
+        upload(c, s.level.p, ll);
+        upload(c, s.u.p, lu);
+        upload(c, s.ubar.p, lb);
+        upload(c, s.p.p, lp);
+        OTF_HIP(hipStreamSynchronize(c.stream));
+        setup_after_structure(c, false);
+        c.valid = true;
+    });
+}
+
+otf_status otf_profile(otf_ctx *ctx, int32_t enable) {
+    if (!ctx) return OTF_E_INVALID;
+    ctx->c.prof = enable != 0;
+    for (int k = 0; k < kProfKinds; ++k) {
+        ctx->c.prof_ms[k] = 0.0;
+        ctx->c.prof_n[k] = 0;
+    }
+    ctx->c.prof_leaf_updates = 0;
+    ctx->c.prof_bytes[0] = ctx->c.prof_bytes[1] = 0.0;
+    return OTF_OK;
+}
+
+otf_status otf_profile_read(otf_ctx *ctx, double *ms, int64_t *launches, int64_t *leaf_updates, double *bytes) {
+    if (!ctx) return OTF_E_INVALID;
+    for (int k = 0; k < kProfKinds; ++k) {
+        if (ms) ms[k] = ctx->c.prof_ms[k];
+        if (launches) launches[k] = ctx->c.prof_n[k];
+    }
+    if (leaf_updates) *leaf_updates = ctx->c.prof_leaf_updates;
+    if (bytes) {
+        bytes[0] = ctx->c.prof_bytes[0];
+        bytes[1] = ctx->c.prof_bytes[1];
+    }
+    return OTF_OK;
+}
+
+}  // extern "C"

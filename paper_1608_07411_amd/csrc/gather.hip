@@ -1,0 +1,160 @@
+// Data fetch of Fig. 4: for a fused-octree node at level L and every view,
+// the view's stored node at level L, else the deepest view leaf containing it;
+// F = sum/count, W = count/volume, W = 0 dropped. The observations of a node
+// are sorted by (F, view) with the prefix weights and the normaliser
+// 1/(sum W + gamma) of Eq. 5.
+//
+// One segment of SEG lanes (a power of two >= n_views) per target node: lane j
+// descends view j's octree; the segment sorts by rank (each lane counts the
+// lanes ordered before it) and its first lane forms the sequential sums.
+#include "otf_internal.h"
+
+namespace otf {
+namespace {
+
+constexpr int kBlk = 256;
+
+struct GatherOut {
+    const uint32_t *tidx;  // target t is leaf tidx[t] (key, level, header), or null: leaf t
+    const uint32_t *off;   // per-target segment offset (+ base), or null: t * stride
+    uint32_t base;
+    int stride;
+    float *F, *W;
+    uint8_t *Mcount;  // count mode: M per target t
+    uint8_t *M, *unit;
+    float *inv, *wtot, *u0;
+    uint32_t *off_out;  // fill mode: segment offset written into the header, or null
+};
+
+template <int SEG>
+__global__ void __launch_bounds__(kBlk) k_gather(ViewDev vd, int64_t n, const uint32_t *__restrict__ tkey,
+                                                 const uint8_t *__restrict__ tlevel, GatherOut o, float gamma,
+                                                 int count_only) {
+    __shared__ float sF[kBlk], sW[kBlk];
+    const int tid = threadIdx.x;
+    const int64_t t = ((int64_t)blockIdx.x * kBlk + tid) / SEG;
+    const int j = tid % SEG;
+    const int lane = tid & 63;
+    const int seg_lane0 = lane - j;
+    const int seg_tid0 = tid - j;
+    bool valid = false;
+    float f = 0.0f, w = 0.0f;
+    const int64_t h = (t < n && o.tidx) ? (int64_t)o.tidx[t] : t;
+    if (t < n && j < vd.n_views) {
+        const int D = vd.max_depth;
+        const uint32_t key = tkey[h];
+        const int L = tlevel[h];
+        uint32_t node = vd.root[j];
+        int l = 0;
+        while (l < L) {
+            const uint32_t ch = vd.child[node];
+            if (ch == kNone) break;
+            node = ch + ((key >> (3 * (D - l - 1))) & 7u);
+            ++l;
+        }
+        const uint32_t cn = vd.cnt[node];
+        if (cn > 0u) {
+            valid = true;
+            f = vd.S[node] / (float)cn;
+            w = ldexpf((float)cn, -3 * (D - l));
+        }
+    }
+    const uint64_t ballot = __ballot(valid);
+    const uint64_t segmask = (SEG == 64) ? ~0ull : (((1ull << SEG) - 1ull) << seg_lane0);
+    const int m = __popcll(ballot & segmask);
+    if (count_only) {
+        if (t < n && j == 0) o.Mcount[t] = (uint8_t)m;
+        return;
+    }
+    int rank = 0;
+#pragma unroll
+    for (int i = 0; i < SEG; ++i) {
+        const float fi = __shfl(f, seg_lane0 + i, 64);
+        const bool vi = (ballot >> (seg_lane0 + i)) & 1ull;
+        if (vi && (fi < f || (fi == f && i < j))) ++rank;
+    }
+    if (valid) {
+        sF[seg_tid0 + rank] = f;
+        sW[seg_tid0 + rank] = w;
+    }
+    __syncthreads();
+    if (t >= n) return;
+    const uint32_t off = o.base + (o.off ? o.off[t] : (uint32_t)(t * o.stride));
+    if (valid) {
+        o.F[off + rank] = f;
+        o.W[off + rank] = w;
+    }
+    if (j == 0) {
+        float P = 0.0f, acc = 0.0f;
+        bool all1 = true;
+        for (int k = 0; k < m; ++k) {
+            const float wk = sW[seg_tid0 + k];
+            P = P + wk;
+            acc = __fmaf_rn(wk, sF[seg_tid0 + k], acc);
+            all1 = all1 && (wk == 1.0f);
+        }
+        const float inv = 1.0f / (P + gamma);
+        o.M[h] = (uint8_t)m;
+        o.unit[h] = all1 ? 1 : 0;
+        o.inv[h] = inv;
+        o.wtot[h] = P;
+        if (o.u0) o.u0[h] = acc * inv;
+        if (o.off_out) o.off_out[h] = off;
+    }
+}
+
+template <int SEG>
+void launch_seg(Ctx &c, int64_t n, const uint32_t *tkey, const uint8_t *tlevel, const GatherOut &o, bool count_only) {
+    const int64_t threads = n * SEG;
+    hipLaunchKernelGGL((k_gather<SEG>), dim3((unsigned)cdiv(threads, kBlk)), dim3(kBlk), 0, c.stream, c.view_dev(), n,
+                       tkey, tlevel, o, c.prm.gamma, count_only ? 1 : 0);
+    OTF_LAUNCH_CHECK("k_gather");
+}
+
+void gather_launch(Ctx &c, int64_t n, const uint32_t *tkey, const uint8_t *tlevel, const GatherOut &o,
+                   bool count_only);
+
+}  // namespace
+
+void gather_count(Ctx &c, int64_t n, const uint32_t *tkey, const uint8_t *tlevel, const uint32_t *tidx,
+                  uint8_t *Mcount) {
+    if (n <= 0) return;
+    GatherOut o{tidx, nullptr, 0, 0, nullptr, nullptr, Mcount, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    gather_launch(c, n, tkey, tlevel, o, true);
+}
+
+void gather_fill(Ctx &c, int64_t n, const uint32_t *tkey, const uint8_t *tlevel, const uint32_t *tidx,
+                 const uint32_t *out_off, uint32_t base, int stride, float *F, float *W, uint8_t *M, uint8_t *unit,
+                 float *inv, float *wtot, float *u0, uint32_t *off_out) {
+    if (n <= 0) return;
+    GatherOut o{tidx, out_off, base, stride, F, W, nullptr, M, unit, inv, wtot, u0, off_out};
+    gather_launch(c, n, tkey, tlevel, o, false);
+}
+
+namespace {
+void gather_launch(Ctx &c, int64_t n, const uint32_t *tkey, const uint8_t *tlevel, const GatherOut &o,
+                   bool count_only) {
+    const int nv = c.n_views;
+    if (nv <= 1) launch_seg<1>(c, n, tkey, tlevel, o, count_only);
+    else if (nv <= 2) launch_seg<2>(c, n, tkey, tlevel, o, count_only);
+    else if (nv <= 4) launch_seg<4>(c, n, tkey, tlevel, o, count_only);
+    else if (nv <= 8) launch_seg<8>(c, n, tkey, tlevel, o, count_only);
+    else if (nv <= 16) launch_seg<16>(c, n, tkey, tlevel, o, count_only);
+    else if (nv <= 32) launch_seg<32>(c, n, tkey, tlevel, o, count_only);
+    else launch_seg<64>(c, n, tkey, tlevel, o, count_only);
+}
+}  // namespace
+
+// Observation pool for every leaf of the current store, in leaf order.
+void gather_all_leaves(Ctx &c, bool init_values) {
+    LeafStore &s = c.lv();
+    gather_count(c, c.L, s.key.p, s.level.p, nullptr, s.obs_m.p);
+    const uint32_t total = scan_exclusive_u8(c, s.obs_m.p, s.obs_off.p, c.L);
+    c.ocur = 0;
+    c.op().reserve(total + total / 4 + 1024);  // headroom for observations of new leaves
+    c.op().used = total;
+    gather_fill(c, c.L, s.key.p, s.level.p, nullptr, s.obs_off.p, 0, 0, c.op().F.p, c.op().W.p, s.obs_m.p,
+                s.obs_unit.p, s.inv.p, s.wtot.p, init_values ? s.u.p : nullptr, nullptr);
+}
+
+}  // namespace otf

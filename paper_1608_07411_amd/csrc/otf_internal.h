@@ -1,0 +1,316 @@
+// Internal declarations of libotf: device buffers, the context, device-side
+// helpers shared by the kernels, and the host launchers of every phase.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "otf.h"
+
+namespace otf {
+
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr int kMaxViews = 64;
+constexpr int kMaxDepth = 10;
+// adjacency entry: neighbour index (26 bits) | direction (2 bits) | level (4 bits)
+constexpr int kIdxBits = 26;
+constexpr uint32_t kIdxMask = (1u << kIdxBits) - 1u;
+constexpr int64_t kLeafLimit = int64_t(1) << kIdxBits;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+struct Failure {
+    otf_status st;
+    std::string msg;
+};
+
+[[noreturn]] void fail(otf_status st, const std::string &msg);
+void hip_check(hipError_t e, const char *what);
+#define OTF_HIP(x) ::otf::hip_check((x), #x)
+#define OTF_LAUNCH_CHECK(name) ::otf::hip_check(hipGetLastError(), name)
+
+// ---------------------------------------------------------------------------
+// device buffer (hipMalloc / hipFree), grows on demand
+// ---------------------------------------------------------------------------
+template <class T>
+struct DBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    ~DBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    // ensure capacity for `count` elements; contents are discarded on growth
+    void reserve(size_t count) {
+        if (count <= n && p) return;
+        release();
+        size_t c = count ? count : 1;
+        hipError_t e = hipMalloc((void **)&p, c * sizeof(T));
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            fail(OTF_E_NOMEM, "hipMalloc of " + std::to_string(c * sizeof(T)) + " bytes failed");
+        }
+        n = c;
+    }
+    void swap(DBuf &o) {
+        std::swap(p, o.p);
+        std::swap(n, o.n);
+    }
+    T *get() const { return p; }
+};
+
+// ---------------------------------------------------------------------------
+// geometry helpers
+// ---------------------------------------------------------------------------
+__host__ __device__ inline uint32_t part1by2(uint32_t v) {
+    v &= 0x3FFu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+__host__ __device__ inline uint32_t compact1by2(uint32_t v) {
+    v &= 0x09249249u;
+    v = (v ^ (v >> 2)) & 0x030C30C3u;
+    v = (v ^ (v >> 4)) & 0x0300F00Fu;
+    v = (v ^ (v >> 8)) & 0xFF0000FFu;
+    v = (v ^ (v >> 16)) & 0x000003FFu;
+    return v;
+}
+__host__ __device__ inline uint32_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+    return part1by2(x) | (part1by2(y) << 1) | (part1by2(z) << 2);
+}
+__host__ __device__ inline void demorton3(uint32_t k, uint32_t &x, uint32_t &y, uint32_t &z) {
+    x = compact1by2(k);
+    y = compact1by2(k >> 1);
+    z = compact1by2(k >> 2);
+}
+
+// Coupling coefficients by level pair, one correctly rounded division of exact
+// operands each: c[ln][lk] for the gradient of leaf n toward its + neighbour k,
+// cp[lm][ln] for the divergence of leaf n from its - neighbour m.
+struct Coef {
+    float c[kMaxDepth + 1][kMaxDepth + 1];
+    float cp[kMaxDepth + 1][kMaxDepth + 1];
+};
+Coef make_coef(int max_depth);
+
+struct CamDev {
+    float fx, fy, cx, cy;
+    int32_t width, height;
+    float R[9];
+    float C[3];
+};
+
+// Eq. 1 at one finest voxel centre; returns whether the voxel is observed.
+// Operation order is fixed (one IEEE operation at a time, explicit fma).
+__device__ inline bool tsdf_voxel(const CamDev &cam, const float *__restrict__ depth_v, float h, float delta,
+                                  float eta, uint32_t a, uint32_t b, uint32_t c, float &f) {
+    float dx = __fsub_rn(__fmul_rn(__fadd_rn((float)a, 0.5f), h), cam.C[0]);
+    float dy = __fsub_rn(__fmul_rn(__fadd_rn((float)b, 0.5f), h), cam.C[1]);
+    float dz = __fsub_rn(__fmul_rn(__fadd_rn((float)c, 0.5f), h), cam.C[2]);
+    const float *R = cam.R;
+    float X = __fmaf_rn(R[0], dx, __fmaf_rn(R[3], dy, __fmul_rn(R[6], dz)));
+    float Y = __fmaf_rn(R[1], dx, __fmaf_rn(R[4], dy, __fmul_rn(R[7], dz)));
+    float Z = __fmaf_rn(R[2], dx, __fmaf_rn(R[5], dy, __fmul_rn(R[8], dz)));
+    if (!(Z > 0.0f)) return false;
+    float pu = __fmaf_rn(cam.fx, X / Z, cam.cx);
+    float pv = __fmaf_rn(cam.fy, Y / Z, cam.cy);
+    if (!(pu >= 0.0f && pu < (float)cam.width && pv >= 0.0f && pv < (float)cam.height)) return false;
+    int pi = (int)pu, pj = (int)pv;
+    float Dm = depth_v[(size_t)pj * cam.width + pi];
+    if (!(Dm > 0.0f && Dm <= 3.4028234663852886e38f)) return false;
+    float r = sqrtf(__fmaf_rn(dx, dx, __fmaf_rn(dy, dy, __fmul_rn(dz, dz))));
+    float phi = __fsub_rn(Dm, r);
+    if (phi < -eta) return false;
+    f = fminf(1.0f, fmaxf(-1.0f, phi / delta));
+    return true;
+}
+
+// Generalised shrinkage (the prox of the normalised weighted L1 data term):
+// the median of {F_(1..M)} and {u' - t S_k, k = 0..M}, S_k = 2 P_k - W_tot.
+// p_k is non-increasing and F_(k+1) non-decreasing in k, so the smallest k
+// with p_k <= F_(k+1) (F_(M+1) = +inf) selects the median as max(p_k, F_(k))
+// (F_(0) = -inf). Unit weights give S_k = 2k - M exactly. A zero is returned
+// as +0.
+__device__ inline float prox_select(float up, float t, int M, bool unit, const float *__restrict__ F,
+                                    const float *__restrict__ W, float wt) {
+    if (M == 0) return up + 0.0f;
+    int k = 0;
+    float pk;
+    if (unit) {
+        for (;;) {
+            pk = __fmaf_rn(-t, (float)(2 * k - M), up);
+            if (k == M || !(pk > F[k])) break;
+            ++k;
+        }
+    } else {
+        float P = 0.0f;
+        for (;;) {
+            pk = __fmaf_rn(-t, __fmaf_rn(2.0f, P, -wt), up);
+            if (k == M || !(pk > F[k])) break;
+            P = P + W[k];
+            ++k;
+        }
+    }
+    const float v = (k == 0 || pk >= F[k - 1]) ? pk : F[k - 1];
+    return v + 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// stores
+// ---------------------------------------------------------------------------
+// Per-view linear octrees, all views in one pool; each view's nodes in
+// (level, key) order with the 8 children of an inner node contiguous.
+struct ViewStore {
+    DBuf<float> S;
+    DBuf<uint32_t> cnt, child, key;
+    DBuf<uint8_t> level;
+    DBuf<uint32_t> root;               // per view: pool index of the root
+    std::vector<int64_t> count, base;  // per view node count and pool offset (host)
+    int64_t n_nodes = 0;
+};
+
+struct ViewDev {
+    const float *S;
+    const uint32_t *cnt;
+    const uint32_t *child;
+    const uint32_t *root;
+    int n_views;
+    int max_depth;
+};
+
+// Fused leaves: Morton-sorted structure of arrays.
+struct LeafStore {
+    DBuf<uint32_t> key;
+    DBuf<uint8_t> level;
+    DBuf<float> u, ubar, p, ds;  // p: 3 planes of `cap` floats (x, y, z)
+    DBuf<uint32_t> obs_off;
+    DBuf<uint8_t> obs_m, obs_unit;
+    DBuf<float> inv, wtot;
+    DBuf<uint32_t> nbp_off, nbm_off;  // cap + 1
+    DBuf<uint8_t> flag;
+    DBuf<float> uprime, uold;
+    int64_t cap = 0;
+    void reserve(int64_t n);
+};
+
+struct ObsPool {
+    DBuf<float> F, W;
+    int64_t used = 0, cap = 0;
+    void reserve(int64_t n);
+};
+
+// One round of the split cascade: the 8 children of every parent.
+struct Round {
+    DBuf<uint32_t> porigin;                    // per parent: origin leaf (old index)
+    DBuf<uint32_t> ckey, corigin, crank, cnt, pos;
+    DBuf<uint8_t> clevel, csplit;
+    DBuf<float> cu, cub;
+    int64_t np = 0, nc = 0;
+};
+
+// Scratch reused across phases.
+struct Scratch {
+    DBuf<uint32_t> a, b, c, d, e, f, g;
+    DBuf<uint8_t> u8a, u8b;
+    DBuf<float> fa, fb, fc, fd, fe;
+    DBuf<uint32_t> scan_lv[4];  // per-level tile sums of the device scans
+    DBuf<double> dred;
+    std::vector<Round *> rounds;
+    ~Scratch() {
+        for (Round *r : rounds) delete r;
+    }
+};
+
+enum ProfKind { kProfDual = 0, kProfPrimal = 1, kProfRestructure = 2, kProfEnergy = 3, kProfKinds = 4 };
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    otf_params prm{};
+    int n_views = 0;
+    int64_t iteration = 0;
+    bool valid = false;
+    ViewStore views;
+    LeafStore leaves[2];
+    int cur = 0;
+    int64_t L = 0;
+    ObsPool obs[2];
+    int ocur = 0;
+    DBuf<uint32_t> nbp, nbm;
+    int64_t n_nbp = 0, n_nbm = 0;
+    Coef coef{};
+    Scratch s;
+    DBuf<uint32_t> counters;        // device counters (split / join flags)
+    uint32_t *h_counters = nullptr;  // pinned mirror
+    int64_t last_splits = 0, last_joins = 0;
+    // profiling
+    bool prof = false;
+    double prof_ms[kProfKinds] = {0, 0, 0, 0};
+    int64_t prof_n[kProfKinds] = {0, 0, 0, 0};
+    int64_t prof_leaf_updates = 0;
+    double prof_bytes[2] = {0, 0};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    std::string err;
+
+    LeafStore &lv() { return leaves[cur]; }
+    ObsPool &op() { return obs[ocur]; }
+    ViewDev view_dev() const {
+        return ViewDev{views.S.p, views.cnt.p, views.child.p, views.root.p, n_views, prm.max_depth};
+    }
+};
+
+// ---------------------------------------------------------------------------
+// launchers (each issues work on ctx.stream)
+// ---------------------------------------------------------------------------
+// scans over n elements; the total is returned to the host (synchronises)
+uint32_t scan_exclusive_u8(Ctx &c, const uint8_t *in, uint32_t *out, int64_t n);
+uint32_t scan_exclusive_u32(Ctx &c, const uint32_t *in, uint32_t *out, int64_t n);
+// exclusive scan without a host read-back: out has n+1 entries, out[n] = total
+void scan_exclusive_u32_dev(Ctx &c, const uint32_t *in, uint32_t *out, int64_t n);
+void scan_inclusive_max_u32(Ctx &c, const uint32_t *in, uint32_t *out, int64_t n);
+
+// build: per-view trees, union structure, initial leaves (keys/levels only)
+void build_views_and_union(Ctx &c, const float *depth_dev, const std::vector<CamDev> &cams);
+// Observation gather for n targets. Target t is the node (tkey[h], tlevel[h])
+// with h = tidx ? tidx[t] : t.
+// gather_count: Mcount[t] = number of observations.
+// gather_fill: observations sorted by (F, view) at base + (out_off ? out_off[t]
+// : t * stride) in F / W; header (M, unit, inv, wtot, optional u0 and segment
+// offset) written at index h.
+void gather_count(Ctx &c, int64_t n, const uint32_t *tkey, const uint8_t *tlevel, const uint32_t *tidx,
+                  uint8_t *Mcount);
+void gather_fill(Ctx &c, int64_t n, const uint32_t *tkey, const uint8_t *tlevel, const uint32_t *tidx,
+                 const uint32_t *out_off, uint32_t base, int stride, float *F, float *W, uint8_t *M, uint8_t *unit,
+                 float *inv, float *wtot, float *u0, uint32_t *off_out);
+// pool-compacting gather for every leaf of the current store (two passes)
+void gather_all_leaves(Ctx &c, bool init_values);
+// face adjacency of the current leaf store
+void build_neighbours(Ctx &c);
+// sweeps
+void launch_dual(Ctx &c, float sigma);
+void launch_primal(Ctx &c, float tau, float tl);
+void energy(Ctx &c, double *tv, double *data);
+// split / join; returns true when the structure changed
+bool restructure(Ctx &c, float tl);
+
+// profiling helpers
+void prof_begin(Ctx &c);
+void prof_end(Ctx &c, ProfKind k);
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace otf

@@ -1,0 +1,522 @@
+// Split and join of leaves after the primal update (Sec. 3.2, the two
+// restructuring rules), keeping the leaf arrays in Morton order without a sort.
+//
+// Join: a leaf is joinable when |u+| > tau_j; an inner node collapses when
+// every leaf below it is joinable with one sign, and only the largest such node
+// is kept. Runs of consecutive same-sign joinable leaves are found with a
+// max-scan of run heads; a leaf's collapse node is the largest aligned block
+// containing it whose key range lies inside its run. The new leaf takes the
+// hierarchical means (1/8 of the sum of its 8 children, recursively) of u,
+// ubar and p.
+// Split: a leaf with |u+| < tau_s above max depth becomes 8 children that
+// inherit u', u_old and p; each child re-runs the prox on its own observations
+// and splits again while still flagged (rounds of one level each).
+// Emission: every old leaf contributes 0 (absorbed), 1 (kept or collapse
+// head) or its cascade's leaf count; an exclusive scan of these counts gives
+// the Morton-ordered positions in the new arrays.
+#include "otf_internal.h"
+
+namespace otf {
+namespace {
+
+constexpr int kBlk = 256;
+unsigned grid(int64_t n) { return (unsigned)cdiv(n > 0 ? n : 1, kBlk); }
+#define TID() ((int64_t)blockIdx.x * kBlk + threadIdx.x)
+
+__global__ void k_zero_counter2(uint32_t *counters) {
+    if (threadIdx.x == 0) counters[2] = 0u;
+}
+
+__global__ void k_split_bits(int64_t L, const uint8_t *flag, uint8_t *out) {
+    const int64_t i = TID();
+    if (i < L) out[i] = flag[i] & 1;
+}
+
+// ---------------------------------------------------------------- joins
+__global__ void k_run_heads(int64_t L, const uint8_t *flag, uint32_t *head) {
+    const int64_t i = TID();
+    if (i >= L) return;
+    const uint8_t j = flag[i] & 6;
+    const bool b = j && (i == 0 || (flag[i - 1] & 6) != j);
+    head[i] = b ? (uint32_t)i : 0u;
+}
+
+__global__ void k_run_ends(int64_t L, const uint8_t *flag, const uint32_t *rs, uint32_t *runend) {
+    const int64_t i = TID();
+    if (i >= L) return;
+    const uint8_t j = flag[i] & 6;
+    if (!j) return;
+    if (i == L - 1 || (flag[i + 1] & 6) != j) runend[rs[i]] = (uint32_t)i;
+}
+
+__global__ void k_join_target(int64_t L, int D, const uint8_t *flag, const uint32_t *key, const uint8_t *level,
+                              const uint32_t *rs, const uint32_t *runend, uint8_t *jt, uint8_t *jhead,
+                              uint32_t *counters) {
+    const int64_t i = TID();
+    if (i >= L) return;
+    uint8_t t = 0xFF, h = 0;
+    if (flag[i] & 6) {
+        const uint32_t s = rs[i], e = runend[s];
+        const uint64_t K0 = key[s];
+        const uint64_t K1 = (uint64_t)key[e] + (uint64_t(1) << (3 * (D - level[e])));
+        const int ln = level[i];
+        const uint64_t k = key[i];
+        for (int l = 0; l < ln; ++l) {
+            const uint64_t sz = uint64_t(1) << (3 * (D - l));
+            const uint64_t B0 = k & ~(sz - 1);
+            if (B0 >= K0 && B0 + sz <= K1) {
+                t = (uint8_t)l;
+                h = (k == B0) ? 1 : 0;
+                break;
+            }
+        }
+    }
+    jt[i] = t;
+    jhead[i] = h;
+    if (h) atomicAdd(&counters[2], 1u);
+}
+
+struct NewStore {
+    uint32_t *key;
+    uint8_t *level;
+    float *u, *ubar, *p;
+    int64_t cap;
+    uint32_t *obs_off;
+    uint8_t *obs_m, *obs_unit;
+    float *inv, *wtot;
+    uint8_t *isnew;
+};
+
+struct OldStore {
+    const uint32_t *key;
+    const uint8_t *level;
+    const float *u, *ubar, *p;
+    int64_t cap;
+    const uint32_t *obs_off;
+    const uint8_t *obs_m, *obs_unit;
+    const float *inv, *wtot;
+    const uint8_t *flag;
+};
+
+// Hierarchical means of the collapsed block, written by its first leaf.
+__global__ void k_join_emit(int64_t L, int D, OldStore o, const uint8_t *jt, const uint8_t *jhead,
+                            const uint32_t *out_off, NewStore ns) {
+    const int64_t i = TID();
+    if (i >= L || !jhead[i]) return;
+    const int tl = jt[i];
+    const uint64_t B0 = o.key[i];
+    const uint64_t B1 = B0 + (uint64_t(1) << (3 * (D - tl)));
+    float acc[kMaxDepth + 1][5];
+    int cnt[kMaxDepth + 1];
+    for (int a = 0; a <= kMaxDepth; ++a) {
+        cnt[a] = 0;
+        for (int q = 0; q < 5; ++q) acc[a][q] = 0.0f;
+    }
+    float v[5] = {0, 0, 0, 0, 0};
+    for (int64_t j = i; j < L && (uint64_t)o.key[j] < B1; ++j) {
+        v[0] = o.u[j];
+        v[1] = o.ubar[j];
+        v[2] = o.p[j];
+        v[3] = o.p[o.cap + j];
+        v[4] = o.p[2 * o.cap + j];
+        int lv = o.level[j];
+        while (lv > tl) {
+            const int a = lv - 1;
+            for (int q = 0; q < 5; ++q) acc[a][q] = acc[a][q] + v[q];
+            if (++cnt[a] < 8) break;
+            for (int q = 0; q < 5; ++q) {
+                v[q] = 0.125f * acc[a][q];
+                acc[a][q] = 0.0f;
+            }
+            cnt[a] = 0;
+            lv = a;
+        }
+    }
+    const uint32_t w = out_off[i];
+    ns.key[w] = (uint32_t)B0;
+    ns.level[w] = (uint8_t)tl;
+    ns.u[w] = v[0];
+    ns.ubar[w] = v[1];
+    ns.p[w] = v[2];
+    ns.p[ns.cap + w] = v[3];
+    ns.p[2 * ns.cap + w] = v[4];
+    ns.isnew[w] = 1;
+}
+
+// ---------------------------------------------------------------- splits
+__global__ void k_make_parents0(int64_t L, const uint8_t *flag, const uint32_t *rank, uint32_t *porigin) {
+    const int64_t i = TID();
+    if (i >= L || !(flag[i] & 1)) return;
+    porigin[rank[i]] = (uint32_t)i;
+}
+
+// children of round 0: parents are old leaves
+__global__ void k_children0(int64_t np, int D, const uint32_t *porigin, const uint32_t *key, const uint8_t *level,
+                            uint32_t *ckey, uint8_t *clevel, uint32_t *corigin) {
+    const int64_t j = TID();
+    if (j >= 8 * np) return;
+    const int64_t q = j >> 3;
+    const int c = (int)(j & 7);
+    const uint32_t o = porigin[q];
+    const int l = level[o] + 1;
+    ckey[j] = key[o] | ((uint32_t)c << (3 * (D - l)));
+    clevel[j] = (uint8_t)l;
+    corigin[j] = o;
+}
+
+// children of a later round: parents are the split children of the previous one
+__global__ void k_children_next(int64_t nc_prev, int D, const uint8_t *csplit, const uint32_t *crank,
+                                const uint32_t *pkey, const uint8_t *plevel, const uint32_t *porig,
+                                uint32_t *ckey, uint8_t *clevel, uint32_t *corigin) {
+    const int64_t jp = TID();
+    if (jp >= nc_prev || !csplit[jp]) return;
+    const int64_t q = crank[jp];
+    const int l = plevel[jp] + 1;
+    for (int c = 0; c < 8; ++c) {
+        ckey[8 * q + c] = pkey[jp] | ((uint32_t)c << (3 * (D - l)));
+        clevel[8 * q + c] = (uint8_t)l;
+        corigin[8 * q + c] = porig[jp];
+    }
+}
+
+__global__ void k_cascade_prox(int64_t nc, int stride, const float *tF, const float *tW, const uint8_t *tM,
+                               const uint8_t *tU, const float *tInv, const float *tWt, const uint32_t *corigin,
+                               const uint8_t *clevel, const float *uprime, const float *uold, float tl,
+                               float split_tau, int D, float *cu, float *cub, uint8_t *csplit) {
+    const int64_t j = TID();
+    if (j >= nc) return;
+    const uint32_t o = corigin[j];
+    const float up = uprime[o], uo = uold[o];
+    const float val =
+        prox_select(up, tl * tInv[j], tM[j], tU[j] != 0, tF + j * (int64_t)stride, tW + j * (int64_t)stride, tWt[j]);
+    cu[j] = val;
+    cub[j] = __fmaf_rn(2.0f, val, -uo);
+    csplit[j] = (fabsf(val) < split_tau && clevel[j] < D) ? 1 : 0;
+}
+
+__global__ void k_leafcnt(int64_t nc, const uint8_t *csplit, const uint32_t *crank, const uint32_t *next_cnt,
+                          uint32_t *cnt) {
+    const int64_t j = TID();
+    if (j >= nc) return;
+    uint32_t s = 1;
+    if (csplit[j]) {
+        const int64_t q = crank[j];
+        s = 0;
+        for (int c = 0; c < 8; ++c) s += next_cnt[8 * q + c];
+    }
+    cnt[j] = s;
+}
+
+// ---------------------------------------------------------------- emission
+__global__ void k_out_count(int64_t L, const uint8_t *flag, const uint8_t *jt, const uint8_t *jhead,
+                            const uint32_t *rank0, const uint32_t *cnt0, uint32_t *cnt) {
+    const int64_t i = TID();
+    if (i >= L) return;
+    uint32_t v = 1;
+    if (jt && jt[i] != 0xFF) {
+        v = jhead[i] ? 1u : 0u;
+    } else if (rank0 && (flag[i] & 1)) {
+        const int64_t q = rank0[i];
+        v = 0;
+        for (int c = 0; c < 8; ++c) v += cnt0[8 * q + c];
+    }
+    cnt[i] = v;
+}
+
+__global__ void k_emit_keep(int64_t L, OldStore o, const uint8_t *jt, int splits, const uint32_t *out_off,
+                            NewStore ns) {
+    const int64_t i = TID();
+    if (i >= L) return;
+    if ((jt && jt[i] != 0xFF) || (splits && (o.flag[i] & 1))) return;
+    const uint32_t w = out_off[i];
+    ns.key[w] = o.key[i];
+    ns.level[w] = o.level[i];
+    ns.u[w] = o.u[i];
+    ns.ubar[w] = o.ubar[i];
+    for (int d = 0; d < 3; ++d) ns.p[d * ns.cap + w] = o.p[d * o.cap + i];
+    ns.obs_off[w] = o.obs_off[i];
+    ns.obs_m[w] = o.obs_m[i];
+    ns.obs_unit[w] = o.obs_unit[i];
+    ns.inv[w] = o.inv[i];
+    ns.wtot[w] = o.wtot[i];
+    ns.isnew[w] = 0;
+}
+
+__global__ void k_pos0(int64_t nc, const uint32_t *corigin, const uint32_t *out_off, const uint32_t *cnt,
+                       uint32_t *pos) {
+    const int64_t j = TID();
+    if (j >= nc) return;
+    const int64_t q = j >> 3;
+    uint32_t b = out_off[corigin[j]];
+    for (int64_t c = 0; c < (j & 7); ++c) b += cnt[8 * q + c];
+    pos[j] = b;
+}
+
+// positions of round r+1 children from their parents (split children of round r)
+__global__ void k_pos_next(int64_t nc_prev, const uint8_t *csplit, const uint32_t *crank, const uint32_t *ppos,
+                           const uint32_t *cnt_next, uint32_t *pos_next) {
+    const int64_t jp = TID();
+    if (jp >= nc_prev || !csplit[jp]) return;
+    const int64_t q = crank[jp];
+    uint32_t b = ppos[jp];
+    for (int c = 0; c < 8; ++c) {
+        pos_next[8 * q + c] = b;
+        b += cnt_next[8 * q + c];
+    }
+}
+
+__global__ void k_emit_final(int64_t nc, const uint8_t *csplit, const uint32_t *pos, const uint32_t *ckey,
+                             const uint8_t *clevel, const uint32_t *corigin, const float *cu, const float *cub,
+                             const float *p_old, int64_t cap_old, NewStore ns) {
+    const int64_t j = TID();
+    if (j >= nc || csplit[j]) return;
+    const uint32_t w = pos[j];
+    const uint32_t o = corigin[j];
+    ns.key[w] = ckey[j];
+    ns.level[w] = clevel[j];
+    ns.u[w] = cu[j];
+    ns.ubar[w] = cub[j];
+    for (int d = 0; d < 3; ++d) ns.p[d * ns.cap + w] = p_old[d * cap_old + o];
+    ns.isnew[w] = 1;
+}
+
+__global__ void k_compact_idx(int64_t n, const uint8_t *flag, const uint32_t *rank, uint32_t *idx) {
+    const int64_t i = TID();
+    if (i >= n || !flag[i]) return;
+    idx[rank[i]] = (uint32_t)i;
+}
+
+__global__ void k_scatter_m(int64_t n, const uint32_t *tidx, const uint8_t *Mt, uint8_t *M) {
+    const int64_t t = TID();
+    if (t >= n) return;
+    M[tidx[t]] = Mt[t];
+}
+
+__global__ void k_copy_segments(int64_t L, const uint8_t *isnew, const uint8_t *M, const uint32_t *new_off,
+                                uint32_t *obs_off, const float *F0, const float *W0, float *F1, float *W1) {
+    const int64_t i = TID();
+    if (i >= L) return;
+    const uint32_t dst = new_off[i];
+    if (!isnew[i]) {
+        const uint32_t src = obs_off[i];
+        for (int k = 0; k < M[i]; ++k) {
+            F1[dst + k] = F0[src + k];
+            W1[dst + k] = W0[src + k];
+        }
+    }
+    obs_off[i] = dst;
+}
+
+__global__ void k_take(int64_t n, const uint32_t *tidx, const uint32_t *src, uint32_t *dst) {
+    const int64_t t = TID();
+    if (t < n) dst[t] = src[tidx[t]];
+}
+
+Round &round_at(Ctx &c, size_t r) {
+    while (c.s.rounds.size() <= r) c.s.rounds.push_back(new Round());
+    return *c.s.rounds[r];
+}
+
+uint32_t read_u32(Ctx &c, const uint32_t *dev, int slot) {
+    OTF_HIP(hipMemcpyAsync(c.h_counters + slot, dev, sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
+    OTF_HIP(hipStreamSynchronize(c.stream));
+    return c.h_counters[slot];
+}
+
+}  // namespace
+
+bool restructure(Ctx &c, float tl) {
+    const int D = c.prm.max_depth;
+    const int64_t L = c.L;
+    LeafStore &os = c.lv();
+    OTF_HIP(hipMemcpyAsync(c.h_counters, c.counters.p, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
+    OTF_HIP(hipStreamSynchronize(c.stream));
+    const uint32_t n_split = c.h_counters[0], n_join = c.h_counters[1];
+    c.last_splits = c.last_joins = 0;
+    if (n_split == 0 && n_join == 0) return false;
+    Scratch &s = c.s;
+    const unsigned gL = grid(L);
+
+    // ---- joins
+    uint8_t *jt = nullptr, *jhead = nullptr;
+    if (n_join > 0) {
+        s.a.reserve(L);
+        s.b.reserve(L);
+        s.c.reserve(L);
+        s.u8a.reserve(L);
+        s.u8b.reserve(L);
+        hipLaunchKernelGGL(k_run_heads, dim3(gL), dim3(kBlk), 0, c.stream, L, os.flag.p, s.a.p);
+        scan_inclusive_max_u32(c, s.a.p, s.b.p, L);
+        hipLaunchKernelGGL(k_run_ends, dim3(gL), dim3(kBlk), 0, c.stream, L, os.flag.p, s.b.p, s.c.p);
+        hipLaunchKernelGGL(k_zero_counter2, dim3(1), dim3(64), 0, c.stream, c.counters.p);
+        hipLaunchKernelGGL(k_join_target, dim3(gL), dim3(kBlk), 0, c.stream, L, D, os.flag.p, os.key.p, os.level.p,
+                           s.b.p, s.c.p, s.u8a.p, s.u8b.p, c.counters.p);
+        OTF_LAUNCH_CHECK("join analysis");
+        jt = s.u8a.p;
+        jhead = s.u8b.p;
+    }
+
+    // ---- split cascade
+    int64_t nrounds = 0, total_splits = 0;
+    uint32_t *rank0 = nullptr;
+    if (n_split > 0) {
+        s.d.reserve(L);
+        // rank of the split-flagged leaves
+        DBuf<uint8_t> sf;
+        sf.reserve(L);
+        hipLaunchKernelGGL(k_split_bits, dim3(gL), dim3(kBlk), 0, c.stream, L, os.flag.p, sf.p);
+        const uint32_t np0 = scan_exclusive_u8(c, sf.p, s.d.p, L);
+        rank0 = s.d.p;
+        Round &r0 = round_at(c, 0);
+        r0.np = np0;
+        r0.porigin.reserve(np0);
+        hipLaunchKernelGGL(k_make_parents0, dim3(gL), dim3(kBlk), 0, c.stream, L, os.flag.p, rank0, r0.porigin.p);
+        int64_t np = np0;
+        size_t r = 0;
+        const int stride = c.n_views;
+        while (np > 0) {
+            Round &R = round_at(c, r);
+            R.np = np;
+            R.nc = 8 * np;
+            const int64_t nc = R.nc;
+            R.ckey.reserve(nc);
+            R.corigin.reserve(nc);
+            R.crank.reserve(nc + 1);
+            R.cnt.reserve(nc);
+            R.pos.reserve(nc);
+            R.clevel.reserve(nc);
+            R.csplit.reserve(nc);
+            R.cu.reserve(nc);
+            R.cub.reserve(nc);
+            if (r == 0) {
+                hipLaunchKernelGGL(k_children0, dim3(grid(nc)), dim3(kBlk), 0, c.stream, np, D, R.porigin.p, os.key.p,
+                                   os.level.p, R.ckey.p, R.clevel.p, R.corigin.p);
+            } else {
+                Round &P = *s.rounds[r - 1];
+                hipLaunchKernelGGL(k_children_next, dim3(grid(P.nc)), dim3(kBlk), 0, c.stream, P.nc, D, P.csplit.p,
+                                   P.crank.p, P.ckey.p, P.clevel.p, P.corigin.p, R.ckey.p, R.clevel.p, R.corigin.p);
+            }
+            OTF_LAUNCH_CHECK("cascade children");
+            // observations of the children (stride n_views), then their prox
+            s.fa.reserve(nc * stride);
+            s.fb.reserve(nc * stride);
+            s.fc.reserve(nc);
+            s.fd.reserve(nc);
+            DBuf<uint8_t> tM, tU;
+            tM.reserve(nc);
+            tU.reserve(nc);
+            gather_fill(c, nc, R.ckey.p, R.clevel.p, nullptr, nullptr, 0, stride, s.fa.p, s.fb.p, tM.p, tU.p, s.fc.p,
+                        s.fd.p, nullptr, nullptr);
+            hipLaunchKernelGGL(k_cascade_prox, dim3(grid(nc)), dim3(kBlk), 0, c.stream, nc, stride, s.fa.p, s.fb.p,
+                               tM.p, tU.p, s.fc.p, s.fd.p, R.corigin.p, R.clevel.p, os.uprime.p, os.uold.p, tl,
+                               c.prm.split_tau, D, R.cu.p, R.cub.p, R.csplit.p);
+            OTF_LAUNCH_CHECK("k_cascade_prox");
+            const uint32_t next = scan_exclusive_u8(c, R.csplit.p, R.crank.p, nc);
+            OTF_HIP(hipStreamSynchronize(c.stream));  // tM / tU are freed on scope exit
+            total_splits += np;
+            np = next;
+            ++r;
+        }
+        nrounds = (int64_t)r;
+        // leaf counts bottom-up
+        for (int64_t q = nrounds - 1; q >= 0; --q) {
+            Round &R = *s.rounds[q];
+            const uint32_t *next_cnt = (q + 1 < nrounds) ? s.rounds[q + 1]->cnt.p : nullptr;
+            hipLaunchKernelGGL(k_leafcnt, dim3(grid(R.nc)), dim3(kBlk), 0, c.stream, R.nc, R.csplit.p, R.crank.p,
+                               next_cnt, R.cnt.p);
+            OTF_LAUNCH_CHECK("k_leafcnt");
+        }
+    }
+
+    // ---- emission
+    s.e.reserve(L + 1);
+    s.f.reserve(L + 1);
+    hipLaunchKernelGGL(k_out_count, dim3(gL), dim3(kBlk), 0, c.stream, L, os.flag.p, jt, jhead, rank0,
+                       nrounds ? s.rounds[0]->cnt.p : (const uint32_t *)nullptr, s.e.p);
+    OTF_LAUNCH_CHECK("k_out_count");
+    scan_exclusive_u32_dev(c, s.e.p, s.f.p, L);
+    const uint32_t *out_off = s.f.p;
+    const int64_t Lnew = read_u32(c, s.f.p + L, 12);
+    if (jt) c.last_joins = read_u32(c, c.counters.p + 2, 13);
+    c.last_splits = total_splits;
+    if (Lnew >= kLeafLimit) fail(OTF_E_CAPACITY, "leaf count exceeds 2^26");
+    if (c.prm.max_leaves > 0 && Lnew > c.prm.max_leaves) fail(OTF_E_CAPACITY, "leaf count exceeds max_leaves");
+
+    LeafStore &ns = c.leaves[c.cur ^ 1];
+    ns.reserve(Lnew);
+    DBuf<uint8_t> isnew;
+    isnew.reserve(Lnew);
+    NewStore nsd{ns.key.p, ns.level.p, ns.u.p, ns.ubar.p, ns.p.p, ns.cap, ns.obs_off.p, ns.obs_m.p, ns.obs_unit.p,
+                 ns.inv.p, ns.wtot.p, isnew.p};
+    OldStore osd{os.key.p, os.level.p, os.u.p, os.ubar.p, os.p.p, os.cap, os.obs_off.p, os.obs_m.p, os.obs_unit.p,
+                 os.inv.p, os.wtot.p, os.flag.p};
+    hipLaunchKernelGGL(k_emit_keep, dim3(gL), dim3(kBlk), 0, c.stream, L, osd, jt, n_split > 0 ? 1 : 0, out_off, nsd);
+    OTF_LAUNCH_CHECK("k_emit_keep");
+    if (jt) {
+        hipLaunchKernelGGL(k_join_emit, dim3(gL), dim3(kBlk), 0, c.stream, L, D, osd, jt, jhead, out_off, nsd);
+        OTF_LAUNCH_CHECK("k_join_emit");
+    }
+    for (int64_t q = 0; q < nrounds; ++q) {
+        Round &R = *s.rounds[q];
+        if (q == 0) {
+            hipLaunchKernelGGL(k_pos0, dim3(grid(R.nc)), dim3(kBlk), 0, c.stream, R.nc, R.corigin.p, out_off,
+                               R.cnt.p, R.pos.p);
+        }
+        hipLaunchKernelGGL(k_emit_final, dim3(grid(R.nc)), dim3(kBlk), 0, c.stream, R.nc, R.csplit.p, R.pos.p,
+                           R.ckey.p, R.clevel.p, R.corigin.p, R.cu.p, R.cub.p, os.p.p, os.cap, nsd);
+        if (q + 1 < nrounds) {
+            Round &Nx = *s.rounds[q + 1];
+            hipLaunchKernelGGL(k_pos_next, dim3(grid(R.nc)), dim3(kBlk), 0, c.stream, R.nc, R.csplit.p, R.crank.p,
+                               R.pos.p, Nx.cnt.p, Nx.pos.p);
+        }
+        OTF_LAUNCH_CHECK("cascade emission");
+    }
+
+    // ---- observations of the new leaves (append to the pool, or compact)
+    DBuf<uint32_t> nrank, tidx, moff;
+    nrank.reserve(Lnew + 1);
+    const uint32_t n_new = scan_exclusive_u8(c, isnew.p, nrank.p, Lnew);
+    tidx.reserve(n_new);
+    hipLaunchKernelGGL(k_compact_idx, dim3(grid(Lnew)), dim3(kBlk), 0, c.stream, Lnew, isnew.p, nrank.p, tidx.p);
+    DBuf<uint8_t> Mt;
+    Mt.reserve(n_new);
+    gather_count(c, n_new, ns.key.p, ns.level.p, tidx.p, Mt.p);
+    moff.reserve(n_new + 1);
+    const uint32_t new_obs = scan_exclusive_u8(c, Mt.p, moff.p, n_new);
+    hipLaunchKernelGGL(k_scatter_m, dim3(grid(n_new)), dim3(kBlk), 0, c.stream, (int64_t)n_new, tidx.p, Mt.p,
+                       ns.obs_m.p);
+    ObsPool &pool = c.op();
+    // live observations of the new store
+    DBuf<uint32_t> loff;
+    loff.reserve(Lnew + 1);
+    const uint32_t live = scan_exclusive_u8(c, ns.obs_m.p, loff.p, Lnew);
+    const bool compact = (pool.used + (int64_t)new_obs > pool.cap) || (pool.used > 2 * (int64_t)live + 4096);
+    if (!compact) {
+        gather_fill(c, n_new, ns.key.p, ns.level.p, tidx.p, moff.p, (uint32_t)pool.used, 0, pool.F.p, pool.W.p,
+                    ns.obs_m.p, ns.obs_unit.p, ns.inv.p, ns.wtot.p, nullptr, ns.obs_off.p);
+        pool.used += new_obs;
+    } else {
+        ObsPool &np = c.obs[c.ocur ^ 1];
+        np.reserve((int64_t)live + live / 4 + 1024);
+        hipLaunchKernelGGL(k_copy_segments, dim3(grid(Lnew)), dim3(kBlk), 0, c.stream, Lnew, isnew.p, ns.obs_m.p,
+                           loff.p, ns.obs_off.p, pool.F.p, pool.W.p, np.F.p, np.W.p);
+        OTF_LAUNCH_CHECK("k_copy_segments");
+        DBuf<uint32_t> toff;
+        toff.reserve(n_new);
+        hipLaunchKernelGGL(k_take, dim3(grid(n_new)), dim3(kBlk), 0, c.stream, (int64_t)n_new, tidx.p, loff.p, toff.p);
+        gather_fill(c, n_new, ns.key.p, ns.level.p, tidx.p, toff.p, 0, 0, np.F.p, np.W.p, ns.obs_m.p, ns.obs_unit.p,
+                    ns.inv.p, ns.wtot.p, nullptr, ns.obs_off.p);
+        np.used = live;
+        c.ocur ^= 1;
+        OTF_HIP(hipStreamSynchronize(c.stream));
+    }
+
+    // ---- switch to the new arrays and rebuild the adjacency
+    c.cur ^= 1;
+    c.L = Lnew;
+    build_neighbours(c);
+    OTF_HIP(hipStreamSynchronize(c.stream));  // temporaries are freed on return
+    return true;
+}
+
+}  // namespace otf

@@ -1,0 +1,232 @@
+"""Thin ctypes binding of libotf (include/otf.h): argument marshalling only.
+
+Every step of the fusion runs in the HIP library. PyTorch supplies the stream
+(and, optionally, device memory for the range maps). Loading fails loudly when
+the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from .synth import CAMERA_DTYPE
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libotf.so")
+
+PARAMS_DTYPE = np.dtype([
+    ("max_depth", "<i4"), ("delta", "<f4"), ("eta", "<f4"), ("spread_tau", "<f4"),
+    ("gamma", "<f4"), ("split_tau", "<f4"), ("join_tau", "<f4"),
+    ("restructure_every", "<i4"), ("max_leaves", "<i8"),
+])
+
+STATUS = {0: "OTF_OK", 1: "OTF_E_INVALID", 2: "OTF_E_NOMEM", 3: "OTF_E_CAPACITY", 4: "OTF_E_DEVICE",
+          5: "OTF_E_STATE"}
+PROFILE_KINDS = ("dual", "primal", "restructure", "energy")
+
+_lib = None
+
+
+class OtfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def lib():
+    """Load libotf.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise OSError(f"libotf.so not found at {LIB_PATH}; build it with paper_1608_07411_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
+        sig = {
+            "otf_create": [C.c_int, P, P],
+            "otf_destroy": [P],
+            "otf_build_octree": [P, P, I32, I32, P, P],
+            "otf_fuse": [P, I32, C.c_float, C.c_float, C.c_float],
+            "otf_num_leaves": [P, P],
+            "otf_extract": [P, I64, P, P, P, P, P, P],
+            "otf_extract_obs": [P, I64, P, P, P, I64, P, P, P],
+            "otf_extract_neighbours": [P, I64, P, I64, P, P],
+            "otf_energy": [P, P, P],
+            "otf_last_counts": [P, P, P],
+            "otf_export_state": [P, P, I64, P],
+            "otf_import_state": [P, P, I64],
+            "otf_profile": [P, I32],
+            "otf_profile_read": [P, P, P, P, P],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = C.c_int
+        L.otf_last_error.argtypes = [P]
+        L.otf_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def params_record(p: dict) -> np.ndarray:
+    r = np.zeros((), dtype=PARAMS_DTYPE)
+    for k in PARAMS_DTYPE.names:
+        r[k] = p.get(k, 0)
+    return r
+
+
+def _stream_handle(stream):
+    if stream is not None:
+        return C.c_void_p(int(stream))
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return C.c_void_p(int(torch.cuda.current_stream().cuda_stream))
+    except Exception:
+        pass
+    return C.c_void_p(0)
+
+
+class Context:
+    """One fused octree on one GPU (otf_ctx)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self._lib = lib()
+        self.h = C.c_void_p()
+        self._check(self._lib.otf_create(device, _stream_handle(stream), C.byref(self.h)), "otf_create")
+
+    def close(self):
+        if self.h:
+            self._lib.otf_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, what):
+        if st != 0:
+            msg = self._lib.otf_last_error(self.h).decode() if self.h else what
+            raise OtfError(st, f"{what}: {msg}")
+
+    # construction -----------------------------------------------------------
+    def build_octree(self, depth, cams: np.ndarray, params: dict):
+        cams = np.ascontiguousarray(cams, dtype=CAMERA_DTYPE)
+        prm = params_record(params)
+        is_dev = 0
+        keep = depth
+        if hasattr(depth, "is_cuda"):  # torch tensor
+            if depth.is_cuda:
+                keep = depth.contiguous().float()
+                ptr = C.c_void_p(keep.data_ptr())
+                is_dev = 1
+            else:
+                keep = depth.contiguous().float().numpy()
+                ptr = _ptr(keep)
+        else:
+            keep = np.ascontiguousarray(depth, dtype=np.float32)
+            ptr = _ptr(keep)
+        n_views = int(keep.shape[0])
+        self._check(self._lib.otf_build_octree(self.h, ptr, is_dev, n_views, _ptr(cams), _ptr(prm)),
+                    "otf_build_octree")
+        return self
+
+    def import_state(self, blob: bytes):
+        buf = np.frombuffer(blob, dtype=np.uint8).copy()
+        self._check(self._lib.otf_import_state(self.h, _ptr(buf), buf.size), "otf_import_state")
+        return self
+
+    def export_state(self) -> bytes:
+        n = C.c_int64(0)
+        self._check(self._lib.otf_export_state(self.h, None, 0, C.byref(n)), "otf_export_state")
+        buf = np.zeros(n.value, np.uint8)
+        self._check(self._lib.otf_export_state(self.h, _ptr(buf), buf.size, C.byref(n)), "otf_export_state")
+        return buf.tobytes()
+
+    # solver -----------------------------------------------------------------
+    def fuse(self, iterations: int, lam: float, tau: float, sigma: float):
+        self._check(self._lib.otf_fuse(self.h, int(iterations), lam, tau, sigma), "otf_fuse")
+        return self
+
+    def num_leaves(self) -> int:
+        n = C.c_int64(0)
+        self._check(self._lib.otf_num_leaves(self.h, C.byref(n)), "otf_num_leaves")
+        return n.value
+
+    def last_counts(self):
+        s, j = C.c_int64(0), C.c_int64(0)
+        self._check(self._lib.otf_last_counts(self.h, C.byref(s), C.byref(j)), "otf_last_counts")
+        return s.value, j.value
+
+    def extract(self) -> dict:
+        n = self.num_leaves()
+        keys = np.zeros(n, np.uint32)
+        levels = np.zeros(n, np.uint8)
+        u = np.zeros(n, np.float32)
+        ubar = np.zeros(n, np.float32)
+        p = np.zeros((n, 3), np.float32)
+        w = C.c_int64(0)
+        self._check(self._lib.otf_extract(self.h, n, _ptr(keys), _ptr(levels), _ptr(u), _ptr(ubar), _ptr(p),
+                                          C.byref(w)), "otf_extract")
+        return dict(keys=keys, levels=levels, u=u, ubar=ubar, p=p)
+
+    def extract_obs(self) -> dict:
+        n = self.num_leaves()
+        M = np.zeros(n, np.int32)
+        wtot = np.zeros(n, np.float32)
+        inv = np.zeros(n, np.float32)
+        tot = C.c_int64(0)
+        st = self._lib.otf_extract_obs(self.h, n, _ptr(M), _ptr(wtot), _ptr(inv), 0, None, None, C.byref(tot))
+        if st not in (0, 3):
+            self._check(st, "otf_extract_obs")
+        F = np.zeros(max(tot.value, 1), np.float32)
+        W = np.zeros(max(tot.value, 1), np.float32)
+        self._check(self._lib.otf_extract_obs(self.h, n, _ptr(M), _ptr(wtot), _ptr(inv), F.size, _ptr(F), _ptr(W),
+                                              C.byref(tot)), "otf_extract_obs")
+        off = np.zeros(n + 1, np.int64)
+        off[1:] = np.cumsum(M)
+        return dict(M=M, wtot=wtot, inv=inv, F=F[:tot.value], W=W[:tot.value], off=off)
+
+    def extract_neighbours(self):
+        n = self.num_leaves()
+        counts = np.zeros((n, 6), np.int32)
+        tot = C.c_int64(0)
+        st = self._lib.otf_extract_neighbours(self.h, n, _ptr(counts), 0, None, C.byref(tot))
+        if st not in (0, 3):
+            self._check(st, "otf_extract_neighbours")
+        idx = np.zeros(max(tot.value, 1), np.int64)
+        self._check(self._lib.otf_extract_neighbours(self.h, n, _ptr(counts), idx.size, _ptr(idx), C.byref(tot)),
+                    "otf_extract_neighbours")
+        return counts, idx[:tot.value]
+
+    def energy(self):
+        tv, data = C.c_double(0), C.c_double(0)
+        self._check(self._lib.otf_energy(self.h, C.byref(tv), C.byref(data)), "otf_energy")
+        return tv.value, data.value
+
+    # profiling --------------------------------------------------------------
+    def profile(self, enable: bool = True):
+        self._check(self._lib.otf_profile(self.h, 1 if enable else 0), "otf_profile")
+
+    def profile_read(self) -> dict:
+        ms = np.zeros(4)
+        n = np.zeros(4, np.int64)
+        lu = C.c_int64(0)
+        by = np.zeros(2)
+        self._check(self._lib.otf_profile_read(self.h, _ptr(ms), _ptr(n), C.byref(lu), _ptr(by)), "otf_profile_read")
+        out = {k: dict(ms=float(ms[i]), launches=int(n[i])) for i, k in enumerate(PROFILE_KINDS)}
+        out["leaf_updates"] = lu.value
+        out["bytes"] = dict(dual=float(by[0]), primal=float(by[1]))
+        return out
+
+
+def raw_status(fn_name: str, *args) -> int:
+    """Call an entry point directly and return its status (tests of error paths)."""
+    return getattr(lib(), fn_name)(*args)

@@ -1,0 +1,219 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+The oracle runs in its canonical fp32 mode, whose operation order the kernels
+follow, so structure, observations and values are compared bit for bit.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import Oracle
+from paper_1608_07411_amd import synth
+from tests.helpers import TAU32, base_params, blob_set, blob_volumes, parse_views, plane_volumes
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - the GPU suite runs on the MI355X machine
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1608_07411_amd import otf  # noqa: E402
+
+
+def _ctx():
+    return otf.Context(0)
+
+
+def _same_leaves(g: dict, o: dict, what=""):
+    assert np.array_equal(g["keys"], o["keys"]), f"{what}: keys differ"
+    assert np.array_equal(g["levels"], o["levels"]), f"{what}: levels differ"
+    for k in ("u", "ubar"):
+        a, b = g[k].astype(np.float64), o[k]
+        bad = np.nonzero(a != b)[0]
+        assert bad.size == 0, f"{what}: {k} differs at {bad[:5]} gpu={a[bad[:5]]} oracle={b[bad[:5]]}"
+    a, b = g["p"].astype(np.float64), o["p"]
+    assert np.array_equal(a, b), f"{what}: p differs"
+
+
+def _small_sphere(**kw):
+    return synth.sphere_workload(max_depth=kw.pop("max_depth", 5), n_views=kw.pop("n_views", 4), W=80, H=60,
+                                 f=75.0, **kw)
+
+
+def test_build_blob_identical():
+    w = _small_sphere()
+    g = _ctx().build_octree(w.depth, w.cams, w.params)
+    o = Oracle("f32").build(w.depth, w.cams, w.params)
+    gb, ob = g.export_state(), o.export_state()
+    gv, gl = parse_views(gb)
+    ov, ol = parse_views(ob)
+    for v in range(len(ov)):
+        assert np.array_equal(gv[v], ov[v]), f"view {v} octree differs"
+    assert np.array_equal(gl, ol)
+    assert gb == ob
+
+
+def test_build_from_device_depth_identical():
+    w = _small_sphere(n_views=3)
+    dev = torch.from_numpy(w.depth).cuda()
+    g = _ctx().build_octree(dev, w.cams, w.params)
+    h = _ctx().build_octree(w.depth, w.cams, w.params)
+    assert g.export_state() == h.export_state()
+
+
+def test_observations_and_adjacency_identical():
+    w = _small_sphere()
+    g = _ctx().build_octree(w.depth, w.cams, w.params)
+    o = Oracle("f32").build(w.depth, w.cams, w.params)
+    go, oo = g.extract_obs(), o.leaf_obs()
+    assert np.array_equal(go["M"], oo["M"])
+    for k in ("F", "W", "wtot", "inv"):
+        assert np.array_equal(go[k].astype(np.float64), oo[k]), k
+    gc, gi = g.extract_neighbours()
+    oc, oi = o.neighbours()
+    assert np.array_equal(gc, oc)
+    assert np.array_equal(gi, oi)
+
+
+@pytest.mark.parametrize("restructure", [0, 1])
+def test_free_running_parity_small(restructure):
+    w = _small_sphere()
+    prm = dict(w.params, restructure_every=restructure)
+    g = _ctx().build_octree(w.depth, w.cams, prm)
+    o = Oracle("f32").build(w.depth, w.cams, prm)
+    for step in range(6):
+        g.fuse(5, w.lam, w.tau, w.sigma)
+        o.fuse(5, w.lam, w.tau, w.sigma)
+        _same_leaves(g.extract(), o.extract(), f"after {5 * (step + 1)} iterations")
+        assert g.last_counts() == o.last_counts()
+
+
+def test_same_state_single_step_from_oracle_blob():
+    w = _small_sphere(n_views=3)
+    o = Oracle("f32").build(w.depth, w.cams, w.params)
+    o.fuse(3, w.lam, w.tau, w.sigma)
+    blob = o.export_state()
+    g = _ctx().import_state(blob)
+    assert g.export_state() == blob
+    o.fuse(1, w.lam, w.tau, w.sigma)
+    g.fuse(1, w.lam, w.tau, w.sigma)
+    assert g.last_counts() == o.last_counts()
+    assert g.export_state() == o.export_state()
+
+
+@pytest.mark.parametrize("maker,D,seed", [(plane_volumes, 4, 1), (blob_volumes, 5, 4), (blob_volumes, 5, 8)])
+def test_volume_states_parity(maker, D, seed):
+    f, w = maker(3, D, seed, p_unobs=0.2)
+    o = Oracle("f32").build_volumes(f, w, base_params(D))
+    g = _ctx().import_state(o.export_state())
+    for _ in range(4):
+        o.fuse(3, 0.5, TAU32, TAU32)
+        g.fuse(3, 0.5, TAU32, TAU32)
+        assert g.export_state() == o.export_state()
+
+
+def test_fully_refined_fixed_structure_parity():
+    D = 4
+    rng = np.random.default_rng(3)
+    G = 1 << D
+    f = rng.uniform(-1, 1, (4, G, G, G)).astype(np.float32)
+    w = (rng.uniform(size=(4, G, G, G)) > 0.3).astype(np.uint8)
+    w[0] = 1
+    prm = base_params(D, spread_tau=-1.0, split_tau=0.0, join_tau=2.0, restructure_every=0)
+    o = Oracle("f32").build_volumes(f, w, prm)
+    assert o.num_leaves() == G ** 3
+    g = _ctx().import_state(o.export_state())
+    o.fuse(40, 0.5, TAU32, TAU32)
+    g.fuse(40, 0.5, TAU32, TAU32)
+    _same_leaves(g.extract(), o.extract(), "fully refined")
+
+
+def test_sphere_workload_full_parity():
+    """The 64^3, 8-view sphere workload: 200 iterations with split and join."""
+    w = synth.workload(1)
+    g = _ctx().build_octree(w.depth, w.cams, w.params)
+    o = Oracle("f32").build(w.depth, w.cams, w.params)
+    assert g.export_state() == o.export_state()
+    for k in range(4):
+        g.fuse(50, w.lam, w.tau, w.sigma)
+        o.fuse(50, w.lam, w.tau, w.sigma)
+        _same_leaves(g.extract(), o.extract(), f"sphere after {50 * (k + 1)}")
+
+
+def test_energy_matches_oracle():
+    w = _small_sphere()
+    g = _ctx().build_octree(w.depth, w.cams, w.params)
+    o = Oracle("f32").build(w.depth, w.cams, w.params)
+    g.fuse(7, w.lam, w.tau, w.sigma)
+    o.fuse(7, w.lam, w.tau, w.sigma)
+    gt, gd = g.energy()
+    ot, od = o.energy()
+    assert abs(gt - ot) <= 1e-10 * abs(ot)
+    assert abs(gd - od) <= 1e-10 * abs(od)
+
+
+def test_lambda_infinity_single_view_gpu():
+    w = synth.sphere_workload(max_depth=5, n_views=1, W=80, H=60, f=75.0)
+    prm = dict(w.params, restructure_every=2)
+    g = _ctx().build_octree(w.depth, w.cams, prm)
+    g.fuse(7, 1e30, TAU32, TAU32)
+    ex = g.extract()
+    ob = g.extract_obs()
+    obs = ob["M"] == 1
+    assert obs.sum() > 100
+    assert np.array_equal(ex["u"][obs], ob["F"][ob["off"][:-1][obs]])
+
+
+def test_determinism_two_runs():
+    w = _small_sphere()
+    a = _ctx().build_octree(w.depth, w.cams, w.params).fuse(20, w.lam, w.tau, w.sigma)
+    b = _ctx().build_octree(w.depth, w.cams, w.params).fuse(20, w.lam, w.tau, w.sigma)
+    assert a.export_state() == b.export_state()
+
+
+def test_thresholds_disable_split_and_join_gpu():
+    w = _small_sphere()
+    g = _ctx().build_octree(w.depth, w.cams, dict(w.params, split_tau=0.0))
+    n0 = g.num_leaves()
+    for _ in range(5):
+        g.fuse(1, w.lam, w.tau, w.sigma)
+        assert g.last_counts()[0] == 0
+    assert g.num_leaves() <= n0
+    g = _ctx().build_octree(w.depth, w.cams, dict(w.params, join_tau=1.5))
+    for _ in range(5):
+        g.fuse(1, w.lam, w.tau, w.sigma)
+        assert g.last_counts()[1] == 0
+
+
+def test_error_paths():
+    w = _small_sphere(n_views=2)
+    g = _ctx()
+    with pytest.raises(otf.OtfError) as e:
+        g.fuse(1, 0.5, TAU32, TAU32)
+    assert e.value.status == 5  # no state yet
+    with pytest.raises(otf.OtfError) as e:
+        g.build_octree(w.depth, w.cams, dict(w.params, split_tau=0.95, join_tau=0.9))
+    assert e.value.status == 1
+    g.build_octree(w.depth, w.cams, w.params)
+    for bad in ((float("nan"), TAU32, TAU32), (0.5, 0.0, TAU32), (-1.0, TAU32, TAU32), (0.5, TAU32, float("inf"))):
+        with pytest.raises(otf.OtfError) as e:
+            g.fuse(1, *bad)
+        assert e.value.status == 1
+    g.fuse(1, 0.5, TAU32, TAU32)  # state is still valid after rejected arguments
+    # capacity: a leaf cap at the initial count, below what the first splits need
+    n0 = _ctx().build_octree(w.depth, w.cams, w.params).num_leaves()
+    h = _ctx().build_octree(w.depth, w.cams, dict(w.params, max_leaves=n0))
+    with pytest.raises(otf.OtfError) as e:
+        h.fuse(3, 0.5, TAU32, TAU32)
+    assert e.value.status == 3
+    with pytest.raises(otf.OtfError) as e:
+        h.extract()
+    assert e.value.status == 5
+    # a corrupt blob is rejected before any device work
+    blob = bytearray(g.export_state())
+    blob[0] = ord("X")
+    with pytest.raises(otf.OtfError) as e:
+        _ctx().import_state(bytes(blob))
+    assert e.value.status == 1
