@@ -73,19 +73,43 @@ void ObsPool::reserve(int64_t n) {
     cap = c;
 }
 
+namespace {
+hipEvent_t next_event(Ctx &c) {
+    if (c.ev_used == c.ev_pool.size()) {
+        hipEvent_t e;
+        OTF_HIP(hipEventCreate(&e));
+        c.ev_pool.push_back(e);
+    }
+    return c.ev_pool[c.ev_used++];
+}
+}  // namespace
+
 void prof_begin(Ctx &c) {
     if (!c.prof) return;
-    OTF_HIP(hipEventRecord(c.ev[0], c.stream));
+    c.prof_open = next_event(c);
+    OTF_HIP(hipEventRecord(c.prof_open, c.stream));
 }
 
 void prof_end(Ctx &c, ProfKind k) {
-    if (!c.prof) return;
-    OTF_HIP(hipEventRecord(c.ev[1], c.stream));
-    OTF_HIP(hipEventSynchronize(c.ev[1]));
-    float ms = 0.0f;
-    OTF_HIP(hipEventElapsedTime(&ms, c.ev[0], c.ev[1]));
-    c.prof_ms[k] += ms;
-    c.prof_n[k] += 1;
+    if (!c.prof || !c.prof_open) return;
+    hipEvent_t b = next_event(c);
+    OTF_HIP(hipEventRecord(b, c.stream));
+    c.prof_recs.push_back(Ctx::ProfRec{(int)k, c.prof_open, b});
+    c.prof_open = nullptr;
+}
+
+// Sum the recorded event pairs into the per-kind totals and recycle the events.
+void prof_collect(Ctx &c) {
+    if (c.prof_recs.empty()) return;
+    OTF_HIP(hipStreamSynchronize(c.stream));
+    for (const auto &r : c.prof_recs) {
+        float ms = 0.0f;
+        OTF_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+        c.prof_ms[r.kind] += ms;
+        c.prof_n[r.kind] += 1;
+    }
+    c.prof_recs.clear();
+    c.ev_used = 0;
 }
 
 namespace {
@@ -169,10 +193,29 @@ void setup_after_structure(Ctx &c, bool init_values) {
     gather_all_leaves(c, init_values);
     if (init_values) init_state_values(c);
     build_neighbours(c);
-    OTF_HIP(hipStreamSynchronize(c.stream));
+    count_obs(c);
 }
 
 }  // namespace
+
+// Algorithmic bytes of one dual sweep: every leaf reads its level, ubar and p
+// and its + adjacency (offset and entries), writes p and ds; a neighbour's
+// ubar is counted once per leaf, not per entry (a Morton sweep reuses it).
+double dual_bytes(const Ctx &c) {
+    const double L = (double)c.L;
+    return L * (1 + 4 + 12 + 4) + 4.0 * (double)c.n_nbp + L * (12 + 4);
+}
+
+// Algorithmic bytes of one primal sweep: level, ds, u, the - adjacency, p
+// once per leaf, the observation header (offset, count, unit flag, normaliser,
+// total weight) and segment (F, plus W for leaves with fractional weights);
+// writes u, ubar and the flag byte.
+double primal_bytes(const Ctx &c) {
+    const double L = (double)c.L;
+    return L * (1 + 4 + 4 + 12) + 4.0 * (double)c.n_nbm + L * (4 + 1 + 1 + 4 + 4) +
+           4.0 * (double)(c.obs_total + c.obs_nonunit) + L * (4 + 4 + 1);
+}
+
 }  // namespace otf
 
 using namespace otf;
@@ -234,8 +277,6 @@ otf_status otf_create(int device, void *hip_stream, otf_ctx **out) {
         void *h = nullptr;
         OTF_HIP(hipHostMalloc(&h, 16 * sizeof(uint32_t), hipHostMallocDefault));
         ctx->c.h_counters = (uint32_t *)h;
-        OTF_HIP(hipEventCreate(&ctx->c.ev[0]));
-        OTF_HIP(hipEventCreate(&ctx->c.ev[1]));
     });
     if (st != OTF_OK) {
         otf_destroy(ctx);
@@ -250,8 +291,7 @@ otf_status otf_destroy(otf_ctx *ctx) {
     (void)hipSetDevice(ctx->c.device);
     (void)hipStreamSynchronize(ctx->c.stream);
     if (ctx->c.h_counters) (void)hipHostFree(ctx->c.h_counters);
-    for (auto &e : ctx->c.ev)
-        if (e) (void)hipEventDestroy(e);
+    for (auto &e : ctx->c.ev_pool) (void)hipEventDestroy(e);
     delete ctx;
     return OTF_OK;
 }
@@ -325,15 +365,9 @@ otf_status otf_fuse(otf_ctx *ctx, int32_t iterations, float lambda, float tau, f
             prof_begin(c);
             launch_primal(c, tau, tl);
             prof_end(c, kProfPrimal);
-            c.prof_leaf_updates += c.L;
-            if (c.prof) {
-                const double E = (double)c.n_nbp, Em = (double)c.n_nbm;
-                // dual: ubar own + gathered, p r/w, ds w, + entries and offsets
-                c.prof_bytes[0] += 4.0 * c.L * (1 + 6 + 1 + 1) + 4.0 * E * 2 + 1.0 * c.L;
-                // primal: ds, u r/w, ubar w, p gathers, - entries and offsets, obs header and data
-                c.prof_bytes[1] += 4.0 * c.L * (1 + 2 + 1 + 1) + 4.0 * Em * 2 + c.L * (4.0 + 1 + 1 + 4 + 4 + 1) +
-                                   4.0 * (double)c.op().used;
-            }
+            c.leaf_updates += c.L;
+            c.alg_bytes[0] += dual_bytes(c);
+            c.alg_bytes[1] += primal_bytes(c);
             c.last_splits = c.last_joins = 0;
             if (c.prm.restructure_every > 0 && c.iteration % c.prm.restructure_every == 0) {
                 prof_begin(c);
@@ -649,28 +683,34 @@ otf_status otf_import_state(otf_ctx *ctx, const void *buf, int64_t n_bytes) {
 
 otf_status otf_profile(otf_ctx *ctx, int32_t enable) {
     if (!ctx) return OTF_E_INVALID;
-    ctx->c.prof = enable != 0;
-    for (int k = 0; k < kProfKinds; ++k) {
-        ctx->c.prof_ms[k] = 0.0;
-        ctx->c.prof_n[k] = 0;
-    }
-    ctx->c.prof_leaf_updates = 0;
-    ctx->c.prof_bytes[0] = ctx->c.prof_bytes[1] = 0.0;
-    return OTF_OK;
+    return guard(ctx, false, [&] {
+        Ctx &c = ctx->c;
+        prof_collect(c);
+        c.prof = enable != 0;
+        for (int k = 0; k < kProfKinds; ++k) {
+            c.prof_ms[k] = 0.0;
+            c.prof_n[k] = 0;
+        }
+        c.leaf_updates = 0;
+        c.alg_bytes[0] = c.alg_bytes[1] = 0.0;
+    });
 }
 
 otf_status otf_profile_read(otf_ctx *ctx, double *ms, int64_t *launches, int64_t *leaf_updates, double *bytes) {
     if (!ctx) return OTF_E_INVALID;
-    for (int k = 0; k < kProfKinds; ++k) {
-        if (ms) ms[k] = ctx->c.prof_ms[k];
-        if (launches) launches[k] = ctx->c.prof_n[k];
-    }
-    if (leaf_updates) *leaf_updates = ctx->c.prof_leaf_updates;
-    if (bytes) {
-        bytes[0] = ctx->c.prof_bytes[0];
-        bytes[1] = ctx->c.prof_bytes[1];
-    }
-    return OTF_OK;
+    return guard(ctx, false, [&] {
+        Ctx &c = ctx->c;
+        prof_collect(c);
+        for (int k = 0; k < kProfKinds; ++k) {
+            if (ms) ms[k] = c.prof_ms[k];
+            if (launches) launches[k] = c.prof_n[k];
+        }
+        if (leaf_updates) *leaf_updates = c.leaf_updates;
+        if (bytes) {
+            bytes[0] = c.alg_bytes[0];
+            bytes[1] = c.alg_bytes[1];
+        }
+    });
 }
 
 }  // extern "C"

@@ -145,6 +145,52 @@ void gather_launch(Ctx &c, int64_t n, const uint32_t *tkey, const uint8_t *tleve
 }
 }  // namespace
 
+namespace {
+__global__ void __launch_bounds__(kBlk) k_obs_sizes(int64_t L, const uint8_t *M, const uint8_t *unit,
+                                                    unsigned long long *out) {
+    __shared__ uint32_t st[kBlk], sn[kBlk];
+    const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
+    uint32_t m = 0, nu = 0;
+    if (i < L) {
+        m = M[i];
+        nu = unit[i] ? 0u : m;
+    }
+    st[threadIdx.x] = m;
+    sn[threadIdx.x] = nu;
+    __syncthreads();
+    for (int s = kBlk / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            st[threadIdx.x] += st[threadIdx.x + s];
+            sn[threadIdx.x] += sn[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicAdd(&out[0], (unsigned long long)st[0]);
+        atomicAdd(&out[1], (unsigned long long)sn[0]);
+    }
+}
+
+__global__ void k_zero_u64x2(unsigned long long *p) {
+    if (threadIdx.x < 2) p[threadIdx.x] = 0ull;
+}
+}  // namespace
+
+// Totals of observations (all leaves, and leaves with fractional weights).
+void count_obs(Ctx &c) {
+    unsigned long long *d = reinterpret_cast<unsigned long long *>(c.counters.p + 4);
+    hipLaunchKernelGGL(k_zero_u64x2, dim3(1), dim3(64), 0, c.stream, d);
+    hipLaunchKernelGGL(k_obs_sizes, dim3((unsigned)cdiv(c.L > 0 ? c.L : 1, kBlk)), dim3(kBlk), 0, c.stream, c.L,
+                       c.lv().obs_m.p, c.lv().obs_unit.p, d);
+    OTF_LAUNCH_CHECK("k_obs_sizes");
+    OTF_HIP(hipMemcpyAsync(c.h_counters + 4, c.counters.p + 4, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
+    OTF_HIP(hipStreamSynchronize(c.stream));
+    unsigned long long h[2];
+    std::memcpy(h, c.h_counters + 4, sizeof h);
+    c.obs_total = (int64_t)h[0];
+    c.obs_nonunit = (int64_t)h[1];
+}
+
 // Observation pool for every leaf of the current store, in leaf order.
 void gather_all_leaves(Ctx &c, bool init_values) {
     LeafStore &s = c.lv();

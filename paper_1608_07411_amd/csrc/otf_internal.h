@@ -257,13 +257,22 @@ struct Ctx {
     DBuf<uint32_t> counters;        // device counters (split / join flags)
     uint32_t *h_counters = nullptr;  // pinned mirror
     int64_t last_splits = 0, last_joins = 0;
-    // profiling
+    // profiling: event pairs recorded on the stream, summed when read
+    struct ProfRec {
+        int kind;
+        hipEvent_t a, b;
+    };
     bool prof = false;
+    std::vector<ProfRec> prof_recs;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    hipEvent_t prof_open = nullptr;
     double prof_ms[kProfKinds] = {0, 0, 0, 0};
     int64_t prof_n[kProfKinds] = {0, 0, 0, 0};
-    int64_t prof_leaf_updates = 0;
-    double prof_bytes[2] = {0, 0};
-    hipEvent_t ev[2] = {nullptr, nullptr};
+    int64_t leaf_updates = 0;     // sum over iterations of the leaf count (always counted)
+    double alg_bytes[2] = {0, 0};  // algorithmic bytes of the dual and primal sweeps (always counted)
+    // structure sizes for the algorithmic byte counts
+    int64_t obs_total = 0, obs_nonunit = 0;
     std::string err;
 
     LeafStore &lv() { return leaves[cur]; }
@@ -298,6 +307,8 @@ void gather_fill(Ctx &c, int64_t n, const uint32_t *tkey, const uint8_t *tlevel,
                  float *inv, float *wtot, float *u0, uint32_t *off_out);
 // pool-compacting gather for every leaf of the current store (two passes)
 void gather_all_leaves(Ctx &c, bool init_values);
+// totals of observations for the algorithmic byte counts (synchronises)
+void count_obs(Ctx &c);
 // face adjacency of the current leaf store
 void build_neighbours(Ctx &c);
 // sweeps

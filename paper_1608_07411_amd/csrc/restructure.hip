@@ -515,7 +515,7 @@ bool restructure(Ctx &c, float tl) {
     c.cur ^= 1;
     c.L = Lnew;
     build_neighbours(c);
-    OTF_HIP(hipStreamSynchronize(c.stream));  // temporaries are freed on return
+    count_obs(c);  // synchronises: temporaries are freed on return
     return true;
 }
 

@@ -226,6 +226,10 @@ class Context:
         out["bytes"] = dict(dual=float(by[0]), primal=float(by[1]))
         return out
 
+    def reset_counters(self, profile: bool):
+        """Zero the leaf-update and byte counters; enable or disable kernel timing."""
+        self.profile(profile)
+
 
 def raw_status(fn_name: str, *args) -> int:
     """Call an entry point directly and return its status (tests of error paths)."""

@@ -317,10 +317,19 @@ def _hemisphere_cams(rng: Stream, n, radius, f, W, H):
 
 
 def _render_all(prims, cams, noise):
+    """Render and perturb every view (views in parallel threads; each view's
+    result depends only on its own camera and random streams)."""
+    import concurrent.futures as cf
+    import os
+
     out = np.zeros((len(cams), int(cams[0]["height"]), int(cams[0]["width"])), dtype=np.float32)
-    for i, cam in enumerate(cams):
-        D = render(prims, cam)
-        out[i] = noise(i, cam, D).astype(np.float32)
+
+    def one(i):
+        out[i] = noise(i, cams[i], render(prims, cams[i])).astype(np.float32)
+
+    workers = max(1, min(16, os.cpu_count() or 1, len(cams)))
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(one, range(len(cams))))
     return out
 
 
