@@ -62,6 +62,8 @@ void LeafStore::reserve(int64_t n) {
     flag.reserve(c);
     uprime.reserve(c);
     uold.reserve(c);
+    src.reserve(c);
+    need.reserve(c);
     cap = c;
 }
 
@@ -203,7 +205,7 @@ void setup_after_structure(Ctx &c, bool init_values) {
 // ubar is counted once per leaf, not per entry (a Morton sweep reuses it).
 double dual_bytes(const Ctx &c) {
     const double L = (double)c.L;
-    return L * (1 + 4 + 12 + 4) + 4.0 * (double)c.n_nbp + L * (12 + 4);
+    return L * (1 + 4 + 12 + 4) + 4.0 * (double)c.leaves[c.cur].n_nbp + L * (12 + 4);
 }
 
 // Algorithmic bytes of one primal sweep: level, ds, u, the - adjacency, p
@@ -212,7 +214,7 @@ double dual_bytes(const Ctx &c) {
 // writes u, ubar and the flag byte.
 double primal_bytes(const Ctx &c) {
     const double L = (double)c.L;
-    return L * (1 + 4 + 4 + 12) + 4.0 * (double)c.n_nbm + L * (4 + 1 + 1 + 4 + 4) +
+    return L * (1 + 4 + 4 + 12) + 4.0 * (double)c.leaves[c.cur].n_nbm + L * (4 + 1 + 1 + 4 + 4) +
            4.0 * (double)(c.obs_total + c.obs_nonunit) + L * (4 + 4 + 1);
 }
 
@@ -470,10 +472,10 @@ otf_status otf_extract_neighbours(const otf_ctx *cctx, int64_t cap_leaves, int32
         const int64_t L = c.L;
         auto op = download(c, s.nbp_off.p, L + 1);
         auto om = download(c, s.nbm_off.p, L + 1);
-        auto ep = download(c, c.nbp.p, c.n_nbp);
-        auto em = download(c, c.nbm.p, c.n_nbm);
+        auto ep = download(c, s.nbp.p, s.n_nbp);
+        auto em = download(c, s.nbm.p, s.n_nbm);
         OTF_HIP(hipStreamSynchronize(c.stream));
-        *n_idx = c.n_nbp + c.n_nbm;
+        *n_idx = s.n_nbp + s.n_nbm;
         if (*n_idx > cap_idx) {
             cap_st = OTF_E_CAPACITY;
             return;

@@ -7,6 +7,8 @@
 // One segment of SEG lanes (a power of two >= n_views) per target node: lane j
 // descends view j's octree; the segment sorts by rank (each lane counts the
 // lanes ordered before it) and its first lane forms the sequential sums.
+#include <algorithm>
+
 #include "otf_internal.h"
 
 namespace otf {
@@ -149,11 +151,11 @@ namespace {
 __global__ void __launch_bounds__(kBlk) k_obs_sizes(int64_t L, const uint8_t *M, const uint8_t *unit,
                                                     unsigned long long *out) {
     __shared__ uint32_t st[kBlk], sn[kBlk];
-    const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
     uint32_t m = 0, nu = 0;
-    if (i < L) {
-        m = M[i];
-        nu = unit[i] ? 0u : m;
+    for (int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x; i < L; i += (int64_t)gridDim.x * kBlk) {
+        const uint32_t mi = M[i];
+        m += mi;
+        nu += unit[i] ? 0u : mi;
     }
     st[threadIdx.x] = m;
     sn[threadIdx.x] = nu;
@@ -180,7 +182,8 @@ __global__ void k_zero_u64x2(unsigned long long *p) {
 void count_obs(Ctx &c) {
     unsigned long long *d = reinterpret_cast<unsigned long long *>(c.counters.p + 4);
     hipLaunchKernelGGL(k_zero_u64x2, dim3(1), dim3(64), 0, c.stream, d);
-    hipLaunchKernelGGL(k_obs_sizes, dim3((unsigned)cdiv(c.L > 0 ? c.L : 1, kBlk)), dim3(kBlk), 0, c.stream, c.L,
+    const int64_t blocks = std::min<int64_t>(1024, cdiv(c.L > 0 ? c.L : 1, kBlk));
+    hipLaunchKernelGGL(k_obs_sizes, dim3((unsigned)blocks), dim3(kBlk), 0, c.stream, c.L,
                        c.lv().obs_m.p, c.lv().obs_unit.p, d);
     OTF_LAUNCH_CHECK("k_obs_sizes");
     OTF_HIP(hipMemcpyAsync(c.h_counters + 4, c.counters.p + 4, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));

@@ -1,16 +1,32 @@
 // Face adjacency of the fused octree (the neighbourhood of the forward and
 // backward differences, Sec. 3.2 and Fig. 5) on the Morton-sorted leaf array.
-// For each leaf and face, the same-size cell across the face is looked up by
-// binary search on the keys; if it is subdivided, its sub-cells touching the
-// face are visited depth first in child order, which yields ascending keys.
 // Entries: neighbour index | direction << 26 | neighbour level << 28.
-// + list (faces +x,+y,+z) feeds the gradient, - list (-x,-y,-z) the divergence.
+// + list (faces +x,+y,+z) feeds the gradient, - list (-x,-y,-z) the divergence;
+// within a face the neighbours are in ascending key (= index) order.
+//
+// For a leaf n and a face, the same-size cell across the face is located by a
+// binary search for the leaf containing its minimum corner. If that leaf is at
+// least as large as n it is the only neighbour. Otherwise the cell is a union
+// of smaller leaves, contiguous in the array from that leaf up to the first key
+// past the cell; the neighbours are those of them lying on the shared face.
+// A short range is scanned by the leaf's own thread; a long one (a large leaf
+// next to a finely split region) is handed to one wave that scans it 64 leaves
+// at a time and places the hits with a ballot and prefix popcounts.
+//
+// After a restructure only leaves that are new or touch a changed leaf are
+// searched: a kept leaf whose neighbours were all kept has the same neighbours
+// as before (the space next to its faces is covered by the same leaves), so
+// its lists are copied with indices mapped to the new positions; the mapping
+// is monotone, so the order is preserved.
+#include <algorithm>
+
 #include "otf_internal.h"
 
 namespace otf {
 namespace {
 
 constexpr int kBlk = 256;
+constexpr uint32_t kLight = 32;  // longest range scanned by a single thread
 
 __device__ inline int64_t find_leaf(const uint32_t *__restrict__ key, int64_t L, uint32_t k) {
     // largest i with key[i] <= k (key[0] == 0)
@@ -23,96 +39,274 @@ __device__ inline int64_t find_leaf(const uint32_t *__restrict__ key, int64_t L,
     return lo;
 }
 
-template <bool FILL>
-__global__ void __launch_bounds__(kBlk) k_nbr(int64_t L, const uint32_t *__restrict__ key,
-                                              const uint8_t *__restrict__ level, int D, uint32_t *cnt_p,
-                                              uint32_t *cnt_m, const uint32_t *__restrict__ off_p,
-                                              const uint32_t *__restrict__ off_m, uint32_t *ent_p, uint32_t *ent_m) {
+__device__ inline int64_t lower_bound(const uint32_t *__restrict__ key, int64_t lo, int64_t hi, uint64_t k) {
+    // first i in [lo, hi) with key[i] >= k, or hi
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((uint64_t)key[mid] < k) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+struct Face {
+    bool inside;     // the face is not on the domain boundary
+    bool single;     // one neighbour, at least as large: index j
+    int64_t j, hi;   // otherwise the cell's leaves are [j, hi)
+    uint32_t plane;  // coordinate of the shared face along d
+};
+
+__device__ inline Face locate(const uint32_t *__restrict__ key, const uint8_t *__restrict__ level, int64_t L, int D,
+                              const uint32_t xyz[3], int ln, int face) {
+    Face f{false, false, 0, 0, 0};
+    const uint32_t G = 1u << D, s = 1u << (D - ln);
+    const int d = face % 3;
+    uint32_t q[3] = {xyz[0], xyz[1], xyz[2]};
+    if (face < 3) {
+        if (q[d] + s >= G) return f;
+        q[d] += s;
+        f.plane = q[d];
+    } else {
+        if (q[d] == 0) return f;
+        q[d] -= s;
+        f.plane = xyz[d];
+    }
+    f.inside = true;
+    const uint32_t kq = morton3(q[0], q[1], q[2]);
+    f.j = find_leaf(key, L, kq);
+    if (level[f.j] <= ln) {
+        f.single = true;
+        return f;
+    }
+    f.hi = lower_bound(key, f.j, L, (uint64_t)kq + (uint64_t(1) << (3 * (D - ln))));
+    return f;
+}
+
+// Leaf m (inside the cell across `face`) lies on the shared face.
+__device__ inline bool on_face(uint32_t km, int lm, int D, int face, uint32_t plane) {
+    const int d = face % 3;
+    const uint32_t c = compact1by2(km >> d);
+    return face < 3 ? (c == plane) : (c + (1u << (D - lm)) == plane);
+}
+
+__device__ inline uint32_t entry(int64_t j, int face, int lj) {
+    return (uint32_t)j | ((uint32_t)(face % 3) << kIdxBits) | ((uint32_t)lj << (kIdxBits + 2));
+}
+
+struct NbrOld {  // previous store, for leaves that copy their lists
+    const uint8_t *need;
+    const uint32_t *src;
+    const uint32_t *off_p, *off_m, *ent_p, *ent_m;
+    const uint32_t *remap;
+};
+
+struct Heavy {
+    uint32_t *leaf;
+    uint8_t *face;
+    uint32_t *lo, *hi;
+    uint32_t *count;  // device counter
+    uint32_t cap;
+};
+
+__global__ void __launch_bounds__(kBlk) k_nbr_count(int64_t L, const uint32_t *__restrict__ key,
+                                                    const uint8_t *__restrict__ level, int D, uint32_t *cnt_p,
+                                                    uint32_t *cnt_m, uint32_t *fc, NbrOld old, Heavy hv) {
     const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
     if (i >= L) return;
-    const uint32_t G = 1u << D;
+    if (old.need && !old.need[i]) {
+        const uint32_t j = old.src[i];
+        cnt_p[i] = old.off_p[j + 1] - old.off_p[j];
+        cnt_m[i] = old.off_m[j + 1] - old.off_m[j];
+        return;
+    }
     const int ln = level[i];
-    const uint32_t s = 1u << (D - ln);
     uint32_t xyz[3];
     demorton3(key[i], xyz[0], xyz[1], xyz[2]);
     uint32_t np = 0, nm = 0;
-    uint32_t base_p = FILL ? off_p[i] : 0, base_m = FILL ? off_m[i] : 0;
-    // explicit DFS stack of (cell min-corner key, cell level)
-    uint32_t st_key[40];
-    uint8_t st_lvl[40];
     for (int face = 0; face < 6; ++face) {
-        const int d = face % 3;
-        const bool plus = face < 3;
-        uint32_t q[3] = {xyz[0], xyz[1], xyz[2]};
-        if (plus) {
-            if (q[d] + s >= G) continue;
-            q[d] += s;
-        } else {
-            if (q[d] == 0) continue;
-            q[d] -= s;
-        }
-        int sp = 0;
-        st_key[sp] = morton3(q[0], q[1], q[2]);
-        st_lvl[sp] = (uint8_t)ln;
-        ++sp;
-        while (sp > 0) {
-            --sp;
-            const uint32_t ck = st_key[sp];
-            const int cl = st_lvl[sp];
-            const int64_t j = find_leaf(key, L, ck);
-            const int lj = level[j];
-            if (lj <= cl) {
-                if (FILL) {
-                    const uint32_t e = (uint32_t)j | ((uint32_t)d << kIdxBits) | ((uint32_t)lj << (kIdxBits + 2));
-                    if (plus) ent_p[base_p + np] = e;
-                    else ent_m[base_m + nm] = e;
-                }
-                if (plus) ++np;
-                else ++nm;
+        const Face f = locate(key, level, L, D, xyz, ln, face);
+        uint32_t n = 0;
+        if (f.inside) {
+            if (f.single) {
+                n = 1;
+            } else if ((uint64_t)(f.hi - f.j) <= kLight) {
+                for (int64_t m = f.j; m < f.hi; ++m) n += on_face(key[m], level[m], D, face, f.plane) ? 1u : 0u;
             } else {
-                // the 4 children touching the face; pushed in reverse child order
-                const int shift = 3 * (D - cl - 1);
-                const int want = plus ? 0 : 1;
-                for (int ch = 7; ch >= 0; --ch) {
-                    if (((ch >> d) & 1) != want) continue;
-                    st_key[sp] = ck | ((uint32_t)ch << shift);
-                    st_lvl[sp] = (uint8_t)(cl + 1);
-                    ++sp;
+                const uint32_t slot = atomicAdd(hv.count, 1u);
+                if (slot < hv.cap) {
+                    hv.leaf[slot] = (uint32_t)i;
+                    hv.face[slot] = (uint8_t)face;
+                    hv.lo[slot] = (uint32_t)f.j;
+                    hv.hi[slot] = (uint32_t)f.hi;
                 }
             }
         }
+        fc[6 * i + face] = n;  // heavy faces are filled in by k_nbr_heavy
+        if (face < 3) np += n;
+        else nm += n;
     }
-    if (!FILL) {
-        cnt_p[i] = np;
-        cnt_m[i] = nm;
+    cnt_p[i] = np;
+    cnt_m[i] = nm;
+}
+
+// One wave per heavy face. count pass: add the hits to the face and leaf
+// counts. fill pass: write the entries after the leaf's earlier faces.
+template <bool FILL>
+__global__ void __launch_bounds__(kBlk) k_nbr_heavy(uint32_t n_items, Heavy hv, const uint32_t *__restrict__ key,
+                                                    const uint8_t *__restrict__ level, int D, uint32_t *fc,
+                                                    uint32_t *cnt_p, uint32_t *cnt_m, const uint32_t *off_p,
+                                                    const uint32_t *off_m, uint32_t *ent_p, uint32_t *ent_m) {
+    const uint32_t item = ((uint32_t)blockIdx.x * kBlk + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (item >= n_items) return;
+    const uint32_t i = hv.leaf[item];
+    const int face = hv.face[item];
+    const int64_t lo = hv.lo[item], hi = hv.hi[item];
+    const int ln = level[i];
+    uint32_t xyz[3];
+    demorton3(key[i], xyz[0], xyz[1], xyz[2]);
+    const int d = face % 3;
+    const uint32_t plane = face < 3 ? xyz[d] + (1u << (D - ln)) : xyz[d];
+    uint32_t w = 0;
+    if (FILL) {
+        w = face < 3 ? off_p[i] : off_m[i];
+        for (int f = (face < 3 ? 0 : 3); f < face; ++f) w += fc[6 * (int64_t)i + f];
+    }
+    uint32_t total = 0;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int64_t base = lo; base < hi; base += 64) {
+        const int64_t m = base + lane;
+        bool hit = false;
+        int lm = 0;
+        if (m < hi) {
+            lm = level[m];
+            hit = on_face(key[m], lm, D, face, plane);
+        }
+        const uint64_t b = __ballot(hit);
+        if (FILL && hit) {
+            const uint32_t pos = w + total + (uint32_t)__popcll(b & below);
+            if (face < 3) ent_p[pos] = entry(m, face, lm);
+            else ent_m[pos] = entry(m, face, lm);
+        }
+        total += (uint32_t)__popcll(b);
+    }
+    if (!FILL && lane == 0) {
+        fc[6 * (int64_t)i + face] = total;
+        atomicAdd(face < 3 ? &cnt_p[i] : &cnt_m[i], total);
     }
 }
 
-}  // namespace
+__global__ void __launch_bounds__(kBlk) k_nbr_fill(int64_t L, const uint32_t *__restrict__ key,
+                                                   const uint8_t *__restrict__ level, int D,
+                                                   const uint32_t *__restrict__ fc, const uint32_t *__restrict__ off_p,
+                                                   const uint32_t *__restrict__ off_m, uint32_t *ent_p,
+                                                   uint32_t *ent_m, NbrOld old) {
+    const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
+    if (i >= L) return;
+    if (old.need && !old.need[i]) {
+        const uint32_t j = old.src[i];
+        uint32_t w = off_p[i];
+        for (uint32_t e = old.off_p[j]; e < old.off_p[j + 1]; ++e, ++w) {
+            const uint32_t v = old.ent_p[e];
+            ent_p[w] = (v & ~kIdxMask) | old.remap[v & kIdxMask];
+        }
+        w = off_m[i];
+        for (uint32_t e = old.off_m[j]; e < old.off_m[j + 1]; ++e, ++w) {
+            const uint32_t v = old.ent_m[e];
+            ent_m[w] = (v & ~kIdxMask) | old.remap[v & kIdxMask];
+        }
+        return;
+    }
+    const int ln = level[i];
+    uint32_t xyz[3];
+    demorton3(key[i], xyz[0], xyz[1], xyz[2]);
+    uint32_t wp = off_p[i], wm = off_m[i];
+    for (int face = 0; face < 6; ++face) {
+        const uint32_t n = fc[6 * i + face];
+        uint32_t &w = face < 3 ? wp : wm;
+        uint32_t *ent = face < 3 ? ent_p : ent_m;
+        if (n == 0) continue;
+        const Face f = locate(key, level, L, D, xyz, ln, face);
+        if (f.single) {
+            ent[w] = entry(f.j, face, level[f.j]);
+        } else if ((uint64_t)(f.hi - f.j) <= kLight) {
+            uint32_t k = w;
+            for (int64_t m = f.j; m < f.hi; ++m) {
+                const int lm = level[m];
+                if (on_face(key[m], lm, D, face, f.plane)) ent[k++] = entry(m, face, lm);
+            }
+        }  // else: written by the heavy fill
+        w += n;
+    }
+}
 
-void build_neighbours(Ctx &c) {
+__global__ void k_zero1(uint32_t *p) {
+    if (threadIdx.x == 0) *p = 0u;
+}
+
+void build(Ctx &c, const NbrOld &old) {
     LeafStore &s = c.lv();
     const int64_t L = c.L;
+    const int D = c.prm.max_depth;
     const unsigned g = (unsigned)cdiv(L, kBlk);
     c.s.a.reserve(L + 1);
     c.s.b.reserve(L + 1);
-    hipLaunchKernelGGL(k_nbr<false>, dim3(g), dim3(kBlk), 0, c.stream, L, s.key.p, s.level.p, c.prm.max_depth,
-                       c.s.a.p, c.s.b.p, (const uint32_t *)nullptr, (const uint32_t *)nullptr, (uint32_t *)nullptr,
-                       (uint32_t *)nullptr);
-    OTF_LAUNCH_CHECK("k_nbr count");
+    c.s.g.reserve(6 * L);
+    uint32_t cap = (uint32_t)std::min<int64_t>(6 * L, std::max<int64_t>(4096, L / 8));
+    uint32_t n_heavy = 0;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        c.s.hv_leaf.reserve(cap);
+        c.s.hv_lo.reserve(cap);
+        c.s.hv_hi.reserve(cap);
+        c.s.hv_face.reserve(cap);
+        Heavy hv{c.s.hv_leaf.p, c.s.hv_face.p, c.s.hv_lo.p, c.s.hv_hi.p, c.counters.p + 3, cap};
+        hipLaunchKernelGGL(k_zero1, dim3(1), dim3(64), 0, c.stream, c.counters.p + 3);
+        hipLaunchKernelGGL(k_nbr_count, dim3(g), dim3(kBlk), 0, c.stream, L, s.key.p, s.level.p, D, c.s.a.p, c.s.b.p,
+                           c.s.g.p, old, hv);
+        OTF_LAUNCH_CHECK("k_nbr_count");
+        OTF_HIP(hipMemcpyAsync(c.h_counters + 3, c.counters.p + 3, sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
+        OTF_HIP(hipStreamSynchronize(c.stream));
+        n_heavy = c.h_counters[3];
+        if (n_heavy <= cap) break;
+        cap = n_heavy;  // rare: more long ranges than room; count again with room for all
+    }
+    Heavy hv{c.s.hv_leaf.p, c.s.hv_face.p, c.s.hv_lo.p, c.s.hv_hi.p, c.counters.p + 3, cap};
+    if (n_heavy > 0) {
+        hipLaunchKernelGGL(k_nbr_heavy<false>, dim3((unsigned)cdiv((int64_t)n_heavy * 64, kBlk)), dim3(kBlk), 0,
+                           c.stream, n_heavy, hv, s.key.p, s.level.p, D, c.s.g.p, c.s.a.p, c.s.b.p,
+                           (const uint32_t *)nullptr, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+                           (uint32_t *)nullptr);
+        OTF_LAUNCH_CHECK("k_nbr_heavy count");
+    }
     scan_exclusive_u32_dev(c, c.s.a.p, s.nbp_off.p, L);
     scan_exclusive_u32_dev(c, c.s.b.p, s.nbm_off.p, L);
     OTF_HIP(hipMemcpyAsync(c.h_counters + 10, s.nbp_off.p + L, sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
     OTF_HIP(hipMemcpyAsync(c.h_counters + 11, s.nbm_off.p + L, sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
     OTF_HIP(hipStreamSynchronize(c.stream));
-    c.n_nbp = c.h_counters[10];
-    c.n_nbm = c.h_counters[11];
-    c.nbp.reserve(c.n_nbp);
-    c.nbm.reserve(c.n_nbm);
-    hipLaunchKernelGGL(k_nbr<true>, dim3(g), dim3(kBlk), 0, c.stream, L, s.key.p, s.level.p, c.prm.max_depth,
-                       (uint32_t *)nullptr, (uint32_t *)nullptr, (const uint32_t *)s.nbp_off.p,
-                       (const uint32_t *)s.nbm_off.p, c.nbp.p, c.nbm.p);
-    OTF_LAUNCH_CHECK("k_nbr fill");
+    s.n_nbp = c.h_counters[10];
+    s.n_nbm = c.h_counters[11];
+    s.nbp.reserve(s.n_nbp);
+    s.nbm.reserve(s.n_nbm);
+    hipLaunchKernelGGL(k_nbr_fill, dim3(g), dim3(kBlk), 0, c.stream, L, s.key.p, s.level.p, D,
+                       (const uint32_t *)c.s.g.p, (const uint32_t *)s.nbp_off.p, (const uint32_t *)s.nbm_off.p,
+                       s.nbp.p, s.nbm.p, old);
+    OTF_LAUNCH_CHECK("k_nbr_fill");
+    if (n_heavy > 0) {
+        hipLaunchKernelGGL(k_nbr_heavy<true>, dim3((unsigned)cdiv((int64_t)n_heavy * 64, kBlk)), dim3(kBlk), 0,
+                           c.stream, n_heavy, hv, s.key.p, s.level.p, D, c.s.g.p, (uint32_t *)nullptr,
+                           (uint32_t *)nullptr, (const uint32_t *)s.nbp_off.p, (const uint32_t *)s.nbm_off.p, s.nbp.p,
+                           s.nbm.p);
+        OTF_LAUNCH_CHECK("k_nbr_heavy fill");
+    }
+}
+
+}  // namespace
+
+void build_neighbours(Ctx &c) { build(c, NbrOld{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr}); }
+
+void build_neighbours_incremental(Ctx &c, const LeafStore &old, const uint32_t *remap) {
+    const LeafStore &s = c.lv();
+    build(c, NbrOld{s.need.p, s.src.p, old.nbp_off.p, old.nbm_off.p, old.nbp.p, old.nbm.p, remap});
 }
 
 }  // namespace otf

@@ -201,8 +201,12 @@ struct LeafStore {
     DBuf<uint8_t> obs_m, obs_unit;
     DBuf<float> inv, wtot;
     DBuf<uint32_t> nbp_off, nbm_off;  // cap + 1
+    DBuf<uint32_t> nbp, nbm;          // adjacency entries (+ faces, - faces)
+    int64_t n_nbp = 0, n_nbm = 0;
     DBuf<uint8_t> flag;
     DBuf<float> uprime, uold;
+    DBuf<uint32_t> src;  // restructure: index of the leaf in the previous store, or kNone
+    DBuf<uint8_t> need;  // restructure: adjacency must be searched (new, or next to a change)
     int64_t cap = 0;
     void reserve(int64_t n);
 };
@@ -228,6 +232,8 @@ struct Scratch {
     DBuf<uint8_t> u8a, u8b;
     DBuf<float> fa, fb, fc, fd, fe;
     DBuf<uint32_t> scan_lv[4];  // per-level tile sums of the device scans
+    DBuf<uint32_t> hv_leaf, hv_lo, hv_hi;  // adjacency: faces with long ranges
+    DBuf<uint8_t> hv_face;
     DBuf<double> dred;
     std::vector<Round *> rounds;
     ~Scratch() {
@@ -250,8 +256,6 @@ struct Ctx {
     int64_t L = 0;
     ObsPool obs[2];
     int ocur = 0;
-    DBuf<uint32_t> nbp, nbm;
-    int64_t n_nbp = 0, n_nbm = 0;
     Coef coef{};
     Scratch s;
     DBuf<uint32_t> counters;        // device counters (split / join flags)
@@ -311,6 +315,10 @@ void gather_all_leaves(Ctx &c, bool init_values);
 void count_obs(Ctx &c);
 // face adjacency of the current leaf store
 void build_neighbours(Ctx &c);
+// Adjacency after a restructure: leaves marked in `need` are searched, the
+// others copy their lists from the previous store `old` (leaf src[i]) with
+// indices mapped through remap (old index -> new index).
+void build_neighbours_incremental(Ctx &c, const LeafStore &old, const uint32_t *remap);
 // sweeps
 void launch_dual(Ctx &c, float sigma);
 void launch_primal(Ctx &c, float tau, float tl);

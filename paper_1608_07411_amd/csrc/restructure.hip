@@ -85,6 +85,8 @@ struct NewStore {
     uint8_t *obs_m, *obs_unit;
     float *inv, *wtot;
     uint8_t *isnew;
+    uint32_t *src;
+    uint8_t *need;
 };
 
 struct OldStore {
@@ -141,6 +143,8 @@ __global__ void k_join_emit(int64_t L, int D, OldStore o, const uint8_t *jt, con
     ns.p[ns.cap + w] = v[3];
     ns.p[2 * ns.cap + w] = v[4];
     ns.isnew[w] = 1;
+    ns.src[w] = kNone;
+    ns.need[w] = 1;
 }
 
 // ---------------------------------------------------------------- splits
@@ -240,6 +244,31 @@ __global__ void k_emit_keep(int64_t L, OldStore o, const uint8_t *jt, int splits
     ns.inv[w] = o.inv[i];
     ns.wtot[w] = o.wtot[i];
     ns.isnew[w] = 0;
+    ns.src[w] = (uint32_t)i;
+    ns.need[w] = 0;
+}
+
+// A kept leaf next to a changed (absorbed, collapsed or split) leaf must have
+// its adjacency searched again.
+__device__ inline bool changed(int64_t j, const uint8_t *flag, const uint8_t *jt, int splits) {
+    return (jt && jt[j] != 0xFF) || (splits && (flag[j] & 1));
+}
+
+// Marked from the changed side (adjacency is symmetric): every kept neighbour
+// of a changed leaf. Concurrent stores all write 1.
+__global__ void k_nbr_mark(int64_t L, const uint8_t *flag, const uint8_t *jt, int splits, const uint32_t *off_p,
+                           const uint32_t *ent_p, const uint32_t *off_m, const uint32_t *ent_m,
+                           const uint32_t *out_off, uint8_t *need) {
+    const int64_t i = TID();
+    if (i >= L || !changed(i, flag, jt, splits)) return;
+    for (uint32_t e = off_p[i]; e < off_p[i + 1]; ++e) {
+        const uint32_t k = ent_p[e] & kIdxMask;
+        if (!changed(k, flag, jt, splits)) need[out_off[k]] = 1;
+    }
+    for (uint32_t e = off_m[i]; e < off_m[i + 1]; ++e) {
+        const uint32_t k = ent_m[e] & kIdxMask;
+        if (!changed(k, flag, jt, splits)) need[out_off[k]] = 1;
+    }
 }
 
 __global__ void k_pos0(int64_t nc, const uint32_t *corigin, const uint32_t *out_off, const uint32_t *cnt,
@@ -278,6 +307,8 @@ __global__ void k_emit_final(int64_t nc, const uint8_t *csplit, const uint32_t *
     ns.ubar[w] = cub[j];
     for (int d = 0; d < 3; ++d) ns.p[d * ns.cap + w] = p_old[d * cap_old + o];
     ns.isnew[w] = 1;
+    ns.src[w] = kNone;
+    ns.need[w] = 1;
 }
 
 __global__ void k_compact_idx(int64_t n, const uint8_t *flag, const uint32_t *rank, uint32_t *idx) {
@@ -292,19 +323,19 @@ __global__ void k_scatter_m(int64_t n, const uint32_t *tidx, const uint8_t *Mt, 
     M[tidx[t]] = Mt[t];
 }
 
+// One wave per leaf: lane k copies observation k (M <= 64).
 __global__ void k_copy_segments(int64_t L, const uint8_t *isnew, const uint8_t *M, const uint32_t *new_off,
                                 uint32_t *obs_off, const float *F0, const float *W0, float *F1, float *W1) {
-    const int64_t i = TID();
+    const int64_t i = ((int64_t)blockIdx.x * kBlk + threadIdx.x) >> 6;
+    const int k = threadIdx.x & 63;
     if (i >= L) return;
     const uint32_t dst = new_off[i];
-    if (!isnew[i]) {
+    if (!isnew[i] && k < M[i]) {
         const uint32_t src = obs_off[i];
-        for (int k = 0; k < M[i]; ++k) {
-            F1[dst + k] = F0[src + k];
-            W1[dst + k] = W0[src + k];
-        }
+        F1[dst + k] = F0[src + k];
+        W1[dst + k] = W0[src + k];
     }
-    obs_off[i] = dst;
+    if (k == 0) obs_off[i] = dst;
 }
 
 __global__ void k_take(int64_t n, const uint32_t *tidx, const uint32_t *src, uint32_t *dst) {
@@ -446,8 +477,8 @@ bool restructure(Ctx &c, float tl) {
     ns.reserve(Lnew);
     DBuf<uint8_t> isnew;
     isnew.reserve(Lnew);
-    NewStore nsd{ns.key.p, ns.level.p, ns.u.p, ns.ubar.p, ns.p.p, ns.cap, ns.obs_off.p, ns.obs_m.p, ns.obs_unit.p,
-                 ns.inv.p, ns.wtot.p, isnew.p};
+    NewStore nsd{ns.key.p, ns.level.p, ns.u.p,     ns.ubar.p, ns.p.p, ns.cap, ns.obs_off.p, ns.obs_m.p, ns.obs_unit.p,
+                 ns.inv.p, ns.wtot.p,  isnew.p, ns.src.p, ns.need.p};
     OldStore osd{os.key.p, os.level.p, os.u.p, os.ubar.p, os.p.p, os.cap, os.obs_off.p, os.obs_m.p, os.obs_unit.p,
                  os.inv.p, os.wtot.p, os.flag.p};
     hipLaunchKernelGGL(k_emit_keep, dim3(gL), dim3(kBlk), 0, c.stream, L, osd, jt, n_split > 0 ? 1 : 0, out_off, nsd);
@@ -498,8 +529,8 @@ bool restructure(Ctx &c, float tl) {
     } else {
         ObsPool &np = c.obs[c.ocur ^ 1];
         np.reserve((int64_t)live + live / 4 + 1024);
-        hipLaunchKernelGGL(k_copy_segments, dim3(grid(Lnew)), dim3(kBlk), 0, c.stream, Lnew, isnew.p, ns.obs_m.p,
-                           loff.p, ns.obs_off.p, pool.F.p, pool.W.p, np.F.p, np.W.p);
+        hipLaunchKernelGGL(k_copy_segments, dim3(grid(64 * Lnew)), dim3(kBlk), 0, c.stream, Lnew, isnew.p,
+                           ns.obs_m.p, loff.p, ns.obs_off.p, pool.F.p, pool.W.p, np.F.p, np.W.p);
         OTF_LAUNCH_CHECK("k_copy_segments");
         DBuf<uint32_t> toff;
         toff.reserve(n_new);
@@ -511,10 +542,13 @@ bool restructure(Ctx &c, float tl) {
         OTF_HIP(hipStreamSynchronize(c.stream));
     }
 
-    // ---- switch to the new arrays and rebuild the adjacency
+    // ---- adjacency: search only around changes
+    hipLaunchKernelGGL(k_nbr_mark, dim3(gL), dim3(kBlk), 0, c.stream, L, os.flag.p, jt, n_split > 0 ? 1 : 0,
+                       os.nbp_off.p, os.nbp.p, os.nbm_off.p, os.nbm.p, out_off, ns.need.p);
+    OTF_LAUNCH_CHECK("k_nbr_mark");
     c.cur ^= 1;
     c.L = Lnew;
-    build_neighbours(c);
+    build_neighbours_incremental(c, os, out_off);
     count_obs(c);  // synchronises: temporaries are freed on return
     return true;
 }

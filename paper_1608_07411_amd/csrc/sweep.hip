@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(kBlk) k_energy(int64_t L, int D, const uint8_t
 
 void launch_dual(Ctx &c, float sigma) {
     LeafStore &s = c.lv();
-    DualArgs a{c.L, s.cap, s.level.p, s.ubar.p, s.nbp_off.p, c.nbp.p, s.p.p, s.ds.p, sigma};
+    DualArgs a{c.L, s.cap, s.level.p, s.ubar.p, s.nbp_off.p, s.nbp.p, s.p.p, s.ds.p, sigma};
     hipLaunchKernelGGL(k_dual, dim3((unsigned)cdiv(c.L, kBlk)), dim3(kBlk), 0, c.stream, a, c.coef);
     OTF_LAUNCH_CHECK("k_dual");
 }
@@ -193,7 +193,7 @@ void launch_primal(Ctx &c, float tau, float tl) {
     a.ds = s.ds.p;
     a.p = s.p.p;
     a.off = s.nbm_off.p;
-    a.ent = c.nbm.p;
+    a.ent = s.nbm.p;
     a.obs_off = s.obs_off.p;
     a.obs_m = s.obs_m.p;
     a.obs_unit = s.obs_unit.p;
@@ -222,7 +222,7 @@ void energy(Ctx &c, double *tv, double *data) {
     const int64_t blocks = cdiv(c.L, kBlk);
     c.s.dred.reserve(2 * blocks);
     hipLaunchKernelGGL(k_energy, dim3((unsigned)blocks), dim3(kBlk), 0, c.stream, c.L, c.prm.max_depth, s.level.p,
-                       s.u.p, s.nbp_off.p, c.nbp.p, s.obs_off.p, s.obs_m.p, s.inv.p, c.op().F.p, c.op().W.p, c.coef,
+                       s.u.p, s.nbp_off.p, s.nbp.p, s.obs_off.p, s.obs_m.p, s.inv.p, c.op().F.p, c.op().W.p, c.coef,
                        c.s.dred.p);
     OTF_LAUNCH_CHECK("k_energy");
     std::vector<double> h(2 * blocks);

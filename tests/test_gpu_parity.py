@@ -77,6 +77,27 @@ def test_observations_and_adjacency_identical():
     assert np.array_equal(gi, oi)
 
 
+def test_adjacency_and_observations_after_restructuring():
+    """Incrementally rebuilt adjacency and appended observations equal the
+    oracle's from-scratch ones after many split/join steps."""
+    w = _small_sphere()
+    g = _ctx().build_octree(w.depth, w.cams, w.params)
+    o = Oracle("f32").build(w.depth, w.cams, w.params)
+    changed = 0
+    for _ in range(8):
+        g.fuse(2, w.lam, w.tau, w.sigma)
+        o.fuse(2, w.lam, w.tau, w.sigma)
+        changed += sum(o.last_counts())
+        gc, gi = g.extract_neighbours()
+        oc, oi = o.neighbours()
+        assert np.array_equal(gc, oc) and np.array_equal(gi, oi)
+        go, oo = g.extract_obs(), o.leaf_obs()
+        assert np.array_equal(go["M"], oo["M"])
+        for k in ("F", "W", "wtot", "inv"):
+            assert np.array_equal(go[k].astype(np.float64), oo[k]), k
+    assert changed > 0
+
+
 @pytest.mark.parametrize("restructure", [0, 1])
 def test_free_running_parity_small(restructure):
     w = _small_sphere()
