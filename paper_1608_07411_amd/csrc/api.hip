@@ -72,6 +72,7 @@ void ObsPool::reserve(int64_t n) {
     int64_t c = n < 1024 ? 1024 : n;
     F.reserve(c);
     W.reserve(c);
+    P.reserve(c);
     cap = c;
 }
 

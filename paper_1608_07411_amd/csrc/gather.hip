@@ -21,8 +21,8 @@ struct GatherOut {
     const uint32_t *off;   // per-target segment offset (+ base), or null: t * stride
     uint32_t base;
     int stride;
-    float *F, *W;
-    uint8_t *Mcount;  // count mode: M per target t
+    float *F, *W, *P;  // P may be null
+    uint8_t *Mcount;     // count mode: M per target t
     uint8_t *M, *unit;
     float *inv, *wtot, *u0;
     uint32_t *off_out;  // fill mode: segment offset written into the header, or null
@@ -91,6 +91,7 @@ __global__ void __launch_bounds__(kBlk) k_gather(ViewDev vd, int64_t n, const ui
         bool all1 = true;
         for (int k = 0; k < m; ++k) {
             const float wk = sW[seg_tid0 + k];
+            if (o.P) o.P[off + k] = P;
             P = P + wk;
             acc = __fmaf_rn(wk, sF[seg_tid0 + k], acc);
             all1 = all1 && (wk == 1.0f);
@@ -121,15 +122,16 @@ void gather_launch(Ctx &c, int64_t n, const uint32_t *tkey, const uint8_t *tleve
 void gather_count(Ctx &c, int64_t n, const uint32_t *tkey, const uint8_t *tlevel, const uint32_t *tidx,
                   uint8_t *Mcount) {
     if (n <= 0) return;
-    GatherOut o{tidx, nullptr, 0, 0, nullptr, nullptr, Mcount, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    GatherOut o{tidx,    nullptr, 0,       0,       nullptr, nullptr, nullptr,
+                Mcount,  nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     gather_launch(c, n, tkey, tlevel, o, true);
 }
 
 void gather_fill(Ctx &c, int64_t n, const uint32_t *tkey, const uint8_t *tlevel, const uint32_t *tidx,
-                 const uint32_t *out_off, uint32_t base, int stride, float *F, float *W, uint8_t *M, uint8_t *unit,
-                 float *inv, float *wtot, float *u0, uint32_t *off_out) {
+                 const uint32_t *out_off, uint32_t base, int stride, float *F, float *W, float *P, uint8_t *M,
+                 uint8_t *unit, float *inv, float *wtot, float *u0, uint32_t *off_out) {
     if (n <= 0) return;
-    GatherOut o{tidx, out_off, base, stride, F, W, nullptr, M, unit, inv, wtot, u0, off_out};
+    GatherOut o{tidx, out_off, base, stride, F, W, P, nullptr, M, unit, inv, wtot, u0, off_out};
     gather_launch(c, n, tkey, tlevel, o, false);
 }
 
@@ -202,7 +204,7 @@ void gather_all_leaves(Ctx &c, bool init_values) {
     c.ocur = 0;
     c.op().reserve(total + total / 4 + 1024);  // headroom for observations of new leaves
     c.op().used = total;
-    gather_fill(c, c.L, s.key.p, s.level.p, nullptr, s.obs_off.p, 0, 0, c.op().F.p, c.op().W.p, s.obs_m.p,
+    gather_fill(c, c.L, s.key.p, s.level.p, nullptr, s.obs_off.p, 0, 0, c.op().F.p, c.op().W.p, c.op().P.p, s.obs_m.p,
                 s.obs_unit.p, s.inv.p, s.wtot.p, init_values ? s.u.p : nullptr, nullptr);
 }
 

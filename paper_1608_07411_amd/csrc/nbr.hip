@@ -244,6 +244,19 @@ __global__ void k_zero1(uint32_t *p) {
     if (threadIdx.x == 0) *p = 0u;
 }
 
+// Work lists of the leaves whose + or - list is long (order irrelevant).
+__global__ void __launch_bounds__(kBlk) k_heavy_lists(int64_t L, const uint32_t *off_p, const uint32_t *off_m,
+                                                      uint32_t *hp, uint32_t *hm, uint32_t *counters) {
+    const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
+    if (i >= L) return;
+    if (off_p[i + 1] - off_p[i] > kLongList) hp[atomicAdd(&counters[0], 1u)] = (uint32_t)i;
+    if (off_m[i + 1] - off_m[i] > kLongList) hm[atomicAdd(&counters[1], 1u)] = (uint32_t)i;
+}
+
+__global__ void k_zero2(uint32_t *p) {
+    if (threadIdx.x < 2) p[threadIdx.x] = 0u;
+}
+
 void build(Ctx &c, const NbrOld &old) {
     LeafStore &s = c.lv();
     const int64_t L = c.L;
@@ -298,6 +311,17 @@ void build(Ctx &c, const NbrOld &old) {
                            s.nbm.p);
         OTF_LAUNCH_CHECK("k_nbr_heavy fill");
     }
+    s.heavy_p.reserve(L);
+    s.heavy_m.reserve(L);
+    hipLaunchKernelGGL(k_zero2, dim3(1), dim3(64), 0, c.stream, c.counters.p + 14);
+    hipLaunchKernelGGL(k_heavy_lists, dim3(g), dim3(kBlk), 0, c.stream, L, (const uint32_t *)s.nbp_off.p,
+                       (const uint32_t *)s.nbm_off.p, s.heavy_p.p, s.heavy_m.p, c.counters.p + 14);
+    OTF_LAUNCH_CHECK("k_heavy_lists");
+    OTF_HIP(hipMemcpyAsync(c.h_counters + 14, c.counters.p + 14, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                           c.stream));
+    OTF_HIP(hipStreamSynchronize(c.stream));
+    s.n_heavy_p = c.h_counters[14];
+    s.n_heavy_m = c.h_counters[15];
 }
 
 }  // namespace

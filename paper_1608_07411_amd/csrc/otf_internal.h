@@ -20,6 +20,8 @@ constexpr int kMaxDepth = 10;
 constexpr int kIdxBits = 26;
 constexpr uint32_t kIdxMask = (1u << kIdxBits) - 1u;
 constexpr int64_t kLeafLimit = int64_t(1) << kIdxBits;
+// adjacency lists longer than this are summed by a whole wave (see sweep.hip)
+constexpr uint32_t kLongList = 64;
 
 // ---------------------------------------------------------------------------
 // errors
@@ -207,12 +209,17 @@ struct LeafStore {
     DBuf<float> uprime, uold;
     DBuf<uint32_t> src;  // restructure: index of the leaf in the previous store, or kNone
     DBuf<uint8_t> need;  // restructure: adjacency must be searched (new, or next to a change)
+    DBuf<uint32_t> heavy_p, heavy_m;  // leaves whose + / - list is longer than kLongList
+    int64_t n_heavy_p = 0, n_heavy_m = 0;
     int64_t cap = 0;
     void reserve(int64_t n);
 };
 
+// Observation pool: per leaf a segment of M entries sorted by (F, view):
+// F, the weight W, and P = the sum of the weights before the entry (P_0 = 0,
+// formed sequentially in sorted order).
 struct ObsPool {
-    DBuf<float> F, W;
+    DBuf<float> F, W, P;
     int64_t used = 0, cap = 0;
     void reserve(int64_t n);
 };
@@ -307,8 +314,8 @@ void build_views_and_union(Ctx &c, const float *depth_dev, const std::vector<Cam
 void gather_count(Ctx &c, int64_t n, const uint32_t *tkey, const uint8_t *tlevel, const uint32_t *tidx,
                   uint8_t *Mcount);
 void gather_fill(Ctx &c, int64_t n, const uint32_t *tkey, const uint8_t *tlevel, const uint32_t *tidx,
-                 const uint32_t *out_off, uint32_t base, int stride, float *F, float *W, uint8_t *M, uint8_t *unit,
-                 float *inv, float *wtot, float *u0, uint32_t *off_out);
+                 const uint32_t *out_off, uint32_t base, int stride, float *F, float *W, float *P, uint8_t *M,
+                 uint8_t *unit, float *inv, float *wtot, float *u0, uint32_t *off_out);
 // pool-compacting gather for every leaf of the current store (two passes)
 void gather_all_leaves(Ctx &c, bool init_values);
 // totals of observations for the algorithmic byte counts (synchronises)

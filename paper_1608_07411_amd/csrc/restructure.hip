@@ -325,7 +325,8 @@ __global__ void k_scatter_m(int64_t n, const uint32_t *tidx, const uint8_t *Mt, 
 
 // One wave per leaf: lane k copies observation k (M <= 64).
 __global__ void k_copy_segments(int64_t L, const uint8_t *isnew, const uint8_t *M, const uint32_t *new_off,
-                                uint32_t *obs_off, const float *F0, const float *W0, float *F1, float *W1) {
+                                uint32_t *obs_off, const float *F0, const float *W0, const float *P0, float *F1,
+                                float *W1, float *P1) {
     const int64_t i = ((int64_t)blockIdx.x * kBlk + threadIdx.x) >> 6;
     const int k = threadIdx.x & 63;
     if (i >= L) return;
@@ -334,6 +335,7 @@ __global__ void k_copy_segments(int64_t L, const uint8_t *isnew, const uint8_t *
         const uint32_t src = obs_off[i];
         F1[dst + k] = F0[src + k];
         W1[dst + k] = W0[src + k];
+        P1[dst + k] = P0[src + k];
     }
     if (k == 0) obs_off[i] = dst;
 }
@@ -436,8 +438,8 @@ bool restructure(Ctx &c, float tl) {
             DBuf<uint8_t> tM, tU;
             tM.reserve(nc);
             tU.reserve(nc);
-            gather_fill(c, nc, R.ckey.p, R.clevel.p, nullptr, nullptr, 0, stride, s.fa.p, s.fb.p, tM.p, tU.p, s.fc.p,
-                        s.fd.p, nullptr, nullptr);
+            gather_fill(c, nc, R.ckey.p, R.clevel.p, nullptr, nullptr, 0, stride, s.fa.p, s.fb.p, nullptr, tM.p, tU.p,
+                        s.fc.p, s.fd.p, nullptr, nullptr);
             hipLaunchKernelGGL(k_cascade_prox, dim3(grid(nc)), dim3(kBlk), 0, c.stream, nc, stride, s.fa.p, s.fb.p,
                                tM.p, tU.p, s.fc.p, s.fd.p, R.corigin.p, R.clevel.p, os.uprime.p, os.uold.p, tl,
                                c.prm.split_tau, D, R.cu.p, R.cub.p, R.csplit.p);
@@ -524,19 +526,19 @@ bool restructure(Ctx &c, float tl) {
     const bool compact = (pool.used + (int64_t)new_obs > pool.cap) || (pool.used > 2 * (int64_t)live + 4096);
     if (!compact) {
         gather_fill(c, n_new, ns.key.p, ns.level.p, tidx.p, moff.p, (uint32_t)pool.used, 0, pool.F.p, pool.W.p,
-                    ns.obs_m.p, ns.obs_unit.p, ns.inv.p, ns.wtot.p, nullptr, ns.obs_off.p);
+                    pool.P.p, ns.obs_m.p, ns.obs_unit.p, ns.inv.p, ns.wtot.p, nullptr, ns.obs_off.p);
         pool.used += new_obs;
     } else {
         ObsPool &np = c.obs[c.ocur ^ 1];
         np.reserve((int64_t)live + live / 4 + 1024);
         hipLaunchKernelGGL(k_copy_segments, dim3(grid(64 * Lnew)), dim3(kBlk), 0, c.stream, Lnew, isnew.p,
-                           ns.obs_m.p, loff.p, ns.obs_off.p, pool.F.p, pool.W.p, np.F.p, np.W.p);
+                           ns.obs_m.p, loff.p, ns.obs_off.p, pool.F.p, pool.W.p, pool.P.p, np.F.p, np.W.p, np.P.p);
         OTF_LAUNCH_CHECK("k_copy_segments");
         DBuf<uint32_t> toff;
         toff.reserve(n_new);
         hipLaunchKernelGGL(k_take, dim3(grid(n_new)), dim3(kBlk), 0, c.stream, (int64_t)n_new, tidx.p, loff.p, toff.p);
-        gather_fill(c, n_new, ns.key.p, ns.level.p, tidx.p, toff.p, 0, 0, np.F.p, np.W.p, ns.obs_m.p, ns.obs_unit.p,
-                    ns.inv.p, ns.wtot.p, nullptr, ns.obs_off.p);
+        gather_fill(c, n_new, ns.key.p, ns.level.p, tidx.p, toff.p, 0, 0, np.F.p, np.W.p, np.P.p, ns.obs_m.p,
+                    ns.obs_unit.p, ns.inv.p, ns.wtot.p, nullptr, ns.obs_off.p);
         np.used = live;
         c.ocur ^= 1;
         OTF_HIP(hipStreamSynchronize(c.stream));

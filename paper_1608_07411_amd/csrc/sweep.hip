@@ -20,6 +20,11 @@ namespace {
 
 constexpr int kBlk = 256;
 
+__device__ inline float rdlane(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ inline int rdlane_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
 struct DualArgs {
     int64_t L, cap;
     const uint8_t *level;
@@ -31,14 +36,36 @@ struct DualArgs {
     float sigma;
 };
 
+// q = p + sigma g, projection onto the unit ball, and the leaf's own part of
+// the divergence from the updated p.
+__device__ inline void dual_finish(const DualArgs &a, int64_t i, float gx, float gy, float gz, float Cx, float Cy,
+                                   float Cz) {
+    float qx = __fmaf_rn(a.sigma, gx, a.p[i]);
+    float qy = __fmaf_rn(a.sigma, gy, a.p[a.cap + i]);
+    float qz = __fmaf_rn(a.sigma, gz, a.p[2 * a.cap + i]);
+    const float r2 = __fmaf_rn(qx, qx, __fmaf_rn(qy, qy, qz * qz));
+    if (r2 > 1.0f) {
+        const float nrm = sqrtf(r2);
+        qx = qx / nrm;
+        qy = qy / nrm;
+        qz = qz / nrm;
+    }
+    a.p[i] = qx;
+    a.p[a.cap + i] = qy;
+    a.p[2 * a.cap + i] = qz;
+    a.ds[i] = __fmaf_rn(Cz, qz, __fmaf_rn(Cy, qy, __fmaf_rn(Cx, qx, 0.0f)));
+}
+
+// One thread per leaf; leaves with a long + list are left to k_dual_long.
 __global__ void __launch_bounds__(kBlk) k_dual(DualArgs a, Coef cf) {
     const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
     if (i >= a.L) return;
+    const uint32_t e0 = a.off[i], e1 = a.off[i + 1];
+    if (e1 - e0 > kLongList) return;
     const int ln = a.level[i];
     const float ub = a.ubar[i];
     float gx = 0.0f, gy = 0.0f, gz = 0.0f, Cx = 0.0f, Cy = 0.0f, Cz = 0.0f;
-    const uint32_t e1 = a.off[i + 1];
-    for (uint32_t e = a.off[i]; e < e1; ++e) {
+    for (uint32_t e = e0; e < e1; ++e) {
         const uint32_t v = a.ent[e];
         const uint32_t k = v & kIdxMask;
         const int d = (v >> kIdxBits) & 3;
@@ -56,33 +83,61 @@ __global__ void __launch_bounds__(kBlk) k_dual(DualArgs a, Coef cf) {
             Cz = Cz + c;
         }
     }
-    float qx = __fmaf_rn(a.sigma, gx, a.p[i]);
-    float qy = __fmaf_rn(a.sigma, gy, a.p[a.cap + i]);
-    float qz = __fmaf_rn(a.sigma, gz, a.p[2 * a.cap + i]);
-    const float r2 = __fmaf_rn(qx, qx, __fmaf_rn(qy, qy, qz * qz));
-    if (r2 > 1.0f) {
-        const float nrm = sqrtf(r2);
-        qx = qx / nrm;
-        qy = qy / nrm;
-        qz = qz / nrm;
+    dual_finish(a, i, gx, gy, gz, Cx, Cy, Cz);
+}
+
+// One wave per leaf with a long + list: lanes fetch 64 entries at a time and
+// the wave then folds them in list order (the same sequential fma chain).
+__global__ void __launch_bounds__(kBlk) k_dual_long(uint32_t n, const uint32_t *list, DualArgs a, Coef cf) {
+    const uint32_t item = ((uint32_t)blockIdx.x * kBlk + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (item >= n) return;
+    const int64_t i = list[item];
+    const int ln = a.level[i];
+    const float ub = a.ubar[i];
+    const uint32_t e0 = a.off[i], e1 = a.off[i + 1];
+    float gx = 0.0f, gy = 0.0f, gz = 0.0f, Cx = 0.0f, Cy = 0.0f, Cz = 0.0f;
+    for (uint32_t base = e0; base < e1; base += 64) {
+        const uint32_t e = base + lane;
+        float c = 0.0f, diff = 0.0f;
+        int d = 0;
+        if (e < e1) {
+            const uint32_t v = a.ent[e];
+            d = (v >> kIdxBits) & 3;
+            c = cf.c[ln][v >> (kIdxBits + 2)];
+            diff = a.ubar[v & kIdxMask] - ub;
+        }
+        const int cnt = (int)min(64u, e1 - base);
+        for (int j = 0; j < cnt; ++j) {
+            const float cj = rdlane(c, j), vj = rdlane(diff, j);
+            const int dj = rdlane_i(d, j);
+            if (dj == 0) {
+                gx = __fmaf_rn(cj, vj, gx);
+                Cx = Cx + cj;
+            } else if (dj == 1) {
+                gy = __fmaf_rn(cj, vj, gy);
+                Cy = Cy + cj;
+            } else {
+                gz = __fmaf_rn(cj, vj, gz);
+                Cz = Cz + cj;
+            }
+        }
     }
-    a.p[i] = qx;
-    a.p[a.cap + i] = qy;
-    a.p[2 * a.cap + i] = qz;
-    a.ds[i] = __fmaf_rn(Cz, qz, __fmaf_rn(Cy, qy, __fmaf_rn(Cx, qx, 0.0f)));
+    if (lane == 0) dual_finish(a, i, gx, gy, gz, Cx, Cy, Cz);
 }
 
 struct PrimalArgs {
     int64_t L, cap;
     const uint8_t *level;
-    const float *ds;
+    float *ds;  // own divergence term; replaced by u' for leaves with a long - list
     const float *p;
     const uint32_t *off;
     const uint32_t *ent;
     const uint32_t *obs_off;
     const uint8_t *obs_m, *obs_unit;
     const float *inv, *wtot;
-    const float *F, *W;
+    const float *F, *P;
+    const float *u_in;
     float *u, *ubar;
     uint8_t *flag;
     float *uprime, *uold;
@@ -91,39 +146,109 @@ struct PrimalArgs {
     int join_enabled, max_depth;
 };
 
+// u' for leaves with a long - list, one wave each (sequential fma chain).
+__global__ void __launch_bounds__(kBlk) k_primal_long(uint32_t n, const uint32_t *list, PrimalArgs a, Coef cf) {
+    const uint32_t item = ((uint32_t)blockIdx.x * kBlk + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (item >= n) return;
+    const int64_t i = list[item];
+    const int ln = a.level[i];
+    const uint32_t e0 = a.off[i], e1 = a.off[i + 1];
+    float acc = a.ds[i];
+    for (uint32_t base = e0; base < e1; base += 64) {
+        const uint32_t e = base + lane;
+        float c = 0.0f, pm = 0.0f;
+        if (e < e1) {
+            const uint32_t v = a.ent[e];
+            c = cf.cp[v >> (kIdxBits + 2)][ln];
+            pm = a.p[(int64_t)((v >> kIdxBits) & 3) * a.cap + (v & kIdxMask)];
+        }
+        const int cnt = (int)min(64u, e1 - base);
+        for (int j = 0; j < cnt; ++j) acc = __fmaf_rn(-rdlane(c, j), rdlane(pm, j), acc);
+    }
+    if (lane == 0) a.ds[i] = __fmaf_rn(a.tau, acc, a.u_in[i]);
+}
+
+// Divergence per thread, then the prox cooperatively: the wave takes its 64
+// leaves one after another; lane k tests breakpoint k of the current leaf
+// (p_k = u' - t S_k against F_(k+1), coalesced loads of F and P), a ballot
+// counts the true predicates (a prefix: p_k falls, F rises), which is the
+// index k* of the sequential search; max(p_k*, F_(k*)) is the median.
 __global__ void __launch_bounds__(kBlk) k_primal(PrimalArgs a, Coef cf) {
     const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
-    bool split = false, join = false;
-    if (i < a.L) {
-        const int ln = a.level[i];
-        float acc = a.ds[i];
-        const uint32_t e1 = a.off[i + 1];
-        for (uint32_t e = a.off[i]; e < e1; ++e) {
-            const uint32_t v = a.ent[e];
-            const uint32_t m = v & kIdxMask;
-            const int d = (v >> kIdxBits) & 3;
-            const int lm = v >> (kIdxBits + 2);
-            acc = __fmaf_rn(-cf.cp[lm][ln], a.p[(int64_t)d * a.cap + m], acc);
+    const int lane = threadIdx.x & 63;
+    const bool valid = i < a.L;
+    float up = 0.0f, un = 0.0f, t = 0.0f, wt = 0.0f;
+    int M = 0, unit = 1, ln = 0;
+    uint32_t oo = 0;
+    if (valid) {
+        ln = a.level[i];
+        un = a.u_in[i];
+        const uint32_t e0 = a.off[i], e1 = a.off[i + 1];
+        if (e1 - e0 > kLongList) {
+            up = a.ds[i];
+        } else {
+            float acc = a.ds[i];
+            for (uint32_t e = e0; e < e1; ++e) {
+                const uint32_t v = a.ent[e];
+                const uint32_t m = v & kIdxMask;
+                const int d = (v >> kIdxBits) & 3;
+                const int lm = v >> (kIdxBits + 2);
+                acc = __fmaf_rn(-cf.cp[lm][ln], a.p[(int64_t)d * a.cap + m], acc);
+            }
+            up = __fmaf_rn(a.tau, acc, un);
         }
-        const float un = a.u[i];
-        const float up = __fmaf_rn(a.tau, acc, un);
-        const int M = a.obs_m[i];
-        const uint32_t oo = a.obs_off[i];
-        const float val = prox_select(up, a.tl * a.inv[i], M, a.obs_unit[i] != 0, a.F + oo, a.W + oo, a.wtot[i]);
-        a.ubar[i] = __fmaf_rn(2.0f, val, -un);
-        a.u[i] = val;
-        const float av = fabsf(val);
+        M = a.obs_m[i];
+        oo = a.obs_off[i];
+        unit = a.obs_unit[i];
+        t = a.tl * a.inv[i];
+        wt = a.wtot[i];
+    }
+    const uint64_t active = __ballot(valid);
+    float myv = 0.0f;
+    for (int l = 0; l < 64; ++l) {
+        if (!((active >> l) & 1ull)) break;  // valid lanes form a prefix of the wave
+        const int Ml = rdlane_i(M, l);
+        const float upl = rdlane(up, l);
+        float v = upl;
+        if (Ml > 0) {
+            const float tl_ = rdlane(t, l), wtl = rdlane(wt, l);
+            const uint32_t ool = (uint32_t)rdlane_i((int)oo, l);
+            const int unitl = rdlane_i(unit, l);
+            float Fk = 0.0f, pk = 0.0f;
+            bool pred = false;
+            if (lane < Ml) {
+                Fk = a.F[ool + lane];
+                const float S = unitl ? (float)(2 * lane - Ml) : __fmaf_rn(2.0f, a.P[ool + lane], -wtl);
+                pk = __fmaf_rn(-tl_, S, upl);
+                pred = pk > Fk;
+            }
+            const int ks = __popcll(__ballot(pred));
+            const float pks = (ks < Ml) ? rdlane(pk, ks) : __fmaf_rn(-tl_, unitl ? (float)Ml : wtl, upl);
+            v = pks;
+            if (ks > 0) {
+                const float Fp = rdlane(Fk, ks - 1);
+                v = (pks >= Fp) ? pks : Fp;
+            }
+        }
+        v = v + 0.0f;
+        if (lane == l) myv = v;
+    }
+    bool split = false, join = false;
+    if (valid) {
+        a.ubar[i] = __fmaf_rn(2.0f, myv, -un);
+        a.u[i] = myv;
+        const float av = fabsf(myv);
         split = av < a.split_tau && ln < a.max_depth;
         join = a.join_enabled && av > a.join_tau;
-        uint8_t fl = split ? 1 : (join ? (val > 0.0f ? 2 : 4) : 0);
-        a.flag[i] = fl;
+        a.flag[i] = split ? 1 : (join ? (myv > 0.0f ? 2 : 4) : 0);
         if (split) {
             a.uprime[i] = up;
             a.uold[i] = un;
         }
     }
     const uint64_t bs = __ballot(split), bj = __ballot(join);
-    if ((threadIdx.x & 63) == 0) {
+    if (lane == 0) {
         if (bs) atomicAdd(&a.counters[0], (uint32_t)__popcll(bs));
         if (bj) atomicAdd(&a.counters[1], (uint32_t)__popcll(bj));
     }
@@ -182,6 +307,11 @@ void launch_dual(Ctx &c, float sigma) {
     DualArgs a{c.L, s.cap, s.level.p, s.ubar.p, s.nbp_off.p, s.nbp.p, s.p.p, s.ds.p, sigma};
     hipLaunchKernelGGL(k_dual, dim3((unsigned)cdiv(c.L, kBlk)), dim3(kBlk), 0, c.stream, a, c.coef);
     OTF_LAUNCH_CHECK("k_dual");
+    if (s.n_heavy_p > 0) {
+        hipLaunchKernelGGL(k_dual_long, dim3((unsigned)cdiv(s.n_heavy_p * 64, kBlk)), dim3(kBlk), 0, c.stream,
+                           (uint32_t)s.n_heavy_p, s.heavy_p.p, a, c.coef);
+        OTF_LAUNCH_CHECK("k_dual_long");
+    }
 }
 
 void launch_primal(Ctx &c, float tau, float tl) {
@@ -200,7 +330,8 @@ void launch_primal(Ctx &c, float tau, float tl) {
     a.inv = s.inv.p;
     a.wtot = s.wtot.p;
     a.F = c.op().F.p;
-    a.W = c.op().W.p;
+    a.P = c.op().P.p;
+    a.u_in = s.u.p;
     a.u = s.u.p;
     a.ubar = s.ubar.p;
     a.flag = s.flag.p;
@@ -213,6 +344,11 @@ void launch_primal(Ctx &c, float tau, float tl) {
     a.join_tau = c.prm.join_tau;
     a.join_enabled = !(c.prm.join_tau > 1.0f);
     a.max_depth = c.prm.max_depth;
+    if (s.n_heavy_m > 0) {
+        hipLaunchKernelGGL(k_primal_long, dim3((unsigned)cdiv(s.n_heavy_m * 64, kBlk)), dim3(kBlk), 0, c.stream,
+                           (uint32_t)s.n_heavy_m, s.heavy_m.p, a, c.coef);
+        OTF_LAUNCH_CHECK("k_primal_long");
+    }
     hipLaunchKernelGGL(k_primal, dim3((unsigned)cdiv(c.L, kBlk)), dim3(kBlk), 0, c.stream, a, c.coef);
     OTF_LAUNCH_CHECK("k_primal");
 }
