@@ -10,8 +10,8 @@
 // of smaller leaves, contiguous in the array from that leaf up to the first key
 // past the cell; the neighbours are those of them lying on the shared face.
 // A short range is scanned by the leaf's own thread; a long one (a large leaf
-// next to a finely split region) is handed to one wave that scans it 64 leaves
-// at a time and places the hits with a ballot and prefix popcounts.
+// next to a finely split region) is cut into chunks, each scanned by one wave
+// 64 leaves at a time, the hits placed with a ballot and prefix popcounts.
 //
 // After a restructure only leaves that are new or touch a changed leaf are
 // searched: a kept leaf whose neighbours were all kept has the same neighbours
@@ -141,7 +141,7 @@ __global__ void __launch_bounds__(kBlk) k_nbr_count(int64_t L, const uint32_t *_
                 }
             }
         }
-        fc[6 * i + face] = n;  // heavy faces are filled in by k_nbr_heavy
+        fc[6 * i + face] = n;  // long ranges are counted by the chunk kernels
         if (face < 3) np += n;
         else nm += n;
     }
@@ -149,19 +149,44 @@ __global__ void __launch_bounds__(kBlk) k_nbr_count(int64_t L, const uint32_t *_
     cnt_m[i] = nm;
 }
 
-// One wave per heavy face. count pass: add the hits to the face and leaf
-// counts. fill pass: write the entries after the leaf's earlier faces.
+// Long ranges are cut into chunks of kChunk leaves, one wave per chunk.
+// count pass: hits per chunk. fill pass: hits written after the leaf's earlier
+// faces and the item's earlier chunks, in ascending index order (ballot and
+// prefix popcounts within the chunk).
+constexpr uint32_t kChunk = 2048;
+
+struct Chunks {
+    const uint32_t *item;  // chunk -> heavy item
+    const uint32_t *base;  // heavy item -> first chunk (n_items + 1)
+    uint32_t *count;       // hits per chunk
+    const uint32_t *pos;   // exclusive scan of count
+};
+
+__global__ void k_chunk_count(uint32_t n_items, Heavy hv, uint32_t *nch) {
+    const uint32_t t = blockIdx.x * kBlk + threadIdx.x;
+    if (t < n_items) nch[t] = (hv.hi[t] - hv.lo[t] + kChunk - 1) / kChunk;
+}
+
+__global__ void k_chunk_expand(uint32_t n_items, const uint32_t *base, uint32_t *item) {
+    const uint32_t t = blockIdx.x * kBlk + threadIdx.x;
+    if (t >= n_items) return;
+    for (uint32_t c = base[t]; c < base[t + 1]; ++c) item[c] = t;
+}
+
 template <bool FILL>
-__global__ void __launch_bounds__(kBlk) k_nbr_heavy(uint32_t n_items, Heavy hv, const uint32_t *__restrict__ key,
-                                                    const uint8_t *__restrict__ level, int D, uint32_t *fc,
-                                                    uint32_t *cnt_p, uint32_t *cnt_m, const uint32_t *off_p,
+__global__ void __launch_bounds__(kBlk) k_nbr_chunk(uint32_t n_chunks, Heavy hv, Chunks ch,
+                                                    const uint32_t *__restrict__ key,
+                                                    const uint8_t *__restrict__ level, int D,
+                                                    const uint32_t *__restrict__ fc, const uint32_t *off_p,
                                                     const uint32_t *off_m, uint32_t *ent_p, uint32_t *ent_m) {
-    const uint32_t item = ((uint32_t)blockIdx.x * kBlk + threadIdx.x) >> 6;
+    const uint32_t chunk = ((uint32_t)blockIdx.x * kBlk + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
-    if (item >= n_items) return;
+    if (chunk >= n_chunks) return;
+    const uint32_t item = ch.item[chunk];
     const uint32_t i = hv.leaf[item];
     const int face = hv.face[item];
-    const int64_t lo = hv.lo[item], hi = hv.hi[item];
+    const int64_t lo = (int64_t)hv.lo[item] + (int64_t)(chunk - ch.base[item]) * kChunk;
+    const int64_t hi = min((int64_t)hv.hi[item], lo + (int64_t)kChunk);
     const int ln = level[i];
     uint32_t xyz[3];
     demorton3(key[i], xyz[0], xyz[1], xyz[2]);
@@ -171,11 +196,12 @@ __global__ void __launch_bounds__(kBlk) k_nbr_heavy(uint32_t n_items, Heavy hv, 
     if (FILL) {
         w = face < 3 ? off_p[i] : off_m[i];
         for (int f = (face < 3 ? 0 : 3); f < face; ++f) w += fc[6 * (int64_t)i + f];
+        w += ch.pos[chunk] - ch.pos[ch.base[item]];
     }
     uint32_t total = 0;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int64_t base = lo; base < hi; base += 64) {
-        const int64_t m = base + lane;
+    for (int64_t b0 = lo; b0 < hi; b0 += 64) {
+        const int64_t m = b0 + lane;
         bool hit = false;
         int lm = 0;
         if (m < hi) {
@@ -190,10 +216,19 @@ __global__ void __launch_bounds__(kBlk) k_nbr_heavy(uint32_t n_items, Heavy hv, 
         }
         total += (uint32_t)__popcll(b);
     }
-    if (!FILL && lane == 0) {
-        fc[6 * (int64_t)i + face] = total;
-        atomicAdd(face < 3 ? &cnt_p[i] : &cnt_m[i], total);
-    }
+    if (!FILL && lane == 0) ch.count[chunk] = total;
+}
+
+// Per heavy item: face count from its chunks, added to the leaf's list count.
+__global__ void k_chunk_totals(uint32_t n_items, Heavy hv, Chunks ch, uint32_t *fc, uint32_t *cnt_p,
+                               uint32_t *cnt_m) {
+    const uint32_t t = blockIdx.x * kBlk + threadIdx.x;
+    if (t >= n_items) return;
+    const uint32_t total = ch.pos[ch.base[t + 1]] - ch.pos[ch.base[t]];
+    const uint32_t i = hv.leaf[t];
+    const int face = hv.face[t];
+    fc[6 * (int64_t)i + face] = total;
+    atomicAdd(face < 3 ? &cnt_p[i] : &cnt_m[i], total);
 }
 
 __global__ void __launch_bounds__(kBlk) k_nbr_fill(int64_t L, const uint32_t *__restrict__ key,
@@ -202,6 +237,29 @@ __global__ void __launch_bounds__(kBlk) k_nbr_fill(int64_t L, const uint32_t *__
                                                    const uint32_t *__restrict__ off_m, uint32_t *ent_p,
                                                    uint32_t *ent_m, NbrOld old) {
     const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    if (old.need) {
+        // a wave of 64 unchanged leaves with consecutive sources copies one
+        // contiguous block of entries, coalesced
+        const bool clean = i < L && !old.need[i];
+        const uint32_t j = clean ? old.src[i] : 0u;
+        const uint32_t j0 = (uint32_t)__builtin_amdgcn_readlane((int)j, 0);
+        if (__ballot(clean && j == j0 + (uint32_t)lane) == ~0ull) {
+            const uint32_t wp = (uint32_t)__builtin_amdgcn_readlane((int)off_p[i], 0);
+            const uint32_t wm = (uint32_t)__builtin_amdgcn_readlane((int)off_m[i], 0);
+            const uint32_t p0 = old.off_p[j0], p1 = old.off_p[j0 + 64];
+            const uint32_t m0 = old.off_m[j0], m1 = old.off_m[j0 + 64];
+            for (uint32_t e = p0 + lane; e < p1; e += 64) {
+                const uint32_t v = old.ent_p[e];
+                ent_p[wp + (e - p0)] = (v & ~kIdxMask) | old.remap[v & kIdxMask];
+            }
+            for (uint32_t e = m0 + lane; e < m1; e += 64) {
+                const uint32_t v = old.ent_m[e];
+                ent_m[wm + (e - m0)] = (v & ~kIdxMask) | old.remap[v & kIdxMask];
+            }
+            return;
+        }
+    }
     if (i >= L) return;
     if (old.need && !old.need[i]) {
         const uint32_t j = old.src[i];
@@ -284,12 +342,31 @@ void build(Ctx &c, const NbrOld &old) {
         cap = n_heavy;  // rare: more long ranges than room; count again with room for all
     }
     Heavy hv{c.s.hv_leaf.p, c.s.hv_face.p, c.s.hv_lo.p, c.s.hv_hi.p, c.counters.p + 3, cap};
+    Chunks ch{nullptr, nullptr, nullptr, nullptr};
+    uint32_t n_chunks = 0;
     if (n_heavy > 0) {
-        hipLaunchKernelGGL(k_nbr_heavy<false>, dim3((unsigned)cdiv((int64_t)n_heavy * 64, kBlk)), dim3(kBlk), 0,
-                           c.stream, n_heavy, hv, s.key.p, s.level.p, D, c.s.g.p, c.s.a.p, c.s.b.p,
+        const unsigned gi = (unsigned)cdiv(n_heavy, kBlk);
+        c.s.ch_base.reserve(n_heavy + 1);
+        hipLaunchKernelGGL(k_chunk_count, dim3(gi), dim3(kBlk), 0, c.stream, n_heavy, hv, c.s.ch_base.p);
+        scan_exclusive_u32_dev(c, c.s.ch_base.p, c.s.ch_base.p, n_heavy);
+        OTF_HIP(hipMemcpyAsync(c.h_counters + 3, c.s.ch_base.p + n_heavy, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                               c.stream));
+        OTF_HIP(hipStreamSynchronize(c.stream));
+        n_chunks = c.h_counters[3];
+        c.s.ch_item.reserve(n_chunks);
+        c.s.ch_count.reserve(n_chunks + 1);
+        c.s.ch_pos.reserve(n_chunks + 1);
+        ch = Chunks{c.s.ch_item.p, c.s.ch_base.p, c.s.ch_count.p, c.s.ch_pos.p};
+        hipLaunchKernelGGL(k_chunk_expand, dim3(gi), dim3(kBlk), 0, c.stream, n_heavy, c.s.ch_base.p, c.s.ch_item.p);
+        hipLaunchKernelGGL(k_nbr_chunk<false>, dim3((unsigned)cdiv((int64_t)n_chunks * 64, kBlk)), dim3(kBlk), 0,
+                           c.stream, n_chunks, hv, ch, s.key.p, s.level.p, D, (const uint32_t *)c.s.g.p,
                            (const uint32_t *)nullptr, (const uint32_t *)nullptr, (uint32_t *)nullptr,
                            (uint32_t *)nullptr);
-        OTF_LAUNCH_CHECK("k_nbr_heavy count");
+        OTF_LAUNCH_CHECK("k_nbr_chunk count");
+        scan_exclusive_u32_dev(c, c.s.ch_count.p, c.s.ch_pos.p, n_chunks);
+        hipLaunchKernelGGL(k_chunk_totals, dim3(gi), dim3(kBlk), 0, c.stream, n_heavy, hv, ch, c.s.g.p, c.s.a.p,
+                           c.s.b.p);
+        OTF_LAUNCH_CHECK("k_chunk_totals");
     }
     scan_exclusive_u32_dev(c, c.s.a.p, s.nbp_off.p, L);
     scan_exclusive_u32_dev(c, c.s.b.p, s.nbm_off.p, L);
@@ -305,11 +382,10 @@ void build(Ctx &c, const NbrOld &old) {
                        s.nbp.p, s.nbm.p, old);
     OTF_LAUNCH_CHECK("k_nbr_fill");
     if (n_heavy > 0) {
-        hipLaunchKernelGGL(k_nbr_heavy<true>, dim3((unsigned)cdiv((int64_t)n_heavy * 64, kBlk)), dim3(kBlk), 0,
-                           c.stream, n_heavy, hv, s.key.p, s.level.p, D, c.s.g.p, (uint32_t *)nullptr,
-                           (uint32_t *)nullptr, (const uint32_t *)s.nbp_off.p, (const uint32_t *)s.nbm_off.p, s.nbp.p,
-                           s.nbm.p);
-        OTF_LAUNCH_CHECK("k_nbr_heavy fill");
+        hipLaunchKernelGGL(k_nbr_chunk<true>, dim3((unsigned)cdiv((int64_t)n_chunks * 64, kBlk)), dim3(kBlk), 0,
+                           c.stream, n_chunks, hv, ch, s.key.p, s.level.p, D, (const uint32_t *)c.s.g.p,
+                           (const uint32_t *)s.nbp_off.p, (const uint32_t *)s.nbm_off.p, s.nbp.p, s.nbm.p);
+        OTF_LAUNCH_CHECK("k_nbr_chunk fill");
     }
     s.heavy_p.reserve(L);
     s.heavy_m.reserve(L);

@@ -241,6 +241,7 @@ struct Scratch {
     DBuf<uint32_t> scan_lv[4];  // per-level tile sums of the device scans
     DBuf<uint32_t> hv_leaf, hv_lo, hv_hi;  // adjacency: faces with long ranges
     DBuf<uint8_t> hv_face;
+    DBuf<uint32_t> ch_base, ch_item, ch_count, ch_pos;  // chunks of the long ranges
     DBuf<double> dred;
     std::vector<Round *> rounds;
     ~Scratch() {
