@@ -39,14 +39,38 @@ __device__ inline int64_t find_leaf(const uint32_t *__restrict__ key, int64_t L,
     return lo;
 }
 
-__device__ inline int64_t lower_bound(const uint32_t *__restrict__ key, int64_t lo, int64_t hi, uint64_t k) {
-    // first i in [lo, hi) with key[i] >= k, or hi
-    while (lo < hi) {
+// Bucket index over the key space: table[b] = the leaf containing the first
+// point of bucket b, so a lookup only searches between two table entries.
+struct KeyIndex {
+    const uint32_t *key;
+    int64_t L;
+    const uint32_t *table;
+    int shift;
+    uint32_t nb;
+};
+
+__global__ void k_key_table(const uint32_t *key, int64_t L, int shift, uint32_t nb, uint32_t *table) {
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < nb) table[b] = (uint32_t)find_leaf(key, L, b << shift);
+}
+
+// largest i with key[i] <= k
+__device__ inline int64_t find_leaf(const KeyIndex &ki, uint32_t k) {
+    const uint32_t b = k >> ki.shift;
+    int64_t lo = ki.table[b];
+    int64_t hi = (b + 1 < ki.nb) ? (int64_t)ki.table[b + 1] + 1 : ki.L;
+    while (hi - lo > 1) {
         const int64_t mid = (lo + hi) >> 1;
-        if ((uint64_t)key[mid] < k) lo = mid + 1;
+        if (ki.key[mid] <= k) lo = mid;
         else hi = mid;
     }
     return lo;
+}
+
+// first i with key[i] >= k (k may be the end of the domain)
+__device__ inline int64_t lower_bound(const KeyIndex &ki, uint64_t k, uint64_t domain) {
+    if (k >= domain) return ki.L;
+    return find_leaf(ki, (uint32_t)(k - 1)) + 1;
 }
 
 struct Face {
@@ -56,8 +80,8 @@ struct Face {
     uint32_t plane;  // coordinate of the shared face along d
 };
 
-__device__ inline Face locate(const uint32_t *__restrict__ key, const uint8_t *__restrict__ level, int64_t L, int D,
-                              const uint32_t xyz[3], int ln, int face) {
+__device__ inline Face locate(const KeyIndex &ki, const uint8_t *__restrict__ level, int D, const uint32_t xyz[3],
+                              int ln, int face) {
     Face f{false, false, 0, 0, 0};
     const uint32_t G = 1u << D, s = 1u << (D - ln);
     const int d = face % 3;
@@ -73,12 +97,12 @@ __device__ inline Face locate(const uint32_t *__restrict__ key, const uint8_t *_
     }
     f.inside = true;
     const uint32_t kq = morton3(q[0], q[1], q[2]);
-    f.j = find_leaf(key, L, kq);
+    f.j = find_leaf(ki, kq);
     if (level[f.j] <= ln) {
         f.single = true;
         return f;
     }
-    f.hi = lower_bound(key, f.j, L, (uint64_t)kq + (uint64_t(1) << (3 * (D - ln))));
+    f.hi = lower_bound(ki, (uint64_t)kq + (uint64_t(1) << (3 * (D - ln))), uint64_t(1) << (3 * D));
     return f;
 }
 
@@ -98,6 +122,8 @@ struct NbrOld {  // previous store, for leaves that copy their lists
     const uint32_t *src;
     const uint32_t *off_p, *off_m, *ent_p, *ent_m;
     const uint32_t *remap;
+    uint32_t *long_list;   // unchanged leaves with a long list, copied by a whole wave
+    uint32_t *long_count;  // device counter
 };
 
 struct Heavy {
@@ -108,15 +134,19 @@ struct Heavy {
     uint32_t cap;
 };
 
-__global__ void __launch_bounds__(kBlk) k_nbr_count(int64_t L, const uint32_t *__restrict__ key,
-                                                    const uint8_t *__restrict__ level, int D, uint32_t *cnt_p,
-                                                    uint32_t *cnt_m, uint32_t *fc, NbrOld old, Heavy hv) {
+__global__ void __launch_bounds__(kBlk) k_nbr_count(KeyIndex ki, const uint8_t *__restrict__ level, int D,
+                                                    uint32_t *cnt_p, uint32_t *cnt_m, uint32_t *fc, NbrOld old,
+                                                    Heavy hv) {
+    const int64_t L = ki.L;
+    const uint32_t *__restrict__ key = ki.key;
     const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
     if (i >= L) return;
     if (old.need && !old.need[i]) {
         const uint32_t j = old.src[i];
-        cnt_p[i] = old.off_p[j + 1] - old.off_p[j];
-        cnt_m[i] = old.off_m[j + 1] - old.off_m[j];
+        const uint32_t np = old.off_p[j + 1] - old.off_p[j], nm = old.off_m[j + 1] - old.off_m[j];
+        cnt_p[i] = np;
+        cnt_m[i] = nm;
+        if (np > kLongList || nm > kLongList) old.long_list[atomicAdd(old.long_count, 1u)] = (uint32_t)i;
         return;
     }
     const int ln = level[i];
@@ -124,7 +154,7 @@ __global__ void __launch_bounds__(kBlk) k_nbr_count(int64_t L, const uint32_t *_
     demorton3(key[i], xyz[0], xyz[1], xyz[2]);
     uint32_t np = 0, nm = 0;
     for (int face = 0; face < 6; ++face) {
-        const Face f = locate(key, level, L, D, xyz, ln, face);
+        const Face f = locate(ki, level, D, xyz, ln, face);
         uint32_t n = 0;
         if (f.inside) {
             if (f.single) {
@@ -231,11 +261,12 @@ __global__ void k_chunk_totals(uint32_t n_items, Heavy hv, Chunks ch, uint32_t *
     atomicAdd(face < 3 ? &cnt_p[i] : &cnt_m[i], total);
 }
 
-__global__ void __launch_bounds__(kBlk) k_nbr_fill(int64_t L, const uint32_t *__restrict__ key,
-                                                   const uint8_t *__restrict__ level, int D,
+__global__ void __launch_bounds__(kBlk) k_nbr_fill(KeyIndex ki, const uint8_t *__restrict__ level, int D,
                                                    const uint32_t *__restrict__ fc, const uint32_t *__restrict__ off_p,
                                                    const uint32_t *__restrict__ off_m, uint32_t *ent_p,
                                                    uint32_t *ent_m, NbrOld old) {
+    const int64_t L = ki.L;
+    const uint32_t *__restrict__ key = ki.key;
     const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
     const int lane = threadIdx.x & 63;
     if (old.need) {
@@ -263,6 +294,7 @@ __global__ void __launch_bounds__(kBlk) k_nbr_fill(int64_t L, const uint32_t *__
     if (i >= L) return;
     if (old.need && !old.need[i]) {
         const uint32_t j = old.src[i];
+        if (old.off_p[j + 1] - old.off_p[j] > kLongList || old.off_m[j + 1] - old.off_m[j] > kLongList) return;
         uint32_t w = off_p[i];
         for (uint32_t e = old.off_p[j]; e < old.off_p[j + 1]; ++e, ++w) {
             const uint32_t v = old.ent_p[e];
@@ -284,7 +316,7 @@ __global__ void __launch_bounds__(kBlk) k_nbr_fill(int64_t L, const uint32_t *__
         uint32_t &w = face < 3 ? wp : wm;
         uint32_t *ent = face < 3 ? ent_p : ent_m;
         if (n == 0) continue;
-        const Face f = locate(key, level, L, D, xyz, ln, face);
+        const Face f = locate(ki, level, D, xyz, ln, face);
         if (f.single) {
             ent[w] = entry(f.j, face, level[f.j]);
         } else if ((uint64_t)(f.hi - f.j) <= kLight) {
@@ -295,6 +327,25 @@ __global__ void __launch_bounds__(kBlk) k_nbr_fill(int64_t L, const uint32_t *__
             }
         }  // else: written by the heavy fill
         w += n;
+    }
+}
+
+// Unchanged leaves with a long list: one wave copies both lists, coalesced.
+__global__ void __launch_bounds__(kBlk) k_nbr_copy_long(uint32_t n, NbrOld old, const uint32_t *off_p,
+                                                        const uint32_t *off_m, uint32_t *ent_p, uint32_t *ent_m) {
+    const uint32_t item = ((uint32_t)blockIdx.x * kBlk + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (item >= n) return;
+    const uint32_t i = old.long_list[item], j = old.src[i];
+    const uint32_t p0 = old.off_p[j], p1 = old.off_p[j + 1], wp = off_p[i];
+    for (uint32_t e = p0 + lane; e < p1; e += 64) {
+        const uint32_t v = old.ent_p[e];
+        ent_p[wp + (e - p0)] = (v & ~kIdxMask) | old.remap[v & kIdxMask];
+    }
+    const uint32_t m0 = old.off_m[j], m1 = old.off_m[j + 1], wm = off_m[i];
+    for (uint32_t e = m0 + lane; e < m1; e += 64) {
+        const uint32_t v = old.ent_m[e];
+        ent_m[wm + (e - m0)] = (v & ~kIdxMask) | old.remap[v & kIdxMask];
     }
 }
 
@@ -323,6 +374,13 @@ void build(Ctx &c, const NbrOld &old) {
     c.s.a.reserve(L + 1);
     c.s.b.reserve(L + 1);
     c.s.g.reserve(6 * L);
+    const int shift = std::max(0, 3 * D - 20);
+    const uint32_t nb = 1u << (3 * D - shift);
+    c.s.key_table.reserve(nb);
+    hipLaunchKernelGGL(k_key_table, dim3((unsigned)cdiv(nb, kBlk)), dim3(kBlk), 0, c.stream, s.key.p, L, shift, nb,
+                       c.s.key_table.p);
+    OTF_LAUNCH_CHECK("k_key_table");
+    const KeyIndex ki{s.key.p, L, c.s.key_table.p, shift, nb};
     uint32_t cap = (uint32_t)std::min<int64_t>(6 * L, std::max<int64_t>(4096, L / 8));
     uint32_t n_heavy = 0;
     for (int attempt = 0; attempt < 2; ++attempt) {
@@ -332,10 +390,12 @@ void build(Ctx &c, const NbrOld &old) {
         c.s.hv_face.reserve(cap);
         Heavy hv{c.s.hv_leaf.p, c.s.hv_face.p, c.s.hv_lo.p, c.s.hv_hi.p, c.counters.p + 3, cap};
         hipLaunchKernelGGL(k_zero1, dim3(1), dim3(64), 0, c.stream, c.counters.p + 3);
-        hipLaunchKernelGGL(k_nbr_count, dim3(g), dim3(kBlk), 0, c.stream, L, s.key.p, s.level.p, D, c.s.a.p, c.s.b.p,
+        hipLaunchKernelGGL(k_zero1, dim3(1), dim3(64), 0, c.stream, c.counters.p + 9);
+        hipLaunchKernelGGL(k_nbr_count, dim3(g), dim3(kBlk), 0, c.stream, ki, s.level.p, D, c.s.a.p, c.s.b.p,
                            c.s.g.p, old, hv);
         OTF_LAUNCH_CHECK("k_nbr_count");
         OTF_HIP(hipMemcpyAsync(c.h_counters + 3, c.counters.p + 3, sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
+        OTF_HIP(hipMemcpyAsync(c.h_counters + 9, c.counters.p + 9, sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
         OTF_HIP(hipStreamSynchronize(c.stream));
         n_heavy = c.h_counters[3];
         if (n_heavy <= cap) break;
@@ -377,10 +437,15 @@ void build(Ctx &c, const NbrOld &old) {
     s.n_nbm = c.h_counters[11];
     s.nbp.reserve(s.n_nbp);
     s.nbm.reserve(s.n_nbm);
-    hipLaunchKernelGGL(k_nbr_fill, dim3(g), dim3(kBlk), 0, c.stream, L, s.key.p, s.level.p, D,
-                       (const uint32_t *)c.s.g.p, (const uint32_t *)s.nbp_off.p, (const uint32_t *)s.nbm_off.p,
+    hipLaunchKernelGGL(k_nbr_fill, dim3(g), dim3(kBlk), 0, c.stream, ki, s.level.p, D, (const uint32_t *)c.s.g.p, (const uint32_t *)s.nbp_off.p, (const uint32_t *)s.nbm_off.p,
                        s.nbp.p, s.nbm.p, old);
     OTF_LAUNCH_CHECK("k_nbr_fill");
+    const uint32_t n_long = old.need ? c.h_counters[9] : 0u;
+    if (n_long > 0) {
+        hipLaunchKernelGGL(k_nbr_copy_long, dim3((unsigned)cdiv((int64_t)n_long * 64, kBlk)), dim3(kBlk), 0, c.stream,
+                           n_long, old, (const uint32_t *)s.nbp_off.p, (const uint32_t *)s.nbm_off.p, s.nbp.p, s.nbm.p);
+        OTF_LAUNCH_CHECK("k_nbr_copy_long");
+    }
     if (n_heavy > 0) {
         hipLaunchKernelGGL(k_nbr_chunk<true>, dim3((unsigned)cdiv((int64_t)n_chunks * 64, kBlk)), dim3(kBlk), 0,
                            c.stream, n_chunks, hv, ch, s.key.p, s.level.p, D, (const uint32_t *)c.s.g.p,
@@ -402,11 +467,16 @@ void build(Ctx &c, const NbrOld &old) {
 
 }  // namespace
 
-void build_neighbours(Ctx &c) { build(c, NbrOld{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr}); }
+void build_neighbours(Ctx &c) {
+    build(c, NbrOld{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr});
+}
 
 void build_neighbours_incremental(Ctx &c, const LeafStore &old, const uint32_t *remap) {
     const LeafStore &s = c.lv();
-    build(c, NbrOld{s.need.p, s.src.p, old.nbp_off.p, old.nbm_off.p, old.nbp.p, old.nbm.p, remap});
+    // an unchanged leaf with a long list had that list in the previous store
+    c.s.long_copy.reserve(old.n_heavy_p + old.n_heavy_m + 1);
+    build(c, NbrOld{s.need.p, s.src.p, old.nbp_off.p, old.nbm_off.p, old.nbp.p, old.nbm.p, remap, c.s.long_copy.p,
+                    c.counters.p + 9});
 }
 
 }  // namespace otf

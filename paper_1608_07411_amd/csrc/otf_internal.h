@@ -242,6 +242,8 @@ struct Scratch {
     DBuf<uint32_t> hv_leaf, hv_lo, hv_hi;  // adjacency: faces with long ranges
     DBuf<uint8_t> hv_face;
     DBuf<uint32_t> ch_base, ch_item, ch_count, ch_pos;  // chunks of the long ranges
+    DBuf<uint32_t> key_table;                           // bucket index over leaf keys
+    DBuf<uint32_t> long_copy;                           // unchanged leaves with long adjacency lists
     DBuf<double> dred;
     std::vector<Round *> rounds;
     ~Scratch() {

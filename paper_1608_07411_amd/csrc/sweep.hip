@@ -97,15 +97,25 @@ __global__ void __launch_bounds__(kBlk) k_dual_long(uint32_t n, const uint32_t *
     const float ub = a.ubar[i];
     const uint32_t e0 = a.off[i], e1 = a.off[i + 1];
     float gx = 0.0f, gy = 0.0f, gz = 0.0f, Cx = 0.0f, Cy = 0.0f, Cz = 0.0f;
+    // lane values of the current chunk; the next chunk is fetched before the
+    // current one is folded
+    float c = 0.0f, diff = 0.0f;
+    int d = 0;
+    if (e0 + lane < e1) {
+        const uint32_t v = a.ent[e0 + lane];
+        d = (v >> kIdxBits) & 3;
+        c = cf.c[ln][v >> (kIdxBits + 2)];
+        diff = a.ubar[v & kIdxMask] - ub;
+    }
     for (uint32_t base = e0; base < e1; base += 64) {
-        const uint32_t e = base + lane;
-        float c = 0.0f, diff = 0.0f;
-        int d = 0;
-        if (e < e1) {
-            const uint32_t v = a.ent[e];
-            d = (v >> kIdxBits) & 3;
-            c = cf.c[ln][v >> (kIdxBits + 2)];
-            diff = a.ubar[v & kIdxMask] - ub;
+        float cn = 0.0f, diffn = 0.0f;
+        int dn = 0;
+        const uint32_t en = base + 64 + lane;
+        if (en < e1) {
+            const uint32_t v = a.ent[en];
+            dn = (v >> kIdxBits) & 3;
+            cn = cf.c[ln][v >> (kIdxBits + 2)];
+            diffn = a.ubar[v & kIdxMask] - ub;
         }
         const int cnt = (int)min(64u, e1 - base);
         for (int j = 0; j < cnt; ++j) {
@@ -122,6 +132,9 @@ __global__ void __launch_bounds__(kBlk) k_dual_long(uint32_t n, const uint32_t *
                 Cz = Cz + cj;
             }
         }
+        c = cn;
+        diff = diffn;
+        d = dn;
     }
     if (lane == 0) dual_finish(a, i, gx, gy, gz, Cx, Cy, Cz);
 }
@@ -155,16 +168,24 @@ __global__ void __launch_bounds__(kBlk) k_primal_long(uint32_t n, const uint32_t
     const int ln = a.level[i];
     const uint32_t e0 = a.off[i], e1 = a.off[i + 1];
     float acc = a.ds[i];
+    float c = 0.0f, pm = 0.0f;
+    if (e0 + lane < e1) {
+        const uint32_t v = a.ent[e0 + lane];
+        c = cf.cp[v >> (kIdxBits + 2)][ln];
+        pm = a.p[(int64_t)((v >> kIdxBits) & 3) * a.cap + (v & kIdxMask)];
+    }
     for (uint32_t base = e0; base < e1; base += 64) {
-        const uint32_t e = base + lane;
-        float c = 0.0f, pm = 0.0f;
-        if (e < e1) {
-            const uint32_t v = a.ent[e];
-            c = cf.cp[v >> (kIdxBits + 2)][ln];
-            pm = a.p[(int64_t)((v >> kIdxBits) & 3) * a.cap + (v & kIdxMask)];
+        float cn = 0.0f, pmn = 0.0f;
+        const uint32_t en = base + 64 + lane;
+        if (en < e1) {
+            const uint32_t v = a.ent[en];
+            cn = cf.cp[v >> (kIdxBits + 2)][ln];
+            pmn = a.p[(int64_t)((v >> kIdxBits) & 3) * a.cap + (v & kIdxMask)];
         }
         const int cnt = (int)min(64u, e1 - base);
         for (int j = 0; j < cnt; ++j) acc = __fmaf_rn(-rdlane(c, j), rdlane(pm, j), acc);
+        c = cn;
+        pm = pmn;
     }
     if (lane == 0) a.ds[i] = __fmaf_rn(a.tau, acc, a.u_in[i]);
 }
