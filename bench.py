@@ -15,6 +15,7 @@ Prints one JSON line on stdout; progress goes to stderr.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import struct
@@ -43,7 +44,23 @@ def parse_args():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="oracle CPU-baseline budget")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized buffer on the GPU 5 times (reference for hardware byte counters)")
     return ap.parse_args()
+
+
+def copy_calibration(mib: int):
+    import torch
+
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": 4 * n, "copy_calibration_bytes_written": 4 * n,
+                      "launches": 5}), flush=True)
 
 
 # --------------------------------------------------------------------------
@@ -142,6 +159,9 @@ def cpu_baseline(blob: bytes, w, budget_s: float):
 # --------------------------------------------------------------------------
 def main():
     args = parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU sharding is designed but "
                                    "not built", "n_gpus": args.gpus}), flush=True)
@@ -217,6 +237,7 @@ def main():
                          f"maps {w.depth.shape[2]}x{w.depth.shape[1]}, lambda {w.lam}, tau=sigma=1/sqrt(12), "
                          f"split/join every iteration, seed {args.seed}"),
             "leaves_after_build": L0, "leaves_at_end": L1, "mean_leaves_per_step": updates / args.steps,
+            "inputs_md5": hashlib.md5(w.depth.tobytes()).hexdigest(),
         },
         "roofline": roofline,
         "sweep_only": {"value": updates / (sweep_ms * 1e-3) if sweep_ms > 0 else None, "unit": "leaf-updates/s",

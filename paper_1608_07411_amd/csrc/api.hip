@@ -211,12 +211,12 @@ double dual_bytes(const Ctx &c) {
 
 // Algorithmic bytes of one primal sweep: level, ds, u, the - adjacency, p
 // once per leaf, the observation header (offset, count, unit flag, normaliser,
-// total weight) and segment (F, plus W for leaves with fractional weights);
-// writes u, ubar and the flag byte.
+// total weight); writes u, ubar and the flag byte. The observation segments
+// (F, plus P for leaves with fractional weights: 4 bytes each) are added from
+// the device-side accumulator when read.
 double primal_bytes(const Ctx &c) {
     const double L = (double)c.L;
-    return L * (1 + 4 + 4 + 12) + 4.0 * (double)c.leaves[c.cur].n_nbm + L * (4 + 1 + 1 + 4 + 4) +
-           4.0 * (double)(c.obs_total + c.obs_nonunit) + L * (4 + 4 + 1);
+    return L * (1 + 4 + 4 + 12) + 4.0 * (double)c.leaves[c.cur].n_nbm + L * (4 + 1 + 1 + 4 + 4) + L * (4 + 4 + 1);
 }
 
 }  // namespace otf
@@ -276,9 +276,11 @@ otf_status otf_create(int device, void *hip_stream, otf_ctx **out) {
     ctx->c.device = device;
     ctx->c.stream = (hipStream_t)hip_stream;
     otf_status st = guard(ctx, false, [&] {
-        ctx->c.counters.reserve(16);
+        ctx->c.counters.reserve(32);
+        OTF_HIP(hipMemsetAsync(ctx->c.counters.p, 0, 32 * sizeof(uint32_t), ctx->c.stream));
+        OTF_HIP(hipStreamSynchronize(ctx->c.stream));
         void *h = nullptr;
-        OTF_HIP(hipHostMalloc(&h, 16 * sizeof(uint32_t), hipHostMallocDefault));
+        OTF_HIP(hipHostMalloc(&h, 32 * sizeof(uint32_t), hipHostMallocDefault));
         ctx->c.h_counters = (uint32_t *)h;
     });
     if (st != OTF_OK) {
@@ -371,6 +373,7 @@ otf_status otf_fuse(otf_ctx *ctx, int32_t iterations, float lambda, float tau, f
             c.leaf_updates += c.L;
             c.alg_bytes[0] += dual_bytes(c);
             c.alg_bytes[1] += primal_bytes(c);
+            accumulate_obs(c);
             c.last_splits = c.last_joins = 0;
             if (c.prm.restructure_every > 0 && c.iteration % c.prm.restructure_every == 0) {
                 prof_begin(c);
@@ -696,6 +699,8 @@ otf_status otf_profile(otf_ctx *ctx, int32_t enable) {
         }
         c.leaf_updates = 0;
         c.alg_bytes[0] = c.alg_bytes[1] = 0.0;
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, c.stream, c.counters.p + 16, 2);
+        OTF_HIP(hipStreamSynchronize(c.stream));
     });
 }
 
@@ -710,8 +715,12 @@ otf_status otf_profile_read(otf_ctx *ctx, double *ms, int64_t *launches, int64_t
         }
         if (leaf_updates) *leaf_updates = c.leaf_updates;
         if (bytes) {
+            OTF_HIP(hipMemcpyAsync(c.h_counters + 16, c.counters.p + 16, 8, hipMemcpyDeviceToHost, c.stream));
+            OTF_HIP(hipStreamSynchronize(c.stream));
+            unsigned long long obs_acc;
+            std::memcpy(&obs_acc, c.h_counters + 16, 8);
             bytes[0] = c.alg_bytes[0];
-            bytes[1] = c.alg_bytes[1];
+            bytes[1] = c.alg_bytes[1] + 4.0 * (double)obs_acc;
         }
     });
 }

@@ -180,20 +180,26 @@ __global__ void k_zero_u64x2(unsigned long long *p) {
 }
 }  // namespace
 
-// Totals of observations (all leaves, and leaves with fractional weights).
+// Totals of observations (all leaves, and leaves with fractional weights),
+// left in the device counters.
 void count_obs(Ctx &c) {
     unsigned long long *d = reinterpret_cast<unsigned long long *>(c.counters.p + 4);
     hipLaunchKernelGGL(k_zero_u64x2, dim3(1), dim3(64), 0, c.stream, d);
     const int64_t blocks = std::min<int64_t>(1024, cdiv(c.L > 0 ? c.L : 1, kBlk));
-    hipLaunchKernelGGL(k_obs_sizes, dim3((unsigned)blocks), dim3(kBlk), 0, c.stream, c.L,
-                       c.lv().obs_m.p, c.lv().obs_unit.p, d);
+    hipLaunchKernelGGL(k_obs_sizes, dim3((unsigned)blocks), dim3(kBlk), 0, c.stream, c.L, c.lv().obs_m.p,
+                       c.lv().obs_unit.p, d);
     OTF_LAUNCH_CHECK("k_obs_sizes");
-    OTF_HIP(hipMemcpyAsync(c.h_counters + 4, c.counters.p + 4, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
-    OTF_HIP(hipStreamSynchronize(c.stream));
-    unsigned long long h[2];
-    std::memcpy(h, c.h_counters + 4, sizeof h);
-    c.obs_total = (int64_t)h[0];
-    c.obs_nonunit = (int64_t)h[1];
+}
+
+namespace {
+__global__ void k_accum_obs(unsigned long long *c) {
+    if (threadIdx.x == 0) c[6] += c[0] + c[1];  // counters [16..17] += [4..5] + [6..7]
+}
+}  // namespace
+
+void accumulate_obs(Ctx &c) {
+    hipLaunchKernelGGL(k_accum_obs, dim3(1), dim3(64), 0, c.stream,
+                       reinterpret_cast<unsigned long long *>(c.counters.p + 4));
 }
 
 // Observation pool for every leaf of the current store, in leaf order.

@@ -430,11 +430,22 @@ void build(Ctx &c, const NbrOld &old) {
     }
     scan_exclusive_u32_dev(c, c.s.a.p, s.nbp_off.p, L);
     scan_exclusive_u32_dev(c, c.s.b.p, s.nbm_off.p, L);
+    // work lists of the leaves with long lists need only the offsets
+    s.heavy_p.reserve(L);
+    s.heavy_m.reserve(L);
+    hipLaunchKernelGGL(k_zero2, dim3(1), dim3(64), 0, c.stream, c.counters.p + 14);
+    hipLaunchKernelGGL(k_heavy_lists, dim3(g), dim3(kBlk), 0, c.stream, L, (const uint32_t *)s.nbp_off.p,
+                       (const uint32_t *)s.nbm_off.p, s.heavy_p.p, s.heavy_m.p, c.counters.p + 14);
+    OTF_LAUNCH_CHECK("k_heavy_lists");
     OTF_HIP(hipMemcpyAsync(c.h_counters + 10, s.nbp_off.p + L, sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
     OTF_HIP(hipMemcpyAsync(c.h_counters + 11, s.nbm_off.p + L, sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
+    OTF_HIP(hipMemcpyAsync(c.h_counters + 14, c.counters.p + 14, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                           c.stream));
     OTF_HIP(hipStreamSynchronize(c.stream));
     s.n_nbp = c.h_counters[10];
     s.n_nbm = c.h_counters[11];
+    s.n_heavy_p = c.h_counters[14];
+    s.n_heavy_m = c.h_counters[15];
     s.nbp.reserve(s.n_nbp);
     s.nbm.reserve(s.n_nbm);
     hipLaunchKernelGGL(k_nbr_fill, dim3(g), dim3(kBlk), 0, c.stream, ki, s.level.p, D, (const uint32_t *)c.s.g.p, (const uint32_t *)s.nbp_off.p, (const uint32_t *)s.nbm_off.p,
@@ -452,17 +463,6 @@ void build(Ctx &c, const NbrOld &old) {
                            (const uint32_t *)s.nbp_off.p, (const uint32_t *)s.nbm_off.p, s.nbp.p, s.nbm.p);
         OTF_LAUNCH_CHECK("k_nbr_chunk fill");
     }
-    s.heavy_p.reserve(L);
-    s.heavy_m.reserve(L);
-    hipLaunchKernelGGL(k_zero2, dim3(1), dim3(64), 0, c.stream, c.counters.p + 14);
-    hipLaunchKernelGGL(k_heavy_lists, dim3(g), dim3(kBlk), 0, c.stream, L, (const uint32_t *)s.nbp_off.p,
-                       (const uint32_t *)s.nbm_off.p, s.heavy_p.p, s.heavy_m.p, c.counters.p + 14);
-    OTF_LAUNCH_CHECK("k_heavy_lists");
-    OTF_HIP(hipMemcpyAsync(c.h_counters + 14, c.counters.p + 14, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost,
-                           c.stream));
-    OTF_HIP(hipStreamSynchronize(c.stream));
-    s.n_heavy_p = c.h_counters[14];
-    s.n_heavy_m = c.h_counters[15];
 }
 
 }  // namespace

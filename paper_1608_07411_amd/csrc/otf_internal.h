@@ -52,11 +52,13 @@ struct DBuf {
         p = nullptr;
         n = 0;
     }
-    // ensure capacity for `count` elements; contents are discarded on growth
+    // ensure capacity for `count` elements; contents are discarded on growth,
+    // which leaves a quarter of headroom so that slowly growing sizes do not
+    // reallocate (and synchronise) on every call
     void reserve(size_t count) {
         if (count <= n && p) return;
         release();
-        size_t c = count ? count : 1;
+        size_t c = count ? count + count / 4 + 64 : 1;
         hipError_t e = hipMalloc((void **)&p, c * sizeof(T));
         if (e != hipSuccess) {
             p = nullptr;
@@ -244,6 +246,13 @@ struct Scratch {
     DBuf<uint32_t> ch_base, ch_item, ch_count, ch_pos;  // chunks of the long ranges
     DBuf<uint32_t> key_table;                           // bucket index over leaf keys
     DBuf<uint32_t> long_copy;                           // unchanged leaves with long adjacency lists
+    // restructure temporaries (grow-only: an allocation or free per iteration
+    // would synchronise the device)
+    DBuf<uint8_t> r_sf, r_tM, r_tU, r_isnew, r_jf, r_Mt;
+    DBuf<uint32_t> r_jr, r_cnt, r_pos, r_nrank, r_tidx, r_moff, r_loff, r_toff;
+    DBuf<uint32_t> r_jkey[2], r_jhead[2];
+    DBuf<uint8_t> r_jlev[2], r_jtgt[2], r_jrole[2];
+    DBuf<float> r_jv[2];
     DBuf<double> dred;
     std::vector<Round *> rounds;
     ~Scratch() {
@@ -268,8 +277,11 @@ struct Ctx {
     int ocur = 0;
     Coef coef{};
     Scratch s;
-    DBuf<uint32_t> counters;        // device counters (split / join flags)
-    uint32_t *h_counters = nullptr;  // pinned mirror
+    // device counters: [0] split flags [1] join flags [2] collapse heads
+    // [3] long ranges [4..7] observation totals (2 x u64) [9] long copies
+    // [14,15] long-list counts [16..17] accumulated observation totals (u64)
+    DBuf<uint32_t> counters;
+    uint32_t *h_counters = nullptr;  // pinned host slots for read-backs (32)
     int64_t last_splits = 0, last_joins = 0;
     // profiling: event pairs recorded on the stream, summed when read
     struct ProfRec {
@@ -286,7 +298,7 @@ struct Ctx {
     int64_t leaf_updates = 0;     // sum over iterations of the leaf count (always counted)
     double alg_bytes[2] = {0, 0};  // algorithmic bytes of the dual and primal sweeps (always counted)
     // structure sizes for the algorithmic byte counts
-    int64_t obs_total = 0, obs_nonunit = 0;
+
     std::string err;
 
     LeafStore &lv() { return leaves[cur]; }
@@ -304,6 +316,7 @@ uint32_t scan_exclusive_u8(Ctx &c, const uint8_t *in, uint32_t *out, int64_t n);
 uint32_t scan_exclusive_u32(Ctx &c, const uint32_t *in, uint32_t *out, int64_t n);
 // exclusive scan without a host read-back: out has n+1 entries, out[n] = total
 void scan_exclusive_u32_dev(Ctx &c, const uint32_t *in, uint32_t *out, int64_t n);
+void scan_exclusive_u32_dev_u8(Ctx &c, const uint8_t *in, uint32_t *out, int64_t n);
 void scan_inclusive_max_u32(Ctx &c, const uint32_t *in, uint32_t *out, int64_t n);
 
 // build: per-view trees, union structure, initial leaves (keys/levels only)
@@ -321,8 +334,10 @@ void gather_fill(Ctx &c, int64_t n, const uint32_t *tkey, const uint8_t *tlevel,
                  uint8_t *unit, float *inv, float *wtot, float *u0, uint32_t *off_out);
 // pool-compacting gather for every leaf of the current store (two passes)
 void gather_all_leaves(Ctx &c, bool init_values);
-// totals of observations for the algorithmic byte counts (synchronises)
+// totals of observations into the device counters (no read-back)
 void count_obs(Ctx &c);
+// add the observation totals to the per-primal accumulator (device)
+void accumulate_obs(Ctx &c);
 // face adjacency of the current leaf store
 void build_neighbours(Ctx &c);
 // Adjacency after a restructure: leaves marked in `need` are searched, the

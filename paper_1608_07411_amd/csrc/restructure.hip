@@ -23,6 +23,10 @@ constexpr int kBlk = 256;
 unsigned grid(int64_t n) { return (unsigned)cdiv(n > 0 ? n : 1, kBlk); }
 #define TID() ((int64_t)blockIdx.x * kBlk + threadIdx.x)
 
+__global__ void k_copy_u32(const uint32_t *src, uint32_t *dst) {
+    if (threadIdx.x == 0) *dst = *src;
+}
+
 __global__ void k_zero_counter2(uint32_t *counters) {
     if (threadIdx.x == 0) counters[2] = 0u;
 }
@@ -100,48 +104,101 @@ struct OldStore {
     const uint8_t *flag;
 };
 
-// Hierarchical means of the collapsed block, written by its first leaf.
-__global__ void k_join_emit(int64_t L, int D, OldStore o, const uint8_t *jt, const uint8_t *jhead,
-                            const uint32_t *out_off, NewStore ns) {
+// Hierarchical means of the collapsed blocks, bottom-up in parallel. The
+// joinable leaves with a collapse target form a list in Morton order; for
+// level l = D .. 1 every complete group of 8 consecutive siblings at level l
+// (inside a block that collapses above l) is replaced by its parent with
+// 1/8 of the sum of the 8 values in child order. Afterwards each block is one
+// node. Each node carries the old index of its subtree's first leaf, which for
+// the final node is the block's first leaf (whose emission slot it takes).
+struct JNodes {
+    uint32_t *key, *head;
+    uint8_t *lev, *tgt, *role;
+    float *v;  // 5 planes (u, ubar, px, py, pz) of `cap`
+    int64_t cap;
+};
+
+__global__ void k_jflags(int64_t L, const uint8_t *jt, uint8_t *f) {
     const int64_t i = TID();
-    if (i >= L || !jhead[i]) return;
-    const int tl = jt[i];
-    const uint64_t B0 = o.key[i];
-    const uint64_t B1 = B0 + (uint64_t(1) << (3 * (D - tl)));
-    float acc[kMaxDepth + 1][5];
-    int cnt[kMaxDepth + 1];
-    for (int a = 0; a <= kMaxDepth; ++a) {
-        cnt[a] = 0;
-        for (int q = 0; q < 5; ++q) acc[a][q] = 0.0f;
+    if (i < L) f[i] = jt[i] != 0xFF ? 1 : 0;
+}
+
+__global__ void k_jinit(int64_t L, const uint8_t *jt, const uint32_t *rank, OldStore o, JNodes J) {
+    const int64_t i = TID();
+    if (i >= L || jt[i] == 0xFF) return;
+    const uint32_t t = rank[i];
+    J.key[t] = o.key[i];
+    J.head[t] = (uint32_t)i;
+    J.lev[t] = o.level[i];
+    J.tgt[t] = jt[i];
+    J.v[t] = o.u[i];
+    J.v[J.cap + t] = o.ubar[i];
+    J.v[2 * J.cap + t] = o.p[i];
+    J.v[3 * J.cap + t] = o.p[o.cap + i];
+    J.v[4 * J.cap + t] = o.p[2 * o.cap + i];
+}
+
+__device__ inline bool group_complete(const JNodes &J, int64_t g, uint32_t n, int l, int D) {
+    if (g < 0 || g + 7 >= (int64_t)n) return false;
+    const int sh = 3 * (D - l);
+    const uint32_t k0 = J.key[g];
+    if (((k0 >> sh) & 7u) != 0) return false;
+    for (int c = 0; c < 8; ++c)
+        if (J.lev[g + c] != l || J.key[g + c] != k0 + ((uint32_t)c << sh)) return false;
+    return true;
+}
+
+// role: 0 carried, 1 first child of a complete group, 2 other child
+__global__ void k_jmark(int64_t nmax, const uint32_t *n_dev, JNodes J, int l, int D, uint32_t *cnt) {
+    const int64_t t = TID();
+    if (t >= nmax) return;
+    const uint32_t n = *n_dev;
+    if (t >= (int64_t)n) {
+        cnt[t] = 0;
+        return;
     }
-    float v[5] = {0, 0, 0, 0, 0};
-    for (int64_t j = i; j < L && (uint64_t)o.key[j] < B1; ++j) {
-        v[0] = o.u[j];
-        v[1] = o.ubar[j];
-        v[2] = o.p[j];
-        v[3] = o.p[o.cap + j];
-        v[4] = o.p[2 * o.cap + j];
-        int lv = o.level[j];
-        while (lv > tl) {
-            const int a = lv - 1;
-            for (int q = 0; q < 5; ++q) acc[a][q] = acc[a][q] + v[q];
-            if (++cnt[a] < 8) break;
-            for (int q = 0; q < 5; ++q) {
-                v[q] = 0.125f * acc[a][q];
-                acc[a][q] = 0.0f;
-            }
-            cnt[a] = 0;
-            lv = a;
+    uint8_t role = 0;
+    if (J.lev[t] == l && J.tgt[t] < l) {
+        const int ci = (int)((J.key[t] >> (3 * (D - l))) & 7u);
+        if (group_complete(J, t - ci, n, l, D)) role = ci == 0 ? 1 : 2;
+    }
+    J.role[t] = role;
+    cnt[t] = role == 2 ? 0u : 1u;
+}
+
+__global__ void k_jmerge(int64_t nmax, const uint32_t *n_dev, JNodes A, JNodes B, const uint32_t *pos) {
+    const int64_t t = TID();
+    if (t >= nmax || t >= (int64_t)*n_dev) return;
+    const uint8_t role = A.role[t];
+    if (role == 2) return;
+    const uint32_t w = pos[t];
+    B.key[w] = A.key[t];
+    B.head[w] = A.head[t];
+    B.tgt[w] = A.tgt[t];
+    if (role == 0) {
+        B.lev[w] = A.lev[t];
+        for (int q = 0; q < 5; ++q) B.v[q * B.cap + w] = A.v[q * A.cap + t];
+    } else {
+        B.lev[w] = A.lev[t] - 1;
+        for (int q = 0; q < 5; ++q) {
+            float acc = 0.0f;
+            for (int c = 0; c < 8; ++c) acc = acc + A.v[q * A.cap + t + c];
+            B.v[q * B.cap + w] = 0.125f * acc;
         }
     }
-    const uint32_t w = out_off[i];
-    ns.key[w] = (uint32_t)B0;
-    ns.level[w] = (uint8_t)tl;
-    ns.u[w] = v[0];
-    ns.ubar[w] = v[1];
-    ns.p[w] = v[2];
-    ns.p[ns.cap + w] = v[3];
-    ns.p[2 * ns.cap + w] = v[4];
+}
+
+__global__ void k_jemit(int64_t nmax, const uint32_t *n_dev, JNodes J, const uint32_t *out_off, NewStore ns) {
+    const int64_t t = TID();
+    if (t >= nmax || t >= (int64_t)*n_dev) return;
+    const uint32_t w = out_off[J.head[t]];
+    ns.key[w] = J.key[t];
+    ns.level[w] = J.lev[t];
+    ns.u[w] = J.v[t];
+    ns.ubar[w] = J.v[J.cap + t];
+    ns.p[w] = J.v[2 * J.cap + t];
+    ns.p[ns.cap + w] = J.v[3 * J.cap + t];
+    ns.p[2 * ns.cap + w] = J.v[4 * J.cap + t];
     ns.isnew[w] = 1;
     ns.src[w] = kNone;
     ns.need[w] = 1;
@@ -395,10 +452,12 @@ bool restructure(Ctx &c, float tl) {
     if (n_split > 0) {
         s.d.reserve(L);
         // rank of the split-flagged leaves
-        DBuf<uint8_t> sf;
+        DBuf<uint8_t> &sf = s.r_sf;
         sf.reserve(L);
         hipLaunchKernelGGL(k_split_bits, dim3(gL), dim3(kBlk), 0, c.stream, L, os.flag.p, sf.p);
-        const uint32_t np0 = scan_exclusive_u8(c, sf.p, s.d.p, L);
+        s.d.reserve(L + 1);
+        scan_exclusive_u32_dev_u8(c, sf.p, s.d.p, L);
+        const uint32_t np0 = n_split;
         rank0 = s.d.p;
         Round &r0 = round_at(c, 0);
         r0.np = np0;
@@ -435,7 +494,7 @@ bool restructure(Ctx &c, float tl) {
             s.fb.reserve(nc * stride);
             s.fc.reserve(nc);
             s.fd.reserve(nc);
-            DBuf<uint8_t> tM, tU;
+            DBuf<uint8_t> &tM = s.r_tM, &tU = s.r_tU;
             tM.reserve(nc);
             tU.reserve(nc);
             gather_fill(c, nc, R.ckey.p, R.clevel.p, nullptr, nullptr, 0, stride, s.fa.p, s.fb.p, nullptr, tM.p, tU.p,
@@ -445,7 +504,6 @@ bool restructure(Ctx &c, float tl) {
                                c.prm.split_tau, D, R.cu.p, R.cub.p, R.csplit.p);
             OTF_LAUNCH_CHECK("k_cascade_prox");
             const uint32_t next = scan_exclusive_u8(c, R.csplit.p, R.crank.p, nc);
-            OTF_HIP(hipStreamSynchronize(c.stream));  // tM / tU are freed on scope exit
             total_splits += np;
             np = next;
             ++r;
@@ -469,15 +527,18 @@ bool restructure(Ctx &c, float tl) {
     OTF_LAUNCH_CHECK("k_out_count");
     scan_exclusive_u32_dev(c, s.e.p, s.f.p, L);
     const uint32_t *out_off = s.f.p;
-    const int64_t Lnew = read_u32(c, s.f.p + L, 12);
-    if (jt) c.last_joins = read_u32(c, c.counters.p + 2, 13);
+    OTF_HIP(hipMemcpyAsync(c.h_counters + 12, s.f.p + L, sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
+    OTF_HIP(hipMemcpyAsync(c.h_counters + 13, c.counters.p + 2, sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
+    OTF_HIP(hipStreamSynchronize(c.stream));
+    const int64_t Lnew = c.h_counters[12];
+    if (jt) c.last_joins = c.h_counters[13];
     c.last_splits = total_splits;
     if (Lnew >= kLeafLimit) fail(OTF_E_CAPACITY, "leaf count exceeds 2^26");
     if (c.prm.max_leaves > 0 && Lnew > c.prm.max_leaves) fail(OTF_E_CAPACITY, "leaf count exceeds max_leaves");
 
     LeafStore &ns = c.leaves[c.cur ^ 1];
     ns.reserve(Lnew);
-    DBuf<uint8_t> isnew;
+    DBuf<uint8_t> &isnew = s.r_isnew;
     isnew.reserve(Lnew);
     NewStore nsd{ns.key.p, ns.level.p, ns.u.p,     ns.ubar.p, ns.p.p, ns.cap, ns.obs_off.p, ns.obs_m.p, ns.obs_unit.p,
                  ns.inv.p, ns.wtot.p,  isnew.p, ns.src.p, ns.need.p};
@@ -486,8 +547,44 @@ bool restructure(Ctx &c, float tl) {
     hipLaunchKernelGGL(k_emit_keep, dim3(gL), dim3(kBlk), 0, c.stream, L, osd, jt, n_split > 0 ? 1 : 0, out_off, nsd);
     OTF_LAUNCH_CHECK("k_emit_keep");
     if (jt) {
-        hipLaunchKernelGGL(k_join_emit, dim3(gL), dim3(kBlk), 0, c.stream, L, D, osd, jt, jhead, out_off, nsd);
-        OTF_LAUNCH_CHECK("k_join_emit");
+        // collapse: merge list of the joinable leaves with a target
+        const int64_t nmax = n_join;
+        DBuf<uint8_t> &jf = s.r_jf;
+        jf.reserve(L);
+        DBuf<uint32_t> &jr = s.r_jr, &cnt = s.r_cnt, &pos = s.r_pos;
+        jr.reserve(L + 1);
+        cnt.reserve(nmax);
+        pos.reserve(nmax + 1);
+        DBuf<uint32_t> *k2 = s.r_jkey, *h2 = s.r_jhead;
+        DBuf<uint8_t> *lv2 = s.r_jlev, *tg2 = s.r_jtgt, *ro2 = s.r_jrole;
+        DBuf<float> *v2 = s.r_jv;
+        JNodes J[2];
+        for (int b = 0; b < 2; ++b) {
+            k2[b].reserve(nmax);
+            h2[b].reserve(nmax);
+            lv2[b].reserve(nmax);
+            tg2[b].reserve(nmax);
+            ro2[b].reserve(nmax);
+            v2[b].reserve(5 * nmax);
+            J[b] = JNodes{k2[b].p, h2[b].p, lv2[b].p, tg2[b].p, ro2[b].p, v2[b].p, nmax};
+        }
+        hipLaunchKernelGGL(k_jflags, dim3(gL), dim3(kBlk), 0, c.stream, L, jt, jf.p);
+        scan_exclusive_u32_dev_u8(c, jf.p, jr.p, L);  // jr[L] = list length
+        hipLaunchKernelGGL(k_jinit, dim3(gL), dim3(kBlk), 0, c.stream, L, jt, jr.p, osd, J[0]);
+        const uint32_t *n_dev = jr.p + L;
+        const unsigned gN = grid(nmax);
+        int a = 0;
+        for (int l = D; l >= 1; --l) {
+            hipLaunchKernelGGL(k_jmark, dim3(gN), dim3(kBlk), 0, c.stream, nmax, n_dev, J[a], l, D, cnt.p);
+            scan_exclusive_u32_dev(c, cnt.p, pos.p, nmax);
+            hipLaunchKernelGGL(k_jmerge, dim3(gN), dim3(kBlk), 0, c.stream, nmax, n_dev, J[a], J[a ^ 1], pos.p);
+            OTF_LAUNCH_CHECK("join merge");
+            // the merged list length is the scan total; keep it for the next level
+            hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(64), 0, c.stream, pos.p + nmax, jr.p + L);
+            a ^= 1;
+        }
+        hipLaunchKernelGGL(k_jemit, dim3(gN), dim3(kBlk), 0, c.stream, nmax, n_dev, J[a], out_off, nsd);
+        OTF_LAUNCH_CHECK("k_jemit");
     }
     for (int64_t q = 0; q < nrounds; ++q) {
         Round &R = *s.rounds[q];
@@ -506,23 +603,27 @@ bool restructure(Ctx &c, float tl) {
     }
 
     // ---- observations of the new leaves (append to the pool, or compact)
-    DBuf<uint32_t> nrank, tidx, moff;
+    DBuf<uint32_t> &nrank = s.r_nrank, &tidx = s.r_tidx, &moff = s.r_moff;
     nrank.reserve(Lnew + 1);
     const uint32_t n_new = scan_exclusive_u8(c, isnew.p, nrank.p, Lnew);
     tidx.reserve(n_new);
     hipLaunchKernelGGL(k_compact_idx, dim3(grid(Lnew)), dim3(kBlk), 0, c.stream, Lnew, isnew.p, nrank.p, tidx.p);
-    DBuf<uint8_t> Mt;
+    DBuf<uint8_t> &Mt = s.r_Mt;
     Mt.reserve(n_new);
     gather_count(c, n_new, ns.key.p, ns.level.p, tidx.p, Mt.p);
     moff.reserve(n_new + 1);
-    const uint32_t new_obs = scan_exclusive_u8(c, Mt.p, moff.p, n_new);
+    scan_exclusive_u32_dev_u8(c, Mt.p, moff.p, n_new);
     hipLaunchKernelGGL(k_scatter_m, dim3(grid(n_new)), dim3(kBlk), 0, c.stream, (int64_t)n_new, tidx.p, Mt.p,
                        ns.obs_m.p);
     ObsPool &pool = c.op();
     // live observations of the new store
-    DBuf<uint32_t> loff;
+    DBuf<uint32_t> &loff = s.r_loff;
     loff.reserve(Lnew + 1);
-    const uint32_t live = scan_exclusive_u8(c, ns.obs_m.p, loff.p, Lnew);
+    scan_exclusive_u32_dev_u8(c, ns.obs_m.p, loff.p, Lnew);
+    OTF_HIP(hipMemcpyAsync(c.h_counters + 12, moff.p + n_new, sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
+    OTF_HIP(hipMemcpyAsync(c.h_counters + 13, loff.p + Lnew, sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
+    OTF_HIP(hipStreamSynchronize(c.stream));
+    const uint32_t new_obs = c.h_counters[12], live = c.h_counters[13];
     const bool compact = (pool.used + (int64_t)new_obs > pool.cap) || (pool.used > 2 * (int64_t)live + 4096);
     if (!compact) {
         gather_fill(c, n_new, ns.key.p, ns.level.p, tidx.p, moff.p, (uint32_t)pool.used, 0, pool.F.p, pool.W.p,
@@ -534,7 +635,7 @@ bool restructure(Ctx &c, float tl) {
         hipLaunchKernelGGL(k_copy_segments, dim3(grid(64 * Lnew)), dim3(kBlk), 0, c.stream, Lnew, isnew.p,
                            ns.obs_m.p, loff.p, ns.obs_off.p, pool.F.p, pool.W.p, pool.P.p, np.F.p, np.W.p, np.P.p);
         OTF_LAUNCH_CHECK("k_copy_segments");
-        DBuf<uint32_t> toff;
+        DBuf<uint32_t> &toff = s.r_toff;
         toff.reserve(n_new);
         hipLaunchKernelGGL(k_take, dim3(grid(n_new)), dim3(kBlk), 0, c.stream, (int64_t)n_new, tidx.p, loff.p, toff.p);
         gather_fill(c, n_new, ns.key.p, ns.level.p, tidx.p, toff.p, 0, 0, np.F.p, np.W.p, np.P.p, ns.obs_m.p,
@@ -551,7 +652,7 @@ bool restructure(Ctx &c, float tl) {
     c.cur ^= 1;
     c.L = Lnew;
     build_neighbours_incremental(c, os, out_off);
-    count_obs(c);  // synchronises: temporaries are freed on return
+    count_obs(c);
     return true;
 }
 

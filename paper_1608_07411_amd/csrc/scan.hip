@@ -159,6 +159,10 @@ void scan_exclusive_u32_dev(Ctx &c, const uint32_t *in, uint32_t *out, int64_t n
     scan_any(c, in, out, n, AddOp{}, true, out + n);
 }
 
+void scan_exclusive_u32_dev_u8(Ctx &c, const uint8_t *in, uint32_t *out, int64_t n) {
+    scan_any(c, in, out, n, AddOp{}, true, out + n);
+}
+
 void scan_inclusive_max_u32(Ctx &c, const uint32_t *in, uint32_t *out, int64_t n) {
     scan_any(c, in, out, n, MaxOp{}, false, (uint32_t *)nullptr);
 }

@@ -14,6 +14,9 @@ compares against (it uses the Euclidean distance to the projection centre).
 Randomness: SplitMix64 (Steele, Lea, Flood 2014) in counter form. A stream is
 keyed by (workload, seed, purpose); uniforms are (x >> 11) * 2^-53 and
 Gaussians use the cosine branch of Box-Muller.
+
+Geometry is written with explicit element-wise arithmetic in a fixed order (no
+BLAS products), so that the same seed gives the same range maps on any host.
 """
 from __future__ import annotations
 
@@ -108,18 +111,28 @@ CAMERA_DTYPE = np.dtype([
 ])  # byte layout of the C struct otf_camera (72 bytes)
 assert CAMERA_DTYPE.itemsize == 72
 
+def _dot(a, b):
+    """Row-wise dot product of (..., 3) arrays (or with a 3-vector), fixed order."""
+    return a[..., 0] * b[..., 0] + a[..., 1] * b[..., 1] + a[..., 2] * b[..., 2]
+
+
+def _mat(v, M):
+    """v @ M for (..., 3) rows v and a 3x3 M, written out."""
+    return np.stack([v[..., 0] * M[0, j] + v[..., 1] * M[1, j] + v[..., 2] * M[2, j] for j in range(3)], axis=-1)
+
+
 CENTRE = np.array([0.5, 0.5, 0.5])
 
 
 def look_at(C: np.ndarray, target: np.ndarray = CENTRE) -> np.ndarray:
     """Camera->world rotation whose columns are the camera axes in world space."""
     fwd = target - C
-    fwd = fwd / np.linalg.norm(fwd)
+    fwd = fwd / math.sqrt(float(_dot(fwd, fwd)))
     up = np.array([0.0, 0.0, 1.0])
-    if abs(fwd @ up) > 0.99:
+    if abs(fwd[2]) > 0.99:
         up = np.array([0.0, 1.0, 0.0])
     right = np.cross(fwd, up)
-    right /= np.linalg.norm(right)
+    right /= math.sqrt(float(_dot(right, right)))
     down = np.cross(fwd, right)
     return np.stack([right, down, fwd], axis=1)
 
@@ -142,9 +155,9 @@ def camera_rays(cam: np.ndarray):
     dc = np.stack([(ii + 0.5 - float(cam["cx"])) / float(cam["fx"]),
                    (jj + 0.5 - float(cam["cy"])) / float(cam["fy"]),
                    np.ones_like(ii)], axis=-1).reshape(-1, 3)
-    dc /= np.linalg.norm(dc, axis=1, keepdims=True)
+    dc /= np.sqrt(_dot(dc, dc))[:, None]
     R = cam["R_cw"].astype(np.float64).reshape(3, 3)
-    return np.asarray(cam["C"], dtype=np.float64), dc @ R.T
+    return np.asarray(cam["C"], dtype=np.float64), _mat(dc, R.T)
 
 
 # ----------------------------------------------------------------------------
@@ -162,8 +175,8 @@ def _nearest(*cands):
 
 def _sphere_roots(o, d, c, r):
     oc = o - c
-    b = d @ oc if oc.ndim == 1 else np.einsum("ij,ij->i", d, oc)
-    cc = oc @ oc - r * r
+    b = _dot(d, oc)
+    cc = _dot(oc, oc) - r * r
     disc = b * b - cc
     ok = disc >= 0
     s = np.sqrt(np.where(ok, disc, 0.0))
@@ -188,8 +201,8 @@ class Box:
     e: np.ndarray
 
     def intersect(self, o, d):
-        ol = (o - self.c) @ self.Q
-        dl = d @ self.Q
+        ol = _mat(o - self.c, self.Q)
+        dl = _mat(d, self.Q)
         with np.errstate(divide="ignore", invalid="ignore"):
             t1 = (-self.e - ol) / dl
             t2 = (self.e - ol) / dl
@@ -209,13 +222,13 @@ class Cylinder:
 
     def intersect(self, o, d):
         oc = o - self.c
-        da = d @ self.a
-        oa = oc @ self.a
-        dp = d - np.outer(da, self.a)
+        da = _dot(d, self.a)
+        oa = float(_dot(oc, self.a))
+        dp = d - da[:, None] * self.a[None, :]
         op = oc - oa * self.a
-        A = np.einsum("ij,ij->i", dp, dp)
-        B = dp @ op
-        Cc = op @ op - self.r * self.r
+        A = _dot(dp, dp)
+        B = _dot(dp, op)
+        Cc = float(_dot(op, op)) - self.r * self.r
         disc = B * B - A * Cc
         ok = (disc >= 0) & (A > 1e-300)
         s = np.sqrt(np.where(ok, disc, 0.0))
@@ -228,7 +241,7 @@ class Cylinder:
             for sgn in (-1.0, 1.0):
                 t = (sgn * self.hl - oa) / da
                 q = op + t[:, None] * dp
-                cands.append((t, np.isfinite(t) & (np.einsum("ij,ij->i", q, q) <= self.r * self.r)))
+                cands.append((t, np.isfinite(t) & (_dot(q, q) <= self.r * self.r)))
         return _nearest(*cands)
 
 
@@ -242,17 +255,18 @@ class HemiShell:
 
     def intersect(self, o, d):
         oc = o - self.c
+        ocn = float(_dot(oc, self.n))
+        dn = _dot(d, self.n)
         cands = []
         for r in (self.ro, self.ri):
             t0, t1, ok = _sphere_roots(o, d, self.c, r)
             for t in (t0, t1):
-                side = oc @ self.n + t * (d @ self.n)
+                side = ocn + t * dn
                 cands.append((t, ok & (side >= 0)))
-        dn = d @ self.n
         with np.errstate(divide="ignore", invalid="ignore"):
-            t = -(oc @ self.n) / dn
+            t = -ocn / dn
             q = oc + t[:, None] * d
-            rr = np.einsum("ij,ij->i", q, q)
+            rr = _dot(q, q)
         cands.append((t, np.isfinite(t) & (rr >= self.ri ** 2) & (rr <= self.ro ** 2)))
         return _nearest(*cands)
 
@@ -373,7 +387,8 @@ def blocks_workload(seed: int = 0, max_depth: int = 8, n_views: int = 32, W: int
         D = np.where(D > 0, D + h * n, 0.0)
         s = Stream(wid, seed, 200 + i)
         out = s.uniform(D.size).reshape(D.shape) < 0.02
-        R = float(np.linalg.norm(np.asarray(cam["C"], dtype=np.float64) - CENTRE))
+        dc = np.asarray(cam["C"], dtype=np.float64) - CENTRE
+        R = math.sqrt(float(_dot(dc, dc)))
         val = s.uniform(D.size, R - math.sqrt(3) / 2, R + math.sqrt(3) / 2).reshape(D.shape)
         return np.where(out, val, D)
 
