@@ -70,11 +70,14 @@ _NODE = np.dtype([("key", "<u4"), ("level", "u1"), ("leaf", "u1"), ("pad", "<u2"
 _LEAF = np.dtype([("key", "<u4"), ("level", "u1"), ("pad", "u1", (3,)), ("v", "<f4", (5,))])
 
 
-def crop_state(blob: bytes, cube_level: int):
-    """State blob of the densest aligned cube at `cube_level`, re-rooted as a
-    domain of depth D - cube_level. A view whose octree has no node for the cube
-    contributes its containing leaf, with the count scaled to the cube's volume
-    (kept >= 1 when observed) so that every leaf keeps its observation count."""
+def crop_state(blob: bytes, cube_level: int, M=None, min_leaves: int = 10000):
+    """State blob of one aligned cube at `cube_level`, re-rooted as a domain of
+    depth D - cube_level: among cubes with at least `min_leaves` leaves, the one
+    whose mean observation count per leaf is closest to the whole octree's
+    (the densest cube if M is not given). A view whose octree has no node for
+    the cube contributes its containing leaf, with the count scaled to the
+    cube's volume (kept >= 1 when observed) so that every leaf keeps its
+    observation count."""
     D = struct.unpack_from("<i", blob, 8)[0]
     at = 8 + 40 + 8
     nv = struct.unpack_from("<i", blob, at)[0]
@@ -90,7 +93,13 @@ def crop_state(blob: bytes, cube_level: int):
     leaves = np.frombuffer(blob, _LEAF, nl, at)
     sh = 3 * (D - cube_level)
     cube_of = leaves["key"].astype(np.int64) >> sh
-    best = int(np.bincount(cube_of).argmax())
+    counts = np.bincount(cube_of)
+    best = int(counts.argmax())
+    if M is not None and (counts >= min_leaves).any():
+        msum = np.bincount(cube_of, weights=M.astype(np.float64), minlength=len(counts))
+        ok = counts >= min_leaves
+        mean = np.where(ok, msum / np.maximum(counts, 1), np.inf)
+        best = int(np.argmin(np.abs(mean - M.mean())))
     sel = leaves[(cube_of == best) & (leaves["level"] >= cube_level)]
     assert np.sum((1 << (3 * (D - sel["level"].astype(np.int64))))) == (1 << sh), "cube not tiled by leaves"
     mask = (1 << sh) - 1
@@ -124,12 +133,12 @@ def crop_state(blob: bytes, cube_level: int):
     return bytes(out), len(cl), best
 
 
-def cpu_baseline(blob: bytes, w, budget_s: float):
+def cpu_baseline(blob: bytes, M, w, budget_s: float):
     import oracle
 
     for level in (3, 2, 4, 1):
         try:
-            sub, nleaves, cube = crop_state(blob, level)
+            sub, nleaves, cube = crop_state(blob, level, M)
         except AssertionError:
             continue
         if 2000 <= nleaves <= 400000:
@@ -150,9 +159,10 @@ def cpu_baseline(blob: bytes, w, budget_s: float):
     rate = updates / el
     return {
         "value": rate, "unit": "leaf-updates/s", "cores": 1, "kind": "oracle",
-        "sample": (f"oracle fp32 (single-threaded C, pointer octree) on the densest level-{level} cube "
-                   f"(#{cube}, {nleaves} leaves at start) of the GPU state after warmup, re-rooted as its own "
-                   f"domain; {iters} iterations with split/join in {el:.1f} s (import {t_import:.1f} s excluded)"),
+        "sample": (f"oracle fp32 (single-threaded C, pointer octree) on level-{level} cube #{cube} of the GPU "
+                   f"state after warmup ({nleaves} leaves at start, mean observations per leaf closest to the "
+                   f"whole octree's {float(M.mean()):.1f}), re-rooted as its own domain; {iters} iterations with "
+                   f"split/join in {el:.1f} s (state import {t_import:.1f} s excluded)"),
     }
 
 
@@ -192,6 +202,7 @@ def main():
     log(f"[bench] warmup {args.warmup} iterations {time.perf_counter() - t0:.2f} s, {ctx.num_leaves()} leaves, "
         f"last split/join {ctx.last_counts()}")
     blob_for_cpu = None if args.no_cpu else ctx.export_state()
+    M_for_cpu = None if args.no_cpu else ctx.obs_counts()
 
     # timed region: kernel events are recorded on the library's stream as it runs
     ctx.reset_counters(profile=True)
@@ -246,7 +257,7 @@ def main():
     }
     if blob_for_cpu is not None:
         log("[bench] CPU baseline (oracle) ...")
-        result["cpu_baseline"] = cpu_baseline(blob_for_cpu, w, args.cpu_seconds)
+        result["cpu_baseline"] = cpu_baseline(blob_for_cpu, M_for_cpu, w, args.cpu_seconds)
         log(f"[bench] CPU baseline {result['cpu_baseline']['value']:.4g} leaf-updates/s")
     else:
         result["cpu_baseline"] = None

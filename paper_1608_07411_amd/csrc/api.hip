@@ -439,13 +439,14 @@ otf_status otf_extract_obs(const otf_ctx *cctx, int64_t cap_leaves, int32_t *M, 
         auto hoff = download(c, s.obs_off.p, L);
         auto hw = download(c, s.wtot.p, L);
         auto hi = download(c, s.inv.p, L);
-        auto hF = download(c, c.op().F.p, c.op().used);
-        auto hW = download(c, c.op().W.p, c.op().used);
+        const bool values = F || W;  // counts only: skip the pool download
+        auto hF = download(c, c.op().F.p, values ? c.op().used : 0);
+        auto hW = download(c, c.op().W.p, values ? c.op().used : 0);
         OTF_HIP(hipStreamSynchronize(c.stream));
         int64_t tot = 0;
         for (int64_t i = 0; i < L; ++i) tot += hm[i];
         *n_obs = tot;
-        if (tot > cap_obs) {
+        if (values && tot > cap_obs) {
             cap_st = OTF_E_CAPACITY;
             return;
         }

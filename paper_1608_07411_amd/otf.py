@@ -194,6 +194,15 @@ class Context:
         off[1:] = np.cumsum(M)
         return dict(M=M, wtot=wtot, inv=inv, F=F[:tot.value], W=W[:tot.value], off=off)
 
+    def obs_counts(self) -> np.ndarray:
+        """Observation count M of every leaf (no pool download)."""
+        n = self.num_leaves()
+        M = np.zeros(n, np.int32)
+        tot = C.c_int64(0)
+        self._check(self._lib.otf_extract_obs(self.h, n, _ptr(M), None, None, 0, None, None, C.byref(tot)),
+                    "otf_extract_obs")
+        return M
+
     def extract_neighbours(self):
         n = self.num_leaves()
         counts = np.zeros((n, 6), np.int32)
