@@ -86,19 +86,20 @@ __global__ void __launch_bounds__(kBlk) k_dual(DualArgs a, Coef cf) {
     dual_finish(a, i, gx, gy, gz, Cx, Cy, Cz);
 }
 
-// One wave per leaf with a long + list: lanes fetch 64 entries at a time and
-// the wave then folds them in list order (the same sequential fma chain).
-__global__ void __launch_bounds__(kBlk) k_dual_long(uint32_t n, const uint32_t *list, DualArgs a, Coef cf) {
-    const uint32_t item = ((uint32_t)blockIdx.x * kBlk + threadIdx.x) >> 6;
-    const int lane = threadIdx.x & 63;
-    if (item >= n) return;
-    const int64_t i = list[item];
+// Leaves with a long + list, one 256-thread block each: the block stages the
+// list's coefficients, neighbour differences and directions in LDS with
+// parallel loads, then one lane folds them in list order (the same sequential
+// fma chain as k_dual). Lists beyond the LDS budget are folded in 64-entry
+// chunks by the first wave, the next chunk fetched while one is folded.
+constexpr int kStageBytes = 64 * 1024;
+constexpr uint32_t kDualStage = kStageBytes / 9;    // float c, float diff, u8 dir
+constexpr uint32_t kPrimalStage = kStageBytes / 8;  // float c', float p
+
+__device__ void dual_long_chunked(const DualArgs &a, const Coef &cf, int64_t i, int lane) {
     const int ln = a.level[i];
     const float ub = a.ubar[i];
     const uint32_t e0 = a.off[i], e1 = a.off[i + 1];
     float gx = 0.0f, gy = 0.0f, gz = 0.0f, Cx = 0.0f, Cy = 0.0f, Cz = 0.0f;
-    // lane values of the current chunk; the next chunk is fetched before the
-    // current one is folded
     float c = 0.0f, diff = 0.0f;
     int d = 0;
     if (e0 + lane < e1) {
@@ -139,6 +140,46 @@ __global__ void __launch_bounds__(kBlk) k_dual_long(uint32_t n, const uint32_t *
     if (lane == 0) dual_finish(a, i, gx, gy, gz, Cx, Cy, Cz);
 }
 
+__global__ void __launch_bounds__(kBlk) k_dual_long(uint32_t n, const uint32_t *list, DualArgs a, Coef cf) {
+    extern __shared__ unsigned char smem[];
+    if (blockIdx.x >= n) return;
+    const int64_t i = list[blockIdx.x];
+    const uint32_t e0 = a.off[i], e1 = a.off[i + 1], ne = e1 - e0;
+    if (ne > kDualStage) {
+        if (threadIdx.x < 64) dual_long_chunked(a, cf, i, threadIdx.x);
+        return;
+    }
+    float *sc = reinterpret_cast<float *>(smem);
+    float *sv = sc + kDualStage;
+    uint8_t *sd = reinterpret_cast<uint8_t *>(sv + kDualStage);
+    const int ln = a.level[i];
+    const float ub = a.ubar[i];
+    for (uint32_t q = threadIdx.x; q < ne; q += kBlk) {
+        const uint32_t v = a.ent[e0 + q];
+        sd[q] = (uint8_t)((v >> kIdxBits) & 3);
+        sc[q] = cf.c[ln][v >> (kIdxBits + 2)];
+        sv[q] = a.ubar[v & kIdxMask] - ub;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    float gx = 0.0f, gy = 0.0f, gz = 0.0f, Cx = 0.0f, Cy = 0.0f, Cz = 0.0f;
+    for (uint32_t q = 0; q < ne; ++q) {
+        const float c = sc[q], v = sv[q];
+        const int d = sd[q];
+        if (d == 0) {
+            gx = __fmaf_rn(c, v, gx);
+            Cx = Cx + c;
+        } else if (d == 1) {
+            gy = __fmaf_rn(c, v, gy);
+            Cy = Cy + c;
+        } else {
+            gz = __fmaf_rn(c, v, gz);
+            Cz = Cz + c;
+        }
+    }
+    dual_finish(a, i, gx, gy, gz, Cx, Cy, Cz);
+}
+
 struct PrimalArgs {
     int64_t L, cap;
     const uint8_t *level;
@@ -159,12 +200,9 @@ struct PrimalArgs {
     int join_enabled, max_depth;
 };
 
-// u' for leaves with a long - list, one wave each (sequential fma chain).
-__global__ void __launch_bounds__(kBlk) k_primal_long(uint32_t n, const uint32_t *list, PrimalArgs a, Coef cf) {
-    const uint32_t item = ((uint32_t)blockIdx.x * kBlk + threadIdx.x) >> 6;
-    const int lane = threadIdx.x & 63;
-    if (item >= n) return;
-    const int64_t i = list[item];
+// u' for leaves with a long - list (sequential fma chain), staged in LDS by a
+// 256-thread block like k_dual_long; u' replaces ds for k_primal.
+__device__ void primal_long_chunked(const PrimalArgs &a, const Coef &cf, int64_t i, int lane) {
     const int ln = a.level[i];
     const uint32_t e0 = a.off[i], e1 = a.off[i + 1];
     float acc = a.ds[i];
@@ -188,6 +226,30 @@ __global__ void __launch_bounds__(kBlk) k_primal_long(uint32_t n, const uint32_t
         pm = pmn;
     }
     if (lane == 0) a.ds[i] = __fmaf_rn(a.tau, acc, a.u_in[i]);
+}
+
+__global__ void __launch_bounds__(kBlk) k_primal_long(uint32_t n, const uint32_t *list, PrimalArgs a, Coef cf) {
+    extern __shared__ unsigned char smem[];
+    if (blockIdx.x >= n) return;
+    const int64_t i = list[blockIdx.x];
+    const uint32_t e0 = a.off[i], e1 = a.off[i + 1], ne = e1 - e0;
+    if (ne > kPrimalStage) {
+        if (threadIdx.x < 64) primal_long_chunked(a, cf, i, threadIdx.x);
+        return;
+    }
+    float *sc = reinterpret_cast<float *>(smem);
+    float *sp = sc + kPrimalStage;
+    const int ln = a.level[i];
+    for (uint32_t q = threadIdx.x; q < ne; q += kBlk) {
+        const uint32_t v = a.ent[e0 + q];
+        sc[q] = cf.cp[v >> (kIdxBits + 2)][ln];
+        sp[q] = a.p[(int64_t)((v >> kIdxBits) & 3) * a.cap + (v & kIdxMask)];
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    float acc = a.ds[i];
+    for (uint32_t q = 0; q < ne; ++q) acc = __fmaf_rn(-sc[q], sp[q], acc);
+    a.ds[i] = __fmaf_rn(a.tau, acc, a.u_in[i]);
 }
 
 // Divergence per thread, then the prox cooperatively: the wave takes its 64
@@ -329,7 +391,7 @@ void launch_dual(Ctx &c, float sigma) {
     hipLaunchKernelGGL(k_dual, dim3((unsigned)cdiv(c.L, kBlk)), dim3(kBlk), 0, c.stream, a, c.coef);
     OTF_LAUNCH_CHECK("k_dual");
     if (s.n_heavy_p > 0) {
-        hipLaunchKernelGGL(k_dual_long, dim3((unsigned)cdiv(s.n_heavy_p * 64, kBlk)), dim3(kBlk), 0, c.stream,
+        hipLaunchKernelGGL(k_dual_long, dim3((unsigned)s.n_heavy_p), dim3(kBlk), kStageBytes, c.stream,
                            (uint32_t)s.n_heavy_p, s.heavy_p.p, a, c.coef);
         OTF_LAUNCH_CHECK("k_dual_long");
     }
@@ -366,7 +428,7 @@ void launch_primal(Ctx &c, float tau, float tl) {
     a.join_enabled = !(c.prm.join_tau > 1.0f);
     a.max_depth = c.prm.max_depth;
     if (s.n_heavy_m > 0) {
-        hipLaunchKernelGGL(k_primal_long, dim3((unsigned)cdiv(s.n_heavy_m * 64, kBlk)), dim3(kBlk), 0, c.stream,
+        hipLaunchKernelGGL(k_primal_long, dim3((unsigned)s.n_heavy_m), dim3(kBlk), kStageBytes, c.stream,
                            (uint32_t)s.n_heavy_m, s.heavy_m.p, a, c.coef);
         OTF_LAUNCH_CHECK("k_primal_long");
     }

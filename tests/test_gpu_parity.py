@@ -238,3 +238,43 @@ def test_error_paths():
     with pytest.raises(otf.OtfError) as e:
         _ctx().import_state(bytes(blob))
     assert e.value.status == 1
+
+
+def _slab_volumes(D, x0, width=2, seed=0):
+    G = 1 << D
+    rng = np.random.default_rng(seed)
+    f = np.ones((2, G, G, G), np.float32)
+    f[:, :, :, x0:x0 + width] = rng.uniform(-1, 1, (2, G, G, width)).astype(np.float32)
+    return f, np.ones((2, G, G, G), np.uint8)
+
+
+@pytest.mark.parametrize("D,x0", [(7, 64), (7, 62), (8, 128), (8, 126)])
+def test_long_adjacency_lists_parity(D, x0):
+    """Half-domain leaves against a refined slab: + lists (slab right of the
+    middle) or - lists (left of it) of 64^2 entries (staged in LDS) or 128^2
+    (folded in chunks) are summed in the canonical order."""
+    f, w = _slab_volumes(D, x0)
+    o = Oracle("f32").build_volumes(f, w, base_params(D))
+    counts, _ = o.neighbours()
+    side = 1 << (D - 1)
+    col = slice(0, 3) if x0 >= side else slice(3, 6)
+    assert counts[:, col].sum(1).max() >= side * side
+    g = _ctx().import_state(o.export_state())
+    for _ in range(3):
+        o.fuse(2, 0.5, TAU32, TAU32)
+        g.fuse(2, 0.5, TAU32, TAU32)
+        assert g.export_state() == o.export_state()
+
+
+def test_blocks_workload_parity():
+    """The depth-8 workload of 6 spheres and 4 boxes, 32 views 640x480 with
+    outliers: build and two iterations with split/join, bit for bit."""
+    w = synth.workload(2)
+    g = _ctx().build_octree(w.depth, w.cams, w.params)
+    o = Oracle("f32").build(w.depth, w.cams, w.params)
+    assert g.export_state() == o.export_state()
+    for _ in range(2):
+        g.fuse(1, w.lam, w.tau, w.sigma)
+        o.fuse(1, w.lam, w.tau, w.sigma)
+        assert g.last_counts() == o.last_counts()
+        assert g.export_state() == o.export_state()
