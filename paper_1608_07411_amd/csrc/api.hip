@@ -280,8 +280,12 @@ otf_status otf_create(int device, void *hip_stream, otf_ctx **out) {
         OTF_HIP(hipMemsetAsync(ctx->c.counters.p, 0, 32 * sizeof(uint32_t), ctx->c.stream));
         OTF_HIP(hipStreamSynchronize(ctx->c.stream));
         void *h = nullptr;
-        OTF_HIP(hipHostMalloc(&h, 32 * sizeof(uint32_t), hipHostMallocDefault));
+        OTF_HIP(hipHostMalloc(&h, 32 * sizeof(uint32_t), hipHostMallocMapped | hipHostMallocCoherent));
         ctx->c.h_counters = (uint32_t *)h;
+        std::memset(h, 0, 32 * sizeof(uint32_t));
+        void *d = nullptr;
+        OTF_HIP(hipHostGetDevicePointer(&d, h, 0));
+        ctx->c.d_h_counters = (uint32_t *)d;
     });
     if (st != OTF_OK) {
         otf_destroy(ctx);
@@ -381,7 +385,7 @@ otf_status otf_fuse(otf_ctx *ctx, int32_t iterations, float lambda, float tau, f
                 prof_end(c, kProfRestructure);
             }
         }
-        OTF_HIP(hipStreamSynchronize(c.stream));
+        read_back(c, {});  // synchronises and checks the scan health flag
     });
 }
 
@@ -716,8 +720,7 @@ otf_status otf_profile_read(otf_ctx *ctx, double *ms, int64_t *launches, int64_t
         }
         if (leaf_updates) *leaf_updates = c.leaf_updates;
         if (bytes) {
-            OTF_HIP(hipMemcpyAsync(c.h_counters + 16, c.counters.p + 16, 8, hipMemcpyDeviceToHost, c.stream));
-            OTF_HIP(hipStreamSynchronize(c.stream));
+            read_back(c, {{c.counters.p + 16, 16}, {c.counters.p + 17, 17}});
             unsigned long long obs_acc;
             std::memcpy(&obs_acc, c.h_counters + 16, 8);
             bytes[0] = c.alg_bytes[0];

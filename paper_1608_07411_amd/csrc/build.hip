@@ -326,8 +326,7 @@ void build_views_and_union(Ctx &c, const float *depth_dev, const std::vector<Cam
         OTF_LAUNCH_CHECK("k_union_offsets");
     }
     uint32_t L0 = 0;
-    OTF_HIP(hipMemcpyAsync(&c.h_counters[9], lc.p, sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
-    OTF_HIP(hipStreamSynchronize(c.stream));
+    read_back(c, {{lc.p, 9}});
     L0 = c.h_counters[9];
     if (c.prm.max_leaves > 0 && (int64_t)L0 > c.prm.max_leaves) fail(OTF_E_CAPACITY, "initial leaves exceed max_leaves");
     if ((int64_t)L0 >= kLeafLimit) fail(OTF_E_CAPACITY, "initial leaves exceed 2^26");

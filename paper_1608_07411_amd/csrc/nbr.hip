@@ -394,9 +394,7 @@ void build(Ctx &c, const NbrOld &old) {
         hipLaunchKernelGGL(k_nbr_count, dim3(g), dim3(kBlk), 0, c.stream, ki, s.level.p, D, c.s.a.p, c.s.b.p,
                            c.s.g.p, old, hv);
         OTF_LAUNCH_CHECK("k_nbr_count");
-        OTF_HIP(hipMemcpyAsync(c.h_counters + 3, c.counters.p + 3, sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
-        OTF_HIP(hipMemcpyAsync(c.h_counters + 9, c.counters.p + 9, sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
-        OTF_HIP(hipStreamSynchronize(c.stream));
+        read_back(c, {{c.counters.p + 3, 3}, {c.counters.p + 9, 9}});
         n_heavy = c.h_counters[3];
         if (n_heavy <= cap) break;
         cap = n_heavy;  // rare: more long ranges than room; count again with room for all
@@ -409,9 +407,7 @@ void build(Ctx &c, const NbrOld &old) {
         c.s.ch_base.reserve(n_heavy + 1);
         hipLaunchKernelGGL(k_chunk_count, dim3(gi), dim3(kBlk), 0, c.stream, n_heavy, hv, c.s.ch_base.p);
         scan_exclusive_u32_dev(c, c.s.ch_base.p, c.s.ch_base.p, n_heavy);
-        OTF_HIP(hipMemcpyAsync(c.h_counters + 3, c.s.ch_base.p + n_heavy, sizeof(uint32_t), hipMemcpyDeviceToHost,
-                               c.stream));
-        OTF_HIP(hipStreamSynchronize(c.stream));
+        read_back(c, {{c.s.ch_base.p + n_heavy, 3}});
         n_chunks = c.h_counters[3];
         c.s.ch_item.reserve(n_chunks);
         c.s.ch_count.reserve(n_chunks + 1);
@@ -437,11 +433,7 @@ void build(Ctx &c, const NbrOld &old) {
     hipLaunchKernelGGL(k_heavy_lists, dim3(g), dim3(kBlk), 0, c.stream, L, (const uint32_t *)s.nbp_off.p,
                        (const uint32_t *)s.nbm_off.p, s.heavy_p.p, s.heavy_m.p, c.counters.p + 14);
     OTF_LAUNCH_CHECK("k_heavy_lists");
-    OTF_HIP(hipMemcpyAsync(c.h_counters + 10, s.nbp_off.p + L, sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
-    OTF_HIP(hipMemcpyAsync(c.h_counters + 11, s.nbm_off.p + L, sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
-    OTF_HIP(hipMemcpyAsync(c.h_counters + 14, c.counters.p + 14, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost,
-                           c.stream));
-    OTF_HIP(hipStreamSynchronize(c.stream));
+    read_back(c, {{s.nbp_off.p + L, 10}, {s.nbm_off.p + L, 11}, {c.counters.p + 14, 14}, {c.counters.p + 15, 15}});
     s.n_nbp = c.h_counters[10];
     s.n_nbm = c.h_counters[11];
     s.n_heavy_p = c.h_counters[14];

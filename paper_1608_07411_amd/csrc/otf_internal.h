@@ -8,6 +8,7 @@
 #include <cstring>
 #include <string>
 #include <vector>
+#include <initializer_list>
 
 #include "otf.h"
 
@@ -235,12 +236,19 @@ struct Round {
     int64_t np = 0, nc = 0;
 };
 
+// Look-back scan state: per-tile state words, epoch-tagged so that they are
+// never cleared between scans.
+struct ScanState {
+    DBuf<unsigned long long> state;
+    uint32_t epoch = 0;
+};
+
 // Scratch reused across phases.
 struct Scratch {
     DBuf<uint32_t> a, b, c, d, e, f, g;
     DBuf<uint8_t> u8a, u8b;
     DBuf<float> fa, fb, fc, fd, fe;
-    DBuf<uint32_t> scan_lv[4];  // per-level tile sums of the device scans
+    ScanState scan;
     DBuf<uint32_t> hv_leaf, hv_lo, hv_hi;  // adjacency: faces with long ranges
     DBuf<uint8_t> hv_face;
     DBuf<uint32_t> ch_base, ch_item, ch_count, ch_pos;  // chunks of the long ranges
@@ -248,11 +256,9 @@ struct Scratch {
     DBuf<uint32_t> long_copy;                           // unchanged leaves with long adjacency lists
     // restructure temporaries (grow-only: an allocation or free per iteration
     // would synchronise the device)
-    DBuf<uint8_t> r_sf, r_tM, r_tU, r_isnew, r_jf, r_Mt;
-    DBuf<uint32_t> r_jr, r_cnt, r_pos, r_nrank, r_tidx, r_moff, r_loff, r_toff;
-    DBuf<uint32_t> r_jkey[2], r_jhead[2];
-    DBuf<uint8_t> r_jlev[2], r_jtgt[2], r_jrole[2];
-    DBuf<float> r_jv[2];
+    DBuf<uint8_t> r_sf, r_tM, r_tU, r_isnew, r_Mt;
+    DBuf<uint32_t> r_nrank, r_tidx, r_moff, r_loff, r_toff;
+    DBuf<float> r_jv;
     DBuf<double> dred;
     std::vector<Round *> rounds;
     ~Scratch() {
@@ -280,8 +286,10 @@ struct Ctx {
     // device counters: [0] split flags [1] join flags [2] collapse heads
     // [3] long ranges [4..7] observation totals (2 x u64) [9] long copies
     // [14,15] long-list counts [16..17] accumulated observation totals (u64)
+    // [24] scan health flag (non-zero: a look-back wait timed out)
     DBuf<uint32_t> counters;
-    uint32_t *h_counters = nullptr;  // pinned host slots for read-backs (32)
+    uint32_t *h_counters = nullptr;    // pinned, coherent host slots for read-backs (32)
+    uint32_t *d_h_counters = nullptr;  // the same slots as the device addresses them
     int64_t last_splits = 0, last_joins = 0;
     // profiling: event pairs recorded on the stream, summed when read
     struct ProfRec {
@@ -311,6 +319,16 @@ struct Ctx {
 // ---------------------------------------------------------------------------
 // launchers (each issues work on ctx.stream)
 // ---------------------------------------------------------------------------
+// Host read-back: one small kernel stores up to kReadMax device u32 values into
+// the host slots h_counters[slot], then the stream is synchronised. The scan
+// health flag travels with every read-back and raises OTF_E_DEVICE when set.
+constexpr int kReadMax = 4;
+constexpr int kScanHealthSlot = 24;
+struct ReadItem {
+    const uint32_t *src;
+    int slot;
+};
+void read_back(Ctx &c, std::initializer_list<ReadItem> items);
 // scans over n elements; the total is returned to the host (synchronises)
 uint32_t scan_exclusive_u8(Ctx &c, const uint8_t *in, uint32_t *out, int64_t n);
 uint32_t scan_exclusive_u32(Ctx &c, const uint32_t *in, uint32_t *out, int64_t n);

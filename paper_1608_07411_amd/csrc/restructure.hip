@@ -23,10 +23,6 @@ constexpr int kBlk = 256;
 unsigned grid(int64_t n) { return (unsigned)cdiv(n > 0 ? n : 1, kBlk); }
 #define TID() ((int64_t)blockIdx.x * kBlk + threadIdx.x)
 
-__global__ void k_copy_u32(const uint32_t *src, uint32_t *dst) {
-    if (threadIdx.x == 0) *dst = *src;
-}
-
 __global__ void k_zero_counter2(uint32_t *counters) {
     if (threadIdx.x == 0) counters[2] = 0u;
 }
@@ -104,101 +100,67 @@ struct OldStore {
     const uint8_t *flag;
 };
 
-// Hierarchical means of the collapsed blocks, bottom-up in parallel. The
-// joinable leaves with a collapse target form a list in Morton order; for
-// level l = D .. 1 every complete group of 8 consecutive siblings at level l
-// (inside a block that collapses above l) is replaced by its parent with
-// 1/8 of the sum of the 8 values in child order. Afterwards each block is one
-// node. Each node carries the old index of its subtree's first leaf, which for
-// the final node is the block's first leaf (whose emission slot it takes).
-struct JNodes {
-    uint32_t *key, *head;
-    uint8_t *lev, *tgt, *role;
-    float *v;  // 5 planes (u, ubar, px, py, pz) of `cap`
-    int64_t cap;
-};
-
-__global__ void k_jflags(int64_t L, const uint8_t *jt, uint8_t *f) {
-    const int64_t i = TID();
-    if (i < L) f[i] = jt[i] != 0xFF ? 1 : 0;
-}
-
-__global__ void k_jinit(int64_t L, const uint8_t *jt, const uint32_t *rank, OldStore o, JNodes J) {
+// Hierarchical means of the collapsed blocks, bottom-up in parallel, in place
+// over the old leaf positions. val holds, at the position of a node's first
+// leaf, the node's 5 values (u, ubar, px, py, pz); it starts as the leaves'
+// own values. For q = D-1 .. 0, every inner node at level q inside a block
+// (block level <= q, first leaf deeper than q) reads its 8 children at level
+// q+1 (child c starts at the first leaf with key >= key + c * 8^(D-q-1)) and
+// stores 1/8 of their sum in child order at its first leaf. Afterwards the
+// block's first leaf holds the block's values.
+__global__ void k_jval_init(int64_t L, const uint8_t *jt, OldStore o, float *val, int64_t cap) {
     const int64_t i = TID();
     if (i >= L || jt[i] == 0xFF) return;
-    const uint32_t t = rank[i];
-    J.key[t] = o.key[i];
-    J.head[t] = (uint32_t)i;
-    J.lev[t] = o.level[i];
-    J.tgt[t] = jt[i];
-    J.v[t] = o.u[i];
-    J.v[J.cap + t] = o.ubar[i];
-    J.v[2 * J.cap + t] = o.p[i];
-    J.v[3 * J.cap + t] = o.p[o.cap + i];
-    J.v[4 * J.cap + t] = o.p[2 * o.cap + i];
+    val[i] = o.u[i];
+    val[cap + i] = o.ubar[i];
+    val[2 * cap + i] = o.p[i];
+    val[3 * cap + i] = o.p[o.cap + i];
+    val[4 * cap + i] = o.p[2 * o.cap + i];
 }
 
-__device__ inline bool group_complete(const JNodes &J, int64_t g, uint32_t n, int l, int D) {
-    if (g < 0 || g + 7 >= (int64_t)n) return false;
-    const int sh = 3 * (D - l);
-    const uint32_t k0 = J.key[g];
-    if (((k0 >> sh) & 7u) != 0) return false;
-    for (int c = 0; c < 8; ++c)
-        if (J.lev[g + c] != l || J.key[g + c] != k0 + ((uint32_t)c << sh)) return false;
-    return true;
-}
-
-// role: 0 carried, 1 first child of a complete group, 2 other child
-__global__ void k_jmark(int64_t nmax, const uint32_t *n_dev, JNodes J, int l, int D, uint32_t *cnt) {
-    const int64_t t = TID();
-    if (t >= nmax) return;
-    const uint32_t n = *n_dev;
-    if (t >= (int64_t)n) {
-        cnt[t] = 0;
-        return;
-    }
-    uint8_t role = 0;
-    if (J.lev[t] == l && J.tgt[t] < l) {
-        const int ci = (int)((J.key[t] >> (3 * (D - l))) & 7u);
-        if (group_complete(J, t - ci, n, l, D)) role = ci == 0 ? 1 : 2;
-    }
-    J.role[t] = role;
-    cnt[t] = role == 2 ? 0u : 1u;
-}
-
-__global__ void k_jmerge(int64_t nmax, const uint32_t *n_dev, JNodes A, JNodes B, const uint32_t *pos) {
-    const int64_t t = TID();
-    if (t >= nmax || t >= (int64_t)*n_dev) return;
-    const uint8_t role = A.role[t];
-    if (role == 2) return;
-    const uint32_t w = pos[t];
-    B.key[w] = A.key[t];
-    B.head[w] = A.head[t];
-    B.tgt[w] = A.tgt[t];
-    if (role == 0) {
-        B.lev[w] = A.lev[t];
-        for (int q = 0; q < 5; ++q) B.v[q * B.cap + w] = A.v[q * A.cap + t];
-    } else {
-        B.lev[w] = A.lev[t] - 1;
-        for (int q = 0; q < 5; ++q) {
-            float acc = 0.0f;
-            for (int c = 0; c < 8; ++c) acc = acc + A.v[q * A.cap + t + c];
-            B.v[q * B.cap + w] = 0.125f * acc;
+__global__ void k_jval_level(int64_t L, int D, int q, const uint8_t *jt, const uint32_t *key, const uint8_t *level,
+                             float *val, int64_t cap) {
+    const int64_t i = TID();
+    if (i >= L || jt[i] == 0xFF || jt[i] > q || level[i] <= q) return;
+    const uint64_t k0 = key[i];
+    if (k0 & ((uint64_t(1) << (3 * (D - q))) - 1)) return;  // not the first leaf of a level-q node
+    const uint64_t step = uint64_t(1) << (3 * (D - q - 1));
+    int64_t pos[8];
+    pos[0] = i;
+    int64_t lo = i + 1;
+    const int64_t end = min(L, i + (int64_t)(uint64_t(1) << (3 * (D - q))));
+    for (int c = 1; c < 8; ++c) {
+        const uint64_t kc = k0 + c * step;
+        int64_t a = lo, b = end;  // first index in [lo, end) with key >= kc
+        while (a < b) {
+            const int64_t m = (a + b) >> 1;
+            if ((uint64_t)key[m] < kc) a = m + 1;
+            else b = m;
         }
+        pos[c] = a;
+        lo = a + 1;
     }
+    float v[5];
+    for (int w = 0; w < 5; ++w) {
+        float acc = 0.0f;
+        for (int c = 0; c < 8; ++c) acc = acc + val[w * cap + pos[c]];
+        v[w] = 0.125f * acc;
+    }
+    for (int w = 0; w < 5; ++w) val[w * cap + i] = v[w];
 }
 
-__global__ void k_jemit(int64_t nmax, const uint32_t *n_dev, JNodes J, const uint32_t *out_off, NewStore ns) {
-    const int64_t t = TID();
-    if (t >= nmax || t >= (int64_t)*n_dev) return;
-    const uint32_t w = out_off[J.head[t]];
-    ns.key[w] = J.key[t];
-    ns.level[w] = J.lev[t];
-    ns.u[w] = J.v[t];
-    ns.ubar[w] = J.v[J.cap + t];
-    ns.p[w] = J.v[2 * J.cap + t];
-    ns.p[ns.cap + w] = J.v[3 * J.cap + t];
-    ns.p[2 * ns.cap + w] = J.v[4 * J.cap + t];
+__global__ void k_jval_emit(int64_t L, const uint8_t *jt, const uint8_t *jhead, const float *val, int64_t cap,
+                            const uint32_t *out_off, NewStore ns, const uint32_t *key) {
+    const int64_t i = TID();
+    if (i >= L || !jhead[i]) return;
+    const uint32_t w = out_off[i];
+    ns.key[w] = key[i];
+    ns.level[w] = jt[i];
+    ns.u[w] = val[i];
+    ns.ubar[w] = val[cap + i];
+    ns.p[w] = val[2 * cap + i];
+    ns.p[ns.cap + w] = val[3 * cap + i];
+    ns.p[2 * ns.cap + w] = val[4 * cap + i];
     ns.isnew[w] = 1;
     ns.src[w] = kNone;
     ns.need[w] = 1;
@@ -408,8 +370,7 @@ Round &round_at(Ctx &c, size_t r) {
 }
 
 uint32_t read_u32(Ctx &c, const uint32_t *dev, int slot) {
-    OTF_HIP(hipMemcpyAsync(c.h_counters + slot, dev, sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
-    OTF_HIP(hipStreamSynchronize(c.stream));
+    read_back(c, {{dev, slot}});
     return c.h_counters[slot];
 }
 
@@ -419,8 +380,7 @@ bool restructure(Ctx &c, float tl) {
     const int D = c.prm.max_depth;
     const int64_t L = c.L;
     LeafStore &os = c.lv();
-    OTF_HIP(hipMemcpyAsync(c.h_counters, c.counters.p, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
-    OTF_HIP(hipStreamSynchronize(c.stream));
+    read_back(c, {{c.counters.p, 0}, {c.counters.p + 1, 1}});
     const uint32_t n_split = c.h_counters[0], n_join = c.h_counters[1];
     c.last_splits = c.last_joins = 0;
     if (n_split == 0 && n_join == 0) return false;
@@ -527,9 +487,7 @@ bool restructure(Ctx &c, float tl) {
     OTF_LAUNCH_CHECK("k_out_count");
     scan_exclusive_u32_dev(c, s.e.p, s.f.p, L);
     const uint32_t *out_off = s.f.p;
-    OTF_HIP(hipMemcpyAsync(c.h_counters + 12, s.f.p + L, sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
-    OTF_HIP(hipMemcpyAsync(c.h_counters + 13, c.counters.p + 2, sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
-    OTF_HIP(hipStreamSynchronize(c.stream));
+    read_back(c, {{s.f.p + L, 12}, {c.counters.p + 2, 13}});
     const int64_t Lnew = c.h_counters[12];
     if (jt) c.last_joins = c.h_counters[13];
     c.last_splits = total_splits;
@@ -547,44 +505,17 @@ bool restructure(Ctx &c, float tl) {
     hipLaunchKernelGGL(k_emit_keep, dim3(gL), dim3(kBlk), 0, c.stream, L, osd, jt, n_split > 0 ? 1 : 0, out_off, nsd);
     OTF_LAUNCH_CHECK("k_emit_keep");
     if (jt) {
-        // collapse: merge list of the joinable leaves with a target
-        const int64_t nmax = n_join;
-        DBuf<uint8_t> &jf = s.r_jf;
-        jf.reserve(L);
-        DBuf<uint32_t> &jr = s.r_jr, &cnt = s.r_cnt, &pos = s.r_pos;
-        jr.reserve(L + 1);
-        cnt.reserve(nmax);
-        pos.reserve(nmax + 1);
-        DBuf<uint32_t> *k2 = s.r_jkey, *h2 = s.r_jhead;
-        DBuf<uint8_t> *lv2 = s.r_jlev, *tg2 = s.r_jtgt, *ro2 = s.r_jrole;
-        DBuf<float> *v2 = s.r_jv;
-        JNodes J[2];
-        for (int b = 0; b < 2; ++b) {
-            k2[b].reserve(nmax);
-            h2[b].reserve(nmax);
-            lv2[b].reserve(nmax);
-            tg2[b].reserve(nmax);
-            ro2[b].reserve(nmax);
-            v2[b].reserve(5 * nmax);
-            J[b] = JNodes{k2[b].p, h2[b].p, lv2[b].p, tg2[b].p, ro2[b].p, v2[b].p, nmax};
-        }
-        hipLaunchKernelGGL(k_jflags, dim3(gL), dim3(kBlk), 0, c.stream, L, jt, jf.p);
-        scan_exclusive_u32_dev_u8(c, jf.p, jr.p, L);  // jr[L] = list length
-        hipLaunchKernelGGL(k_jinit, dim3(gL), dim3(kBlk), 0, c.stream, L, jt, jr.p, osd, J[0]);
-        const uint32_t *n_dev = jr.p + L;
-        const unsigned gN = grid(nmax);
-        int a = 0;
-        for (int l = D; l >= 1; --l) {
-            hipLaunchKernelGGL(k_jmark, dim3(gN), dim3(kBlk), 0, c.stream, nmax, n_dev, J[a], l, D, cnt.p);
-            scan_exclusive_u32_dev(c, cnt.p, pos.p, nmax);
-            hipLaunchKernelGGL(k_jmerge, dim3(gN), dim3(kBlk), 0, c.stream, nmax, n_dev, J[a], J[a ^ 1], pos.p);
-            OTF_LAUNCH_CHECK("join merge");
-            // the merged list length is the scan total; keep it for the next level
-            hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(64), 0, c.stream, pos.p + nmax, jr.p + L);
-            a ^= 1;
-        }
-        hipLaunchKernelGGL(k_jemit, dim3(gN), dim3(kBlk), 0, c.stream, nmax, n_dev, J[a], out_off, nsd);
-        OTF_LAUNCH_CHECK("k_jemit");
+        // collapse: hierarchical means level by level, in place
+        DBuf<float> &val = s.r_jv;
+        val.reserve(5 * (size_t)L);
+        const int64_t vc = L;
+        hipLaunchKernelGGL(k_jval_init, dim3(gL), dim3(kBlk), 0, c.stream, L, jt, osd, val.p, vc);
+        for (int q = D - 1; q >= 0; --q)
+            hipLaunchKernelGGL(k_jval_level, dim3(gL), dim3(kBlk), 0, c.stream, L, D, q, jt, os.key.p, os.level.p,
+                               val.p, vc);
+        hipLaunchKernelGGL(k_jval_emit, dim3(gL), dim3(kBlk), 0, c.stream, L, jt, jhead, val.p, vc, out_off, nsd,
+                           os.key.p);
+        OTF_LAUNCH_CHECK("join means");
     }
     for (int64_t q = 0; q < nrounds; ++q) {
         Round &R = *s.rounds[q];
@@ -620,9 +551,7 @@ bool restructure(Ctx &c, float tl) {
     DBuf<uint32_t> &loff = s.r_loff;
     loff.reserve(Lnew + 1);
     scan_exclusive_u32_dev_u8(c, ns.obs_m.p, loff.p, Lnew);
-    OTF_HIP(hipMemcpyAsync(c.h_counters + 12, moff.p + n_new, sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
-    OTF_HIP(hipMemcpyAsync(c.h_counters + 13, loff.p + Lnew, sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
-    OTF_HIP(hipStreamSynchronize(c.stream));
+    read_back(c, {{moff.p + n_new, 12}, {loff.p + Lnew, 13}});
     const uint32_t new_obs = c.h_counters[12], live = c.h_counters[13];
     const bool compact = (pool.used + (int64_t)new_obs > pool.cap) || (pool.used > 2 * (int64_t)live + 4096);
     if (!compact) {

@@ -1,13 +1,14 @@
-// Device-wide prefix scans (reduce-then-scan over tiles of 2048 elements;
-// wave64 shuffles inside a wave, LDS across the 4 waves of a block). Used for
-// compaction: leaf emission, observation and adjacency offsets, split lists.
+// Device-wide prefix scans (one pass over tiles of 8192 elements with
+// decoupled look-back; wave64 shuffles inside a wave, LDS across the 4 waves
+// of a block), used for compaction: leaf emission, observation and adjacency
+// offsets, split lists. Also the small host read-backs of device counters.
 #include "otf_internal.h"
 
 namespace otf {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kItems = 8;
+constexpr int kItems = 32;  // consecutive elements per thread, moved with 16-byte loads and stores
 constexpr int kTile = kThreads * kItems;
 constexpr int kWaves = kThreads / 64;
 
@@ -43,52 +44,144 @@ __device__ void block_scan(uint32_t v, uint32_t *smem, Op op, uint32_t &excl, ui
     total = tot;
 }
 
-template <class In, class Op>
-__global__ void __launch_bounds__(kThreads) tile_reduce(const In *__restrict__ in, int64_t n,
-                                                        uint32_t *__restrict__ tile_sums, Op op) {
-    __shared__ uint32_t smem[kWaves];
-    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
-    uint32_t acc = 0;
+// Thread-contiguous loads of kItems elements (16-byte vectors when the whole
+// run is in range and aligned) and the matching u32 stores.
+__device__ inline void load_items(const uint32_t *in, int64_t first, int64_t n, bool vec, uint32_t (&v)[kItems]) {
+    if (vec && first + kItems <= n) {
+        const uint4 *q = reinterpret_cast<const uint4 *>(in + first);
 #pragma unroll
-    for (int k = 0; k < kItems; ++k)
-        if (base + k < n) acc = op(acc, (uint32_t)in[base + k]);
-    uint32_t excl, total;
-    block_scan(acc, smem, op, excl, total);
-    if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+        for (int k = 0; k < kItems / 4; ++k) {
+            const uint4 w = q[k];
+            v[4 * k] = w.x;
+            v[4 * k + 1] = w.y;
+            v[4 * k + 2] = w.z;
+            v[4 * k + 3] = w.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) v[k] = (first + k < n) ? in[first + k] : 0u;
+    }
 }
 
-// out[i] = op(tile prefix, in[tile start .. i-1]) (exclusive) or .. i (inclusive).
-// May run in place (each thread reads its items before writing them).
+__device__ inline void load_items(const uint8_t *in, int64_t first, int64_t n, bool vec, uint32_t (&v)[kItems]) {
+    if (vec && first + kItems <= n) {
+        const uint4 *q = reinterpret_cast<const uint4 *>(in + first);
+#pragma unroll
+        for (int k = 0; k < kItems / 16; ++k) {
+            const uint4 w = q[k];
+            const uint32_t x[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int j = 0; j < 16; ++j) v[16 * k + j] = (x[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) v[k] = (first + k < n) ? (uint32_t)in[first + k] : 0u;
+    }
+}
+
+__device__ inline void store_items(uint32_t *out, int64_t first, int64_t n, bool vec, const uint32_t (&o)[kItems]) {
+    if (vec && first + kItems <= n) {
+        uint4 *q = reinterpret_cast<uint4 *>(out + first);
+#pragma unroll
+        for (int k = 0; k < kItems / 4; ++k) q[k] = make_uint4(o[4 * k], o[4 * k + 1], o[4 * k + 2], o[4 * k + 3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < kItems; ++k)
+            if (first + k < n) out[first + k] = o[k];
+    }
+}
+
+// Single-pass scan with decoupled look-back. Block b scans tile b: it
+// publishes the tile aggregate, then its first wave looks back over the
+// states of the preceding tiles, 64 at a time, until it meets a tile whose
+// inclusive prefix is published; it then publishes its own inclusive prefix
+// and writes its outputs. Workgroups are dispatched in index order, so every
+// tile a block waits on belongs to a block that is running or done.
+//
+// Tile state word: epoch (bits 63..34) | status (33..32: 1 aggregate,
+// 2 inclusive prefix) | value (31..0). The epoch changes with every scan, so
+// the states never need clearing; a word of another epoch reads as "not yet".
+// The wait is bounded: after kSpinLimit polls the block records the failure
+// in the health flag (read back by the host) and continues, so a kernel never
+// hangs.
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+__device__ inline uint64_t pack_state(uint32_t epoch, uint32_t status, uint32_t value) {
+    return ((uint64_t)epoch << 34) | ((uint64_t)status << 32) | value;
+}
+
 template <class In, class Op>
-__global__ void __launch_bounds__(kThreads) tile_scan(const In *in, int64_t n, const uint32_t *__restrict__ tile_prefix,
-                                                      uint32_t *out, Op op, int exclusive,
-                                                      uint32_t *__restrict__ total_out) {
+__global__ void __launch_bounds__(kThreads) k_scan(const In *in, int64_t n, uint32_t *out, Op op, int exclusive,
+                                                   int vec, uint32_t *total_out, unsigned long long *state,
+                                                   uint32_t epoch, int64_t ntiles, uint32_t *health) {
     __shared__ uint32_t smem[kWaves];
-    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
+    __shared__ uint32_t s_prefix;
+    const int64_t tile = blockIdx.x;
+    const int64_t first = tile * kTile + (int64_t)threadIdx.x * kItems;
     uint32_t v[kItems];
+    load_items(in, first, n, vec != 0, v);
     uint32_t acc = 0;
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        v[k] = (base + k < n) ? (uint32_t)in[base + k] : 0u;
-        acc = op(acc, v[k]);
-    }
+    for (int k = 0; k < kItems; ++k) acc = op(acc, v[k]);
     uint32_t excl, total;
     block_scan(acc, smem, op, excl, total);
-    const uint32_t tp = tile_prefix ? tile_prefix[blockIdx.x] : 0u;
+    if (threadIdx.x == 0)
+        __hip_atomic_store(&state[tile], pack_state(epoch, tile == 0 ? 2u : 1u, total), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    if (tile > 0 && threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        uint32_t prefix = 0;
+        int64_t look = tile - 1;  // lane j reads tile look - j
+        uint32_t spins = 0;
+        while (true) {
+            const int64_t t = look - lane;
+            uint32_t st = 2, val = 0;  // before tile 0: an empty prefix (never summed)
+            if (t >= 0) {
+                const uint64_t w = __hip_atomic_load(&state[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                st = ((uint32_t)(w >> 34) == epoch) ? (uint32_t)(w >> 32) & 3u : 0u;
+                val = (uint32_t)w;
+            }
+            const uint64_t have_prefix = __ballot(st == 2);
+            const uint64_t not_ready = __ballot(st == 0);
+            const int stop = have_prefix ? __ffsll((long long)have_prefix) - 1 : 64;  // nearest published prefix
+            const uint64_t needed = stop >= 63 ? ~0ull : ((2ull << stop) - 1);
+            if (not_ready & needed) {
+                if (++spins > kSpinLimit) {
+                    if (lane == 0) atomicOr(health, 1u);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                continue;
+            }
+            uint32_t x = lane <= stop ? val : 0u;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) x = op(x, (uint32_t)__shfl_xor((int)x, off, 64));
+            prefix = op(prefix, x);
+            if (stop < 64) break;
+            look -= 64;
+        }
+        if (lane == 0) {
+            __hip_atomic_store(&state[tile], pack_state(epoch, 2u, op(prefix, total)), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            s_prefix = prefix;
+        }
+    }
+    __syncthreads();
+    const uint32_t tp = tile > 0 ? s_prefix : 0u;
     uint32_t run = op(tp, excl);
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
-        if (base + k < n) {
-            if (exclusive) {
-                out[base + k] = run;
-                run = op(run, v[k]);
-            } else {
-                run = op(run, v[k]);
-                out[base + k] = run;
-            }
+        const uint32_t x = v[k];
+        if (exclusive) {
+            v[k] = run;
+            run = op(run, x);
+        } else {
+            run = op(run, x);
+            v[k] = run;
         }
     }
-    if (total_out && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total_out = op(tp, total);
+    store_items(out, first, n, vec != 0, v);
+    if (total_out && tile == ntiles - 1 && threadIdx.x == 0) *total_out = op(tp, total);
 }
 
 __global__ void fill_u32(uint32_t *p, int64_t n, uint32_t v) {
@@ -96,24 +189,9 @@ __global__ void fill_u32(uint32_t *p, int64_t n, uint32_t v) {
     if (i < n) p[i] = v;
 }
 
-// Exclusive scan of the per-tile values in place (recursive over levels).
-template <class Op>
-void scan_tiles(Ctx &c, uint32_t *vals, int64_t n, Op op, size_t depth) {
-    if (n <= 1) {
-        if (n == 1) hipLaunchKernelGGL(fill_u32, dim3(1), dim3(64), 0, c.stream, vals, (int64_t)1, 0u);
-        return;
-    }
-    int64_t tiles = cdiv(n, kTile);
-    if (depth >= 4) fail(OTF_E_INVALID, "scan too large");
-    c.s.scan_lv[depth].reserve((size_t)tiles);
-    uint32_t *sums = c.s.scan_lv[depth].p;
-    hipLaunchKernelGGL((tile_reduce<uint32_t, Op>), dim3((unsigned)tiles), dim3(kThreads), 0, c.stream,
-                       (const uint32_t *)vals, n, sums, op);
-    OTF_LAUNCH_CHECK("tile_reduce");
-    scan_tiles(c, sums, tiles, op, depth + 1);
-    hipLaunchKernelGGL((tile_scan<uint32_t, Op>), dim3((unsigned)tiles), dim3(kThreads), 0, c.stream,
-                       (const uint32_t *)vals, n, (const uint32_t *)sums, vals, op, 1, (uint32_t *)nullptr);
-    OTF_LAUNCH_CHECK("tile_scan");
+__global__ void fill_u64(unsigned long long *p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
 }
 
 template <class In, class Op>
@@ -122,27 +200,62 @@ void scan_any(Ctx &c, const In *in, uint32_t *out, int64_t n, Op op, bool exclus
         if (total_dev) hipLaunchKernelGGL(fill_u32, dim3(1), dim3(64), 0, c.stream, total_dev, (int64_t)1, 0u);
         return;
     }
-    int64_t tiles = cdiv(n, kTile);
-    c.s.scan_lv[0].reserve((size_t)tiles);
-    uint32_t *sums = c.s.scan_lv[0].p;
-    if (tiles > 1) {
-        hipLaunchKernelGGL((tile_reduce<In, Op>), dim3((unsigned)tiles), dim3(kThreads), 0, c.stream, in, n, sums,
-                           op);
-        OTF_LAUNCH_CHECK("tile_reduce");
-        scan_tiles(c, sums, tiles, op, 1);
+    const int64_t tiles = cdiv(n, kTile);
+    ScanState &ss = c.s.scan;
+    if ((size_t)tiles > ss.state.n || !ss.state.p) {
+        ss.state.reserve((size_t)tiles);
+        hipLaunchKernelGGL(fill_u64, dim3((unsigned)cdiv((int64_t)ss.state.n, 256)), dim3(256), 0, c.stream,
+                           ss.state.p, (int64_t)ss.state.n);
+        ss.epoch = 0;
     }
-    hipLaunchKernelGGL((tile_scan<In, Op>), dim3((unsigned)tiles), dim3(kThreads), 0, c.stream, in, n,
-                       tiles > 1 ? (const uint32_t *)sums : (const uint32_t *)nullptr, out, op, exclusive ? 1 : 0,
-                       total_dev);
-    OTF_LAUNCH_CHECK("tile_scan");
+    if (++ss.epoch >= (1u << 30)) {  // epochs wrap: clear the states and restart
+        hipLaunchKernelGGL(fill_u64, dim3((unsigned)cdiv((int64_t)ss.state.n, 256)), dim3(256), 0, c.stream,
+                           ss.state.p, (int64_t)ss.state.n);
+        ss.epoch = 1;
+    }
+    const int vec = ((uintptr_t)in % 16 == 0 && (uintptr_t)out % 16 == 0) ? 1 : 0;
+    hipLaunchKernelGGL((k_scan<In, Op>), dim3((unsigned)tiles), dim3(kThreads), 0, c.stream, in, n, out, op,
+                       exclusive ? 1 : 0, vec, total_dev, ss.state.p, ss.epoch, tiles,
+                       c.counters.p + kScanHealthSlot);
+    OTF_LAUNCH_CHECK("k_scan");
+}
+
+struct ReadArgs {
+    const uint32_t *src[kReadMax + 1];
+    int slot[kReadMax + 1];
+    int n;
+};
+
+__global__ void k_read_back(ReadArgs a, uint32_t *host) {
+    const int t = threadIdx.x;
+    if (t < a.n) __hip_atomic_store(host + a.slot[t], *a.src[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 uint32_t read_total(Ctx &c, const uint32_t *dev) {
-    OTF_HIP(hipMemcpyAsync(c.h_counters + 8, dev, sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
-    OTF_HIP(hipStreamSynchronize(c.stream));
+    read_back(c, {{dev, 8}});
     return c.h_counters[8];
 }
 
+}  // namespace
+
+void read_back(Ctx &c, std::initializer_list<ReadItem> items) {
+    if (items.size() > (size_t)kReadMax) fail(OTF_E_INVALID, "too many read-back items");
+    ReadArgs a{};
+    for (const ReadItem &it : items) {
+        a.src[a.n] = it.src;
+        a.slot[a.n] = it.slot;
+        ++a.n;
+    }
+    a.src[a.n] = c.counters.p + kScanHealthSlot;
+    a.slot[a.n] = kScanHealthSlot;
+    ++a.n;
+    hipLaunchKernelGGL(k_read_back, dim3(1), dim3(64), 0, c.stream, a, c.d_h_counters);
+    OTF_LAUNCH_CHECK("k_read_back");
+    OTF_HIP(hipStreamSynchronize(c.stream));
+    if (c.h_counters[kScanHealthSlot]) fail(OTF_E_DEVICE, "a device scan's look-back wait timed out");
+}
+
+namespace {
 }  // namespace
 
 uint32_t scan_exclusive_u8(Ctx &c, const uint8_t *in, uint32_t *out, int64_t n) {

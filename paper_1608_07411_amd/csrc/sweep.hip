@@ -19,6 +19,8 @@ namespace otf {
 namespace {
 
 constexpr int kBlk = 256;
+constexpr int kAhead = 4;   // leaves whose observations one wave loads ahead in k_primal
+constexpr int kUnroll = 4;  // list entries per thread in flight while staging a long list
 
 __device__ inline float rdlane(float v, int l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
@@ -88,9 +90,11 @@ __global__ void __launch_bounds__(kBlk) k_dual(DualArgs a, Coef cf) {
 
 // Leaves with a long + list, one 256-thread block each: the block stages the
 // list's coefficients, neighbour differences and directions in LDS with
-// parallel loads, then one lane folds them in list order (the same sequential
-// fma chain as k_dual). Lists beyond the LDS budget are folded in 64-entry
-// chunks by the first wave, the next chunk fetched while one is folded.
+// parallel loads (kUnroll entries per thread in flight). The list holds the
+// +x, +y and +z neighbours one face after another, so the three fma chains of
+// k_dual are contiguous segments: lanes 0, 1 and 2 fold one each, in list
+// order. Lists beyond the LDS budget are folded in 64-entry chunks by the
+// first wave, the next chunk fetched while one is folded.
 constexpr int kStageBytes = 64 * 1024;
 constexpr uint32_t kDualStage = kStageBytes / 9;    // float c, float diff, u8 dir
 constexpr uint32_t kPrimalStage = kStageBytes / 8;  // float c', float p
@@ -140,6 +144,16 @@ __device__ void dual_long_chunked(const DualArgs &a, const Coef &cf, int64_t i, 
     if (lane == 0) dual_finish(a, i, gx, gy, gz, Cx, Cy, Cz);
 }
 
+__device__ inline uint32_t first_dir_at_least(const uint8_t *sd, uint32_t n, int d) {
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t m = (lo + hi) >> 1;
+        if (sd[m] < d) lo = m + 1;
+        else hi = m;
+    }
+    return lo;
+}
+
 __global__ void __launch_bounds__(kBlk) k_dual_long(uint32_t n, const uint32_t *list, DualArgs a, Coef cf) {
     extern __shared__ unsigned char smem[];
     if (blockIdx.x >= n) return;
@@ -154,30 +168,57 @@ __global__ void __launch_bounds__(kBlk) k_dual_long(uint32_t n, const uint32_t *
     uint8_t *sd = reinterpret_cast<uint8_t *>(sv + kDualStage);
     const int ln = a.level[i];
     const float ub = a.ubar[i];
-    for (uint32_t q = threadIdx.x; q < ne; q += kBlk) {
-        const uint32_t v = a.ent[e0 + q];
-        sd[q] = (uint8_t)((v >> kIdxBits) & 3);
-        sc[q] = cf.c[ln][v >> (kIdxBits + 2)];
-        sv[q] = a.ubar[v & kIdxMask] - ub;
-    }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    float gx = 0.0f, gy = 0.0f, gz = 0.0f, Cx = 0.0f, Cy = 0.0f, Cz = 0.0f;
-    for (uint32_t q = 0; q < ne; ++q) {
-        const float c = sc[q], v = sv[q];
-        const int d = sd[q];
-        if (d == 0) {
-            gx = __fmaf_rn(c, v, gx);
-            Cx = Cx + c;
-        } else if (d == 1) {
-            gy = __fmaf_rn(c, v, gy);
-            Cy = Cy + c;
-        } else {
-            gz = __fmaf_rn(c, v, gz);
-            Cz = Cz + c;
+    for (uint32_t q0 = threadIdx.x; q0 < ne; q0 += kUnroll * kBlk) {
+        uint32_t v[kUnroll];
+        float u[kUnroll];
+#pragma unroll
+        for (int r = 0; r < kUnroll; ++r) {
+            const uint32_t q = q0 + r * kBlk;
+            v[r] = q < ne ? a.ent[e0 + q] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < kUnroll; ++r) {
+            const uint32_t q = q0 + r * kBlk;
+            u[r] = q < ne ? a.ubar[v[r] & kIdxMask] : 0.0f;
+        }
+#pragma unroll
+        for (int r = 0; r < kUnroll; ++r) {
+            const uint32_t q = q0 + r * kBlk;
+            if (q < ne) {
+                sd[q] = (uint8_t)((v[r] >> kIdxBits) & 3);
+                sc[q] = cf.c[ln][v[r] >> (kIdxBits + 2)];
+                sv[q] = u[r] - ub;
+            }
         }
     }
-    dual_finish(a, i, gx, gy, gz, Cx, Cy, Cz);
+    __syncthreads();
+    if (threadIdx.x >= 64) return;
+    const int lane = threadIdx.x;
+    float g = 0.0f, C = 0.0f;
+    if (lane < 3) {
+        const uint32_t lo = first_dir_at_least(sd, ne, lane), hi = first_dir_at_least(sd, ne, lane + 1);
+        uint32_t q = lo;
+        for (; q + 8 <= hi; q += 8) {
+            float cc[8], vv[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                cc[r] = sc[q + r];
+                vv[r] = sv[q + r];
+            }
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                g = __fmaf_rn(cc[r], vv[r], g);
+                C = C + cc[r];
+            }
+        }
+        for (; q < hi; ++q) {
+            g = __fmaf_rn(sc[q], sv[q], g);
+            C = C + sc[q];
+        }
+    }
+    const float gx = rdlane(g, 0), gy = rdlane(g, 1), gz = rdlane(g, 2);
+    const float Cx = rdlane(C, 0), Cy = rdlane(C, 1), Cz = rdlane(C, 2);
+    if (lane == 0) dual_finish(a, i, gx, gy, gz, Cx, Cy, Cz);
 }
 
 struct PrimalArgs {
@@ -240,15 +281,43 @@ __global__ void __launch_bounds__(kBlk) k_primal_long(uint32_t n, const uint32_t
     float *sc = reinterpret_cast<float *>(smem);
     float *sp = sc + kPrimalStage;
     const int ln = a.level[i];
-    for (uint32_t q = threadIdx.x; q < ne; q += kBlk) {
-        const uint32_t v = a.ent[e0 + q];
-        sc[q] = cf.cp[v >> (kIdxBits + 2)][ln];
-        sp[q] = a.p[(int64_t)((v >> kIdxBits) & 3) * a.cap + (v & kIdxMask)];
+    for (uint32_t q0 = threadIdx.x; q0 < ne; q0 += kUnroll * kBlk) {
+        uint32_t v[kUnroll];
+        float pv[kUnroll];
+#pragma unroll
+        for (int r = 0; r < kUnroll; ++r) {
+            const uint32_t q = q0 + r * kBlk;
+            v[r] = q < ne ? a.ent[e0 + q] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < kUnroll; ++r) {
+            const uint32_t q = q0 + r * kBlk;
+            pv[r] = q < ne ? a.p[(int64_t)((v[r] >> kIdxBits) & 3) * a.cap + (v[r] & kIdxMask)] : 0.0f;
+        }
+#pragma unroll
+        for (int r = 0; r < kUnroll; ++r) {
+            const uint32_t q = q0 + r * kBlk;
+            if (q < ne) {
+                sc[q] = cf.cp[v[r] >> (kIdxBits + 2)][ln];
+                sp[q] = pv[r];
+            }
+        }
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
     float acc = a.ds[i];
-    for (uint32_t q = 0; q < ne; ++q) acc = __fmaf_rn(-sc[q], sp[q], acc);
+    uint32_t q = 0;
+    for (; q + 8 <= ne; q += 8) {
+        float cc[8], pp[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            cc[r] = sc[q + r];
+            pp[r] = sp[q + r];
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r) acc = __fmaf_rn(-cc[r], pp[r], acc);
+    }
+    for (; q < ne; ++q) acc = __fmaf_rn(-sc[q], sp[q], acc);
     a.ds[i] = __fmaf_rn(a.tau, acc, a.u_in[i]);
 }
 
@@ -287,35 +356,56 @@ __global__ void __launch_bounds__(kBlk) k_primal(PrimalArgs a, Coef cf) {
         t = a.tl * a.inv[i];
         wt = a.wtot[i];
     }
-    const uint64_t active = __ballot(valid);
+    // valid lanes form a prefix of the wave; the F and P loads of kAhead
+    // leaves are issued before the first of them is used, to keep enough
+    // bytes in flight per wave.
+    const int nact = __popcll(__ballot(valid));
     float myv = 0.0f;
-    for (int l = 0; l < 64; ++l) {
-        if (!((active >> l) & 1ull)) break;  // valid lanes form a prefix of the wave
-        const int Ml = rdlane_i(M, l);
-        const float upl = rdlane(up, l);
-        float v = upl;
-        if (Ml > 0) {
-            const float tl_ = rdlane(t, l), wtl = rdlane(wt, l);
-            const uint32_t ool = (uint32_t)rdlane_i((int)oo, l);
-            const int unitl = rdlane_i(unit, l);
-            float Fk = 0.0f, pk = 0.0f;
-            bool pred = false;
-            if (lane < Ml) {
-                Fk = a.F[ool + lane];
-                const float S = unitl ? (float)(2 * lane - Ml) : __fmaf_rn(2.0f, a.P[ool + lane], -wtl);
-                pk = __fmaf_rn(-tl_, S, upl);
-                pred = pk > Fk;
-            }
-            const int ks = __popcll(__ballot(pred));
-            const float pks = (ks < Ml) ? rdlane(pk, ks) : __fmaf_rn(-tl_, unitl ? (float)Ml : wtl, upl);
-            v = pks;
-            if (ks > 0) {
-                const float Fp = rdlane(Fk, ks - 1);
-                v = (pks >= Fp) ? pks : Fp;
+    for (int l0 = 0; l0 < nact; l0 += kAhead) {
+        float Fr[kAhead], Pr[kAhead];
+#pragma unroll
+        for (int g = 0; g < kAhead; ++g) {
+            const int l = l0 + g;
+            Fr[g] = 0.0f;
+            Pr[g] = 0.0f;
+            if (l < nact) {
+                const int Ml = rdlane_i(M, l);
+                const uint32_t ool = (uint32_t)rdlane_i((int)oo, l);
+                if (lane < Ml) {
+                    Fr[g] = a.F[ool + lane];
+                    if (!rdlane_i(unit, l)) Pr[g] = a.P[ool + lane];
+                }
             }
         }
-        v = v + 0.0f;
-        if (lane == l) myv = v;
+#pragma unroll
+        for (int g = 0; g < kAhead; ++g) {
+            const int l = l0 + g;
+            if (l >= nact) break;
+            const int Ml = rdlane_i(M, l);
+            const float upl = rdlane(up, l);
+            float v = upl;
+            if (Ml > 0) {
+                const float tl_ = rdlane(t, l), wtl = rdlane(wt, l);
+                const int unitl = rdlane_i(unit, l);
+                const float Fk = Fr[g];
+                float pk = 0.0f;
+                bool pred = false;
+                if (lane < Ml) {
+                    const float S = unitl ? (float)(2 * lane - Ml) : __fmaf_rn(2.0f, Pr[g], -wtl);
+                    pk = __fmaf_rn(-tl_, S, upl);
+                    pred = pk > Fk;
+                }
+                const int ks = __popcll(__ballot(pred));
+                const float pks = (ks < Ml) ? rdlane(pk, ks) : __fmaf_rn(-tl_, unitl ? (float)Ml : wtl, upl);
+                v = pks;
+                if (ks > 0) {
+                    const float Fp = rdlane(Fk, ks - 1);
+                    v = (pks >= Fp) ? pks : Fp;
+                }
+            }
+            v = v + 0.0f;
+            if (lane == l) myv = v;
+        }
     }
     bool split = false, join = false;
     if (valid) {
