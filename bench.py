@@ -29,6 +29,32 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+SWEEP_SOURCES = ("paper_1608_07411_amd/csrc/sweep.hip", "paper_1608_07411_amd/csrc/otf_internal.h")
+
+
+def traffic_ratio(kernel: str, workload: str):
+    """Hardware-to-algorithmic byte ratio of a kernel from its committed profile.
+
+    The profile records FETCH_SIZE/WRITE_SIZE (scaled by a plain copy's
+    reading) over algorithmic bytes for the same dispatches, and a hash of the
+    sweep sources; a hash that no longer matches means the kernel has changed
+    since the counters were taken, and no ratio is returned.
+    """
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path).read().splitlines():
+        if " " in line:
+            k, v = line.split(" ", 1)
+            rec[k] = v.strip()
+    src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in SWEEP_SOURCES)
+    if rec.get("source_sha256_16") != hashlib.sha256(src).hexdigest()[:16]:
+        return None
+    try:
+        return float(rec["traffic_over_algorithmic"])
+    except (KeyError, ValueError):
+        return None
 
 
 def log(*a):
@@ -229,9 +255,13 @@ def main():
         bytes_per_launch = prof["bytes"][kind] / max(n, 1)
         kern[kind] = dict(avg_ms=avg_ms, bytes=bytes_per_launch, gbs=bytes_per_launch / (avg_ms * 1e-3) / 1e9)
     dom = max(kern, key=lambda k: kern[k]["avg_ms"])
+    ratio = traffic_ratio(f"k_{dom}", f"{w.name}_depth{w.max_depth}")
     roofline = {
         "bound": "hbm", "kernel": f"k_{dom}", "achieved": kern[dom]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": kern[dom]["gbs"] / HBM_PEAK_GBS, "traffic": None,
+        "frac": kern[dom]["gbs"] / HBM_PEAK_GBS,
+        "traffic": None if ratio is None else ratio * kern[dom]["bytes"],
+        "traffic_note": ("hardware bytes per launch = profiled FETCH/WRITE-to-algorithmic ratio x this run's "
+                         "algorithmic bytes" if ratio is not None else "no profile of the current kernel source"),
         "algorithmic_bytes_per_launch": kern[dom]["bytes"], "avg_launch_ms": kern[dom]["avg_ms"],
     }
     phase_ms = {k: prof[k]["ms"] for k in ("dual", "primal", "restructure")}

@@ -370,10 +370,10 @@ otf_status otf_fuse(otf_ctx *ctx, int32_t iterations, float lambda, float tau, f
             prof_begin(c);
             launch_dual(c, sigma);
             prof_end(c, kProfDual);
-            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, c.stream, c.counters.p, 2);
             prof_begin(c);
             launch_primal(c, tau, tl);
             prof_end(c, kProfPrimal);
+            count_flags(c);
             c.leaf_updates += c.L;
             c.alg_bytes[0] += dual_bytes(c);
             c.alg_bytes[1] += primal_bytes(c);

@@ -150,8 +150,11 @@ void gather_launch(Ctx &c, int64_t n, const uint32_t *tkey, const uint8_t *tleve
 }  // namespace
 
 namespace {
+constexpr int kObsBlocks = 1024;
+
+// Per-block observation totals (all leaves, leaves with fractional weights).
 __global__ void __launch_bounds__(kBlk) k_obs_sizes(int64_t L, const uint8_t *M, const uint8_t *unit,
-                                                    unsigned long long *out) {
+                                                    uint32_t *part) {
     __shared__ uint32_t st[kBlk], sn[kBlk];
     uint32_t m = 0, nu = 0;
     for (int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x; i < L; i += (int64_t)gridDim.x * kBlk) {
@@ -170,13 +173,32 @@ __global__ void __launch_bounds__(kBlk) k_obs_sizes(int64_t L, const uint8_t *M,
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        atomicAdd(&out[0], (unsigned long long)st[0]);
-        atomicAdd(&out[1], (unsigned long long)sn[0]);
+        part[blockIdx.x] = st[0];
+        part[kObsBlocks + blockIdx.x] = sn[0];
     }
 }
 
-__global__ void k_zero_u64x2(unsigned long long *p) {
-    if (threadIdx.x < 2) p[threadIdx.x] = 0ull;
+// The two totals as u64 (one block of kObsBlocks threads).
+__global__ void __launch_bounds__(kObsBlocks) k_obs_total(const uint32_t *part, int nblocks,
+                                                          unsigned long long *out) {
+    __shared__ unsigned long long red[2][kObsBlocks / 64];
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    unsigned long long a = t < nblocks ? part[t] : 0ull, b = t < nblocks ? part[kObsBlocks + t] : 0ull;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off, 64);
+        b += __shfl_xor(b, off, 64);
+    }
+    if (lane == 0) {
+        red[0][wid] = a;
+        red[1][wid] = b;
+    }
+    __syncthreads();
+    if (t < 2) {
+        unsigned long long s = 0;
+        for (int w = 0; w < kObsBlocks / 64; ++w) s += red[t][w];
+        out[t] = s;
+    }
 }
 }  // namespace
 
@@ -184,10 +206,11 @@ __global__ void k_zero_u64x2(unsigned long long *p) {
 // left in the device counters.
 void count_obs(Ctx &c) {
     unsigned long long *d = reinterpret_cast<unsigned long long *>(c.counters.p + 4);
-    hipLaunchKernelGGL(k_zero_u64x2, dim3(1), dim3(64), 0, c.stream, d);
-    const int64_t blocks = std::min<int64_t>(1024, cdiv(c.L > 0 ? c.L : 1, kBlk));
+    const int64_t blocks = std::min<int64_t>(kObsBlocks, cdiv(c.L > 0 ? c.L : 1, kBlk));
+    c.s.part.reserve(2 * kObsBlocks);
     hipLaunchKernelGGL(k_obs_sizes, dim3((unsigned)blocks), dim3(kBlk), 0, c.stream, c.L, c.lv().obs_m.p,
-                       c.lv().obs_unit.p, d);
+                       c.lv().obs_unit.p, c.s.part.p);
+    hipLaunchKernelGGL(k_obs_total, dim3(1), dim3(kObsBlocks), 0, c.stream, c.s.part.p, (int)blocks, d);
     OTF_LAUNCH_CHECK("k_obs_sizes");
 }
 

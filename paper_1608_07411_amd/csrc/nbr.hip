@@ -118,12 +118,12 @@ __device__ inline uint32_t entry(int64_t j, int face, int lj) {
 }
 
 struct NbrOld {  // previous store, for leaves that copy their lists
-    const uint8_t *need;
-    const uint32_t *src;
+    const uint8_t *need;      // new leaf: 1 = search its lists, 0 = copy them
+    const uint32_t *src;      // new leaf -> old index (kept leaves)
     const uint32_t *off_p, *off_m, *ent_p, *ent_m;
-    const uint32_t *remap;
-    uint32_t *long_list;   // unchanged leaves with a long list, copied by a whole wave
-    uint32_t *long_count;  // device counter
+    const uint32_t *remap;    // old index -> new index of a kept leaf
+    const uint32_t *heavy_p, *heavy_m;  // old leaves with a long + / - list
+    uint32_t n_heavy_p, n_heavy_m;
 };
 
 struct Heavy {
@@ -134,49 +134,68 @@ struct Heavy {
     uint32_t cap;
 };
 
-__global__ void __launch_bounds__(kBlk) k_nbr_count(KeyIndex ki, const uint8_t *__restrict__ level, int D,
-                                                    uint32_t *cnt_p, uint32_t *cnt_m, uint32_t *fc, NbrOld old,
-                                                    Heavy hv) {
-    const int64_t L = ki.L;
-    const uint32_t *__restrict__ key = ki.key;
+// Unchanged leaves take their counts from the previous store; the others are
+// listed, in index order, at their rank dpos[i] among the leaves to search.
+__global__ void __launch_bounds__(kBlk) k_nbr_count_clean(int64_t L, uint32_t *cnt_p, uint32_t *cnt_m, NbrOld old,
+                                                          const uint32_t *dpos, uint32_t *dirty) {
     const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
     if (i >= L) return;
-    if (old.need && !old.need[i]) {
-        const uint32_t j = old.src[i];
-        const uint32_t np = old.off_p[j + 1] - old.off_p[j], nm = old.off_m[j + 1] - old.off_m[j];
-        cnt_p[i] = np;
-        cnt_m[i] = nm;
-        if (np > kLongList || nm > kLongList) old.long_list[atomicAdd(old.long_count, 1u)] = (uint32_t)i;
+    if (old.need[i]) {
+        dirty[dpos[i]] = (uint32_t)i;
         return;
     }
-    const int ln = level[i];
-    uint32_t xyz[3];
-    demorton3(key[i], xyz[0], xyz[1], xyz[2]);
-    uint32_t np = 0, nm = 0;
-    for (int face = 0; face < 6; ++face) {
-        const Face f = locate(ki, level, D, xyz, ln, face);
-        uint32_t n = 0;
-        if (f.inside) {
-            if (f.single) {
-                n = 1;
-            } else if ((uint64_t)(f.hi - f.j) <= kLight) {
-                for (int64_t m = f.j; m < f.hi; ++m) n += on_face(key[m], level[m], D, face, f.plane) ? 1u : 0u;
-            } else {
-                const uint32_t slot = atomicAdd(hv.count, 1u);
-                if (slot < hv.cap) {
-                    hv.leaf[slot] = (uint32_t)i;
-                    hv.face[slot] = (uint8_t)face;
-                    hv.lo[slot] = (uint32_t)f.j;
-                    hv.hi[slot] = (uint32_t)f.hi;
+    const uint32_t j = old.src[i];
+    cnt_p[i] = old.off_p[j + 1] - old.off_p[j];
+    cnt_m[i] = old.off_m[j + 1] - old.off_m[j];
+}
+
+// Searched leaves, 8 lanes per leaf (lane f < 6 takes face f), grid-stride
+// over the n leaves of the list (all leaves when dirty is null; n is read from
+// n_dev when given).
+__global__ void __launch_bounds__(kBlk) k_nbr_count(KeyIndex ki, const uint8_t *__restrict__ level, int D,
+                                                    uint32_t *cnt_p, uint32_t *cnt_m, uint32_t *fc,
+                                                    const uint32_t *dirty, const uint32_t *n_dev, int64_t n_host,
+                                                    Heavy hv) {
+    const uint32_t *__restrict__ key = ki.key;
+    const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
+    const int face = threadIdx.x & 7;
+    const int64_t stride = ((int64_t)gridDim.x * kBlk) >> 3;
+    for (int64_t q = ((int64_t)blockIdx.x * kBlk + threadIdx.x) >> 3; q < n; q += stride) {
+        const int64_t i = dirty ? (int64_t)dirty[q] : q;
+        uint32_t nf = 0;
+        if (face < 6) {
+            const int ln = level[i];
+            uint32_t xyz[3];
+            demorton3(key[i], xyz[0], xyz[1], xyz[2]);
+            const Face f = locate(ki, level, D, xyz, ln, face);
+            if (f.inside) {
+                if (f.single) {
+                    nf = 1;
+                } else if ((uint64_t)(f.hi - f.j) <= kLight) {
+                    for (int64_t m = f.j; m < f.hi; ++m) nf += on_face(key[m], level[m], D, face, f.plane) ? 1u : 0u;
+                } else {
+                    const uint32_t slot = atomicAdd(hv.count, 1u);  // rare: a large leaf by a fine region
+                    if (slot < hv.cap) {
+                        hv.leaf[slot] = (uint32_t)i;
+                        hv.face[slot] = (uint8_t)face;
+                        hv.lo[slot] = (uint32_t)f.j;
+                        hv.hi[slot] = (uint32_t)f.hi;
+                    }
                 }
             }
+            fc[6 * i + face] = nf;  // long ranges are counted by the chunk kernels
         }
-        fc[6 * i + face] = n;  // long ranges are counted by the chunk kernels
-        if (face < 3) np += n;
-        else nm += n;
+        uint32_t sp = face < 3 ? nf : 0u, sm = face < 3 ? 0u : nf;
+#pragma unroll
+        for (int o = 1; o < 8; o <<= 1) {
+            sp += (uint32_t)__shfl_xor((int)sp, o, 64);
+            sm += (uint32_t)__shfl_xor((int)sm, o, 64);
+        }
+        if (face == 0) {
+            cnt_p[i] = sp;
+            cnt_m[i] = sm;
+        }
     }
-    cnt_p[i] = np;
-    cnt_m[i] = nm;
 }
 
 // Long ranges are cut into chunks of kChunk leaves, one wave per chunk.
@@ -261,96 +280,125 @@ __global__ void k_chunk_totals(uint32_t n_items, Heavy hv, Chunks ch, uint32_t *
     atomicAdd(face < 3 ? &cnt_p[i] : &cnt_m[i], total);
 }
 
+// One wave copies entries [e0, e1) of an old list to dst + (e - e0), indices
+// mapped to the new positions; kCopyUnroll loads per lane in flight.
+constexpr int kCopyUnroll = 4;
+
+__device__ inline void wave_copy(const uint32_t *__restrict__ src, uint32_t e0, uint32_t e1, uint32_t *dst,
+                                 const uint32_t *__restrict__ remap, int lane) {
+    for (uint32_t base = e0; base < e1; base += 64 * kCopyUnroll) {
+        uint32_t v[kCopyUnroll], m[kCopyUnroll];
+#pragma unroll
+        for (int r = 0; r < kCopyUnroll; ++r) {
+            const uint32_t e = base + 64 * r + lane;
+            v[r] = e < e1 ? src[e] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < kCopyUnroll; ++r) {
+            const uint32_t e = base + 64 * r + lane;
+            m[r] = e < e1 ? remap[v[r] & kIdxMask] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < kCopyUnroll; ++r) {
+            const uint32_t e = base + 64 * r + lane;
+            if (e < e1) dst[e - e0] = (v[r] & ~kIdxMask) | m[r];
+        }
+    }
+}
+
+// One thread copies entries [e0, e1) like wave_copy, kCopyUnroll at a time.
+__device__ inline void thread_copy(const uint32_t *__restrict__ src, uint32_t e0, uint32_t e1, uint32_t *dst,
+                                   const uint32_t *__restrict__ remap) {
+    for (uint32_t base = e0; base < e1; base += kCopyUnroll) {
+        uint32_t v[kCopyUnroll], m[kCopyUnroll];
+#pragma unroll
+        for (int r = 0; r < kCopyUnroll; ++r) v[r] = base + r < e1 ? src[base + r] : 0u;
+#pragma unroll
+        for (int r = 0; r < kCopyUnroll; ++r) m[r] = base + r < e1 ? remap[v[r] & kIdxMask] : 0u;
+#pragma unroll
+        for (int r = 0; r < kCopyUnroll; ++r)
+            if (base + r < e1) dst[base + r - e0] = (v[r] & ~kIdxMask) | m[r];
+    }
+}
+
+// Lists of unchanged leaves: a wave of 64 unchanged leaves with consecutive
+// sources copies one contiguous block of entries; otherwise each unchanged
+// leaf copies its own short lists (long ones are copied by k_nbr_copy_long).
+__global__ void __launch_bounds__(kBlk) k_nbr_fill_clean(int64_t L, const uint32_t *__restrict__ off_p,
+                                                         const uint32_t *__restrict__ off_m, uint32_t *ent_p,
+                                                         uint32_t *ent_m, NbrOld old) {
+    const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const bool clean = i < L && !old.need[i];
+    const uint32_t j = clean ? old.src[i] : 0u;
+    const uint32_t j0 = (uint32_t)__builtin_amdgcn_readlane((int)j, 0);
+    if (__ballot(clean && j == j0 + (uint32_t)lane) == ~0ull) {
+        const uint32_t wp = (uint32_t)__builtin_amdgcn_readlane((int)off_p[i], 0);
+        const uint32_t wm = (uint32_t)__builtin_amdgcn_readlane((int)off_m[i], 0);
+        wave_copy(old.ent_p, old.off_p[j0], old.off_p[j0 + 64], ent_p + wp, old.remap, lane);
+        wave_copy(old.ent_m, old.off_m[j0], old.off_m[j0 + 64], ent_m + wm, old.remap, lane);
+        return;
+    }
+    if (!clean) return;
+    const uint32_t p0 = old.off_p[j], p1 = old.off_p[j + 1];
+    if (p1 - p0 <= kLongList) thread_copy(old.ent_p, p0, p1, ent_p + off_p[i], old.remap);
+    const uint32_t m0 = old.off_m[j], m1 = old.off_m[j + 1];
+    if (m1 - m0 <= kLongList) thread_copy(old.ent_m, m0, m1, ent_m + off_m[i], old.remap);
+}
+
+// Searched leaves, 8 lanes per leaf as in k_nbr_count: lane f writes face f's
+// short range after the leaf's earlier faces; long ranges are written by the
+// chunk fill.
 __global__ void __launch_bounds__(kBlk) k_nbr_fill(KeyIndex ki, const uint8_t *__restrict__ level, int D,
                                                    const uint32_t *__restrict__ fc, const uint32_t *__restrict__ off_p,
                                                    const uint32_t *__restrict__ off_m, uint32_t *ent_p,
-                                                   uint32_t *ent_m, NbrOld old) {
-    const int64_t L = ki.L;
+                                                   uint32_t *ent_m, const uint32_t *dirty, const uint32_t *n_dev,
+                                                   int64_t n_host) {
     const uint32_t *__restrict__ key = ki.key;
-    const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
-    const int lane = threadIdx.x & 63;
-    if (old.need) {
-        // a wave of 64 unchanged leaves with consecutive sources copies one
-        // contiguous block of entries, coalesced
-        const bool clean = i < L && !old.need[i];
-        const uint32_t j = clean ? old.src[i] : 0u;
-        const uint32_t j0 = (uint32_t)__builtin_amdgcn_readlane((int)j, 0);
-        if (__ballot(clean && j == j0 + (uint32_t)lane) == ~0ull) {
-            const uint32_t wp = (uint32_t)__builtin_amdgcn_readlane((int)off_p[i], 0);
-            const uint32_t wm = (uint32_t)__builtin_amdgcn_readlane((int)off_m[i], 0);
-            const uint32_t p0 = old.off_p[j0], p1 = old.off_p[j0 + 64];
-            const uint32_t m0 = old.off_m[j0], m1 = old.off_m[j0 + 64];
-            for (uint32_t e = p0 + lane; e < p1; e += 64) {
-                const uint32_t v = old.ent_p[e];
-                ent_p[wp + (e - p0)] = (v & ~kIdxMask) | old.remap[v & kIdxMask];
-            }
-            for (uint32_t e = m0 + lane; e < m1; e += 64) {
-                const uint32_t v = old.ent_m[e];
-                ent_m[wm + (e - m0)] = (v & ~kIdxMask) | old.remap[v & kIdxMask];
-            }
-            return;
-        }
-    }
-    if (i >= L) return;
-    if (old.need && !old.need[i]) {
-        const uint32_t j = old.src[i];
-        if (old.off_p[j + 1] - old.off_p[j] > kLongList || old.off_m[j + 1] - old.off_m[j] > kLongList) return;
-        uint32_t w = off_p[i];
-        for (uint32_t e = old.off_p[j]; e < old.off_p[j + 1]; ++e, ++w) {
-            const uint32_t v = old.ent_p[e];
-            ent_p[w] = (v & ~kIdxMask) | old.remap[v & kIdxMask];
-        }
-        w = off_m[i];
-        for (uint32_t e = old.off_m[j]; e < old.off_m[j + 1]; ++e, ++w) {
-            const uint32_t v = old.ent_m[e];
-            ent_m[w] = (v & ~kIdxMask) | old.remap[v & kIdxMask];
-        }
-        return;
-    }
-    const int ln = level[i];
-    uint32_t xyz[3];
-    demorton3(key[i], xyz[0], xyz[1], xyz[2]);
-    uint32_t wp = off_p[i], wm = off_m[i];
-    for (int face = 0; face < 6; ++face) {
-        const uint32_t n = fc[6 * i + face];
-        uint32_t &w = face < 3 ? wp : wm;
+    const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
+    const int face = threadIdx.x & 7;
+    if (face >= 6) return;
+    const int64_t stride = ((int64_t)gridDim.x * kBlk) >> 3;
+    for (int64_t q = ((int64_t)blockIdx.x * kBlk + threadIdx.x) >> 3; q < n; q += stride) {
+        const int64_t i = dirty ? (int64_t)dirty[q] : q;
+        const uint32_t nf = fc[6 * i + face];
+        if (nf == 0) continue;
+        uint32_t w = face < 3 ? off_p[i] : off_m[i];
+        for (int f = (face < 3 ? 0 : 3); f < face; ++f) w += fc[6 * i + f];
         uint32_t *ent = face < 3 ? ent_p : ent_m;
-        if (n == 0) continue;
-        const Face f = locate(ki, level, D, xyz, ln, face);
-        if (f.single) {
-            ent[w] = entry(f.j, face, level[f.j]);
-        } else if ((uint64_t)(f.hi - f.j) <= kLight) {
-            uint32_t k = w;
-            for (int64_t m = f.j; m < f.hi; ++m) {
+        const int ln = level[i];
+        uint32_t xyz[3];
+        demorton3(key[i], xyz[0], xyz[1], xyz[2]);
+        const Face fa = locate(ki, level, D, xyz, ln, face);
+        if (fa.single) {
+            ent[w] = entry(fa.j, face, level[fa.j]);
+        } else if ((uint64_t)(fa.hi - fa.j) <= kLight) {
+            for (int64_t m = fa.j; m < fa.hi; ++m) {
                 const int lm = level[m];
-                if (on_face(key[m], lm, D, face, f.plane)) ent[k++] = entry(m, face, lm);
+                if (on_face(key[m], lm, D, face, fa.plane)) ent[w++] = entry(m, face, lm);
             }
         }  // else: written by the heavy fill
-        w += n;
     }
 }
 
-// Unchanged leaves with a long list: one wave copies both lists, coalesced.
-__global__ void __launch_bounds__(kBlk) k_nbr_copy_long(uint32_t n, NbrOld old, const uint32_t *off_p,
+// Long lists of unchanged leaves, one wave per leaf of the old long-list work
+// lists (items 0..n_p-1: + lists, then - lists); an old leaf whose new
+// position holds another leaf, or a searched one, is skipped.
+__global__ void __launch_bounds__(kBlk) k_nbr_copy_long(int64_t L, NbrOld old, const uint32_t *off_p,
                                                         const uint32_t *off_m, uint32_t *ent_p, uint32_t *ent_m) {
     const uint32_t item = ((uint32_t)blockIdx.x * kBlk + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
-    if (item >= n) return;
-    const uint32_t i = old.long_list[item], j = old.src[i];
-    const uint32_t p0 = old.off_p[j], p1 = old.off_p[j + 1], wp = off_p[i];
-    for (uint32_t e = p0 + lane; e < p1; e += 64) {
-        const uint32_t v = old.ent_p[e];
-        ent_p[wp + (e - p0)] = (v & ~kIdxMask) | old.remap[v & kIdxMask];
-    }
-    const uint32_t m0 = old.off_m[j], m1 = old.off_m[j + 1], wm = off_m[i];
-    for (uint32_t e = m0 + lane; e < m1; e += 64) {
-        const uint32_t v = old.ent_m[e];
-        ent_m[wm + (e - m0)] = (v & ~kIdxMask) | old.remap[v & kIdxMask];
-    }
+    if (item >= old.n_heavy_p + old.n_heavy_m) return;
+    const bool plus = item < old.n_heavy_p;
+    const uint32_t j = plus ? old.heavy_p[item] : old.heavy_m[item - old.n_heavy_p];
+    const uint32_t i = old.remap[j];
+    if ((int64_t)i >= L || old.need[i] || old.src[i] != j) return;
+    if (plus) wave_copy(old.ent_p, old.off_p[j], old.off_p[j + 1], ent_p + off_p[i], old.remap, lane);
+    else wave_copy(old.ent_m, old.off_m[j], old.off_m[j + 1], ent_m + off_m[i], old.remap, lane);
 }
 
-__global__ void k_zero1(uint32_t *p) {
-    if (threadIdx.x == 0) *p = 0u;
+__global__ void k_zero_n(uint32_t *p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
 }
 
 // Work lists of the leaves whose + or - list is long (order irrelevant).
@@ -362,9 +410,6 @@ __global__ void __launch_bounds__(kBlk) k_heavy_lists(int64_t L, const uint32_t 
     if (off_m[i + 1] - off_m[i] > kLongList) hm[atomicAdd(&counters[1], 1u)] = (uint32_t)i;
 }
 
-__global__ void k_zero2(uint32_t *p) {
-    if (threadIdx.x < 2) p[threadIdx.x] = 0u;
-}
 
 void build(Ctx &c, const NbrOld &old) {
     LeafStore &s = c.lv();
@@ -383,18 +428,32 @@ void build(Ctx &c, const NbrOld &old) {
     const KeyIndex ki{s.key.p, L, c.s.key_table.p, shift, nb};
     uint32_t cap = (uint32_t)std::min<int64_t>(6 * L, std::max<int64_t>(4096, L / 8));
     uint32_t n_heavy = 0;
+    // leaves to search: all of them, or (after a restructure) those marked in
+    // need, listed at their rank dpos[i]; their number dpos[L] stays on the device
+    const uint32_t *dirty = nullptr, *n_dirty_dev = nullptr;
+    if (old.need) {
+        c.s.e.reserve(L + 1);
+        c.s.dirty.reserve(L);
+        scan_exclusive_u32_dev_u8(c, old.need, c.s.e.p, L);
+        hipLaunchKernelGGL(k_nbr_count_clean, dim3(g), dim3(kBlk), 0, c.stream, L, c.s.a.p, c.s.b.p, old,
+                           (const uint32_t *)c.s.e.p, c.s.dirty.p);
+        OTF_LAUNCH_CHECK("k_nbr_count_clean");
+        dirty = c.s.dirty.p;
+        n_dirty_dev = c.s.e.p + L;
+    }
+    // 8 lanes per searched leaf; a bounded grid strides over the list
+    const unsigned g8 = (unsigned)std::min<int64_t>(cdiv(8 * L, kBlk), 8192);
     for (int attempt = 0; attempt < 2; ++attempt) {
         c.s.hv_leaf.reserve(cap);
         c.s.hv_lo.reserve(cap);
         c.s.hv_hi.reserve(cap);
         c.s.hv_face.reserve(cap);
         Heavy hv{c.s.hv_leaf.p, c.s.hv_face.p, c.s.hv_lo.p, c.s.hv_hi.p, c.counters.p + 3, cap};
-        hipLaunchKernelGGL(k_zero1, dim3(1), dim3(64), 0, c.stream, c.counters.p + 3);
-        hipLaunchKernelGGL(k_zero1, dim3(1), dim3(64), 0, c.stream, c.counters.p + 9);
-        hipLaunchKernelGGL(k_nbr_count, dim3(g), dim3(kBlk), 0, c.stream, ki, s.level.p, D, c.s.a.p, c.s.b.p,
-                           c.s.g.p, old, hv);
+        hipLaunchKernelGGL(k_zero_n, dim3(1), dim3(64), 0, c.stream, c.counters.p + 3, 1);
+        hipLaunchKernelGGL(k_nbr_count, dim3(g8), dim3(kBlk), 0, c.stream, ki, s.level.p, D, c.s.a.p, c.s.b.p, c.s.g.p,
+                           dirty, n_dirty_dev, L, hv);
         OTF_LAUNCH_CHECK("k_nbr_count");
-        read_back(c, {{c.counters.p + 3, 3}, {c.counters.p + 9, 9}});
+        read_back(c, {{c.counters.p + 3, 3}});
         n_heavy = c.h_counters[3];
         if (n_heavy <= cap) break;
         cap = n_heavy;  // rare: more long ranges than room; count again with room for all
@@ -429,7 +488,7 @@ void build(Ctx &c, const NbrOld &old) {
     // work lists of the leaves with long lists need only the offsets
     s.heavy_p.reserve(L);
     s.heavy_m.reserve(L);
-    hipLaunchKernelGGL(k_zero2, dim3(1), dim3(64), 0, c.stream, c.counters.p + 14);
+    hipLaunchKernelGGL(k_zero_n, dim3(1), dim3(64), 0, c.stream, c.counters.p + 14, 2);
     hipLaunchKernelGGL(k_heavy_lists, dim3(g), dim3(kBlk), 0, c.stream, L, (const uint32_t *)s.nbp_off.p,
                        (const uint32_t *)s.nbm_off.p, s.heavy_p.p, s.heavy_m.p, c.counters.p + 14);
     OTF_LAUNCH_CHECK("k_heavy_lists");
@@ -440,15 +499,21 @@ void build(Ctx &c, const NbrOld &old) {
     s.n_heavy_m = c.h_counters[15];
     s.nbp.reserve(s.n_nbp);
     s.nbm.reserve(s.n_nbm);
-    hipLaunchKernelGGL(k_nbr_fill, dim3(g), dim3(kBlk), 0, c.stream, ki, s.level.p, D, (const uint32_t *)c.s.g.p, (const uint32_t *)s.nbp_off.p, (const uint32_t *)s.nbm_off.p,
-                       s.nbp.p, s.nbm.p, old);
-    OTF_LAUNCH_CHECK("k_nbr_fill");
-    const uint32_t n_long = old.need ? c.h_counters[9] : 0u;
-    if (n_long > 0) {
-        hipLaunchKernelGGL(k_nbr_copy_long, dim3((unsigned)cdiv((int64_t)n_long * 64, kBlk)), dim3(kBlk), 0, c.stream,
-                           n_long, old, (const uint32_t *)s.nbp_off.p, (const uint32_t *)s.nbm_off.p, s.nbp.p, s.nbm.p);
-        OTF_LAUNCH_CHECK("k_nbr_copy_long");
+    if (old.need) {
+        hipLaunchKernelGGL(k_nbr_fill_clean, dim3(g), dim3(kBlk), 0, c.stream, L, (const uint32_t *)s.nbp_off.p,
+                           (const uint32_t *)s.nbm_off.p, s.nbp.p, s.nbm.p, old);
+        OTF_LAUNCH_CHECK("k_nbr_fill_clean");
+        const int64_t n_long = (int64_t)old.n_heavy_p + old.n_heavy_m;
+        if (n_long > 0) {
+            hipLaunchKernelGGL(k_nbr_copy_long, dim3((unsigned)cdiv(n_long * 64, kBlk)), dim3(kBlk), 0, c.stream, L,
+                               old, (const uint32_t *)s.nbp_off.p, (const uint32_t *)s.nbm_off.p, s.nbp.p, s.nbm.p);
+            OTF_LAUNCH_CHECK("k_nbr_copy_long");
+        }
     }
+    hipLaunchKernelGGL(k_nbr_fill, dim3(g8), dim3(kBlk), 0, c.stream, ki, s.level.p, D, (const uint32_t *)c.s.g.p,
+                       (const uint32_t *)s.nbp_off.p, (const uint32_t *)s.nbm_off.p, s.nbp.p, s.nbm.p, dirty,
+                       n_dirty_dev, L);
+    OTF_LAUNCH_CHECK("k_nbr_fill");
     if (n_heavy > 0) {
         hipLaunchKernelGGL(k_nbr_chunk<true>, dim3((unsigned)cdiv((int64_t)n_chunks * 64, kBlk)), dim3(kBlk), 0,
                            c.stream, n_chunks, hv, ch, s.key.p, s.level.p, D, (const uint32_t *)c.s.g.p,
@@ -460,15 +525,15 @@ void build(Ctx &c, const NbrOld &old) {
 }  // namespace
 
 void build_neighbours(Ctx &c) {
-    build(c, NbrOld{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr});
+    build(c, NbrOld{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0u, 0u});
 }
 
 void build_neighbours_incremental(Ctx &c, const LeafStore &old, const uint32_t *remap) {
     const LeafStore &s = c.lv();
-    // an unchanged leaf with a long list had that list in the previous store
-    c.s.long_copy.reserve(old.n_heavy_p + old.n_heavy_m + 1);
-    build(c, NbrOld{s.need.p, s.src.p, old.nbp_off.p, old.nbm_off.p, old.nbp.p, old.nbm.p, remap, c.s.long_copy.p,
-                    c.counters.p + 9});
+    // an unchanged leaf with a long list had that list in the previous store,
+    // so it is on one of the old long-list work lists
+    build(c, NbrOld{s.need.p, s.src.p, old.nbp_off.p, old.nbm_off.p, old.nbp.p, old.nbm.p, remap, old.heavy_p.p,
+                    old.heavy_m.p, (uint32_t)old.n_heavy_p, (uint32_t)old.n_heavy_m});
 }
 
 }  // namespace otf

@@ -253,7 +253,8 @@ struct Scratch {
     DBuf<uint8_t> hv_face;
     DBuf<uint32_t> ch_base, ch_item, ch_count, ch_pos;  // chunks of the long ranges
     DBuf<uint32_t> key_table;                           // bucket index over leaf keys
-    DBuf<uint32_t> long_copy;                           // unchanged leaves with long adjacency lists
+    DBuf<uint32_t> dirty;                               // leaves whose adjacency is searched again
+    DBuf<uint32_t> part;                                // per-block partial counts
     // restructure temporaries (grow-only: an allocation or free per iteration
     // would synchronise the device)
     DBuf<uint8_t> r_sf, r_tM, r_tU, r_isnew, r_Mt;
@@ -336,6 +337,9 @@ uint32_t scan_exclusive_u32(Ctx &c, const uint32_t *in, uint32_t *out, int64_t n
 void scan_exclusive_u32_dev(Ctx &c, const uint32_t *in, uint32_t *out, int64_t n);
 void scan_exclusive_u32_dev_u8(Ctx &c, const uint8_t *in, uint32_t *out, int64_t n);
 void scan_inclusive_max_u32(Ctx &c, const uint32_t *in, uint32_t *out, int64_t n);
+// dst[j] = sum over b < nblocks of part[j * stride + b] for j < k (per-block
+// partial counts written by a kernel; a fixed order, no atomics)
+void sum_parts(Ctx &c, const uint32_t *part, int64_t nblocks, int k, int64_t stride, uint32_t *dst);
 
 // build: per-view trees, union structure, initial leaves (keys/levels only)
 void build_views_and_union(Ctx &c, const float *depth_dev, const std::vector<CamDev> &cams);
@@ -365,6 +369,8 @@ void build_neighbours_incremental(Ctx &c, const LeafStore &old, const uint32_t *
 // sweeps
 void launch_dual(Ctx &c, float sigma);
 void launch_primal(Ctx &c, float tau, float tl);
+// split and join flag counts of the last primal sweep into counters[0], [1]
+void count_flags(Ctx &c);
 void energy(Ctx &c, double *tv, double *data);
 // split / join; returns true when the structure changed
 bool restructure(Ctx &c, float tl);

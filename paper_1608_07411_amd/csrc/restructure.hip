@@ -23,10 +23,6 @@ constexpr int kBlk = 256;
 unsigned grid(int64_t n) { return (unsigned)cdiv(n > 0 ? n : 1, kBlk); }
 #define TID() ((int64_t)blockIdx.x * kBlk + threadIdx.x)
 
-__global__ void k_zero_counter2(uint32_t *counters) {
-    if (threadIdx.x == 0) counters[2] = 0u;
-}
-
 __global__ void k_split_bits(int64_t L, const uint8_t *flag, uint8_t *out) {
     const int64_t i = TID();
     if (i < L) out[i] = flag[i] & 1;
@@ -49,13 +45,13 @@ __global__ void k_run_ends(int64_t L, const uint8_t *flag, const uint32_t *rs, u
     if (i == L - 1 || (flag[i + 1] & 6) != j) runend[rs[i]] = (uint32_t)i;
 }
 
-__global__ void k_join_target(int64_t L, int D, const uint8_t *flag, const uint32_t *key, const uint8_t *level,
-                              const uint32_t *rs, const uint32_t *runend, uint8_t *jt, uint8_t *jhead,
-                              uint32_t *counters) {
+__global__ void __launch_bounds__(kBlk) k_join_target(int64_t L, int D, const uint8_t *flag, const uint32_t *key,
+                                                      const uint8_t *level, const uint32_t *rs,
+                                                      const uint32_t *runend, uint8_t *jt, uint8_t *jhead,
+                                                      uint32_t *part) {
     const int64_t i = TID();
-    if (i >= L) return;
     uint8_t t = 0xFF, h = 0;
-    if (flag[i] & 6) {
+    if (i < L && (flag[i] & 6)) {
         const uint32_t s = rs[i], e = runend[s];
         const uint64_t K0 = key[s];
         const uint64_t K1 = (uint64_t)key[e] + (uint64_t(1) << (3 * (D - level[e])));
@@ -71,9 +67,20 @@ __global__ void k_join_target(int64_t L, int D, const uint8_t *flag, const uint3
             }
         }
     }
-    jt[i] = t;
-    jhead[i] = h;
-    if (h) atomicAdd(&counters[2], 1u);
+    if (i < L) {
+        jt[i] = t;
+        jhead[i] = h;
+    }
+    // per-block count of collapse heads
+    __shared__ uint32_t cnt[kBlk / 64];
+    const uint64_t b = __ballot(h != 0);
+    if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = (uint32_t)__popcll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t n = 0;
+        for (int w = 0; w < kBlk / 64; ++w) n += cnt[w];
+        part[blockIdx.x] = n;
+    }
 }
 
 struct NewStore {
@@ -275,18 +282,33 @@ __device__ inline bool changed(int64_t j, const uint8_t *flag, const uint8_t *jt
 
 // Marked from the changed side (adjacency is symmetric): every kept neighbour
 // of a changed leaf. Concurrent stores all write 1.
-__global__ void k_nbr_mark(int64_t L, const uint8_t *flag, const uint8_t *jt, int splits, const uint32_t *off_p,
-                           const uint32_t *ent_p, const uint32_t *off_m, const uint32_t *ent_m,
-                           const uint32_t *out_off, uint8_t *need) {
+// Marks the kept neighbours of changed leaves; kMarkBatch entries of a list
+// are in flight at a time (the lookups form a chain of dependent loads).
+constexpr int kMarkBatch = 8;
+
+__global__ void __launch_bounds__(kBlk) k_nbr_mark(int64_t L, const uint8_t *flag, const uint8_t *jt, int splits,
+                                                   const uint32_t *off_p, const uint32_t *ent_p,
+                                                   const uint32_t *off_m, const uint32_t *ent_m,
+                                                   const uint32_t *out_off, uint8_t *need) {
     const int64_t i = TID();
     if (i >= L || !changed(i, flag, jt, splits)) return;
-    for (uint32_t e = off_p[i]; e < off_p[i + 1]; ++e) {
-        const uint32_t k = ent_p[e] & kIdxMask;
-        if (!changed(k, flag, jt, splits)) need[out_off[k]] = 1;
-    }
-    for (uint32_t e = off_m[i]; e < off_m[i + 1]; ++e) {
-        const uint32_t k = ent_m[e] & kIdxMask;
-        if (!changed(k, flag, jt, splits)) need[out_off[k]] = 1;
+    for (int side = 0; side < 2; ++side) {
+        const uint32_t *off = side ? off_m : off_p;
+        const uint32_t *ent = side ? ent_m : ent_p;
+        const uint32_t e1 = off[i + 1];
+        for (uint32_t e = off[i]; e < e1; e += kMarkBatch) {
+            uint32_t n[kMarkBatch], o[kMarkBatch];
+            bool keep[kMarkBatch];
+#pragma unroll
+            for (int r = 0; r < kMarkBatch; ++r) n[r] = e + r < e1 ? ent[e + r] & kIdxMask : 0u;
+#pragma unroll
+            for (int r = 0; r < kMarkBatch; ++r) keep[r] = e + r < e1 && !changed(n[r], flag, jt, splits);
+#pragma unroll
+            for (int r = 0; r < kMarkBatch; ++r) o[r] = keep[r] ? out_off[n[r]] : 0u;
+#pragma unroll
+            for (int r = 0; r < kMarkBatch; ++r)
+                if (keep[r]) need[o[r]] = 1;
+        }
     }
 }
 
@@ -398,9 +420,10 @@ bool restructure(Ctx &c, float tl) {
         hipLaunchKernelGGL(k_run_heads, dim3(gL), dim3(kBlk), 0, c.stream, L, os.flag.p, s.a.p);
         scan_inclusive_max_u32(c, s.a.p, s.b.p, L);
         hipLaunchKernelGGL(k_run_ends, dim3(gL), dim3(kBlk), 0, c.stream, L, os.flag.p, s.b.p, s.c.p);
-        hipLaunchKernelGGL(k_zero_counter2, dim3(1), dim3(64), 0, c.stream, c.counters.p);
+        s.part.reserve(gL);
         hipLaunchKernelGGL(k_join_target, dim3(gL), dim3(kBlk), 0, c.stream, L, D, os.flag.p, os.key.p, os.level.p,
-                           s.b.p, s.c.p, s.u8a.p, s.u8b.p, c.counters.p);
+                           s.b.p, s.c.p, s.u8a.p, s.u8b.p, s.part.p);
+        sum_parts(c, s.part.p, gL, 1, gL, c.counters.p + 2);
         OTF_LAUNCH_CHECK("join analysis");
         jt = s.u8a.p;
         jhead = s.u8b.p;

@@ -220,6 +220,35 @@ void scan_any(Ctx &c, const In *in, uint32_t *out, int64_t n, Op op, bool exclus
     OTF_LAUNCH_CHECK("k_scan");
 }
 
+// dst[j] = sum over b < nblocks of part[j * stride + b], j < k: one block,
+// a fixed reduction order (no atomics; many same-address atomics from the
+// blocks of a large grid serialise).
+__global__ void __launch_bounds__(1024) k_sum_parts(const uint32_t *part, int64_t nblocks, int k, int64_t stride,
+                                                    uint32_t *dst) {
+    __shared__ uint32_t red[16];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int j = 0; j < k; ++j) {
+        uint32_t acc = 0;
+        for (int64_t b0 = threadIdx.x; b0 < nblocks; b0 += 8 * 1024) {
+            uint32_t x[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) x[r] = b0 + r * 1024 < nblocks ? part[j * stride + b0 + r * 1024] : 0u;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) acc += x[r];
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc += (uint32_t)__shfl_xor((int)acc, off, 64);
+        if (lane == 0) red[wid] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t t = 0;
+            for (int w = 0; w < 16; ++w) t += red[w];
+            dst[j] = t;
+        }
+        __syncthreads();
+    }
+}
+
 struct ReadArgs {
     const uint32_t *src[kReadMax + 1];
     int slot[kReadMax + 1];
@@ -274,6 +303,11 @@ void scan_exclusive_u32_dev(Ctx &c, const uint32_t *in, uint32_t *out, int64_t n
 
 void scan_exclusive_u32_dev_u8(Ctx &c, const uint8_t *in, uint32_t *out, int64_t n) {
     scan_any(c, in, out, n, AddOp{}, true, out + n);
+}
+
+void sum_parts(Ctx &c, const uint32_t *part, int64_t nblocks, int k, int64_t stride, uint32_t *dst) {
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(1024), 0, c.stream, part, nblocks, k, stride, dst);
+    OTF_LAUNCH_CHECK("k_sum_parts");
 }
 
 void scan_inclusive_max_u32(Ctx &c, const uint32_t *in, uint32_t *out, int64_t n) {

@@ -21,6 +21,7 @@ namespace {
 constexpr int kBlk = 256;
 constexpr int kAhead = 4;   // leaves whose observations one wave loads ahead in k_primal
 constexpr int kUnroll = 4;  // list entries per thread in flight while staging a long list
+constexpr int kGather = 4;  // neighbour entries per thread in flight in the short-list sweeps
 
 __device__ inline float rdlane(float v, int l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
@@ -67,22 +68,30 @@ __global__ void __launch_bounds__(kBlk) k_dual(DualArgs a, Coef cf) {
     const int ln = a.level[i];
     const float ub = a.ubar[i];
     float gx = 0.0f, gy = 0.0f, gz = 0.0f, Cx = 0.0f, Cy = 0.0f, Cz = 0.0f;
-    for (uint32_t e = e0; e < e1; ++e) {
-        const uint32_t v = a.ent[e];
-        const uint32_t k = v & kIdxMask;
-        const int d = (v >> kIdxBits) & 3;
-        const int lk = v >> (kIdxBits + 2);
-        const float c = cf.c[ln][lk];
-        const float diff = a.ubar[k] - ub;
-        if (d == 0) {
-            gx = __fmaf_rn(c, diff, gx);
-            Cx = Cx + c;
-        } else if (d == 1) {
-            gy = __fmaf_rn(c, diff, gy);
-            Cy = Cy + c;
-        } else {
-            gz = __fmaf_rn(c, diff, gz);
-            Cz = Cz + c;
+    // kGather entries at a time: their loads are issued before the first is used
+    for (uint32_t e = e0; e < e1; e += kGather) {
+        uint32_t v[kGather];
+        float ubk[kGather];
+#pragma unroll
+        for (int r = 0; r < kGather; ++r) v[r] = e + r < e1 ? a.ent[e + r] : 0u;
+#pragma unroll
+        for (int r = 0; r < kGather; ++r) ubk[r] = e + r < e1 ? a.ubar[v[r] & kIdxMask] : 0.0f;
+#pragma unroll
+        for (int r = 0; r < kGather; ++r) {
+            if (e + r >= e1) break;
+            const int d = (v[r] >> kIdxBits) & 3;
+            const float c = cf.c[ln][v[r] >> (kIdxBits + 2)];
+            const float diff = ubk[r] - ub;
+            if (d == 0) {
+                gx = __fmaf_rn(c, diff, gx);
+                Cx = Cx + c;
+            } else if (d == 1) {
+                gy = __fmaf_rn(c, diff, gy);
+                Cy = Cy + c;
+            } else {
+                gz = __fmaf_rn(c, diff, gz);
+                Cz = Cz + c;
+            }
         }
     }
     dual_finish(a, i, gx, gy, gz, Cx, Cy, Cz);
@@ -236,7 +245,8 @@ struct PrimalArgs {
     float *u, *ubar;
     uint8_t *flag;
     float *uprime, *uold;
-    uint32_t *counters;  // [0] split flags, [1] join flags
+    uint32_t *part;  // per-block counts of split flags [0, stride) and join flags [stride, 2 stride)
+    int64_t part_stride;
     float tau, tl, split_tau, join_tau;
     int join_enabled, max_depth;
 };
@@ -341,12 +351,19 @@ __global__ void __launch_bounds__(kBlk) k_primal(PrimalArgs a, Coef cf) {
             up = a.ds[i];
         } else {
             float acc = a.ds[i];
-            for (uint32_t e = e0; e < e1; ++e) {
-                const uint32_t v = a.ent[e];
-                const uint32_t m = v & kIdxMask;
-                const int d = (v >> kIdxBits) & 3;
-                const int lm = v >> (kIdxBits + 2);
-                acc = __fmaf_rn(-cf.cp[lm][ln], a.p[(int64_t)d * a.cap + m], acc);
+            for (uint32_t e = e0; e < e1; e += kGather) {
+                uint32_t v[kGather];
+                float pm[kGather];
+#pragma unroll
+                for (int r = 0; r < kGather; ++r) v[r] = e + r < e1 ? a.ent[e + r] : 0u;
+#pragma unroll
+                for (int r = 0; r < kGather; ++r)
+                    pm[r] = e + r < e1 ? a.p[(int64_t)((v[r] >> kIdxBits) & 3) * a.cap + (v[r] & kIdxMask)] : 0.0f;
+#pragma unroll
+                for (int r = 0; r < kGather; ++r) {
+                    if (e + r >= e1) break;
+                    acc = __fmaf_rn(-cf.cp[v[r] >> (kIdxBits + 2)][ln], pm[r], acc);
+                }
             }
             up = __fmaf_rn(a.tau, acc, un);
         }
@@ -420,10 +437,18 @@ __global__ void __launch_bounds__(kBlk) k_primal(PrimalArgs a, Coef cf) {
             a.uold[i] = un;
         }
     }
+    // per-block flag counts, summed by sum_parts
+    __shared__ uint32_t cnt[2][kBlk / 64];
     const uint64_t bs = __ballot(split), bj = __ballot(join);
     if (lane == 0) {
-        if (bs) atomicAdd(&a.counters[0], (uint32_t)__popcll(bs));
-        if (bj) atomicAdd(&a.counters[1], (uint32_t)__popcll(bj));
+        cnt[0][threadIdx.x >> 6] = (uint32_t)__popcll(bs);
+        cnt[1][threadIdx.x >> 6] = (uint32_t)__popcll(bj);
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        uint32_t t = 0;
+        for (int w = 0; w < kBlk / 64; ++w) t += cnt[threadIdx.x][w];
+        a.part[threadIdx.x * a.part_stride + blockIdx.x] = t;
     }
 }
 
@@ -510,7 +535,10 @@ void launch_primal(Ctx &c, float tau, float tl) {
     a.flag = s.flag.p;
     a.uprime = s.uprime.p;
     a.uold = s.uold.p;
-    a.counters = c.counters.p;
+    const int64_t nblk = cdiv(c.L, kBlk);
+    c.s.part.reserve(2 * nblk);
+    a.part = c.s.part.p;
+    a.part_stride = nblk;
     a.tau = tau;
     a.tl = tl;
     a.split_tau = c.prm.split_tau;
@@ -522,8 +550,13 @@ void launch_primal(Ctx &c, float tau, float tl) {
                            (uint32_t)s.n_heavy_m, s.heavy_m.p, a, c.coef);
         OTF_LAUNCH_CHECK("k_primal_long");
     }
-    hipLaunchKernelGGL(k_primal, dim3((unsigned)cdiv(c.L, kBlk)), dim3(kBlk), 0, c.stream, a, c.coef);
+    hipLaunchKernelGGL(k_primal, dim3((unsigned)nblk), dim3(kBlk), 0, c.stream, a, c.coef);
     OTF_LAUNCH_CHECK("k_primal");
+}
+
+void count_flags(Ctx &c) {
+    const int64_t nblk = cdiv(c.L, kBlk);
+    sum_parts(c, c.s.part.p, nblk, 2, nblk, c.counters.p);  // counters[0] split flags, [1] join flags
 }
 
 void energy(Ctx &c, double *tv, double *data) {
