@@ -19,7 +19,7 @@ namespace otf {
 namespace {
 
 constexpr int kBlk = 256;
-constexpr int kAhead = 4;   // leaves whose observations one wave loads ahead in k_primal
+constexpr int kAhead = 8;   // leaves whose observations one wave loads ahead in k_primal
 constexpr int kUnroll = 4;  // list entries per thread in flight while staging a long list
 constexpr int kGather = 4;  // neighbour entries per thread in flight in the short-list sweeps
 
