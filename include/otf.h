@@ -168,6 +168,58 @@ otf_status otf_profile_read(otf_ctx *ctx, double *ms, int64_t *launches, int64_t
  * next call on the context. */
 const char *otf_last_error(const otf_ctx *ctx);
 
+/* ---------------------------------------------------------------------------
+ * Batches: the primal-dual iterations (Sec. 3.2, Eq. 5; the primal-dual
+ * scheme of Chambolle and Pock that Sec. 5 names) of many fused octrees in
+ * the same kernel launches, for callers that fuse many objects at once
+ * (octrees of different depths and view counts).
+ *
+ * A batch borrows its member contexts: each keeps its own octree,
+ * observations and split/join parameters, and a batch iteration performs one
+ * iteration of every member, with results bit-identical to otf_fuse on each
+ * member alone. Members must have been created with the batch's device and
+ * stream and hold a built or imported octree; the caller keeps them alive,
+ * does not call otf_fuse, otf_build_octree or otf_import_state on them while
+ * they are members, and destroys the batch before them. Inspection calls
+ * (otf_extract, otf_energy, ...) on members are allowed between batch calls.
+ *
+ * The first iterations of a batch double as an autotuner: each runs the
+ * sweeps with another launch shape (threads per block and persistent grid
+ * size) and the fastest per leaf is kept (otf_batch_config). When no member
+ * restructures (restructure_every == 0), whole chunks of 16 iterations are
+ * captured once in a HIP graph and replayed.
+ * ------------------------------------------------------------------------- */
+typedef struct otf_batch otf_batch;
+
+/* Create an empty batch on `device` and `hip_stream` (borrowed; may be null,
+ * the default stream). Errors: OTF_E_INVALID (bad device or null out). */
+otf_status otf_batch_create(int device, void *hip_stream, otf_batch **out);
+
+/* Destroy the batch (not its members). */
+otf_status otf_batch_destroy(otf_batch *batch);
+
+/* Add a member. Errors: OTF_E_INVALID (another device or stream, or already a
+ * member), OTF_E_STATE (no octree in the context). */
+otf_status otf_batch_add(otf_batch *batch, otf_ctx *ctx);
+
+/* `iterations` primal-dual iterations of every member, arguments as
+ * otf_fuse. An empty batch or zero iterations does nothing. Errors:
+ * OTF_E_INVALID (arguments; nothing ran), OTF_E_STATE (a member has no valid
+ * state), OTF_E_CAPACITY / OTF_E_NOMEM / OTF_E_DEVICE (a member's split/join
+ * or the device failed; every member's state is then unspecified, as after a
+ * failed otf_fuse). */
+otf_status otf_batch_fuse(otf_batch *batch, int32_t iterations, float lambda, float tau, float sigma);
+
+/* The sweep launch shape in use: threads per block (leaves per tile), grid
+ * blocks (0: one per tile), whether the autotuner has finished, and how many
+ * iterations of the last otf_batch_fuse were graph replays. Any output may be
+ * null. */
+otf_status otf_batch_config(const otf_batch *batch, int32_t *block, int32_t *grid, int32_t *tuned,
+                            int32_t *graph_iterations);
+
+/* Message of the batch's last failed call. */
+const char *otf_batch_last_error(const otf_batch *batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -5,10 +5,6 @@
 
 #include "otf_internal.h"
 
-struct otf_ctx {
-    otf::Ctx c;
-};
-
 namespace otf {
 
 void fail(otf_status st, const std::string &msg) { throw Failure{st, msg}; }

@@ -381,4 +381,39 @@ void prof_end(Ctx &c, ProfKind k);
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+
+// ---------------------------------------------------------------------------
+// batches: the sweeps of many contexts in the same launches
+// ---------------------------------------------------------------------------
+struct BatchConfig {
+    int blk = 256;  // threads per block = leaves per tile (64, 128, 256 or 512)
+    int grid = 0;   // blocks of the sweeps (they stride over the tiles); 0: one per tile
+};
+struct BatchState {
+    std::vector<Ctx *> objs;
+    BatchConfig cfg;
+    uint32_t ntiles = 0, n_hp = 0, n_hm = 0;  // tiles; long + and - lists over all objects
+    DBuf<unsigned char> table;                 // per-object sweep arguments
+    DBuf<uint32_t> tile_begin, hp_begin, hm_begin, part;
+    DBuf<Coef> coefs;                          // coupling tables by max depth
+    unsigned char *h_stage = nullptr;          // pinned staging for the table uploads
+    size_t h_cap = 0;
+    hipEvent_t staged = nullptr;               // completion of the last upload
+    BatchState() = default;
+    BatchState(const BatchState &) = delete;
+    BatchState &operator=(const BatchState &) = delete;
+    ~BatchState();
+};
+// (Re)build the device table from the objects' current stores for cfg.blk.
+void batch_upload(hipStream_t st, BatchState &b, float sigma, float tau, float tl);
+// One iteration's sweeps of every object: dual, long dual, long primal,
+// primal, then per object its flag counts and observation totals.
+void batch_sweeps(hipStream_t st, BatchState &b);
+double dual_bytes(const Ctx &c);
+double primal_bytes(const Ctx &c);
+
 }  // namespace otf
+
+struct otf_ctx {
+    otf::Ctx c;
+};

@@ -59,10 +59,9 @@ __device__ inline void dual_finish(const DualArgs &a, int64_t i, float gx, float
     a.ds[i] = __fmaf_rn(Cz, qz, __fmaf_rn(Cy, qy, __fmaf_rn(Cx, qx, 0.0f)));
 }
 
-// One thread per leaf; leaves with a long + list are left to k_dual_long.
-__global__ void __launch_bounds__(kBlk) k_dual(DualArgs a, Coef cf) {
-    const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
-    if (i >= a.L) return;
+// Dual update of leaf i (one thread); a leaf with a long + list is left to
+// dual_long_block.
+__device__ inline void dual_leaf(const DualArgs &a, const Coef &cf, int64_t i) {
     const uint32_t e0 = a.off[i], e1 = a.off[i + 1];
     if (e1 - e0 > kLongList) return;
     const int ln = a.level[i];
@@ -95,6 +94,12 @@ __global__ void __launch_bounds__(kBlk) k_dual(DualArgs a, Coef cf) {
         }
     }
     dual_finish(a, i, gx, gy, gz, Cx, Cy, Cz);
+}
+
+// One thread per leaf.
+__global__ void __launch_bounds__(kBlk) k_dual(DualArgs a, Coef cf) {
+    const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
+    if (i < a.L) dual_leaf(a, cf, i);
 }
 
 // Leaves with a long + list, one 256-thread block each: the block stages the
@@ -163,10 +168,8 @@ __device__ inline uint32_t first_dir_at_least(const uint8_t *sd, uint32_t n, int
     return lo;
 }
 
-__global__ void __launch_bounds__(kBlk) k_dual_long(uint32_t n, const uint32_t *list, DualArgs a, Coef cf) {
-    extern __shared__ unsigned char smem[];
-    if (blockIdx.x >= n) return;
-    const int64_t i = list[blockIdx.x];
+// The whole 256-thread block works on leaf i; smem holds kStageBytes.
+__device__ void dual_long_block(const DualArgs &a, const Coef &cf, int64_t i, unsigned char *smem) {
     const uint32_t e0 = a.off[i], e1 = a.off[i + 1], ne = e1 - e0;
     if (ne > kDualStage) {
         if (threadIdx.x < 64) dual_long_chunked(a, cf, i, threadIdx.x);
@@ -230,6 +233,11 @@ __global__ void __launch_bounds__(kBlk) k_dual_long(uint32_t n, const uint32_t *
     if (lane == 0) dual_finish(a, i, gx, gy, gz, Cx, Cy, Cz);
 }
 
+__global__ void __launch_bounds__(kBlk) k_dual_long(uint32_t n, const uint32_t *list, DualArgs a, Coef cf) {
+    extern __shared__ unsigned char smem[];
+    if (blockIdx.x < n) dual_long_block(a, cf, list[blockIdx.x], smem);
+}
+
 struct PrimalArgs {
     int64_t L, cap;
     const uint8_t *level;
@@ -279,10 +287,7 @@ __device__ void primal_long_chunked(const PrimalArgs &a, const Coef &cf, int64_t
     if (lane == 0) a.ds[i] = __fmaf_rn(a.tau, acc, a.u_in[i]);
 }
 
-__global__ void __launch_bounds__(kBlk) k_primal_long(uint32_t n, const uint32_t *list, PrimalArgs a, Coef cf) {
-    extern __shared__ unsigned char smem[];
-    if (blockIdx.x >= n) return;
-    const int64_t i = list[blockIdx.x];
+__device__ void primal_long_block(const PrimalArgs &a, const Coef &cf, int64_t i, unsigned char *smem) {
     const uint32_t e0 = a.off[i], e1 = a.off[i + 1], ne = e1 - e0;
     if (ne > kPrimalStage) {
         if (threadIdx.x < 64) primal_long_chunked(a, cf, i, threadIdx.x);
@@ -331,13 +336,21 @@ __global__ void __launch_bounds__(kBlk) k_primal_long(uint32_t n, const uint32_t
     a.ds[i] = __fmaf_rn(a.tau, acc, a.u_in[i]);
 }
 
+__global__ void __launch_bounds__(kBlk) k_primal_long(uint32_t n, const uint32_t *list, PrimalArgs a, Coef cf) {
+    extern __shared__ unsigned char smem[];
+    if (blockIdx.x < n) primal_long_block(a, cf, list[blockIdx.x], smem);
+}
+
 // Divergence per thread, then the prox cooperatively: the wave takes its 64
 // leaves one after another; lane k tests breakpoint k of the current leaf
 // (p_k = u' - t S_k against F_(k+1), coalesced loads of F and P), a ballot
 // counts the true predicates (a prefix: p_k falls, F rises), which is the
 // index k* of the sequential search; max(p_k*, F_(k*)) is the median.
-__global__ void __launch_bounds__(kBlk) k_primal(PrimalArgs a, Coef cf) {
-    const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
+// The wave's 64 consecutive leaves (this lane: leaf i, valid if i < L; valid
+// lanes form a prefix of the wave). Returns the wave's split and join flag
+// counts (the same on every lane).
+__device__ inline void primal_wave(const PrimalArgs &a, const Coef &cf, int64_t i, uint32_t &n_split,
+                                   uint32_t &n_join) {
     const int lane = threadIdx.x & 63;
     const bool valid = i < a.L;
     float up = 0.0f, un = 0.0f, t = 0.0f, wt = 0.0f;
@@ -437,19 +450,32 @@ __global__ void __launch_bounds__(kBlk) k_primal(PrimalArgs a, Coef cf) {
             a.uold[i] = un;
         }
     }
-    // per-block flag counts, summed by sum_parts
-    __shared__ uint32_t cnt[2][kBlk / 64];
-    const uint64_t bs = __ballot(split), bj = __ballot(join);
-    if (lane == 0) {
-        cnt[0][threadIdx.x >> 6] = (uint32_t)__popcll(bs);
-        cnt[1][threadIdx.x >> 6] = (uint32_t)__popcll(bj);
+    n_split = (uint32_t)__popcll(__ballot(split));
+    n_join = (uint32_t)__popcll(__ballot(join));
+}
+
+// Per-block flag counts: part[blk] (split) and part[stride + blk] (join).
+template <int BLK>
+__device__ inline void block_flag_counts(uint32_t n_split, uint32_t n_join, uint32_t *part, int64_t stride,
+                                         int64_t blk) {
+    __shared__ uint32_t cnt[2][BLK / 64];
+    if ((threadIdx.x & 63) == 0) {
+        cnt[0][threadIdx.x >> 6] = n_split;
+        cnt[1][threadIdx.x >> 6] = n_join;
     }
     __syncthreads();
     if (threadIdx.x < 2) {
         uint32_t t = 0;
-        for (int w = 0; w < kBlk / 64; ++w) t += cnt[threadIdx.x][w];
-        a.part[threadIdx.x * a.part_stride + blockIdx.x] = t;
+        for (int w = 0; w < BLK / 64; ++w) t += cnt[threadIdx.x][w];
+        part[threadIdx.x * stride + blk] = t;
     }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(kBlk) k_primal(PrimalArgs a, Coef cf) {
+    uint32_t ns, nj;
+    primal_wave(a, cf, (int64_t)blockIdx.x * kBlk + threadIdx.x, ns, nj);
+    block_flag_counts<kBlk>(ns, nj, a.part, a.part_stride, blockIdx.x);
 }
 
 // Energy: per-leaf terms in double, block partial sums in a fixed tree order.
@@ -496,6 +522,171 @@ __global__ void __launch_bounds__(kBlk) k_energy(int64_t L, int D, const uint8_t
         partial[2 * blockIdx.x] = s_tv[0];
         partial[2 * blockIdx.x + 1] = s_da[0];
     }
+}
+
+// ---------------------------------------------------------------- batches
+// Many octrees swept by the same launches. Each object keeps its own store;
+// a device table holds its sweep arguments. Tiles of BLK leaves never
+// straddle two objects: tile t belongs to the object j with
+// tile_begin[j] <= t < tile_begin[j+1] and covers its leaves from
+// (t - tile_begin[j]) * BLK. Blocks stride over the tiles.
+struct ObjDev {
+    DualArgs d;
+    PrimalArgs p;
+    const uint32_t *heavy_p, *heavy_m;
+    uint32_t *counters;
+    int D;  // max depth: index of the coefficient table
+};
+
+// largest j < nobj with begin[j] <= t (begin[0] = 0)
+__device__ inline int find_obj(const uint32_t *begin, int nobj, uint32_t t) {
+    int lo = 0, hi = nobj;
+    while (hi - lo > 1) {
+        const int m = (lo + hi) >> 1;
+        if (begin[m] <= t) lo = m;
+        else hi = m;
+    }
+    return lo;
+}
+
+template <int BLK>
+__global__ void __launch_bounds__(BLK) k_dual_b(const ObjDev *objs, int nobj, const uint32_t *tile_begin,
+                                                uint32_t ntiles, const Coef *coefs) {
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int j = find_obj(tile_begin, nobj, t);
+        const DualArgs a = objs[j].d;
+        const int64_t i = (int64_t)(t - tile_begin[j]) * BLK + threadIdx.x;
+        if (i < a.L) dual_leaf(a, coefs[objs[j].D], i);
+    }
+}
+
+template <int BLK>
+__global__ void __launch_bounds__(BLK) k_primal_b(const ObjDev *objs, int nobj, const uint32_t *tile_begin,
+                                                  uint32_t ntiles, const Coef *coefs, uint32_t *part) {
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int j = find_obj(tile_begin, nobj, t);
+        const PrimalArgs a = objs[j].p;
+        uint32_t ns, nj;
+        primal_wave(a, coefs[objs[j].D], (int64_t)(t - tile_begin[j]) * BLK + threadIdx.x, ns, nj);
+        block_flag_counts<BLK>(ns, nj, part, ntiles, t);
+    }
+}
+
+// Long lists of all objects: block b is item b - begin[j] of object j's list.
+__global__ void __launch_bounds__(kBlk) k_dual_long_b(const ObjDev *objs, int nobj, const uint32_t *begin,
+                                                      const Coef *coefs) {
+    extern __shared__ unsigned char smem[];
+    const int j = find_obj(begin, nobj, blockIdx.x);
+    dual_long_block(objs[j].d, coefs[objs[j].D], objs[j].heavy_p[blockIdx.x - begin[j]], smem);
+}
+
+__global__ void __launch_bounds__(kBlk) k_primal_long_b(const ObjDev *objs, int nobj, const uint32_t *begin,
+                                                        const Coef *coefs) {
+    extern __shared__ unsigned char smem[];
+    const int j = find_obj(begin, nobj, blockIdx.x);
+    primal_long_block(objs[j].p, coefs[objs[j].D], objs[j].heavy_m[blockIdx.x - begin[j]], smem);
+}
+
+// Object j's split and join flag counts from its tiles' partials (block j),
+// then the observation totals accumulated as by one iteration of a single
+// context.
+__global__ void __launch_bounds__(kBlk) k_batch_counts(const ObjDev *objs, const uint32_t *tile_begin,
+                                                       uint32_t ntiles, const uint32_t *part) {
+    __shared__ uint32_t red[2][kBlk / 64];
+    const int j = blockIdx.x;
+    const uint32_t t0 = tile_begin[j], t1 = tile_begin[j + 1];
+    uint32_t s0 = 0, s1 = 0;
+    for (uint32_t t = t0 + threadIdx.x; t < t1; t += kBlk) {
+        s0 += part[t];
+        s1 += part[ntiles + t];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        s0 += (uint32_t)__shfl_xor((int)s0, off, 64);
+        s1 += (uint32_t)__shfl_xor((int)s1, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = s0;
+        red[1][threadIdx.x >> 6] = s1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t a = 0, b = 0;
+        for (int w = 0; w < kBlk / 64; ++w) {
+            a += red[0][w];
+            b += red[1][w];
+        }
+        uint32_t *c = objs[j].counters;
+        c[0] = a;
+        c[1] = b;
+        unsigned long long *o = reinterpret_cast<unsigned long long *>(c + 4);  // [16..17] += [4..5] + [6..7]
+        o[6] += o[0] + o[1];
+    }
+}
+
+DualArgs dual_args(Ctx &c, float sigma) {
+    LeafStore &s = c.lv();
+    return DualArgs{c.L, s.cap, s.level.p, s.ubar.p, s.nbp_off.p, s.nbp.p, s.p.p, s.ds.p, sigma};
+}
+
+PrimalArgs primal_args(Ctx &c, float tau, float tl) {
+    LeafStore &s = c.lv();
+    PrimalArgs a;
+    a.L = c.L;
+    a.cap = s.cap;
+    a.level = s.level.p;
+    a.ds = s.ds.p;
+    a.p = s.p.p;
+    a.off = s.nbm_off.p;
+    a.ent = s.nbm.p;
+    a.obs_off = s.obs_off.p;
+    a.obs_m = s.obs_m.p;
+    a.obs_unit = s.obs_unit.p;
+    a.inv = s.inv.p;
+    a.wtot = s.wtot.p;
+    a.F = c.op().F.p;
+    a.P = c.op().P.p;
+    a.u_in = s.u.p;
+    a.u = s.u.p;
+    a.ubar = s.ubar.p;
+    a.flag = s.flag.p;
+    a.uprime = s.uprime.p;
+    a.uold = s.uold.p;
+    a.part = nullptr;
+    a.part_stride = 0;
+    a.tau = tau;
+    a.tl = tl;
+    a.split_tau = c.prm.split_tau;
+    a.join_tau = c.prm.join_tau;
+    a.join_enabled = !(c.prm.join_tau > 1.0f);
+    a.max_depth = c.prm.max_depth;
+    return a;
+}
+
+template <int BLK>
+void launch_batch(hipStream_t st, BatchState &b) {
+    const ObjDev *objs = reinterpret_cast<const ObjDev *>(b.table.p);
+    const int nobj = (int)b.objs.size();
+    const unsigned grid = (unsigned)(b.cfg.grid > 0 ? std::min<uint32_t>(b.cfg.grid, b.ntiles) : b.ntiles);
+    hipLaunchKernelGGL(k_dual_b<BLK>, dim3(grid), dim3(BLK), 0, st, objs, nobj, (const uint32_t *)b.tile_begin.p,
+                       b.ntiles, (const Coef *)b.coefs.p);
+    OTF_LAUNCH_CHECK("k_dual_b");
+    if (b.n_hp > 0) {
+        hipLaunchKernelGGL(k_dual_long_b, dim3(b.n_hp), dim3(kBlk), kStageBytes, st, objs, nobj,
+                           (const uint32_t *)b.hp_begin.p, (const Coef *)b.coefs.p);
+        OTF_LAUNCH_CHECK("k_dual_long_b");
+    }
+    if (b.n_hm > 0) {
+        hipLaunchKernelGGL(k_primal_long_b, dim3(b.n_hm), dim3(kBlk), kStageBytes, st, objs, nobj,
+                           (const uint32_t *)b.hm_begin.p, (const Coef *)b.coefs.p);
+        OTF_LAUNCH_CHECK("k_primal_long_b");
+    }
+    hipLaunchKernelGGL(k_primal_b<BLK>, dim3(grid), dim3(BLK), 0, st, objs, nobj, (const uint32_t *)b.tile_begin.p,
+                       b.ntiles, (const Coef *)b.coefs.p, b.part.p);
+    OTF_LAUNCH_CHECK("k_primal_b");
+    hipLaunchKernelGGL(k_batch_counts, dim3((unsigned)nobj), dim3(kBlk), 0, st, objs,
+                       (const uint32_t *)b.tile_begin.p, b.ntiles, (const uint32_t *)b.part.p);
+    OTF_LAUNCH_CHECK("k_batch_counts");
 }
 
 }  // namespace
@@ -577,6 +768,72 @@ void energy(Ctx &c, double *tv, double *data) {
     }
     *tv = t;
     *data = d;
+}
+
+BatchState::~BatchState() {
+    if (h_stage) (void)hipHostFree(h_stage);
+    if (staged) (void)hipEventDestroy(staged);
+}
+
+void batch_upload(hipStream_t st, BatchState &b, float sigma, float tau, float tl) {
+    const int nobj = (int)b.objs.size();
+    const int blk = b.cfg.blk;
+    if (!b.coefs.p) {
+        std::vector<Coef> cf(kMaxDepth + 1);
+        for (int D = 1; D <= kMaxDepth; ++D) cf[D] = make_coef(D);
+        b.coefs.reserve(kMaxDepth + 1);
+        OTF_HIP(hipMemcpy(b.coefs.p, cf.data(), cf.size() * sizeof(Coef), hipMemcpyHostToDevice));
+    }
+    const size_t tbytes = (size_t)nobj * sizeof(ObjDev), ibytes = (size_t)(nobj + 1) * sizeof(uint32_t);
+    const size_t need = tbytes + 3 * ibytes;
+    if (b.staged) OTF_HIP(hipEventSynchronize(b.staged));  // the previous upload has left the staging area
+    else OTF_HIP(hipEventCreateWithFlags(&b.staged, hipEventDisableTiming));
+    if (need > b.h_cap) {
+        if (b.h_stage) OTF_HIP(hipHostFree(b.h_stage));
+        b.h_stage = nullptr;
+        OTF_HIP(hipHostMalloc((void **)&b.h_stage, 2 * need, hipHostMallocDefault));
+        b.h_cap = 2 * need;
+    }
+    ObjDev *rec = reinterpret_cast<ObjDev *>(b.h_stage);
+    uint32_t *tb = reinterpret_cast<uint32_t *>(b.h_stage + tbytes);
+    uint32_t *hp = tb + (nobj + 1), *hm = hp + (nobj + 1);
+    tb[0] = hp[0] = hm[0] = 0;
+    for (int j = 0; j < nobj; ++j) {
+        Ctx &c = *b.objs[j];
+        LeafStore &s = c.lv();
+        rec[j].d = dual_args(c, sigma);
+        rec[j].p = primal_args(c, tau, tl);
+        rec[j].heavy_p = s.heavy_p.p;
+        rec[j].heavy_m = s.heavy_m.p;
+        rec[j].counters = c.counters.p;
+        rec[j].D = c.prm.max_depth;
+        tb[j + 1] = tb[j] + (uint32_t)cdiv(c.L, blk);
+        hp[j + 1] = hp[j] + (uint32_t)s.n_heavy_p;
+        hm[j + 1] = hm[j] + (uint32_t)s.n_heavy_m;
+    }
+    b.ntiles = tb[nobj];
+    b.n_hp = hp[nobj];
+    b.n_hm = hm[nobj];
+    b.table.reserve(tbytes);
+    b.tile_begin.reserve(nobj + 1);
+    b.hp_begin.reserve(nobj + 1);
+    b.hm_begin.reserve(nobj + 1);
+    b.part.reserve(2 * (size_t)b.ntiles);
+    OTF_HIP(hipMemcpyAsync(b.table.p, rec, tbytes, hipMemcpyHostToDevice, st));
+    OTF_HIP(hipMemcpyAsync(b.tile_begin.p, tb, ibytes, hipMemcpyHostToDevice, st));
+    OTF_HIP(hipMemcpyAsync(b.hp_begin.p, hp, ibytes, hipMemcpyHostToDevice, st));
+    OTF_HIP(hipMemcpyAsync(b.hm_begin.p, hm, ibytes, hipMemcpyHostToDevice, st));
+    OTF_HIP(hipEventRecord(b.staged, st));
+}
+
+void batch_sweeps(hipStream_t st, BatchState &b) {
+    switch (b.cfg.blk) {
+        case 64: launch_batch<64>(st, b); break;
+        case 128: launch_batch<128>(st, b); break;
+        case 256: launch_batch<256>(st, b); break;
+        case 512: launch_batch<512>(st, b); break;
+        default: fail(OTF_E_INVALID, "unsupported batch block size");
+    }
 }
 
 }  // namespace otf

@@ -58,6 +58,11 @@ def lib():
             "otf_import_state": [P, P, I64],
             "otf_profile": [P, I32],
             "otf_profile_read": [P, P, P, P, P],
+            "otf_batch_create": [C.c_int, P, P],
+            "otf_batch_destroy": [P],
+            "otf_batch_add": [P, P],
+            "otf_batch_fuse": [P, I32, C.c_float, C.c_float, C.c_float],
+            "otf_batch_config": [P, P, P, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -65,6 +70,8 @@ def lib():
             fn.restype = C.c_int
         L.otf_last_error.argtypes = [P]
         L.otf_last_error.restype = C.c_char_p
+        L.otf_batch_last_error.argtypes = [P]
+        L.otf_batch_last_error.restype = C.c_char_p
         _lib = L
     return _lib
 
@@ -238,6 +245,49 @@ class Context:
     def reset_counters(self, profile: bool):
         """Zero the leaf-update and byte counters; enable or disable kernel timing."""
         self.profile(profile)
+
+
+class Batch:
+    """Many contexts swept by the same launches (otf_batch). Members stay owned
+    by the caller and must outlive the batch."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self._lib = lib()
+        self.h = C.c_void_p()
+        self.members = []
+        st = self._lib.otf_batch_create(device, _stream_handle(stream), C.byref(self.h))
+        if st != 0:
+            raise OtfError(st, "otf_batch_create")
+
+    def close(self):
+        if self.h:
+            self._lib.otf_batch_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, what):
+        if st != 0:
+            raise OtfError(st, f"{what}: {self._lib.otf_batch_last_error(self.h).decode()}")
+
+    def add(self, ctx: Context):
+        self._check(self._lib.otf_batch_add(self.h, ctx.h), "otf_batch_add")
+        self.members.append(ctx)
+        return self
+
+    def fuse(self, iterations: int, lam: float, tau: float, sigma: float):
+        self._check(self._lib.otf_batch_fuse(self.h, int(iterations), lam, tau, sigma), "otf_batch_fuse")
+        return self
+
+    def config(self) -> dict:
+        b, g, t, gi = C.c_int32(0), C.c_int32(0), C.c_int32(0), C.c_int32(0)
+        self._check(self._lib.otf_batch_config(self.h, C.byref(b), C.byref(g), C.byref(t), C.byref(gi)),
+                    "otf_batch_config")
+        return dict(block=b.value, grid=g.value, tuned=bool(t.value), graph_iterations=gi.value)
 
 
 def raw_status(fn_name: str, *args) -> int:

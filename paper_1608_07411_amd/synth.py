@@ -431,6 +431,23 @@ def thin_workload(seed: int = 0, max_depth: int = 9, n_views: int = 64, W: int =
                     iterations, prims=prims)
 
 
+def batch_workloads(n_objects: int = 48, first_seed: int = 1000, restructure_every: int = 0) -> list:
+    """Many independent sphere objects (the batched workload): object j draws
+    its max depth uniformly from {6, 7, 8, 9} and its view count from
+    {8, ..., 64} with seed first_seed + j, views on the circle as in the sphere
+    workload (160x120, f = 150)."""
+    out = []
+    for j in range(n_objects):
+        s = Stream(4, first_seed + j, 0)
+        D = 6 + int(s.uniform(1)[0] * 4)
+        V = 8 + int(s.uniform(1)[0] * 57)
+        w = sphere_workload(seed=first_seed + j, max_depth=D, n_views=V, workload_id=4,
+                            restructure_every=restructure_every)
+        w.name = f"batch-object-{j}"
+        out.append(w)
+    return out
+
+
 def workload(k: int, seed: int = 0, **kw) -> Workload:
     """The three plain-method workloads: 1 sphere (depth 6), 2 blocks (depth 8), 3 thin (depth 9)."""
     if k == 1:
