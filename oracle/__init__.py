@@ -37,6 +37,8 @@ def _lib(precision: str):
         lib.orc_build_volumes.argtypes = [P, P, P, C.c_int, P]
         lib.orc_tsdf_volume.argtypes = [P, C.c_int, P, P, C.c_int, P, P]
         lib.orc_fuse.argtypes = [P, C.c_int, C.c_float, C.c_float, C.c_float]
+        lib.orc_fuse_gd.argtypes = [P, C.c_int, C.c_float, C.c_float, C.c_float]
+        lib.orc_energy_eps.argtypes = [P, C.c_double, P, P]
         lib.orc_num_leaves.restype = C.c_int64
         lib.orc_num_leaves.argtypes = [P]
         lib.orc_last_counts.argtypes = [P, P, P]
@@ -127,6 +129,11 @@ class Oracle:
         self._check(self.lib.orc_fuse(self.h, int(iterations), lam, tau, sigma))
         return self
 
+    def fuse_gd(self, iterations: int, lam: float, xi: float, eps: float):
+        """The paper's gradient descent (lambda on TV, step xi, smoothing eps)."""
+        self._check(self.lib.orc_fuse_gd(self.h, int(iterations), lam, xi, eps))
+        return self
+
     def last_counts(self):
         s, j = C.c_int64(0), C.c_int64(0)
         self.lib.orc_last_counts(self.h, C.byref(s), C.byref(j))
@@ -182,6 +189,12 @@ class Oracle:
     def energy(self):
         tv, data = C.c_double(0), C.c_double(0)
         self._check(self.lib.orc_energy(self.h, C.byref(tv), C.byref(data)))
+        return tv.value, data.value
+
+    def energy_eps(self, eps: float):
+        """Smoothed terms (tv, data) of the gradient-descent energy."""
+        tv, data = C.c_double(0), C.c_double(0)
+        self._check(self.lib.orc_energy_eps(self.h, float(eps), C.byref(tv), C.byref(data)))
         return tv.value, data.value
 
 

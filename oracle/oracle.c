@@ -26,7 +26,9 @@
  *     unequal size, dual ascent and unit-ball projection, divergence, and the
  *     generalised shrinkage (median) prox [Sec. 3.2; Sec. 5 names primal-dual];
  *   - split and join of leaves from the updated values [Sec. 3.2, the two
- *     restructuring rules].
+ *     restructuring rules];
+ *   - the paper's own solver: gradient descent to the steady state of Eq. 6 on
+ *     the smoothed (Eq. 4), normalised (Eq. 5) energy, lambda on TV.
  * Where the paper is silent the readings are: lambda weights the normalised
  * data term; leaves of unequal size couple through area-weighted differences
  * over centre distance (exactly adjoint to the divergence); a split cascades
@@ -102,8 +104,16 @@ typedef struct unode {
     real Wtot, inv;
 } unode;
 
+/* Solver of the running fuse call: the primal-dual iteration, or the paper's
+ * own gradient descent (lambda on TV, step xi, smoothing eps^2). */
+typedef struct {
+    int gd;
+    real lam, xi, eps2;
+} solver_t;
+
 typedef struct orc {
     orc_params prm;
+    solver_t sol;
     int n_views;
     vnode *views; /* n_views roots */
     unode *root;
@@ -555,6 +565,68 @@ static int primal_leaf(const orc *o, unode *n, real tau, real tl, leafvec *nb) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* The paper's own solver: explicit gradient descent to the steady state of   */
+/* the PDE of Eq. 6 for the energy of Eq. 5 with both terms smoothed as in    */
+/* Eq. 4, Gamma(x^2) = sqrt(x^2 + eps^2), and lambda on the TV term:          */
+/*   E(u) = sum_n vol_n [ sum_i W_i Gamma((u_n - F_i)^2) / (sum W + gamma)    */
+/*                        + lambda Gamma(|(Gu)_n|^2) ]                        */
+/*   u <- u + xi (lambda div(q) - d'(u)),   q = Gu / Gamma(|Gu|^2),           */
+/*   d'(u) = sum_i W_i (u - F_i) / Gamma((u - F_i)^2) / (sum W + gamma).      */
+/* q is kept in p; div is the same volume-weighted adjoint as above.          */
+/* ------------------------------------------------------------------------ */
+static int gd_flux_leaf(const orc *o, unode *n, real eps2, leafvec *nb) {
+    real g[3];
+    for (int d = 0; d < 3; ++d) {
+        int st = neighbours(n, d, +1, nb);
+        if (st) return st;
+        real acc = 0;
+        for (int64_t j = 0; j < nb->n; ++j) {
+            unode *k = nb->a[j];
+            acc = R_FMA(coef_grad(o, n, k), k->u - n->u, acc);
+        }
+        g[d] = acc;
+    }
+    real r2 = R_FMA(g[0], g[0], R_FMA(g[1], g[1], g[2] * g[2]));
+    real den = R_SQRT(r2 + eps2);
+    for (int d = 0; d < 3; ++d) n->p[d] = g[d] / den;
+    return ORC_OK;
+}
+
+/* d'(u) for leaf n's observations, in (F, view) order. */
+static real gd_data_grad(const unode *n, real u, real eps2) {
+    real acc = 0;
+    for (int k = 0; k < n->M; ++k) {
+        real r = u - n->F[k];
+        real den = R_SQRT(R_FMA(r, r, eps2));
+        acc = R_FMA(n->W[k], r / den, acc);
+    }
+    return acc * n->inv;
+}
+
+static void set_flags(const orc *o, unode *n) {
+    n->split_flag = (R_ABS(n->uplus) < (real)o->prm.split_tau) && (n->level < o->prm.max_depth);
+    n->join_sign = 0;
+    if (!(o->prm.join_tau > 1.0f) && R_ABS(n->uplus) > (real)o->prm.join_tau) n->join_sign = n->uplus > 0 ? 1 : -1;
+    n->fresh_join = 0;
+}
+
+/* One descent step of leaf n; the divergence is kept (uprime) so that split
+ * children can take the same step with their own data term. */
+static int gd_update_leaf(const orc *o, unode *n, leafvec *nb) {
+    const solver_t *s = &o->sol;
+    real dv;
+    int st = div_leaf(o, n, nb, &dv);
+    if (st) return st;
+    n->uprime = dv;
+    n->uold = n->u;
+    n->uplus = R_FMA(s->xi, R_FMA(s->lam, dv, -gd_data_grad(n, n->u, s->eps2)), n->u);
+    n->u = n->uplus;
+    n->ubar = n->uplus;
+    set_flags(o, n);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Restructuring [Sec. 3.2, split and join rules].                           */
 /* ------------------------------------------------------------------------ */
 /* +1 / -1 if every leaf below n is joinable with that sign, else 0. */
@@ -603,7 +675,8 @@ static int collapse(orc *o, unode *n) {
 }
 
 /* Split n into 8 children that inherit u', u_old and p; each child runs the
- * prox on its own observations and splits again while it is still flagged. */
+ * prox (gradient descent: the descent step) on its own observations and
+ * splits again while it is still flagged. */
 static int cascade(orc *o, unode *n, real tl) {
     int st = make_kids(o, n);
     if (st) return st;
@@ -617,11 +690,19 @@ static int cascade(orc *o, unode *n, real tl) {
         k->p[2] = n->p[2];
         st = gather_obs(o, k);
         if (st) return st;
-        real *scr = scratch_for(k->M);
-        if (!scr) return ORC_E_NOMEM;
-        k->uplus = prox_median(k->M, k->F, k->Sk, k->uprime, tl * k->inv, scr);
-        k->u = k->uplus;
-        k->ubar = R_FMA((real)2, k->uplus, -k->uold);
+        if (o->sol.gd) {
+            /* the parent's step with the child's own data term */
+            const solver_t *s = &o->sol;
+            k->uplus = R_FMA(s->xi, R_FMA(s->lam, k->uprime, -gd_data_grad(k, k->uold, s->eps2)), k->uold);
+            k->u = k->uplus;
+            k->ubar = k->uplus;
+        } else {
+            real *scr = scratch_for(k->M);
+            if (!scr) return ORC_E_NOMEM;
+            k->uplus = prox_median(k->M, k->F, k->Sk, k->uprime, tl * k->inv, scr);
+            k->u = k->uplus;
+            k->ubar = R_FMA((real)2, k->uplus, -k->uold);
+        }
         k->join_sign = 0;
         k->split_flag = (R_ABS(k->uplus) < (real)o->prm.split_tau) && (k->level < o->prm.max_depth);
     }
@@ -771,6 +852,7 @@ int orc_fuse(orc *o, int iterations, float lam, float tau, float sigma) {
         return set_err(o, "bad fuse arguments"), ORC_E_INVALID;
     const real rt = (real)tau, rs = (real)sigma;
     const real tl = rt * (real)lam;
+    o->sol.gd = 0;
     leafvec lv = {0}, nb = {0};
     int st = ORC_OK;
     for (int it = 0; it < iterations && !st; ++it) {
@@ -783,6 +865,36 @@ int orc_fuse(orc *o, int iterations, float lam, float tau, float sigma) {
         if (!st && o->prm.restructure_every > 0 && o->iteration % o->prm.restructure_every == 0)
             st = restructure(o, tl);
     }
+    free(lv.a);
+    free(nb.a);
+    return st;
+}
+
+/* `iterations` steps of the paper's gradient descent (see gd_update_leaf)
+ * with step xi, TV weight lam and smoothing eps, split/join as for orc_fuse
+ * with the descent step in place of the prox. Jacobi phases: every flux from
+ * the current u, then every update. */
+int orc_fuse_gd(orc *o, int iterations, float lam, float xi, float eps) {
+    if (!o || !o->root) return ORC_E_STATE;
+    if (iterations < 0 || !isfinite(lam) || !isfinite(xi) || !isfinite(eps) || lam < 0 || !(xi > 0) || !(eps > 0))
+        return set_err(o, "bad fuse arguments"), ORC_E_INVALID;
+    o->sol.gd = 1;
+    o->sol.lam = (real)lam;
+    o->sol.xi = (real)xi;
+    o->sol.eps2 = (real)eps * (real)eps;
+    leafvec lv = {0}, nb = {0};
+    int st = ORC_OK;
+    for (int it = 0; it < iterations && !st; ++it) {
+        o->iteration++;
+        lv.n = 0;
+        st = collect(o->root, &lv);
+        for (int64_t i = 0; i < lv.n && !st; ++i) st = gd_flux_leaf(o, lv.a[i], o->sol.eps2, &nb);
+        for (int64_t i = 0; i < lv.n && !st; ++i) st = gd_update_leaf(o, lv.a[i], &nb);
+        o->last_splits = o->last_joins = 0;
+        if (!st && o->prm.restructure_every > 0 && o->iteration % o->prm.restructure_every == 0)
+            st = restructure(o, 0);
+    }
+    o->sol.gd = 0;
     free(lv.a);
     free(nb.a);
     return st;
@@ -935,6 +1047,42 @@ int orc_apply_div(const orc *o, const double *p, double *out) {
 /* Energy [Eq. 3 with the normaliser of Eq. 5, lambda on the data term]:
  * tv = sum_n vol_n |(G u)_n|, data = sum_n vol_n inv_n sum_i W_i |u_n - F_i|;
  * E = tv + lambda * data. Accumulated in double. */
+/* Smoothed energy terms of Eq. 4-5 (eps > 0): tv = sum vol sqrt(|Gu|^2 + eps^2),
+ * data = sum vol inv sum W sqrt((u - F)^2 + eps^2); in double. With eps = 0
+ * these are the exact terms of orc_energy. */
+int orc_energy_eps(const orc *o, double eps, double *tv, double *data) {
+    if (!o || !o->root) return ORC_E_STATE;
+    const double e2 = eps * eps;
+    leafvec lv = {0}, nb = {0};
+    collect(o->root, &lv);
+    double t = 0, dt = 0;
+    for (int64_t i = 0; i < lv.n; ++i) {
+        unode *n = lv.a[i];
+        double vol = (double)side_of(o, n->level);
+        vol = vol * vol * vol;
+        double g2 = 0;
+        for (int d = 0; d < 3; ++d) {
+            neighbours(n, d, +1, &nb);
+            double g = 0;
+            for (int64_t j = 0; j < nb.n; ++j)
+                g += (double)coef_grad(o, n, nb.a[j]) * ((double)nb.a[j]->u - (double)n->u);
+            g2 += g * g;
+        }
+        t += vol * sqrt(g2 + e2);
+        double s = 0;
+        for (int k = 0; k < n->M; ++k) {
+            double r = (double)n->u - (double)n->F[k];
+            s += (double)n->W[k] * sqrt(r * r + e2);
+        }
+        dt += vol * (double)n->inv * s;
+    }
+    free(lv.a);
+    free(nb.a);
+    *tv = t;
+    *data = dt;
+    return ORC_OK;
+}
+
 int orc_energy(const orc *o, double *tv, double *data) {
     if (!o || !o->root) return ORC_E_STATE;
     leafvec lv = {0}, nb = {0};

@@ -52,6 +52,26 @@ def parse_views(blob: bytes):
     return views, leaves
 
 
+def blob_set_leaves(blob: bytes, u=None, ubar=None, p=None) -> bytes:
+    """Copy of a state blob with the leaves' u, ubar or p replaced (leaf order)."""
+    at = 8 + 40 + 8
+    n_views = struct.unpack_from("<i", blob, at)[0]
+    at += 8
+    for _ in range(n_views):
+        n = struct.unpack_from("<q", blob, at)[0]
+        at += 8 + 16 * n
+    nl = struct.unpack_from("<q", blob, at)[0]
+    at += 8
+    ldt = np.dtype([("key", "<u4"), ("level", "u1"), ("pad", "u1", (3,)), ("u", "<f4"), ("ubar", "<f4"),
+                    ("p", "<f4", (3,))])
+    b = bytearray(blob)
+    leaves = np.frombuffer(b, dtype=ldt, count=nl, offset=at)
+    for name, v in (("u", u), ("ubar", ubar), ("p", p)):
+        if v is not None:
+            leaves[name] = np.asarray(v, dtype=np.float32).reshape(leaves[name].shape)
+    return bytes(b)
+
+
 def leaf_boxes(keys, levels, max_depth):
     x, y, z = morton_decode(keys)
     s = (1 << (max_depth - levels.astype(np.int64)))
