@@ -169,6 +169,33 @@ otf_status otf_profile_read(otf_ctx *ctx, double *ms, int64_t *launches, int64_t
 const char *otf_last_error(const otf_ctx *ctx);
 
 /* ---------------------------------------------------------------------------
+ * The paper's own solver (Sec. 3.2, Eq. 4-6): explicit gradient descent to
+ * the steady state of the PDE of Eq. 6, on the energy of Eq. 5 with both
+ * terms smoothed as in Eq. 4 (Gamma(x^2) = sqrt(x^2 + epsilon^2)) and lambda
+ * on the TV term:
+ *   E(u) = sum_n vol_n [ sum_i W_i Gamma((u_n - F_i)^2) / (sum_i W_i + gamma)
+ *                        + lambda Gamma(|(Gu)_n|^2) ],
+ *   u <- u + step (lambda div(Gu / Gamma(|Gu|^2)) - d'(u)),
+ *   d'(u) = sum_i W_i (u - F_i) / Gamma((u - F_i)^2) / (sum_i W_i + gamma),
+ * with G and div the same unequal-leaf operators as otf_fuse, Jacobi phases
+ * (every flux from the current u, then every update), and split/join after
+ * each step as in otf_fuse, a split child taking its parent's step with its
+ * own data term. The paper runs 100 steps, the step 0.1 halved every 20; the
+ * caller does that by calling this function in chunks.
+ * ------------------------------------------------------------------------- */
+
+/* `iterations` descent steps. Errors: OTF_E_INVALID (iterations < 0, a
+ * non-finite argument, lambda < 0, step <= 0 or epsilon <= 0; nothing ran),
+ * OTF_E_STATE (no octree), otherwise as otf_fuse. */
+otf_status otf_fuse_gd(otf_ctx *ctx, int32_t iterations, float lambda, float step, float epsilon);
+
+/* The smoothed terms of the gradient-descent energy in double:
+ * tv = sum_n vol_n Gamma(|(Gu)_n|^2), data = sum_n vol_n inv_n sum_i W_i
+ * Gamma((u_n - F_i)^2); the energy is data + lambda tv. Errors: OTF_E_INVALID
+ * (null outputs, epsilon not finite or <= 0), OTF_E_STATE. */
+otf_status otf_energy_eps(otf_ctx *ctx, double epsilon, double *tv, double *data);
+
+/* ---------------------------------------------------------------------------
  * Batches: the primal-dual iterations (Sec. 3.2, Eq. 5; the primal-dual
  * scheme of Chambolle and Pock that Sec. 5 names) of many fused octrees in
  * the same kernel launches, for callers that fuse many objects at once

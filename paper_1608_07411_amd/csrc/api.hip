@@ -361,6 +361,7 @@ otf_status otf_fuse(otf_ctx *ctx, int32_t iterations, float lambda, float tau, f
     return guard(ctx, true, [&] {
         Ctx &c = ctx->c;
         const float tl = tau * lambda;
+        c.sol = Solver{};
         for (int it = 0; it < iterations; ++it) {
             c.iteration++;
             prof_begin(c);
@@ -382,6 +383,39 @@ otf_status otf_fuse(otf_ctx *ctx, int32_t iterations, float lambda, float tau, f
             }
         }
         read_back(c, {});  // synchronises and checks the scan health flag
+    });
+}
+
+otf_status otf_fuse_gd(otf_ctx *ctx, int32_t iterations, float lambda, float step, float epsilon) {
+    if (!ctx) return OTF_E_INVALID;
+    if (iterations < 0 || !std::isfinite(lambda) || !std::isfinite(step) || !std::isfinite(epsilon) ||
+        lambda < 0.0f || !(step > 0.0f) || !(epsilon > 0.0f)) {
+        ctx->c.err = "bad fuse arguments";
+        return OTF_E_INVALID;
+    }
+    if (!ctx->c.valid) {
+        ctx->c.err = "no valid state";
+        return OTF_E_STATE;
+    }
+    return guard(ctx, true, [&] {
+        Ctx &c = ctx->c;
+        c.sol = Solver{1, lambda, step, epsilon * epsilon};
+        for (int it = 0; it < iterations; ++it) {
+            c.iteration++;
+            prof_begin(c);
+            launch_gd(c, c.sol.lam, c.sol.xi, c.sol.eps2);
+            prof_end(c, kProfPrimal);
+            count_flags(c);
+            c.leaf_updates += c.L;
+            c.last_splits = c.last_joins = 0;
+            if (c.prm.restructure_every > 0 && c.iteration % c.prm.restructure_every == 0) {
+                prof_begin(c);
+                restructure(c, 0.0f);
+                prof_end(c, kProfRestructure);
+            }
+        }
+        c.sol = Solver{};
+        read_back(c, {});
     });
 }
 
@@ -512,6 +546,16 @@ otf_status otf_energy(otf_ctx *ctx, double *tv, double *data) {
     return guard(ctx, false, [&] {
         prof_begin(ctx->c);
         energy(ctx->c, tv, data);
+        prof_end(ctx->c, kProfEnergy);
+    });
+}
+
+otf_status otf_energy_eps(otf_ctx *ctx, double epsilon, double *tv, double *data) {
+    if (!ctx || !tv || !data || !std::isfinite(epsilon) || !(epsilon > 0.0)) return OTF_E_INVALID;
+    if (!ctx->c.valid) return OTF_E_STATE;
+    return guard(ctx, false, [&] {
+        prof_begin(ctx->c);
+        energy(ctx->c, tv, data, epsilon);
         prof_end(ctx->c, kProfEnergy);
     });
 }

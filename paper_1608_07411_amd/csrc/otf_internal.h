@@ -269,8 +269,16 @@ struct Scratch {
 
 enum ProfKind { kProfDual = 0, kProfPrimal = 1, kProfRestructure = 2, kProfEnergy = 3, kProfKinds = 4 };
 
+// Solver of the running fuse call: primal-dual, or the paper's gradient
+// descent (TV weight lam, step xi, smoothing eps^2); split children follow it.
+struct Solver {
+    int gd = 0;
+    float lam = 0.0f, xi = 0.0f, eps2 = 0.0f;
+};
+
 struct Ctx {
     int device = 0;
+    Solver sol;
     hipStream_t stream = nullptr;
     otf_params prm{};
     int n_views = 0;
@@ -369,9 +377,13 @@ void build_neighbours_incremental(Ctx &c, const LeafStore &old, const uint32_t *
 // sweeps
 void launch_dual(Ctx &c, float sigma);
 void launch_primal(Ctx &c, float tau, float tl);
+// one step of the paper's gradient descent: flux sweep, then the update sweep
+// (flags as the primal sweep's)
+void launch_gd(Ctx &c, float lam, float xi, float eps2);
 // split and join flag counts of the last primal sweep into counters[0], [1]
 void count_flags(Ctx &c);
-void energy(Ctx &c, double *tv, double *data);
+// energy terms in double; eps > 0: the smoothed terms of the gradient-descent energy
+void energy(Ctx &c, double *tv, double *data, double eps = 0.0);
 // split / join; returns true when the structure changed
 bool restructure(Ctx &c, float tl);
 

@@ -209,18 +209,34 @@ __global__ void k_children_next(int64_t nc_prev, int D, const uint8_t *csplit, c
     }
 }
 
+// Children's values: the prox of the parent's u' on the child's own
+// observations (primal-dual), or the parent's descent step (divergence kept in
+// uprime) with the child's own data term (gradient descent).
 __global__ void k_cascade_prox(int64_t nc, int stride, const float *tF, const float *tW, const uint8_t *tM,
                                const uint8_t *tU, const float *tInv, const float *tWt, const uint32_t *corigin,
                                const uint8_t *clevel, const float *uprime, const float *uold, float tl,
-                               float split_tau, int D, float *cu, float *cub, uint8_t *csplit) {
+                               float split_tau, int D, Solver sol, float *cu, float *cub, uint8_t *csplit) {
     const int64_t j = TID();
     if (j >= nc) return;
     const uint32_t o = corigin[j];
     const float up = uprime[o], uo = uold[o];
-    const float val =
-        prox_select(up, tl * tInv[j], tM[j], tU[j] != 0, tF + j * (int64_t)stride, tW + j * (int64_t)stride, tWt[j]);
-    cu[j] = val;
-    cub[j] = __fmaf_rn(2.0f, val, -uo);
+    const float *F = tF + j * (int64_t)stride, *W = tW + j * (int64_t)stride;
+    float val;
+    if (sol.gd) {
+        float acc = 0.0f;
+        for (int k = 0; k < tM[j]; ++k) {
+            const float r = uo - F[k];
+            const float den = sqrtf(__fmaf_rn(r, r, sol.eps2));
+            acc = __fmaf_rn(W[k], r / den, acc);
+        }
+        val = __fmaf_rn(sol.xi, __fmaf_rn(sol.lam, up, -(acc * tInv[j])), uo);
+        cu[j] = val;
+        cub[j] = val;
+    } else {
+        val = prox_select(up, tl * tInv[j], tM[j], tU[j] != 0, F, W, tWt[j]);
+        cu[j] = val;
+        cub[j] = __fmaf_rn(2.0f, val, -uo);
+    }
     csplit[j] = (fabsf(val) < split_tau && clevel[j] < D) ? 1 : 0;
 }
 
@@ -484,7 +500,7 @@ bool restructure(Ctx &c, float tl) {
                         s.fc.p, s.fd.p, nullptr, nullptr);
             hipLaunchKernelGGL(k_cascade_prox, dim3(grid(nc)), dim3(kBlk), 0, c.stream, nc, stride, s.fa.p, s.fb.p,
                                tM.p, tU.p, s.fc.p, s.fd.p, R.corigin.p, R.clevel.p, os.uprime.p, os.uold.p, tl,
-                               c.prm.split_tau, D, R.cu.p, R.cub.p, R.csplit.p);
+                               c.prm.split_tau, D, c.sol, R.cu.p, R.cub.p, R.csplit.p);
             OTF_LAUNCH_CHECK("k_cascade_prox");
             const uint32_t next = scan_exclusive_u8(c, R.csplit.p, R.crank.p, nc);
             total_splits += np;

@@ -31,21 +31,36 @@ __device__ inline int rdlane_i(int v, int l) { return __builtin_amdgcn_readlane(
 struct DualArgs {
     int64_t L, cap;
     const uint8_t *level;
-    const float *ubar;
+    const float *ubar;  // the field differenced: ubar (primal-dual) or u (gradient descent)
     const uint32_t *off;
     const uint32_t *ent;
     float *p;
     float *ds;
     float sigma;
+    int gd;      // 1: gradient-descent flux q = g / sqrt(|g|^2 + eps^2) instead of the dual step
+    float eps2;
 };
 
 // q = p + sigma g, projection onto the unit ball, and the leaf's own part of
 // the divergence from the updated p.
 __device__ inline void dual_finish(const DualArgs &a, int64_t i, float gx, float gy, float gz, float Cx, float Cy,
                                    float Cz) {
-    float qx = __fmaf_rn(a.sigma, gx, a.p[i]);
-    float qy = __fmaf_rn(a.sigma, gy, a.p[a.cap + i]);
-    float qz = __fmaf_rn(a.sigma, gz, a.p[2 * a.cap + i]);
+    float qx, qy, qz;
+    if (a.gd) {
+        const float r2 = __fmaf_rn(gx, gx, __fmaf_rn(gy, gy, gz * gz));
+        const float den = sqrtf(r2 + a.eps2);
+        qx = gx / den;
+        qy = gy / den;
+        qz = gz / den;
+        a.p[i] = qx;
+        a.p[a.cap + i] = qy;
+        a.p[2 * a.cap + i] = qz;
+        a.ds[i] = __fmaf_rn(Cz, qz, __fmaf_rn(Cy, qy, __fmaf_rn(Cx, qx, 0.0f)));
+        return;
+    }
+    qx = __fmaf_rn(a.sigma, gx, a.p[i]);
+    qy = __fmaf_rn(a.sigma, gy, a.p[a.cap + i]);
+    qz = __fmaf_rn(a.sigma, gz, a.p[2 * a.cap + i]);
     const float r2 = __fmaf_rn(qx, qx, __fmaf_rn(qy, qy, qz * qz));
     if (r2 > 1.0f) {
         const float nrm = sqrtf(r2);
@@ -257,6 +272,10 @@ struct PrimalArgs {
     int64_t part_stride;
     float tau, tl, split_tau, join_tau;
     int join_enabled, max_depth;
+    // gradient descent: divergence kept in ds for long lists, step xi, TV weight lam
+    int gd;
+    float lam, xi, eps2;
+    const float *W;
 };
 
 // u' for leaves with a long - list (sequential fma chain), staged in LDS by a
@@ -284,7 +303,7 @@ __device__ void primal_long_chunked(const PrimalArgs &a, const Coef &cf, int64_t
         c = cn;
         pm = pmn;
     }
-    if (lane == 0) a.ds[i] = __fmaf_rn(a.tau, acc, a.u_in[i]);
+    if (lane == 0) a.ds[i] = a.gd ? acc : __fmaf_rn(a.tau, acc, a.u_in[i]);
 }
 
 __device__ void primal_long_block(const PrimalArgs &a, const Coef &cf, int64_t i, unsigned char *smem) {
@@ -333,12 +352,33 @@ __device__ void primal_long_block(const PrimalArgs &a, const Coef &cf, int64_t i
         for (int r = 0; r < 8; ++r) acc = __fmaf_rn(-cc[r], pp[r], acc);
     }
     for (; q < ne; ++q) acc = __fmaf_rn(-sc[q], sp[q], acc);
-    a.ds[i] = __fmaf_rn(a.tau, acc, a.u_in[i]);
+    a.ds[i] = a.gd ? acc : __fmaf_rn(a.tau, acc, a.u_in[i]);
 }
 
 __global__ void __launch_bounds__(kBlk) k_primal_long(uint32_t n, const uint32_t *list, PrimalArgs a, Coef cf) {
     extern __shared__ unsigned char smem[];
     if (blockIdx.x < n) primal_long_block(a, cf, list[blockIdx.x], smem);
+}
+
+// Own divergence term ds minus the incoming terms of the short - list
+// [e0, e1), in list order; kGather entries in flight.
+__device__ inline float divergence(const PrimalArgs &a, const Coef &cf, uint32_t e0, uint32_t e1, int ln,
+                                   float acc) {
+    for (uint32_t e = e0; e < e1; e += kGather) {
+        uint32_t v[kGather];
+        float pm[kGather];
+#pragma unroll
+        for (int r = 0; r < kGather; ++r) v[r] = e + r < e1 ? a.ent[e + r] : 0u;
+#pragma unroll
+        for (int r = 0; r < kGather; ++r)
+            pm[r] = e + r < e1 ? a.p[(int64_t)((v[r] >> kIdxBits) & 3) * a.cap + (v[r] & kIdxMask)] : 0.0f;
+#pragma unroll
+        for (int r = 0; r < kGather; ++r) {
+            if (e + r >= e1) break;
+            acc = __fmaf_rn(-cf.cp[v[r] >> (kIdxBits + 2)][ln], pm[r], acc);
+        }
+    }
+    return acc;
 }
 
 // Divergence per thread, then the prox cooperatively: the wave takes its 64
@@ -360,26 +400,8 @@ __device__ inline void primal_wave(const PrimalArgs &a, const Coef &cf, int64_t 
         ln = a.level[i];
         un = a.u_in[i];
         const uint32_t e0 = a.off[i], e1 = a.off[i + 1];
-        if (e1 - e0 > kLongList) {
-            up = a.ds[i];
-        } else {
-            float acc = a.ds[i];
-            for (uint32_t e = e0; e < e1; e += kGather) {
-                uint32_t v[kGather];
-                float pm[kGather];
-#pragma unroll
-                for (int r = 0; r < kGather; ++r) v[r] = e + r < e1 ? a.ent[e + r] : 0u;
-#pragma unroll
-                for (int r = 0; r < kGather; ++r)
-                    pm[r] = e + r < e1 ? a.p[(int64_t)((v[r] >> kIdxBits) & 3) * a.cap + (v[r] & kIdxMask)] : 0.0f;
-#pragma unroll
-                for (int r = 0; r < kGather; ++r) {
-                    if (e + r >= e1) break;
-                    acc = __fmaf_rn(-cf.cp[v[r] >> (kIdxBits + 2)][ln], pm[r], acc);
-                }
-            }
-            up = __fmaf_rn(a.tau, acc, un);
-        }
+        if (e1 - e0 > kLongList) up = a.ds[i];
+        else up = __fmaf_rn(a.tau, divergence(a, cf, e0, e1, ln, a.ds[i]), un);
         M = a.obs_m[i];
         oo = a.obs_off[i];
         unit = a.obs_unit[i];
@@ -478,11 +500,52 @@ __global__ void __launch_bounds__(kBlk) k_primal(PrimalArgs a, Coef cf) {
     block_flag_counts<kBlk>(ns, nj, a.part, a.part_stride, blockIdx.x);
 }
 
+// Gradient descent (the paper's solver): one thread per leaf.
+//   div = ds - sum c' q_m,  d' = (sum_k W_k r_k / sqrt(r_k^2 + eps^2)) inv,
+//   r_k = u - F_k in (F, view) order,  u <- u + xi (lam div - d').
+// The divergence is kept (uprime) so that split children take the same step
+// with their own data term.
+__global__ void __launch_bounds__(kBlk) k_gd_update(PrimalArgs a, Coef cf) {
+    const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
+    const bool valid = i < a.L;
+    bool split = false, join = false;
+    if (valid) {
+        const int ln = a.level[i];
+        const float un = a.u_in[i];
+        const uint32_t e0 = a.off[i], e1 = a.off[i + 1];
+        const float dv = (e1 - e0 > kLongList) ? a.ds[i] : divergence(a, cf, e0, e1, ln, a.ds[i]);
+        const int M = a.obs_m[i];
+        const uint32_t oo = a.obs_off[i];
+        float acc = 0.0f;
+        for (int k = 0; k < M; ++k) {
+            const float r = un - a.F[oo + k];
+            const float den = sqrtf(__fmaf_rn(r, r, a.eps2));
+            acc = __fmaf_rn(a.W[oo + k], r / den, acc);
+        }
+        const float dg = acc * a.inv[i];
+        const float v = __fmaf_rn(a.xi, __fmaf_rn(a.lam, dv, -dg), un);
+        a.u[i] = v;
+        a.ubar[i] = v;
+        const float av = fabsf(v);
+        split = av < a.split_tau && ln < a.max_depth;
+        join = a.join_enabled && av > a.join_tau;
+        a.flag[i] = split ? 1 : (join ? (v > 0.0f ? 2 : 4) : 0);
+        if (split) {
+            a.uprime[i] = dv;
+            a.uold[i] = un;
+        }
+    }
+    block_flag_counts<kBlk>((uint32_t)__popcll(__ballot(split)), (uint32_t)__popcll(__ballot(join)), a.part,
+                            a.part_stride, blockIdx.x);
+}
+
 // Energy: per-leaf terms in double, block partial sums in a fixed tree order.
+// With eps2 > 0 the terms are the smoothed ones of the gradient-descent
+// energy: sqrt(|Gu|^2 + eps^2) and sqrt((u - F)^2 + eps^2).
 __global__ void __launch_bounds__(kBlk) k_energy(int64_t L, int D, const uint8_t *level, const float *u,
                                                  const uint32_t *off, const uint32_t *ent, const uint32_t *obs_off,
                                                  const uint8_t *obs_m, const float *inv, const float *F,
-                                                 const float *W, Coef cf, double *partial) {
+                                                 const float *W, Coef cf, double eps2, double *partial) {
     __shared__ double s_tv[kBlk], s_da[kBlk];
     const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
     double tv = 0.0, da = 0.0;
@@ -502,10 +565,14 @@ __global__ void __launch_bounds__(kBlk) k_energy(int64_t L, int D, const uint8_t
         }
         const double s = ldexp(1.0, D - ln);
         const double vol = s * s * s;
-        tv = vol * sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+        const double g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+        tv = vol * (eps2 > 0.0 ? sqrt(g2 + eps2) : sqrt(g2));
         double acc = 0.0;
         const uint32_t o = obs_off[i];
-        for (int k = 0; k < obs_m[i]; ++k) acc += (double)W[o + k] * fabs(un - (double)F[o + k]);
+        for (int k = 0; k < obs_m[i]; ++k) {
+            const double r = un - (double)F[o + k];
+            acc += (double)W[o + k] * (eps2 > 0.0 ? sqrt(r * r + eps2) : fabs(r));
+        }
         da = vol * (double)inv[i] * acc;
     }
     s_tv[threadIdx.x] = tv;
@@ -626,7 +693,7 @@ __global__ void __launch_bounds__(kBlk) k_batch_counts(const ObjDev *objs, const
 
 DualArgs dual_args(Ctx &c, float sigma) {
     LeafStore &s = c.lv();
-    return DualArgs{c.L, s.cap, s.level.p, s.ubar.p, s.nbp_off.p, s.nbp.p, s.p.p, s.ds.p, sigma};
+    return DualArgs{c.L, s.cap, s.level.p, s.ubar.p, s.nbp_off.p, s.nbp.p, s.p.p, s.ds.p, sigma, 0, 0.0f};
 }
 
 PrimalArgs primal_args(Ctx &c, float tau, float tl) {
@@ -660,6 +727,9 @@ PrimalArgs primal_args(Ctx &c, float tau, float tl) {
     a.join_tau = c.prm.join_tau;
     a.join_enabled = !(c.prm.join_tau > 1.0f);
     a.max_depth = c.prm.max_depth;
+    a.gd = 0;
+    a.lam = a.xi = a.eps2 = 0.0f;
+    a.W = c.op().W.p;
     return a;
 }
 
@@ -693,7 +763,7 @@ void launch_batch(hipStream_t st, BatchState &b) {
 
 void launch_dual(Ctx &c, float sigma) {
     LeafStore &s = c.lv();
-    DualArgs a{c.L, s.cap, s.level.p, s.ubar.p, s.nbp_off.p, s.nbp.p, s.p.p, s.ds.p, sigma};
+    const DualArgs a = dual_args(c, sigma);
     hipLaunchKernelGGL(k_dual, dim3((unsigned)cdiv(c.L, kBlk)), dim3(kBlk), 0, c.stream, a, c.coef);
     OTF_LAUNCH_CHECK("k_dual");
     if (s.n_heavy_p > 0) {
@@ -705,37 +775,11 @@ void launch_dual(Ctx &c, float sigma) {
 
 void launch_primal(Ctx &c, float tau, float tl) {
     LeafStore &s = c.lv();
-    PrimalArgs a;
-    a.L = c.L;
-    a.cap = s.cap;
-    a.level = s.level.p;
-    a.ds = s.ds.p;
-    a.p = s.p.p;
-    a.off = s.nbm_off.p;
-    a.ent = s.nbm.p;
-    a.obs_off = s.obs_off.p;
-    a.obs_m = s.obs_m.p;
-    a.obs_unit = s.obs_unit.p;
-    a.inv = s.inv.p;
-    a.wtot = s.wtot.p;
-    a.F = c.op().F.p;
-    a.P = c.op().P.p;
-    a.u_in = s.u.p;
-    a.u = s.u.p;
-    a.ubar = s.ubar.p;
-    a.flag = s.flag.p;
-    a.uprime = s.uprime.p;
-    a.uold = s.uold.p;
+    PrimalArgs a = primal_args(c, tau, tl);
     const int64_t nblk = cdiv(c.L, kBlk);
     c.s.part.reserve(2 * nblk);
     a.part = c.s.part.p;
     a.part_stride = nblk;
-    a.tau = tau;
-    a.tl = tl;
-    a.split_tau = c.prm.split_tau;
-    a.join_tau = c.prm.join_tau;
-    a.join_enabled = !(c.prm.join_tau > 1.0f);
-    a.max_depth = c.prm.max_depth;
     if (s.n_heavy_m > 0) {
         hipLaunchKernelGGL(k_primal_long, dim3((unsigned)s.n_heavy_m), dim3(kBlk), kStageBytes, c.stream,
                            (uint32_t)s.n_heavy_m, s.heavy_m.p, a, c.coef);
@@ -745,18 +789,49 @@ void launch_primal(Ctx &c, float tau, float tl) {
     OTF_LAUNCH_CHECK("k_primal");
 }
 
+void launch_gd(Ctx &c, float lam, float xi, float eps2) {
+    LeafStore &s = c.lv();
+    DualArgs d = dual_args(c, 0.0f);
+    d.ubar = s.u.p;  // the flux differences u itself
+    d.gd = 1;
+    d.eps2 = eps2;
+    hipLaunchKernelGGL(k_dual, dim3((unsigned)cdiv(c.L, kBlk)), dim3(kBlk), 0, c.stream, d, c.coef);
+    OTF_LAUNCH_CHECK("k_dual (flux)");
+    if (s.n_heavy_p > 0) {
+        hipLaunchKernelGGL(k_dual_long, dim3((unsigned)s.n_heavy_p), dim3(kBlk), kStageBytes, c.stream,
+                           (uint32_t)s.n_heavy_p, s.heavy_p.p, d, c.coef);
+        OTF_LAUNCH_CHECK("k_dual_long (flux)");
+    }
+    PrimalArgs a = primal_args(c, 1.0f, 0.0f);
+    const int64_t nblk = cdiv(c.L, kBlk);
+    c.s.part.reserve(2 * nblk);
+    a.part = c.s.part.p;
+    a.part_stride = nblk;
+    a.gd = 1;
+    a.lam = lam;
+    a.xi = xi;
+    a.eps2 = eps2;
+    if (s.n_heavy_m > 0) {
+        hipLaunchKernelGGL(k_primal_long, dim3((unsigned)s.n_heavy_m), dim3(kBlk), kStageBytes, c.stream,
+                           (uint32_t)s.n_heavy_m, s.heavy_m.p, a, c.coef);
+        OTF_LAUNCH_CHECK("k_primal_long (divergence)");
+    }
+    hipLaunchKernelGGL(k_gd_update, dim3((unsigned)nblk), dim3(kBlk), 0, c.stream, a, c.coef);
+    OTF_LAUNCH_CHECK("k_gd_update");
+}
+
 void count_flags(Ctx &c) {
     const int64_t nblk = cdiv(c.L, kBlk);
     sum_parts(c, c.s.part.p, nblk, 2, nblk, c.counters.p);  // counters[0] split flags, [1] join flags
 }
 
-void energy(Ctx &c, double *tv, double *data) {
+void energy(Ctx &c, double *tv, double *data, double eps) {
     LeafStore &s = c.lv();
     const int64_t blocks = cdiv(c.L, kBlk);
     c.s.dred.reserve(2 * blocks);
     hipLaunchKernelGGL(k_energy, dim3((unsigned)blocks), dim3(kBlk), 0, c.stream, c.L, c.prm.max_depth, s.level.p,
                        s.u.p, s.nbp_off.p, s.nbp.p, s.obs_off.p, s.obs_m.p, s.inv.p, c.op().F.p, c.op().W.p, c.coef,
-                       c.s.dred.p);
+                       eps * eps, c.s.dred.p);
     OTF_LAUNCH_CHECK("k_energy");
     std::vector<double> h(2 * blocks);
     OTF_HIP(hipMemcpyAsync(h.data(), c.s.dred.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream));

@@ -53,6 +53,8 @@ def lib():
             "otf_extract_obs": [P, I64, P, P, P, I64, P, P, P],
             "otf_extract_neighbours": [P, I64, P, I64, P, P],
             "otf_energy": [P, P, P],
+            "otf_fuse_gd": [P, I32, C.c_float, C.c_float, C.c_float],
+            "otf_energy_eps": [P, C.c_double, P, P],
             "otf_last_counts": [P, P, P],
             "otf_export_state": [P, P, I64, P],
             "otf_import_state": [P, P, I64],
@@ -161,6 +163,17 @@ class Context:
     def fuse(self, iterations: int, lam: float, tau: float, sigma: float):
         self._check(self._lib.otf_fuse(self.h, int(iterations), lam, tau, sigma), "otf_fuse")
         return self
+
+    def fuse_gd(self, iterations: int, lam: float, step: float, eps: float):
+        """The paper's gradient descent (lambda on TV, step, smoothing eps)."""
+        self._check(self._lib.otf_fuse_gd(self.h, int(iterations), lam, step, eps), "otf_fuse_gd")
+        return self
+
+    def energy_eps(self, eps: float):
+        """Smoothed (tv, data) terms of the gradient-descent energy."""
+        tv, data = C.c_double(0), C.c_double(0)
+        self._check(self._lib.otf_energy_eps(self.h, float(eps), C.byref(tv), C.byref(data)), "otf_energy_eps")
+        return tv.value, data.value
 
     def num_leaves(self) -> int:
         n = C.c_int64(0)
