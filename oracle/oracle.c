@@ -592,15 +592,23 @@ static int gd_flux_leaf(const orc *o, unode *n, real eps2, leafvec *nb) {
     return ORC_OK;
 }
 
-/* d'(u) for leaf n's observations, in (F, view) order. */
+/* d'(u) for leaf n's observations. Term k (in (F, view) order) is
+ * W_k * (r_k / sqrt(r_k^2 + eps^2)), r_k = u - F_k; the terms sit in 64 slots
+ * (slots k >= M hold 0) and are summed pairwise: (t0 + t1) + (t2 + t3), then
+ * those sums pairwise, and so on (M <= 64 views). */
 static real gd_data_grad(const unode *n, real u, real eps2) {
-    real acc = 0;
-    for (int k = 0; k < n->M; ++k) {
-        real r = u - n->F[k];
-        real den = R_SQRT(R_FMA(r, r, eps2));
-        acc = R_FMA(n->W[k], r / den, acc);
+    real t[64];
+    for (int k = 0; k < 64; ++k) {
+        t[k] = 0;
+        if (k < n->M) {
+            real r = u - n->F[k];
+            real den = R_SQRT(R_FMA(r, r, eps2));
+            t[k] = n->W[k] * (r / den);
+        }
     }
-    return acc * n->inv;
+    for (int s = 1; s < 64; s *= 2)
+        for (int k = 0; k < 64; k += 2 * s) t[k] = t[k] + t[k + s];
+    return t[0] * n->inv;
 }
 
 static void set_flags(const orc *o, unode *n) {
@@ -734,7 +742,7 @@ static int restructure(orc *o, real tl) {
 /* Public API (ctypes).                                                      */
 /* ------------------------------------------------------------------------ */
 static int check_params(orc *o, const orc_params *p, int n_views) {
-    if (!p || n_views < 1) return set_err(o, "bad params / n_views"), ORC_E_INVALID;
+    if (!p || n_views < 1 || n_views > 64) return set_err(o, "bad params / n_views (1..64)"), ORC_E_INVALID;
     if (p->max_depth < 1 || p->max_depth > 10) return set_err(o, "max_depth out of 1..10"), ORC_E_INVALID;
     if (!(p->delta > 0) || !(p->eta >= p->delta)) return set_err(o, "need eta >= delta > 0"), ORC_E_INVALID;
     if (!(p->gamma > 0)) return set_err(o, "need gamma > 0"), ORC_E_INVALID;
