@@ -68,6 +68,9 @@ def parse_args():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="thin", choices=["thin", "blocks", "sphere", "batch48"])
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--solver", default="pd", choices=["pd", "gd"],
+                    help="pd: primal-dual on the exact energy; gd: the paper's gradient descent (lambda on TV, "
+                         "step 0.1 halved every 20 iterations, eps 0.3)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="oracle CPU-baseline budget")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -159,7 +162,34 @@ def crop_state(blob: bytes, cube_level: int, M=None, min_leaves: int = 10000):
     return bytes(out), len(cl), best
 
 
-def cpu_baseline(blob: bytes, M, w, budget_s: float):
+GD_LAMBDA, GD_STEP0, GD_EPS, GD_HALVE = 0.5, 0.1, 0.3, 20
+
+
+def gd_step(t: int) -> float:
+    """The paper's schedule: step 0.1 halved every 20 iterations (iteration t from 0)."""
+    return GD_STEP0 * 0.5 ** (t // GD_HALVE)
+
+
+class Stepper:
+    """Runs iterations of the chosen solver on a context (or the oracle),
+    keeping the gradient-descent schedule across calls."""
+
+    def __init__(self, solver: str, w):
+        self.solver, self.w, self.t = solver, w, 0
+
+    def run(self, ctx, n: int):
+        if self.solver == "pd":
+            ctx.fuse(n, self.w.lam, self.w.tau, self.w.sigma)
+            self.t += n
+            return
+        while n > 0:
+            k = min(n, GD_HALVE - self.t % GD_HALVE)
+            ctx.fuse_gd(k, GD_LAMBDA, gd_step(self.t), GD_EPS)
+            self.t += k
+            n -= k
+
+
+def cpu_baseline(blob: bytes, M, w, budget_s: float, solver: str = "pd", t0_iter: int = 0):
     import oracle
 
     for level in (3, 2, 4, 1):
@@ -173,10 +203,12 @@ def cpu_baseline(blob: bytes, M, w, budget_s: float):
     o = oracle.Oracle("f32").import_state(sub)
     t_import = time.perf_counter() - t0
     updates, iters = 0, 0
+    st = Stepper(solver, w)
+    st.t = t0_iter
     t0 = time.perf_counter()
     while True:
         n = o.num_leaves()
-        o.fuse(1, w.lam, w.tau, w.sigma)
+        st.run(o, 1)
         updates += n
         iters += 1
         el = time.perf_counter() - t0
@@ -301,8 +333,9 @@ def main():
     L0 = ctx.num_leaves()
     log(f"[bench] build {build_s:.3f} s, {L0} leaves")
     t0 = time.perf_counter()
+    stepper = Stepper(args.solver, w)
     for k in range(args.warmup):
-        ctx.fuse(1, w.lam, w.tau, w.sigma)
+        stepper.run(ctx, 1)
     torch.cuda.synchronize()
     log(f"[bench] warmup {args.warmup} iterations {time.perf_counter() - t0:.2f} s, {ctx.num_leaves()} leaves, "
         f"last split/join {ctx.last_counts()}")
@@ -317,7 +350,7 @@ def main():
     done = 0
     while done < args.steps:
         n = min(chunk, args.steps - done)
-        ctx.fuse(n, w.lam, w.tau, w.sigma)
+        stepper.run(ctx, n)
         done += n
         log(f"[bench] {done}/{args.steps} iterations, {ctx.num_leaves()} leaves")
     torch.cuda.synchronize()
@@ -334,9 +367,10 @@ def main():
         bytes_per_launch = prof["bytes"][kind] / max(n, 1)
         kern[kind] = dict(avg_ms=avg_ms, bytes=bytes_per_launch, gbs=bytes_per_launch / (avg_ms * 1e-3) / 1e9)
     dom = max(kern, key=lambda k: kern[k]["avg_ms"])
-    ratio = traffic_ratio(f"k_{dom}", f"{w.name}_depth{w.max_depth}")
+    ratio = traffic_ratio(f"k_{dom}", f"{w.name}_depth{w.max_depth}") if args.solver == "pd" else None
+    kname = f"k_{dom}" if args.solver == "pd" else {"dual": "k_dual (flux)", "primal": "k_gd_update"}[dom]
     roofline = {
-        "bound": "hbm", "kernel": f"k_{dom}", "achieved": kern[dom]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "bound": "hbm", "kernel": kname, "achieved": kern[dom]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": kern[dom]["gbs"] / HBM_PEAK_GBS,
         "traffic": None if ratio is None else ratio * kern[dom]["bytes"],
         "traffic_note": ("hardware bytes per launch = profiled FETCH/WRITE-to-algorithmic ratio x this run's "
@@ -354,8 +388,12 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {
             "workload": (f"{w.name}: octree depth {w.max_depth} ({1 << w.max_depth}^3), {w.depth.shape[0]} range "
-                         f"maps {w.depth.shape[2]}x{w.depth.shape[1]}, lambda {w.lam}, tau=sigma=1/sqrt(12), "
-                         f"split/join every iteration, seed {args.seed}"),
+                         f"maps {w.depth.shape[2]}x{w.depth.shape[1]}, "
+                         + (f"primal-dual, lambda {w.lam}, tau=sigma=1/sqrt(12)" if args.solver == "pd" else
+                            f"the paper's gradient descent, lambda {GD_LAMBDA} on TV, step {GD_STEP0} halved every "
+                            f"{GD_HALVE} iterations, eps {GD_EPS}")
+                         + f", split/join every iteration, seed {args.seed}"),
+            "solver": args.solver,
             "leaves_after_build": L0, "leaves_at_end": L1, "mean_leaves_per_step": updates / args.steps,
             "inputs_md5": hashlib.md5(w.depth.tobytes()).hexdigest(),
         },
@@ -366,7 +404,8 @@ def main():
     }
     if blob_for_cpu is not None:
         log("[bench] CPU baseline (oracle) ...")
-        result["cpu_baseline"] = cpu_baseline(blob_for_cpu, M_for_cpu, w, args.cpu_seconds)
+        result["cpu_baseline"] = cpu_baseline(blob_for_cpu, M_for_cpu, w, args.cpu_seconds, args.solver,
+                                              args.warmup)
         log(f"[bench] CPU baseline {result['cpu_baseline']['value']:.4g} leaf-updates/s")
     else:
         result["cpu_baseline"] = None

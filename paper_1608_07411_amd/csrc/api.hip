@@ -403,10 +403,17 @@ otf_status otf_fuse_gd(otf_ctx *ctx, int32_t iterations, float lambda, float ste
         for (int it = 0; it < iterations; ++it) {
             c.iteration++;
             prof_begin(c);
-            launch_gd(c, c.sol.lam, c.sol.xi, c.sol.eps2);
+            launch_gd_flux(c, c.sol.eps2);
+            prof_end(c, kProfDual);
+            prof_begin(c);
+            launch_gd_update(c, c.sol.lam, c.sol.xi, c.sol.eps2);
             prof_end(c, kProfPrimal);
             count_flags(c);
             c.leaf_updates += c.L;
+            // same bytes as the primal-dual sweeps, with W in place of P for every observation
+            c.alg_bytes[0] += dual_bytes(c);
+            c.alg_bytes[1] += primal_bytes(c);
+            accumulate_obs(c, true);
             c.last_splits = c.last_joins = 0;
             if (c.prm.restructure_every > 0 && c.iteration % c.prm.restructure_every == 0) {
                 prof_begin(c);

@@ -215,14 +215,17 @@ void count_obs(Ctx &c) {
 }
 
 namespace {
-__global__ void k_accum_obs(unsigned long long *c) {
-    if (threadIdx.x == 0) c[6] += c[0] + c[1];  // counters [16..17] += [4..5] + [6..7]
+// counters [16..17] += [4..5] + [6..7] (observations read, plus the prefix
+// weights of leaves with fractional weights), or + 2 [4..5] when every
+// observation's weight is read (gradient descent)
+__global__ void k_accum_obs(unsigned long long *c, int all_weights) {
+    if (threadIdx.x == 0) c[6] += c[0] + (all_weights ? c[0] : c[1]);
 }
 }  // namespace
 
-void accumulate_obs(Ctx &c) {
+void accumulate_obs(Ctx &c, bool all_weights) {
     hipLaunchKernelGGL(k_accum_obs, dim3(1), dim3(64), 0, c.stream,
-                       reinterpret_cast<unsigned long long *>(c.counters.p + 4));
+                       reinterpret_cast<unsigned long long *>(c.counters.p + 4), all_weights ? 1 : 0);
 }
 
 // Observation pool for every leaf of the current store, in leaf order.

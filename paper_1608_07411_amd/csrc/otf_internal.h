@@ -367,7 +367,7 @@ void gather_all_leaves(Ctx &c, bool init_values);
 // totals of observations into the device counters (no read-back)
 void count_obs(Ctx &c);
 // add the observation totals to the per-primal accumulator (device)
-void accumulate_obs(Ctx &c);
+void accumulate_obs(Ctx &c, bool all_weights = false);
 // face adjacency of the current leaf store
 void build_neighbours(Ctx &c);
 // Adjacency after a restructure: leaves marked in `need` are searched, the
@@ -377,9 +377,10 @@ void build_neighbours_incremental(Ctx &c, const LeafStore &old, const uint32_t *
 // sweeps
 void launch_dual(Ctx &c, float sigma);
 void launch_primal(Ctx &c, float tau, float tl);
-// one step of the paper's gradient descent: flux sweep, then the update sweep
-// (flags as the primal sweep's)
-void launch_gd(Ctx &c, float lam, float xi, float eps2);
+// one step of the paper's gradient descent: the flux sweep (q = Gu / Gamma),
+// then the update sweep (flags as the primal sweep's)
+void launch_gd_flux(Ctx &c, float eps2);
+void launch_gd_update(Ctx &c, float lam, float xi, float eps2);
 // split and join flag counts of the last primal sweep into counters[0], [1]
 void count_flags(Ctx &c);
 // energy terms in double; eps > 0: the smoothed terms of the gradient-descent energy

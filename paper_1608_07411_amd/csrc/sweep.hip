@@ -500,29 +500,68 @@ __global__ void __launch_bounds__(kBlk) k_primal(PrimalArgs a, Coef cf) {
     block_flag_counts<kBlk>(ns, nj, a.part, a.part_stride, blockIdx.x);
 }
 
-// Gradient descent (the paper's solver): one thread per leaf.
-//   div = ds - sum c' q_m,  d' = (sum_k W_k r_k / sqrt(r_k^2 + eps^2)) inv,
-//   r_k = u - F_k in (F, view) order,  u <- u + xi (lam div - d').
+// Gradient descent (the paper's solver). Divergence per thread, then the
+// data gradient cooperatively as in k_primal: the wave takes its 64 leaves in
+// turn, lane k loads observation k (coalesced) and forms
+//   t_k = W_k (r_k / sqrt(r_k^2 + eps^2)),  r_k = u - F_k  (0 for k >= M),
+// and a butterfly over the 64 lanes sums them pairwise: (t0 + t1) + (t2 + t3)
+// and so on, the same order as a plain pairwise sum over 64 slots. Then
+//   u <- u + xi (lam div - d'),  d' = sum * inv.
 // The divergence is kept (uprime) so that split children take the same step
 // with their own data term.
 __global__ void __launch_bounds__(kBlk) k_gd_update(PrimalArgs a, Coef cf) {
     const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
+    const int lane = threadIdx.x & 63;
     const bool valid = i < a.L;
+    float dv = 0.0f, un = 0.0f;
+    int M = 0, ln = 0;
+    uint32_t oo = 0;
+    if (valid) {
+        ln = a.level[i];
+        un = a.u_in[i];
+        const uint32_t e0 = a.off[i], e1 = a.off[i + 1];
+        dv = (e1 - e0 > kLongList) ? a.ds[i] : divergence(a, cf, e0, e1, ln, a.ds[i]);
+        M = a.obs_m[i];
+        oo = a.obs_off[i];
+    }
+    const int nact = __popcll(__ballot(valid));
+    float mysum = 0.0f;
+    for (int l0 = 0; l0 < nact; l0 += kAhead) {
+        float Fr[kAhead], Wr[kAhead];
+#pragma unroll
+        for (int g = 0; g < kAhead; ++g) {
+            const int l = l0 + g;
+            Fr[g] = 0.0f;
+            Wr[g] = 0.0f;
+            if (l < nact) {
+                const int Ml = rdlane_i(M, l);
+                const uint32_t ool = (uint32_t)rdlane_i((int)oo, l);
+                if (lane < Ml) {
+                    Fr[g] = a.F[ool + lane];
+                    Wr[g] = a.W[ool + lane];
+                }
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < kAhead; ++g) {
+            const int l = l0 + g;
+            if (l >= nact) break;
+            const int Ml = rdlane_i(M, l);
+            const float ul = rdlane(un, l);
+            float t = 0.0f;
+            if (lane < Ml) {
+                const float r = ul - Fr[g];
+                const float den = sqrtf(__fmaf_rn(r, r, a.eps2));
+                t = Wr[g] * (r / den);
+            }
+#pragma unroll
+            for (int sh = 1; sh < 64; sh <<= 1) t = t + __shfl_xor(t, sh, 64);
+            if (lane == l) mysum = t;
+        }
+    }
     bool split = false, join = false;
     if (valid) {
-        const int ln = a.level[i];
-        const float un = a.u_in[i];
-        const uint32_t e0 = a.off[i], e1 = a.off[i + 1];
-        const float dv = (e1 - e0 > kLongList) ? a.ds[i] : divergence(a, cf, e0, e1, ln, a.ds[i]);
-        const int M = a.obs_m[i];
-        const uint32_t oo = a.obs_off[i];
-        float acc = 0.0f;
-        for (int k = 0; k < M; ++k) {
-            const float r = un - a.F[oo + k];
-            const float den = sqrtf(__fmaf_rn(r, r, a.eps2));
-            acc = __fmaf_rn(a.W[oo + k], r / den, acc);
-        }
-        const float dg = acc * a.inv[i];
+        const float dg = mysum * a.inv[i];
         const float v = __fmaf_rn(a.xi, __fmaf_rn(a.lam, dv, -dg), un);
         a.u[i] = v;
         a.ubar[i] = v;
@@ -789,7 +828,7 @@ void launch_primal(Ctx &c, float tau, float tl) {
     OTF_LAUNCH_CHECK("k_primal");
 }
 
-void launch_gd(Ctx &c, float lam, float xi, float eps2) {
+void launch_gd_flux(Ctx &c, float eps2) {
     LeafStore &s = c.lv();
     DualArgs d = dual_args(c, 0.0f);
     d.ubar = s.u.p;  // the flux differences u itself
@@ -802,6 +841,10 @@ void launch_gd(Ctx &c, float lam, float xi, float eps2) {
                            (uint32_t)s.n_heavy_p, s.heavy_p.p, d, c.coef);
         OTF_LAUNCH_CHECK("k_dual_long (flux)");
     }
+}
+
+void launch_gd_update(Ctx &c, float lam, float xi, float eps2) {
+    LeafStore &s = c.lv();
     PrimalArgs a = primal_args(c, 1.0f, 0.0f);
     const int64_t nblk = cdiv(c.L, kBlk);
     c.s.part.reserve(2 * nblk);
