@@ -169,6 +169,36 @@ otf_status otf_profile_read(otf_ctx *ctx, double *ms, int64_t *launches, int64_t
 const char *otf_last_error(const otf_ctx *ctx);
 
 /* ---------------------------------------------------------------------------
+ * Evaluation (Sec. 3.2, the final meshing step; Sec. 4, Eq. 7).
+ * ------------------------------------------------------------------------- */
+
+/* u resampled to the finest grid: out[(z G + y) G + x] = u of the leaf that
+ * contains voxel (x, y, z), G = 2^max_depth. `out` holds `capacity` floats,
+ * on the device if out_is_device (the context's device) else on the host.
+ * Errors: OTF_E_INVALID (null out), OTF_E_STATE, OTF_E_CAPACITY (capacity <
+ * G^3; nothing written). */
+otf_status otf_dense_field(otf_ctx *ctx, float *out, int32_t out_is_device, int64_t capacity);
+
+/* Marching cubes on the finest-grid field at `iso` (0: the fused surface).
+ * Cells join 8 voxel centres; every cell edge whose end values straddle iso
+ * (one below, one not) carries a vertex, linearly interpolated; the cell's
+ * triangles come from a case table derived from face segments (an ambiguous
+ * face separates its inside corners), so the mesh is closed away from the
+ * domain boundary. Triangle t: xyz[9t .. 9t+8] its vertices in world
+ * coordinates, edges[3t .. 3t+2] their grid edges, 3 ((z G + y) G + x) + axis
+ * of the edge's lower voxel (equal ids = the same vertex). Host arrays of
+ * `capacity` triangles; *n_tris = the count. Errors: OTF_E_INVALID,
+ * OTF_E_STATE, OTF_E_CAPACITY (capacity too small or null arrays; *n_tris is
+ * set, nothing copied). Needs 9 bytes of device memory per finest voxel. */
+otf_status otf_mesh(otf_ctx *ctx, float iso, int64_t capacity, float *xyz, uint64_t *edges, int64_t *n_tris);
+
+/* Eq. 7: sum over leaves n of |u(n) - mean of `dense` over the finest voxels
+ * of n|, in double; `dense` is a finest-grid field laid out as in
+ * otf_dense_field (for example a fully refined solve's), on the device if
+ * dense_is_device else on the host. Errors: OTF_E_INVALID, OTF_E_STATE. */
+otf_status otf_quantisation_error(otf_ctx *ctx, const float *dense, int32_t dense_is_device, double *err);
+
+/* ---------------------------------------------------------------------------
  * The paper's own solver (Sec. 3.2, Eq. 4-6): explicit gradient descent to
  * the steady state of the PDE of Eq. 6, on the energy of Eq. 5 with both
  * terms smoothed as in Eq. 4 (Gamma(x^2) = sqrt(x^2 + epsilon^2)) and lambda

@@ -567,6 +567,58 @@ otf_status otf_energy_eps(otf_ctx *ctx, double epsilon, double *tv, double *data
     });
 }
 
+otf_status otf_dense_field(otf_ctx *ctx, float *out, int32_t out_is_device, int64_t capacity) {
+    if (!ctx || !out) return OTF_E_INVALID;
+    if (!ctx->c.valid) return OTF_E_STATE;
+    const int64_t n = int64_t(1) << (3 * ctx->c.prm.max_depth);
+    if (capacity < n) {
+        ctx->c.err = "capacity below (2^max_depth)^3";
+        return OTF_E_CAPACITY;
+    }
+    return guard(ctx, false, [&] {
+        Ctx &c = ctx->c;
+        if (out_is_device) {
+            dense_field(c, out);
+            OTF_HIP(hipStreamSynchronize(c.stream));
+        } else {
+            DBuf<float> d;
+            d.reserve((size_t)n);
+            dense_field(c, d.p);
+            OTF_HIP(hipMemcpyAsync(out, d.p, sizeof(float) * n, hipMemcpyDeviceToHost, c.stream));
+            OTF_HIP(hipStreamSynchronize(c.stream));
+        }
+    });
+}
+
+otf_status otf_mesh(otf_ctx *ctx, float iso, int64_t capacity, float *xyz, uint64_t *edges, int64_t *n_tris) {
+    if (!ctx || !n_tris || capacity < 0 || !std::isfinite(iso)) return OTF_E_INVALID;
+    if (!ctx->c.valid) return OTF_E_STATE;
+    otf_status cap_st = OTF_OK;
+    otf_status st = guard(ctx, false, [&] {
+        const int64_t n = marching_cubes(ctx->c, iso, capacity, xyz, reinterpret_cast<unsigned long long *>(edges));
+        *n_tris = n;
+        if (n > capacity || (n > 0 && (!xyz || !edges))) cap_st = OTF_E_CAPACITY;
+    });
+    return st != OTF_OK ? st : cap_st;
+}
+
+otf_status otf_quantisation_error(otf_ctx *ctx, const float *dense, int32_t dense_is_device, double *err) {
+    if (!ctx || !dense || !err) return OTF_E_INVALID;
+    if (!ctx->c.valid) return OTF_E_STATE;
+    return guard(ctx, false, [&] {
+        Ctx &c = ctx->c;
+        if (dense_is_device) {
+            *err = quantisation_error(c, dense);
+        } else {
+            const int64_t n = int64_t(1) << (3 * c.prm.max_depth);
+            DBuf<float> d;
+            d.reserve((size_t)n);
+            OTF_HIP(hipMemcpyAsync(d.p, dense, sizeof(float) * n, hipMemcpyHostToDevice, c.stream));
+            *err = quantisation_error(c, d.p);
+        }
+    });
+}
+
 otf_status otf_export_state(const otf_ctx *cctx, void *buf, int64_t cap, int64_t *n_bytes) {
     otf_ctx *ctx = const_cast<otf_ctx *>(cctx);
     if (!ctx || !n_bytes || cap < 0) return OTF_E_INVALID;

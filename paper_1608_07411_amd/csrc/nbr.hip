@@ -28,43 +28,9 @@ namespace {
 constexpr int kBlk = 256;
 constexpr uint32_t kLight = 32;  // longest range scanned by a single thread
 
-__device__ inline int64_t find_leaf(const uint32_t *__restrict__ key, int64_t L, uint32_t k) {
-    // largest i with key[i] <= k (key[0] == 0)
-    int64_t lo = 0, hi = L;
-    while (hi - lo > 1) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (key[mid] <= k) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
-
-// Bucket index over the key space: table[b] = the leaf containing the first
-// point of bucket b, so a lookup only searches between two table entries.
-struct KeyIndex {
-    const uint32_t *key;
-    int64_t L;
-    const uint32_t *table;
-    int shift;
-    uint32_t nb;
-};
-
 __global__ void k_key_table(const uint32_t *key, int64_t L, int shift, uint32_t nb, uint32_t *table) {
     const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b < nb) table[b] = (uint32_t)find_leaf(key, L, b << shift);
-}
-
-// largest i with key[i] <= k
-__device__ inline int64_t find_leaf(const KeyIndex &ki, uint32_t k) {
-    const uint32_t b = k >> ki.shift;
-    int64_t lo = ki.table[b];
-    int64_t hi = (b + 1 < ki.nb) ? (int64_t)ki.table[b + 1] + 1 : ki.L;
-    while (hi - lo > 1) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (ki.key[mid] <= k) lo = mid;
-        else hi = mid;
-    }
-    return lo;
 }
 
 // first i with key[i] >= k (k may be the end of the domain)

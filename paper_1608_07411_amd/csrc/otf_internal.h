@@ -103,6 +103,45 @@ __host__ __device__ inline void demorton3(uint32_t k, uint32_t &x, uint32_t &y, 
     z = compact1by2(k >> 2);
 }
 
+// Leaf lookup in the Morton-sorted key array: largest i with key[i] <= k
+// (key[0] == 0).
+__device__ inline int64_t find_leaf(const uint32_t *__restrict__ key, int64_t L, uint32_t k) {
+    int64_t lo = 0, hi = L;
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (key[mid] <= k) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Bucket index over the key space: table[b] = the leaf containing the first
+// point of bucket b (buckets of 2^shift keys), so a lookup only searches
+// between two table entries. Built for the current store by the adjacency
+// build (Scratch::key_table); key_table_shift gives its bucket size.
+struct KeyIndex {
+    const uint32_t *key;
+    int64_t L;
+    const uint32_t *table;
+    int shift;
+    uint32_t nb;
+};
+
+inline int key_table_shift(int D) { return 3 * D > 20 ? 3 * D - 20 : 0; }
+
+// largest i with key[i] <= k
+__device__ inline int64_t find_leaf(const KeyIndex &ki, uint32_t k) {
+    const uint32_t b = k >> ki.shift;
+    int64_t lo = ki.table[b];
+    int64_t hi = (b + 1 < ki.nb) ? (int64_t)ki.table[b + 1] + 1 : ki.L;
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (ki.key[mid] <= k) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
 // Coupling coefficients by level pair, one correctly rounded division of exact
 // operands each: c[ln][lk] for the gradient of leaf n toward its + neighbour k,
 // cp[lm][ln] for the divergence of leaf n from its - neighbour m.
@@ -255,6 +294,7 @@ struct Scratch {
     DBuf<uint32_t> key_table;                           // bucket index over leaf keys
     DBuf<uint32_t> dirty;                               // leaves whose adjacency is searched again
     DBuf<uint32_t> part;                                // per-block partial counts
+    DBuf<unsigned char> mc_table;                       // marching-cubes case table (device)
     // restructure temporaries (grow-only: an allocation or free per iteration
     // would synchronise the device)
     DBuf<uint8_t> r_sf, r_tM, r_tU, r_isnew, r_Mt;
@@ -383,6 +423,13 @@ void launch_gd_flux(Ctx &c, float eps2);
 void launch_gd_update(Ctx &c, float lam, float xi, float eps2);
 // split and join flag counts of the last primal sweep into counters[0], [1]
 void count_flags(Ctx &c);
+// evaluation (meshing and Eq. 7): the finest-grid field of u (G^3 floats,
+// index (z G + y) G + x); the marching-cubes mesh at iso (returns the triangle
+// count; copies to the host arrays when they hold cap triangles); the
+// quantisation error against a finest-grid field on the device
+void dense_field(Ctx &c, float *dense);
+int64_t marching_cubes(Ctx &c, float iso, int64_t cap, float *h_xyz, unsigned long long *h_edge);
+double quantisation_error(Ctx &c, const float *dense_dev);
 // energy terms in double; eps > 0: the smoothed terms of the gradient-descent energy
 void energy(Ctx &c, double *tv, double *data, double eps = 0.0);
 // split / join; returns true when the structure changed

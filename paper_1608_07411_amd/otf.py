@@ -54,6 +54,9 @@ def lib():
             "otf_extract_neighbours": [P, I64, P, I64, P, P],
             "otf_energy": [P, P, P],
             "otf_fuse_gd": [P, I32, C.c_float, C.c_float, C.c_float],
+            "otf_dense_field": [P, P, I32, I64],
+            "otf_mesh": [P, C.c_float, I64, P, P, P],
+            "otf_quantisation_error": [P, P, I32, P],
             "otf_energy_eps": [P, C.c_double, P, P],
             "otf_last_counts": [P, P, P],
             "otf_export_state": [P, P, I64, P],
@@ -107,6 +110,7 @@ class Context:
     def __init__(self, device: int = 0, stream=None):
         self._lib = lib()
         self.h = C.c_void_p()
+        self._D = None
         self._check(self._lib.otf_create(device, _stream_handle(stream), C.byref(self.h)), "otf_create")
 
     def close(self):
@@ -145,11 +149,13 @@ class Context:
         n_views = int(keep.shape[0])
         self._check(self._lib.otf_build_octree(self.h, ptr, is_dev, n_views, _ptr(cams), _ptr(prm)),
                     "otf_build_octree")
+        self._D = int(prm["max_depth"])
         return self
 
     def import_state(self, blob: bytes):
         buf = np.frombuffer(blob, dtype=np.uint8).copy()
         self._check(self._lib.otf_import_state(self.h, _ptr(buf), buf.size), "otf_import_state")
+        self._D = int(np.frombuffer(blob, dtype="<i4", count=1, offset=8)[0])
         return self
 
     def export_state(self) -> bytes:
@@ -174,6 +180,46 @@ class Context:
         tv, data = C.c_double(0), C.c_double(0)
         self._check(self._lib.otf_energy_eps(self.h, float(eps), C.byref(tv), C.byref(data)), "otf_energy_eps")
         return tv.value, data.value
+
+    def dense_field(self, out=None):
+        """u on the finest grid as a (G, G, G) [z, y, x] float32 array (or into a
+        contiguous CUDA float tensor `out`)."""
+        G = 1 << self.max_depth()
+        if out is not None and hasattr(out, "is_cuda") and out.is_cuda:
+            self._check(self._lib.otf_dense_field(self.h, C.c_void_p(out.data_ptr()), 1, out.numel()),
+                        "otf_dense_field")
+            return out
+        a = np.zeros((G, G, G), np.float32)
+        self._check(self._lib.otf_dense_field(self.h, _ptr(a), 0, a.size), "otf_dense_field")
+        return a
+
+    def mesh(self, iso: float = 0.0):
+        """Marching-cubes triangles: (T, 3, 3) float32 vertices and (T, 3) uint64 edge ids."""
+        n = C.c_int64(0)
+        st = self._lib.otf_mesh(self.h, iso, 0, None, None, C.byref(n))
+        if st not in (0, 3):
+            self._check(st, "otf_mesh")
+        xyz = np.zeros((max(n.value, 1), 3, 3), np.float32)
+        ed = np.zeros((max(n.value, 1), 3), np.uint64)
+        if n.value > 0:
+            self._check(self._lib.otf_mesh(self.h, iso, n.value, _ptr(xyz), _ptr(ed), C.byref(n)), "otf_mesh")
+        return xyz[:n.value], ed[:n.value]
+
+    def quantisation_error(self, dense) -> float:
+        """Eq. 7 against a finest-grid field (numpy array or CUDA tensor)."""
+        err = C.c_double(0)
+        if hasattr(dense, "is_cuda") and dense.is_cuda:
+            st = self._lib.otf_quantisation_error(self.h, C.c_void_p(dense.data_ptr()), 1, C.byref(err))
+        else:
+            d = np.ascontiguousarray(dense, dtype=np.float32)
+            st = self._lib.otf_quantisation_error(self.h, _ptr(d), 0, C.byref(err))
+        self._check(st, "otf_quantisation_error")
+        return err.value
+
+    def max_depth(self) -> int:
+        if self._D is None:
+            raise OtfError(5, "no octree built or imported")
+        return self._D
 
     def num_leaves(self) -> int:
         n = C.c_int64(0)
