@@ -199,6 +199,52 @@ otf_status otf_mesh(otf_ctx *ctx, float iso, int64_t capacity, float *xyz, uint6
 otf_status otf_quantisation_error(otf_ctx *ctx, const float *dense, int32_t dense_is_device, double *err);
 
 /* ---------------------------------------------------------------------------
+ * Learned warm start, for callers that fuse many similar scenes: a per-leaf
+ * network predicts the converged u and p of the primal-dual iteration
+ * (Sec. 3.2) from each leaf's sorted observations (Fig. 4 fetch) and its
+ * face neighbours, and the iteration starts from that prediction.
+ *
+ * Network: 32 features -> 128 -> 128 -> 128 -> 4 outputs (u, px, py, pz),
+ * ReLU on hidden layers; bfloat16 weights and activations (fp32 rounded to
+ * nearest, ties to even), fp32 accumulation on the matrix cores, fp32 biases
+ * and master weights; loss: mean squared error over rows and outputs;
+ * optimiser: Adam (beta 0.9, 0.999, eps 1e-8). Parameters: per layer W (in x
+ * out, row-major) then b, otf_mlp_num_params() floats.
+ * Features of a leaf: 16 quantiles F[floor((2k+1) M / 32)] of its sorted
+ * observations (0 if M = 0), the mean u of its neighbours across each face
+ * (+x, +y, +z, -x, -y, -z; 0 without neighbours), u, W/(W + gamma), M/64,
+ * level/max_depth, then zeros.
+ * Device arrays below are on the network's (context's) device, row-major.
+ * ------------------------------------------------------------------------- */
+typedef struct otf_mlp otf_mlp;
+
+/* Create a network (parameters 0) on `device` and `hip_stream` (borrowed). */
+otf_status otf_mlp_create(int device, void *hip_stream, otf_mlp **out);
+otf_status otf_mlp_destroy(otf_mlp *net);
+int64_t otf_mlp_num_params(void);
+/* Host fp32 parameter vector of exactly otf_mlp_num_params() floats; setting
+ * resets the optimiser state. Errors: OTF_E_INVALID (null or wrong size). */
+otf_status otf_mlp_set_params(otf_mlp *net, const float *params, int64_t n);
+otf_status otf_mlp_get_params(otf_mlp *net, float *params, int64_t n);
+/* Y (rows x 4, device) = network(X (rows x 32, device)). */
+otf_status otf_mlp_forward(otf_mlp *net, const float *X, int64_t rows, float *Y);
+/* Loss against T (rows x 4, device) and its gradient (host, num_params
+ * floats, may be null); parameters unchanged. */
+otf_status otf_mlp_gradient(otf_mlp *net, const float *X, const float *T, int64_t rows, float *grad, double *loss);
+/* One Adam step with learning rate lr > 0 on the loss over these rows. */
+otf_status otf_mlp_train_step(otf_mlp *net, const float *X, const float *T, int64_t rows, float lr, double *loss);
+const char *otf_mlp_last_error(const otf_mlp *net);
+/* Features (L x 32) and current (u, px, py, pz) (L x 4) of the context's
+ * leaves into device arrays of cap_rows rows. Errors: OTF_E_INVALID,
+ * OTF_E_STATE, OTF_E_CAPACITY (cap_rows < leaves). */
+otf_status otf_features(otf_ctx *ctx, float *X, int64_t cap_rows);
+otf_status otf_leaf_targets(otf_ctx *ctx, float *T, int64_t cap_rows);
+/* u, ubar and p of every leaf set from the network's prediction (p
+ * projected onto the unit ball). The network must use the context's device
+ * and stream (else OTF_E_INVALID). */
+otf_status otf_warm_start(otf_ctx *ctx, otf_mlp *net);
+
+/* ---------------------------------------------------------------------------
  * The paper's own solver (Sec. 3.2, Eq. 4-6): explicit gradient descent to
  * the steady state of the PDE of Eq. 6, on the energy of Eq. 5 with both
  * terms smoothed as in Eq. 4 (Gamma(x^2) = sqrt(x^2 + epsilon^2)) and lambda

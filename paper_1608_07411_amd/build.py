@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 OBJDIR = os.path.join(HERE, "lib", "obj")
 LIB = os.path.join(LIBDIR, "libotf.so")
-SOURCES = ["api.hip", "batch.hip", "build.hip", "gather.hip", "mesh.hip", "nbr.hip", "restructure.hip", "scan.hip", "sweep.hip"]
+SOURCES = ["api.hip", "batch.hip", "build.hip", "gather.hip", "mesh.hip", "mlp.hip", "nbr.hip", "restructure.hip", "scan.hip", "sweep.hip"]
 
 ARCH = os.environ.get("OTF_OFFLOAD_ARCH", "gfx950")
 HIPCC_FLAGS = [

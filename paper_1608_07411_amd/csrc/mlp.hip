@@ -1,0 +1,507 @@
+// Learned warm start: a per-leaf network predicts the converged fused value
+// u and dual p of every leaf from the leaf's sorted observations and its
+// neighbourhood, so that the primal-dual iteration (Sec. 3.2) starts closer
+// to its solution.
+//
+// Network: 32 features -> 128 -> 128 -> 128 -> 4 (u, px, py, pz), ReLU on the
+// hidden layers. Weights and activations are bfloat16, products accumulate in
+// fp32 on the matrix cores (v_mfma_f32_16x16x16 bf16), biases and the master
+// weights (Adam) are fp32. Parameter vector: per layer W (in x out,
+// row-major) then b.
+//
+// Features of a leaf: 16 quantiles of its observations (they are stored
+// sorted by F), the mean u of its neighbours across each of the 6 faces, its
+// u, its normalised weight sum W/(W + gamma), M/64, level/max_depth, zeros.
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "otf_internal.h"
+
+namespace otf {
+namespace {
+
+constexpr int kBlk = 256;
+constexpr int kIn = 32, kHid = 128, kOut = 4, kLayers = 4;
+constexpr int kSizes[kLayers + 1] = {kIn, kHid, kHid, kHid, kOut};
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // nearest, ties to even
+    return (uint16_t)(u >> 16);
+}
+__device__ inline float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// C(m, n) = sum_k A(m, k) B(k, n); A(m, k) = A[m sam + k sak], B(k, n) =
+// B[k sbk + n sbn] (the strides express transposes). A wave computes one
+// 16x16 tile with MFMA, 4 waves per block along n. With gridDim.z > 1 the
+// k range is split: block z writes its partial sum to C + z M N and
+// k_sum_splits adds them. Epilogue (one split): + bias[n], then ReLU, or the
+// ReLU mask of a stored activation (v = mask(m, n) > 0 ? v : 0); fp32 to C
+// and/or bf16 to Cb (row-major M x N).
+__global__ void __launch_bounds__(kBlk) k_gemm(int M, int N, int64_t K, const uint16_t *A, int64_t sam, int64_t sak,
+                                               const uint16_t *B, int64_t sbk, int64_t sbn, float *C, uint16_t *Cb,
+                                               int64_t kchunk, const float *bias, int relu, const uint16_t *mask) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int m0 = blockIdx.x * 16, n0 = (blockIdx.y * 4 + w) * 16;
+    if (n0 >= N) return;  // whole wave
+    const int64_t kb = (int64_t)blockIdx.z * kchunk, ke = min(K, kb + kchunk);
+    const int mr = m0 + (lane & 15), nc = n0 + (lane & 15), kq = 4 * (lane >> 4);
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int64_t k0 = kb; k0 < ke; k0 += 16) {
+        bf16x4 a, b;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t k = k0 + kq + j;
+            a[j] = (mr < M && k < ke) ? (short)A[mr * sam + k * sak] : (short)0;
+            b[j] = (nc < N && k < ke) ? (short)B[k * sbk + nc * sbn] : (short)0;
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = m0 + kq + r;
+        if (row >= M || nc >= N) continue;
+        float v = acc[r];
+        if (gridDim.z > 1) {
+            C[(int64_t)blockIdx.z * M * N + (int64_t)row * N + nc] = v;
+            continue;
+        }
+        if (bias) v = v + bias[nc];
+        if (relu) v = fmaxf(v, 0.0f);
+        if (mask && !(bf2f(mask[(int64_t)row * N + nc]) > 0.0f)) v = 0.0f;
+        if (C) C[(int64_t)row * N + nc] = v;
+        if (Cb) Cb[(int64_t)row * N + nc] = f2bf(v);
+    }
+}
+
+__global__ void k_sum_splits(const float *part, int splits, int64_t n, float *out) {
+    const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.0f;
+    for (int z = 0; z < splits; ++z) s = s + part[(int64_t)z * n + i];
+    out[i] = s;
+}
+
+// per-block column sums of a bf16 matrix (rows x N, N <= kBlk) in row order
+__global__ void k_colsum(const uint16_t *Z, int64_t rows, int N, int64_t chunk, float *part) {
+    const int t = threadIdx.x;
+    if (t >= N) return;
+    const int64_t r0 = (int64_t)blockIdx.x * chunk, r1 = min(rows, r0 + chunk);
+    float s = 0.0f;
+    for (int64_t r = r0; r < r1; ++r) s = s + bf2f(Z[r * N + t]);
+    part[(int64_t)blockIdx.x * N + t] = s;
+}
+
+__global__ void k_to_bf16(const float *x, int64_t n, uint16_t *y) {
+    const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
+    if (i < n) y[i] = f2bf(x[i]);
+}
+
+// dZ = bf16(2 (Y - T) / (rows * kOut)); per-block sums of (Y - T)^2 in double
+__global__ void k_mse(const float *Y, const float *T, int64_t n, float scale, uint16_t *dZ, double *part) {
+    __shared__ double red[kBlk];
+    const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
+    double sq = 0.0;
+    if (i < n) {
+        const float d = Y[i] - T[i];
+        dZ[i] = f2bf(scale * d);
+        sq = (double)d * (double)d;
+    }
+    red[threadIdx.x] = sq;
+    __syncthreads();
+    for (int s = kBlk / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_adam(float *w, float *m, float *v, const float *g, int64_t n, float lr, float b1, float b2,
+                       float c1, float c2, float eps) {
+    const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// features of leaf i (row i of X, 32 floats)
+__global__ void k_features(int64_t L, int D, float gamma, const uint8_t *level, const float *u,
+                           const uint32_t *obs_off, const uint8_t *obs_m, const float *wtot, const float *F,
+                           const uint32_t *offp, const uint32_t *entp, const uint32_t *offm, const uint32_t *entm,
+                           float *X) {
+    const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
+    if (i >= L) return;
+    float *x = X + i * kIn;
+    const int M = obs_m[i];
+    const uint32_t oo = obs_off[i];
+    for (int k = 0; k < 16; ++k) x[k] = M > 0 ? F[oo + (uint32_t)(((2 * k + 1) * M) / 32)] : 0.0f;
+    for (int side = 0; side < 2; ++side) {
+        const uint32_t *off = side ? offm : offp, *ent = side ? entm : entp;
+        float s[3] = {0.0f, 0.0f, 0.0f};
+        int n[3] = {0, 0, 0};
+        for (uint32_t e = off[i]; e < off[i + 1]; ++e) {
+            const uint32_t v = ent[e];
+            const int d = (v >> kIdxBits) & 3;
+            s[d] = s[d] + u[v & kIdxMask];
+            n[d] += 1;
+        }
+        for (int d = 0; d < 3; ++d) x[16 + 3 * side + d] = n[d] ? s[d] / (float)n[d] : 0.0f;
+    }
+    x[22] = u[i];
+    x[23] = wtot[i] / (wtot[i] + gamma);
+    x[24] = (float)M / 64.0f;
+    x[25] = (float)level[i] / (float)D;
+    for (int k = 26; k < kIn; ++k) x[k] = 0.0f;
+}
+
+// leaf targets / warm start: rows (u, px, py, pz)
+__global__ void k_targets(int64_t L, int64_t cap, const float *u, const float *p, float *T) {
+    const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
+    if (i >= L) return;
+    T[4 * i] = u[i];
+    T[4 * i + 1] = p[i];
+    T[4 * i + 2] = p[cap + i];
+    T[4 * i + 3] = p[2 * cap + i];
+}
+
+// the predicted u (ubar = u) and p, p projected onto the unit ball as the
+// dual constraint requires
+__global__ void k_apply_warm(int64_t L, int64_t cap, const float *Y, float *u, float *ubar, float *p) {
+    const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
+    if (i >= L) return;
+    const float v = Y[4 * i];
+    u[i] = v;
+    ubar[i] = v;
+    float q[3] = {Y[4 * i + 1], Y[4 * i + 2], Y[4 * i + 3]};
+    const float r2 = __fmaf_rn(q[0], q[0], __fmaf_rn(q[1], q[1], q[2] * q[2]));
+    if (r2 > 1.0f) {
+        const float nrm = sqrtf(r2);
+        for (int d = 0; d < 3; ++d) q[d] = q[d] / nrm;
+    }
+    for (int d = 0; d < 3; ++d) p[(int64_t)d * cap + i] = q[d];
+}
+
+unsigned g1(int64_t n) { return (unsigned)cdiv(n > 0 ? n : 1, kBlk); }
+
+}  // namespace
+
+struct Mlp {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int64_t n_params = 0;
+    int64_t off_w[kLayers], off_b[kLayers];
+    DBuf<float> theta, m, v, grad, Y, part;
+    DBuf<double> lpart;
+    DBuf<uint16_t> wbf, X, H[kLayers], dZ, dZ2;
+    DBuf<float> dH;
+    int64_t step = 0;
+    std::string err;
+
+    Mlp() {
+        int64_t at = 0;
+        for (int l = 0; l < kLayers; ++l) {
+            off_w[l] = at;
+            at += (int64_t)kSizes[l] * kSizes[l + 1];
+            off_b[l] = at;
+            at += kSizes[l + 1];
+        }
+        n_params = at;
+    }
+
+    void sync_bf16() {
+        hipLaunchKernelGGL(k_to_bf16, dim3(g1(n_params)), dim3(kBlk), 0, stream, theta.p, n_params, wbf.p);
+        OTF_LAUNCH_CHECK("k_to_bf16");
+    }
+
+    // C = A B with the epilogue of k_gemm; split over k when K is long
+    void gemm(int M, int N, int64_t K, const uint16_t *A, int64_t sam, int64_t sak, const uint16_t *B, int64_t sbk,
+              int64_t sbn, float *C, uint16_t *Cb, const float *bias, int relu, const uint16_t *mask) {
+        const unsigned gx = (unsigned)cdiv(M, 16), gy = (unsigned)cdiv(N, 64);
+        int splits = 1;
+        if ((int64_t)gx * gy < 256 && K > 4096) splits = (int)std::min<int64_t>(512, cdiv(K, 2048));
+        if (splits == 1) {
+            hipLaunchKernelGGL(k_gemm, dim3(gx, gy, 1), dim3(kBlk), 0, stream, M, N, K, A, sam, sak, B, sbk, sbn, C, Cb,
+                               K, bias, relu, mask);
+            OTF_LAUNCH_CHECK("k_gemm");
+            return;
+        }
+        const int64_t chunk = ((cdiv(K, splits) + 15) / 16) * 16;
+        splits = (int)cdiv(K, chunk);
+        part.reserve((size_t)splits * M * N);
+        hipLaunchKernelGGL(k_gemm, dim3(gx, gy, (unsigned)splits), dim3(kBlk), 0, stream, M, N, K, A, sam, sak, B, sbk,
+                           sbn, part.p, (uint16_t *)nullptr, chunk, (const float *)nullptr, 0,
+                           (const uint16_t *)nullptr);
+        OTF_LAUNCH_CHECK("k_gemm split");
+        hipLaunchKernelGGL(k_sum_splits, dim3(g1((int64_t)M * N)), dim3(kBlk), 0, stream, part.p, splits,
+                           (int64_t)M * N, C);
+        OTF_LAUNCH_CHECK("k_sum_splits");
+    }
+
+    // forward of `rows` feature rows (device fp32, rows x 32) to Y (rows x 4)
+    void forward(const float *Xf, int64_t rows, float *Yout) {
+        X.reserve((size_t)rows * kIn);
+        hipLaunchKernelGGL(k_to_bf16, dim3(g1(rows * kIn)), dim3(kBlk), 0, stream, Xf, rows * kIn, X.p);
+        OTF_LAUNCH_CHECK("features to bf16");
+        const uint16_t *h = X.p;
+        for (int l = 0; l < kLayers; ++l) {
+            const int in = kSizes[l], out = kSizes[l + 1];
+            const bool last = l == kLayers - 1;
+            if (!last) H[l].reserve((size_t)rows * out);
+            gemm((int)rows, out, in, h, in, 1, wbf.p + off_w[l], out, 1, last ? Yout : nullptr,
+                 last ? nullptr : H[l].p, theta.p + off_b[l], last ? 0 : 1, nullptr);
+            if (!last) h = H[l].p;
+        }
+    }
+
+    // loss and gradient (grad) of the mean squared error against T (rows x 4)
+    double backward(const float *Xf, const float *T, int64_t rows) {
+        Y.reserve((size_t)rows * kOut);
+        forward(Xf, rows, Y.p);
+        grad.reserve((size_t)n_params);
+        dZ.reserve((size_t)rows * kHid);
+        dZ2.reserve((size_t)rows * kHid);
+        dH.reserve((size_t)rows * kHid);
+        const int64_t n = rows * kOut;
+        const int64_t nb = (int64_t)g1(n);
+        lpart.reserve((size_t)nb);
+        hipLaunchKernelGGL(k_mse, dim3((unsigned)nb), dim3(kBlk), 0, stream, Y.p, T, n, 2.0f / (float)n, dZ.p, lpart.p);
+        OTF_LAUNCH_CHECK("k_mse");
+        uint16_t *dz = dZ.p, *dzn = dZ2.p;
+        for (int l = kLayers - 1; l >= 0; --l) {
+            const int in = kSizes[l], out = kSizes[l + 1];
+            const uint16_t *hin = l == 0 ? X.p : H[l - 1].p;
+            // dW = H_in^T dZ (in x out), reduced over the rows
+            gemm(in, out, rows, hin, 1, in, dz, out, 1, grad.p + off_w[l], nullptr, nullptr, 0, nullptr);
+            // db = column sums of dZ
+            const int64_t chunk = 4096, nbk = cdiv(rows, chunk);
+            part.reserve((size_t)std::max<int64_t>(nbk * out, 1));
+            hipLaunchKernelGGL(k_colsum, dim3((unsigned)nbk), dim3(kBlk), 0, stream, dz, rows, out, chunk, part.p);
+            OTF_LAUNCH_CHECK("k_colsum");
+            hipLaunchKernelGGL(k_sum_splits, dim3(g1(out)), dim3(kBlk), 0, stream, part.p, (int)nbk, (int64_t)out,
+                               grad.p + off_b[l]);
+            OTF_LAUNCH_CHECK("bias gradient");
+            if (l > 0) {
+                // dZ_prev = mask(H_in) (dZ W^T), rows x in
+                gemm((int)rows, in, out, dz, out, 1, wbf.p + off_w[l], 1, out, nullptr, dzn, nullptr, 0, hin);
+                std::swap(dz, dzn);
+            }
+        }
+        std::vector<double> h((size_t)nb);
+        OTF_HIP(hipMemcpyAsync(h.data(), lpart.p, sizeof(double) * nb, hipMemcpyDeviceToHost, stream));
+        OTF_HIP(hipStreamSynchronize(stream));
+        double s = 0.0;
+        for (double x : h) s += x;
+        return s / (double)n;
+    }
+};
+
+}  // namespace otf
+
+struct otf_mlp {
+    otf::Mlp m;
+};
+
+using namespace otf;
+
+namespace {
+template <class F>
+otf_status mguard(otf_mlp *nn, F &&f) {
+    if (hipSetDevice(nn->m.device) != hipSuccess) {
+        (void)hipGetLastError();
+        nn->m.err = "hipSetDevice failed";
+        return OTF_E_DEVICE;
+    }
+    try {
+        f();
+        nn->m.err.clear();
+        return OTF_OK;
+    } catch (const Failure &e) {
+        nn->m.err = e.msg;
+        return e.st;
+    } catch (...) {
+        nn->m.err = "unexpected failure";
+        return OTF_E_DEVICE;
+    }
+}
+}  // namespace
+
+extern "C" {
+
+otf_status otf_mlp_create(int device, void *hip_stream, otf_mlp **out) {
+    if (!out) return OTF_E_INVALID;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+        (void)hipGetLastError();
+        return OTF_E_INVALID;
+    }
+    otf_mlp *nn = new (std::nothrow) otf_mlp();
+    if (!nn) return OTF_E_NOMEM;
+    nn->m.device = device;
+    nn->m.stream = (hipStream_t)hip_stream;
+    otf_status st = mguard(nn, [&] {
+        Mlp &m = nn->m;
+        m.theta.reserve(m.n_params);
+        m.m.reserve(m.n_params);
+        m.v.reserve(m.n_params);
+        m.wbf.reserve(m.n_params);
+        OTF_HIP(hipMemsetAsync(m.theta.p, 0, sizeof(float) * m.n_params, m.stream));
+        OTF_HIP(hipMemsetAsync(m.m.p, 0, sizeof(float) * m.n_params, m.stream));
+        OTF_HIP(hipMemsetAsync(m.v.p, 0, sizeof(float) * m.n_params, m.stream));
+        m.sync_bf16();
+        OTF_HIP(hipStreamSynchronize(m.stream));
+    });
+    if (st != OTF_OK) {
+        delete nn;
+        return st;
+    }
+    *out = nn;
+    return OTF_OK;
+}
+
+otf_status otf_mlp_destroy(otf_mlp *nn) {
+    if (!nn) return OTF_E_INVALID;
+    (void)hipSetDevice(nn->m.device);
+    (void)hipStreamSynchronize(nn->m.stream);
+    delete nn;
+    return OTF_OK;
+}
+
+int64_t otf_mlp_num_params(void) { return Mlp().n_params; }
+
+otf_status otf_mlp_set_params(otf_mlp *nn, const float *params, int64_t n) {
+    if (!nn || !params || n != nn->m.n_params) return OTF_E_INVALID;
+    return mguard(nn, [&] {
+        Mlp &m = nn->m;
+        OTF_HIP(hipMemcpyAsync(m.theta.p, params, sizeof(float) * n, hipMemcpyHostToDevice, m.stream));
+        OTF_HIP(hipMemsetAsync(m.m.p, 0, sizeof(float) * n, m.stream));
+        OTF_HIP(hipMemsetAsync(m.v.p, 0, sizeof(float) * n, m.stream));
+        m.step = 0;
+        m.sync_bf16();
+        OTF_HIP(hipStreamSynchronize(m.stream));
+    });
+}
+
+otf_status otf_mlp_get_params(otf_mlp *nn, float *params, int64_t n) {
+    if (!nn || !params || n != nn->m.n_params) return OTF_E_INVALID;
+    return mguard(nn, [&] {
+        Mlp &m = nn->m;
+        OTF_HIP(hipMemcpyAsync(params, m.theta.p, sizeof(float) * n, hipMemcpyDeviceToHost, m.stream));
+        OTF_HIP(hipStreamSynchronize(m.stream));
+    });
+}
+
+otf_status otf_mlp_forward(otf_mlp *nn, const float *X, int64_t rows, float *Y) {
+    if (!nn || !X || !Y || rows < 1) return OTF_E_INVALID;
+    return mguard(nn, [&] {
+        nn->m.forward(X, rows, Y);
+        OTF_HIP(hipStreamSynchronize(nn->m.stream));
+    });
+}
+
+otf_status otf_mlp_gradient(otf_mlp *nn, const float *X, const float *T, int64_t rows, float *grad, double *loss) {
+    if (!nn || !X || !T || rows < 1) return OTF_E_INVALID;
+    return mguard(nn, [&] {
+        Mlp &m = nn->m;
+        const double l = m.backward(X, T, rows);
+        if (loss) *loss = l;
+        if (grad) {
+            OTF_HIP(hipMemcpyAsync(grad, m.grad.p, sizeof(float) * m.n_params, hipMemcpyDeviceToHost, m.stream));
+            OTF_HIP(hipStreamSynchronize(m.stream));
+        }
+    });
+}
+
+otf_status otf_mlp_train_step(otf_mlp *nn, const float *X, const float *T, int64_t rows, float lr, double *loss) {
+    if (!nn || !X || !T || rows < 1 || !std::isfinite(lr) || !(lr > 0.0f)) return OTF_E_INVALID;
+    return mguard(nn, [&] {
+        Mlp &m = nn->m;
+        const double l = m.backward(X, T, rows);
+        if (loss) *loss = l;
+        m.step += 1;
+        const float b1 = 0.9f, b2 = 0.999f;
+        const float c1 = 1.0f - std::pow(b1, (float)m.step), c2 = 1.0f - std::pow(b2, (float)m.step);
+        hipLaunchKernelGGL(k_adam, dim3(g1(m.n_params)), dim3(kBlk), 0, m.stream, m.theta.p, m.m.p, m.v.p, m.grad.p,
+                           m.n_params, lr, b1, b2, c1, c2, 1e-8f);
+        OTF_LAUNCH_CHECK("k_adam");
+        m.sync_bf16();
+    });
+}
+
+const char *otf_mlp_last_error(const otf_mlp *nn) { return nn ? nn->m.err.c_str() : "null network"; }
+
+otf_status otf_features(otf_ctx *ctx, float *X, int64_t cap_rows) {
+    if (!ctx || !X) return OTF_E_INVALID;
+    if (!ctx->c.valid) return OTF_E_STATE;
+    if (cap_rows < ctx->c.L) return OTF_E_CAPACITY;
+    Ctx &c = ctx->c;
+    try {
+        OTF_HIP(hipSetDevice(c.device));
+        LeafStore &s = c.lv();
+        hipLaunchKernelGGL(k_features, dim3(g1(c.L)), dim3(kBlk), 0, c.stream, c.L, c.prm.max_depth, c.prm.gamma,
+                           s.level.p, s.u.p, s.obs_off.p, s.obs_m.p, s.wtot.p, c.op().F.p, s.nbp_off.p, s.nbp.p,
+                           s.nbm_off.p, s.nbm.p, X);
+        OTF_LAUNCH_CHECK("k_features");
+        OTF_HIP(hipStreamSynchronize(c.stream));
+    } catch (const Failure &e) {
+        c.err = e.msg;
+        return e.st;
+    }
+    return OTF_OK;
+}
+
+otf_status otf_leaf_targets(otf_ctx *ctx, float *T, int64_t cap_rows) {
+    if (!ctx || !T) return OTF_E_INVALID;
+    if (!ctx->c.valid) return OTF_E_STATE;
+    if (cap_rows < ctx->c.L) return OTF_E_CAPACITY;
+    Ctx &c = ctx->c;
+    try {
+        OTF_HIP(hipSetDevice(c.device));
+        LeafStore &s = c.lv();
+        hipLaunchKernelGGL(k_targets, dim3(g1(c.L)), dim3(kBlk), 0, c.stream, c.L, s.cap, s.u.p, s.p.p, T);
+        OTF_LAUNCH_CHECK("k_targets");
+        OTF_HIP(hipStreamSynchronize(c.stream));
+    } catch (const Failure &e) {
+        c.err = e.msg;
+        return e.st;
+    }
+    return OTF_OK;
+}
+
+otf_status otf_warm_start(otf_ctx *ctx, otf_mlp *nn) {
+    if (!ctx || !nn) return OTF_E_INVALID;
+    if (!ctx->c.valid) return OTF_E_STATE;
+    if (ctx->c.device != nn->m.device || ctx->c.stream != nn->m.stream) return OTF_E_INVALID;
+    Ctx &c = ctx->c;
+    try {
+        OTF_HIP(hipSetDevice(c.device));
+        DBuf<float> X, Y;
+        X.reserve((size_t)c.L * kIn);
+        Y.reserve((size_t)c.L * kOut);
+        LeafStore &s = c.lv();
+        hipLaunchKernelGGL(k_features, dim3(g1(c.L)), dim3(kBlk), 0, c.stream, c.L, c.prm.max_depth, c.prm.gamma,
+                           s.level.p, s.u.p, s.obs_off.p, s.obs_m.p, s.wtot.p, c.op().F.p, s.nbp_off.p, s.nbp.p,
+                           s.nbm_off.p, s.nbm.p, X.p);
+        OTF_LAUNCH_CHECK("k_features");
+        nn->m.forward(X.p, c.L, Y.p);
+        hipLaunchKernelGGL(k_apply_warm, dim3(g1(c.L)), dim3(kBlk), 0, c.stream, c.L, s.cap, Y.p, s.u.p, s.ubar.p,
+                           s.p.p);
+        OTF_LAUNCH_CHECK("k_apply_warm");
+        OTF_HIP(hipStreamSynchronize(c.stream));
+    } catch (const Failure &e) {
+        c.err = e.msg;
+        return e.st;
+    }
+    return OTF_OK;
+}
+
+}  // extern "C"

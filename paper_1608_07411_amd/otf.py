@@ -57,6 +57,16 @@ def lib():
             "otf_dense_field": [P, P, I32, I64],
             "otf_mesh": [P, C.c_float, I64, P, P, P],
             "otf_quantisation_error": [P, P, I32, P],
+            "otf_mlp_create": [C.c_int, P, P],
+            "otf_mlp_destroy": [P],
+            "otf_mlp_set_params": [P, P, I64],
+            "otf_mlp_get_params": [P, P, I64],
+            "otf_mlp_forward": [P, P, I64, P],
+            "otf_mlp_gradient": [P, P, P, I64, P, P],
+            "otf_mlp_train_step": [P, P, P, I64, C.c_float, P],
+            "otf_features": [P, P, I64],
+            "otf_leaf_targets": [P, P, I64],
+            "otf_warm_start": [P, P],
             "otf_energy_eps": [P, C.c_double, P, P],
             "otf_last_counts": [P, P, P],
             "otf_export_state": [P, P, I64, P],
@@ -77,6 +87,10 @@ def lib():
         L.otf_last_error.restype = C.c_char_p
         L.otf_batch_last_error.argtypes = [P]
         L.otf_batch_last_error.restype = C.c_char_p
+        L.otf_mlp_last_error.argtypes = [P]
+        L.otf_mlp_last_error.restype = C.c_char_p
+        L.otf_mlp_num_params.argtypes = []
+        L.otf_mlp_num_params.restype = I64
         _lib = L
     return _lib
 
@@ -221,6 +235,25 @@ class Context:
             raise OtfError(5, "no octree built or imported")
         return self._D
 
+    def features(self):
+        """Warm-start features of every leaf: CUDA float tensor (L, 32)."""
+        import torch
+        X = torch.empty((self.num_leaves(), 32), dtype=torch.float32, device="cuda")
+        self._check(self._lib.otf_features(self.h, C.c_void_p(X.data_ptr()), X.shape[0]), "otf_features")
+        return X
+
+    def targets(self):
+        """Current (u, px, py, pz) of every leaf: CUDA float tensor (L, 4)."""
+        import torch
+        T = torch.empty((self.num_leaves(), 4), dtype=torch.float32, device="cuda")
+        self._check(self._lib.otf_leaf_targets(self.h, C.c_void_p(T.data_ptr()), T.shape[0]), "otf_leaf_targets")
+        return T
+
+    def warm_start(self, net: "Mlp"):
+        """Replace u (and ubar) and p of every leaf by the network's prediction."""
+        self._check(self._lib.otf_warm_start(self.h, net.h), "otf_warm_start")
+        return self
+
     def num_leaves(self) -> int:
         n = C.c_int64(0)
         self._check(self._lib.otf_num_leaves(self.h, C.byref(n)), "otf_num_leaves")
@@ -347,6 +380,63 @@ class Batch:
         self._check(self._lib.otf_batch_config(self.h, C.byref(b), C.byref(g), C.byref(t), C.byref(gi)),
                     "otf_batch_config")
         return dict(block=b.value, grid=g.value, tuned=bool(t.value), graph_iterations=gi.value)
+
+
+class Mlp:
+    """The warm-start network (otf_mlp): parameters, forward, gradient, Adam steps.
+    X, T and Y are contiguous CUDA float tensors (rows x 32, rows x 4)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self._lib = lib()
+        self.h = C.c_void_p()
+        st = self._lib.otf_mlp_create(device, _stream_handle(stream), C.byref(self.h))
+        if st != 0:
+            raise OtfError(st, "otf_mlp_create")
+        self.n_params = int(self._lib.otf_mlp_num_params())
+
+    def close(self):
+        if self.h:
+            self._lib.otf_mlp_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, what):
+        if st != 0:
+            raise OtfError(st, f"{what}: {self._lib.otf_mlp_last_error(self.h).decode()}")
+
+    def set_params(self, theta: np.ndarray):
+        t = np.ascontiguousarray(theta, dtype=np.float32)
+        self._check(self._lib.otf_mlp_set_params(self.h, _ptr(t), t.size), "otf_mlp_set_params")
+
+    def get_params(self) -> np.ndarray:
+        t = np.zeros(self.n_params, np.float32)
+        self._check(self._lib.otf_mlp_get_params(self.h, _ptr(t), t.size), "otf_mlp_get_params")
+        return t
+
+    def forward(self, X):
+        import torch
+        Y = torch.empty((X.shape[0], 4), dtype=torch.float32, device=X.device)
+        self._check(self._lib.otf_mlp_forward(self.h, C.c_void_p(X.data_ptr()), X.shape[0], C.c_void_p(Y.data_ptr())),
+                    "otf_mlp_forward")
+        return Y
+
+    def gradient(self, X, T):
+        g = np.zeros(self.n_params, np.float32)
+        loss = C.c_double(0)
+        self._check(self._lib.otf_mlp_gradient(self.h, C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()),
+                                                X.shape[0], _ptr(g), C.byref(loss)), "otf_mlp_gradient")
+        return loss.value, g
+
+    def train_step(self, X, T, lr: float) -> float:
+        loss = C.c_double(0)
+        self._check(self._lib.otf_mlp_train_step(self.h, C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()),
+                                                  X.shape[0], lr, C.byref(loss)), "otf_mlp_train_step")
+        return loss.value
 
 
 def raw_status(fn_name: str, *args) -> int:

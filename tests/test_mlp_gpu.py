@@ -1,0 +1,122 @@
+"""The warm-start network on the GPU (MFMA kernels) against the numpy oracle:
+forward outputs, loss and gradients (to bf16 accuracy: the two sides round
+the same values to bf16 but accumulate in different orders), training that
+lowers the loss, features against their definition, and the warm start."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from oracle import mlp as om
+from paper_1608_07411_amd import synth
+from tests.helpers import TAU32
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - the GPU suite runs on the MI355X machine
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1608_07411_amd import otf  # noqa: E402
+
+
+def _data(rows, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((rows, 32)).astype(np.float32)
+    T = rng.standard_normal((rows, 4)).astype(np.float32)
+    return X, T
+
+
+def test_forward_matches_oracle():
+    net = otf.Mlp(0)
+    theta = om.init_params(5)
+    net.set_params(theta)
+    assert np.array_equal(net.get_params(), theta)
+    for rows in (1, 17, 1000):
+        X, _ = _data(rows, rows)
+        Y = net.forward(torch.from_numpy(X).cuda()).cpu().numpy()
+        R, _ = om.forward(theta, X)
+        assert np.max(np.abs(Y - R)) <= 2e-2 * (1.0 + np.max(np.abs(R))), rows
+
+
+def test_gradient_matches_oracle():
+    net = otf.Mlp(0)
+    theta = om.init_params(7)
+    net.set_params(theta)
+    X, T = _data(6000, 1)  # long enough for the split reduction over rows
+    loss, g = net.gradient(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda())
+    rl, rg = om.loss_and_grad(theta, X, T)
+    assert abs(loss - rl) <= 1e-2 * rl
+    at = 0
+    for a, b in zip(om.SIZES[:-1], om.SIZES[1:]):
+        for n in (a * b, b):
+            seg, ref = g[at:at + n], rg[at:at + n]
+            assert np.max(np.abs(seg - ref)) <= 3e-2 * np.max(np.abs(ref)) + 1e-6, (a, b, n)
+            at += n
+
+
+def test_training_lowers_the_loss():
+    net = otf.Mlp(0)
+    net.set_params(om.init_params(11))
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((4096, 32)).astype(np.float32)
+    # targets from a fixed smooth function of the inputs
+    T = np.stack([np.tanh(X[:, :8].sum(1) / 3), np.sin(X[:, 8]), 0.5 * X[:, 9] * X[:, 10], X[:, 11] ** 2 / 4],
+                 axis=1).astype(np.float32)
+    Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+    first = net.train_step(Xd, Td, 1e-3)
+    for _ in range(300):
+        last = net.train_step(Xd, Td, 1e-3)
+    assert last < 0.2 * first, (first, last)
+
+
+def _oracle_features(g):
+    lv = g.extract()
+    o = Oracle("f32").import_state(g.export_state())
+    obs = o.leaf_obs()
+    counts, idx = o.neighbours()
+    L = len(lv["u"])
+    X = np.zeros((L, 32), np.float64)
+    off = np.concatenate([[0], np.cumsum(counts.sum(1))])
+    u = lv["u"].astype(np.float64)
+    for i in range(L):
+        M, o0 = obs["M"][i], obs["off"][i]
+        for k in range(16):
+            X[i, k] = obs["F"][o0 + ((2 * k + 1) * M) // 32] if M else 0.0
+        at = off[i]
+        for f in range(6):
+            nb = idx[at:at + counts[i, f]]
+            at += counts[i, f]
+            X[i, 16 + f] = u[nb].mean() if len(nb) else 0.0
+        X[i, 22] = u[i]
+        X[i, 23] = obs["wtot"][i] / (obs["wtot"][i] + 1e-2)
+        X[i, 24] = M / 64.0
+        X[i, 25] = lv["levels"][i] / 5.0
+    return X
+
+
+def test_features_match_their_definition():
+    w = synth.sphere_workload(max_depth=5, n_views=4, W=80, H=60, f=75.0)
+    g = otf.Context(0).build_octree(w.depth, w.cams, w.params)
+    g.fuse(3, 0.5, TAU32, TAU32)
+    X = g.features().cpu().numpy()
+    R = _oracle_features(g)
+    assert np.max(np.abs(X - R)) < 1e-5
+
+
+def test_warm_start_writes_the_prediction():
+    w = synth.sphere_workload(max_depth=5, n_views=4, W=80, H=60, f=75.0, restructure_every=0)
+    g = otf.Context(0).build_octree(w.depth, w.cams, w.params)
+    net = otf.Mlp(0)
+    net.set_params(om.init_params(13) * 0.3)
+    Y = net.forward(g.features()).cpu().numpy()
+    g.warm_start(net)
+    lv = g.extract()
+    assert np.array_equal(lv["u"], Y[:, 0]) and np.array_equal(lv["ubar"], Y[:, 0])
+    q = Y[:, 1:].astype(np.float64)
+    n = np.sqrt((q ** 2).sum(1))
+    assert np.all(np.sqrt((lv["p"].astype(np.float64) ** 2).sum(1)) <= 1.0 + 1e-6)
+    inside = n <= 1.0
+    assert np.array_equal(lv["p"][inside], Y[inside, 1:])
+    g.fuse(5, 0.5, TAU32, TAU32)  # the solver runs from the warm state
