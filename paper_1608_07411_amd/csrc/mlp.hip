@@ -1,9 +1,9 @@
-// Learned warm start: a per-leaf network predicts the converged fused value
-// u and dual p of every leaf from the leaf's sorted observations and its
-// neighbourhood, so that the primal-dual iteration (Sec. 3.2) starts closer
-// to its solution.
+// Learned warm start: a per-leaf network predicts how far the converged fused
+// value u of every leaf lies from its start, and its converged dual p, from
+// the leaf's sorted observations and its neighbourhood, so that the
+// primal-dual iteration (Sec. 3.2) starts closer to its solution.
 //
-// Network: 32 features -> 128 -> 128 -> 128 -> 4 (u, px, py, pz), ReLU on the
+// Network: 32 features -> 128 -> 128 -> 128 -> 4 (change of u, px, py, pz), ReLU on the
 // hidden layers. Weights and activations are bfloat16, products accumulate in
 // fp32 on the matrix cores (v_mfma_f32_16x16x16 bf16), biases and the master
 // weights (Adam) are fp32. Parameter vector: per layer W (in x out,
@@ -173,12 +173,13 @@ __global__ void k_targets(int64_t L, int64_t cap, const float *u, const float *p
     T[4 * i + 3] = p[2 * cap + i];
 }
 
-// the predicted u (ubar = u) and p, p projected onto the unit ball as the
-// dual constraint requires
+// the prediction applied: output 0 is the change of u (u <- u + y0, kept in
+// the TSDF range [-1, 1]; ubar = u), outputs 1..3 are p, projected onto the
+// unit ball as the dual constraint requires
 __global__ void k_apply_warm(int64_t L, int64_t cap, const float *Y, float *u, float *ubar, float *p) {
     const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
     if (i >= L) return;
-    const float v = Y[4 * i];
+    const float v = fminf(1.0f, fmaxf(-1.0f, u[i] + Y[4 * i]));
     u[i] = v;
     ubar[i] = v;
     float q[3] = {Y[4 * i + 1], Y[4 * i + 2], Y[4 * i + 3]};

@@ -448,6 +448,18 @@ def batch_workloads(n_objects: int = 48, first_seed: int = 1000, restructure_eve
     return out
 
 
+def warm_training_workload(j: int, restructure_every: int = 0) -> Workload:
+    """Training scene j of the learned warm start: a sphere as in the sphere
+    workload with radius uniform in [0.2, 0.35] and its centre moved by up to
+    0.05 per axis (seed j)."""
+    s = Stream(5, j, 0)
+    r = float(s.uniform(1, 0.2, 0.35)[0])
+    c = CENTRE + s.uniform(3, -0.05, 0.05)
+    w = sphere_workload(seed=j, radius=r, centre=c, workload_id=5, restructure_every=restructure_every)
+    w.name = f"warm-train-{j}"
+    return w
+
+
 def workload(k: int, seed: int = 0, **kw) -> Workload:
     """The three plain-method workloads: 1 sphere (depth 6), 2 blocks (depth 8), 3 thin (depth 9)."""
     if k == 1:
