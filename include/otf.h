@@ -200,11 +200,13 @@ otf_status otf_quantisation_error(otf_ctx *ctx, const float *dense, int32_t dens
 
 /* ---------------------------------------------------------------------------
  * Learned warm start, for callers that fuse many similar scenes: a per-leaf
- * network predicts the converged u and p of the primal-dual iteration
- * (Sec. 3.2) from each leaf's sorted observations (Fig. 4 fetch) and its
- * face neighbours, and the iteration starts from that prediction.
+ * network predicts the change from the initial to the converged u, and the
+ * converged p, of the primal-dual iteration (Sec. 3.2) from each leaf's
+ * sorted observations (Fig. 4 fetch) and its face neighbours, and the
+ * iteration starts from that prediction.
  *
- * Network: 32 features -> 128 -> 128 -> 128 -> 4 outputs (u, px, py, pz),
+ * Network: 32 features -> 128 -> 128 -> 128 -> 4 outputs (change of u, px,
+ * py, pz),
  * ReLU on hidden layers; bfloat16 weights and activations (fp32 rounded to
  * nearest, ties to even), fp32 accumulation on the matrix cores, fp32 biases
  * and master weights; loss: mean squared error over rows and outputs;
@@ -239,9 +241,9 @@ const char *otf_mlp_last_error(const otf_mlp *net);
  * OTF_E_STATE, OTF_E_CAPACITY (cap_rows < leaves). */
 otf_status otf_features(otf_ctx *ctx, float *X, int64_t cap_rows);
 otf_status otf_leaf_targets(otf_ctx *ctx, float *T, int64_t cap_rows);
-/* u, ubar and p of every leaf set from the network's prediction (p
- * projected onto the unit ball). The network must use the context's device
- * and stream (else OTF_E_INVALID). */
+/* Every leaf's u (and ubar) becomes u + output 0 clamped to [-1, 1], its p
+ * outputs 1..3 projected onto the unit ball. The network must use the
+ * context's device and stream (else OTF_E_INVALID). */
 otf_status otf_warm_start(otf_ctx *ctx, otf_mlp *net);
 
 /* ---------------------------------------------------------------------------
