@@ -189,6 +189,7 @@ static_assert(sizeof(otf_params) == 40, "params record");
 static_assert(sizeof(otf_camera) == 72, "camera record");
 
 void setup_after_structure(Ctx &c, bool init_values) {
+    build_view_table(c);
     gather_all_leaves(c, init_values);
     if (init_values) init_state_values(c);
     build_neighbours(c);
@@ -382,7 +383,7 @@ otf_status otf_fuse(otf_ctx *ctx, int32_t iterations, float lambda, float tau, f
                 prof_end(c, kProfRestructure);
             }
         }
-        read_back(c, {});  // synchronises and checks the scan health flag
+        finish(c);  // synchronises and checks the scan health flag
     });
 }
 
@@ -422,7 +423,7 @@ otf_status otf_fuse_gd(otf_ctx *ctx, int32_t iterations, float lambda, float ste
             }
         }
         c.sol = Solver{};
-        read_back(c, {});
+        finish(c);
     });
 }
 

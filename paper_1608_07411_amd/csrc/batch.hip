@@ -262,7 +262,7 @@ otf_status otf_batch_fuse(otf_batch *bt, int32_t iterations, float lambda, float
             if (after_sweeps(bt, tl)) bt->table_ok = false;
             ++it;
         }
-        for (Ctx *c : bt->b.objs) read_back(*c, {});  // synchronises and checks each member's scan health
+        for (Ctx *c : bt->b.objs) finish(*c);  // synchronises and checks each member's scan health
     });
 }
 

@@ -46,9 +46,17 @@ __global__ void __launch_bounds__(kBlk) k_gather(ViewDev vd, int64_t n, const ui
         const int D = vd.max_depth;
         const uint32_t key = tkey[h];
         const int L = tlevel[h];
-        uint32_t node = vd.root[j];
-        int l = 0;
-        while (l < L) {
+        uint32_t node, l;
+        if (vd.table && L >= vd.table_level) {  // start at the dense index
+            const uint32_t e =
+                vd.table[(size_t)(key >> (3 * (D - vd.table_level))) * (uint32_t)vd.n_views + (uint32_t)j];
+            node = e & ((1u << kTableIdxBits) - 1u);
+            l = e >> kTableIdxBits;
+        } else {
+            node = vd.root[j];
+            l = 0;
+        }
+        while ((int)l < L) {
             const uint32_t ch = vd.child[node];
             if (ch == kNone) break;
             node = ch + ((key >> (3 * (D - l - 1))) & 7u);
@@ -226,6 +234,40 @@ __global__ void k_accum_obs(unsigned long long *c, int all_weights) {
 void accumulate_obs(Ctx &c, bool all_weights) {
     hipLaunchKernelGGL(k_accum_obs, dim3(1), dim3(64), 0, c.stream,
                        reinterpret_cast<unsigned long long *>(c.counters.p + 4), all_weights ? 1 : 0);
+}
+
+namespace {
+// Dense index: thread t = cell * n_views + view descends the view's octree
+// towards the level-T cell and records where it stops.
+__global__ void k_view_table(ViewDev vd, int T, int64_t n, uint32_t *table) {
+    const int64_t t = (int64_t)blockIdx.x * kBlk + threadIdx.x;
+    if (t >= n) return;
+    const uint64_t cell = (uint64_t)(t / vd.n_views);
+    const int j = (int)(t % vd.n_views);
+    uint32_t node = vd.root[j];
+    int l = 0;
+    while (l < T) {
+        const uint32_t ch = vd.child[node];
+        if (ch == kNone) break;
+        node = ch + (uint32_t)((cell >> (3 * (T - l - 1))) & 7u);
+        ++l;
+    }
+    table[t] = ((uint32_t)l << kTableIdxBits) | node;
+}
+constexpr int kTableLevel = 6;  // 8^6 cells x up to 64 views x 4 bytes = 64 MiB
+}  // namespace
+
+void build_view_table(Ctx &c) {
+    ViewStore &vs = c.views;
+    vs.table_level = -1;
+    if (vs.n_nodes >= (int64_t(1) << kTableIdxBits) || c.n_views <= 0) return;  // indices do not fit: no index
+    const int T = std::min(c.prm.max_depth, kTableLevel);
+    const int64_t n = (int64_t(1) << (3 * T)) * c.n_views;
+    vs.table.reserve(n);
+    hipLaunchKernelGGL(k_view_table, dim3((unsigned)cdiv(n, kBlk)), dim3(kBlk), 0, c.stream, c.view_dev(), T, n,
+                       vs.table.p);
+    OTF_LAUNCH_CHECK("k_view_table");
+    vs.table_level = T;
 }
 
 // Observation pool for every leaf of the current store, in leaf order.

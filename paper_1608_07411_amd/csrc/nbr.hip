@@ -83,15 +83,6 @@ __device__ inline uint32_t entry(int64_t j, int face, int lj) {
     return (uint32_t)j | ((uint32_t)(face % 3) << kIdxBits) | ((uint32_t)lj << (kIdxBits + 2));
 }
 
-struct NbrOld {  // previous store, for leaves that copy their lists
-    const uint8_t *need;      // new leaf: 1 = search its lists, 0 = copy them
-    const uint32_t *src;      // new leaf -> old index (kept leaves)
-    const uint32_t *off_p, *off_m, *ent_p, *ent_m;
-    const uint32_t *remap;    // old index -> new index of a kept leaf
-    const uint32_t *heavy_p, *heavy_m;  // old leaves with a long + / - list
-    uint32_t n_heavy_p, n_heavy_m;
-};
-
 struct Heavy {
     uint32_t *leaf;
     uint8_t *face;
@@ -377,7 +368,32 @@ __global__ void __launch_bounds__(kBlk) k_heavy_lists(int64_t L, const uint32_t 
 }
 
 
-void build(Ctx &c, const NbrOld &old) {
+KeyIndex key_index(Ctx &c) {
+    const int D = c.prm.max_depth;
+    const int shift = std::max(0, 3 * D - 20);
+    const uint32_t nb = 1u << (3 * D - shift);
+    return KeyIndex{c.lv().key.p, c.L, c.s.key_table.p, shift, nb};
+}
+
+unsigned grid8(int64_t L) { return (unsigned)std::min<int64_t>(cdiv(8 * L, kBlk), 8192); }
+
+// the count pass (8 lanes per searched leaf, a bounded grid strides over the
+// list), with room for p.cap long ranges; starts the read-back of their number
+uint32_t count_pass(Ctx &c, NbrPending &p) {
+    LeafStore &s = c.lv();
+    c.s.hv_leaf.reserve(p.cap);
+    c.s.hv_lo.reserve(p.cap);
+    c.s.hv_hi.reserve(p.cap);
+    c.s.hv_face.reserve(p.cap);
+    Heavy hv{c.s.hv_leaf.p, c.s.hv_face.p, c.s.hv_lo.p, c.s.hv_hi.p, c.counters.p + 3, p.cap};
+    hipLaunchKernelGGL(k_zero_n, dim3(1), dim3(64), 0, c.stream, c.counters.p + 3, 1);
+    hipLaunchKernelGGL(k_nbr_count, dim3(grid8(c.L)), dim3(kBlk), 0, c.stream, key_index(c), s.level.p,
+                       c.prm.max_depth, c.s.a.p, c.s.b.p, c.s.g.p, p.dirty, p.n_dirty_dev, c.L, hv);
+    OTF_LAUNCH_CHECK("k_nbr_count");
+    return read_back_begin(c, {{c.counters.p + 3, 3}});
+}
+
+NbrPending search_begin(Ctx &c, const NbrOld &old) {
     LeafStore &s = c.lv();
     const int64_t L = c.L;
     const int D = c.prm.max_depth;
@@ -391,12 +407,11 @@ void build(Ctx &c, const NbrOld &old) {
     hipLaunchKernelGGL(k_key_table, dim3((unsigned)cdiv(nb, kBlk)), dim3(kBlk), 0, c.stream, s.key.p, L, shift, nb,
                        c.s.key_table.p);
     OTF_LAUNCH_CHECK("k_key_table");
-    const KeyIndex ki{s.key.p, L, c.s.key_table.p, shift, nb};
-    uint32_t cap = (uint32_t)std::min<int64_t>(6 * L, std::max<int64_t>(4096, L / 8));
-    uint32_t n_heavy = 0;
+    NbrPending p{};
+    p.old = old;
+    p.cap = (uint32_t)std::min<int64_t>(6 * L, std::max<int64_t>(4096, L / 8));
     // leaves to search: all of them, or (after a restructure) those marked in
     // need, listed at their rank dpos[i]; their number dpos[L] stays on the device
-    const uint32_t *dirty = nullptr, *n_dirty_dev = nullptr;
     if (old.need) {
         c.s.e.reserve(L + 1);
         c.s.dirty.reserve(L);
@@ -404,27 +419,29 @@ void build(Ctx &c, const NbrOld &old) {
         hipLaunchKernelGGL(k_nbr_count_clean, dim3(g), dim3(kBlk), 0, c.stream, L, c.s.a.p, c.s.b.p, old,
                            (const uint32_t *)c.s.e.p, c.s.dirty.p);
         OTF_LAUNCH_CHECK("k_nbr_count_clean");
-        dirty = c.s.dirty.p;
-        n_dirty_dev = c.s.e.p + L;
+        p.dirty = c.s.dirty.p;
+        p.n_dirty_dev = c.s.e.p + L;
     }
-    // 8 lanes per searched leaf; a bounded grid strides over the list
-    const unsigned g8 = (unsigned)std::min<int64_t>(cdiv(8 * L, kBlk), 8192);
-    for (int attempt = 0; attempt < 2; ++attempt) {
-        c.s.hv_leaf.reserve(cap);
-        c.s.hv_lo.reserve(cap);
-        c.s.hv_hi.reserve(cap);
-        c.s.hv_face.reserve(cap);
-        Heavy hv{c.s.hv_leaf.p, c.s.hv_face.p, c.s.hv_lo.p, c.s.hv_hi.p, c.counters.p + 3, cap};
-        hipLaunchKernelGGL(k_zero_n, dim3(1), dim3(64), 0, c.stream, c.counters.p + 3, 1);
-        hipLaunchKernelGGL(k_nbr_count, dim3(g8), dim3(kBlk), 0, c.stream, ki, s.level.p, D, c.s.a.p, c.s.b.p, c.s.g.p,
-                           dirty, n_dirty_dev, L, hv);
-        OTF_LAUNCH_CHECK("k_nbr_count");
-        read_back(c, {{c.counters.p + 3, 3}});
+    p.ticket = count_pass(c, p);
+    return p;
+}
+
+void search_end(Ctx &c, NbrPending &p, void (*overlap)(Ctx &)) {
+    LeafStore &s = c.lv();
+    const int64_t L = c.L;
+    const int D = c.prm.max_depth;
+    const unsigned g = (unsigned)cdiv(L, kBlk);
+    const NbrOld &old = p.old;
+    read_back_wait(c, p.ticket);
+    uint32_t n_heavy = c.h_counters[3];
+    if (n_heavy > p.cap) {  // rare: more long ranges than room; count again with room for all
+        p.cap = n_heavy;
+        read_back_wait(c, count_pass(c, p));
         n_heavy = c.h_counters[3];
-        if (n_heavy <= cap) break;
-        cap = n_heavy;  // rare: more long ranges than room; count again with room for all
+        if (n_heavy > p.cap) fail(OTF_E_DEVICE, "long-range count changed between passes");
     }
-    Heavy hv{c.s.hv_leaf.p, c.s.hv_face.p, c.s.hv_lo.p, c.s.hv_hi.p, c.counters.p + 3, cap};
+    const KeyIndex ki = key_index(c);
+    Heavy hv{c.s.hv_leaf.p, c.s.hv_face.p, c.s.hv_lo.p, c.s.hv_hi.p, c.counters.p + 3, p.cap};
     Chunks ch{nullptr, nullptr, nullptr, nullptr};
     uint32_t n_chunks = 0;
     if (n_heavy > 0) {
@@ -458,7 +475,10 @@ void build(Ctx &c, const NbrOld &old) {
     hipLaunchKernelGGL(k_heavy_lists, dim3(g), dim3(kBlk), 0, c.stream, L, (const uint32_t *)s.nbp_off.p,
                        (const uint32_t *)s.nbm_off.p, s.heavy_p.p, s.heavy_m.p, c.counters.p + 14);
     OTF_LAUNCH_CHECK("k_heavy_lists");
-    read_back(c, {{s.nbp_off.p + L, 10}, {s.nbm_off.p + L, 11}, {c.counters.p + 14, 14}, {c.counters.p + 15, 15}});
+    const uint32_t t_tot = read_back_begin(
+        c, {{s.nbp_off.p + L, 10}, {s.nbm_off.p + L, 11}, {c.counters.p + 14, 14}, {c.counters.p + 15, 15}});
+    if (overlap) overlap(c);
+    read_back_wait(c, t_tot);
     s.n_nbp = c.h_counters[10];
     s.n_nbm = c.h_counters[11];
     s.n_heavy_p = c.h_counters[14];
@@ -476,9 +496,9 @@ void build(Ctx &c, const NbrOld &old) {
             OTF_LAUNCH_CHECK("k_nbr_copy_long");
         }
     }
-    hipLaunchKernelGGL(k_nbr_fill, dim3(g8), dim3(kBlk), 0, c.stream, ki, s.level.p, D, (const uint32_t *)c.s.g.p,
-                       (const uint32_t *)s.nbp_off.p, (const uint32_t *)s.nbm_off.p, s.nbp.p, s.nbm.p, dirty,
-                       n_dirty_dev, L);
+    hipLaunchKernelGGL(k_nbr_fill, dim3(grid8(L)), dim3(kBlk), 0, c.stream, ki, s.level.p, D,
+                       (const uint32_t *)c.s.g.p, (const uint32_t *)s.nbp_off.p, (const uint32_t *)s.nbm_off.p,
+                       s.nbp.p, s.nbm.p, p.dirty, p.n_dirty_dev, L);
     OTF_LAUNCH_CHECK("k_nbr_fill");
     if (n_heavy > 0) {
         hipLaunchKernelGGL(k_nbr_chunk<true>, dim3((unsigned)cdiv((int64_t)n_chunks * 64, kBlk)), dim3(kBlk), 0,
@@ -491,15 +511,19 @@ void build(Ctx &c, const NbrOld &old) {
 }  // namespace
 
 void build_neighbours(Ctx &c) {
-    build(c, NbrOld{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0u, 0u});
+    NbrPending p =
+        search_begin(c, NbrOld{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0u, 0u});
+    search_end(c, p, nullptr);
 }
 
-void build_neighbours_incremental(Ctx &c, const LeafStore &old, const uint32_t *remap) {
+NbrPending build_neighbours_begin(Ctx &c, const LeafStore &old, const uint32_t *remap) {
     const LeafStore &s = c.lv();
     // an unchanged leaf with a long list had that list in the previous store,
     // so it is on one of the old long-list work lists
-    build(c, NbrOld{s.need.p, s.src.p, old.nbp_off.p, old.nbm_off.p, old.nbp.p, old.nbm.p, remap, old.heavy_p.p,
-                    old.heavy_m.p, (uint32_t)old.n_heavy_p, (uint32_t)old.n_heavy_m});
+    return search_begin(c, NbrOld{s.need.p, s.src.p, old.nbp_off.p, old.nbm_off.p, old.nbp.p, old.nbm.p, remap,
+                                  old.heavy_p.p, old.heavy_m.p, (uint32_t)old.n_heavy_p, (uint32_t)old.n_heavy_m});
 }
+
+void build_neighbours_end(Ctx &c, NbrPending &p, void (*overlap)(Ctx &)) { search_end(c, p, overlap); }
 
 }  // namespace otf

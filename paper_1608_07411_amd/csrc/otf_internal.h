@@ -223,6 +223,10 @@ struct ViewStore {
     DBuf<uint32_t> cnt, child, key;
     DBuf<uint8_t> level;
     DBuf<uint32_t> root;               // per view: pool index of the root
+    // dense index at level table_level (-1: none): per cell (Morton order)
+    // and view, the deepest node containing the cell, (level << 28) | index
+    DBuf<uint32_t> table;
+    int table_level = -1;
     std::vector<int64_t> count, base;  // per view node count and pool offset (host)
     int64_t n_nodes = 0;
 };
@@ -234,7 +238,10 @@ struct ViewDev {
     const uint32_t *root;
     int n_views;
     int max_depth;
+    const uint32_t *table;  // dense index (null: descend from the roots)
+    int table_level;
 };
+constexpr uint32_t kTableIdxBits = 28;
 
 // Fused leaves: Morton-sorted structure of arrays.
 struct LeafStore {
@@ -339,7 +346,9 @@ struct Ctx {
     DBuf<uint32_t> counters;
     uint32_t *h_counters = nullptr;    // pinned, coherent host slots for read-backs (32)
     uint32_t *d_h_counters = nullptr;  // the same slots as the device addresses them
+    uint32_t read_seq = 0;             // last read-back sequence number issued
     int64_t last_splits = 0, last_joins = 0;
+    bool had_splits = true, had_joins = true;  // flags at the previous restructure
     // profiling: event pairs recorded on the stream, summed when read
     struct ProfRec {
         int kind;
@@ -361,7 +370,9 @@ struct Ctx {
     LeafStore &lv() { return leaves[cur]; }
     ObsPool &op() { return obs[ocur]; }
     ViewDev view_dev() const {
-        return ViewDev{views.S.p, views.cnt.p, views.child.p, views.root.p, n_views, prm.max_depth};
+        return ViewDev{views.S.p,         views.cnt.p, views.child.p,
+                       views.root.p,      n_views,     prm.max_depth,
+                       views.table_level >= 0 ? views.table.p : nullptr, views.table_level};
     }
 };
 
@@ -369,15 +380,25 @@ struct Ctx {
 // launchers (each issues work on ctx.stream)
 // ---------------------------------------------------------------------------
 // Host read-back: one small kernel stores up to kReadMax device u32 values into
-// the host slots h_counters[slot], then the stream is synchronised. The scan
-// health flag travels with every read-back and raises OTF_E_DEVICE when set.
+// the host slots h_counters[slot] and then a sequence number into
+// h_counters[kSeqSlot]; the host spins on that number (work queued on the
+// stream before the kernel has then finished) instead of synchronising the
+// stream, so that work queued after the kernel keeps the device busy while the
+// host waits. The scan health flag travels with every read-back and raises
+// OTF_E_DEVICE when set. Between read_back_begin and read_back_wait no other
+// read-back may use the same slots.
 constexpr int kReadMax = 4;
 constexpr int kScanHealthSlot = 24;
+constexpr int kSeqSlot = 31;
 struct ReadItem {
     const uint32_t *src;
     int slot;
 };
+uint32_t read_back_begin(Ctx &c, std::initializer_list<ReadItem> items);
+void read_back_wait(Ctx &c, uint32_t ticket);
 void read_back(Ctx &c, std::initializer_list<ReadItem> items);
+// all work on the stream finished (stream synchronised), scan health checked
+void finish(Ctx &c);
 // scans over n elements; the total is returned to the host (synchronises)
 uint32_t scan_exclusive_u8(Ctx &c, const uint8_t *in, uint32_t *out, int64_t n);
 uint32_t scan_exclusive_u32(Ctx &c, const uint32_t *in, uint32_t *out, int64_t n);
@@ -402,6 +423,8 @@ void gather_count(Ctx &c, int64_t n, const uint32_t *tkey, const uint8_t *tlevel
 void gather_fill(Ctx &c, int64_t n, const uint32_t *tkey, const uint8_t *tlevel, const uint32_t *tidx,
                  const uint32_t *out_off, uint32_t base, int stride, float *F, float *W, float *P, uint8_t *M,
                  uint8_t *unit, float *inv, float *wtot, float *u0, uint32_t *off_out);
+// dense index of the view octrees (after they change)
+void build_view_table(Ctx &c);
 // pool-compacting gather for every leaf of the current store (two passes)
 void gather_all_leaves(Ctx &c, bool init_values);
 // totals of observations into the device counters (no read-back)
@@ -412,8 +435,26 @@ void accumulate_obs(Ctx &c, bool all_weights = false);
 void build_neighbours(Ctx &c);
 // Adjacency after a restructure: leaves marked in `need` are searched, the
 // others copy their lists from the previous store `old` (leaf src[i]) with
-// indices mapped through remap (old index -> new index).
-void build_neighbours_incremental(Ctx &c, const LeafStore &old, const uint32_t *remap);
+// indices mapped through remap (old index -> new index). Two steps: _begin
+// queues the search up to the count of long ranges and starts reading that
+// count back; _end (after whatever independent work the caller queues in
+// between) finishes it, queueing `overlap` (may be null) while the host waits
+// for the list totals.
+struct NbrOld {  // previous store, for leaves that copy their lists
+    const uint8_t *need;      // new leaf: 1 = search its lists, 0 = copy them
+    const uint32_t *src;      // new leaf -> old index (kept leaves)
+    const uint32_t *off_p, *off_m, *ent_p, *ent_m;
+    const uint32_t *remap;    // old index -> new index of a kept leaf
+    const uint32_t *heavy_p, *heavy_m;  // old leaves with a long + / - list
+    uint32_t n_heavy_p, n_heavy_m;
+};
+struct NbrPending {
+    NbrOld old;
+    uint32_t ticket, cap;
+    const uint32_t *dirty, *n_dirty_dev;
+};
+NbrPending build_neighbours_begin(Ctx &c, const LeafStore &old, const uint32_t *remap);
+void build_neighbours_end(Ctx &c, NbrPending &p, void (*overlap)(Ctx &));
 // sweeps
 void launch_dual(Ctx &c, float sigma);
 void launch_primal(Ctx &c, float tau, float tl);

@@ -134,9 +134,13 @@ __global__ void k_jval_level(int64_t L, int D, int q, const uint8_t *jt, const u
     const uint64_t step = uint64_t(1) << (3 * (D - q - 1));
     int64_t pos[8];
     pos[0] = i;
-    int64_t lo = i + 1;
     const int64_t end = min(L, i + (int64_t)(uint64_t(1) << (3 * (D - q))));
     for (int c = 1; c < 8; ++c) {
+        const int64_t lo = pos[c - 1] + 1;
+        if (level[pos[c - 1]] == q + 1) {  // child c-1 is a single leaf: child c starts right after it
+            pos[c] = lo;
+            continue;
+        }
         const uint64_t kc = k0 + c * step;
         int64_t a = lo, b = end;  // first index in [lo, end) with key >= kc
         while (a < b) {
@@ -145,7 +149,6 @@ __global__ void k_jval_level(int64_t L, int D, int q, const uint8_t *jt, const u
             else b = m;
         }
         pos[c] = a;
-        lo = a + 1;
     }
     float v[5];
     for (int w = 0; w < 5; ++w) {
@@ -272,19 +275,35 @@ __global__ void k_leafcnt(int64_t nc, const uint8_t *csplit, const uint32_t *cra
 }
 
 // ---------------------------------------------------------------- emission
-__global__ void k_out_count(int64_t L, const uint8_t *flag, const uint8_t *jt, const uint8_t *jhead,
-                            const uint32_t *rank0, const uint32_t *cnt0, uint32_t *cnt) {
+// Per old leaf its number of new-store leaves; per block the number of those
+// that are new (collapse heads and cascade leaves) into part[blockIdx].
+__global__ void __launch_bounds__(kBlk) k_out_count(int64_t L, const uint8_t *flag, const uint8_t *jt,
+                                                    const uint8_t *jhead, const uint32_t *rank0,
+                                                    const uint32_t *cnt0, uint32_t *cnt, uint32_t *part) {
     const int64_t i = TID();
-    if (i >= L) return;
-    uint32_t v = 1;
-    if (jt && jt[i] != 0xFF) {
-        v = jhead[i] ? 1u : 0u;
-    } else if (rank0 && (flag[i] & 1)) {
-        const int64_t q = rank0[i];
-        v = 0;
-        for (int c = 0; c < 8; ++c) v += cnt0[8 * q + c];
+    uint32_t v = 1, fresh = 0;
+    if (i < L) {
+        if (jt && jt[i] != 0xFF) {
+            v = jhead[i] ? 1u : 0u;
+            fresh = v;
+        } else if (rank0 && (flag[i] & 1)) {
+            const int64_t q = rank0[i];
+            v = 0;
+            for (int c = 0; c < 8; ++c) v += cnt0[8 * q + c];
+            fresh = v;
+        }
+        cnt[i] = v;
     }
-    cnt[i] = v;
+    __shared__ uint32_t red[kBlk / 64];
+    uint32_t w = fresh;
+    for (int off = 32; off > 0; off >>= 1) w += (uint32_t)__shfl_xor((int)w, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = w;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int k = 0; k < kBlk / 64; ++k) t += red[k];
+        part[blockIdx.x] = t;
+    }
 }
 
 __global__ void k_emit_keep(int64_t L, OldStore o, const uint8_t *jt, int splits, const uint32_t *out_off,
@@ -386,10 +405,18 @@ __global__ void k_emit_final(int64_t nc, const uint8_t *csplit, const uint32_t *
     ns.need[w] = 1;
 }
 
-__global__ void k_compact_idx(int64_t n, const uint8_t *flag, const uint32_t *rank, uint32_t *idx) {
+__global__ void k_zero_u32(int64_t n, uint32_t *a) {
+    const int64_t i = TID();
+    if (i < n) a[i] = 0u;
+}
+
+// idx[rank[i]] = i for flagged i; ranks at or above cap are dropped (the
+// host checks the total against cap)
+__global__ void k_compact_idx(int64_t n, const uint8_t *flag, const uint32_t *rank, uint32_t *idx, uint32_t cap) {
     const int64_t i = TID();
     if (i >= n || !flag[i]) return;
-    idx[rank[i]] = (uint32_t)i;
+    const uint32_t r = rank[i];
+    if (r < cap) idx[r] = (uint32_t)i;
 }
 
 __global__ void k_scatter_m(int64_t n, const uint32_t *tidx, const uint8_t *Mt, uint8_t *M) {
@@ -432,50 +459,94 @@ uint32_t read_u32(Ctx &c, const uint32_t *dev, int slot) {
 
 }  // namespace
 
+namespace {
+
+// Join analysis: run heads, run ends, collapse target (jt) and head flag
+// (jhead) per leaf, the number of collapse heads into counters[2].
+void join_analysis(Ctx &c) {
+    const int64_t L = c.L;
+    const unsigned gL = grid(L);
+    Scratch &s = c.s;
+    LeafStore &os = c.lv();
+    s.a.reserve(L);
+    s.b.reserve(L);
+    s.c.reserve(L);
+    s.u8a.reserve(L);
+    s.u8b.reserve(L);
+    hipLaunchKernelGGL(k_run_heads, dim3(gL), dim3(kBlk), 0, c.stream, L, os.flag.p, s.a.p);
+    scan_inclusive_max_u32(c, s.a.p, s.b.p, L);
+    hipLaunchKernelGGL(k_run_ends, dim3(gL), dim3(kBlk), 0, c.stream, L, os.flag.p, s.b.p, s.c.p);
+    s.part.reserve(gL);
+    hipLaunchKernelGGL(k_join_target, dim3(gL), dim3(kBlk), 0, c.stream, L, c.prm.max_depth, os.flag.p, os.key.p,
+                       os.level.p, s.b.p, s.c.p, s.u8a.p, s.u8b.p, s.part.p);
+    sum_parts(c, s.part.p, gL, 1, gL, c.counters.p + 2);
+    OTF_LAUNCH_CHECK("join analysis");
+}
+
+// Rank of the split-flagged leaves (exclusive scan into s.d).
+void split_rank(Ctx &c) {
+    const int64_t L = c.L;
+    Scratch &s = c.s;
+    s.r_sf.reserve(L);
+    s.d.reserve(L + 1);
+    hipLaunchKernelGGL(k_split_bits, dim3(grid(L)), dim3(kBlk), 0, c.stream, L, c.lv().flag.p, s.r_sf.p);
+    scan_exclusive_u32_dev_u8(c, s.r_sf.p, s.d.p, L);
+}
+
+// Collapse values: hierarchical means level by level, in place over the old
+// leaf positions (scratch r_jv).
+void join_values(Ctx &c, const uint8_t *jt) {
+    const int64_t L = c.L;
+    const int D = c.prm.max_depth;
+    LeafStore &os = c.lv();
+    DBuf<float> &val = c.s.r_jv;
+    val.reserve(5 * (size_t)L);
+    const OldStore osd{os.key.p, os.level.p, os.u.p, os.ubar.p, os.p.p, os.cap, os.obs_off.p, os.obs_m.p,
+                       os.obs_unit.p, os.inv.p, os.wtot.p, os.flag.p};
+    hipLaunchKernelGGL(k_jval_init, dim3(grid(L)), dim3(kBlk), 0, c.stream, L, jt, osd, val.p, L);
+    for (int q = D - 1; q >= 0; --q)
+        hipLaunchKernelGGL(k_jval_level, dim3(grid(L)), dim3(kBlk), 0, c.stream, L, D, q, jt, os.key.p, os.level.p,
+                           val.p, L);
+    OTF_LAUNCH_CHECK("join means");
+}
+
+}  // namespace
+
 bool restructure(Ctx &c, float tl) {
     const int D = c.prm.max_depth;
     const int64_t L = c.L;
     LeafStore &os = c.lv();
-    read_back(c, {{c.counters.p, 0}, {c.counters.p + 1, 1}});
-    const uint32_t n_split = c.h_counters[0], n_join = c.h_counters[1];
-    c.last_splits = c.last_joins = 0;
-    if (n_split == 0 && n_join == 0) return false;
     Scratch &s = c.s;
     const unsigned gL = grid(L);
-
-    // ---- joins
-    uint8_t *jt = nullptr, *jhead = nullptr;
-    if (n_join > 0) {
-        s.a.reserve(L);
-        s.b.reserve(L);
-        s.c.reserve(L);
-        s.u8a.reserve(L);
-        s.u8b.reserve(L);
-        hipLaunchKernelGGL(k_run_heads, dim3(gL), dim3(kBlk), 0, c.stream, L, os.flag.p, s.a.p);
-        scan_inclusive_max_u32(c, s.a.p, s.b.p, L);
-        hipLaunchKernelGGL(k_run_ends, dim3(gL), dim3(kBlk), 0, c.stream, L, os.flag.p, s.b.p, s.c.p);
-        s.part.reserve(gL);
-        hipLaunchKernelGGL(k_join_target, dim3(gL), dim3(kBlk), 0, c.stream, L, D, os.flag.p, os.key.p, os.level.p,
-                           s.b.p, s.c.p, s.u8a.p, s.u8b.p, s.part.p);
-        sum_parts(c, s.part.p, gL, 1, gL, c.counters.p + 2);
-        OTF_LAUNCH_CHECK("join analysis");
-        jt = s.u8a.p;
-        jhead = s.u8b.p;
-    }
+    // While the host waits for the flag counts, the device analyses the joins
+    // and ranks the splits when the previous restructure had them (results
+    // that turn out unneeded are dropped).
+    const uint32_t t_flags = read_back_begin(c, {{c.counters.p, 0}, {c.counters.p + 1, 1}});
+    const bool spec_join = c.had_joins, spec_split = c.had_splits;
+    if (spec_join) join_analysis(c);
+    if (spec_split) split_rank(c);
+    read_back_wait(c, t_flags);
+    const uint32_t n_split = c.h_counters[0], n_join = c.h_counters[1];
+    c.had_joins = n_join > 0;
+    c.had_splits = n_split > 0;
+    c.last_splits = c.last_joins = 0;
+    if (n_split == 0 && n_join == 0) return false;
+    if (n_join > 0 && !spec_join) join_analysis(c);
+    if (n_split > 0 && !spec_split) split_rank(c);
+    const uint8_t *jt = n_join > 0 ? s.u8a.p : nullptr;
+    const uint8_t *jhead = n_join > 0 ? s.u8b.p : nullptr;
+    bool jvals_queued = false;
+    auto queue_join_values = [&] {
+        if (jt && !jvals_queued) join_values(c, jt);
+        jvals_queued = true;
+    };
 
     // ---- split cascade
-    int64_t nrounds = 0, total_splits = 0;
+    int64_t nrounds = 0, total_splits = 0, cascade_leaves = 0;
     uint32_t *rank0 = nullptr;
     if (n_split > 0) {
-        s.d.reserve(L);
-        // rank of the split-flagged leaves
-        DBuf<uint8_t> &sf = s.r_sf;
-        sf.reserve(L);
-        hipLaunchKernelGGL(k_split_bits, dim3(gL), dim3(kBlk), 0, c.stream, L, os.flag.p, sf.p);
-        s.d.reserve(L + 1);
-        scan_exclusive_u32_dev_u8(c, sf.p, s.d.p, L);
-        const uint32_t np0 = n_split;
         rank0 = s.d.p;
+        const uint32_t np0 = n_split;
         Round &r0 = round_at(c, 0);
         r0.np = np0;
         r0.porigin.reserve(np0);
@@ -520,8 +591,14 @@ bool restructure(Ctx &c, float tl) {
                                tM.p, tU.p, s.fc.p, s.fd.p, R.corigin.p, R.clevel.p, os.uprime.p, os.uold.p, tl,
                                c.prm.split_tau, D, c.sol, R.cu.p, R.cub.p, R.csplit.p);
             OTF_LAUNCH_CHECK("k_cascade_prox");
-            const uint32_t next = scan_exclusive_u8(c, R.csplit.p, R.crank.p, nc);
+            scan_exclusive_u32_dev_u8(c, R.csplit.p, R.crank.p, nc);
+            const uint32_t t_next = read_back_begin(c, {{R.crank.p + nc, 8}});
+            queue_join_values();  // independent of the cascade: keeps the device busy meanwhile
+            read_back_wait(c, t_next);
+            const uint32_t next = c.h_counters[8];
+            if (next > nc) fail(OTF_E_DEVICE, "split cascade count out of range");
             total_splits += np;
+            cascade_leaves += nc - next;
             np = next;
             ++r;
         }
@@ -535,44 +612,52 @@ bool restructure(Ctx &c, float tl) {
             OTF_LAUNCH_CHECK("k_leafcnt");
         }
     }
+    queue_join_values();
 
     // ---- emission
     s.e.reserve(L + 1);
     s.f.reserve(L + 1);
+    s.part.reserve(gL);
     hipLaunchKernelGGL(k_out_count, dim3(gL), dim3(kBlk), 0, c.stream, L, os.flag.p, jt, jhead, rank0,
-                       nrounds ? s.rounds[0]->cnt.p : (const uint32_t *)nullptr, s.e.p);
+                       nrounds ? s.rounds[0]->cnt.p : (const uint32_t *)nullptr, s.e.p, s.part.p);
     OTF_LAUNCH_CHECK("k_out_count");
+    sum_parts(c, s.part.p, gL, 1, gL, c.counters.p + 18);
     scan_exclusive_u32_dev(c, s.e.p, s.f.p, L);
     const uint32_t *out_off = s.f.p;
-    read_back(c, {{s.f.p + L, 12}, {c.counters.p + 2, 13}});
-    const int64_t Lnew = c.h_counters[12];
-    if (jt) c.last_joins = c.h_counters[13];
-    c.last_splits = total_splits;
-    if (Lnew >= kLeafLimit) fail(OTF_E_CAPACITY, "leaf count exceeds 2^26");
-    if (c.prm.max_leaves > 0 && Lnew > c.prm.max_leaves) fail(OTF_E_CAPACITY, "leaf count exceeds max_leaves");
-
+    const uint32_t t_out =
+        read_back_begin(c, {{s.f.p + L, 12}, {c.counters.p + 2, 13}, {c.counters.p + 18, 18}});
+    // Collapses only remove leaves, so kept leaves plus the cascade's leaves
+    // bound the new count: the new store is sized by that bound and filled
+    // while the host waits for the exact count (an out-of-range bound waits
+    // for the exact count first).
+    const int64_t Lub = L - (int64_t)n_split + cascade_leaves;
+    int64_t Lnew = -1;
+    uint32_t n_new = 0;
+    auto take_counts = [&] {
+        read_back_wait(c, t_out);
+        Lnew = c.h_counters[12];
+        n_new = c.h_counters[18];
+        if (Lnew >= kLeafLimit) fail(OTF_E_CAPACITY, "leaf count exceeds 2^26");
+        if (c.prm.max_leaves > 0 && Lnew > c.prm.max_leaves) fail(OTF_E_CAPACITY, "leaf count exceeds max_leaves");
+        if (Lnew > Lub || (int64_t)n_new > Lnew) fail(OTF_E_DEVICE, "restructure counts out of range");
+    };
+    if (Lub >= kLeafLimit || (c.prm.max_leaves > 0 && Lub > c.prm.max_leaves)) take_counts();
+    const int64_t Lsize = Lnew >= 0 ? Lnew : Lub;
     LeafStore &ns = c.leaves[c.cur ^ 1];
-    ns.reserve(Lnew);
     DBuf<uint8_t> &isnew = s.r_isnew;
-    isnew.reserve(Lnew);
-    NewStore nsd{ns.key.p, ns.level.p, ns.u.p,     ns.ubar.p, ns.p.p, ns.cap, ns.obs_off.p, ns.obs_m.p, ns.obs_unit.p,
-                 ns.inv.p, ns.wtot.p,  isnew.p, ns.src.p, ns.need.p};
-    OldStore osd{os.key.p, os.level.p, os.u.p, os.ubar.p, os.p.p, os.cap, os.obs_off.p, os.obs_m.p, os.obs_unit.p,
-                 os.inv.p, os.wtot.p, os.flag.p};
-    hipLaunchKernelGGL(k_emit_keep, dim3(gL), dim3(kBlk), 0, c.stream, L, osd, jt, n_split > 0 ? 1 : 0, out_off, nsd);
+    ns.reserve(Lsize);
+    isnew.reserve(Lsize);
+    const NewStore nsd{ns.key.p, ns.level.p, ns.u.p,     ns.ubar.p, ns.p.p, ns.cap, ns.obs_off.p, ns.obs_m.p,
+                       ns.obs_unit.p, ns.inv.p, ns.wtot.p,  isnew.p, ns.src.p, ns.need.p};
+    const OldStore osd{os.key.p, os.level.p, os.u.p, os.ubar.p, os.p.p, os.cap, os.obs_off.p, os.obs_m.p,
+                       os.obs_unit.p, os.inv.p, os.wtot.p, os.flag.p};
+    hipLaunchKernelGGL(k_emit_keep, dim3(gL), dim3(kBlk), 0, c.stream, L, osd, jt, n_split > 0 ? 1 : 0, out_off,
+                       nsd);
     OTF_LAUNCH_CHECK("k_emit_keep");
     if (jt) {
-        // collapse: hierarchical means level by level, in place
-        DBuf<float> &val = s.r_jv;
-        val.reserve(5 * (size_t)L);
-        const int64_t vc = L;
-        hipLaunchKernelGGL(k_jval_init, dim3(gL), dim3(kBlk), 0, c.stream, L, jt, osd, val.p, vc);
-        for (int q = D - 1; q >= 0; --q)
-            hipLaunchKernelGGL(k_jval_level, dim3(gL), dim3(kBlk), 0, c.stream, L, D, q, jt, os.key.p, os.level.p,
-                               val.p, vc);
-        hipLaunchKernelGGL(k_jval_emit, dim3(gL), dim3(kBlk), 0, c.stream, L, jt, jhead, val.p, vc, out_off, nsd,
+        hipLaunchKernelGGL(k_jval_emit, dim3(gL), dim3(kBlk), 0, c.stream, L, jt, jhead, s.r_jv.p, L, out_off, nsd,
                            os.key.p);
-        OTF_LAUNCH_CHECK("join means");
+        OTF_LAUNCH_CHECK("k_jval_emit");
     }
     for (int64_t q = 0; q < nrounds; ++q) {
         Round &R = *s.rounds[q];
@@ -589,13 +674,24 @@ bool restructure(Ctx &c, float tl) {
         }
         OTF_LAUNCH_CHECK("cascade emission");
     }
+    // adjacency: a kept leaf next to a change is searched again
+    hipLaunchKernelGGL(k_nbr_mark, dim3(gL), dim3(kBlk), 0, c.stream, L, os.flag.p, jt, n_split > 0 ? 1 : 0,
+                       os.nbp_off.p, os.nbp.p, os.nbm_off.p, os.nbm.p, out_off, ns.need.p);
+    OTF_LAUNCH_CHECK("k_nbr_mark");
+    if (Lnew < 0) take_counts();
+    if (jt) c.last_joins = c.h_counters[13];
+    c.last_splits = total_splits;
 
     // ---- observations of the new leaves (append to the pool, or compact)
     DBuf<uint32_t> &nrank = s.r_nrank, &tidx = s.r_tidx, &moff = s.r_moff;
     nrank.reserve(Lnew + 1);
-    const uint32_t n_new = scan_exclusive_u8(c, isnew.p, nrank.p, Lnew);
+    scan_exclusive_u32_dev_u8(c, isnew.p, nrank.p, Lnew);
     tidx.reserve(n_new);
-    hipLaunchKernelGGL(k_compact_idx, dim3(grid(Lnew)), dim3(kBlk), 0, c.stream, Lnew, isnew.p, nrank.p, tidx.p);
+    // cleared first, so that every entry is a valid leaf index even if the
+    // two counts of new leaves were to disagree (checked below)
+    hipLaunchKernelGGL(k_zero_u32, dim3(grid(n_new)), dim3(kBlk), 0, c.stream, (int64_t)n_new, tidx.p);
+    hipLaunchKernelGGL(k_compact_idx, dim3(grid(Lnew)), dim3(kBlk), 0, c.stream, Lnew, isnew.p, nrank.p, tidx.p,
+                       n_new);
     DBuf<uint8_t> &Mt = s.r_Mt;
     Mt.reserve(n_new);
     gather_count(c, n_new, ns.key.p, ns.level.p, tidx.p, Mt.p);
@@ -608,8 +704,15 @@ bool restructure(Ctx &c, float tl) {
     DBuf<uint32_t> &loff = s.r_loff;
     loff.reserve(Lnew + 1);
     scan_exclusive_u32_dev_u8(c, ns.obs_m.p, loff.p, Lnew);
-    read_back(c, {{moff.p + n_new, 12}, {loff.p + Lnew, 13}});
-    const uint32_t new_obs = c.h_counters[12], live = c.h_counters[13];
+    const uint32_t t_obs = read_back_begin(c, {{moff.p + n_new, 19}, {loff.p + Lnew, 20}, {nrank.p + Lnew, 21}});
+    // the new store becomes current; its adjacency search does not depend on
+    // the observation pool and runs while the host waits
+    c.cur ^= 1;
+    c.L = Lnew;
+    NbrPending nbr = build_neighbours_begin(c, os, out_off);
+    read_back_wait(c, t_obs);
+    const uint32_t new_obs = c.h_counters[19], live = c.h_counters[20];
+    if (c.h_counters[21] != n_new) fail(OTF_E_DEVICE, "new-leaf counts disagree");
     const bool compact = (pool.used + (int64_t)new_obs > pool.cap) || (pool.used > 2 * (int64_t)live + 4096);
     if (!compact) {
         gather_fill(c, n_new, ns.key.p, ns.level.p, tidx.p, moff.p, (uint32_t)pool.used, 0, pool.F.p, pool.W.p,
@@ -630,15 +733,9 @@ bool restructure(Ctx &c, float tl) {
         c.ocur ^= 1;
         OTF_HIP(hipStreamSynchronize(c.stream));
     }
-
-    // ---- adjacency: search only around changes
-    hipLaunchKernelGGL(k_nbr_mark, dim3(gL), dim3(kBlk), 0, c.stream, L, os.flag.p, jt, n_split > 0 ? 1 : 0,
-                       os.nbp_off.p, os.nbp.p, os.nbm_off.p, os.nbm.p, out_off, ns.need.p);
-    OTF_LAUNCH_CHECK("k_nbr_mark");
-    c.cur ^= 1;
-    c.L = Lnew;
-    build_neighbours_incremental(c, os, out_off);
-    count_obs(c);
+    // the observation totals of the new store are counted while the host
+    // waits for the adjacency list totals
+    build_neighbours_end(c, nbr, count_obs);
     return true;
 }
 

@@ -255,9 +255,12 @@ struct ReadArgs {
     int n;
 };
 
-__global__ void k_read_back(ReadArgs a, uint32_t *host) {
-    const int t = threadIdx.x;
-    if (t < a.n) __hip_atomic_store(host + a.slot[t], *a.src[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+// one lane: the values, then (release, system scope) the sequence number
+__global__ void k_read_back(ReadArgs a, uint32_t *host, uint32_t seq) {
+    if (threadIdx.x != 0) return;
+    for (int t = 0; t < a.n; ++t)
+        __hip_atomic_store(host + a.slot[t], *a.src[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(host + kSeqSlot, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 uint32_t read_total(Ctx &c, const uint32_t *dev) {
@@ -267,7 +270,7 @@ uint32_t read_total(Ctx &c, const uint32_t *dev) {
 
 }  // namespace
 
-void read_back(Ctx &c, std::initializer_list<ReadItem> items) {
+uint32_t read_back_begin(Ctx &c, std::initializer_list<ReadItem> items) {
     if (items.size() > (size_t)kReadMax) fail(OTF_E_INVALID, "too many read-back items");
     ReadArgs a{};
     for (const ReadItem &it : items) {
@@ -278,10 +281,40 @@ void read_back(Ctx &c, std::initializer_list<ReadItem> items) {
     a.src[a.n] = c.counters.p + kScanHealthSlot;
     a.slot[a.n] = kScanHealthSlot;
     ++a.n;
-    hipLaunchKernelGGL(k_read_back, dim3(1), dim3(64), 0, c.stream, a, c.d_h_counters);
+    const uint32_t seq = ++c.read_seq;
+    hipLaunchKernelGGL(k_read_back, dim3(1), dim3(64), 0, c.stream, a, c.d_h_counters, seq);
     OTF_LAUNCH_CHECK("k_read_back");
+    return seq;
+}
+
+// Spins until the sequence number reaches the ticket. Every few thousand
+// polls the stream is queried: an error fails; a finished stream without the
+// number means the store never arrived and fails too.
+void read_back_wait(Ctx &c, uint32_t ticket) {
+    const uint32_t *seqp = c.h_counters + kSeqSlot;
+    auto arrived = [&] { return (int32_t)(__atomic_load_n(seqp, __ATOMIC_ACQUIRE) - ticket) >= 0; };
+    for (uint32_t spins = 1; !arrived(); ++spins) {
+        if ((spins & 4095u) == 0) {
+            const hipError_t e = hipStreamQuery(c.stream);
+            if (e == hipSuccess) {
+                if (arrived()) break;
+                fail(OTF_E_DEVICE, "read-back store did not arrive");
+            }
+            if (e != hipErrorNotReady) {
+                (void)hipGetLastError();
+                fail(OTF_E_DEVICE, std::string("stream failed: ") + hipGetErrorString(e));
+            }
+        }
+    }
+    if (__atomic_load_n(c.h_counters + kScanHealthSlot, __ATOMIC_ACQUIRE))
+        fail(OTF_E_DEVICE, "a device scan's look-back wait timed out");
+}
+
+void read_back(Ctx &c, std::initializer_list<ReadItem> items) { read_back_wait(c, read_back_begin(c, items)); }
+
+void finish(Ctx &c) {
+    read_back(c, {});
     OTF_HIP(hipStreamSynchronize(c.stream));
-    if (c.h_counters[kScanHealthSlot]) fail(OTF_E_DEVICE, "a device scan's look-back wait timed out");
 }
 
 namespace {
