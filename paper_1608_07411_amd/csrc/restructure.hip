@@ -349,6 +349,7 @@ __global__ void __launch_bounds__(kBlk) k_nbr_mark(int64_t L, const uint8_t *fla
         const uint32_t *off = side ? off_m : off_p;
         const uint32_t *ent = side ? ent_m : ent_p;
         const uint32_t e1 = off[i + 1];
+        if (e1 - off[i] > kLongList) continue;  // long lists: k_nbr_mark_long
         for (uint32_t e = off[i]; e < e1; e += kMarkBatch) {
             uint32_t n[kMarkBatch], o[kMarkBatch];
             bool keep[kMarkBatch];
@@ -362,6 +363,29 @@ __global__ void __launch_bounds__(kBlk) k_nbr_mark(int64_t L, const uint8_t *fla
             for (int r = 0; r < kMarkBatch; ++r)
                 if (keep[r]) need[o[r]] = 1;
         }
+    }
+}
+
+// Long lists of changed leaves: one wave per leaf on the old long-list work
+// lists, lanes striding over the entries.
+__global__ void __launch_bounds__(kBlk) k_nbr_mark_long(const uint8_t *flag, const uint8_t *jt, int splits,
+                                                        const uint32_t *off_p, const uint32_t *ent_p,
+                                                        const uint32_t *off_m, const uint32_t *ent_m,
+                                                        const uint32_t *heavy_p, const uint32_t *heavy_m,
+                                                        uint32_t n_heavy_p, uint32_t n_heavy_m,
+                                                        const uint32_t *out_off, uint8_t *need) {
+    const uint32_t item = ((uint32_t)blockIdx.x * kBlk + threadIdx.x) >> 6;
+    const uint32_t lane = threadIdx.x & 63;
+    if (item >= n_heavy_p + n_heavy_m) return;
+    const bool plus = item < n_heavy_p;
+    const uint32_t i = plus ? heavy_p[item] : heavy_m[item - n_heavy_p];
+    if (!changed(i, flag, jt, splits)) return;
+    const uint32_t *off = plus ? off_p : off_m;
+    const uint32_t *ent = plus ? ent_p : ent_m;
+    const uint32_t e1 = off[i + 1];
+    for (uint32_t e = off[i] + lane; e < e1; e += 64) {
+        const uint32_t n = ent[e] & kIdxMask;
+        if (!changed(n, flag, jt, splits)) need[out_off[n]] = 1;
     }
 }
 
@@ -678,6 +702,13 @@ bool restructure(Ctx &c, float tl) {
     hipLaunchKernelGGL(k_nbr_mark, dim3(gL), dim3(kBlk), 0, c.stream, L, os.flag.p, jt, n_split > 0 ? 1 : 0,
                        os.nbp_off.p, os.nbp.p, os.nbm_off.p, os.nbm.p, out_off, ns.need.p);
     OTF_LAUNCH_CHECK("k_nbr_mark");
+    const int64_t n_long = (int64_t)os.n_heavy_p + os.n_heavy_m;
+    if (n_long > 0) {
+        hipLaunchKernelGGL(k_nbr_mark_long, dim3(grid(64 * n_long)), dim3(kBlk), 0, c.stream, os.flag.p, jt,
+                           n_split > 0 ? 1 : 0, os.nbp_off.p, os.nbp.p, os.nbm_off.p, os.nbm.p, os.heavy_p.p,
+                           os.heavy_m.p, (uint32_t)os.n_heavy_p, (uint32_t)os.n_heavy_m, out_off, ns.need.p);
+        OTF_LAUNCH_CHECK("k_nbr_mark_long");
+    }
     if (Lnew < 0) take_counts();
     if (jt) c.last_joins = c.h_counters[13];
     c.last_splits = total_splits;

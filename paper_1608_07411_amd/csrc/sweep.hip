@@ -111,10 +111,124 @@ __device__ inline void dual_leaf(const DualArgs &a, const Coef &cf, int64_t i) {
     dual_finish(a, i, gx, gy, gz, Cx, Cy, Cz);
 }
 
-// One thread per leaf.
+// The coefficient tables copied into LDS (a kernel argument indexed by the
+// levels of a leaf and its neighbour would be fetched from memory, one
+// dependent load per list entry).
+__device__ inline const Coef &stage_coef(const Coef &cf, Coef &sh) {
+    const float *src = &cf.c[0][0];
+    float *dst = &sh.c[0][0];
+    for (int k = threadIdx.x; k < (int)(sizeof(Coef) / sizeof(float)); k += blockDim.x) dst[k] = src[k];
+    __syncthreads();
+    return sh;
+}
+
+// Dual update of kDualLeaves leaves per thread, the same arithmetic as
+// dual_leaf: every leaf-local load (list bounds, level, ubar, p) is issued
+// first, then the list entries of all the thread's leaves, then their
+// neighbours' ubar, so that one thread has its leaves' dependent loads in
+// flight together (the sweep is bound by these chains, not by bandwidth).
+constexpr int kDualLeaves = 2;
+
+__device__ inline void dual_leaves(const DualArgs &a, const Coef &cf, const int64_t (&idx)[kDualLeaves]) {
+    constexpr int N = kDualLeaves;
+    // loads are unconditional (out-of-range leaves read leaf 0, entries past
+    // a list's end read its first slot, which lies inside the allocation) so
+    // that they issue back to back without branches
+    uint32_t e0[N], e1[N];
+    int ln[N];
+    float ub[N], pv[N][3];
+    bool on[N];
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        on[n] = idx[n] < a.L;
+        const int64_t i = on[n] ? idx[n] : 0;
+        e0[n] = a.off[i];
+        e1[n] = a.off[i + 1];
+        ln[n] = a.level[i];
+        ub[n] = a.ubar[i];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) pv[n][d] = a.p[d * a.cap + i];
+    }
+    uint32_t len = 0;
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        on[n] = on[n] && e1[n] - e0[n] <= kLongList;  // long lists: k_dual_long
+        if (!on[n]) e1[n] = e0[n];
+        len = max(len, e1[n] - e0[n]);
+    }
+    float g[N][3], C[N][3];
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) g[n][d] = C[n][d] = 0.0f;
+    for (uint32_t k = 0; k < len; k += kGather) {
+        uint32_t v[N][kGather];
+        float ubk[N][kGather];
+#pragma unroll
+        for (int n = 0; n < N; ++n)
+#pragma unroll
+            for (int r = 0; r < kGather; ++r) {
+                const uint32_t e = e0[n] + k + r;
+                v[n][r] = a.ent[e < e1[n] ? e : e0[n]];
+            }
+#pragma unroll
+        for (int n = 0; n < N; ++n)
+#pragma unroll
+            for (int r = 0; r < kGather; ++r)
+                ubk[n][r] = a.ubar[e0[n] + k + r < e1[n] ? (v[n][r] & kIdxMask) : 0u];
+        // entries folded in list order; selects rather than branches, so that
+        // no load is deferred into a conditional block
+#pragma unroll
+        for (int n = 0; n < N; ++n)
+#pragma unroll
+            for (int r = 0; r < kGather; ++r) {
+                const bool ok = e0[n] + k + r < e1[n];
+                const int d = ok ? (int)((v[n][r] >> kIdxBits) & 3) : 3;
+                const float c = cf.c[ln[n]][v[n][r] >> (kIdxBits + 2)];
+                const float diff = ubk[n][r] - ub[n];
+#pragma unroll
+                for (int x = 0; x < 3; ++x) {
+                    const float gn = __fmaf_rn(c, diff, g[n][x]), Cn = C[n][x] + c;
+                    g[n][x] = d == x ? gn : g[n][x];
+                    C[n][x] = d == x ? Cn : C[n][x];
+                }
+            }
+    }
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        if (!on[n]) continue;
+        const int64_t i = idx[n];
+        if (a.gd) {
+            dual_finish(a, i, g[n][0], g[n][1], g[n][2], C[n][0], C[n][1], C[n][2]);
+            continue;
+        }
+        float qx = __fmaf_rn(a.sigma, g[n][0], pv[n][0]);
+        float qy = __fmaf_rn(a.sigma, g[n][1], pv[n][1]);
+        float qz = __fmaf_rn(a.sigma, g[n][2], pv[n][2]);
+        const float r2 = __fmaf_rn(qx, qx, __fmaf_rn(qy, qy, qz * qz));
+        if (r2 > 1.0f) {
+            const float nrm = sqrtf(r2);
+            qx = qx / nrm;
+            qy = qy / nrm;
+            qz = qz / nrm;
+        }
+        a.p[i] = qx;
+        a.p[a.cap + i] = qy;
+        a.p[2 * a.cap + i] = qz;
+        a.ds[i] = __fmaf_rn(C[n][2], qz, __fmaf_rn(C[n][1], qy, __fmaf_rn(C[n][0], qx, 0.0f)));
+    }
+}
+
+// kDualLeaves leaves per thread: a block covers kDualLeaves * kBlk consecutive
+// leaves, thread t takes t, t + kBlk, ... (each group coalesced).
 __global__ void __launch_bounds__(kBlk) k_dual(DualArgs a, Coef cf) {
-    const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
-    if (i < a.L) dual_leaf(a, cf, i);
+    __shared__ Coef scf;
+    const Coef &lcf = stage_coef(cf, scf);
+    const int64_t base = (int64_t)blockIdx.x * (kDualLeaves * kBlk) + threadIdx.x;
+    int64_t idx[kDualLeaves];
+#pragma unroll
+    for (int n = 0; n < kDualLeaves; ++n) idx[n] = base + (int64_t)n * kBlk;
+    dual_leaves(a, lcf, idx);
 }
 
 // Leaves with a long + list, one 256-thread block each: the block stages the
@@ -364,18 +478,21 @@ __global__ void __launch_bounds__(kBlk) k_primal_long(uint32_t n, const uint32_t
 // [e0, e1), in list order; kGather entries in flight.
 __device__ inline float divergence(const PrimalArgs &a, const Coef &cf, uint32_t e0, uint32_t e1, int ln,
                                    float acc) {
+    // unconditional loads (entries past the end read the list's first slot,
+    // inside the allocation; their neighbour reads leaf 0) and selects, so
+    // that every load of a group issues before the first is used
     for (uint32_t e = e0; e < e1; e += kGather) {
         uint32_t v[kGather];
         float pm[kGather];
 #pragma unroll
-        for (int r = 0; r < kGather; ++r) v[r] = e + r < e1 ? a.ent[e + r] : 0u;
+        for (int r = 0; r < kGather; ++r) v[r] = a.ent[e + r < e1 ? e + r : e0];
 #pragma unroll
         for (int r = 0; r < kGather; ++r)
-            pm[r] = e + r < e1 ? a.p[(int64_t)((v[r] >> kIdxBits) & 3) * a.cap + (v[r] & kIdxMask)] : 0.0f;
+            pm[r] = a.p[e + r < e1 ? (int64_t)((v[r] >> kIdxBits) & 3) * a.cap + (v[r] & kIdxMask) : 0];
 #pragma unroll
         for (int r = 0; r < kGather; ++r) {
-            if (e + r >= e1) break;
-            acc = __fmaf_rn(-cf.cp[v[r] >> (kIdxBits + 2)][ln], pm[r], acc);
+            const float nx = __fmaf_rn(-cf.cp[v[r] >> (kIdxBits + 2)][ln], pm[r], acc);
+            acc = e + r < e1 ? nx : acc;
         }
     }
     return acc;
@@ -397,16 +514,20 @@ __device__ inline void primal_wave(const PrimalArgs &a, const Coef &cf, int64_t 
     int M = 0, unit = 1, ln = 0;
     uint32_t oo = 0;
     if (valid) {
+        // the leaf's own loads first, all in flight before the divergence's
+        // dependent list loads
         ln = a.level[i];
         un = a.u_in[i];
         const uint32_t e0 = a.off[i], e1 = a.off[i + 1];
-        if (e1 - e0 > kLongList) up = a.ds[i];
-        else up = __fmaf_rn(a.tau, divergence(a, cf, e0, e1, ln, a.ds[i]), un);
+        const float dsi = a.ds[i];
         M = a.obs_m[i];
         oo = a.obs_off[i];
         unit = a.obs_unit[i];
-        t = a.tl * a.inv[i];
+        const float inv = a.inv[i];
         wt = a.wtot[i];
+        t = a.tl * inv;
+        if (e1 - e0 > kLongList) up = dsi;
+        else up = __fmaf_rn(a.tau, divergence(a, cf, e0, e1, ln, dsi), un);
     }
     // valid lanes form a prefix of the wave; the F and P loads of kAhead
     // leaves are issued before the first of them is used, to keep enough
@@ -495,8 +616,10 @@ __device__ inline void block_flag_counts(uint32_t n_split, uint32_t n_join, uint
 }
 
 __global__ void __launch_bounds__(kBlk) k_primal(PrimalArgs a, Coef cf) {
+    __shared__ Coef scf;
+    const Coef &lcf = stage_coef(cf, scf);
     uint32_t ns, nj;
-    primal_wave(a, cf, (int64_t)blockIdx.x * kBlk + threadIdx.x, ns, nj);
+    primal_wave(a, lcf, (int64_t)blockIdx.x * kBlk + threadIdx.x, ns, nj);
     block_flag_counts<kBlk>(ns, nj, a.part, a.part_stride, blockIdx.x);
 }
 
@@ -509,7 +632,9 @@ __global__ void __launch_bounds__(kBlk) k_primal(PrimalArgs a, Coef cf) {
 //   u <- u + xi (lam div - d'),  d' = sum * inv.
 // The divergence is kept (uprime) so that split children take the same step
 // with their own data term.
-__global__ void __launch_bounds__(kBlk) k_gd_update(PrimalArgs a, Coef cf) {
+__global__ void __launch_bounds__(kBlk) k_gd_update(PrimalArgs a, Coef cf_arg) {
+    __shared__ Coef scf;
+    const Coef &cf = stage_coef(cf_arg, scf);
     const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const bool valid = i < a.L;
@@ -803,7 +928,7 @@ void launch_batch(hipStream_t st, BatchState &b) {
 void launch_dual(Ctx &c, float sigma) {
     LeafStore &s = c.lv();
     const DualArgs a = dual_args(c, sigma);
-    hipLaunchKernelGGL(k_dual, dim3((unsigned)cdiv(c.L, kBlk)), dim3(kBlk), 0, c.stream, a, c.coef);
+    hipLaunchKernelGGL(k_dual, dim3((unsigned)cdiv(c.L, kDualLeaves * kBlk)), dim3(kBlk), 0, c.stream, a, c.coef);
     OTF_LAUNCH_CHECK("k_dual");
     if (s.n_heavy_p > 0) {
         hipLaunchKernelGGL(k_dual_long, dim3((unsigned)s.n_heavy_p), dim3(kBlk), kStageBytes, c.stream,
@@ -834,7 +959,7 @@ void launch_gd_flux(Ctx &c, float eps2) {
     d.ubar = s.u.p;  // the flux differences u itself
     d.gd = 1;
     d.eps2 = eps2;
-    hipLaunchKernelGGL(k_dual, dim3((unsigned)cdiv(c.L, kBlk)), dim3(kBlk), 0, c.stream, d, c.coef);
+    hipLaunchKernelGGL(k_dual, dim3((unsigned)cdiv(c.L, kDualLeaves * kBlk)), dim3(kBlk), 0, c.stream, d, c.coef);
     OTF_LAUNCH_CHECK("k_dual (flux)");
     if (s.n_heavy_p > 0) {
         hipLaunchKernelGGL(k_dual_long, dim3((unsigned)s.n_heavy_p), dim3(kBlk), kStageBytes, c.stream,
