@@ -462,6 +462,21 @@ static int neighbours(unode *n, int d, int s, leafvec *out) {
     return face_leaves(m, d, s, out);
 }
 
+/* The neighbour list of one side (s = +1 or -1) of n: the x neighbours, then
+ * y, then z, each in ascending key; b[d] .. b[d+1] are direction d's entries. */
+static int side_list(unode *n, int s, leafvec *out, int64_t b[4]) {
+    out->n = 0;
+    for (int d = 0; d < 3; ++d) {
+        b[d] = out->n;
+        unode *m = nb_ge(n, d, s);
+        if (!m) continue;
+        int st = face_leaves(m, d, s, out);
+        if (st) return st;
+    }
+    b[3] = out->n;
+    return ORC_OK;
+}
+
 /* Coupling coefficients between face-adjacent leaves (sides in voxel units).
  * Gradient: (Gu)_{n,d} = sum_{k in N+_d(n)} c_nk (u_k - u_n),
  *   c_nk = (min(s_n,s_k)/s_n)^2 / h_nk, h_nk = (s_n + s_k)/2:
@@ -485,20 +500,67 @@ static real coef_div(const orc *o, const unode *m, const unode *n) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Order of the sums over a leaf's neighbours. The paper leaves it open; here */
+/* a side list (x, y, z neighbours, each in ascending key) of at most        */
+/* LONG_LIST entries is summed as one chain in list order. A longer list is  */
+/* summed in NPART interleaved parts: list entry q goes to part q mod NPART, */
+/* each part a chain from 0 in list order, and the parts are then added in   */
+/* part order. (The + side's three direction sums each have their own parts, */
+/* indexed by the position in the whole side list.)                         */
+/* ------------------------------------------------------------------------ */
+#define LONG_LIST 64
+#define NPART 64
+
+/* Gradient sums of n over its + list (b: direction bounds): g[d] = sum of
+ * c_nk (v_k - v_n), C[d] = sum of c_nk over direction d's entries, with v the
+ * ubar (field 0) or u (field 1) values. */
+static void grad_sums(const orc *o, const unode *n, const leafvec *nb, const int64_t b[4], int field, real g[3],
+                      real C[3]) {
+    const real vn = field ? n->u : n->ubar;
+    if (b[3] <= LONG_LIST) {
+        for (int d = 0; d < 3; ++d) {
+            g[d] = 0;
+            C[d] = 0;
+            for (int64_t q = b[d]; q < b[d + 1]; ++q) {
+                const unode *k = nb->a[q];
+                const real c = coef_grad(o, n, k);
+                g[d] = R_FMA(c, (field ? k->u : k->ubar) - vn, g[d]);
+                C[d] = C[d] + c;
+            }
+        }
+        return;
+    }
+    real pg[3][NPART], pc[3][NPART];
+    for (int d = 0; d < 3; ++d)
+        for (int j = 0; j < NPART; ++j) pg[d][j] = pc[d][j] = 0;
+    for (int d = 0; d < 3; ++d)
+        for (int64_t q = b[d]; q < b[d + 1]; ++q) {
+            const unode *k = nb->a[q];
+            const real c = coef_grad(o, n, k);
+            const int j = (int)(q % NPART);
+            pg[d][j] = R_FMA(c, (field ? k->u : k->ubar) - vn, pg[d][j]);
+            pc[d][j] = pc[d][j] + c;
+        }
+    for (int d = 0; d < 3; ++d) {
+        g[d] = 0;
+        C[d] = 0;
+        for (int j = 0; j < NPART; ++j) {
+            g[d] = g[d] + pg[d][j];
+            C[d] = C[d] + pc[d][j];
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* One primal-dual iteration (Jacobi phases).                                */
 /* ------------------------------------------------------------------------ */
 static int dual_leaf(const orc *o, unode *n, real sigma, leafvec *nb) {
-    real q[3];
-    for (int d = 0; d < 3; ++d) {
-        int st = neighbours(n, d, +1, nb);
-        if (st) return st;
-        real g = 0;
-        for (int64_t j = 0; j < nb->n; ++j) {
-            unode *k = nb->a[j];
-            g = R_FMA(coef_grad(o, n, k), k->ubar - n->ubar, g);
-        }
-        q[d] = R_FMA(sigma, g, n->p[d]);
-    }
+    real q[3], g[3], C[3];
+    int64_t b[4];
+    int st = side_list(n, +1, nb, b);
+    if (st) return st;
+    grad_sums(o, n, nb, b, 0, g, C);
+    for (int d = 0; d < 3; ++d) q[d] = R_FMA(sigma, g[d], n->p[d]);
     real r2 = R_FMA(q[0], q[0], R_FMA(q[1], q[1], q[2] * q[2]));
     if (r2 > (real)1) {
         real nrm = R_SQRT(r2);
@@ -510,23 +572,33 @@ static int dual_leaf(const orc *o, unode *n, real sigma, leafvec *nb) {
 }
 
 static int div_leaf(const orc *o, unode *n, leafvec *nb, real *out) {
-    /* own (outgoing) terms first, x, y, z; then incoming terms, x, y, z, each in
-     * ascending neighbour key */
+    /* own (outgoing) terms first, x, y, z; then the incoming terms of the -
+     * list (x, y, z, each in ascending neighbour key) */
+    real g[3], C[3];
+    int64_t b[4];
+    int st = side_list(n, +1, nb, b);
+    if (st) return st;
+    grad_sums(o, n, nb, b, 0, g, C);
     real acc = 0;
-    for (int d = 0; d < 3; ++d) {
-        int st = neighbours(n, d, +1, nb);
-        if (st) return st;
-        real C = 0;
-        for (int64_t j = 0; j < nb->n; ++j) C = C + coef_grad(o, n, nb->a[j]);
-        acc = R_FMA(C, n->p[d], acc);
-    }
-    for (int d = 0; d < 3; ++d) {
-        int st = neighbours(n, d, -1, nb);
-        if (st) return st;
-        for (int64_t j = 0; j < nb->n; ++j) {
-            unode *m = nb->a[j];
-            acc = R_FMA(-coef_div(o, m, n), m->p[d], acc);
-        }
+    for (int d = 0; d < 3; ++d) acc = R_FMA(C[d], n->p[d], acc);
+    st = side_list(n, -1, nb, b);
+    if (st) return st;
+    if (b[3] <= LONG_LIST) {
+        for (int d = 0; d < 3; ++d)
+            for (int64_t q = b[d]; q < b[d + 1]; ++q) {
+                unode *m = nb->a[q];
+                acc = R_FMA(-coef_div(o, m, n), m->p[d], acc);
+            }
+    } else {
+        real part[NPART];
+        for (int j = 0; j < NPART; ++j) part[j] = 0;
+        for (int d = 0; d < 3; ++d)
+            for (int64_t q = b[d]; q < b[d + 1]; ++q) {
+                unode *m = nb->a[q];
+                const int j = (int)(q % NPART);
+                part[j] = R_FMA(-coef_div(o, m, n), m->p[d], part[j]);
+            }
+        for (int j = 0; j < NPART; ++j) acc = acc + part[j];
     }
     *out = acc;
     return ORC_OK;
@@ -575,17 +647,11 @@ static int primal_leaf(const orc *o, unode *n, real tau, real tl, leafvec *nb) {
 /* q is kept in p; div is the same volume-weighted adjoint as above.          */
 /* ------------------------------------------------------------------------ */
 static int gd_flux_leaf(const orc *o, unode *n, real eps2, leafvec *nb) {
-    real g[3];
-    for (int d = 0; d < 3; ++d) {
-        int st = neighbours(n, d, +1, nb);
-        if (st) return st;
-        real acc = 0;
-        for (int64_t j = 0; j < nb->n; ++j) {
-            unode *k = nb->a[j];
-            acc = R_FMA(coef_grad(o, n, k), k->u - n->u, acc);
-        }
-        g[d] = acc;
-    }
+    real g[3], C[3];
+    int64_t b[4];
+    int st = side_list(n, +1, nb, b);
+    if (st) return st;
+    grad_sums(o, n, nb, b, 1, g, C);
     real r2 = R_FMA(g[0], g[0], R_FMA(g[1], g[1], g[2] * g[2]));
     real den = R_SQRT(r2 + eps2);
     for (int d = 0; d < 3; ++d) n->p[d] = g[d] / den;

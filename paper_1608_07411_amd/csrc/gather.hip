@@ -47,9 +47,11 @@ __global__ void __launch_bounds__(kBlk) k_gather(ViewDev vd, int64_t n, const ui
         const uint32_t key = tkey[h];
         const int L = tlevel[h];
         uint32_t node, l;
-        if (vd.table && L >= vd.table_level) {  // start at the dense index
-            const uint32_t e =
-                vd.table[(size_t)(key >> (3 * (D - vd.table_level))) * (uint32_t)vd.n_views + (uint32_t)j];
+        const bool fine = vd.table && L >= vd.table_level;
+        if (fine || (vd.table_c && L >= vd.table_c_level)) {  // start at a dense index
+            const uint32_t *tab = fine ? vd.table : vd.table_c;
+            const int T = fine ? vd.table_level : vd.table_c_level;
+            const uint32_t e = tab[(size_t)(key >> (3 * (D - T))) * (uint32_t)vd.n_views + (uint32_t)j];
             node = e & ((1u << kTableIdxBits) - 1u);
             l = e >> kTableIdxBits;
         } else {
@@ -72,10 +74,8 @@ __global__ void __launch_bounds__(kBlk) k_gather(ViewDev vd, int64_t n, const ui
     const uint64_t ballot = __ballot(valid);
     const uint64_t segmask = (SEG == 64) ? ~0ull : (((1ull << SEG) - 1ull) << seg_lane0);
     const int m = __popcll(ballot & segmask);
-    if (count_only) {
-        if (t < n && j == 0) o.Mcount[t] = (uint8_t)m;
-        return;
-    }
+    if (o.Mcount && t < n && j == 0) o.Mcount[t] = (uint8_t)m;
+    if (count_only) return;
     int rank = 0;
 #pragma unroll
     for (int i = 0; i < SEG; ++i) {
@@ -140,6 +140,13 @@ void gather_fill(Ctx &c, int64_t n, const uint32_t *tkey, const uint8_t *tlevel,
                  uint8_t *unit, float *inv, float *wtot, float *u0, uint32_t *off_out) {
     if (n <= 0) return;
     GatherOut o{tidx, out_off, base, stride, F, W, P, nullptr, M, unit, inv, wtot, u0, off_out};
+    gather_launch(c, n, tkey, tlevel, o, false);
+}
+
+void gather_rows(Ctx &c, int64_t n, const uint32_t *tkey, const uint8_t *tlevel, const uint32_t *tidx, int stride,
+                 float *F, float *W, float *P, uint8_t *Mt, uint8_t *M, uint8_t *unit, float *inv, float *wtot) {
+    if (n <= 0) return;
+    GatherOut o{tidx, nullptr, 0, stride, F, W, P, Mt, M, unit, inv, wtot, nullptr, nullptr};
     gather_launch(c, n, tkey, tlevel, o, false);
 }
 
@@ -254,12 +261,13 @@ __global__ void k_view_table(ViewDev vd, int T, int64_t n, uint32_t *table) {
     }
     table[t] = ((uint32_t)l << kTableIdxBits) | node;
 }
-constexpr int kTableLevel = 6;  // 8^6 cells x up to 64 views x 4 bytes = 64 MiB
+constexpr int kTableLevel = 6;        // 8^6 cells x up to 64 views x 4 bytes = 64 MiB
+constexpr int kTableLevelCoarse = 3;  // 512 cells x up to 64 views
 }  // namespace
 
 void build_view_table(Ctx &c) {
     ViewStore &vs = c.views;
-    vs.table_level = -1;
+    vs.table_level = vs.table_c_level = -1;
     if (vs.n_nodes >= (int64_t(1) << kTableIdxBits) || c.n_views <= 0) return;  // indices do not fit: no index
     const int T = std::min(c.prm.max_depth, kTableLevel);
     const int64_t n = (int64_t(1) << (3 * T)) * c.n_views;
@@ -267,6 +275,15 @@ void build_view_table(Ctx &c) {
     hipLaunchKernelGGL(k_view_table, dim3((unsigned)cdiv(n, kBlk)), dim3(kBlk), 0, c.stream, c.view_dev(), T, n,
                        vs.table.p);
     OTF_LAUNCH_CHECK("k_view_table");
+    if (T > kTableLevelCoarse) {  // a coarser index for targets above the fine one
+        const int Tc = kTableLevelCoarse;
+        const int64_t nc = (int64_t(1) << (3 * Tc)) * c.n_views;
+        vs.table_c.reserve(nc);
+        hipLaunchKernelGGL(k_view_table, dim3((unsigned)cdiv(nc, kBlk)), dim3(kBlk), 0, c.stream, c.view_dev(), Tc,
+                           nc, vs.table_c.p);
+        OTF_LAUNCH_CHECK("k_view_table");
+        vs.table_c_level = Tc;
+    }
     vs.table_level = T;
 }
 

@@ -173,10 +173,18 @@ __global__ void k_chunk_count(uint32_t n_items, Heavy hv, uint32_t *nch) {
     if (t < n_items) nch[t] = (hv.hi[t] - hv.lo[t] + kChunk - 1) / kChunk;
 }
 
-__global__ void k_chunk_expand(uint32_t n_items, const uint32_t *base, uint32_t *item) {
-    const uint32_t t = blockIdx.x * kBlk + threadIdx.x;
-    if (t >= n_items) return;
-    for (uint32_t c = base[t]; c < base[t + 1]; ++c) item[c] = t;
+// chunk -> item: one thread per chunk, the last item whose first chunk is at
+// or before it (every item has at least one chunk, so base rises strictly)
+__global__ void k_chunk_expand(uint32_t n_items, uint32_t n_chunks, const uint32_t *base, uint32_t *item) {
+    const uint32_t c = blockIdx.x * kBlk + threadIdx.x;
+    if (c >= n_chunks) return;
+    uint32_t lo = 0, hi = n_items;  // base[lo] <= c < base[hi]
+    while (hi - lo > 1) {
+        const uint32_t m = (lo + hi) >> 1;
+        if (base[m] <= c) lo = m;
+        else hi = m;
+    }
+    item[c] = lo;
 }
 
 template <bool FILL>
@@ -455,7 +463,8 @@ void search_end(Ctx &c, NbrPending &p, void (*overlap)(Ctx &)) {
         c.s.ch_count.reserve(n_chunks + 1);
         c.s.ch_pos.reserve(n_chunks + 1);
         ch = Chunks{c.s.ch_item.p, c.s.ch_base.p, c.s.ch_count.p, c.s.ch_pos.p};
-        hipLaunchKernelGGL(k_chunk_expand, dim3(gi), dim3(kBlk), 0, c.stream, n_heavy, c.s.ch_base.p, c.s.ch_item.p);
+        hipLaunchKernelGGL(k_chunk_expand, dim3((unsigned)cdiv(n_chunks, kBlk)), dim3(kBlk), 0, c.stream, n_heavy,
+                           n_chunks, c.s.ch_base.p, c.s.ch_item.p);
         hipLaunchKernelGGL(k_nbr_chunk<false>, dim3((unsigned)cdiv((int64_t)n_chunks * 64, kBlk)), dim3(kBlk), 0,
                            c.stream, n_chunks, hv, ch, s.key.p, s.level.p, D, (const uint32_t *)c.s.g.p,
                            (const uint32_t *)nullptr, (const uint32_t *)nullptr, (uint32_t *)nullptr,

@@ -223,10 +223,10 @@ struct ViewStore {
     DBuf<uint32_t> cnt, child, key;
     DBuf<uint8_t> level;
     DBuf<uint32_t> root;               // per view: pool index of the root
-    // dense index at level table_level (-1: none): per cell (Morton order)
-    // and view, the deepest node containing the cell, (level << 28) | index
-    DBuf<uint32_t> table;
-    int table_level = -1;
+    // dense indices at two levels (-1: none): per cell (Morton order) and
+    // view, the deepest node containing the cell, (level << 28) | index
+    DBuf<uint32_t> table, table_c;
+    int table_level = -1, table_c_level = -1;
     std::vector<int64_t> count, base;  // per view node count and pool offset (host)
     int64_t n_nodes = 0;
 };
@@ -240,6 +240,8 @@ struct ViewDev {
     int max_depth;
     const uint32_t *table;  // dense index (null: descend from the roots)
     int table_level;
+    const uint32_t *table_c;  // coarser dense index (null: none)
+    int table_c_level;
 };
 constexpr uint32_t kTableIdxBits = 28;
 
@@ -372,7 +374,8 @@ struct Ctx {
     ViewDev view_dev() const {
         return ViewDev{views.S.p,         views.cnt.p, views.child.p,
                        views.root.p,      n_views,     prm.max_depth,
-                       views.table_level >= 0 ? views.table.p : nullptr, views.table_level};
+                       views.table_level >= 0 ? views.table.p : nullptr, views.table_level,
+                       views.table_c_level >= 0 ? views.table_c.p : nullptr, views.table_c_level};
     }
 };
 
@@ -423,6 +426,10 @@ void gather_count(Ctx &c, int64_t n, const uint32_t *tkey, const uint8_t *tlevel
 void gather_fill(Ctx &c, int64_t n, const uint32_t *tkey, const uint8_t *tlevel, const uint32_t *tidx,
                  const uint32_t *out_off, uint32_t base, int stride, float *F, float *W, float *P, uint8_t *M,
                  uint8_t *unit, float *inv, float *wtot, float *u0, uint32_t *off_out);
+// gather_fill into rows of `stride` entries (row t at t * stride) that also
+// records the per-target count Mt[t]
+void gather_rows(Ctx &c, int64_t n, const uint32_t *tkey, const uint8_t *tlevel, const uint32_t *tidx, int stride,
+                 float *F, float *W, float *P, uint8_t *Mt, uint8_t *M, uint8_t *unit, float *inv, float *wtot);
 // dense index of the view octrees (after they change)
 void build_view_table(Ctx &c);
 // pool-compacting gather for every leaf of the current store (two passes)

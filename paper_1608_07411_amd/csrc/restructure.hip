@@ -443,10 +443,24 @@ __global__ void k_compact_idx(int64_t n, const uint8_t *flag, const uint32_t *ra
     if (r < cap) idx[r] = (uint32_t)i;
 }
 
-__global__ void k_scatter_m(int64_t n, const uint32_t *tidx, const uint8_t *Mt, uint8_t *M) {
-    const int64_t t = TID();
+// New leaves' observations from their rows (target t: row t * stride, Mt[t]
+// entries) to the pool at base + (off_t ? off_t[t] : off_leaf[tidx[t]]), one
+// wave per target; the segment offset goes into the leaf header.
+__global__ void k_place_obs(int64_t n, const uint32_t *tidx, const uint8_t *Mt, int stride, const float *F0,
+                            const float *W0, const float *P0, const uint32_t *off_t, const uint32_t *off_leaf,
+                            uint32_t base, float *F1, float *W1, float *P1, uint32_t *obs_off) {
+    const int64_t t = ((int64_t)blockIdx.x * kBlk + threadIdx.x) >> 6;
+    const int k = threadIdx.x & 63;
     if (t >= n) return;
-    M[tidx[t]] = Mt[t];
+    const uint32_t h = tidx[t];
+    const uint32_t dst = base + (off_t ? off_t[t] : off_leaf[h]);
+    if (k < Mt[t]) {
+        const size_t src = (size_t)t * stride + k;
+        F1[dst + k] = F0[src];
+        W1[dst + k] = W0[src];
+        P1[dst + k] = P0[src];
+    }
+    if (k == 0) obs_off[h] = dst;
 }
 
 // One wave per leaf: lane k copies observation k (M <= 64).
@@ -466,10 +480,6 @@ __global__ void k_copy_segments(int64_t L, const uint8_t *isnew, const uint8_t *
     if (k == 0) obs_off[i] = dst;
 }
 
-__global__ void k_take(int64_t n, const uint32_t *tidx, const uint32_t *src, uint32_t *dst) {
-    const int64_t t = TID();
-    if (t < n) dst[t] = src[tidx[t]];
-}
 
 Round &round_at(Ctx &c, size_t r) {
     while (c.s.rounds.size() <= r) c.s.rounds.push_back(new Round());
@@ -723,13 +733,19 @@ bool restructure(Ctx &c, float tl) {
     hipLaunchKernelGGL(k_zero_u32, dim3(grid(n_new)), dim3(kBlk), 0, c.stream, (int64_t)n_new, tidx.p);
     hipLaunchKernelGGL(k_compact_idx, dim3(grid(Lnew)), dim3(kBlk), 0, c.stream, Lnew, isnew.p, nrank.p, tidx.p,
                        n_new);
+    // one fetch pass: sorted observations into rows of n_views (headers
+    // written into the new store), placed into the pool once its offsets are
+    // known
     DBuf<uint8_t> &Mt = s.r_Mt;
     Mt.reserve(n_new);
-    gather_count(c, n_new, ns.key.p, ns.level.p, tidx.p, Mt.p);
+    const int stride = c.n_views;
+    s.fa.reserve((size_t)n_new * stride);
+    s.fb.reserve((size_t)n_new * stride);
+    s.fe.reserve((size_t)n_new * stride);
+    gather_rows(c, n_new, ns.key.p, ns.level.p, tidx.p, stride, s.fa.p, s.fb.p, s.fe.p, Mt.p, ns.obs_m.p,
+                ns.obs_unit.p, ns.inv.p, ns.wtot.p);
     moff.reserve(n_new + 1);
     scan_exclusive_u32_dev_u8(c, Mt.p, moff.p, n_new);
-    hipLaunchKernelGGL(k_scatter_m, dim3(grid(n_new)), dim3(kBlk), 0, c.stream, (int64_t)n_new, tidx.p, Mt.p,
-                       ns.obs_m.p);
     ObsPool &pool = c.op();
     // live observations of the new store
     DBuf<uint32_t> &loff = s.r_loff;
@@ -746,8 +762,10 @@ bool restructure(Ctx &c, float tl) {
     if (c.h_counters[21] != n_new) fail(OTF_E_DEVICE, "new-leaf counts disagree");
     const bool compact = (pool.used + (int64_t)new_obs > pool.cap) || (pool.used > 2 * (int64_t)live + 4096);
     if (!compact) {
-        gather_fill(c, n_new, ns.key.p, ns.level.p, tidx.p, moff.p, (uint32_t)pool.used, 0, pool.F.p, pool.W.p,
-                    pool.P.p, ns.obs_m.p, ns.obs_unit.p, ns.inv.p, ns.wtot.p, nullptr, ns.obs_off.p);
+        hipLaunchKernelGGL(k_place_obs, dim3(grid(64 * (int64_t)n_new)), dim3(kBlk), 0, c.stream, (int64_t)n_new,
+                           tidx.p, Mt.p, stride, s.fa.p, s.fb.p, s.fe.p, moff.p, (const uint32_t *)nullptr,
+                           (uint32_t)pool.used, pool.F.p, pool.W.p, pool.P.p, ns.obs_off.p);
+        OTF_LAUNCH_CHECK("k_place_obs");
         pool.used += new_obs;
     } else {
         ObsPool &np = c.obs[c.ocur ^ 1];
@@ -755,11 +773,10 @@ bool restructure(Ctx &c, float tl) {
         hipLaunchKernelGGL(k_copy_segments, dim3(grid(64 * Lnew)), dim3(kBlk), 0, c.stream, Lnew, isnew.p,
                            ns.obs_m.p, loff.p, ns.obs_off.p, pool.F.p, pool.W.p, pool.P.p, np.F.p, np.W.p, np.P.p);
         OTF_LAUNCH_CHECK("k_copy_segments");
-        DBuf<uint32_t> &toff = s.r_toff;
-        toff.reserve(n_new);
-        hipLaunchKernelGGL(k_take, dim3(grid(n_new)), dim3(kBlk), 0, c.stream, (int64_t)n_new, tidx.p, loff.p, toff.p);
-        gather_fill(c, n_new, ns.key.p, ns.level.p, tidx.p, toff.p, 0, 0, np.F.p, np.W.p, np.P.p, ns.obs_m.p,
-                    ns.obs_unit.p, ns.inv.p, ns.wtot.p, nullptr, ns.obs_off.p);
+        hipLaunchKernelGGL(k_place_obs, dim3(grid(64 * (int64_t)n_new)), dim3(kBlk), 0, c.stream, (int64_t)n_new,
+                           tidx.p, Mt.p, stride, s.fa.p, s.fb.p, s.fe.p, (const uint32_t *)nullptr, loff.p, 0u,
+                           np.F.p, np.W.p, np.P.p, ns.obs_off.p);
+        OTF_LAUNCH_CHECK("k_place_obs");
         np.used = live;
         c.ocur ^= 1;
         OTF_HIP(hipStreamSynchronize(c.stream));

@@ -13,6 +13,10 @@
 //   ubar = 2 u+ - u,  u = u+
 //   flags: split if |u+| < tau_s below max depth, joinable if |u+| > tau_j.
 // Every floating-point operation is a single IEEE operation in a fixed order.
+// Sums over a + or - list of at most kLongList entries are one chain in list
+// order (x, y, z neighbours, each in ascending key); a longer list is summed
+// in 64 interleaved parts (entry q to part q mod 64, each part a chain from 0
+// in list order), the parts then added in part order.
 #include "otf_internal.h"
 
 namespace otf {
@@ -75,7 +79,7 @@ __device__ inline void dual_finish(const DualArgs &a, int64_t i, float gx, float
 }
 
 // Dual update of leaf i (one thread); a leaf with a long + list is left to
-// dual_long_block.
+// dual_long_wave.
 __device__ inline void dual_leaf(const DualArgs &a, const Coef &cf, int64_t i) {
     const uint32_t e0 = a.off[i], e1 = a.off[i + 1];
     if (e1 - e0 > kLongList) return;
@@ -231,140 +235,60 @@ __global__ void __launch_bounds__(kBlk) k_dual(DualArgs a, Coef cf) {
     dual_leaves(a, lcf, idx);
 }
 
-// Leaves with a long + list, one 256-thread block each: the block stages the
-// list's coefficients, neighbour differences and directions in LDS with
-// parallel loads (kUnroll entries per thread in flight). The list holds the
-// +x, +y and +z neighbours one face after another, so the three fma chains of
-// k_dual are contiguous segments: lanes 0, 1 and 2 fold one each, in list
-// order. Lists beyond the LDS budget are folded in 64-entry chunks by the
-// first wave, the next chunk fetched while one is folded.
-constexpr int kStageBytes = 64 * 1024;
-constexpr uint32_t kDualStage = kStageBytes / 9;    // float c, float diff, u8 dir
-constexpr uint32_t kPrimalStage = kStageBytes / 8;  // float c', float p
+// Leaves whose + list is longer than kLongList, one wave each. Such a list is
+// summed in 64 interleaved parts: lane j folds the entries at list positions
+// j, j + 64, j + 128, ... (an fma chain from 0 in list order, one per
+// direction, with the coefficient sums alongside), then the 64 parts of each
+// sum are added in lane order. Lane j's loads of kLongUnroll entries are in
+// flight together; the wave's loads are coalesced.
+constexpr int kLongUnroll = 4;
+constexpr int kWavesPerBlock = kBlk / 64;
 
-__device__ void dual_long_chunked(const DualArgs &a, const Coef &cf, int64_t i, int lane) {
-    const int ln = a.level[i];
-    const float ub = a.ubar[i];
-    const uint32_t e0 = a.off[i], e1 = a.off[i + 1];
-    float gx = 0.0f, gy = 0.0f, gz = 0.0f, Cx = 0.0f, Cy = 0.0f, Cz = 0.0f;
-    float c = 0.0f, diff = 0.0f;
-    int d = 0;
-    if (e0 + lane < e1) {
-        const uint32_t v = a.ent[e0 + lane];
-        d = (v >> kIdxBits) & 3;
-        c = cf.c[ln][v >> (kIdxBits + 2)];
-        diff = a.ubar[v & kIdxMask] - ub;
-    }
-    for (uint32_t base = e0; base < e1; base += 64) {
-        float cn = 0.0f, diffn = 0.0f;
-        int dn = 0;
-        const uint32_t en = base + 64 + lane;
-        if (en < e1) {
-            const uint32_t v = a.ent[en];
-            dn = (v >> kIdxBits) & 3;
-            cn = cf.c[ln][v >> (kIdxBits + 2)];
-            diffn = a.ubar[v & kIdxMask] - ub;
-        }
-        const int cnt = (int)min(64u, e1 - base);
-        for (int j = 0; j < cnt; ++j) {
-            const float cj = rdlane(c, j), vj = rdlane(diff, j);
-            const int dj = rdlane_i(d, j);
-            if (dj == 0) {
-                gx = __fmaf_rn(cj, vj, gx);
-                Cx = Cx + cj;
-            } else if (dj == 1) {
-                gy = __fmaf_rn(cj, vj, gy);
-                Cy = Cy + cj;
-            } else {
-                gz = __fmaf_rn(cj, vj, gz);
-                Cz = Cz + cj;
-            }
-        }
-        c = cn;
-        diff = diffn;
-        d = dn;
-    }
-    if (lane == 0) dual_finish(a, i, gx, gy, gz, Cx, Cy, Cz);
+// sum of the 64 lanes' v, added in lane order (the same value on every lane)
+__device__ inline float lane_order_sum(float v) {
+    float s = 0.0f;
+    for (int j = 0; j < 64; ++j) s = s + rdlane(v, j);
+    return s;
 }
 
-__device__ inline uint32_t first_dir_at_least(const uint8_t *sd, uint32_t n, int d) {
-    uint32_t lo = 0, hi = n;
-    while (lo < hi) {
-        const uint32_t m = (lo + hi) >> 1;
-        if (sd[m] < d) lo = m + 1;
-        else hi = m;
-    }
-    return lo;
-}
-
-// The whole 256-thread block works on leaf i; smem holds kStageBytes.
-__device__ void dual_long_block(const DualArgs &a, const Coef &cf, int64_t i, unsigned char *smem) {
-    const uint32_t e0 = a.off[i], e1 = a.off[i + 1], ne = e1 - e0;
-    if (ne > kDualStage) {
-        if (threadIdx.x < 64) dual_long_chunked(a, cf, i, threadIdx.x);
-        return;
-    }
-    float *sc = reinterpret_cast<float *>(smem);
-    float *sv = sc + kDualStage;
-    uint8_t *sd = reinterpret_cast<uint8_t *>(sv + kDualStage);
+__device__ void dual_long_wave(const DualArgs &a, const Coef &cf, int64_t i, int lane) {
+    const uint32_t e0 = a.off[i], ne = a.off[i + 1] - e0;
     const int ln = a.level[i];
     const float ub = a.ubar[i];
-    for (uint32_t q0 = threadIdx.x; q0 < ne; q0 += kUnroll * kBlk) {
-        uint32_t v[kUnroll];
-        float u[kUnroll];
+    float g[3] = {0.0f, 0.0f, 0.0f}, C[3] = {0.0f, 0.0f, 0.0f};
+    for (uint32_t q0 = lane; q0 < ne; q0 += 64 * kLongUnroll) {
+        uint32_t v[kLongUnroll];
+        float u[kLongUnroll];
 #pragma unroll
-        for (int r = 0; r < kUnroll; ++r) {
-            const uint32_t q = q0 + r * kBlk;
-            v[r] = q < ne ? a.ent[e0 + q] : 0u;
+        for (int r = 0; r < kLongUnroll; ++r) {
+            const uint32_t q = q0 + 64 * r;
+            v[r] = a.ent[e0 + (q < ne ? q : 0u)];
         }
 #pragma unroll
-        for (int r = 0; r < kUnroll; ++r) {
-            const uint32_t q = q0 + r * kBlk;
-            u[r] = q < ne ? a.ubar[v[r] & kIdxMask] : 0.0f;
-        }
+        for (int r = 0; r < kLongUnroll; ++r) u[r] = a.ubar[q0 + 64 * r < ne ? (v[r] & kIdxMask) : 0u];
 #pragma unroll
-        for (int r = 0; r < kUnroll; ++r) {
-            const uint32_t q = q0 + r * kBlk;
-            if (q < ne) {
-                sd[q] = (uint8_t)((v[r] >> kIdxBits) & 3);
-                sc[q] = cf.c[ln][v[r] >> (kIdxBits + 2)];
-                sv[q] = u[r] - ub;
+        for (int r = 0; r < kLongUnroll; ++r) {
+            const int d = q0 + 64 * r < ne ? (int)((v[r] >> kIdxBits) & 3) : 3;
+            const float c = cf.c[ln][v[r] >> (kIdxBits + 2)];
+            const float diff = u[r] - ub;
+#pragma unroll
+            for (int x = 0; x < 3; ++x) {
+                const float gn = __fmaf_rn(c, diff, g[x]), Cn = C[x] + c;
+                g[x] = d == x ? gn : g[x];
+                C[x] = d == x ? Cn : C[x];
             }
         }
     }
-    __syncthreads();
-    if (threadIdx.x >= 64) return;
-    const int lane = threadIdx.x;
-    float g = 0.0f, C = 0.0f;
-    if (lane < 3) {
-        const uint32_t lo = first_dir_at_least(sd, ne, lane), hi = first_dir_at_least(sd, ne, lane + 1);
-        uint32_t q = lo;
-        for (; q + 8 <= hi; q += 8) {
-            float cc[8], vv[8];
-#pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                cc[r] = sc[q + r];
-                vv[r] = sv[q + r];
-            }
-#pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                g = __fmaf_rn(cc[r], vv[r], g);
-                C = C + cc[r];
-            }
-        }
-        for (; q < hi; ++q) {
-            g = __fmaf_rn(sc[q], sv[q], g);
-            C = C + sc[q];
-        }
-    }
-    const float gx = rdlane(g, 0), gy = rdlane(g, 1), gz = rdlane(g, 2);
-    const float Cx = rdlane(C, 0), Cy = rdlane(C, 1), Cz = rdlane(C, 2);
+    const float gx = lane_order_sum(g[0]), gy = lane_order_sum(g[1]), gz = lane_order_sum(g[2]);
+    const float Cx = lane_order_sum(C[0]), Cy = lane_order_sum(C[1]), Cz = lane_order_sum(C[2]);
     if (lane == 0) dual_finish(a, i, gx, gy, gz, Cx, Cy, Cz);
 }
 
 __global__ void __launch_bounds__(kBlk) k_dual_long(uint32_t n, const uint32_t *list, DualArgs a, Coef cf) {
-    extern __shared__ unsigned char smem[];
-    if (blockIdx.x < n) dual_long_block(a, cf, list[blockIdx.x], smem);
+    __shared__ Coef scf;
+    const Coef &lcf = stage_coef(cf, scf);
+    const uint32_t item = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    if (item < n) dual_long_wave(a, lcf, list[item], threadIdx.x & 63);
 }
 
 struct PrimalArgs {
@@ -392,86 +316,40 @@ struct PrimalArgs {
     const float *W;
 };
 
-// u' for leaves with a long - list (sequential fma chain), staged in LDS by a
-// 256-thread block like k_dual_long; u' replaces ds for k_primal.
-__device__ void primal_long_chunked(const PrimalArgs &a, const Coef &cf, int64_t i, int lane) {
+// u' for leaves with a long - list, one wave each: the incoming terms in 64
+// interleaved parts as in dual_long_wave, added to ds in lane order; u'
+// replaces ds for k_primal (gradient descent keeps the divergence itself).
+__device__ void primal_long_wave(const PrimalArgs &a, const Coef &cf, int64_t i, int lane) {
+    const uint32_t e0 = a.off[i], ne = a.off[i + 1] - e0;
     const int ln = a.level[i];
-    const uint32_t e0 = a.off[i], e1 = a.off[i + 1];
-    float acc = a.ds[i];
-    float c = 0.0f, pm = 0.0f;
-    if (e0 + lane < e1) {
-        const uint32_t v = a.ent[e0 + lane];
-        c = cf.cp[v >> (kIdxBits + 2)][ln];
-        pm = a.p[(int64_t)((v >> kIdxBits) & 3) * a.cap + (v & kIdxMask)];
-    }
-    for (uint32_t base = e0; base < e1; base += 64) {
-        float cn = 0.0f, pmn = 0.0f;
-        const uint32_t en = base + 64 + lane;
-        if (en < e1) {
-            const uint32_t v = a.ent[en];
-            cn = cf.cp[v >> (kIdxBits + 2)][ln];
-            pmn = a.p[(int64_t)((v >> kIdxBits) & 3) * a.cap + (v & kIdxMask)];
+    float part = 0.0f;
+    for (uint32_t q0 = lane; q0 < ne; q0 += 64 * kLongUnroll) {
+        uint32_t v[kLongUnroll];
+        float pm[kLongUnroll];
+#pragma unroll
+        for (int r = 0; r < kLongUnroll; ++r) {
+            const uint32_t q = q0 + 64 * r;
+            v[r] = a.ent[e0 + (q < ne ? q : 0u)];
         }
-        const int cnt = (int)min(64u, e1 - base);
-        for (int j = 0; j < cnt; ++j) acc = __fmaf_rn(-rdlane(c, j), rdlane(pm, j), acc);
-        c = cn;
-        pm = pmn;
+#pragma unroll
+        for (int r = 0; r < kLongUnroll; ++r)
+            pm[r] = a.p[q0 + 64 * r < ne ? (int64_t)((v[r] >> kIdxBits) & 3) * a.cap + (v[r] & kIdxMask) : 0];
+#pragma unroll
+        for (int r = 0; r < kLongUnroll; ++r) {
+            const float nx = __fmaf_rn(-cf.cp[v[r] >> (kIdxBits + 2)][ln], pm[r], part);
+            part = q0 + 64 * r < ne ? nx : part;
+        }
     }
+    float acc = a.ds[i];
+    for (int j = 0; j < 64; ++j) acc = acc + rdlane(part, j);
     if (lane == 0) a.ds[i] = a.gd ? acc : __fmaf_rn(a.tau, acc, a.u_in[i]);
 }
 
-__device__ void primal_long_block(const PrimalArgs &a, const Coef &cf, int64_t i, unsigned char *smem) {
-    const uint32_t e0 = a.off[i], e1 = a.off[i + 1], ne = e1 - e0;
-    if (ne > kPrimalStage) {
-        if (threadIdx.x < 64) primal_long_chunked(a, cf, i, threadIdx.x);
-        return;
-    }
-    float *sc = reinterpret_cast<float *>(smem);
-    float *sp = sc + kPrimalStage;
-    const int ln = a.level[i];
-    for (uint32_t q0 = threadIdx.x; q0 < ne; q0 += kUnroll * kBlk) {
-        uint32_t v[kUnroll];
-        float pv[kUnroll];
-#pragma unroll
-        for (int r = 0; r < kUnroll; ++r) {
-            const uint32_t q = q0 + r * kBlk;
-            v[r] = q < ne ? a.ent[e0 + q] : 0u;
-        }
-#pragma unroll
-        for (int r = 0; r < kUnroll; ++r) {
-            const uint32_t q = q0 + r * kBlk;
-            pv[r] = q < ne ? a.p[(int64_t)((v[r] >> kIdxBits) & 3) * a.cap + (v[r] & kIdxMask)] : 0.0f;
-        }
-#pragma unroll
-        for (int r = 0; r < kUnroll; ++r) {
-            const uint32_t q = q0 + r * kBlk;
-            if (q < ne) {
-                sc[q] = cf.cp[v[r] >> (kIdxBits + 2)][ln];
-                sp[q] = pv[r];
-            }
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    float acc = a.ds[i];
-    uint32_t q = 0;
-    for (; q + 8 <= ne; q += 8) {
-        float cc[8], pp[8];
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            cc[r] = sc[q + r];
-            pp[r] = sp[q + r];
-        }
-#pragma unroll
-        for (int r = 0; r < 8; ++r) acc = __fmaf_rn(-cc[r], pp[r], acc);
-    }
-    for (; q < ne; ++q) acc = __fmaf_rn(-sc[q], sp[q], acc);
-    a.ds[i] = a.gd ? acc : __fmaf_rn(a.tau, acc, a.u_in[i]);
-}
-
 __global__ void __launch_bounds__(kBlk) k_primal_long(uint32_t n, const uint32_t *list, PrimalArgs a, Coef cf) {
-    extern __shared__ unsigned char smem[];
-    if (blockIdx.x < n) primal_long_block(a, cf, list[blockIdx.x], smem);
+    __shared__ Coef scf;
+    const Coef &lcf = stage_coef(cf, scf);
+    const uint32_t item = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    if (item < n) primal_long_wave(a, lcf, list[item], threadIdx.x & 63);
 }
 
 // Own divergence term ds minus the incoming terms of the short - list
@@ -803,19 +681,22 @@ __global__ void __launch_bounds__(BLK) k_primal_b(const ObjDev *objs, int nobj, 
     }
 }
 
-// Long lists of all objects: block b is item b - begin[j] of object j's list.
+// Long lists of all objects, one wave per item: item t < n is item
+// t - begin[j] of object j's list.
 __global__ void __launch_bounds__(kBlk) k_dual_long_b(const ObjDev *objs, int nobj, const uint32_t *begin,
-                                                      const Coef *coefs) {
-    extern __shared__ unsigned char smem[];
-    const int j = find_obj(begin, nobj, blockIdx.x);
-    dual_long_block(objs[j].d, coefs[objs[j].D], objs[j].heavy_p[blockIdx.x - begin[j]], smem);
+                                                      uint32_t n, const Coef *coefs) {
+    const uint32_t t = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    if (t >= n) return;
+    const int j = find_obj(begin, nobj, t);
+    dual_long_wave(objs[j].d, coefs[objs[j].D], objs[j].heavy_p[t - begin[j]], threadIdx.x & 63);
 }
 
 __global__ void __launch_bounds__(kBlk) k_primal_long_b(const ObjDev *objs, int nobj, const uint32_t *begin,
-                                                        const Coef *coefs) {
-    extern __shared__ unsigned char smem[];
-    const int j = find_obj(begin, nobj, blockIdx.x);
-    primal_long_block(objs[j].p, coefs[objs[j].D], objs[j].heavy_m[blockIdx.x - begin[j]], smem);
+                                                        uint32_t n, const Coef *coefs) {
+    const uint32_t t = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    if (t >= n) return;
+    const int j = find_obj(begin, nobj, t);
+    primal_long_wave(objs[j].p, coefs[objs[j].D], objs[j].heavy_m[t - begin[j]], threadIdx.x & 63);
 }
 
 // Object j's split and join flag counts from its tiles' partials (block j),
@@ -906,13 +787,13 @@ void launch_batch(hipStream_t st, BatchState &b) {
                        b.ntiles, (const Coef *)b.coefs.p);
     OTF_LAUNCH_CHECK("k_dual_b");
     if (b.n_hp > 0) {
-        hipLaunchKernelGGL(k_dual_long_b, dim3(b.n_hp), dim3(kBlk), kStageBytes, st, objs, nobj,
-                           (const uint32_t *)b.hp_begin.p, (const Coef *)b.coefs.p);
+        hipLaunchKernelGGL(k_dual_long_b, dim3((unsigned)cdiv(b.n_hp, kWavesPerBlock)), dim3(kBlk), 0, st, objs,
+                           nobj, (const uint32_t *)b.hp_begin.p, (uint32_t)b.n_hp, (const Coef *)b.coefs.p);
         OTF_LAUNCH_CHECK("k_dual_long_b");
     }
     if (b.n_hm > 0) {
-        hipLaunchKernelGGL(k_primal_long_b, dim3(b.n_hm), dim3(kBlk), kStageBytes, st, objs, nobj,
-                           (const uint32_t *)b.hm_begin.p, (const Coef *)b.coefs.p);
+        hipLaunchKernelGGL(k_primal_long_b, dim3((unsigned)cdiv(b.n_hm, kWavesPerBlock)), dim3(kBlk), 0, st, objs,
+                           nobj, (const uint32_t *)b.hm_begin.p, (uint32_t)b.n_hm, (const Coef *)b.coefs.p);
         OTF_LAUNCH_CHECK("k_primal_long_b");
     }
     hipLaunchKernelGGL(k_primal_b<BLK>, dim3(grid), dim3(BLK), 0, st, objs, nobj, (const uint32_t *)b.tile_begin.p,
@@ -931,7 +812,7 @@ void launch_dual(Ctx &c, float sigma) {
     hipLaunchKernelGGL(k_dual, dim3((unsigned)cdiv(c.L, kDualLeaves * kBlk)), dim3(kBlk), 0, c.stream, a, c.coef);
     OTF_LAUNCH_CHECK("k_dual");
     if (s.n_heavy_p > 0) {
-        hipLaunchKernelGGL(k_dual_long, dim3((unsigned)s.n_heavy_p), dim3(kBlk), kStageBytes, c.stream,
+        hipLaunchKernelGGL(k_dual_long, dim3((unsigned)cdiv(s.n_heavy_p, kWavesPerBlock)), dim3(kBlk), 0, c.stream,
                            (uint32_t)s.n_heavy_p, s.heavy_p.p, a, c.coef);
         OTF_LAUNCH_CHECK("k_dual_long");
     }
@@ -945,7 +826,7 @@ void launch_primal(Ctx &c, float tau, float tl) {
     a.part = c.s.part.p;
     a.part_stride = nblk;
     if (s.n_heavy_m > 0) {
-        hipLaunchKernelGGL(k_primal_long, dim3((unsigned)s.n_heavy_m), dim3(kBlk), kStageBytes, c.stream,
+        hipLaunchKernelGGL(k_primal_long, dim3((unsigned)cdiv(s.n_heavy_m, kWavesPerBlock)), dim3(kBlk), 0, c.stream,
                            (uint32_t)s.n_heavy_m, s.heavy_m.p, a, c.coef);
         OTF_LAUNCH_CHECK("k_primal_long");
     }
@@ -962,7 +843,7 @@ void launch_gd_flux(Ctx &c, float eps2) {
     hipLaunchKernelGGL(k_dual, dim3((unsigned)cdiv(c.L, kDualLeaves * kBlk)), dim3(kBlk), 0, c.stream, d, c.coef);
     OTF_LAUNCH_CHECK("k_dual (flux)");
     if (s.n_heavy_p > 0) {
-        hipLaunchKernelGGL(k_dual_long, dim3((unsigned)s.n_heavy_p), dim3(kBlk), kStageBytes, c.stream,
+        hipLaunchKernelGGL(k_dual_long, dim3((unsigned)cdiv(s.n_heavy_p, kWavesPerBlock)), dim3(kBlk), 0, c.stream,
                            (uint32_t)s.n_heavy_p, s.heavy_p.p, d, c.coef);
         OTF_LAUNCH_CHECK("k_dual_long (flux)");
     }
@@ -980,7 +861,7 @@ void launch_gd_update(Ctx &c, float lam, float xi, float eps2) {
     a.xi = xi;
     a.eps2 = eps2;
     if (s.n_heavy_m > 0) {
-        hipLaunchKernelGGL(k_primal_long, dim3((unsigned)s.n_heavy_m), dim3(kBlk), kStageBytes, c.stream,
+        hipLaunchKernelGGL(k_primal_long, dim3((unsigned)cdiv(s.n_heavy_m, kWavesPerBlock)), dim3(kBlk), 0, c.stream,
                            (uint32_t)s.n_heavy_m, s.heavy_m.p, a, c.coef);
         OTF_LAUNCH_CHECK("k_primal_long (divergence)");
     }

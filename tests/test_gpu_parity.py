@@ -248,11 +248,11 @@ def _slab_volumes(D, x0, width=2, seed=0):
     return f, np.ones((2, G, G, G), np.uint8)
 
 
-@pytest.mark.parametrize("D,x0", [(7, 64), (7, 62), (8, 128), (8, 126)])
+@pytest.mark.parametrize("D,x0", [(6, 32), (6, 30), (7, 64), (7, 62), (8, 128), (8, 126)])
 def test_long_adjacency_lists_parity(D, x0):
     """Half-domain leaves against a refined slab: + lists (slab right of the
-    middle) or - lists (left of it) of 64^2 entries (staged in LDS) or 128^2
-    (folded in chunks) are summed in the canonical order."""
+    middle) or - lists (left of it) of 32^2 entries (one LDS chunk), 64^2 or
+    128^2 (several chunks) are summed in the canonical order."""
     f, w = _slab_volumes(D, x0)
     o = Oracle("f32").build_volumes(f, w, base_params(D))
     counts, _ = o.neighbours()
