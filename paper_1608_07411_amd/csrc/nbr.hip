@@ -434,6 +434,8 @@ NbrPending search_begin(Ctx &c, const NbrOld &old) {
     return p;
 }
 
+// `overlap` is queued at the first wait for a count (the chunk total, else
+// the list totals).
 void search_end(Ctx &c, NbrPending &p, void (*overlap)(Ctx &)) {
     LeafStore &s = c.lv();
     const int64_t L = c.L;
@@ -457,7 +459,10 @@ void search_end(Ctx &c, NbrPending &p, void (*overlap)(Ctx &)) {
         c.s.ch_base.reserve(n_heavy + 1);
         hipLaunchKernelGGL(k_chunk_count, dim3(gi), dim3(kBlk), 0, c.stream, n_heavy, hv, c.s.ch_base.p);
         scan_exclusive_u32_dev(c, c.s.ch_base.p, c.s.ch_base.p, n_heavy);
-        read_back(c, {{c.s.ch_base.p + n_heavy, 3}});
+        const uint32_t t_ch = read_back_begin(c, {{c.s.ch_base.p + n_heavy, 3}});
+        if (overlap) overlap(c);
+        overlap = nullptr;
+        read_back_wait(c, t_ch);
         n_chunks = c.h_counters[3];
         c.s.ch_item.reserve(n_chunks);
         c.s.ch_count.reserve(n_chunks + 1);

@@ -446,7 +446,7 @@ void build_neighbours(Ctx &c);
 // queues the search up to the count of long ranges and starts reading that
 // count back; _end (after whatever independent work the caller queues in
 // between) finishes it, queueing `overlap` (may be null) while the host waits
-// for the list totals.
+// for its first count.
 struct NbrOld {  // previous store, for leaves that copy their lists
     const uint8_t *need;      // new leaf: 1 = search its lists, 0 = copy them
     const uint32_t *src;      // new leaf -> old index (kept leaves)

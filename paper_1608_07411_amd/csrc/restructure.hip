@@ -528,19 +528,26 @@ void split_rank(Ctx &c) {
 }
 
 // Collapse values: hierarchical means level by level, in place over the old
-// leaf positions (scratch r_jv).
-void join_values(Ctx &c, const uint8_t *jt) {
+// leaf positions (scratch r_jv). Queued in pieces (the initial copy, then one
+// level each), so that they can fill several host waits: `next` is the first
+// piece not yet queued, at most `count` are queued now.
+void join_values(Ctx &c, const uint8_t *jt, int &next, int count) {
     const int64_t L = c.L;
     const int D = c.prm.max_depth;
     LeafStore &os = c.lv();
     DBuf<float> &val = c.s.r_jv;
-    val.reserve(5 * (size_t)L);
     const OldStore osd{os.key.p, os.level.p, os.u.p, os.ubar.p, os.p.p, os.cap, os.obs_off.p, os.obs_m.p,
                        os.obs_unit.p, os.inv.p, os.wtot.p, os.flag.p};
-    hipLaunchKernelGGL(k_jval_init, dim3(grid(L)), dim3(kBlk), 0, c.stream, L, jt, osd, val.p, L);
-    for (int q = D - 1; q >= 0; --q)
-        hipLaunchKernelGGL(k_jval_level, dim3(grid(L)), dim3(kBlk), 0, c.stream, L, D, q, jt, os.key.p, os.level.p,
-                           val.p, L);
+    for (; count > 0 && next <= D; --count, ++next) {
+        if (next == 0) {
+            val.reserve(5 * (size_t)L);
+            hipLaunchKernelGGL(k_jval_init, dim3(grid(L)), dim3(kBlk), 0, c.stream, L, jt, osd, val.p, L);
+        } else {
+            const int q = D - next;  // levels D-1 .. 0
+            hipLaunchKernelGGL(k_jval_level, dim3(grid(L)), dim3(kBlk), 0, c.stream, L, D, q, jt, os.key.p,
+                               os.level.p, val.p, L);
+        }
+    }
     OTF_LAUNCH_CHECK("join means");
 }
 
@@ -569,10 +576,9 @@ bool restructure(Ctx &c, float tl) {
     if (n_split > 0 && !spec_split) split_rank(c);
     const uint8_t *jt = n_join > 0 ? s.u8a.p : nullptr;
     const uint8_t *jhead = n_join > 0 ? s.u8b.p : nullptr;
-    bool jvals_queued = false;
-    auto queue_join_values = [&] {
-        if (jt && !jvals_queued) join_values(c, jt);
-        jvals_queued = true;
+    int jv_next = 0;  // pieces of the collapse values queued so far
+    auto queue_join_values = [&](int count) {
+        if (jt) join_values(c, jt, jv_next, count);
     };
 
     // ---- split cascade
@@ -627,7 +633,7 @@ bool restructure(Ctx &c, float tl) {
             OTF_LAUNCH_CHECK("k_cascade_prox");
             scan_exclusive_u32_dev_u8(c, R.csplit.p, R.crank.p, nc);
             const uint32_t t_next = read_back_begin(c, {{R.crank.p + nc, 8}});
-            queue_join_values();  // independent of the cascade: keeps the device busy meanwhile
+            queue_join_values(5);  // independent of the cascade: keeps the device busy meanwhile
             read_back_wait(c, t_next);
             const uint32_t next = c.h_counters[8];
             if (next > nc) fail(OTF_E_DEVICE, "split cascade count out of range");
@@ -646,7 +652,7 @@ bool restructure(Ctx &c, float tl) {
             OTF_LAUNCH_CHECK("k_leafcnt");
         }
     }
-    queue_join_values();
+    queue_join_values(D + 1);
 
     // ---- emission
     s.e.reserve(L + 1);
