@@ -207,13 +207,14 @@ double dual_bytes(const Ctx &c) {
 }
 
 // Algorithmic bytes of one primal sweep: level, ds, u, the - adjacency, p
-// once per leaf, the observation header (offset, count, unit flag, normaliser,
-// total weight); writes u, ubar and the flag byte. The observation segments
-// (F, plus P for leaves with fractional weights: 4 bytes each) are added from
-// the device-side accumulator when read.
+// once per leaf, the observation header (offset, count, normaliser, total
+// weight); writes u, ubar and the flag byte. The observation segments (F,
+// plus P for leaves with fractional weights, 4 bytes each: with unit weights
+// P_k = k is implied, although the kernel reads it too) are added from the
+// device-side accumulator when read.
 double primal_bytes(const Ctx &c) {
     const double L = (double)c.L;
-    return L * (1 + 4 + 4 + 12) + 4.0 * (double)c.leaves[c.cur].n_nbm + L * (4 + 1 + 1 + 4 + 4) + L * (4 + 4 + 1);
+    return L * (1 + 4 + 4 + 12) + 4.0 * (double)c.leaves[c.cur].n_nbm + L * (4 + 1 + 4 + 4) + L * (4 + 4 + 1);
 }
 
 }  // namespace otf

@@ -389,7 +389,7 @@ __device__ inline void primal_wave(const PrimalArgs &a, const Coef &cf, int64_t 
     const int lane = threadIdx.x & 63;
     const bool valid = i < a.L;
     float up = 0.0f, un = 0.0f, t = 0.0f, wt = 0.0f;
-    int M = 0, unit = 1, ln = 0;
+    int M = 0, ln = 0;
     uint32_t oo = 0;
     if (valid) {
         // the leaf's own loads first, all in flight before the divergence's
@@ -400,7 +400,6 @@ __device__ inline void primal_wave(const PrimalArgs &a, const Coef &cf, int64_t 
         const float dsi = a.ds[i];
         M = a.obs_m[i];
         oo = a.obs_off[i];
-        unit = a.obs_unit[i];
         const float inv = a.inv[i];
         wt = a.wtot[i];
         t = a.tl * inv;
@@ -414,48 +413,41 @@ __device__ inline void primal_wave(const PrimalArgs &a, const Coef &cf, int64_t 
     float myv = 0.0f;
     for (int l0 = 0; l0 < nact; l0 += kAhead) {
         float Fr[kAhead], Pr[kAhead];
+        // unconditional loads (lanes past a segment's end, and leaves past
+        // the wave's last, read its first entry, inside the pool's
+        // allocation), so that leaf g's compute waits only for its own loads
 #pragma unroll
         for (int g = 0; g < kAhead; ++g) {
-            const int l = l0 + g;
-            Fr[g] = 0.0f;
-            Pr[g] = 0.0f;
-            if (l < nact) {
-                const int Ml = rdlane_i(M, l);
-                const uint32_t ool = (uint32_t)rdlane_i((int)oo, l);
-                if (lane < Ml) {
-                    Fr[g] = a.F[ool + lane];
-                    if (!rdlane_i(unit, l)) Pr[g] = a.P[ool + lane];
-                }
-            }
-        }
-#pragma unroll
-        for (int g = 0; g < kAhead; ++g) {
-            const int l = l0 + g;
-            if (l >= nact) break;
+            const int l = min(l0 + g, 63);
             const int Ml = rdlane_i(M, l);
-            const float upl = rdlane(up, l);
-            float v = upl;
-            if (Ml > 0) {
-                const float tl_ = rdlane(t, l), wtl = rdlane(wt, l);
-                const int unitl = rdlane_i(unit, l);
-                const float Fk = Fr[g];
-                float pk = 0.0f;
-                bool pred = false;
-                if (lane < Ml) {
-                    const float S = unitl ? (float)(2 * lane - Ml) : __fmaf_rn(2.0f, Pr[g], -wtl);
-                    pk = __fmaf_rn(-tl_, S, upl);
-                    pred = pk > Fk;
-                }
-                const int ks = __popcll(__ballot(pred));
-                const float pks = (ks < Ml) ? rdlane(pk, ks) : __fmaf_rn(-tl_, unitl ? (float)Ml : wtl, upl);
-                v = pks;
-                if (ks > 0) {
-                    const float Fp = rdlane(Fk, ks - 1);
-                    v = (pks >= Fp) ? pks : Fp;
-                }
-            }
+            const uint32_t ool = (uint32_t)rdlane_i((int)oo, l);
+            const uint32_t e = ool + (lane < Ml ? (uint32_t)lane : 0u);
+            Fr[g] = a.F[e];
+            Pr[g] = a.P[e];
+        }
+        // every leaf of the group computed without branches (a leaf past the
+        // wave's last reads lane 63 and is dropped), so that no load is
+        // deferred into a conditional block
+#pragma unroll
+        for (int g = 0; g < kAhead; ++g) {
+            const int l = l0 + g;
+            const int lc = min(l, 63);
+            const int Ml = rdlane_i(M, lc);
+            const float upl = rdlane(up, lc), tl_ = rdlane(t, lc), wtl = rdlane(wt, lc);
+            const float Fk = Fr[g];
+            // S_k = 2 P_k - W_tot for every leaf (with unit weights P_k = k and
+            // W_tot = M exactly); lanes at or past Ml compute a value never used
+            const float S = __fmaf_rn(2.0f, Pr[g], -wtl);
+            const float pk = __fmaf_rn(-tl_, S, upl);
+            const bool pred = lane < Ml && pk > Fk;
+            const int ks = __popcll(__ballot(pred));
+            const float pend = __fmaf_rn(-tl_, wtl, upl);
+            const float pks = (ks < Ml) ? rdlane(pk, min(ks, 63)) : pend;
+            const float Fp = rdlane(Fk, max(ks - 1, 0));
+            float v = (ks > 0) ? ((pks >= Fp) ? pks : Fp) : pks;
+            v = (Ml > 0) ? v : upl;
             v = v + 0.0f;
-            if (lane == l) myv = v;
+            myv = (lane == l && l < nact) ? v : myv;
         }
     }
     bool split = false, join = false;
