@@ -164,6 +164,15 @@ otf_status otf_import_state(otf_ctx *ctx, const void *buf, int64_t n_bytes);
 otf_status otf_profile(otf_ctx *ctx, int32_t enable);
 otf_status otf_profile_read(otf_ctx *ctx, double *ms, int64_t *launches, int64_t *leaf_updates, double *bytes);
 
+/* Self-test of the device prefix scans every compaction above relies on:
+ * n pseudo-random elements (splitmix64 from seed) are scanned on the context's
+ * device (exclusive sums of bytes and of words, two scans sharing a launch,
+ * the max-scan of join-run starts, the sum of flag bits) and compared with the
+ * same scans on the host; *mismatches is the number of differing outputs
+ * (0: all equal). Needs no fused state. Errors: OTF_E_INVALID (null, n < 0 or
+ * n > 2^28), OTF_E_NOMEM, OTF_E_DEVICE. */
+otf_status otf_selftest_scan(otf_ctx *ctx, int64_t n, uint64_t seed, int64_t *mismatches);
+
 /* Message of the last failure on this context (empty if none). Valid until the
  * next call on the context. */
 const char *otf_last_error(const otf_ctx *ctx);

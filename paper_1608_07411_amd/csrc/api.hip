@@ -428,6 +428,72 @@ otf_status otf_fuse_gd(otf_ctx *ctx, int32_t iterations, float lambda, float ste
     });
 }
 
+otf_status otf_selftest_scan(otf_ctx *ctx, int64_t n, uint64_t seed, int64_t *mismatches) {
+    if (!ctx || !mismatches || n < 0 || n > (int64_t(1) << 28)) return OTF_E_INVALID;
+    return guard(ctx, false, [&] {
+        Ctx &c = ctx->c;
+        // inputs from splitmix64
+        uint64_t st = seed;
+        auto next = [&] {
+            uint64_t z = (st += 0x9E3779B97F4A7C15ull);
+            z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+            z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+            return z ^ (z >> 31);
+        };
+        std::vector<uint8_t> a(n), b(n), f(n);
+        std::vector<uint32_t> x(n), y(n);
+        for (int64_t i = 0; i < n; ++i) {
+            const uint64_t r = next();
+            a[i] = (uint8_t)(r & 3);
+            b[i] = (uint8_t)((r >> 2) & 1);
+            // join bits in runs: keep the previous value with probability 7/8
+            const uint8_t jb = (uint8_t)(((r >> 3) & 3) << 1);
+            f[i] = (uint8_t)((i > 0 && ((r >> 5) & 7) != 0 ? (f[i - 1] & 6) : jb) | ((r >> 8) & 1));
+            x[i] = (uint32_t)((r >> 16) & 0xFFF);
+            y[i] = (uint32_t)(r >> 40) & 0x3FF;
+        }
+        DBuf<uint8_t> da, db, df;
+        DBuf<uint32_t> dx, dy, o1, o2, o3, o4, o5, o6, o7;
+        const int64_t m = n > 0 ? n : 1;
+        da.reserve(m); db.reserve(m); df.reserve(m); dx.reserve(m); dy.reserve(m);
+        for (DBuf<uint32_t> *o : {&o1, &o2, &o3, &o4, &o5, &o6, &o7}) o->reserve(m + 1);
+        upload(c, da.p, a);
+        upload(c, db.p, b);
+        upload(c, df.p, f);
+        upload(c, dx.p, x);
+        upload(c, dy.p, y);
+        scan_exclusive_u32_dev_u8(c, da.p, o1.p, n);
+        scan_exclusive_pair_u8(c, da.p, o2.p, db.p, o3.p, n);
+        scan_exclusive_pair_u32(c, dx.p, o4.p, dy.p, o5.p, n);
+        scan_run_starts(c, df.p, o6.p, n);
+        scan_exclusive_flag_bits(c, df.p, 1u, o7.p, n);
+        finish(c);
+        auto g1 = download(c, o1.p, n + 1), g2 = download(c, o2.p, n + 1), g3 = download(c, o3.p, n + 1);
+        auto g4 = download(c, o4.p, n + 1), g5 = download(c, o5.p, n + 1), g6 = download(c, o6.p, n);
+        auto g7 = download(c, o7.p, n + 1);
+        int64_t bad = 0;
+        uint32_t sa = 0, sb = 0, sx = 0, sy = 0, sf = 0, run = 0;
+        for (int64_t i = 0; i <= n; ++i) {
+            bad += g1[i] != sa;
+            bad += g2[i] != sa;
+            bad += g3[i] != sb;
+            bad += g4[i] != sx;
+            bad += g5[i] != sy;
+            bad += g7[i] != sf;
+            if (i == n) break;
+            const uint32_t j = f[i] & 6u;
+            if (j && (i == 0 || (f[i - 1] & 6u) != j)) run = (uint32_t)i;
+            bad += g6[i] != run;
+            sa += a[i];
+            sb += b[i];
+            sx += x[i];
+            sy += y[i];
+            sf += f[i] & 1u;
+        }
+        *mismatches = bad;
+    });
+}
+
 otf_status otf_num_leaves(const otf_ctx *ctx, int64_t *n) {
     if (!ctx || !n) return OTF_E_INVALID;
     if (!ctx->c.valid) return OTF_E_STATE;

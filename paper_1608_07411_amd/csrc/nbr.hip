@@ -401,7 +401,7 @@ uint32_t count_pass(Ctx &c, NbrPending &p) {
     return read_back_begin(c, {{c.counters.p + 3, 3}});
 }
 
-NbrPending search_begin(Ctx &c, const NbrOld &old) {
+NbrPending search_begin(Ctx &c, const NbrOld &old, bool need_scanned) {
     LeafStore &s = c.lv();
     const int64_t L = c.L;
     const int D = c.prm.max_depth;
@@ -421,9 +421,11 @@ NbrPending search_begin(Ctx &c, const NbrOld &old) {
     // leaves to search: all of them, or (after a restructure) those marked in
     // need, listed at their rank dpos[i]; their number dpos[L] stays on the device
     if (old.need) {
-        c.s.e.reserve(L + 1);
+        if (!need_scanned) {
+            c.s.e.reserve(L + 1);
+            scan_exclusive_u32_dev_u8(c, old.need, c.s.e.p, L);
+        }
         c.s.dirty.reserve(L);
-        scan_exclusive_u32_dev_u8(c, old.need, c.s.e.p, L);
         hipLaunchKernelGGL(k_nbr_count_clean, dim3(g), dim3(kBlk), 0, c.stream, L, c.s.a.p, c.s.b.p, old,
                            (const uint32_t *)c.s.e.p, c.s.dirty.p);
         OTF_LAUNCH_CHECK("k_nbr_count_clean");
@@ -480,8 +482,7 @@ void search_end(Ctx &c, NbrPending &p, void (*overlap)(Ctx &)) {
                            c.s.b.p);
         OTF_LAUNCH_CHECK("k_chunk_totals");
     }
-    scan_exclusive_u32_dev(c, c.s.a.p, s.nbp_off.p, L);
-    scan_exclusive_u32_dev(c, c.s.b.p, s.nbm_off.p, L);
+    scan_exclusive_pair_u32(c, c.s.a.p, s.nbp_off.p, c.s.b.p, s.nbm_off.p, L);
     // work lists of the leaves with long lists need only the offsets
     s.heavy_p.reserve(L);
     s.heavy_m.reserve(L);
@@ -525,17 +526,19 @@ void search_end(Ctx &c, NbrPending &p, void (*overlap)(Ctx &)) {
 }  // namespace
 
 void build_neighbours(Ctx &c) {
-    NbrPending p =
-        search_begin(c, NbrOld{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0u, 0u});
+    NbrPending p = search_begin(
+        c, NbrOld{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0u, 0u}, false);
     search_end(c, p, nullptr);
 }
 
-NbrPending build_neighbours_begin(Ctx &c, const LeafStore &old, const uint32_t *remap) {
+NbrPending build_neighbours_begin(Ctx &c, const LeafStore &old, const uint32_t *remap, bool need_scanned) {
     const LeafStore &s = c.lv();
     // an unchanged leaf with a long list had that list in the previous store,
     // so it is on one of the old long-list work lists
-    return search_begin(c, NbrOld{s.need.p, s.src.p, old.nbp_off.p, old.nbm_off.p, old.nbp.p, old.nbm.p, remap,
-                                  old.heavy_p.p, old.heavy_m.p, (uint32_t)old.n_heavy_p, (uint32_t)old.n_heavy_m});
+    return search_begin(c,
+                        NbrOld{s.need.p, s.src.p, old.nbp_off.p, old.nbm_off.p, old.nbp.p, old.nbm.p, remap,
+                               old.heavy_p.p, old.heavy_m.p, (uint32_t)old.n_heavy_p, (uint32_t)old.n_heavy_m},
+                        need_scanned);
 }
 
 void build_neighbours_end(Ctx &c, NbrPending &p, void (*overlap)(Ctx &)) { search_end(c, p, overlap); }

@@ -409,6 +409,15 @@ uint32_t scan_exclusive_u32(Ctx &c, const uint32_t *in, uint32_t *out, int64_t n
 void scan_exclusive_u32_dev(Ctx &c, const uint32_t *in, uint32_t *out, int64_t n);
 void scan_exclusive_u32_dev_u8(Ctx &c, const uint8_t *in, uint32_t *out, int64_t n);
 void scan_inclusive_max_u32(Ctx &c, const uint32_t *in, uint32_t *out, int64_t n);
+// two exclusive scans of the same length in one launch (out arrays of n+1)
+void scan_exclusive_pair_u8(Ctx &c, const uint8_t *a, uint32_t *out_a, const uint8_t *b, uint32_t *out_b, int64_t n);
+void scan_exclusive_pair_u32(Ctx &c, const uint32_t *a, uint32_t *out_a, const uint32_t *b, uint32_t *out_b,
+                             int64_t n);
+// inclusive max-scan of the run starts of equal non-zero join bits (flag & 6):
+// out[i] = the first index of the run containing i (0 outside runs before any)
+void scan_run_starts(Ctx &c, const uint8_t *flag, uint32_t *out, int64_t n);
+// exclusive scan of (flag[i] & mask) != 0; out has n+1 entries, out[n] = total
+void scan_exclusive_flag_bits(Ctx &c, const uint8_t *flag, uint32_t mask, uint32_t *out, int64_t n);
 // dst[j] = sum over b < nblocks of part[j * stride + b] for j < k (per-block
 // partial counts written by a kernel; a fixed order, no atomics)
 void sum_parts(Ctx &c, const uint32_t *part, int64_t nblocks, int k, int64_t stride, uint32_t *dst);
@@ -460,7 +469,9 @@ struct NbrPending {
     uint32_t ticket, cap;
     const uint32_t *dirty, *n_dirty_dev;
 };
-NbrPending build_neighbours_begin(Ctx &c, const LeafStore &old, const uint32_t *remap);
+// need_scanned: the exclusive scan of the new store's need flags (L+1
+// entries) is already in the scratch array s.e
+NbrPending build_neighbours_begin(Ctx &c, const LeafStore &old, const uint32_t *remap, bool need_scanned);
 void build_neighbours_end(Ctx &c, NbrPending &p, void (*overlap)(Ctx &));
 // sweeps
 void launch_dual(Ctx &c, float sigma);

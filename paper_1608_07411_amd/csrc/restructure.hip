@@ -23,20 +23,7 @@ constexpr int kBlk = 256;
 unsigned grid(int64_t n) { return (unsigned)cdiv(n > 0 ? n : 1, kBlk); }
 #define TID() ((int64_t)blockIdx.x * kBlk + threadIdx.x)
 
-__global__ void k_split_bits(int64_t L, const uint8_t *flag, uint8_t *out) {
-    const int64_t i = TID();
-    if (i < L) out[i] = flag[i] & 1;
-}
-
 // ---------------------------------------------------------------- joins
-__global__ void k_run_heads(int64_t L, const uint8_t *flag, uint32_t *head) {
-    const int64_t i = TID();
-    if (i >= L) return;
-    const uint8_t j = flag[i] & 6;
-    const bool b = j && (i == 0 || (flag[i - 1] & 6) != j);
-    head[i] = b ? (uint32_t)i : 0u;
-}
-
 __global__ void k_run_ends(int64_t L, const uint8_t *flag, const uint32_t *rs, uint32_t *runend) {
     const int64_t i = TID();
     if (i >= L) return;
@@ -502,13 +489,11 @@ void join_analysis(Ctx &c) {
     const unsigned gL = grid(L);
     Scratch &s = c.s;
     LeafStore &os = c.lv();
-    s.a.reserve(L);
     s.b.reserve(L);
     s.c.reserve(L);
     s.u8a.reserve(L);
     s.u8b.reserve(L);
-    hipLaunchKernelGGL(k_run_heads, dim3(gL), dim3(kBlk), 0, c.stream, L, os.flag.p, s.a.p);
-    scan_inclusive_max_u32(c, s.a.p, s.b.p, L);
+    scan_run_starts(c, os.flag.p, s.b.p, L);
     hipLaunchKernelGGL(k_run_ends, dim3(gL), dim3(kBlk), 0, c.stream, L, os.flag.p, s.b.p, s.c.p);
     s.part.reserve(gL);
     hipLaunchKernelGGL(k_join_target, dim3(gL), dim3(kBlk), 0, c.stream, L, c.prm.max_depth, os.flag.p, os.key.p,
@@ -521,10 +506,8 @@ void join_analysis(Ctx &c) {
 void split_rank(Ctx &c) {
     const int64_t L = c.L;
     Scratch &s = c.s;
-    s.r_sf.reserve(L);
     s.d.reserve(L + 1);
-    hipLaunchKernelGGL(k_split_bits, dim3(grid(L)), dim3(kBlk), 0, c.stream, L, c.lv().flag.p, s.r_sf.p);
-    scan_exclusive_u32_dev_u8(c, s.r_sf.p, s.d.p, L);
+    scan_exclusive_flag_bits(c, c.lv().flag.p, 1u, s.d.p, L);
 }
 
 // Collapse values: hierarchical means level by level, in place over the old
@@ -732,7 +715,10 @@ bool restructure(Ctx &c, float tl) {
     // ---- observations of the new leaves (append to the pool, or compact)
     DBuf<uint32_t> &nrank = s.r_nrank, &tidx = s.r_tidx, &moff = s.r_moff;
     nrank.reserve(Lnew + 1);
-    scan_exclusive_u32_dev_u8(c, isnew.p, nrank.p, Lnew);
+    // ranks of the new leaves, and of the leaves whose adjacency is searched
+    // again (for the adjacency pass), in one launch
+    s.e.reserve(Lnew + 1);
+    scan_exclusive_pair_u8(c, isnew.p, nrank.p, ns.need.p, s.e.p, Lnew);
     tidx.reserve(n_new);
     // cleared first, so that every entry is a valid leaf index even if the
     // two counts of new leaves were to disagree (checked below)
@@ -753,16 +739,15 @@ bool restructure(Ctx &c, float tl) {
     moff.reserve(n_new + 1);
     scan_exclusive_u32_dev_u8(c, Mt.p, moff.p, n_new);
     ObsPool &pool = c.op();
-    // live observations of the new store
-    DBuf<uint32_t> &loff = s.r_loff;
-    loff.reserve(Lnew + 1);
-    scan_exclusive_u32_dev_u8(c, ns.obs_m.p, loff.p, Lnew);
-    const uint32_t t_obs = read_back_begin(c, {{moff.p + n_new, 19}, {loff.p + Lnew, 20}, {nrank.p + Lnew, 21}});
-    // the new store becomes current; its adjacency search does not depend on
-    // the observation pool and runs while the host waits
+    // the new store becomes current; its observation totals (the live
+    // observations among them) are counted, and its adjacency search, which
+    // does not depend on the observation pool, runs while the host waits
     c.cur ^= 1;
     c.L = Lnew;
-    NbrPending nbr = build_neighbours_begin(c, os, out_off);
+    count_obs(c);
+    const uint32_t t_obs =
+        read_back_begin(c, {{moff.p + n_new, 19}, {c.counters.p + 4, 20}, {nrank.p + Lnew, 21}});
+    NbrPending nbr = build_neighbours_begin(c, os, out_off, true);
     read_back_wait(c, t_obs);
     const uint32_t new_obs = c.h_counters[19], live = c.h_counters[20];
     if (c.h_counters[21] != n_new) fail(OTF_E_DEVICE, "new-leaf counts disagree");
@@ -776,6 +761,9 @@ bool restructure(Ctx &c, float tl) {
     } else {
         ObsPool &np = c.obs[c.ocur ^ 1];
         np.reserve((int64_t)live + live / 4 + 1024);
+        DBuf<uint32_t> &loff = s.r_loff;  // segment offsets in the compacted pool
+        loff.reserve(Lnew + 1);
+        scan_exclusive_u32_dev_u8(c, ns.obs_m.p, loff.p, Lnew);
         hipLaunchKernelGGL(k_copy_segments, dim3(grid(64 * Lnew)), dim3(kBlk), 0, c.stream, Lnew, isnew.p,
                            ns.obs_m.p, loff.p, ns.obs_off.p, pool.F.p, pool.W.p, pool.P.p, np.F.p, np.W.p, np.P.p);
         OTF_LAUNCH_CHECK("k_copy_segments");
@@ -787,9 +775,7 @@ bool restructure(Ctx &c, float tl) {
         c.ocur ^= 1;
         OTF_HIP(hipStreamSynchronize(c.stream));
     }
-    // the observation totals of the new store are counted while the host
-    // waits for the adjacency list totals
-    build_neighbours_end(c, nbr, count_obs);
+    build_neighbours_end(c, nbr, nullptr);
     return true;
 }
 

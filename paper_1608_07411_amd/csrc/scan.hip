@@ -79,6 +79,40 @@ __device__ inline void load_items(const uint8_t *in, int64_t first, int64_t n, b
     }
 }
 
+// Input adaptors whose elements are formed from a byte array as they are
+// loaded (no intermediate array): FlagBitIn: 1 where flag & mask is non-zero;
+// RunHeadIn: i where leaf i starts a run of equal non-zero join bits
+// (flag & 6), else 0.
+struct FlagBitIn {
+    const uint8_t *flag;
+    uint32_t mask;
+};
+struct RunHeadIn {
+    const uint8_t *flag;
+};
+
+__device__ inline void load_items(const FlagBitIn &in, int64_t first, int64_t n, bool vec, uint32_t (&v)[kItems]) {
+    load_items(in.flag, first, n, vec, v);
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) v[k] = (v[k] & in.mask) ? 1u : 0u;
+}
+
+__device__ inline void load_items(const RunHeadIn &in, int64_t first, int64_t n, bool vec, uint32_t (&v)[kItems]) {
+    load_items(in.flag, first, n, vec, v);  // 0 past the end
+    uint32_t prev = (first > 0 && first - 1 < n) ? (uint32_t)(in.flag[first - 1] & 6u) : 0u;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const uint32_t j = v[k] & 6u;
+        const int64_t i = first + k;
+        v[k] = (j != 0u && (i == 0 || prev != j)) ? (uint32_t)i : 0u;
+        prev = j;
+    }
+}
+
+__host__ inline bool host_aligned16(const void *p) { return (uintptr_t)p % 16 == 0; }
+__host__ inline bool host_aligned16(const FlagBitIn &in) { return host_aligned16(in.flag); }
+__host__ inline bool host_aligned16(const RunHeadIn &in) { return host_aligned16(in.flag); }
+
 __device__ inline void store_items(uint32_t *out, int64_t first, int64_t n, bool vec, const uint32_t (&o)[kItems]) {
     if (vec && first + kItems <= n) {
         uint4 *q = reinterpret_cast<uint4 *>(out + first);
@@ -110,13 +144,23 @@ __device__ inline uint64_t pack_state(uint32_t epoch, uint32_t status, uint32_t 
     return ((uint64_t)epoch << 34) | ((uint64_t)status << 32) | value;
 }
 
+// Two scans of the same length can share one launch: blocks [ntiles,
+// 2 ntiles) scan (in2, out2) with their own tile states.
 template <class In, class Op>
-__global__ void __launch_bounds__(kThreads) k_scan(const In *in, int64_t n, uint32_t *out, Op op, int exclusive,
+__global__ void __launch_bounds__(kThreads) k_scan(In in, int64_t n, uint32_t *out, Op op, int exclusive,
                                                    int vec, uint32_t *total_out, unsigned long long *state,
-                                                   uint32_t epoch, int64_t ntiles, uint32_t *health) {
+                                                   uint32_t epoch, int64_t ntiles, uint32_t *health, In in2,
+                                                   uint32_t *out2, uint32_t *total_out2) {
     __shared__ uint32_t smem[kWaves];
     __shared__ uint32_t s_prefix;
-    const int64_t tile = blockIdx.x;
+    const bool second = (int64_t)blockIdx.x >= ntiles;
+    const int64_t tile = (int64_t)blockIdx.x - (second ? ntiles : 0);
+    if (second) {
+        in = in2;
+        out = out2;
+        total_out = total_out2;
+        state += ntiles;
+    }
     const int64_t first = tile * kTile + (int64_t)threadIdx.x * kItems;
     uint32_t v[kItems];
     load_items(in, first, n, vec != 0, v);
@@ -195,15 +239,19 @@ __global__ void fill_u64(unsigned long long *p, int64_t n) {
 }
 
 template <class In, class Op>
-void scan_any(Ctx &c, const In *in, uint32_t *out, int64_t n, Op op, bool exclusive, uint32_t *total_dev) {
+void scan_any(Ctx &c, In in, uint32_t *out, int64_t n, Op op, bool exclusive, uint32_t *total_dev, In in2 = In{},
+              uint32_t *out2 = nullptr, uint32_t *total_dev2 = nullptr) {
+    const bool pair = out2 != nullptr;
     if (n <= 0) {
         if (total_dev) hipLaunchKernelGGL(fill_u32, dim3(1), dim3(64), 0, c.stream, total_dev, (int64_t)1, 0u);
+        if (total_dev2) hipLaunchKernelGGL(fill_u32, dim3(1), dim3(64), 0, c.stream, total_dev2, (int64_t)1, 0u);
         return;
     }
     const int64_t tiles = cdiv(n, kTile);
+    const int64_t nstate = pair ? 2 * tiles : tiles;
     ScanState &ss = c.s.scan;
-    if ((size_t)tiles > ss.state.n || !ss.state.p) {
-        ss.state.reserve((size_t)tiles);
+    if ((size_t)nstate > ss.state.n || !ss.state.p) {
+        ss.state.reserve((size_t)nstate);
         hipLaunchKernelGGL(fill_u64, dim3((unsigned)cdiv((int64_t)ss.state.n, 256)), dim3(256), 0, c.stream,
                            ss.state.p, (int64_t)ss.state.n);
         ss.epoch = 0;
@@ -213,10 +261,14 @@ void scan_any(Ctx &c, const In *in, uint32_t *out, int64_t n, Op op, bool exclus
                            ss.state.p, (int64_t)ss.state.n);
         ss.epoch = 1;
     }
-    const int vec = ((uintptr_t)in % 16 == 0 && (uintptr_t)out % 16 == 0) ? 1 : 0;
-    hipLaunchKernelGGL((k_scan<In, Op>), dim3((unsigned)tiles), dim3(kThreads), 0, c.stream, in, n, out, op,
+    const int vec = (host_aligned16(in) && host_aligned16(out) &&
+                     (!pair || (host_aligned16(in2) && host_aligned16(out2))))
+                        ? 1
+                        : 0;
+    hipLaunchKernelGGL((k_scan<In, Op>), dim3((unsigned)nstate), dim3(kThreads), 0, c.stream, in, n, out, op,
                        exclusive ? 1 : 0, vec, total_dev, ss.state.p, ss.epoch, tiles,
-                       c.counters.p + kScanHealthSlot);
+                       c.counters.p + kScanHealthSlot, pair ? in2 : in, pair ? out2 : out,
+                       pair ? total_dev2 : total_dev);
     OTF_LAUNCH_CHECK("k_scan");
 }
 
@@ -345,6 +397,24 @@ void sum_parts(Ctx &c, const uint32_t *part, int64_t nblocks, int k, int64_t str
 
 void scan_inclusive_max_u32(Ctx &c, const uint32_t *in, uint32_t *out, int64_t n) {
     scan_any(c, in, out, n, MaxOp{}, false, (uint32_t *)nullptr);
+}
+
+void scan_exclusive_pair_u8(Ctx &c, const uint8_t *a, uint32_t *out_a, const uint8_t *b, uint32_t *out_b,
+                            int64_t n) {
+    scan_any(c, a, out_a, n, AddOp{}, true, out_a + n, b, out_b, out_b + n);
+}
+
+void scan_exclusive_pair_u32(Ctx &c, const uint32_t *a, uint32_t *out_a, const uint32_t *b, uint32_t *out_b,
+                             int64_t n) {
+    scan_any(c, a, out_a, n, AddOp{}, true, out_a + n, b, out_b, out_b + n);
+}
+
+void scan_run_starts(Ctx &c, const uint8_t *flag, uint32_t *out, int64_t n) {
+    scan_any(c, RunHeadIn{flag}, out, n, MaxOp{}, false, (uint32_t *)nullptr);
+}
+
+void scan_exclusive_flag_bits(Ctx &c, const uint8_t *flag, uint32_t mask, uint32_t *out, int64_t n) {
+    scan_any(c, FlagBitIn{flag, mask}, out, n, AddOp{}, true, out + n);
 }
 
 }  // namespace otf

@@ -78,6 +78,7 @@ def lib():
             "otf_batch_add": [P, P],
             "otf_batch_fuse": [P, I32, C.c_float, C.c_float, C.c_float],
             "otf_batch_config": [P, P, P, P, P],
+            "otf_selftest_scan": [P, I64, C.c_uint64, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -253,6 +254,13 @@ class Context:
         """Replace u (and ubar) and p of every leaf by the network's prediction."""
         self._check(self._lib.otf_warm_start(self.h, net.h), "otf_warm_start")
         return self
+
+    def selftest_scan(self, n: int, seed: int = 0) -> int:
+        """Device scans against host scans on n pseudo-random elements; the
+        number of differing outputs."""
+        bad = C.c_int64(0)
+        self._check(self._lib.otf_selftest_scan(self.h, n, seed, C.byref(bad)), "otf_selftest_scan")
+        return bad.value
 
     def num_leaves(self) -> int:
         n = C.c_int64(0)
