@@ -109,10 +109,15 @@ __global__ void __launch_bounds__(kBlk) k_nbr_count_clean(int64_t L, uint32_t *c
 // Searched leaves, 8 lanes per leaf (lane f < 6 takes face f), grid-stride
 // over the n leaves of the list (all leaves when dirty is null; n is read from
 // n_dev when given).
+// The located face of list item q is kept for the fill pass: cj[6q + face] =
+// the first leaf, cm[6q + face] = 0 for a single neighbour, else the mask of
+// the range's leaves that touch the face (ranges of at most kLight leaves);
+// cj = kNone for a face without such a neighbour set (none, or a long range,
+// whose count the chunk kernels fill in later).
 __global__ void __launch_bounds__(kBlk) k_nbr_count(KeyIndex ki, const uint8_t *__restrict__ level, int D,
                                                     uint32_t *cnt_p, uint32_t *cnt_m, uint32_t *fc,
                                                     const uint32_t *dirty, const uint32_t *n_dev, int64_t n_host,
-                                                    Heavy hv) {
+                                                    Heavy hv, uint32_t *cj, uint32_t *cm) {
     const uint32_t *__restrict__ key = ki.key;
     const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
     const int face = threadIdx.x & 7;
@@ -125,11 +130,18 @@ __global__ void __launch_bounds__(kBlk) k_nbr_count(KeyIndex ki, const uint8_t *
             uint32_t xyz[3];
             demorton3(key[i], xyz[0], xyz[1], xyz[2]);
             const Face f = locate(ki, level, D, xyz, ln, face);
+            uint32_t jo = kNone, mo = 0u;
             if (f.inside) {
                 if (f.single) {
                     nf = 1;
+                    jo = (uint32_t)f.j;
                 } else if ((uint64_t)(f.hi - f.j) <= kLight) {
-                    for (int64_t m = f.j; m < f.hi; ++m) nf += on_face(key[m], level[m], D, face, f.plane) ? 1u : 0u;
+                    uint32_t mask = 0;
+                    for (int64_t m = f.j; m < f.hi; ++m)
+                        if (on_face(key[m], level[m], D, face, f.plane)) mask |= 1u << (uint32_t)(m - f.j);
+                    nf = (uint32_t)__popc(mask);
+                    jo = mask ? (uint32_t)f.j : kNone;  // (a cell's face is always covered: mask != 0)
+                    mo = mask;
                 } else {
                     const uint32_t slot = atomicAdd(hv.count, 1u);  // rare: a large leaf by a fine region
                     if (slot < hv.cap) {
@@ -141,6 +153,8 @@ __global__ void __launch_bounds__(kBlk) k_nbr_count(KeyIndex ki, const uint8_t *
                 }
             }
             fc[6 * i + face] = nf;  // long ranges are counted by the chunk kernels
+            cj[6 * q + face] = jo;
+            cm[6 * q + face] = mo;
         }
         uint32_t sp = face < 3 ? nf : 0u, sm = face < 3 ? 0u : nf;
 #pragma unroll
@@ -314,35 +328,34 @@ __global__ void __launch_bounds__(kBlk) k_nbr_fill_clean(int64_t L, const uint32
 // Searched leaves, 8 lanes per leaf as in k_nbr_count: lane f writes face f's
 // short range after the leaf's earlier faces; long ranges are written by the
 // chunk fill.
-__global__ void __launch_bounds__(kBlk) k_nbr_fill(KeyIndex ki, const uint8_t *__restrict__ level, int D,
+// (the faces located by k_nbr_count are read back from cj / cm)
+__global__ void __launch_bounds__(kBlk) k_nbr_fill(const uint8_t *__restrict__ level,
                                                    const uint32_t *__restrict__ fc, const uint32_t *__restrict__ off_p,
                                                    const uint32_t *__restrict__ off_m, uint32_t *ent_p,
                                                    uint32_t *ent_m, const uint32_t *dirty, const uint32_t *n_dev,
-                                                   int64_t n_host) {
-    const uint32_t *__restrict__ key = ki.key;
+                                                   int64_t n_host, const uint32_t *__restrict__ cj,
+                                                   const uint32_t *__restrict__ cm) {
     const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
     const int face = threadIdx.x & 7;
     if (face >= 6) return;
     const int64_t stride = ((int64_t)gridDim.x * kBlk) >> 3;
     for (int64_t q = ((int64_t)blockIdx.x * kBlk + threadIdx.x) >> 3; q < n; q += stride) {
         const int64_t i = dirty ? (int64_t)dirty[q] : q;
-        const uint32_t nf = fc[6 * i + face];
-        if (nf == 0) continue;
+        const uint32_t j = cj[6 * q + face];
+        if (j == kNone) continue;  // no neighbour, or a long range (written by the chunk fill)
         uint32_t w = face < 3 ? off_p[i] : off_m[i];
         for (int f = (face < 3 ? 0 : 3); f < face; ++f) w += fc[6 * i + f];
         uint32_t *ent = face < 3 ? ent_p : ent_m;
-        const int ln = level[i];
-        uint32_t xyz[3];
-        demorton3(key[i], xyz[0], xyz[1], xyz[2]);
-        const Face fa = locate(ki, level, D, xyz, ln, face);
-        if (fa.single) {
-            ent[w] = entry(fa.j, face, level[fa.j]);
-        } else if ((uint64_t)(fa.hi - fa.j) <= kLight) {
-            for (int64_t m = fa.j; m < fa.hi; ++m) {
-                const int lm = level[m];
-                if (on_face(key[m], lm, D, face, fa.plane)) ent[w++] = entry(m, face, lm);
+        uint32_t mask = cm[6 * q + face];
+        if (mask == 0u) {
+            ent[w] = entry(j, face, level[j]);
+        } else {
+            while (mask) {  // ascending index order
+                const uint32_t b = (uint32_t)__ffs((int)mask) - 1u;
+                mask &= mask - 1u;
+                ent[w++] = entry(j + b, face, level[j + b]);
             }
-        }  // else: written by the heavy fill
+        }
     }
 }
 
@@ -396,7 +409,8 @@ uint32_t count_pass(Ctx &c, NbrPending &p) {
     Heavy hv{c.s.hv_leaf.p, c.s.hv_face.p, c.s.hv_lo.p, c.s.hv_hi.p, c.counters.p + 3, p.cap};
     hipLaunchKernelGGL(k_zero_n, dim3(1), dim3(64), 0, c.stream, c.counters.p + 3, 1);
     hipLaunchKernelGGL(k_nbr_count, dim3(grid8(c.L)), dim3(kBlk), 0, c.stream, key_index(c), s.level.p,
-                       c.prm.max_depth, c.s.a.p, c.s.b.p, c.s.g.p, p.dirty, p.n_dirty_dev, c.L, hv);
+                       c.prm.max_depth, c.s.a.p, c.s.b.p, c.s.g.p, p.dirty, p.n_dirty_dev, c.L, hv, c.s.nb_j.p,
+                       c.s.nb_m.p);
     OTF_LAUNCH_CHECK("k_nbr_count");
     return read_back_begin(c, {{c.counters.p + 3, 3}});
 }
@@ -409,6 +423,8 @@ NbrPending search_begin(Ctx &c, const NbrOld &old, bool need_scanned) {
     c.s.a.reserve(L + 1);
     c.s.b.reserve(L + 1);
     c.s.g.reserve(6 * L);
+    c.s.nb_j.reserve(6 * L);
+    c.s.nb_m.reserve(6 * L);
     const int shift = std::max(0, 3 * D - 20);
     const uint32_t nb = 1u << (3 * D - shift);
     c.s.key_table.reserve(nb);
@@ -452,7 +468,6 @@ void search_end(Ctx &c, NbrPending &p, void (*overlap)(Ctx &)) {
         n_heavy = c.h_counters[3];
         if (n_heavy > p.cap) fail(OTF_E_DEVICE, "long-range count changed between passes");
     }
-    const KeyIndex ki = key_index(c);
     Heavy hv{c.s.hv_leaf.p, c.s.hv_face.p, c.s.hv_lo.p, c.s.hv_hi.p, c.counters.p + 3, p.cap};
     Chunks ch{nullptr, nullptr, nullptr, nullptr};
     uint32_t n_chunks = 0;
@@ -511,9 +526,9 @@ void search_end(Ctx &c, NbrPending &p, void (*overlap)(Ctx &)) {
             OTF_LAUNCH_CHECK("k_nbr_copy_long");
         }
     }
-    hipLaunchKernelGGL(k_nbr_fill, dim3(grid8(L)), dim3(kBlk), 0, c.stream, ki, s.level.p, D,
-                       (const uint32_t *)c.s.g.p, (const uint32_t *)s.nbp_off.p, (const uint32_t *)s.nbm_off.p,
-                       s.nbp.p, s.nbm.p, p.dirty, p.n_dirty_dev, L);
+    hipLaunchKernelGGL(k_nbr_fill, dim3(grid8(L)), dim3(kBlk), 0, c.stream, s.level.p, (const uint32_t *)c.s.g.p,
+                       (const uint32_t *)s.nbp_off.p, (const uint32_t *)s.nbm_off.p, s.nbp.p, s.nbm.p, p.dirty,
+                       p.n_dirty_dev, L, (const uint32_t *)c.s.nb_j.p, (const uint32_t *)c.s.nb_m.p);
     OTF_LAUNCH_CHECK("k_nbr_fill");
     if (n_heavy > 0) {
         hipLaunchKernelGGL(k_nbr_chunk<true>, dim3((unsigned)cdiv((int64_t)n_chunks * 64, kBlk)), dim3(kBlk), 0,

@@ -302,6 +302,7 @@ struct Scratch {
     DBuf<uint32_t> ch_base, ch_item, ch_count, ch_pos;  // chunks of the long ranges
     DBuf<uint32_t> key_table;                           // bucket index over leaf keys
     DBuf<uint32_t> dirty;                               // leaves whose adjacency is searched again
+    DBuf<uint32_t> nb_j, nb_m;                          // faces located by the count pass, for the fill
     DBuf<uint32_t> part;                                // per-block partial counts
     DBuf<unsigned char> mc_table;                       // marching-cubes case table (device)
     // restructure temporaries (grow-only: an allocation or free per iteration
