@@ -308,7 +308,9 @@ struct Scratch {
     // restructure temporaries (grow-only: an allocation or free per iteration
     // would synchronise the device)
     DBuf<uint8_t> r_sf, r_tM, r_tU, r_isnew, r_Mt;
-    DBuf<uint32_t> r_nrank, r_tidx, r_moff, r_loff, r_toff;
+    DBuf<uint32_t> r_nrank, r_tidx, r_moff, r_loff;
+    DBuf<uint8_t> r_jcand;          // collapse: leaves that start an inner node inside a collapse
+    DBuf<uint32_t> r_jrank, r_jlist;  // their ranks and list
     DBuf<float> r_jv;
     DBuf<double> dred;
     std::vector<Round *> rounds;

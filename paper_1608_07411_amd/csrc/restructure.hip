@@ -32,10 +32,21 @@ __global__ void k_run_ends(int64_t L, const uint8_t *flag, const uint32_t *rs, u
     if (i == L - 1 || (flag[i + 1] & 6) != j) runend[rs[i]] = (uint32_t)i;
 }
 
+// The coarsest level whose node starts at key k (k aligned to its size).
+__device__ inline int align_level(uint32_t k, int D) {
+    if (k == 0u) return 0;
+    const int l = D - (int)(__builtin_ctz(k) / 3);
+    return l < 0 ? 0 : l;
+}
+
+// Per leaf: collapse target level jt (0xFF: none), head flag, and cand = 1
+// if the leaf is the first leaf of some inner node inside its collapse block
+// (a node at a level q with jt <= q < the leaf's level, starting at its key),
+// i.e. it computes a hierarchical mean at some level.
 __global__ void __launch_bounds__(kBlk) k_join_target(int64_t L, int D, const uint8_t *flag, const uint32_t *key,
                                                       const uint8_t *level, const uint32_t *rs,
                                                       const uint32_t *runend, uint8_t *jt, uint8_t *jhead,
-                                                      uint32_t *part) {
+                                                      uint32_t *part, uint8_t *cand) {
     const int64_t i = TID();
     uint8_t t = 0xFF, h = 0;
     if (i < L && (flag[i] & 6)) {
@@ -57,6 +68,7 @@ __global__ void __launch_bounds__(kBlk) k_join_target(int64_t L, int D, const ui
     if (i < L) {
         jt[i] = t;
         jhead[i] = h;
+        cand[i] = (t != 0xFF && max((int)t, align_level(key[i], D)) < (int)level[i]) ? 1 : 0;
     }
     // per-block count of collapse heads
     __shared__ uint32_t cnt[kBlk / 64];
@@ -112,38 +124,46 @@ __global__ void k_jval_init(int64_t L, const uint8_t *jt, OldStore o, float *val
     val[4 * cap + i] = o.p[2 * o.cap + i];
 }
 
-__global__ void k_jval_level(int64_t L, int D, int q, const uint8_t *jt, const uint32_t *key, const uint8_t *level,
-                             float *val, int64_t cap) {
-    const int64_t i = TID();
-    if (i >= L || jt[i] == 0xFF || jt[i] > q || level[i] <= q) return;
-    const uint64_t k0 = key[i];
-    if (k0 & ((uint64_t(1) << (3 * (D - q))) - 1)) return;  // not the first leaf of a level-q node
-    const uint64_t step = uint64_t(1) << (3 * (D - q - 1));
-    int64_t pos[8];
-    pos[0] = i;
-    const int64_t end = min(L, i + (int64_t)(uint64_t(1) << (3 * (D - q))));
-    for (int c = 1; c < 8; ++c) {
-        const int64_t lo = pos[c - 1] + 1;
-        if (level[pos[c - 1]] == q + 1) {  // child c-1 is a single leaf: child c starts right after it
-            pos[c] = lo;
-            continue;
+// Level q over the candidate list (its length at n_dev): a candidate that
+// starts a level-q node inside its collapse block (block level <= q, leaf
+// deeper than q) reads the node's 8 children at level q+1 and stores 1/8 of
+// their sum in child order at its own position.
+__global__ void __launch_bounds__(kBlk) k_jval_level(const uint32_t *list, const uint32_t *n_dev, int64_t L, int D,
+                                                     int q, const uint8_t *jt, const uint32_t *key,
+                                                     const uint8_t *level, float *val, int64_t cap) {
+    const uint32_t n = *n_dev;
+    for (uint32_t t = blockIdx.x * kBlk + threadIdx.x; t < n; t += gridDim.x * kBlk) {
+        const int64_t i = list[t];
+        if (jt[i] > q || level[i] <= q) continue;
+        const uint64_t k0 = key[i];
+        if (k0 & ((uint64_t(1) << (3 * (D - q))) - 1)) continue;  // not the first leaf of a level-q node
+        const uint64_t step = uint64_t(1) << (3 * (D - q - 1));
+        int64_t pos[8];
+        pos[0] = i;
+        const int64_t end = min(L, i + (int64_t)(uint64_t(1) << (3 * (D - q))));
+        for (int c = 1; c < 8; ++c) {
+            const int64_t lo = pos[c - 1] + 1;
+            if (level[pos[c - 1]] == q + 1) {  // child c-1 is a single leaf: child c starts right after it
+                pos[c] = lo;
+                continue;
+            }
+            const uint64_t kc = k0 + c * step;
+            int64_t a = lo, b = end;  // first index in [lo, end) with key >= kc
+            while (a < b) {
+                const int64_t m = (a + b) >> 1;
+                if ((uint64_t)key[m] < kc) a = m + 1;
+                else b = m;
+            }
+            pos[c] = a;
         }
-        const uint64_t kc = k0 + c * step;
-        int64_t a = lo, b = end;  // first index in [lo, end) with key >= kc
-        while (a < b) {
-            const int64_t m = (a + b) >> 1;
-            if ((uint64_t)key[m] < kc) a = m + 1;
-            else b = m;
+        float v[5];
+        for (int w = 0; w < 5; ++w) {
+            float acc = 0.0f;
+            for (int c = 0; c < 8; ++c) acc = acc + val[w * cap + pos[c]];
+            v[w] = 0.125f * acc;
         }
-        pos[c] = a;
+        for (int w = 0; w < 5; ++w) val[w * cap + i] = v[w];
     }
-    float v[5];
-    for (int w = 0; w < 5; ++w) {
-        float acc = 0.0f;
-        for (int c = 0; c < 8; ++c) acc = acc + val[w * cap + pos[c]];
-        v[w] = 0.125f * acc;
-    }
-    for (int w = 0; w < 5; ++w) val[w * cap + i] = v[w];
 }
 
 __global__ void k_jval_emit(int64_t L, const uint8_t *jt, const uint8_t *jhead, const float *val, int64_t cap,
@@ -496,9 +516,17 @@ void join_analysis(Ctx &c) {
     scan_run_starts(c, os.flag.p, s.b.p, L);
     hipLaunchKernelGGL(k_run_ends, dim3(gL), dim3(kBlk), 0, c.stream, L, os.flag.p, s.b.p, s.c.p);
     s.part.reserve(gL);
+    s.r_jcand.reserve(L);
     hipLaunchKernelGGL(k_join_target, dim3(gL), dim3(kBlk), 0, c.stream, L, c.prm.max_depth, os.flag.p, os.key.p,
-                       os.level.p, s.b.p, s.c.p, s.u8a.p, s.u8b.p, s.part.p);
+                       os.level.p, s.b.p, s.c.p, s.u8a.p, s.u8b.p, s.part.p, s.r_jcand.p);
     sum_parts(c, s.part.p, gL, 1, gL, c.counters.p + 2);
+    // the leaves that compute hierarchical means, listed (their number stays
+    // on the device, at r_jrank[L])
+    s.r_jrank.reserve(L + 1);
+    s.r_jlist.reserve(L);
+    scan_exclusive_u32_dev_u8(c, s.r_jcand.p, s.r_jrank.p, L);
+    hipLaunchKernelGGL(k_compact_idx, dim3(gL), dim3(kBlk), 0, c.stream, L, s.r_jcand.p, s.r_jrank.p, s.r_jlist.p,
+                       (uint32_t)L);
     OTF_LAUNCH_CHECK("join analysis");
 }
 
@@ -527,8 +555,9 @@ void join_values(Ctx &c, const uint8_t *jt, int &next, int count) {
             hipLaunchKernelGGL(k_jval_init, dim3(grid(L)), dim3(kBlk), 0, c.stream, L, jt, osd, val.p, L);
         } else {
             const int q = D - next;  // levels D-1 .. 0
-            hipLaunchKernelGGL(k_jval_level, dim3(grid(L)), dim3(kBlk), 0, c.stream, L, D, q, jt, os.key.p,
-                               os.level.p, val.p, L);
+            const unsigned gq = (unsigned)std::min<int64_t>(grid(L), 2048);
+            hipLaunchKernelGGL(k_jval_level, dim3(gq), dim3(kBlk), 0, c.stream, (const uint32_t *)c.s.r_jlist.p,
+                               (const uint32_t *)c.s.r_jrank.p + L, L, D, q, jt, os.key.p, os.level.p, val.p, L);
         }
     }
     OTF_LAUNCH_CHECK("join means");
