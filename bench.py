@@ -29,7 +29,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-SWEEP_SOURCES = ("paper_1608_07411_amd/csrc/sweep.hip", "paper_1608_07411_amd/csrc/otf_internal.h")
+SWEEP_SOURCES = ("paper_1608_07411_amd/csrc/sweep.hip",)  # the sweep kernels' source
 
 
 def traffic_ratio(kernel: str, workload: str):
