@@ -653,3 +653,55 @@ def test_invalid_arguments_rejected():
         o.fuse(1, float("inf"), TAU32, TAU32)
     with pytest.raises(oracle.OracleError):
         o.fuse(1, 0.5, -1.0, TAU32)
+
+
+# ---------------------------------------------------------------------------
+# Long neighbour lists (more than 64 entries), summed in 64 interleaved parts
+# ---------------------------------------------------------------------------
+def _slab_oracle(D, x0):
+    """Half-domain leaves against a refined slab of width 2: the coarse leaves
+    left of the slab have + lists of (2^(D-1))^2 entries (x0 = 2^(D-1)), those
+    right of it - lists of that length (x0 = 2^(D-1) - 2)."""
+    G = 1 << D
+    rng = np.random.default_rng(0)
+    f = np.ones((2, G, G, G), np.float32)
+    f[:, :, :, x0:x0 + 2] = rng.uniform(-1, 1, (2, G, G, 2)).astype(np.float32)
+    w = np.ones((2, G, G, G), np.uint8)
+    o = Oracle("f64").build_volumes(f, w, base_params(D, restructure_every=0))
+    counts, _ = o.neighbours()
+    assert max(counts[:, :3].sum(1).max(), counts[:, 3:].sum(1).max()) > 64
+    return o
+
+
+@pytest.mark.parametrize("x0", [32, 30])
+def test_adjoint_with_long_lists(x0):
+    """The divergence (long lists in parts) is minus the adjoint of the plain
+    sequential gradient in volume-weighted inner products."""
+    D = 6
+    o = _slab_oracle(D, x0)
+    ex = o.extract()
+    vol = _vol(ex["levels"], D)
+    rng = np.random.default_rng(x0)
+    for _ in range(3):
+        u = rng.normal(size=len(vol))
+        p = rng.normal(size=(len(vol), 3))
+        lhs = np.sum(vol[:, None] * o.grad(u) * p)
+        rhs = np.sum(vol * u * o.div(p))
+        assert abs(lhs + rhs) < 1e-11 * (abs(lhs) + 1)
+
+
+@pytest.mark.parametrize("x0", [32, 30])
+def test_step_with_long_lists_matches_plain_gradient(x0):
+    """With lambda = 0 the prox returns u', so one iteration is the dual step
+    p1 = proj(p0 + sigma G ubar0) with the plain sequential gradient, then
+    u1 = u0 + tau div p1."""
+    D = 6
+    o = _slab_oracle(D, x0)
+    o.fuse(3, 0.5, TAU32, TAU32)  # a non-trivial p and ubar
+    ex0 = o.extract()
+    o.fuse(1, 0.0, TAU32, TAU32)
+    ex1 = o.extract()
+    q = ex0["p"] + TAU32 * o.grad(ex0["ubar"])
+    p_expect = q / np.maximum(1.0, np.sqrt(np.sum(q * q, axis=1)))[:, None]
+    assert np.max(np.abs(ex1["p"] - p_expect)) < 1e-12
+    assert np.max(np.abs(ex1["u"] - (ex0["u"] + TAU32 * o.div(ex1["p"])))) < 1e-12
