@@ -508,55 +508,51 @@ __global__ void __launch_bounds__(kBlk) k_gd_update(PrimalArgs a, Coef cf_arg) {
     const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const bool valid = i < a.L;
-    float dv = 0.0f, un = 0.0f;
+    float dv = 0.0f, un = 0.0f, inv = 0.0f;
     int M = 0, ln = 0;
     uint32_t oo = 0;
     if (valid) {
+        // the leaf's own loads first, then the divergence's dependent ones
         ln = a.level[i];
         un = a.u_in[i];
         const uint32_t e0 = a.off[i], e1 = a.off[i + 1];
-        dv = (e1 - e0 > kLongList) ? a.ds[i] : divergence(a, cf, e0, e1, ln, a.ds[i]);
+        const float dsi = a.ds[i];
         M = a.obs_m[i];
         oo = a.obs_off[i];
+        inv = a.inv[i];
+        dv = (e1 - e0 > kLongList) ? dsi : divergence(a, cf, e0, e1, ln, dsi);
     }
     const int nact = __popcll(__ballot(valid));
     float mysum = 0.0f;
     for (int l0 = 0; l0 < nact; l0 += kAhead) {
         float Fr[kAhead], Wr[kAhead];
+        // unconditional loads and branch-free terms, as in primal_wave
 #pragma unroll
         for (int g = 0; g < kAhead; ++g) {
-            const int l = l0 + g;
-            Fr[g] = 0.0f;
-            Wr[g] = 0.0f;
-            if (l < nact) {
-                const int Ml = rdlane_i(M, l);
-                const uint32_t ool = (uint32_t)rdlane_i((int)oo, l);
-                if (lane < Ml) {
-                    Fr[g] = a.F[ool + lane];
-                    Wr[g] = a.W[ool + lane];
-                }
-            }
+            const int l = min(l0 + g, 63);
+            const int Ml = rdlane_i(M, l);
+            const uint32_t ool = (uint32_t)rdlane_i((int)oo, l);
+            const uint32_t e = ool + (lane < Ml ? (uint32_t)lane : 0u);
+            Fr[g] = a.F[e];
+            Wr[g] = a.W[e];
         }
 #pragma unroll
         for (int g = 0; g < kAhead; ++g) {
             const int l = l0 + g;
-            if (l >= nact) break;
-            const int Ml = rdlane_i(M, l);
-            const float ul = rdlane(un, l);
-            float t = 0.0f;
-            if (lane < Ml) {
-                const float r = ul - Fr[g];
-                const float den = sqrtf(__fmaf_rn(r, r, a.eps2));
-                t = Wr[g] * (r / den);
-            }
+            const int lc = min(l, 63);
+            const int Ml = rdlane_i(M, lc);
+            const float ul = rdlane(un, lc);
+            const float r = ul - Fr[g];
+            const float den = sqrtf(__fmaf_rn(r, r, a.eps2));  // > 0: eps > 0
+            float t = lane < Ml ? Wr[g] * (r / den) : 0.0f;
 #pragma unroll
             for (int sh = 1; sh < 64; sh <<= 1) t = t + __shfl_xor(t, sh, 64);
-            if (lane == l) mysum = t;
+            mysum = (lane == l && l < nact) ? t : mysum;
         }
     }
     bool split = false, join = false;
     if (valid) {
-        const float dg = mysum * a.inv[i];
+        const float dg = mysum * inv;
         const float v = __fmaf_rn(a.xi, __fmaf_rn(a.lam, dv, -dg), un);
         a.u[i] = v;
         a.ubar[i] = v;
