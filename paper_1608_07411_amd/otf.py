@@ -41,6 +41,13 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise OSError(f"libotf.so not found at {LIB_PATH}; build it with paper_1608_07411_amd.build.build()")
+        # PyTorch, when present, brings its own HIP runtime library: load it
+        # first, so that this library binds to the same runtime instead of
+        # loading a second one into the process
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
         sig = {
