@@ -167,12 +167,25 @@ void gather_launch(Ctx &c, int64_t n, const uint32_t *tkey, const uint8_t *tleve
 namespace {
 constexpr int kObsBlocks = 1024;
 
-// Per-block observation totals (all leaves, leaves with fractional weights).
+// Per-block observation totals (all leaves, leaves with fractional weights);
+// each thread reads 16 bytes of counts and flags at a time.
 __global__ void __launch_bounds__(kBlk) k_obs_sizes(int64_t L, const uint8_t *M, const uint8_t *unit,
                                                     uint32_t *part) {
     __shared__ uint32_t st[kBlk], sn[kBlk];
     uint32_t m = 0, nu = 0;
-    for (int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x; i < L; i += (int64_t)gridDim.x * kBlk) {
+    const int64_t nvec = L / 16;  // whole 16-byte groups (the arrays are 256-byte aligned)
+    for (int64_t g = (int64_t)blockIdx.x * kBlk + threadIdx.x; g < nvec; g += (int64_t)gridDim.x * kBlk) {
+        const uint4 mv = reinterpret_cast<const uint4 *>(M)[g];
+        const uint4 uv = reinterpret_cast<const uint4 *>(unit)[g];
+        const uint32_t mw[4] = {mv.x, mv.y, mv.z, mv.w}, uw[4] = {uv.x, uv.y, uv.z, uv.w};
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const uint32_t mi = (mw[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+            m += mi;
+            nu += ((uw[k >> 2] >> (8 * (k & 3))) & 0xFFu) ? 0u : mi;
+        }
+    }
+    for (int64_t i = 16 * nvec + (int64_t)blockIdx.x * kBlk + threadIdx.x; i < L; i += (int64_t)gridDim.x * kBlk) {
         const uint32_t mi = M[i];
         m += mi;
         nu += unit[i] ? 0u : mi;

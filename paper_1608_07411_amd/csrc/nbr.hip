@@ -33,6 +33,27 @@ __global__ void k_key_table(const uint32_t *key, int64_t L, int shift, uint32_t 
     if (b < nb) table[b] = (uint32_t)find_leaf(key, L, b << shift);
 }
 
+// The same table from a coarser one (tc: buckets of kKeyCoarse fine buckets,
+// nbc entries): each fine bucket searches only between two coarse entries.
+constexpr int kKeyCoarseShift = 6;
+constexpr uint32_t kKeyCoarse = 1u << kKeyCoarseShift;
+
+__global__ void k_key_table_fine(const uint32_t *key, int64_t L, int shift, uint32_t nb, const uint32_t *tc,
+                                 uint32_t nbc, uint32_t *table) {
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    const uint32_t bc = b / kKeyCoarse;
+    const uint32_t k = b << shift;
+    int64_t lo = tc[bc];
+    int64_t hi = (bc + 1 < nbc) ? (int64_t)tc[bc + 1] + 1 : L;
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (key[mid] <= k) lo = mid;
+        else hi = mid;
+    }
+    table[b] = (uint32_t)lo;
+}
+
 // first i with key[i] >= k (k may be the end of the domain)
 __device__ inline int64_t lower_bound(const KeyIndex &ki, uint64_t k, uint64_t domain) {
     if (k >= domain) return ki.L;
@@ -427,9 +448,19 @@ NbrPending search_begin(Ctx &c, const NbrOld &old, bool need_scanned) {
     c.s.nb_m.reserve(6 * L);
     const int shift = std::max(0, 3 * D - 20);
     const uint32_t nb = 1u << (3 * D - shift);
-    c.s.key_table.reserve(nb);
-    hipLaunchKernelGGL(k_key_table, dim3((unsigned)cdiv(nb, kBlk)), dim3(kBlk), 0, c.stream, s.key.p, L, shift, nb,
-                       c.s.key_table.p);
+    if (nb >= 4 * kKeyCoarse) {  // coarse table first (its entries after the fine ones), then the fine one
+        const uint32_t nbc = nb / kKeyCoarse;
+        c.s.key_table.reserve((size_t)nb + nbc);
+        uint32_t *tc = c.s.key_table.p + nb;
+        hipLaunchKernelGGL(k_key_table, dim3((unsigned)cdiv(nbc, kBlk)), dim3(kBlk), 0, c.stream, s.key.p, L,
+                           shift + kKeyCoarseShift, nbc, tc);
+        hipLaunchKernelGGL(k_key_table_fine, dim3((unsigned)cdiv(nb, kBlk)), dim3(kBlk), 0, c.stream, s.key.p, L,
+                           shift, nb, (const uint32_t *)tc, nbc, c.s.key_table.p);
+    } else {
+        c.s.key_table.reserve(nb);
+        hipLaunchKernelGGL(k_key_table, dim3((unsigned)cdiv(nb, kBlk)), dim3(kBlk), 0, c.stream, s.key.p, L, shift,
+                           nb, c.s.key_table.p);
+    }
     OTF_LAUNCH_CHECK("k_key_table");
     NbrPending p{};
     p.old = old;
