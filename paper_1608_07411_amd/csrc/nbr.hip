@@ -282,7 +282,7 @@ __global__ void k_chunk_totals(uint32_t n_items, Heavy hv, Chunks ch, uint32_t *
 
 // One wave copies entries [e0, e1) of an old list to dst + (e - e0), indices
 // mapped to the new positions; kCopyUnroll loads per lane in flight.
-constexpr int kCopyUnroll = 4;
+constexpr int kCopyUnroll = 8;
 
 __device__ inline void wave_copy(const uint32_t *__restrict__ src, uint32_t e0, uint32_t e1, uint32_t *dst,
                                  const uint32_t *__restrict__ remap, int lane) {
