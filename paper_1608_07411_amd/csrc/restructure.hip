@@ -341,9 +341,11 @@ __device__ inline bool changed(int64_t j, const uint8_t *flag, const uint8_t *jt
 }
 
 // Marked from the changed side (adjacency is symmetric): every kept neighbour
-// of a changed leaf. Concurrent stores all write 1.
-// Marks the kept neighbours of changed leaves; kMarkBatch entries of a list
-// are in flight at a time (the lookups form a chain of dependent loads).
+// of a changed leaf; concurrent stores all write 1. The + and - lists are
+// walked together, kMarkBatch entries of each at a time, with every load
+// unconditional at a valid address (entries past a list's end read entry 0
+// and are dropped), so that each step of the lookup chain (entry, changed?,
+// new position) is one round of loads in flight.
 constexpr int kMarkBatch = 8;
 
 __global__ void __launch_bounds__(kBlk) k_nbr_mark(int64_t L, const uint8_t *flag, const uint8_t *jt, int splits,
@@ -352,24 +354,38 @@ __global__ void __launch_bounds__(kBlk) k_nbr_mark(int64_t L, const uint8_t *fla
                                                    const uint32_t *out_off, uint8_t *need) {
     const int64_t i = TID();
     if (i >= L || !changed(i, flag, jt, splits)) return;
-    for (int side = 0; side < 2; ++side) {
-        const uint32_t *off = side ? off_m : off_p;
-        const uint32_t *ent = side ? ent_m : ent_p;
-        const uint32_t e1 = off[i + 1];
-        if (e1 - off[i] > kLongList) continue;  // long lists: k_nbr_mark_long
-        for (uint32_t e = off[i]; e < e1; e += kMarkBatch) {
-            uint32_t n[kMarkBatch], o[kMarkBatch];
-            bool keep[kMarkBatch];
+    const uint32_t *ent[2] = {ent_p, ent_m};
+    uint32_t b0[2] = {off_p[i], off_m[i]}, b1[2] = {off_p[i + 1], off_m[i + 1]};
 #pragma unroll
-            for (int r = 0; r < kMarkBatch; ++r) n[r] = e + r < e1 ? ent[e + r] & kIdxMask : 0u;
+    for (int sd = 0; sd < 2; ++sd)
+        if (b1[sd] - b0[sd] > kLongList) b1[sd] = b0[sd];  // long lists: k_nbr_mark_long
+    const uint32_t len = max(b1[0] - b0[0], b1[1] - b0[1]);
+    for (uint32_t k = 0; k < len; k += kMarkBatch) {
+        uint32_t n[2][kMarkBatch], o[2][kMarkBatch];
+        bool keep[2][kMarkBatch];
 #pragma unroll
-            for (int r = 0; r < kMarkBatch; ++r) keep[r] = e + r < e1 && !changed(n[r], flag, jt, splits);
+        for (int sd = 0; sd < 2; ++sd)
 #pragma unroll
-            for (int r = 0; r < kMarkBatch; ++r) o[r] = keep[r] ? out_off[n[r]] : 0u;
+            for (int r = 0; r < kMarkBatch; ++r) {
+                const uint32_t e = b0[sd] + k + r;
+                const bool ok = e < b1[sd];
+                const uint32_t v = ent[sd][ok ? e : 0u];
+                n[sd][r] = ok ? (v & kIdxMask) : 0u;
+                keep[sd][r] = ok;
+            }
+#pragma unroll
+        for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+            for (int r = 0; r < kMarkBatch; ++r) keep[sd][r] = keep[sd][r] && !changed(n[sd][r], flag, jt, splits);
+#pragma unroll
+        for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+            for (int r = 0; r < kMarkBatch; ++r) o[sd][r] = out_off[keep[sd][r] ? n[sd][r] : 0u];
+#pragma unroll
+        for (int sd = 0; sd < 2; ++sd)
 #pragma unroll
             for (int r = 0; r < kMarkBatch; ++r)
-                if (keep[r]) need[o[r]] = 1;
-        }
+                if (keep[sd][r]) need[o[sd][r]] = 1;
     }
 }
 
