@@ -145,6 +145,14 @@ otf_status otf_energy(otf_ctx *ctx, double *tv, double *data);
 /* Splits and joins made by the last restructuring step of the last fuse. */
 otf_status otf_last_counts(const otf_ctx *ctx, int64_t *splits, int64_t *joins);
 
+/* Observation pool of the fetched data (Fig. 4) in device memory: entries in
+ * use (live segments plus the garbage of replaced leaves; new leaves' segments
+ * are appended), entries reserved, and the number of compactions made by
+ * restructuring steps so far (a restructure compacts the pool in leaf order
+ * when the appended segments would not fit or the garbage exceeds the live
+ * entries). Errors: OTF_E_INVALID (null), OTF_E_STATE (no state). */
+otf_status otf_obs_pool_stats(const otf_ctx *ctx, int64_t *used, int64_t *capacity, int64_t *compactions);
+
 /* State blob (little-endian, version 1): "OTF1", u32 version, otf_params,
  * i64 iteration, i32 n_views, i32 0; per view i64 n_nodes then n_nodes records
  * {u32 key, u8 level, u8 is_leaf, u16 0, f32 sum, u32 count} in (level, key)

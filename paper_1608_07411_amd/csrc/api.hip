@@ -508,6 +508,16 @@ otf_status otf_last_counts(const otf_ctx *ctx, int64_t *splits, int64_t *joins) 
     return OTF_OK;
 }
 
+otf_status otf_obs_pool_stats(const otf_ctx *ctx, int64_t *used, int64_t *capacity, int64_t *compactions) {
+    if (!ctx || !used || !capacity || !compactions) return OTF_E_INVALID;
+    if (!ctx->c.valid) return OTF_E_STATE;
+    const ObsPool &pool = ctx->c.obs[ctx->c.ocur];
+    *used = pool.used;
+    *capacity = pool.cap;
+    *compactions = ctx->c.pool_compactions;
+    return OTF_OK;
+}
+
 otf_status otf_extract(const otf_ctx *cctx, int64_t capacity, uint32_t *keys, uint8_t *levels, float *u, float *ubar,
                        float *p_xyz, int64_t *n_written) {
     otf_ctx *ctx = const_cast<otf_ctx *>(cctx);

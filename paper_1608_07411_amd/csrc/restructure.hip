@@ -818,6 +818,7 @@ bool restructure(Ctx &c, float tl) {
         OTF_LAUNCH_CHECK("k_place_obs");
         np.used = live;
         c.ocur ^= 1;
+        ++c.pool_compactions;
         OTF_HIP(hipStreamSynchronize(c.stream));
     }
     build_neighbours_end(c, nbr, nullptr);

@@ -86,6 +86,7 @@ def lib():
             "otf_batch_fuse": [P, I32, C.c_float, C.c_float, C.c_float],
             "otf_batch_config": [P, P, P, P, P],
             "otf_selftest_scan": [P, I64, C.c_uint64, P],
+            "otf_obs_pool_stats": [P, P, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -261,6 +262,12 @@ class Context:
         """Replace u (and ubar) and p of every leaf by the network's prediction."""
         self._check(self._lib.otf_warm_start(self.h, net.h), "otf_warm_start")
         return self
+
+    def obs_pool_stats(self) -> dict:
+        """Observation pool entries in use and reserved, and compactions so far."""
+        u, cap, k = C.c_int64(0), C.c_int64(0), C.c_int64(0)
+        self._check(self._lib.otf_obs_pool_stats(self.h, C.byref(u), C.byref(cap), C.byref(k)), "otf_obs_pool_stats")
+        return dict(used=u.value, capacity=cap.value, compactions=k.value)
 
     def selftest_scan(self, n: int, seed: int = 0) -> int:
         """Device scans against host scans on n pseudo-random elements; the

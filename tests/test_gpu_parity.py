@@ -98,6 +98,28 @@ def test_adjacency_and_observations_after_restructuring():
     assert changed > 0
 
 
+def test_observation_pool_compaction_parity():
+    """Restructures append new leaves' observations to the pool and compact it
+    in leaf order when it fills: the observations stay identical to the
+    oracle's through at least one compaction."""
+    w = _small_sphere()
+    g = _ctx().build_octree(w.depth, w.cams, w.params)
+    o = Oracle("f32").build(w.depth, w.cams, w.params)
+    for _ in range(40):
+        g.fuse(1, w.lam, w.tau, w.sigma)
+        o.fuse(1, w.lam, w.tau, w.sigma)
+        go, oo = g.extract_obs(), o.leaf_obs()
+        assert np.array_equal(go["M"], oo["M"])
+        for k in ("F", "W", "wtot", "inv"):
+            assert np.array_equal(go[k].astype(np.float64), oo[k]), k
+        st = g.obs_pool_stats()
+        assert st["used"] <= st["capacity"]
+        if st["compactions"] >= 2:
+            break
+    assert g.obs_pool_stats()["compactions"] >= 1
+    _same_leaves(g.extract(), o.extract(), "after the compactions")
+
+
 @pytest.mark.parametrize("restructure", [0, 1])
 def test_free_running_parity_small(restructure):
     w = _small_sphere()
