@@ -109,6 +109,80 @@ __device__ inline void load_items(const RunHeadIn &in, int64_t first, int64_t n,
     }
 }
 
+// Whole tiles go through LDS: loaded with coalesced 16-byte accesses (lane
+// order across the tile), read back by each thread as its kItems
+// consecutive elements, and the results written back the same way. Element i
+// of the tile sits at lds_at(i): one pad word per 32 keeps the per-thread
+// reads free of bank conflicts.
+__device__ inline int lds_at(int i) { return i + (i >> 5); }
+constexpr int kTileLds = kTile + kTile / 32;
+
+__device__ inline void tile_to_lds(const uint32_t *in, uint32_t *s) {
+    const uint4 *q = reinterpret_cast<const uint4 *>(in);
+#pragma unroll
+    for (int k = 0; k < kTile / (4 * kThreads); ++k) {
+        const int v4 = threadIdx.x + kThreads * k;
+        const uint4 w = q[v4];
+        const int i = lds_at(4 * v4);  // the 4 words stay inside one group of 32
+        s[i] = w.x;
+        s[i + 1] = w.y;
+        s[i + 2] = w.z;
+        s[i + 3] = w.w;
+    }
+}
+
+__device__ inline void tile_to_lds(const uint8_t *in, uint32_t *s) {
+    const uint4 *q = reinterpret_cast<const uint4 *>(in);
+#pragma unroll
+    for (int k = 0; k < kTile / (16 * kThreads); ++k) {
+        const int v4 = threadIdx.x + kThreads * k;
+        const uint4 w = q[v4];
+        const uint32_t x[4] = {w.x, w.y, w.z, w.w};
+        const int i = lds_at(16 * v4);  // the 16 bytes stay inside one group of 32
+#pragma unroll
+        for (int j = 0; j < 16; ++j) s[i + j] = (x[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+    }
+}
+
+__device__ inline const uint32_t *raw_of(const uint32_t *in) { return in; }
+__device__ inline const uint8_t *raw_of(const uint8_t *in) { return in; }
+__device__ inline const uint8_t *raw_of(const FlagBitIn &in) { return in.flag; }
+__device__ inline const uint8_t *raw_of(const RunHeadIn &in) { return in.flag; }
+
+// this thread's kItems elements of the tile starting at element base
+template <class P>
+__device__ inline void lds_items(const P *, const uint32_t *s, int64_t, uint32_t (&v)[kItems]) {
+    const int i0 = kItems * threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) v[k] = s[lds_at(i0 + k)];
+}
+__device__ inline void lds_items(const FlagBitIn &in, const uint32_t *s, int64_t, uint32_t (&v)[kItems]) {
+    const int i0 = kItems * threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) v[k] = (s[lds_at(i0 + k)] & in.mask) ? 1u : 0u;
+}
+__device__ inline void lds_items(const RunHeadIn &in, const uint32_t *s, int64_t base, uint32_t (&v)[kItems]) {
+    const int i0 = kItems * threadIdx.x;
+    uint32_t prev = i0 > 0 ? (s[lds_at(i0 - 1)] & 6u) : (base > 0 ? (uint32_t)(in.flag[base - 1] & 6u) : 0u);
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const uint32_t j = s[lds_at(i0 + k)] & 6u;
+        const int64_t i = base + i0 + k;
+        v[k] = (j != 0u && (i == 0 || prev != j)) ? (uint32_t)i : 0u;
+        prev = j;
+    }
+}
+
+__device__ inline void lds_to_tile(const uint32_t *s, uint32_t *out) {
+    uint4 *q = reinterpret_cast<uint4 *>(out);
+#pragma unroll
+    for (int k = 0; k < kTile / (4 * kThreads); ++k) {
+        const int v4 = threadIdx.x + kThreads * k;
+        const int i = lds_at(4 * v4);
+        q[v4] = make_uint4(s[i], s[i + 1], s[i + 2], s[i + 3]);
+    }
+}
+
 __host__ inline bool host_aligned16(const void *p) { return (uintptr_t)p % 16 == 0; }
 __host__ inline bool host_aligned16(const FlagBitIn &in) { return host_aligned16(in.flag); }
 __host__ inline bool host_aligned16(const RunHeadIn &in) { return host_aligned16(in.flag); }
@@ -152,6 +226,7 @@ __global__ void __launch_bounds__(kThreads) k_scan(In in, int64_t n, uint32_t *o
                                                    uint32_t epoch, int64_t ntiles, uint32_t *health, In in2,
                                                    uint32_t *out2, uint32_t *total_out2) {
     __shared__ uint32_t smem[kWaves];
+    __shared__ uint32_t s_tile[kTileLds];
     __shared__ uint32_t s_prefix;
     const bool second = (int64_t)blockIdx.x >= ntiles;
     const int64_t tile = (int64_t)blockIdx.x - (second ? ntiles : 0);
@@ -163,7 +238,15 @@ __global__ void __launch_bounds__(kThreads) k_scan(In in, int64_t n, uint32_t *o
     }
     const int64_t first = tile * kTile + (int64_t)threadIdx.x * kItems;
     uint32_t v[kItems];
-    load_items(in, first, n, vec != 0, v);
+    const int64_t base = tile * kTile;
+    const bool whole = vec != 0 && base + kTile <= n;  // block-uniform
+    if (whole) {
+        tile_to_lds(raw_of(in) + base, s_tile);
+        __syncthreads();
+        lds_items(in, s_tile, base, v);
+    } else {
+        load_items(in, first, n, vec != 0, v);
+    }
     uint32_t acc = 0;
 #pragma unroll
     for (int k = 0; k < kItems; ++k) acc = op(acc, v[k]);
@@ -224,7 +307,16 @@ __global__ void __launch_bounds__(kThreads) k_scan(In in, int64_t n, uint32_t *o
             v[k] = run;
         }
     }
-    store_items(out, first, n, vec != 0, v);
+    if (whole) {
+        __syncthreads();  // every thread has read its elements
+        const int i0 = kItems * threadIdx.x;
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) s_tile[lds_at(i0 + k)] = v[k];
+        __syncthreads();
+        lds_to_tile(s_tile, out + base);
+    } else {
+        store_items(out, first, n, vec != 0, v);
+    }
     if (total_out && tile == ntiles - 1 && threadIdx.x == 0) *total_out = op(tp, total);
 }
 
