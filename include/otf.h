@@ -130,6 +130,13 @@ otf_status otf_extract(const otf_ctx *ctx, int64_t capacity, uint32_t *keys, uin
  * a buffer is too small. */
 otf_status otf_extract_obs(const otf_ctx *ctx, int64_t cap_leaves, int32_t *M, float *wtot, float *inv,
                            int64_t cap_obs, float *F, float *W, int64_t *n_obs);
+/* The same for the listed leaves only (indices into the current leaf order,
+ * host array of n): M[n], wtot[n], inv[n] and the segments one after another
+ * in F / W (host, cap_obs floats; *n_obs = their total, always set).
+ * Errors: OTF_E_INVALID (null, or an index out of range), OTF_E_STATE,
+ * OTF_E_CAPACITY (cap_obs too small). */
+otf_status otf_extract_obs_at(const otf_ctx *ctx, int64_t n, const int64_t *leaves, int32_t *M, float *wtot,
+                              float *inv, int64_t cap_obs, float *F, float *W, int64_t *n_obs);
 
 /* Inspection: face adjacency. counts: 6 per leaf for faces +x,+y,+z,-x,-y,-z;
  * idx: neighbour leaf indices concatenated in that order, ascending key

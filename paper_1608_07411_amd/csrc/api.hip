@@ -583,6 +583,52 @@ otf_status otf_extract_obs(const otf_ctx *cctx, int64_t cap_leaves, int32_t *M, 
     return st != OTF_OK ? st : cap_st;
 }
 
+otf_status otf_extract_obs_at(const otf_ctx *cctx, int64_t n, const int64_t *leaves, int32_t *M, float *wtot,
+                              float *inv, int64_t cap_obs, float *F, float *W, int64_t *n_obs) {
+    otf_ctx *ctx = const_cast<otf_ctx *>(cctx);
+    if (!ctx || !n_obs || n < 0 || (n > 0 && !leaves)) return OTF_E_INVALID;
+    if (!ctx->c.valid) return OTF_E_STATE;
+    for (int64_t t = 0; t < n; ++t)
+        if (leaves[t] < 0 || leaves[t] >= ctx->c.L) return OTF_E_INVALID;
+    otf_status cap_st = OTF_OK;
+    otf_status st = guard(ctx, false, [&] {
+        Ctx &c = ctx->c;
+        LeafStore &s = c.lv();
+        std::vector<uint8_t> hm(n);
+        std::vector<uint32_t> hoff(n);
+        std::vector<float> hw(n), hi(n);
+        for (int64_t t = 0; t < n; ++t) {  // one small copy per field and leaf
+            const int64_t i = leaves[t];
+            OTF_HIP(hipMemcpyAsync(&hm[t], s.obs_m.p + i, 1, hipMemcpyDeviceToHost, c.stream));
+            OTF_HIP(hipMemcpyAsync(&hoff[t], s.obs_off.p + i, 4, hipMemcpyDeviceToHost, c.stream));
+            OTF_HIP(hipMemcpyAsync(&hw[t], s.wtot.p + i, 4, hipMemcpyDeviceToHost, c.stream));
+            OTF_HIP(hipMemcpyAsync(&hi[t], s.inv.p + i, 4, hipMemcpyDeviceToHost, c.stream));
+        }
+        OTF_HIP(hipStreamSynchronize(c.stream));
+        int64_t tot = 0;
+        for (int64_t t = 0; t < n; ++t) tot += hm[t];
+        *n_obs = tot;
+        const bool values = F || W;
+        if (values && tot > cap_obs) {
+            cap_st = OTF_E_CAPACITY;
+            return;
+        }
+        int64_t j = 0;
+        for (int64_t t = 0; t < n; ++t) {
+            if (M) M[t] = hm[t];
+            if (wtot) wtot[t] = hw[t];
+            if (inv) inv[t] = hi[t];
+            if (values && hm[t] > 0) {
+                if (F) OTF_HIP(hipMemcpyAsync(F + j, c.op().F.p + hoff[t], 4 * hm[t], hipMemcpyDeviceToHost, c.stream));
+                if (W) OTF_HIP(hipMemcpyAsync(W + j, c.op().W.p + hoff[t], 4 * hm[t], hipMemcpyDeviceToHost, c.stream));
+            }
+            j += hm[t];
+        }
+        OTF_HIP(hipStreamSynchronize(c.stream));
+    });
+    return st != OTF_OK ? st : cap_st;
+}
+
 otf_status otf_extract_neighbours(const otf_ctx *cctx, int64_t cap_leaves, int32_t *counts, int64_t cap_idx,
                                   int64_t *idx, int64_t *n_idx) {
     otf_ctx *ctx = const_cast<otf_ctx *>(cctx);

@@ -87,6 +87,7 @@ def lib():
             "otf_batch_config": [P, P, P, P, P],
             "otf_selftest_scan": [P, I64, C.c_uint64, P],
             "otf_obs_pool_stats": [P, P, P, P],
+            "otf_extract_obs_at": [P, I64, P, P, P, P, I64, P, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -311,6 +312,24 @@ class Context:
         W = np.zeros(max(tot.value, 1), np.float32)
         self._check(self._lib.otf_extract_obs(self.h, n, _ptr(M), _ptr(wtot), _ptr(inv), F.size, _ptr(F), _ptr(W),
                                               C.byref(tot)), "otf_extract_obs")
+        off = np.zeros(n + 1, np.int64)
+        off[1:] = np.cumsum(M)
+        return dict(M=M, wtot=wtot, inv=inv, F=F[:tot.value], W=W[:tot.value], off=off)
+
+    def extract_obs_at(self, leaves) -> dict:
+        """Observations of the listed leaves (indices in the current order)."""
+        idx = np.ascontiguousarray(leaves, dtype=np.int64)
+        n = idx.size
+        M = np.zeros(n, np.int32)
+        wtot = np.zeros(n, np.float32)
+        inv = np.zeros(n, np.float32)
+        tot = C.c_int64(0)
+        self._check(self._lib.otf_extract_obs_at(self.h, n, _ptr(idx), _ptr(M), _ptr(wtot), _ptr(inv), 0, None, None,
+                                                 C.byref(tot)), "otf_extract_obs_at")
+        F = np.zeros(max(tot.value, 1), np.float32)
+        W = np.zeros(max(tot.value, 1), np.float32)
+        self._check(self._lib.otf_extract_obs_at(self.h, n, _ptr(idx), _ptr(M), _ptr(wtot), _ptr(inv), F.size,
+                                                 _ptr(F), _ptr(W), C.byref(tot)), "otf_extract_obs_at")
         off = np.zeros(n + 1, np.int64)
         off[1:] = np.cumsum(M)
         return dict(M=M, wtot=wtot, inv=inv, F=F[:tot.value], W=W[:tot.value], off=off)

@@ -1,0 +1,97 @@
+"""The full-size workload in the configuration bench.py times (depth-9 thin
+structures, 64 range maps 640x480, ~1.3e7 leaves), checked where the oracle
+cannot run whole: on sampled leaves the oracle computes one by one, and by
+properties that hold at any size.
+
+* Prox: two contexts built from the same inputs take the same frozen-structure
+  warmup; then one iteration with lambda and one with lambda = 0. The dual step
+  does not depend on lambda, and with lambda = 0 the prox returns u' itself, so
+  the second context yields each leaf's u'. For 4096 sampled leaves the
+  oracle's prox of their observations (fetched from the device) at that u'
+  must equal the first context's u bit for bit.
+* Structure and dual feasibility after iterations with split and join: the
+  leaves tile the domain in Morton order, every p has norm at most 1 (up to
+  one rounding), and every leaf has |u| >= tau_s or lies at the maximum depth
+  (a flagged leaf splits until that holds, a collapse takes means of values
+  beyond tau_j >= tau_s of one sign).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1608_07411_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+if not torch.cuda.is_available():  # pragma: no cover - the GPU suite runs on the MI355X machine
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1608_07411_amd import otf  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def work():
+    print("full-size workload: thin, depth 9, 64 views 640x480", flush=True)
+    return synth.thin_workload(seed=0)
+
+
+def _tiles_domain(keys, levels, D):
+    size = np.left_shift(np.ones(keys.size, np.int64), 3 * (D - levels.astype(np.int64)))
+    k = keys.astype(np.int64)
+    return bool(k[0] == 0 and np.all(k[1:] == k[:-1] + size[:-1]) and k[-1] + size[-1] == 1 << (3 * D)
+                and np.all(k % size == 0))
+
+
+def test_full_size_prox_on_sampled_leaves(work):
+    w = work
+    prm = dict(w.params, restructure_every=0)
+    dev = torch.from_numpy(w.depth).cuda()
+    a = otf.Context(0).build_octree(dev, w.cams, prm)
+    b = otf.Context(0).build_octree(dev, w.cams, prm)
+    for c in (a, b):
+        c.fuse(3, w.lam, w.tau, w.sigma)
+    a.fuse(1, w.lam, w.tau, w.sigma)
+    b.fuse(1, 0.0, w.tau, w.sigma)
+    ea, eb = a.extract(), b.extract()
+    assert np.array_equal(ea["keys"], eb["keys"])
+    L = ea["keys"].size
+    print(f"leaves {L}", flush=True)
+    assert L > 10_000_000
+    rng = np.random.default_rng(0)
+    idx = np.sort(rng.choice(L, 4096, replace=False))
+    ob = a.extract_obs_at(idx)
+    tl = float(np.float32(np.float32(w.tau) * np.float32(w.lam)))
+    checked = 0
+    for t, i in enumerate(idx):
+        up = float(eb["u"][i])
+        if up == 0.0:  # a signed zero is not observable through the lambda = 0 run
+            continue
+        s0, s1 = ob["off"][t], ob["off"][t + 1]
+        F = ob["F"][s0:s1].astype(np.float64)
+        W = ob["W"][s0:s1].astype(np.float64)
+        want = oracle.prox(F, W, w.params["gamma"], up, tl, precision="f32")
+        assert np.float32(want) == ea["u"][i], f"leaf {i}: {ea['u'][i]!r} != {want!r}"
+        checked += 1
+    assert checked > 4000
+    a.close()
+    b.close()
+
+
+def test_full_size_structure_after_split_join(work):
+    w = work
+    D = w.max_depth
+    dev = torch.from_numpy(w.depth).cuda()
+    c = otf.Context(0).build_octree(dev, w.cams, w.params)
+    for k in range(3):
+        c.fuse(2, w.lam, w.tau, w.sigma)
+        ex = c.extract()
+        print(f"after {2 * (k + 1)} iterations: {ex['keys'].size} leaves, last split/join {c.last_counts()}",
+              flush=True)
+        assert _tiles_domain(ex["keys"], ex["levels"], D)
+        pn = np.sqrt(np.sum(ex["p"].astype(np.float64) ** 2, axis=1))
+        assert pn.max() <= 1.0 + 1e-6
+        ok = (np.abs(ex["u"]) >= np.float32(w.params["split_tau"])) | (ex["levels"] == D)
+        assert ok.all(), f"{np.count_nonzero(~ok)} leaves below tau_s above max depth"
+    assert sum(c.last_counts()) > 0
+    c.close()
