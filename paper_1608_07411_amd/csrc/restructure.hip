@@ -509,11 +509,6 @@ Round &round_at(Ctx &c, size_t r) {
     return *c.s.rounds[r];
 }
 
-uint32_t read_u32(Ctx &c, const uint32_t *dev, int slot) {
-    read_back(c, {{dev, slot}});
-    return c.h_counters[slot];
-}
-
 }  // namespace
 
 namespace {
