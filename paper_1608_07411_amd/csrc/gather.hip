@@ -6,7 +6,7 @@
 //
 // One segment of SEG lanes (a power of two >= n_views) per target node: lane j
 // descends view j's octree; the segment sorts by rank (each lane counts the
-// lanes ordered before it) and its first lane forms the sequential sums.
+// lanes ordered before it) and the sequential sums are formed in rank order.
 #include <algorithm>
 
 #include "otf_internal.h"
@@ -94,9 +94,25 @@ __global__ void __launch_bounds__(kBlk) k_gather(ViewDev vd, int64_t n, const ui
         o.F[off + rank] = f;
         o.W[off + rank] = w;
     }
-    if (j == 0) {
-        float P = 0.0f, acc = 0.0f;
-        bool all1 = true;
+    float P = 0.0f, acc = 0.0f;
+    bool all1 = true;
+    if constexpr (SEG == 64) {
+        // the segment is the wave: every lane forms the same serial sums from
+        // the sorted entries broadcast one at a time, and lane k keeps the
+        // prefix before entry k (one coalesced store instead of m one-lane
+        // stores); the order of operations is that of the serial loop below
+        const float wj = sW[seg_tid0 + j], fj = sF[seg_tid0 + j];  // entry j (unused for j >= m)
+        float Pj = 0.0f;
+        for (int k = 0; k < m; ++k) {
+            const float wk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wj), k));
+            const float fk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(fj), k));
+            Pj = (j == k) ? P : Pj;
+            P = P + wk;
+            acc = __fmaf_rn(wk, fk, acc);
+            all1 = all1 && (wk == 1.0f);
+        }
+        if (o.P && j < m) o.P[off + j] = Pj;
+    } else if (j == 0) {
         for (int k = 0; k < m; ++k) {
             const float wk = sW[seg_tid0 + k];
             if (o.P) o.P[off + k] = P;
@@ -104,6 +120,8 @@ __global__ void __launch_bounds__(kBlk) k_gather(ViewDev vd, int64_t n, const ui
             acc = __fmaf_rn(wk, sF[seg_tid0 + k], acc);
             all1 = all1 && (wk == 1.0f);
         }
+    }
+    if (j == 0) {
         const float inv = 1.0f / (P + gamma);
         o.M[h] = (uint8_t)m;
         o.unit[h] = all1 ? 1 : 0;

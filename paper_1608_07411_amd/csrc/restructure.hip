@@ -486,23 +486,56 @@ __global__ void k_place_obs(int64_t n, const uint32_t *tidx, const uint8_t *Mt, 
     if (k == 0) obs_off[h] = dst;
 }
 
-// One wave per leaf: lane k copies observation k (M <= 64).
-__global__ void k_copy_segments(int64_t L, const uint8_t *isnew, const uint8_t *M, const uint32_t *new_off,
-                                uint32_t *obs_off, const float *F0, const float *W0, const float *P0, float *F1,
-                                float *W1, float *P1) {
-    const int64_t i = ((int64_t)blockIdx.x * kBlk + threadIdx.x) >> 6;
-    const int k = threadIdx.x & 63;
-    if (i >= L) return;
-    const uint32_t dst = new_off[i];
-    if (!isnew[i] && k < M[i]) {
-        const uint32_t src = obs_off[i];
-        F1[dst + k] = F0[src + k];
-        W1[dst + k] = W0[src + k];
-        P1[dst + k] = P0[src + k];
-    }
-    if (k == 0) obs_off[i] = dst;
-}
+// Pool compaction. A wave takes 64 consecutive leaves, their headers loaded
+// one lane each, then copies their segments one leaf after another, lane k
+// copying observation k (M <= 64). The loads of kSegAhead leaves are issued
+// before the first store; every load is unconditional at a valid address
+// (lanes past a segment's end read its first entry; new leaves, whose
+// observations are placed afterwards, and leaves past the wave's last read
+// entry 0), so that no load waits in a conditional block.
+constexpr int kSegAhead = 8;
 
+__global__ void __launch_bounds__(kBlk) k_copy_segments(int64_t L, const uint8_t *isnew, const uint8_t *M,
+                                                        const uint32_t *new_off, uint32_t *obs_off, const float *F0,
+                                                        const float *W0, const float *P0, float *F1, float *W1,
+                                                        float *P1) {
+    const int64_t i = TID();
+    const int lane = threadIdx.x & 63;
+    const bool valid = i < L;
+    int m = 0;
+    uint32_t src = 0, dst = 0;
+    if (valid) {
+        dst = new_off[i];
+        src = obs_off[i];
+        m = isnew[i] ? 0 : (int)M[i];
+    }
+    const int nact = __popcll(__ballot(valid));
+    for (int l0 = 0; l0 < nact; l0 += kSegAhead) {
+        float f[kSegAhead], w[kSegAhead], p[kSegAhead];
+#pragma unroll
+        for (int g = 0; g < kSegAhead; ++g) {
+            const int l = min(l0 + g, 63);
+            const int ml = __builtin_amdgcn_readlane(m, l);
+            const uint32_t sl = (uint32_t)__builtin_amdgcn_readlane((int)src, l);
+            const uint32_t e = ml > 0 ? sl + (lane < ml ? (uint32_t)lane : 0u) : 0u;
+            f[g] = F0[e];
+            w[g] = W0[e];
+            p[g] = P0[e];
+        }
+#pragma unroll
+        for (int g = 0; g < kSegAhead; ++g) {
+            const int l = min(l0 + g, 63);
+            const int ml = l0 + g < nact ? __builtin_amdgcn_readlane(m, l) : 0;
+            const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)dst, l) + (uint32_t)lane;
+            if (lane < ml) {
+                F1[d] = f[g];
+                W1[d] = w[g];
+                P1[d] = p[g];
+            }
+        }
+    }
+    if (valid) obs_off[i] = dst;
+}
 
 Round &round_at(Ctx &c, size_t r) {
     while (c.s.rounds.size() <= r) c.s.rounds.push_back(new Round());
@@ -804,7 +837,7 @@ bool restructure(Ctx &c, float tl) {
         DBuf<uint32_t> &loff = s.r_loff;  // segment offsets in the compacted pool
         loff.reserve(Lnew + 1);
         scan_exclusive_u32_dev_u8(c, ns.obs_m.p, loff.p, Lnew);
-        hipLaunchKernelGGL(k_copy_segments, dim3(grid(64 * Lnew)), dim3(kBlk), 0, c.stream, Lnew, isnew.p,
+        hipLaunchKernelGGL(k_copy_segments, dim3(grid(Lnew)), dim3(kBlk), 0, c.stream, Lnew, isnew.p,
                            ns.obs_m.p, loff.p, ns.obs_off.p, pool.F.p, pool.W.p, pool.P.p, np.F.p, np.W.p, np.P.p);
         OTF_LAUNCH_CHECK("k_copy_segments");
         hipLaunchKernelGGL(k_place_obs, dim3(grid(64 * (int64_t)n_new)), dim3(kBlk), 0, c.stream, (int64_t)n_new,
