@@ -352,6 +352,7 @@ struct Ctx {
     uint32_t *h_counters = nullptr;    // pinned, coherent host slots for read-backs (32)
     uint32_t *d_h_counters = nullptr;  // the same slots as the device addresses them
     uint32_t read_seq = 0;             // last read-back sequence number issued
+    int64_t part_blocks = 0;           // blocks (flag-count partials) of the last primal launch
     int64_t last_splits = 0, last_joins = 0;
     int64_t pool_compactions = 0;  // observation pool compactions by restructures
     bool had_splits = true, had_joins = true;  // flags at the previous restructure

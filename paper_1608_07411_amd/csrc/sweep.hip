@@ -156,7 +156,7 @@ __device__ inline void dual_leaves(const DualArgs &a, const Coef &cf, const int6
     uint32_t len = 0;
 #pragma unroll
     for (int n = 0; n < N; ++n) {
-        on[n] = on[n] && e1[n] - e0[n] <= kLongList;  // long lists: k_dual_long
+        on[n] = on[n] && e1[n] - e0[n] <= kLongList;  // long lists: dual_long_wave
         if (!on[n]) e1[n] = e0[n];
         len = max(len, e1[n] - e0[n]);
     }
@@ -223,17 +223,6 @@ __device__ inline void dual_leaves(const DualArgs &a, const Coef &cf, const int6
     }
 }
 
-// kDualLeaves leaves per thread: a block covers kDualLeaves * kBlk consecutive
-// leaves, thread t takes t, t + kBlk, ... (each group coalesced).
-__global__ void __launch_bounds__(kBlk) k_dual(DualArgs a, Coef cf) {
-    __shared__ Coef scf;
-    const Coef &lcf = stage_coef(cf, scf);
-    const int64_t base = (int64_t)blockIdx.x * (kDualLeaves * kBlk) + threadIdx.x;
-    int64_t idx[kDualLeaves];
-#pragma unroll
-    for (int n = 0; n < kDualLeaves; ++n) idx[n] = base + (int64_t)n * kBlk;
-    dual_leaves(a, lcf, idx);
-}
 
 // Leaves whose + list is longer than kLongList, one wave each. Such a list is
 // summed in 64 interleaved parts: lane j folds the entries at list positions
@@ -247,6 +236,9 @@ constexpr int kWavesPerBlock = kBlk / 64;
 // sum of the 64 lanes' v, added in lane order (the same value on every lane)
 __device__ inline float lane_order_sum(float v) {
     float s = 0.0f;
+    // (partly unrolled: a full unroll would hold all 64 values in scalar
+    // registers and lower the occupancy of the sweeps that include it)
+#pragma unroll 8
     for (int j = 0; j < 64; ++j) s = s + rdlane(v, j);
     return s;
 }
@@ -284,11 +276,25 @@ __device__ void dual_long_wave(const DualArgs &a, const Coef &cf, int64_t i, int
     if (lane == 0) dual_finish(a, i, gx, gy, gz, Cx, Cy, Cz);
 }
 
-__global__ void __launch_bounds__(kBlk) k_dual_long(uint32_t n, const uint32_t *list, DualArgs a, Coef cf) {
+// Dual sweep in one launch: the first long_blocks blocks take the leaves with
+// a long + list (dual_long_wave, one wave each), the others kDualLeaves leaves
+// per thread: such a block covers kDualLeaves * kBlk consecutive leaves,
+// thread t takes t, t + kBlk, ... (each group coalesced; long-list leaves are
+// skipped). The two kinds of blocks touch disjoint leaves.
+__global__ void __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(8, 8)))
+k_dual(DualArgs a, Coef cf, uint32_t n_long, const uint32_t *long_list, uint32_t long_blocks) {
     __shared__ Coef scf;
     const Coef &lcf = stage_coef(cf, scf);
-    const uint32_t item = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    if (item < n) dual_long_wave(a, lcf, list[item], threadIdx.x & 63);
+    if (blockIdx.x < long_blocks) {
+        const uint32_t item = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+        if (item < n_long) dual_long_wave(a, lcf, long_list[item], threadIdx.x & 63);
+        return;
+    }
+    const int64_t base = (int64_t)(blockIdx.x - long_blocks) * (kDualLeaves * kBlk) + threadIdx.x;
+    int64_t idx[kDualLeaves];
+#pragma unroll
+    for (int n = 0; n < kDualLeaves; ++n) idx[n] = base + (int64_t)n * kBlk;
+    dual_leaves(a, lcf, idx);
 }
 
 struct PrimalArgs {
@@ -316,10 +322,10 @@ struct PrimalArgs {
     const float *W;
 };
 
-// u' for leaves with a long - list, one wave each: the incoming terms in 64
-// interleaved parts as in dual_long_wave, added to ds in lane order; u'
-// replaces ds for k_primal (gradient descent keeps the divergence itself).
-__device__ void primal_long_wave(const PrimalArgs &a, const Coef &cf, int64_t i, int lane) {
+// Divergence of a leaf with a long - list, one wave: the incoming terms in 64
+// interleaved parts as in dual_long_wave, added to ds in lane order (the same
+// value on every lane).
+__device__ float long_divergence(const PrimalArgs &a, const Coef &cf, int64_t i, int lane) {
     const uint32_t e0 = a.off[i], ne = a.off[i + 1] - e0;
     const int ln = a.level[i];
     float part = 0.0f;
@@ -341,7 +347,15 @@ __device__ void primal_long_wave(const PrimalArgs &a, const Coef &cf, int64_t i,
         }
     }
     float acc = a.ds[i];
+#pragma unroll 8
     for (int j = 0; j < 64; ++j) acc = acc + rdlane(part, j);
+    return acc;
+}
+
+// u' for leaves with a long - list, one wave each; u' replaces ds for
+// primal_wave<true> (gradient descent keeps the divergence itself).
+__device__ void primal_long_wave(const PrimalArgs &a, const Coef &cf, int64_t i, int lane) {
+    const float acc = long_divergence(a, cf, i, lane);
     if (lane == 0) a.ds[i] = a.gd ? acc : __fmaf_rn(a.tau, acc, a.u_in[i]);
 }
 
@@ -376,18 +390,65 @@ __device__ inline float divergence(const PrimalArgs &a, const Coef &cf, uint32_t
     return acc;
 }
 
+// The generalised shrinkage of one leaf by a whole wave: lane k holds
+// breakpoint k (F_k and the prefix weight P_k; lanes at or past M hold values
+// never used); upl, tl, wtl and Ml are the leaf's, the same on every lane.
+// p_k = u' - t S_k is tested against F_(k+1), a ballot's popcount is the
+// index k* of the sequential search (the predicate holds on a prefix), and
+// the median is max(p_k*, F_k*) (u' - t W_tot past the last breakpoint; u'
+// itself without observations). Returns it on every lane.
+__device__ inline float wave_prox(float Fk, float Pk, float upl, float tl_, float wtl, int Ml, int lane) {
+    // S_k = 2 P_k - W_tot for every leaf (with unit weights P_k = k and
+    // W_tot = M exactly); lanes at or past Ml compute a value never used
+    const float S = __fmaf_rn(2.0f, Pk, -wtl);
+    const float pk = __fmaf_rn(-tl_, S, upl);
+    const bool pred = lane < Ml && pk > Fk;
+    const int ks = __popcll(__ballot(pred));
+    const float pend = __fmaf_rn(-tl_, wtl, upl);
+    const float pks = (ks < Ml) ? rdlane(pk, min(ks, 63)) : pend;
+    const float Fp = rdlane(Fk, max(ks - 1, 0));
+    float v = (ks > 0) ? ((pks >= Fp) ? pks : Fp) : pks;
+    v = (Ml > 0) ? v : upl;
+    return v + 0.0f;
+}
+
+// Split and join flags of a leaf at level ln with new value v.
+__device__ inline void primal_flags(const PrimalArgs &a, float v, int ln, bool &split, bool &join) {
+    const float av = fabsf(v);
+    split = av < a.split_tau && ln < a.max_depth;
+    join = a.join_enabled && av > a.join_tau;
+}
+
+// Outputs of leaf i: u = v, ubar = 2 v - u_old, the flag byte, and for a leaf
+// flagged to split its u' and u_old.
+__device__ inline void primal_store(const PrimalArgs &a, int64_t i, float v, float un, float up, bool split,
+                                    bool join) {
+    a.ubar[i] = __fmaf_rn(2.0f, v, -un);
+    a.u[i] = v;
+    a.flag[i] = split ? 1 : (join ? (v > 0.0f ? 2 : 4) : 0);
+    if (split) {
+        a.uprime[i] = up;
+        a.uold[i] = un;
+    }
+}
+
 // Divergence per thread, then the prox cooperatively: the wave takes its 64
 // leaves one after another; lane k tests breakpoint k of the current leaf
 // (p_k = u' - t S_k against F_(k+1), coalesced loads of F and P), a ballot
 // counts the true predicates (a prefix: p_k falls, F rises), which is the
 // index k* of the sequential search; max(p_k*, F_(k*)) is the median.
 // The wave's 64 consecutive leaves (this lane: leaf i, valid if i < L; valid
-// lanes form a prefix of the wave). Returns the wave's split and join flag
-// counts (the same on every lane).
+// lanes form a prefix of the wave). A leaf with a long - list takes u' from
+// ds (kLongInDs, after primal_long_wave) or is left to its own wave
+// (primal_long_full in the same launch): then it stays in the wave's prox
+// loop, with a value that is not stored. Returns the wave's split and join
+// flag counts (the same on every lane).
+template <bool kLongInDs>
 __device__ inline void primal_wave(const PrimalArgs &a, const Coef &cf, int64_t i, uint32_t &n_split,
                                    uint32_t &n_join) {
     const int lane = threadIdx.x & 63;
     const bool valid = i < a.L;
+    bool own = valid;
     float up = 0.0f, un = 0.0f, t = 0.0f, wt = 0.0f;
     int M = 0, ln = 0;
     uint32_t oo = 0;
@@ -403,8 +464,12 @@ __device__ inline void primal_wave(const PrimalArgs &a, const Coef &cf, int64_t 
         const float inv = a.inv[i];
         wt = a.wtot[i];
         t = a.tl * inv;
-        if (e1 - e0 > kLongList) up = dsi;
-        else up = __fmaf_rn(a.tau, divergence(a, cf, e0, e1, ln, dsi), un);
+        if (e1 - e0 > kLongList) {
+            up = kLongInDs ? dsi : un;
+            own = kLongInDs;
+        } else {
+            up = __fmaf_rn(a.tau, divergence(a, cf, e0, e1, ln, dsi), un);
+        }
     }
     // valid lanes form a prefix of the wave; the F and P loads of kAhead
     // leaves are issued before the first of them is used, to keep enough
@@ -434,34 +499,14 @@ __device__ inline void primal_wave(const PrimalArgs &a, const Coef &cf, int64_t 
             const int lc = min(l, 63);
             const int Ml = rdlane_i(M, lc);
             const float upl = rdlane(up, lc), tl_ = rdlane(t, lc), wtl = rdlane(wt, lc);
-            const float Fk = Fr[g];
-            // S_k = 2 P_k - W_tot for every leaf (with unit weights P_k = k and
-            // W_tot = M exactly); lanes at or past Ml compute a value never used
-            const float S = __fmaf_rn(2.0f, Pr[g], -wtl);
-            const float pk = __fmaf_rn(-tl_, S, upl);
-            const bool pred = lane < Ml && pk > Fk;
-            const int ks = __popcll(__ballot(pred));
-            const float pend = __fmaf_rn(-tl_, wtl, upl);
-            const float pks = (ks < Ml) ? rdlane(pk, min(ks, 63)) : pend;
-            const float Fp = rdlane(Fk, max(ks - 1, 0));
-            float v = (ks > 0) ? ((pks >= Fp) ? pks : Fp) : pks;
-            v = (Ml > 0) ? v : upl;
-            v = v + 0.0f;
+            const float v = wave_prox(Fr[g], Pr[g], upl, tl_, wtl, Ml, lane);
             myv = (lane == l && l < nact) ? v : myv;
         }
     }
     bool split = false, join = false;
-    if (valid) {
-        a.ubar[i] = __fmaf_rn(2.0f, myv, -un);
-        a.u[i] = myv;
-        const float av = fabsf(myv);
-        split = av < a.split_tau && ln < a.max_depth;
-        join = a.join_enabled && av > a.join_tau;
-        a.flag[i] = split ? 1 : (join ? (myv > 0.0f ? 2 : 4) : 0);
-        if (split) {
-            a.uprime[i] = up;
-            a.uold[i] = un;
-        }
+    if (own) {
+        primal_flags(a, myv, ln, split, join);
+        primal_store(a, i, myv, un, up, split, join);
     }
     n_split = (uint32_t)__popcll(__ballot(split));
     n_join = (uint32_t)__popcll(__ballot(join));
@@ -485,11 +530,45 @@ __device__ inline void block_flag_counts(uint32_t n_split, uint32_t n_join, uint
     __syncthreads();
 }
 
-__global__ void __launch_bounds__(kBlk) k_primal(PrimalArgs a, Coef cf) {
+// The whole primal update of a leaf with a long - list, one wave: its own
+// loads, u' = u + tau div (long_divergence), the prox of its observations
+// (lane k: breakpoint k) and its outputs. The flags are returned on every lane.
+__device__ void primal_long_full(const PrimalArgs &a, const Coef &cf, int64_t i, int lane, bool &split,
+                                 bool &join) {
+    const int ln = a.level[i];
+    const float un = a.u_in[i];
+    const int M = a.obs_m[i];
+    const uint32_t oo = a.obs_off[i];
+    const float inv = a.inv[i], wt = a.wtot[i];
+    const uint32_t e = oo + (lane < M ? (uint32_t)lane : 0u);
+    const float Fk = a.F[e], Pk = a.P[e];
+    const float up = __fmaf_rn(a.tau, long_divergence(a, cf, i, lane), un);
+    const float v = wave_prox(Fk, Pk, up, a.tl * inv, wt, M, lane);
+    primal_flags(a, v, ln, split, join);
+    if (lane == 0) primal_store(a, i, v, un, up, split, join);
+}
+
+// Primal sweep in one launch: the first long_blocks blocks take the leaves
+// with a long - list (primal_long_full, one wave each), the others 64
+// consecutive leaves per wave (primal_wave, long-list leaves not stored).
+// The two kinds of blocks write disjoint leaves; per-block flag counts go to
+// part[block] and part[stride + block].
+__global__ void __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(8, 8)))
+k_primal(PrimalArgs a, Coef cf, uint32_t n_long, const uint32_t *long_list, uint32_t long_blocks) {
     __shared__ Coef scf;
     const Coef &lcf = stage_coef(cf, scf);
-    uint32_t ns, nj;
-    primal_wave(a, lcf, (int64_t)blockIdx.x * kBlk + threadIdx.x, ns, nj);
+    uint32_t ns = 0, nj = 0;
+    if (blockIdx.x < long_blocks) {
+        const uint32_t item = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+        if (item < n_long) {
+            bool split, join;
+            primal_long_full(a, lcf, long_list[item], threadIdx.x & 63, split, join);
+            ns = split ? 1u : 0u;
+            nj = join ? 1u : 0u;
+        }
+    } else {
+        primal_wave<false>(a, lcf, (int64_t)(blockIdx.x - long_blocks) * kBlk + threadIdx.x, ns, nj);
+    }
     block_flag_counts<kBlk>(ns, nj, a.part, a.part_stride, blockIdx.x);
 }
 
@@ -664,7 +743,7 @@ __global__ void __launch_bounds__(BLK) k_primal_b(const ObjDev *objs, int nobj, 
         const int j = find_obj(tile_begin, nobj, t);
         const PrimalArgs a = objs[j].p;
         uint32_t ns, nj;
-        primal_wave(a, coefs[objs[j].D], (int64_t)(t - tile_begin[j]) * BLK + threadIdx.x, ns, nj);
+        primal_wave<true>(a, coefs[objs[j].D], (int64_t)(t - tile_begin[j]) * BLK + threadIdx.x, ns, nj);
         block_flag_counts<BLK>(ns, nj, part, ntiles, t);
     }
 }
@@ -794,31 +873,31 @@ void launch_batch(hipStream_t st, BatchState &b) {
 
 }  // namespace
 
-void launch_dual(Ctx &c, float sigma) {
+namespace {
+// One k_dual launch: the long + lists' waves first, then the short-list leaves.
+void dual_launch(Ctx &c, const DualArgs &a) {
     LeafStore &s = c.lv();
-    const DualArgs a = dual_args(c, sigma);
-    hipLaunchKernelGGL(k_dual, dim3((unsigned)cdiv(c.L, kDualLeaves * kBlk)), dim3(kBlk), 0, c.stream, a, c.coef);
+    const int64_t lb = cdiv(s.n_heavy_p, kWavesPerBlock);
+    const int64_t nblk = lb + cdiv(c.L, kDualLeaves * kBlk);
+    hipLaunchKernelGGL(k_dual, dim3((unsigned)nblk), dim3(kBlk), 0, c.stream, a, c.coef, (uint32_t)s.n_heavy_p,
+                       (const uint32_t *)s.heavy_p.p, (uint32_t)lb);
     OTF_LAUNCH_CHECK("k_dual");
-    if (s.n_heavy_p > 0) {
-        hipLaunchKernelGGL(k_dual_long, dim3((unsigned)cdiv(s.n_heavy_p, kWavesPerBlock)), dim3(kBlk), 0, c.stream,
-                           (uint32_t)s.n_heavy_p, s.heavy_p.p, a, c.coef);
-        OTF_LAUNCH_CHECK("k_dual_long");
-    }
 }
+}  // namespace
+
+void launch_dual(Ctx &c, float sigma) { dual_launch(c, dual_args(c, sigma)); }
 
 void launch_primal(Ctx &c, float tau, float tl) {
     LeafStore &s = c.lv();
     PrimalArgs a = primal_args(c, tau, tl);
-    const int64_t nblk = cdiv(c.L, kBlk);
+    const int64_t lb = cdiv(s.n_heavy_m, kWavesPerBlock);
+    const int64_t nblk = lb + cdiv(c.L, kBlk);
     c.s.part.reserve(2 * nblk);
     a.part = c.s.part.p;
     a.part_stride = nblk;
-    if (s.n_heavy_m > 0) {
-        hipLaunchKernelGGL(k_primal_long, dim3((unsigned)cdiv(s.n_heavy_m, kWavesPerBlock)), dim3(kBlk), 0, c.stream,
-                           (uint32_t)s.n_heavy_m, s.heavy_m.p, a, c.coef);
-        OTF_LAUNCH_CHECK("k_primal_long");
-    }
-    hipLaunchKernelGGL(k_primal, dim3((unsigned)nblk), dim3(kBlk), 0, c.stream, a, c.coef);
+    c.part_blocks = nblk;
+    hipLaunchKernelGGL(k_primal, dim3((unsigned)nblk), dim3(kBlk), 0, c.stream, a, c.coef, (uint32_t)s.n_heavy_m,
+                       (const uint32_t *)s.heavy_m.p, (uint32_t)lb);
     OTF_LAUNCH_CHECK("k_primal");
 }
 
@@ -828,13 +907,7 @@ void launch_gd_flux(Ctx &c, float eps2) {
     d.ubar = s.u.p;  // the flux differences u itself
     d.gd = 1;
     d.eps2 = eps2;
-    hipLaunchKernelGGL(k_dual, dim3((unsigned)cdiv(c.L, kDualLeaves * kBlk)), dim3(kBlk), 0, c.stream, d, c.coef);
-    OTF_LAUNCH_CHECK("k_dual (flux)");
-    if (s.n_heavy_p > 0) {
-        hipLaunchKernelGGL(k_dual_long, dim3((unsigned)cdiv(s.n_heavy_p, kWavesPerBlock)), dim3(kBlk), 0, c.stream,
-                           (uint32_t)s.n_heavy_p, s.heavy_p.p, d, c.coef);
-        OTF_LAUNCH_CHECK("k_dual_long (flux)");
-    }
+    dual_launch(c, d);
 }
 
 void launch_gd_update(Ctx &c, float lam, float xi, float eps2) {
@@ -844,6 +917,7 @@ void launch_gd_update(Ctx &c, float lam, float xi, float eps2) {
     c.s.part.reserve(2 * nblk);
     a.part = c.s.part.p;
     a.part_stride = nblk;
+    c.part_blocks = nblk;
     a.gd = 1;
     a.lam = lam;
     a.xi = xi;
@@ -858,7 +932,7 @@ void launch_gd_update(Ctx &c, float lam, float xi, float eps2) {
 }
 
 void count_flags(Ctx &c) {
-    const int64_t nblk = cdiv(c.L, kBlk);
+    const int64_t nblk = c.part_blocks;  // blocks of the last primal launch
     sum_parts(c, c.s.part.p, nblk, 2, nblk, c.counters.p);  // counters[0] split flags, [1] join flags
 }
 
