@@ -222,13 +222,14 @@ __global__ void k_chunk_expand(uint32_t n_items, uint32_t n_chunks, const uint32
     item[c] = lo;
 }
 
+// One wave per chunk of a long range (block b of the chunk blocks): counts
+// its hits (FILL false) or writes them after the leaf's earlier faces.
 template <bool FILL>
-__global__ void __launch_bounds__(kBlk) k_nbr_chunk(uint32_t n_chunks, Heavy hv, Chunks ch,
-                                                    const uint32_t *__restrict__ key,
-                                                    const uint8_t *__restrict__ level, int D,
-                                                    const uint32_t *__restrict__ fc, const uint32_t *off_p,
-                                                    const uint32_t *off_m, uint32_t *ent_p, uint32_t *ent_m) {
-    const uint32_t chunk = ((uint32_t)blockIdx.x * kBlk + threadIdx.x) >> 6;
+__device__ inline void nbr_chunk(uint32_t b, uint32_t n_chunks, const Heavy &hv, const Chunks &ch,
+                                 const uint32_t *__restrict__ key, const uint8_t *__restrict__ level, int D,
+                                 const uint32_t *__restrict__ fc, const uint32_t *off_p, const uint32_t *off_m,
+                                 uint32_t *ent_p, uint32_t *ent_m) {
+    const uint32_t chunk = (b * kBlk + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     if (chunk >= n_chunks) return;
     const uint32_t item = ch.item[chunk];
@@ -266,6 +267,12 @@ __global__ void __launch_bounds__(kBlk) k_nbr_chunk(uint32_t n_chunks, Heavy hv,
         total += (uint32_t)__popcll(b);
     }
     if (!FILL && lane == 0) ch.count[chunk] = total;
+}
+
+__global__ void __launch_bounds__(kBlk) k_nbr_chunk_count(uint32_t n_chunks, Heavy hv, Chunks ch,
+                                                          const uint32_t *__restrict__ key,
+                                                          const uint8_t *__restrict__ level, int D) {
+    nbr_chunk<false>(blockIdx.x, n_chunks, hv, ch, key, level, D, nullptr, nullptr, nullptr, nullptr, nullptr);
 }
 
 // Per heavy item: face count from its chunks, added to the leaf's list count.
@@ -321,13 +328,14 @@ __device__ inline void thread_copy(const uint32_t *__restrict__ src, uint32_t e0
     }
 }
 
-// Lists of unchanged leaves: a wave of 64 unchanged leaves with consecutive
-// sources copies one contiguous block of entries; otherwise each unchanged
-// leaf copies its own short lists (long ones are copied by k_nbr_copy_long).
-__global__ void __launch_bounds__(kBlk) k_nbr_fill_clean(int64_t L, const uint32_t *__restrict__ off_p,
-                                                         const uint32_t *__restrict__ off_m, uint32_t *ent_p,
-                                                         uint32_t *ent_m, NbrOld old) {
-    const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
+// Lists of unchanged leaves (block b of the short-list blocks): a wave of 64
+// unchanged leaves with consecutive sources copies one contiguous block of
+// entries; otherwise each unchanged leaf copies its own short lists (long
+// ones are copied by nbr_copy_long).
+__device__ inline void nbr_fill_clean(uint32_t b, int64_t L, const uint32_t *__restrict__ off_p,
+                                      const uint32_t *__restrict__ off_m, uint32_t *ent_p, uint32_t *ent_m,
+                                      const NbrOld &old) {
+    const int64_t i = (int64_t)b * kBlk + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const bool clean = i < L && !old.need[i];
     const uint32_t j = clean ? old.src[i] : 0u;
@@ -346,21 +354,20 @@ __global__ void __launch_bounds__(kBlk) k_nbr_fill_clean(int64_t L, const uint32
     if (m1 - m0 <= kLongList) thread_copy(old.ent_m, m0, m1, ent_m + off_m[i], old.remap);
 }
 
-// Searched leaves, 8 lanes per leaf as in k_nbr_count: lane f writes face f's
-// short range after the leaf's earlier faces; long ranges are written by the
-// chunk fill.
+// Searched leaves, 8 lanes per leaf as in k_nbr_count (block b of nb
+// striding blocks): lane f writes face f's short range after the leaf's
+// earlier faces; long ranges are written by the chunk fill.
 // (the faces located by k_nbr_count are read back from cj / cm)
-__global__ void __launch_bounds__(kBlk) k_nbr_fill(const uint8_t *__restrict__ level,
-                                                   const uint32_t *__restrict__ fc, const uint32_t *__restrict__ off_p,
-                                                   const uint32_t *__restrict__ off_m, uint32_t *ent_p,
-                                                   uint32_t *ent_m, const uint32_t *dirty, const uint32_t *n_dev,
-                                                   int64_t n_host, const uint32_t *__restrict__ cj,
-                                                   const uint32_t *__restrict__ cm) {
+__device__ inline void nbr_fill(uint32_t b, uint32_t nb, const uint8_t *__restrict__ level,
+                                const uint32_t *__restrict__ fc, const uint32_t *__restrict__ off_p,
+                                const uint32_t *__restrict__ off_m, uint32_t *ent_p, uint32_t *ent_m,
+                                const uint32_t *dirty, const uint32_t *n_dev, int64_t n_host,
+                                const uint32_t *__restrict__ cj, const uint32_t *__restrict__ cm) {
     const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
     const int face = threadIdx.x & 7;
     if (face >= 6) return;
-    const int64_t stride = ((int64_t)gridDim.x * kBlk) >> 3;
-    for (int64_t q = ((int64_t)blockIdx.x * kBlk + threadIdx.x) >> 3; q < n; q += stride) {
+    const int64_t stride = ((int64_t)nb * kBlk) >> 3;
+    for (int64_t q = ((int64_t)b * kBlk + threadIdx.x) >> 3; q < n; q += stride) {
         const int64_t i = dirty ? (int64_t)dirty[q] : q;
         const uint32_t j = cj[6 * q + face];
         if (j == kNone) continue;  // no neighbour, or a long range (written by the chunk fill)
@@ -381,11 +388,12 @@ __global__ void __launch_bounds__(kBlk) k_nbr_fill(const uint8_t *__restrict__ l
 }
 
 // Long lists of unchanged leaves, one wave per leaf of the old long-list work
-// lists (items 0..n_p-1: + lists, then - lists); an old leaf whose new
-// position holds another leaf, or a searched one, is skipped.
-__global__ void __launch_bounds__(kBlk) k_nbr_copy_long(int64_t L, NbrOld old, const uint32_t *off_p,
-                                                        const uint32_t *off_m, uint32_t *ent_p, uint32_t *ent_m) {
-    const uint32_t item = ((uint32_t)blockIdx.x * kBlk + threadIdx.x) >> 6;
+// lists (items 0..n_p-1: + lists, then - lists; block b of the long-list
+// blocks); an old leaf whose new position holds another leaf, or a searched
+// one, is skipped.
+__device__ inline void nbr_copy_long(uint32_t b, int64_t L, const NbrOld &old, const uint32_t *off_p,
+                                     const uint32_t *off_m, uint32_t *ent_p, uint32_t *ent_m) {
+    const uint32_t item = (b * kBlk + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     if (item >= old.n_heavy_p + old.n_heavy_m) return;
     const bool plus = item < old.n_heavy_p;
@@ -394,6 +402,34 @@ __global__ void __launch_bounds__(kBlk) k_nbr_copy_long(int64_t L, NbrOld old, c
     if ((int64_t)i >= L || old.need[i] || old.src[i] != j) return;
     if (plus) wave_copy(old.ent_p, old.off_p[j], old.off_p[j + 1], ent_p + off_p[i], old.remap, lane);
     else wave_copy(old.ent_m, old.off_m[j], old.off_m[j + 1], ent_m + off_m[i], old.remap, lane);
+}
+
+// The lists of unchanged leaves in one launch: the first long_blocks blocks
+// copy the long lists (a wave each, latency-bound), the others stream the
+// short ones; the two write disjoint entries.
+__global__ void __launch_bounds__(kBlk) k_nbr_fill_clean(int64_t L, const uint32_t *__restrict__ off_p,
+                                                         const uint32_t *__restrict__ off_m, uint32_t *ent_p,
+                                                         uint32_t *ent_m, NbrOld old, uint32_t long_blocks) {
+    if (blockIdx.x < long_blocks) nbr_copy_long(blockIdx.x, L, old, off_p, off_m, ent_p, ent_m);
+    else nbr_fill_clean(blockIdx.x - long_blocks, L, off_p, off_m, ent_p, ent_m, old);
+}
+
+// The searched leaves' lists in one launch: the first chunk_blocks blocks
+// write the long ranges (a wave per chunk), the others stride over the
+// searched leaves' short ranges; the two write disjoint entries.
+__global__ void __launch_bounds__(kBlk) k_nbr_fill(uint32_t chunk_blocks, uint32_t n_chunks, Heavy hv, Chunks ch,
+                                                   const uint32_t *__restrict__ key, int D,
+                                                   const uint8_t *__restrict__ level,
+                                                   const uint32_t *__restrict__ fc, const uint32_t *__restrict__ off_p,
+                                                   const uint32_t *__restrict__ off_m, uint32_t *ent_p,
+                                                   uint32_t *ent_m, const uint32_t *dirty, const uint32_t *n_dev,
+                                                   int64_t n_host, const uint32_t *__restrict__ cj,
+                                                   const uint32_t *__restrict__ cm) {
+    if (blockIdx.x < chunk_blocks)
+        nbr_chunk<true>(blockIdx.x, n_chunks, hv, ch, key, level, D, fc, off_p, off_m, ent_p, ent_m);
+    else
+        nbr_fill(blockIdx.x - chunk_blocks, gridDim.x - chunk_blocks, level, fc, off_p, off_m, ent_p, ent_m, dirty,
+                 n_dev, n_host, cj, cm);
 }
 
 __global__ void k_zero_n(uint32_t *p, int n) {
@@ -518,11 +554,9 @@ void search_end(Ctx &c, NbrPending &p, void (*overlap)(Ctx &)) {
         ch = Chunks{c.s.ch_item.p, c.s.ch_base.p, c.s.ch_count.p, c.s.ch_pos.p};
         hipLaunchKernelGGL(k_chunk_expand, dim3((unsigned)cdiv(n_chunks, kBlk)), dim3(kBlk), 0, c.stream, n_heavy,
                            n_chunks, c.s.ch_base.p, c.s.ch_item.p);
-        hipLaunchKernelGGL(k_nbr_chunk<false>, dim3((unsigned)cdiv((int64_t)n_chunks * 64, kBlk)), dim3(kBlk), 0,
-                           c.stream, n_chunks, hv, ch, s.key.p, s.level.p, D, (const uint32_t *)c.s.g.p,
-                           (const uint32_t *)nullptr, (const uint32_t *)nullptr, (uint32_t *)nullptr,
-                           (uint32_t *)nullptr);
-        OTF_LAUNCH_CHECK("k_nbr_chunk count");
+        hipLaunchKernelGGL(k_nbr_chunk_count, dim3((unsigned)cdiv((int64_t)n_chunks * 64, kBlk)), dim3(kBlk), 0,
+                           c.stream, n_chunks, hv, ch, s.key.p, s.level.p, D);
+        OTF_LAUNCH_CHECK("k_nbr_chunk_count");
         scan_exclusive_u32_dev(c, c.s.ch_count.p, c.s.ch_pos.p, n_chunks);
         hipLaunchKernelGGL(k_chunk_totals, dim3(gi), dim3(kBlk), 0, c.stream, n_heavy, hv, ch, c.s.g.p, c.s.a.p,
                            c.s.b.p);
@@ -547,26 +581,19 @@ void search_end(Ctx &c, NbrPending &p, void (*overlap)(Ctx &)) {
     s.nbp.reserve(s.n_nbp);
     s.nbm.reserve(s.n_nbm);
     if (old.need) {
-        hipLaunchKernelGGL(k_nbr_fill_clean, dim3(g), dim3(kBlk), 0, c.stream, L, (const uint32_t *)s.nbp_off.p,
-                           (const uint32_t *)s.nbm_off.p, s.nbp.p, s.nbm.p, old);
-        OTF_LAUNCH_CHECK("k_nbr_fill_clean");
         const int64_t n_long = (int64_t)old.n_heavy_p + old.n_heavy_m;
-        if (n_long > 0) {
-            hipLaunchKernelGGL(k_nbr_copy_long, dim3((unsigned)cdiv(n_long * 64, kBlk)), dim3(kBlk), 0, c.stream, L,
-                               old, (const uint32_t *)s.nbp_off.p, (const uint32_t *)s.nbm_off.p, s.nbp.p, s.nbm.p);
-            OTF_LAUNCH_CHECK("k_nbr_copy_long");
-        }
+        const int64_t lb = cdiv(n_long * 64, kBlk);
+        hipLaunchKernelGGL(k_nbr_fill_clean, dim3((unsigned)(lb + g)), dim3(kBlk), 0, c.stream, L,
+                           (const uint32_t *)s.nbp_off.p, (const uint32_t *)s.nbm_off.p, s.nbp.p, s.nbm.p, old,
+                           (uint32_t)lb);
+        OTF_LAUNCH_CHECK("k_nbr_fill_clean");
     }
-    hipLaunchKernelGGL(k_nbr_fill, dim3(grid8(L)), dim3(kBlk), 0, c.stream, s.level.p, (const uint32_t *)c.s.g.p,
-                       (const uint32_t *)s.nbp_off.p, (const uint32_t *)s.nbm_off.p, s.nbp.p, s.nbm.p, p.dirty,
-                       p.n_dirty_dev, L, (const uint32_t *)c.s.nb_j.p, (const uint32_t *)c.s.nb_m.p);
+    const int64_t cb = n_heavy > 0 ? cdiv((int64_t)n_chunks * 64, kBlk) : 0;
+    hipLaunchKernelGGL(k_nbr_fill, dim3((unsigned)(cb + grid8(L))), dim3(kBlk), 0, c.stream, (uint32_t)cb, n_chunks,
+                       hv, ch, s.key.p, D, s.level.p, (const uint32_t *)c.s.g.p, (const uint32_t *)s.nbp_off.p,
+                       (const uint32_t *)s.nbm_off.p, s.nbp.p, s.nbm.p, p.dirty, p.n_dirty_dev, L,
+                       (const uint32_t *)c.s.nb_j.p, (const uint32_t *)c.s.nb_m.p);
     OTF_LAUNCH_CHECK("k_nbr_fill");
-    if (n_heavy > 0) {
-        hipLaunchKernelGGL(k_nbr_chunk<true>, dim3((unsigned)cdiv((int64_t)n_chunks * 64, kBlk)), dim3(kBlk), 0,
-                           c.stream, n_chunks, hv, ch, s.key.p, s.level.p, D, (const uint32_t *)c.s.g.p,
-                           (const uint32_t *)s.nbp_off.p, (const uint32_t *)s.nbm_off.p, s.nbp.p, s.nbm.p);
-        OTF_LAUNCH_CHECK("k_nbr_chunk fill");
-    }
 }
 
 }  // namespace
