@@ -232,23 +232,31 @@ otf_status guard(otf_ctx *ctx, bool invalidates, F &&f) {
             return OTF_E_DEVICE;
         }
     }
+    // after a failure, work the call left on the second stream is waited for
+    // (a later call may reuse its buffers)
+    auto settle = [&] {
+        if (ctx && ctx->c.side) (void)hipStreamSynchronize(ctx->c.side);
+    };
     try {
         f();
         if (ctx) ctx->c.err.clear();
         return OTF_OK;
     } catch (const Failure &e) {
+        settle();
         if (ctx) {
             ctx->c.err = e.msg;
             if (invalidates && e.st != OTF_E_INVALID) ctx->c.valid = false;
         }
         return e.st;
     } catch (const std::bad_alloc &) {
+        settle();
         if (ctx) {
             ctx->c.err = "host allocation failed";
             if (invalidates) ctx->c.valid = false;
         }
         return OTF_E_NOMEM;
     } catch (...) {
+        settle();
         if (ctx) {
             ctx->c.err = "unexpected failure";
             if (invalidates) ctx->c.valid = false;
@@ -284,6 +292,9 @@ otf_status otf_create(int device, void *hip_stream, otf_ctx **out) {
         void *d = nullptr;
         OTF_HIP(hipHostGetDevicePointer(&d, h, 0));
         ctx->c.d_h_counters = (uint32_t *)d;
+        OTF_HIP(hipStreamCreateWithFlags(&ctx->c.side, hipStreamNonBlocking));
+        OTF_HIP(hipEventCreateWithFlags(&ctx->c.ev_fork, hipEventDisableTiming));
+        OTF_HIP(hipEventCreateWithFlags(&ctx->c.ev_join, hipEventDisableTiming));
     });
     if (st != OTF_OK) {
         otf_destroy(ctx);
@@ -297,6 +308,12 @@ otf_status otf_destroy(otf_ctx *ctx) {
     if (!ctx) return OTF_E_INVALID;
     (void)hipSetDevice(ctx->c.device);
     (void)hipStreamSynchronize(ctx->c.stream);
+    if (ctx->c.side) {
+        (void)hipStreamSynchronize(ctx->c.side);
+        (void)hipStreamDestroy(ctx->c.side);
+    }
+    if (ctx->c.ev_fork) (void)hipEventDestroy(ctx->c.ev_fork);
+    if (ctx->c.ev_join) (void)hipEventDestroy(ctx->c.ev_join);
     if (ctx->c.h_counters) (void)hipHostFree(ctx->c.h_counters);
     for (auto &e : ctx->c.ev_pool) (void)hipEventDestroy(e);
     delete ctx;

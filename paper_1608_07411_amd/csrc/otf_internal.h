@@ -332,6 +332,11 @@ struct Ctx {
     int device = 0;
     Solver sol;
     hipStream_t stream = nullptr;
+    // a second stream of the library's own (default priority) with fork and
+    // join events: a restructure's observation gather runs there beside the
+    // adjacency search; every use is joined back into `stream`
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     otf_params prm{};
     int n_views = 0;
     int64_t iteration = 0;
@@ -352,6 +357,7 @@ struct Ctx {
     uint32_t *h_counters = nullptr;    // pinned, coherent host slots for read-backs (32)
     uint32_t *d_h_counters = nullptr;  // the same slots as the device addresses them
     uint32_t read_seq = 0;             // last read-back sequence number issued
+    uint32_t side_seq = 0;             // the same for read-backs on the second stream
     int64_t part_blocks = 0;           // blocks (flag-count partials) of the last primal launch
     int64_t last_splits = 0, last_joins = 0;
     int64_t pool_compactions = 0;  // observation pool compactions by restructures
@@ -397,6 +403,7 @@ struct Ctx {
 // read-back may use the same slots.
 constexpr int kReadMax = 4;
 constexpr int kScanHealthSlot = 24;
+constexpr int kSideSeqSlot = 30;
 constexpr int kSeqSlot = 31;
 struct ReadItem {
     const uint32_t *src;
@@ -405,6 +412,19 @@ struct ReadItem {
 uint32_t read_back_begin(Ctx &c, std::initializer_list<ReadItem> items);
 void read_back_wait(Ctx &c, uint32_t ticket);
 void read_back(Ctx &c, std::initializer_list<ReadItem> items);
+// The same on the second stream, with its own sequence slot (kSideSeqSlot),
+// so that read-backs of the two streams never overtake each other's number.
+uint32_t read_back_begin_side(Ctx &c, std::initializer_list<ReadItem> items);
+void read_back_wait_side(Ctx &c, uint32_t ticket);
+// While alive, the launchers issue their work on the second stream.
+struct OnSideStream {
+    Ctx &c;
+    hipStream_t saved;
+    explicit OnSideStream(Ctx &cc) : c(cc), saved(cc.stream) { c.stream = c.side; }
+    ~OnSideStream() { c.stream = saved; }
+    OnSideStream(const OnSideStream &) = delete;
+    OnSideStream &operator=(const OnSideStream &) = delete;
+};
 // all work on the stream finished (stream synchronised), scan health checked
 void finish(Ctx &c);
 // scans over n elements; the total is returned to the host (synchronises)

@@ -800,28 +800,38 @@ bool restructure(Ctx &c, float tl) {
                        n_new);
     // one fetch pass: sorted observations into rows of n_views (headers
     // written into the new store), placed into the pool once its offsets are
-    // known
+    // known. It runs on the second stream, beside the new store's adjacency
+    // search on this one: the search reads keys, levels and marks, the fetch
+    // writes observation headers, rows, their offsets and the observation
+    // totals, and neither runs a scan while the other does (they share the
+    // scan state). Joined before the pool is written.
     DBuf<uint8_t> &Mt = s.r_Mt;
     Mt.reserve(n_new);
     const int stride = c.n_views;
     s.fa.reserve((size_t)n_new * stride);
     s.fb.reserve((size_t)n_new * stride);
     s.fe.reserve((size_t)n_new * stride);
-    gather_rows(c, n_new, ns.key.p, ns.level.p, tidx.p, stride, s.fa.p, s.fb.p, s.fe.p, Mt.p, ns.obs_m.p,
-                ns.obs_unit.p, ns.inv.p, ns.wtot.p);
     moff.reserve(n_new + 1);
-    scan_exclusive_u32_dev_u8(c, Mt.p, moff.p, n_new);
     ObsPool &pool = c.op();
     // the new store becomes current; its observation totals (the live
-    // observations among them) are counted, and its adjacency search, which
-    // does not depend on the observation pool, runs while the host waits
+    // observations among them) are counted with the fetch
     c.cur ^= 1;
     c.L = Lnew;
-    count_obs(c);
-    const uint32_t t_obs =
-        read_back_begin(c, {{moff.p + n_new, 19}, {c.counters.p + 4, 20}, {nrank.p + Lnew, 21}});
+    OTF_HIP(hipEventRecord(c.ev_fork, c.stream));
+    OTF_HIP(hipStreamWaitEvent(c.side, c.ev_fork, 0));
+    uint32_t t_obs;
+    {
+        OnSideStream on_side(c);
+        gather_rows(c, n_new, ns.key.p, ns.level.p, tidx.p, stride, s.fa.p, s.fb.p, s.fe.p, Mt.p, ns.obs_m.p,
+                    ns.obs_unit.p, ns.inv.p, ns.wtot.p);
+        scan_exclusive_u32_dev_u8(c, Mt.p, moff.p, n_new);
+        count_obs(c);
+        t_obs = read_back_begin_side(c, {{moff.p + n_new, 19}, {c.counters.p + 4, 20}, {nrank.p + Lnew, 21}});
+        OTF_HIP(hipEventRecord(c.ev_join, c.side));
+    }
     NbrPending nbr = build_neighbours_begin(c, os, out_off, true);
-    read_back_wait(c, t_obs);
+    read_back_wait_side(c, t_obs);
+    OTF_HIP(hipStreamWaitEvent(c.stream, c.ev_join, 0));
     const uint32_t new_obs = c.h_counters[19], live = c.h_counters[20];
     if (c.h_counters[21] != n_new) fail(OTF_E_DEVICE, "new-leaf counts disagree");
     const bool compact = (pool.used + (int64_t)new_obs > pool.cap) || (pool.used > 2 * (int64_t)live + 4096);

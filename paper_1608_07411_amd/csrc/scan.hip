@@ -400,11 +400,11 @@ struct ReadArgs {
 };
 
 // one lane: the values, then (release, system scope) the sequence number
-__global__ void k_read_back(ReadArgs a, uint32_t *host, uint32_t seq) {
+__global__ void k_read_back(ReadArgs a, uint32_t *host, int seq_slot, uint32_t seq) {
     if (threadIdx.x != 0) return;
     for (int t = 0; t < a.n; ++t)
         __hip_atomic_store(host + a.slot[t], *a.src[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_store(host + kSeqSlot, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(host + seq_slot, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 uint32_t read_total(Ctx &c, const uint32_t *dev) {
@@ -414,7 +414,8 @@ uint32_t read_total(Ctx &c, const uint32_t *dev) {
 
 }  // namespace
 
-uint32_t read_back_begin(Ctx &c, std::initializer_list<ReadItem> items) {
+namespace {
+uint32_t rb_begin(Ctx &c, std::initializer_list<ReadItem> items, hipStream_t st, int seq_slot, uint32_t &counter) {
     if (items.size() > (size_t)kReadMax) fail(OTF_E_INVALID, "too many read-back items");
     ReadArgs a{};
     for (const ReadItem &it : items) {
@@ -425,8 +426,8 @@ uint32_t read_back_begin(Ctx &c, std::initializer_list<ReadItem> items) {
     a.src[a.n] = c.counters.p + kScanHealthSlot;
     a.slot[a.n] = kScanHealthSlot;
     ++a.n;
-    const uint32_t seq = ++c.read_seq;
-    hipLaunchKernelGGL(k_read_back, dim3(1), dim3(64), 0, c.stream, a, c.d_h_counters, seq);
+    const uint32_t seq = ++counter;
+    hipLaunchKernelGGL(k_read_back, dim3(1), dim3(64), 0, st, a, c.d_h_counters, seq_slot, seq);
     OTF_LAUNCH_CHECK("k_read_back");
     return seq;
 }
@@ -434,12 +435,12 @@ uint32_t read_back_begin(Ctx &c, std::initializer_list<ReadItem> items) {
 // Spins until the sequence number reaches the ticket. Every few thousand
 // polls the stream is queried: an error fails; a finished stream without the
 // number means the store never arrived and fails too.
-void read_back_wait(Ctx &c, uint32_t ticket) {
-    const uint32_t *seqp = c.h_counters + kSeqSlot;
+void rb_wait(Ctx &c, uint32_t ticket, hipStream_t st, int seq_slot) {
+    const uint32_t *seqp = c.h_counters + seq_slot;
     auto arrived = [&] { return (int32_t)(__atomic_load_n(seqp, __ATOMIC_ACQUIRE) - ticket) >= 0; };
     for (uint32_t spins = 1; !arrived(); ++spins) {
         if ((spins & 4095u) == 0) {
-            const hipError_t e = hipStreamQuery(c.stream);
+            const hipError_t e = hipStreamQuery(st);
             if (e == hipSuccess) {
                 if (arrived()) break;
                 fail(OTF_E_DEVICE, "read-back store did not arrive");
@@ -453,6 +454,19 @@ void read_back_wait(Ctx &c, uint32_t ticket) {
     if (__atomic_load_n(c.h_counters + kScanHealthSlot, __ATOMIC_ACQUIRE))
         fail(OTF_E_DEVICE, "a device scan's look-back wait timed out");
 }
+}  // namespace
+
+uint32_t read_back_begin(Ctx &c, std::initializer_list<ReadItem> items) {
+    return rb_begin(c, items, c.stream, kSeqSlot, c.read_seq);
+}
+
+void read_back_wait(Ctx &c, uint32_t ticket) { rb_wait(c, ticket, c.stream, kSeqSlot); }
+
+uint32_t read_back_begin_side(Ctx &c, std::initializer_list<ReadItem> items) {
+    return rb_begin(c, items, c.side, kSideSeqSlot, c.side_seq);
+}
+
+void read_back_wait_side(Ctx &c, uint32_t ticket) { rb_wait(c, ticket, c.side, kSideSeqSlot); }
 
 void read_back(Ctx &c, std::initializer_list<ReadItem> items) { read_back_wait(c, read_back_begin(c, items)); }
 
