@@ -166,23 +166,6 @@ __global__ void __launch_bounds__(kBlk) k_jval_level(const uint32_t *list, const
     }
 }
 
-__global__ void k_jval_emit(int64_t L, const uint8_t *jt, const uint8_t *jhead, const float *val, int64_t cap,
-                            const uint32_t *out_off, NewStore ns, const uint32_t *key) {
-    const int64_t i = TID();
-    if (i >= L || !jhead[i]) return;
-    const uint32_t w = out_off[i];
-    ns.key[w] = key[i];
-    ns.level[w] = jt[i];
-    ns.u[w] = val[i];
-    ns.ubar[w] = val[cap + i];
-    ns.p[w] = val[2 * cap + i];
-    ns.p[ns.cap + w] = val[3 * cap + i];
-    ns.p[2 * ns.cap + w] = val[4 * cap + i];
-    ns.isnew[w] = 1;
-    ns.src[w] = kNone;
-    ns.need[w] = 1;
-}
-
 // ---------------------------------------------------------------- splits
 __global__ void k_make_parents0(int64_t L, const uint8_t *flag, const uint32_t *rank, uint32_t *porigin) {
     const int64_t i = TID();
@@ -313,11 +296,30 @@ __global__ void __launch_bounds__(kBlk) k_out_count(int64_t L, const uint8_t *fl
     }
 }
 
-__global__ void k_emit_keep(int64_t L, OldStore o, const uint8_t *jt, int splits, const uint32_t *out_off,
-                            NewStore ns) {
+// Kept leaves are copied; the head of a collapse writes the collapsed leaf
+// (its level and hierarchical means, computed in place at the head's old
+// position: val[k * vcap + i] for u, ubar, p_x, p_y, p_z); absorbed and split
+// leaves write nothing here.
+__global__ void k_emit_keep(int64_t L, OldStore o, const uint8_t *jt, const uint8_t *jhead, const float *val,
+                            int64_t vcap, int splits, const uint32_t *out_off, NewStore ns) {
     const int64_t i = TID();
     if (i >= L) return;
-    if ((jt && jt[i] != 0xFF) || (splits && (o.flag[i] & 1))) return;
+    if (jt && jt[i] != 0xFF) {
+        if (!jhead[i]) return;
+        const uint32_t w = out_off[i];
+        ns.key[w] = o.key[i];
+        ns.level[w] = jt[i];
+        ns.u[w] = val[i];
+        ns.ubar[w] = val[vcap + i];
+        ns.p[w] = val[2 * vcap + i];
+        ns.p[ns.cap + w] = val[3 * vcap + i];
+        ns.p[2 * ns.cap + w] = val[4 * vcap + i];
+        ns.isnew[w] = 1;
+        ns.src[w] = kNone;
+        ns.need[w] = 1;
+        return;
+    }
+    if (splits && (o.flag[i] & 1)) return;
     const uint32_t w = out_off[i];
     ns.key[w] = o.key[i];
     ns.level[w] = o.level[i];
@@ -348,17 +350,15 @@ __device__ inline bool changed(int64_t j, const uint8_t *flag, const uint8_t *jt
 // new position) is one round of loads in flight.
 constexpr int kMarkBatch = 8;
 
-__global__ void __launch_bounds__(kBlk) k_nbr_mark(int64_t L, const uint8_t *flag, const uint8_t *jt, int splits,
-                                                   const uint32_t *off_p, const uint32_t *ent_p,
-                                                   const uint32_t *off_m, const uint32_t *ent_m,
-                                                   const uint32_t *out_off, uint8_t *need) {
-    const int64_t i = TID();
+__device__ inline void nbr_mark(int64_t i, int64_t L, const uint8_t *flag, const uint8_t *jt, int splits,
+                                const uint32_t *off_p, const uint32_t *ent_p, const uint32_t *off_m,
+                                const uint32_t *ent_m, const uint32_t *out_off, uint8_t *need) {
     if (i >= L || !changed(i, flag, jt, splits)) return;
     const uint32_t *ent[2] = {ent_p, ent_m};
     uint32_t b0[2] = {off_p[i], off_m[i]}, b1[2] = {off_p[i + 1], off_m[i + 1]};
 #pragma unroll
     for (int sd = 0; sd < 2; ++sd)
-        if (b1[sd] - b0[sd] > kLongList) b1[sd] = b0[sd];  // long lists: k_nbr_mark_long
+        if (b1[sd] - b0[sd] > kLongList) b1[sd] = b0[sd];  // long lists: nbr_mark_long
     const uint32_t len = max(b1[0] - b0[0], b1[1] - b0[1]);
     for (uint32_t k = 0; k < len; k += kMarkBatch) {
         uint32_t n[2][kMarkBatch], o[2][kMarkBatch];
@@ -390,14 +390,11 @@ __global__ void __launch_bounds__(kBlk) k_nbr_mark(int64_t L, const uint8_t *fla
 }
 
 // Long lists of changed leaves: one wave per leaf on the old long-list work
-// lists, lanes striding over the entries.
-__global__ void __launch_bounds__(kBlk) k_nbr_mark_long(const uint8_t *flag, const uint8_t *jt, int splits,
-                                                        const uint32_t *off_p, const uint32_t *ent_p,
-                                                        const uint32_t *off_m, const uint32_t *ent_m,
-                                                        const uint32_t *heavy_p, const uint32_t *heavy_m,
-                                                        uint32_t n_heavy_p, uint32_t n_heavy_m,
-                                                        const uint32_t *out_off, uint8_t *need) {
-    const uint32_t item = ((uint32_t)blockIdx.x * kBlk + threadIdx.x) >> 6;
+// lists (item: + lists, then - lists), lanes striding over the entries.
+__device__ inline void nbr_mark_long(uint32_t item, const uint8_t *flag, const uint8_t *jt, int splits,
+                                     const uint32_t *off_p, const uint32_t *ent_p, const uint32_t *off_m,
+                                     const uint32_t *ent_m, const uint32_t *heavy_p, const uint32_t *heavy_m,
+                                     uint32_t n_heavy_p, uint32_t n_heavy_m, const uint32_t *out_off, uint8_t *need) {
     const uint32_t lane = threadIdx.x & 63;
     if (item >= n_heavy_p + n_heavy_m) return;
     const bool plus = item < n_heavy_p;
@@ -410,6 +407,22 @@ __global__ void __launch_bounds__(kBlk) k_nbr_mark_long(const uint8_t *flag, con
         const uint32_t n = ent[e] & kIdxMask;
         if (!changed(n, flag, jt, splits)) need[out_off[n]] = 1;
     }
+}
+
+// Both in one launch: the first long_blocks blocks take the long lists (a
+// wave each), the others one leaf per thread; every store writes 1.
+__global__ void __launch_bounds__(kBlk) k_nbr_mark(int64_t L, const uint8_t *flag, const uint8_t *jt, int splits,
+                                                   const uint32_t *off_p, const uint32_t *ent_p,
+                                                   const uint32_t *off_m, const uint32_t *ent_m,
+                                                   const uint32_t *heavy_p, const uint32_t *heavy_m,
+                                                   uint32_t n_heavy_p, uint32_t n_heavy_m, uint32_t long_blocks,
+                                                   const uint32_t *out_off, uint8_t *need) {
+    if (blockIdx.x < long_blocks)
+        nbr_mark_long(((uint32_t)blockIdx.x * kBlk + threadIdx.x) >> 6, flag, jt, splits, off_p, ent_p, off_m, ent_m,
+                      heavy_p, heavy_m, n_heavy_p, n_heavy_m, out_off, need);
+    else
+        nbr_mark((int64_t)(blockIdx.x - long_blocks) * kBlk + threadIdx.x, L, flag, jt, splits, off_p, ent_p, off_m,
+                 ent_m, out_off, need);
 }
 
 __global__ void k_pos0(int64_t nc, const uint32_t *corigin, const uint32_t *out_off, const uint32_t *cnt,
@@ -747,14 +760,9 @@ bool restructure(Ctx &c, float tl) {
                        ns.obs_unit.p, ns.inv.p, ns.wtot.p,  isnew.p, ns.src.p, ns.need.p};
     const OldStore osd{os.key.p, os.level.p, os.u.p, os.ubar.p, os.p.p, os.cap, os.obs_off.p, os.obs_m.p,
                        os.obs_unit.p, os.inv.p, os.wtot.p, os.flag.p};
-    hipLaunchKernelGGL(k_emit_keep, dim3(gL), dim3(kBlk), 0, c.stream, L, osd, jt, n_split > 0 ? 1 : 0, out_off,
-                       nsd);
+    hipLaunchKernelGGL(k_emit_keep, dim3(gL), dim3(kBlk), 0, c.stream, L, osd, jt, jhead,
+                       jt ? (const float *)s.r_jv.p : (const float *)nullptr, L, n_split > 0 ? 1 : 0, out_off, nsd);
     OTF_LAUNCH_CHECK("k_emit_keep");
-    if (jt) {
-        hipLaunchKernelGGL(k_jval_emit, dim3(gL), dim3(kBlk), 0, c.stream, L, jt, jhead, s.r_jv.p, L, out_off, nsd,
-                           os.key.p);
-        OTF_LAUNCH_CHECK("k_jval_emit");
-    }
     for (int64_t q = 0; q < nrounds; ++q) {
         Round &R = *s.rounds[q];
         if (q == 0) {
@@ -771,16 +779,12 @@ bool restructure(Ctx &c, float tl) {
         OTF_LAUNCH_CHECK("cascade emission");
     }
     // adjacency: a kept leaf next to a change is searched again
-    hipLaunchKernelGGL(k_nbr_mark, dim3(gL), dim3(kBlk), 0, c.stream, L, os.flag.p, jt, n_split > 0 ? 1 : 0,
-                       os.nbp_off.p, os.nbp.p, os.nbm_off.p, os.nbm.p, out_off, ns.need.p);
-    OTF_LAUNCH_CHECK("k_nbr_mark");
     const int64_t n_long = (int64_t)os.n_heavy_p + os.n_heavy_m;
-    if (n_long > 0) {
-        hipLaunchKernelGGL(k_nbr_mark_long, dim3(grid(64 * n_long)), dim3(kBlk), 0, c.stream, os.flag.p, jt,
-                           n_split > 0 ? 1 : 0, os.nbp_off.p, os.nbp.p, os.nbm_off.p, os.nbm.p, os.heavy_p.p,
-                           os.heavy_m.p, (uint32_t)os.n_heavy_p, (uint32_t)os.n_heavy_m, out_off, ns.need.p);
-        OTF_LAUNCH_CHECK("k_nbr_mark_long");
-    }
+    const int64_t mlb = cdiv(64 * n_long, kBlk);
+    hipLaunchKernelGGL(k_nbr_mark, dim3((unsigned)(mlb + gL)), dim3(kBlk), 0, c.stream, L, os.flag.p, jt,
+                       n_split > 0 ? 1 : 0, os.nbp_off.p, os.nbp.p, os.nbm_off.p, os.nbm.p, os.heavy_p.p, os.heavy_m.p,
+                       (uint32_t)os.n_heavy_p, (uint32_t)os.n_heavy_m, (uint32_t)mlb, out_off, ns.need.p);
+    OTF_LAUNCH_CHECK("k_nbr_mark");
     if (Lnew < 0) take_counts();
     if (jt) c.last_joins = c.h_counters[13];
     c.last_splits = total_splits;
