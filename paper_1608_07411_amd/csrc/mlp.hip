@@ -191,6 +191,29 @@ __global__ void k_apply_warm(int64_t L, int64_t cap, const float *Y, float *u, f
     for (int d = 0; d < 3; ++d) p[(int64_t)d * cap + i] = q[d];
 }
 
+// The prediction applied at step alpha from the start (u0, p0): u = u0 +
+// alpha y0 (one rounding) kept in [-1, 1], ubar = u, p = (1 - alpha) p0 +
+// alpha q with q the projected prediction (a point of the unit ball again).
+// alpha = 1 gives k_apply_warm's values.
+__global__ void k_apply_warm_alpha(int64_t L, int64_t cap, const float *Y, const float *u0, const float *p0,
+                                   float alpha, float *u, float *ubar, float *p) {
+    const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
+    if (i >= L) return;
+    const float v = fminf(1.0f, fmaxf(-1.0f, __fmaf_rn(alpha, Y[4 * i], u0[i])));
+    u[i] = v;
+    ubar[i] = v;
+    float q[3] = {Y[4 * i + 1], Y[4 * i + 2], Y[4 * i + 3]};
+    const float r2 = __fmaf_rn(q[0], q[0], __fmaf_rn(q[1], q[1], q[2] * q[2]));
+    if (r2 > 1.0f) {
+        const float nrm = sqrtf(r2);
+        for (int d = 0; d < 3; ++d) q[d] = q[d] / nrm;
+    }
+    for (int d = 0; d < 3; ++d) {
+        const int64_t k = (int64_t)d * cap + i;
+        p[k] = __fmaf_rn(alpha, q[d], (1.0f - alpha) * p0[k]);
+    }
+}
+
 unsigned g1(int64_t n) { return (unsigned)cdiv(n > 0 ? n : 1, kBlk); }
 
 }  // namespace
@@ -471,6 +494,72 @@ otf_status otf_leaf_targets(otf_ctx *ctx, float *T, int64_t cap_rows) {
         hipLaunchKernelGGL(k_targets, dim3(g1(c.L)), dim3(kBlk), 0, c.stream, c.L, s.cap, s.u.p, s.p.p, T);
         OTF_LAUNCH_CHECK("k_targets");
         OTF_HIP(hipStreamSynchronize(c.stream));
+    } catch (const Failure &e) {
+        c.err = e.msg;
+        return e.st;
+    }
+    return OTF_OK;
+}
+
+otf_status otf_warm_start_judged(otf_ctx *ctx, otf_mlp *nn, float lambda, int32_t n_alpha, const float *alphas,
+                                 float *alpha_used, double *energy_used) {
+    if (!ctx || !nn || !alphas || !alpha_used || !energy_used) return OTF_E_INVALID;
+    if (n_alpha < 1 || n_alpha > 8 || !std::isfinite(lambda) || lambda < 0.0f) return OTF_E_INVALID;
+    for (int k = 0; k < n_alpha; ++k)
+        if (!(alphas[k] > 0.0f && alphas[k] <= 1.0f)) return OTF_E_INVALID;
+    if (!ctx->c.valid) return OTF_E_STATE;
+    if (ctx->c.device != nn->m.device || ctx->c.stream != nn->m.stream) return OTF_E_INVALID;
+    Ctx &c = ctx->c;
+    try {
+        OTF_HIP(hipSetDevice(c.device));
+        LeafStore &s = c.lv();
+        const int64_t L = c.L;
+        auto E = [&] {
+            double tv = 0.0, data = 0.0;
+            energy(c, &tv, &data);
+            return tv + (double)lambda * data;
+        };
+        // the plain start, kept for the candidates and as the fallback
+        DBuf<float> X, Y, u0, ub0, p0;
+        X.reserve((size_t)L * kIn);
+        Y.reserve((size_t)L * kOut);
+        u0.reserve((size_t)L);
+        ub0.reserve((size_t)L);
+        p0.reserve((size_t)3 * s.cap);
+        OTF_HIP(hipMemcpyAsync(u0.p, s.u.p, (size_t)L * sizeof(float), hipMemcpyDeviceToDevice, c.stream));
+        OTF_HIP(hipMemcpyAsync(ub0.p, s.ubar.p, (size_t)L * sizeof(float), hipMemcpyDeviceToDevice, c.stream));
+        OTF_HIP(hipMemcpyAsync(p0.p, s.p.p, (size_t)3 * s.cap * sizeof(float), hipMemcpyDeviceToDevice, c.stream));
+        const double e_plain = E();
+        hipLaunchKernelGGL(k_features, dim3(g1(L)), dim3(kBlk), 0, c.stream, L, c.prm.max_depth, c.prm.gamma,
+                           s.level.p, s.u.p, s.obs_off.p, s.obs_m.p, s.wtot.p, c.op().F.p, s.nbp_off.p, s.nbp.p,
+                           s.nbm_off.p, s.nbm.p, X.p);
+        OTF_LAUNCH_CHECK("k_features");
+        nn->m.forward(X.p, L, Y.p);
+        float best_a = 0.0f;
+        double best_e = e_plain;
+        for (int k = 0; k < n_alpha; ++k) {
+            hipLaunchKernelGGL(k_apply_warm_alpha, dim3(g1(L)), dim3(kBlk), 0, c.stream, L, s.cap, Y.p, u0.p, p0.p,
+                               alphas[k], s.u.p, s.ubar.p, s.p.p);
+            OTF_LAUNCH_CHECK("k_apply_warm_alpha");
+            const double e = E();
+            if (e < best_e) {
+                best_e = e;
+                best_a = alphas[k];
+            }
+        }
+        if (best_a == 0.0f) {  // the plain start
+            OTF_HIP(hipMemcpyAsync(s.u.p, u0.p, (size_t)L * sizeof(float), hipMemcpyDeviceToDevice, c.stream));
+            OTF_HIP(hipMemcpyAsync(s.ubar.p, ub0.p, (size_t)L * sizeof(float), hipMemcpyDeviceToDevice, c.stream));
+            OTF_HIP(hipMemcpyAsync(s.p.p, p0.p, (size_t)3 * s.cap * sizeof(float), hipMemcpyDeviceToDevice,
+                                   c.stream));
+        } else if (best_a != alphas[n_alpha - 1]) {
+            hipLaunchKernelGGL(k_apply_warm_alpha, dim3(g1(L)), dim3(kBlk), 0, c.stream, L, s.cap, Y.p, u0.p, p0.p,
+                               best_a, s.u.p, s.ubar.p, s.p.p);
+            OTF_LAUNCH_CHECK("k_apply_warm_alpha");
+        }
+        OTF_HIP(hipStreamSynchronize(c.stream));
+        *alpha_used = best_a;
+        *energy_used = best_e;
     } catch (const Failure &e) {
         c.err = e.msg;
         return e.st;

@@ -77,16 +77,20 @@ def energy(c, lam: float) -> float:
     return tv + lam * data
 
 
-def time_to_tolerance(c, w, e_target: float, max_iter: int, chunk: int = 10, warm_net=None):
-    """Iterations and solver seconds (warm-start inference included) until
-    E <= e_target, checking every `chunk` iterations."""
+def time_to_tolerance(c, w, e_target: float, max_iter: int, chunk: int = 10, warm_net=None,
+                      alphas=(1.0, 0.5, 0.25)):
+    """Iterations, solver seconds (warm start included) and the warm start's
+    step until E <= e_target, checking every `chunk` iterations. The warm
+    start is judged by the energy: the network's prediction is kept at the
+    step (alphas, or none) that lowers the energy most."""
     import torch
 
     torch.cuda.synchronize()
     t = 0.0
+    alpha = None
     if warm_net is not None:
         t0 = time.perf_counter()
-        c.warm_start(warm_net)
+        alpha, _ = c.warm_start_judged(warm_net, w.lam, alphas)
         torch.cuda.synchronize()
         t += time.perf_counter() - t0
     it = 0
@@ -97,8 +101,8 @@ def time_to_tolerance(c, w, e_target: float, max_iter: int, chunk: int = 10, war
         t += time.perf_counter() - t0
         it += chunk
         if energy(c, w.lam) <= e_target:
-            return it, t, True
-    return it, t, False
+            return it, t, True, alpha
+    return it, t, False, alpha
 
 
 def distance_to_solution(net, scenes, iterations: int):
@@ -141,8 +145,10 @@ def evaluate(net, scenes, ref_iterations: int, tol: float = 1e-4, log=print):
             c = otf.Context(0).build_octree(depth, w.cams, w.params)
             if nn is not None:
                 e_w = None
-            it, t, ok = time_to_tolerance(c, w, target, 3 * ref_iterations, warm_net=nn)
+            it, t, ok, alpha = time_to_tolerance(c, w, target, 3 * ref_iterations, warm_net=nn)
             res[name] = {"iterations": it, "seconds": t, "reached": ok}
+            if nn is not None:
+                res[name]["alpha"] = alpha
             if nn is not None:
                 c2 = otf.Context(0).build_octree(depth, w.cams, w.params)
                 c2.warm_start(nn)

@@ -138,3 +138,47 @@ def test_trained_warm_start_moves_u_toward_the_solution():
     res = warm.distance_to_solution(net, [synth.warm_training_workload(90000 + k) for k in range(2)], 200)
     for r in res:
         assert r["rms_warm_start"] < 0.9 * r["rms_plain_start"], r
+
+
+def _energy(g, lam):
+    tv, data = g.energy()
+    return tv + lam * data
+
+
+@pytest.mark.parametrize("scale", [0.3, 3.0])
+def test_judged_warm_start_keeps_the_lowest_energy(scale):
+    """The judged warm start against the plain warm start on twin contexts:
+    the kept state is the candidate (alpha 1, 0.5 or the current state) of
+    lowest energy, bit for bit; a network far off (scale 3) is rejected when
+    every candidate raises the energy."""
+    lam = 0.5
+    w = synth.sphere_workload(max_depth=5, n_views=4, W=80, H=60, f=75.0, restructure_every=0)
+    net = otf.Mlp(0)
+    net.set_params(om.init_params(13) * scale)
+    g = otf.Context(0).build_octree(w.depth, w.cams, w.params)
+    g.fuse(3, lam, TAU32, TAU32)
+    st = g.extract()
+    e_plain = _energy(g, lam)
+    Y = net.forward(g.features()).cpu().numpy()
+    # candidate alpha = 1: the plain warm start on a twin context
+    t = otf.Context(0).build_octree(w.depth, w.cams, w.params)
+    t.fuse(3, lam, TAU32, TAU32)
+    t.warm_start(net)
+    e_one = _energy(t, lam)
+    one = t.extract()
+    a, e = g.warm_start_judged(net, lam, (1.0, 0.5))
+    lv = g.extract()
+    assert a in (0.0, 0.5, 1.0)
+    assert e <= e_plain and e <= e_one
+    assert abs(_energy(g, lam) - e) <= 1e-9 * max(1.0, abs(e))
+    if a == 1.0:
+        for k in ("u", "ubar", "p"):
+            assert np.array_equal(lv[k], one[k]), k
+    elif a == 0.0:
+        assert e == e_plain and e_one >= e_plain
+        for k in ("u", "ubar", "p"):
+            assert np.array_equal(lv[k], st[k]), k
+    else:
+        want = np.clip(np.float32(0.5) * Y[:, 0] + st["u"], -1.0, 1.0)
+        assert np.array_equal(lv["u"], want.astype(np.float32)) and e < min(e_plain, e_one)
+    g.fuse(5, lam, TAU32, TAU32)  # the solver runs from the kept state
