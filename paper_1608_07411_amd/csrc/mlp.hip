@@ -214,6 +214,112 @@ __global__ void k_apply_warm_alpha(int64_t L, int64_t cap, const float *Y, const
     }
 }
 
+// Inference forward in one launch. A block holds every layer's weights
+// (transposed, bf16: row n of W^T is column n of W) and biases in LDS; each
+// wave takes a tile of 16 rows through the four layers, its activations
+// staged in LDS between layers as bf16 (the values the layered forward
+// stores). Operands, the order of the MFMA steps over k and the epilogue
+// (+ bias, ReLU, bf16 rounding) are k_gemm's, so the outputs equal the
+// layered forward's bit for bit; only the features are read and the 4
+// outputs written. Row pitches of 4 extra elements keep the 8-byte operand
+// reads of the 16 lanes of a row group on different banks.
+constexpr int kFusedWaves = 4;
+constexpr int kPitchIn = kIn + 4, kPitchHid = kHid + 4;
+struct __align__(16) FusedLds {
+    uint16_t w0[kHid * kPitchIn];
+    uint16_t w1[kHid * kPitchHid];
+    uint16_t w2[kHid * kPitchHid];
+    uint16_t w3[16 * kPitchHid];  // 4 outputs padded to 16 columns of zeros
+    float b[3 * kHid + 16];
+    uint16_t x[kFusedWaves][16 * kPitchIn];
+    uint16_t h[kFusedWaves][2][16 * kPitchHid];
+};
+
+// W (K x N, row-major bf16) into W^T rows of pitch `pitch`
+__device__ inline void stage_wt(const uint16_t *W, int K, int N, uint16_t *wt, int pitch) {
+    for (int idx = threadIdx.x; idx < K * N; idx += blockDim.x) wt[(idx % N) * pitch + idx / N] = W[idx];
+}
+
+// One layer of the wave's tile: out(16 x 16 NT) = in(16 x K) W + b, as k_gemm
+// computes each 16 x 16 output tile.
+template <int K, int NT>
+__device__ inline void fused_layer(const uint16_t *in, int pin, const uint16_t *wt, int pw, const float *bias,
+                                   uint16_t *out, int pout, int lane) {
+    const int r16 = lane & 15, kq = 4 * (lane >> 4);
+    for (int t = 0; t < NT; ++t) {
+        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int k0 = 0; k0 < K; k0 += 16) {
+            const bf16x4 a = *reinterpret_cast<const bf16x4 *>(in + r16 * pin + k0 + kq);
+            const bf16x4 b = *reinterpret_cast<const bf16x4 *>(wt + (t * 16 + r16) * pw + k0 + kq);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float v = fmaxf(acc[r] + bias[t * 16 + r16], 0.0f);
+            out[(kq + r) * pout + t * 16 + r16] = f2bf(v);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(64 * kFusedWaves) k_mlp_forward(const float *X, int64_t rows,
+                                                                  const uint16_t *wbf, const float *theta,
+                                                                  int64_t ow0, int64_t ow1, int64_t ow2, int64_t ow3,
+                                                                  int64_t ob0, int64_t ob1, int64_t ob2, int64_t ob3,
+                                                                  float *Y) {
+    __shared__ FusedLds s;
+    stage_wt(wbf + ow0, kIn, kHid, s.w0, kPitchIn);
+    stage_wt(wbf + ow1, kHid, kHid, s.w1, kPitchHid);
+    stage_wt(wbf + ow2, kHid, kHid, s.w2, kPitchHid);
+    for (int i = threadIdx.x; i < 16 * kPitchHid; i += blockDim.x) s.w3[i] = 0;
+    __syncthreads();
+    stage_wt(wbf + ow3, kHid, kOut, s.w3, kPitchHid);
+    for (int i = threadIdx.x; i < kHid; i += blockDim.x) {
+        s.b[i] = theta[ob0 + i];
+        s.b[kHid + i] = theta[ob1 + i];
+        s.b[2 * kHid + i] = theta[ob2 + i];
+    }
+    if (threadIdx.x < 16) s.b[3 * kHid + threadIdx.x] = threadIdx.x < kOut ? theta[ob3 + threadIdx.x] : 0.0f;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t ntiles = (rows + 15) / 16;
+    // block-uniform loop: every wave of the block takes one tile per round
+    for (int64_t g = blockIdx.x; g * kFusedWaves < ntiles; g += gridDim.x) {
+        const int64_t m0 = (g * kFusedWaves + wv) * 16;
+        {  // the tile's features to bf16: lane takes 8 of row lane / 4
+            const int r = lane >> 2, k = (lane & 3) * 8;
+            const int64_t row = m0 + r;
+            for (int j = 0; j < 8; ++j)
+                s.x[wv][r * kPitchIn + k + j] = row < rows ? f2bf(X[row * kIn + k + j]) : (uint16_t)0;
+        }
+        __syncthreads();
+        fused_layer<kIn, kHid / 16>(s.x[wv], kPitchIn, s.w0, kPitchIn, s.b, s.h[wv][0], kPitchHid, lane);
+        __syncthreads();
+        fused_layer<kHid, kHid / 16>(s.h[wv][0], kPitchHid, s.w1, kPitchHid, s.b + kHid, s.h[wv][1], kPitchHid, lane);
+        __syncthreads();
+        fused_layer<kHid, kHid / 16>(s.h[wv][1], kPitchHid, s.w2, kPitchHid, s.b + 2 * kHid, s.h[wv][0], kPitchHid,
+                                     lane);
+        __syncthreads();
+        {  // output layer: fp32, no ReLU; lane holds column r16 of rows kq..kq+3
+            const int r16 = lane & 15, kq = 4 * (lane >> 4);
+            f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int k0 = 0; k0 < kHid; k0 += 16) {
+                const bf16x4 a = *reinterpret_cast<const bf16x4 *>(s.h[wv][0] + r16 * kPitchHid + k0 + kq);
+                const bf16x4 b = *reinterpret_cast<const bf16x4 *>(s.w3 + r16 * kPitchHid + k0 + kq);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+            }
+            if (r16 < kOut)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t row = m0 + kq + r;
+                    if (row < rows) Y[row * kOut + r16] = acc[r] + s.b[3 * kHid + r16];
+                }
+        }
+        __syncthreads();
+    }
+}
+
 unsigned g1(int64_t n) { return (unsigned)cdiv(n > 0 ? n : 1, kBlk); }
 
 }  // namespace
@@ -284,6 +390,16 @@ struct Mlp {
                  last ? nullptr : H[l].p, theta.p + off_b[l], last ? 0 : 1, nullptr);
             if (!last) h = H[l].p;
         }
+    }
+
+    // the same outputs in one launch (k_mlp_forward), for inference
+    void forward_fused(const float *Xf, int64_t rows, float *Yout) {
+        const int64_t groups = cdiv(cdiv(rows, 16), kFusedWaves);
+        if (groups == 0) return;
+        hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)std::min<int64_t>(groups, 1024)), dim3(64 * kFusedWaves), 0,
+                           stream, Xf, rows, (const uint16_t *)wbf.p, (const float *)theta.p, off_w[0], off_w[1],
+                           off_w[2], off_w[3], off_b[0], off_b[1], off_b[2], off_b[3], Yout);
+        OTF_LAUNCH_CHECK("k_mlp_forward");
     }
 
     // loss and gradient (grad) of the mean squared error against T (rows x 4)
@@ -519,8 +635,9 @@ otf_status otf_warm_start_judged(otf_ctx *ctx, otf_mlp *nn, float lambda, int32_
             energy(c, &tv, &data);
             return tv + (double)lambda * data;
         };
-        // the plain start, kept for the candidates and as the fallback
-        DBuf<float> X, Y, u0, ub0, p0;
+        // the plain start, kept for the candidates and as the fallback (the
+        // context's grow-only scratch: no allocation once it is large enough)
+        DBuf<float> &X = c.s.fa, &Y = c.s.fb, &u0 = c.s.fc, &ub0 = c.s.fd, &p0 = c.s.fe;
         X.reserve((size_t)L * kIn);
         Y.reserve((size_t)L * kOut);
         u0.reserve((size_t)L);
@@ -534,7 +651,7 @@ otf_status otf_warm_start_judged(otf_ctx *ctx, otf_mlp *nn, float lambda, int32_
                            s.level.p, s.u.p, s.obs_off.p, s.obs_m.p, s.wtot.p, c.op().F.p, s.nbp_off.p, s.nbp.p,
                            s.nbm_off.p, s.nbm.p, X.p);
         OTF_LAUNCH_CHECK("k_features");
-        nn->m.forward(X.p, L, Y.p);
+        nn->m.forward_fused(X.p, L, Y.p);
         float best_a = 0.0f;
         double best_e = e_plain;
         for (int k = 0; k < n_alpha; ++k) {
@@ -574,7 +691,7 @@ otf_status otf_warm_start(otf_ctx *ctx, otf_mlp *nn) {
     Ctx &c = ctx->c;
     try {
         OTF_HIP(hipSetDevice(c.device));
-        DBuf<float> X, Y;
+        DBuf<float> &X = c.s.fa, &Y = c.s.fb;  // the context's grow-only scratch
         X.reserve((size_t)c.L * kIn);
         Y.reserve((size_t)c.L * kOut);
         LeafStore &s = c.lv();
@@ -582,7 +699,7 @@ otf_status otf_warm_start(otf_ctx *ctx, otf_mlp *nn) {
                            s.level.p, s.u.p, s.obs_off.p, s.obs_m.p, s.wtot.p, c.op().F.p, s.nbp_off.p, s.nbp.p,
                            s.nbm_off.p, s.nbm.p, X.p);
         OTF_LAUNCH_CHECK("k_features");
-        nn->m.forward(X.p, c.L, Y.p);
+        nn->m.forward_fused(X.p, c.L, Y.p);
         hipLaunchKernelGGL(k_apply_warm, dim3(g1(c.L)), dim3(kBlk), 0, c.stream, c.L, s.cap, Y.p, s.u.p, s.ubar.p,
                            s.p.p);
         OTF_LAUNCH_CHECK("k_apply_warm");
