@@ -402,7 +402,7 @@ def run_warm(args):
         "config": {"workload": "train: 512 sphere scenes (depth 6, 8 views), frozen structure, 300 plain iterations "
                                "as targets; evaluate: 2 multi-object scenes (depth 8, 32 views 640x480) and 2 "
                                "held-out spheres, frozen structure, tolerance 1e-4 on the energy after 1500 plain "
-                               "iterations; the warm start judged by the energy (steps 1, 0.5, 0.25 or none)",
+                               "iterations; the warm start guarded by the energy (steps 1, 0.5, 0.25 or none)",
                    "training_rows": int(len(X)), "epochs": epochs,
                    "data_s": t_data, "train_s": t_train, "final_loss": losses[-1]},
         "held_out_multi_object": res_multi, "held_out_spheres": res_sphere, "rms_to_solution": dist,
@@ -425,7 +425,7 @@ def main():
         run_batch(args)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU sharding is designed but "
+        print(json.dumps({"error": "the benchmark runs on exactly one GPU; multi-GPU sharding is designed but "
                                    "not built", "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
     import torch

@@ -269,7 +269,7 @@ otf_status otf_leaf_targets(otf_ctx *ctx, float *T, int64_t cap_rows);
  * outputs 1..3 projected onto the unit ball. The network must use the
  * context's device and stream (else OTF_E_INVALID). */
 otf_status otf_warm_start(otf_ctx *ctx, otf_mlp *net);
-/* The warm start with the plain method as judge. From the current state (u0,
+/* The warm start guarded by the energy of the plain method. From the current state (u0,
  * ubar0, p0) the prediction is applied at each step alpha in alphas[0..n_alpha)
  * (u = u0 + alpha * output 0 kept in [-1, 1], ubar = u, p = (1 - alpha) p0 +
  * alpha * the projected outputs 1..3), the energy E = tv + lambda * data of
@@ -280,7 +280,7 @@ otf_status otf_warm_start(otf_ctx *ctx, otf_mlp *net);
  * host read-back). Errors: OTF_E_INVALID (null pointer, n_alpha outside
  * 1..8, an alpha outside (0, 1], lambda negative or not finite, network on
  * another device or stream), OTF_E_STATE (no valid state). */
-otf_status otf_warm_start_judged(otf_ctx *ctx, otf_mlp *net, float lambda, int32_t n_alpha, const float *alphas,
+otf_status otf_warm_start_guarded(otf_ctx *ctx, otf_mlp *net, float lambda, int32_t n_alpha, const float *alphas,
                                  float *alpha_used, double *energy_used);
 
 /* ---------------------------------------------------------------------------

@@ -617,7 +617,7 @@ otf_status otf_leaf_targets(otf_ctx *ctx, float *T, int64_t cap_rows) {
     return OTF_OK;
 }
 
-otf_status otf_warm_start_judged(otf_ctx *ctx, otf_mlp *nn, float lambda, int32_t n_alpha, const float *alphas,
+otf_status otf_warm_start_guarded(otf_ctx *ctx, otf_mlp *nn, float lambda, int32_t n_alpha, const float *alphas,
                                  float *alpha_used, double *energy_used) {
     if (!ctx || !nn || !alphas || !alpha_used || !energy_used) return OTF_E_INVALID;
     if (n_alpha < 1 || n_alpha > 8 || !std::isfinite(lambda) || lambda < 0.0f) return OTF_E_INVALID;

@@ -74,7 +74,7 @@ def lib():
             "otf_features": [P, P, I64],
             "otf_leaf_targets": [P, P, I64],
             "otf_warm_start": [P, P],
-            "otf_warm_start_judged": [P, P, C.c_float, I32, P, P, P],
+            "otf_warm_start_guarded": [P, P, C.c_float, I32, P, P, P],
             "otf_energy_eps": [P, C.c_double, P, P],
             "otf_last_counts": [P, P, P],
             "otf_export_state": [P, P, I64, P],
@@ -265,13 +265,13 @@ class Context:
         self._check(self._lib.otf_warm_start(self.h, net.h), "otf_warm_start")
         return self
 
-    def warm_start_judged(self, net: "Mlp", lam: float, alphas=(1.0, 0.5, 0.25)):
+    def warm_start_guarded(self, net: "Mlp", lam: float, alphas=(1.0, 0.5, 0.25)):
         """The prediction applied at the step (alphas, or 0: the current state)
         whose energy tv + lam * data is lowest; returns (alpha, energy)."""
         a = (C.c_float * len(alphas))(*alphas)
         au, eu = C.c_float(0), C.c_double(0)
-        self._check(self._lib.otf_warm_start_judged(self.h, net.h, float(lam), len(alphas), a, C.byref(au),
-                                                    C.byref(eu)), "otf_warm_start_judged")
+        self._check(self._lib.otf_warm_start_guarded(self.h, net.h, float(lam), len(alphas), a, C.byref(au),
+                                                    C.byref(eu)), "otf_warm_start_guarded")
         return au.value, eu.value
 
     def obs_pool_stats(self) -> dict:

@@ -81,7 +81,7 @@ def time_to_tolerance(c, w, e_target: float, max_iter: int, chunk: int = 10, war
                       alphas=(1.0, 0.5, 0.25)):
     """Iterations, solver seconds (warm start included) and the warm start's
     step until E <= e_target, checking every `chunk` iterations. The warm
-    start is judged by the energy: the network's prediction is kept at the
+    start is guarded by the energy: the network's prediction is kept at the
     step (alphas, or none) that lowers the energy most."""
     import torch
 
@@ -90,7 +90,7 @@ def time_to_tolerance(c, w, e_target: float, max_iter: int, chunk: int = 10, war
     alpha = None
     if warm_net is not None:
         t0 = time.perf_counter()
-        alpha, _ = c.warm_start_judged(warm_net, w.lam, alphas)
+        alpha, _ = c.warm_start_guarded(warm_net, w.lam, alphas)
         torch.cuda.synchronize()
         t += time.perf_counter() - t0
     it = 0

@@ -146,8 +146,8 @@ def _energy(g, lam):
 
 
 @pytest.mark.parametrize("scale", [0.3, 3.0])
-def test_judged_warm_start_keeps_the_lowest_energy(scale):
-    """The judged warm start against the plain warm start on twin contexts:
+def test_guarded_warm_start_keeps_the_lowest_energy(scale):
+    """The guarded warm start against the plain warm start on twin contexts:
     the kept state is the candidate (alpha 1, 0.5 or the current state) of
     lowest energy, bit for bit; a network far off (scale 3) is rejected when
     every candidate raises the energy."""
@@ -166,7 +166,7 @@ def test_judged_warm_start_keeps_the_lowest_energy(scale):
     t.warm_start(net)
     e_one = _energy(t, lam)
     one = t.extract()
-    a, e = g.warm_start_judged(net, lam, (1.0, 0.5))
+    a, e = g.warm_start_guarded(net, lam, (1.0, 0.5))
     lv = g.extract()
     assert a in (0.0, 0.5, 1.0)
     assert e <= e_plain and e <= e_one
