@@ -352,18 +352,13 @@ __device__ float long_divergence(const PrimalArgs &a, const Coef &cf, int64_t i,
     return acc;
 }
 
-// u' for leaves with a long - list, one wave each; u' replaces ds for
-// primal_wave<true> (gradient descent keeps the divergence itself).
+// u' for leaves with a long - list, one wave each (the batched sweeps, where
+// a separate launch precedes the tiles: long units inside the persistent
+// blocks would hold their tiles at the block's barriers); u' replaces ds for
+// primal_wave<true>.
 __device__ void primal_long_wave(const PrimalArgs &a, const Coef &cf, int64_t i, int lane) {
     const float acc = long_divergence(a, cf, i, lane);
-    if (lane == 0) a.ds[i] = a.gd ? acc : __fmaf_rn(a.tau, acc, a.u_in[i]);
-}
-
-__global__ void __launch_bounds__(kBlk) k_primal_long(uint32_t n, const uint32_t *list, PrimalArgs a, Coef cf) {
-    __shared__ Coef scf;
-    const Coef &lcf = stage_coef(cf, scf);
-    const uint32_t item = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    if (item < n) primal_long_wave(a, lcf, list[item], threadIdx.x & 63);
+    if (lane == 0) a.ds[i] = __fmaf_rn(a.tau, acc, a.u_in[i]);
 }
 
 // Own divergence term ds minus the incoming terms of the short - list
@@ -581,12 +576,46 @@ k_primal(PrimalArgs a, Coef cf, uint32_t n_long, const uint32_t *long_list, uint
 //   u <- u + xi (lam div - d'),  d' = sum * inv.
 // The divergence is kept (uprime) so that split children take the same step
 // with their own data term.
-__global__ void __launch_bounds__(kBlk) k_gd_update(PrimalArgs a, Coef cf_arg) {
-    __shared__ Coef scf;
-    const Coef &cf = stage_coef(cf_arg, scf);
-    const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
+// Sum of the 64 lanes' t by a butterfly (the same value on every lane: each
+// step adds two equal pairs, and the addition commutes).
+__device__ inline float butterfly_sum(float t) {
+#pragma unroll
+    for (int sh = 1; sh < 64; sh <<= 1) t = t + __shfl_xor(t, sh, 64);
+    return t;
+}
+
+// Data-gradient term of observation k on lane k (0 at or past M).
+__device__ inline float gd_term(float u, float Fk, float Wk, float eps2, int Ml, int lane) {
+    const float r = u - Fk;
+    const float den = sqrtf(__fmaf_rn(r, r, eps2));  // > 0: eps > 0
+    return lane < Ml ? Wk * (r / den) : 0.0f;
+}
+
+// Update, flags and stores of a leaf from its divergence dv and data-gradient
+// sum.
+__device__ inline void gd_store(const PrimalArgs &a, int64_t i, float un, float dv, float sum, float inv, int ln,
+                                bool &split, bool &join) {
+    const float dg = sum * inv;
+    const float v = __fmaf_rn(a.xi, __fmaf_rn(a.lam, dv, -dg), un);
+    a.u[i] = v;
+    a.ubar[i] = v;
+    const float av = fabsf(v);
+    split = av < a.split_tau && ln < a.max_depth;
+    join = a.join_enabled && av > a.join_tau;
+    a.flag[i] = split ? 1 : (join ? (v > 0.0f ? 2 : 4) : 0);
+    if (split) {
+        a.uprime[i] = dv;
+        a.uold[i] = un;
+    }
+}
+
+// The wave's 64 consecutive leaves, as primal_wave; a leaf with a long -
+// list is left to its own wave in the same launch (kept in the loop, not
+// stored).
+__device__ inline void gd_wave(const PrimalArgs &a, const Coef &cf, int64_t i, uint32_t &n_split, uint32_t &n_join) {
     const int lane = threadIdx.x & 63;
     const bool valid = i < a.L;
+    bool own = valid;
     float dv = 0.0f, un = 0.0f, inv = 0.0f;
     int M = 0, ln = 0;
     uint32_t oo = 0;
@@ -599,7 +628,8 @@ __global__ void __launch_bounds__(kBlk) k_gd_update(PrimalArgs a, Coef cf_arg) {
         M = a.obs_m[i];
         oo = a.obs_off[i];
         inv = a.inv[i];
-        dv = (e1 - e0 > kLongList) ? dsi : divergence(a, cf, e0, e1, ln, dsi);
+        if (e1 - e0 > kLongList) own = false;
+        else dv = divergence(a, cf, e0, e1, ln, dsi);
     }
     const int nact = __popcll(__ballot(valid));
     float mysum = 0.0f;
@@ -619,33 +649,60 @@ __global__ void __launch_bounds__(kBlk) k_gd_update(PrimalArgs a, Coef cf_arg) {
         for (int g = 0; g < kAhead; ++g) {
             const int l = l0 + g;
             const int lc = min(l, 63);
-            const int Ml = rdlane_i(M, lc);
-            const float ul = rdlane(un, lc);
-            const float r = ul - Fr[g];
-            const float den = sqrtf(__fmaf_rn(r, r, a.eps2));  // > 0: eps > 0
-            float t = lane < Ml ? Wr[g] * (r / den) : 0.0f;
-#pragma unroll
-            for (int sh = 1; sh < 64; sh <<= 1) t = t + __shfl_xor(t, sh, 64);
+            const float t = butterfly_sum(gd_term(rdlane(un, lc), Fr[g], Wr[g], a.eps2, rdlane_i(M, lc), lane));
             mysum = (lane == l && l < nact) ? t : mysum;
         }
     }
     bool split = false, join = false;
-    if (valid) {
-        const float dg = mysum * inv;
-        const float v = __fmaf_rn(a.xi, __fmaf_rn(a.lam, dv, -dg), un);
-        a.u[i] = v;
-        a.ubar[i] = v;
-        const float av = fabsf(v);
-        split = av < a.split_tau && ln < a.max_depth;
-        join = a.join_enabled && av > a.join_tau;
-        a.flag[i] = split ? 1 : (join ? (v > 0.0f ? 2 : 4) : 0);
-        if (split) {
-            a.uprime[i] = dv;
-            a.uold[i] = un;
-        }
+    if (own) gd_store(a, i, un, dv, mysum, inv, ln, split, join);
+    n_split = (uint32_t)__popcll(__ballot(split));
+    n_join = (uint32_t)__popcll(__ballot(join));
+}
+
+// The whole update of a leaf with a long - list, one wave: its divergence in
+// 64 interleaved parts (long_divergence), the data gradient with lane k on
+// observation k, and its stores. The flags are returned on every lane.
+__device__ void gd_long_full(const PrimalArgs &a, const Coef &cf, int64_t i, int lane, bool &split, bool &join) {
+    const int ln = a.level[i];
+    const float un = a.u_in[i];
+    const int M = a.obs_m[i];
+    const uint32_t oo = a.obs_off[i];
+    const float inv = a.inv[i];
+    const uint32_t e = oo + (lane < M ? (uint32_t)lane : 0u);
+    const float Fk = a.F[e], Wk = a.W[e];
+    const float dv = long_divergence(a, cf, i, lane);
+    const float sum = butterfly_sum(gd_term(un, Fk, Wk, a.eps2, M, lane));
+    // the stores on lane 0, the flags (from the same values) on every lane
+    const float v = __fmaf_rn(a.xi, __fmaf_rn(a.lam, dv, -(sum * inv)), un);
+    const float av = fabsf(v);
+    split = av < a.split_tau && ln < a.max_depth;
+    join = a.join_enabled && av > a.join_tau;
+    if (lane == 0) {
+        bool s_, j_;
+        gd_store(a, i, un, dv, sum, inv, ln, s_, j_);
     }
-    block_flag_counts<kBlk>((uint32_t)__popcll(__ballot(split)), (uint32_t)__popcll(__ballot(join)), a.part,
-                            a.part_stride, blockIdx.x);
+}
+
+// Gradient-descent update in one launch: the first long_blocks blocks take
+// the leaves with a long - list (gd_long_full, a wave each), the others 64
+// consecutive leaves per wave (gd_wave); per-block flag counts as k_primal.
+__global__ void __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(8, 8)))
+k_gd_update(PrimalArgs a, Coef cf_arg, uint32_t n_long, const uint32_t *long_list, uint32_t long_blocks) {
+    __shared__ Coef scf;
+    const Coef &cf = stage_coef(cf_arg, scf);
+    uint32_t ns = 0, nj = 0;
+    if (blockIdx.x < long_blocks) {
+        const uint32_t item = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+        if (item < n_long) {
+            bool split, join;
+            gd_long_full(a, cf, long_list[item], threadIdx.x & 63, split, join);
+            ns = split ? 1u : 0u;
+            nj = join ? 1u : 0u;
+        }
+    } else {
+        gd_wave(a, cf, (int64_t)(blockIdx.x - long_blocks) * kBlk + threadIdx.x, ns, nj);
+    }
+    block_flag_counts<kBlk>(ns, nj, a.part, a.part_stride, blockIdx.x);
 }
 
 // Energy: per-leaf terms in double, block partial sums in a fixed tree order.
@@ -913,7 +970,8 @@ void launch_gd_flux(Ctx &c, float eps2) {
 void launch_gd_update(Ctx &c, float lam, float xi, float eps2) {
     LeafStore &s = c.lv();
     PrimalArgs a = primal_args(c, 1.0f, 0.0f);
-    const int64_t nblk = cdiv(c.L, kBlk);
+    const int64_t lb = cdiv(s.n_heavy_m, kWavesPerBlock);
+    const int64_t nblk = lb + cdiv(c.L, kBlk);
     c.s.part.reserve(2 * nblk);
     a.part = c.s.part.p;
     a.part_stride = nblk;
@@ -922,12 +980,8 @@ void launch_gd_update(Ctx &c, float lam, float xi, float eps2) {
     a.lam = lam;
     a.xi = xi;
     a.eps2 = eps2;
-    if (s.n_heavy_m > 0) {
-        hipLaunchKernelGGL(k_primal_long, dim3((unsigned)cdiv(s.n_heavy_m, kWavesPerBlock)), dim3(kBlk), 0, c.stream,
-                           (uint32_t)s.n_heavy_m, s.heavy_m.p, a, c.coef);
-        OTF_LAUNCH_CHECK("k_primal_long (divergence)");
-    }
-    hipLaunchKernelGGL(k_gd_update, dim3((unsigned)nblk), dim3(kBlk), 0, c.stream, a, c.coef);
+    hipLaunchKernelGGL(k_gd_update, dim3((unsigned)nblk), dim3(kBlk), 0, c.stream, a, c.coef, (uint32_t)s.n_heavy_m,
+                       (const uint32_t *)s.heavy_m.p, (uint32_t)lb);
     OTF_LAUNCH_CHECK("k_gd_update");
 }
 
