@@ -46,3 +46,26 @@ def test_record_layouts():
     assert otf.PARAMS_DTYPE.itemsize == 40
     import oracle
     assert oracle.PARAMS_DTYPE == otf.PARAMS_DTYPE
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libotf.so not built")
+def test_null_context_is_invalid_before_any_device_work():
+    """Entry points validate their arguments before any device call: a null
+    context (or network) returns OTF_E_INVALID (1) on a machine without a GPU."""
+    from paper_1608_07411_amd import otf
+    L = otf.lib()
+    calls = {
+        "otf_fuse": (None, 1, 0.5, 0.3, 0.3),
+        "otf_fuse_gd": (None, 1, 0.5, 0.1, 0.3),
+        "otf_num_leaves": (None, None),
+        "otf_energy": (None, None, None),
+        "otf_extract": (None, 0, None, None, None, None, None, None),
+        "otf_extract_obs_at": (None, 0, None, None, None, None, 0, None, None, None),
+        "otf_obs_pool_stats": (None, None, None, None),
+        "otf_warm_start": (None, None),
+        "otf_warm_start_guarded": (None, None, 0.5, 1, None, None, None),
+        "otf_export_state": (None, None, 0, None),
+        "otf_selftest_scan": (None, 0, 0, None),
+    }
+    for name, args in calls.items():
+        assert getattr(L, name)(*args) == 1, name
