@@ -707,17 +707,29 @@ k_gd_update(PrimalArgs a, Coef cf_arg, uint32_t n_long, const uint32_t *long_lis
 
 // Energy: per-leaf terms in double, block partial sums in a fixed tree order.
 // With eps2 > 0 the terms are the smoothed ones of the gradient-descent
-// energy: sqrt(|Gu|^2 + eps^2) and sqrt((u - F)^2 + eps^2).
+// energy: sqrt(|Gu|^2 + eps^2) and sqrt((u - F)^2 + eps^2). The TV term per
+// thread; the data term cooperatively, as the primal sweep reads the
+// observations: the wave takes its 64 leaves in groups of kAhead, lane k
+// loads observation k of each (coalesced, all of a group in flight), and a
+// leaf's terms are added by a butterfly over the 64 lanes.
 __global__ void __launch_bounds__(kBlk) k_energy(int64_t L, int D, const uint8_t *level, const float *u,
                                                  const uint32_t *off, const uint32_t *ent, const uint32_t *obs_off,
                                                  const uint8_t *obs_m, const float *inv, const float *F,
                                                  const float *W, Coef cf, double eps2, double *partial) {
     __shared__ double s_tv[kBlk], s_da[kBlk];
     const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
-    double tv = 0.0, da = 0.0;
-    if (i < L) {
+    const int lane = threadIdx.x & 63;
+    const bool valid = i < L;
+    double tv = 0.0, vol = 0.0;
+    float uf = 0.0f;
+    int M = 0;
+    uint32_t o = 0;
+    if (valid) {
         const int ln = level[i];
-        const double un = u[i];
+        uf = u[i];
+        M = obs_m[i];
+        o = obs_off[i];
+        const double un = uf;
         double g[3] = {0.0, 0.0, 0.0};
         for (uint32_t e = off[i]; e < off[i + 1]; ++e) {
             const uint32_t v = ent[e];
@@ -730,17 +742,35 @@ __global__ void __launch_bounds__(kBlk) k_energy(int64_t L, int D, const uint8_t
             else g[2] += c * dif;
         }
         const double s = ldexp(1.0, D - ln);
-        const double vol = s * s * s;
+        vol = s * s * s;
         const double g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
         tv = vol * (eps2 > 0.0 ? sqrt(g2 + eps2) : sqrt(g2));
-        double acc = 0.0;
-        const uint32_t o = obs_off[i];
-        for (int k = 0; k < obs_m[i]; ++k) {
-            const double r = un - (double)F[o + k];
-            acc += (double)W[o + k] * (eps2 > 0.0 ? sqrt(r * r + eps2) : fabs(r));
-        }
-        da = vol * (double)inv[i] * acc;
     }
+    const int nact = __popcll(__ballot(valid));
+    double mine = 0.0;
+    for (int l0 = 0; l0 < nact; l0 += kAhead) {
+        float Fr[kAhead], Wr[kAhead];
+#pragma unroll
+        for (int g = 0; g < kAhead; ++g) {
+            const int l = min(l0 + g, 63);
+            const int Ml = rdlane_i(M, l);
+            const uint32_t e = (uint32_t)rdlane_i((int)o, l) + (lane < Ml ? (uint32_t)lane : 0u);
+            Fr[g] = F[e];
+            Wr[g] = W[e];
+        }
+#pragma unroll
+        for (int g = 0; g < kAhead; ++g) {
+            const int l = l0 + g;
+            const int lc = min(l, 63);
+            const int Ml = rdlane_i(M, lc);
+            const double r = (double)rdlane(uf, lc) - (double)Fr[g];
+            double t = lane < Ml ? (double)Wr[g] * (eps2 > 0.0 ? sqrt(r * r + eps2) : fabs(r)) : 0.0;
+#pragma unroll
+            for (int sh = 1; sh < 64; sh <<= 1) t = t + __shfl_xor(t, sh, 64);
+            mine = (lane == l && l < nact) ? t : mine;
+        }
+    }
+    const double da = valid ? vol * (double)inv[i] * mine : 0.0;
     s_tv[threadIdx.x] = tv;
     s_da[threadIdx.x] = da;
     __syncthreads();
