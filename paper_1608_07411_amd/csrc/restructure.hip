@@ -42,38 +42,62 @@ __device__ inline int align_level(uint32_t k, int D) {
 // Per leaf: collapse target level jt (0xFF: none), head flag, and cand = 1
 // if the leaf is the first leaf of some inner node inside its collapse block
 // (a node at a level q with jt <= q < the leaf's level, starting at its key),
-// i.e. it computes a hierarchical mean at some level.
+// i.e. it computes a hierarchical mean at some level. A thread takes two
+// leaves (i and i + kBlk of its block's 2 kBlk), each step of their lookup
+// chains (run start, run end, end key and level) issued for both together.
+constexpr int kJoinLeaves = 2;
+
 __global__ void __launch_bounds__(kBlk) k_join_target(int64_t L, int D, const uint8_t *flag, const uint32_t *key,
                                                       const uint8_t *level, const uint32_t *rs,
                                                       const uint32_t *runend, uint8_t *jt, uint8_t *jhead,
                                                       uint32_t *part, uint8_t *cand) {
-    const int64_t i = TID();
-    uint8_t t = 0xFF, h = 0;
-    if (i < L && (flag[i] & 6)) {
-        const uint32_t s = rs[i], e = runend[s];
-        const uint64_t K0 = key[s];
-        const uint64_t K1 = (uint64_t)key[e] + (uint64_t(1) << (3 * (D - level[e])));
-        const int ln = level[i];
-        const uint64_t k = key[i];
-        for (int l = 0; l < ln; ++l) {
-            const uint64_t sz = uint64_t(1) << (3 * (D - l));
-            const uint64_t B0 = k & ~(sz - 1);
-            if (B0 >= K0 && B0 + sz <= K1) {
-                t = (uint8_t)l;
-                h = (k == B0) ? 1 : 0;
-                break;
+    constexpr int N = kJoinLeaves;
+    int64_t idx[N];
+    bool on[N];
+    uint32_t s[N], e[N], k[N];
+    int ln[N];
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        idx[n] = ((int64_t)blockIdx.x * N + n) * kBlk + threadIdx.x;
+        const bool in = idx[n] < L;
+        on[n] = in && (flag[idx[n]] & 6);
+        k[n] = in ? key[idx[n]] : 0u;
+        ln[n] = in ? level[idx[n]] : 0;
+        s[n] = on[n] ? rs[idx[n]] : 0u;
+    }
+#pragma unroll
+    for (int n = 0; n < N; ++n) e[n] = on[n] ? runend[s[n]] : 0u;
+    uint64_t K0[N], K1[N];
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        K0[n] = on[n] ? key[s[n]] : 0u;
+        K1[n] = on[n] ? (uint64_t)key[e[n]] + (uint64_t(1) << (3 * (D - level[e[n]]))) : 0u;
+    }
+    uint32_t heads = 0;
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        uint8_t t = 0xFF, h = 0;
+        if (on[n]) {
+            for (int l = 0; l < ln[n]; ++l) {
+                const uint64_t sz = uint64_t(1) << (3 * (D - l));
+                const uint64_t B0 = (uint64_t)k[n] & ~(sz - 1);
+                if (B0 >= K0[n] && B0 + sz <= K1[n]) {
+                    t = (uint8_t)l;
+                    h = ((uint64_t)k[n] == B0) ? 1 : 0;
+                    break;
+                }
             }
         }
-    }
-    if (i < L) {
-        jt[i] = t;
-        jhead[i] = h;
-        cand[i] = (t != 0xFF && max((int)t, align_level(key[i], D)) < (int)level[i]) ? 1 : 0;
+        if (idx[n] < L) {
+            jt[idx[n]] = t;
+            jhead[idx[n]] = h;
+            cand[idx[n]] = (t != 0xFF && max((int)t, align_level(k[n], D)) < ln[n]) ? 1 : 0;
+        }
+        heads += (uint32_t)__popcll(__ballot(h != 0));
     }
     // per-block count of collapse heads
     __shared__ uint32_t cnt[kBlk / 64];
-    const uint64_t b = __ballot(h != 0);
-    if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = (uint32_t)__popcll(b);
+    if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = heads;
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t n = 0;
@@ -574,9 +598,10 @@ void join_analysis(Ctx &c) {
     hipLaunchKernelGGL(k_run_ends, dim3(gL), dim3(kBlk), 0, c.stream, L, os.flag.p, s.b.p, s.c.p);
     s.part.reserve(gL);
     s.r_jcand.reserve(L);
-    hipLaunchKernelGGL(k_join_target, dim3(gL), dim3(kBlk), 0, c.stream, L, c.prm.max_depth, os.flag.p, os.key.p,
+    const unsigned gJ = (unsigned)std::max<int64_t>(1, cdiv(L, kJoinLeaves * kBlk));
+    hipLaunchKernelGGL(k_join_target, dim3(gJ), dim3(kBlk), 0, c.stream, L, c.prm.max_depth, os.flag.p, os.key.p,
                        os.level.p, s.b.p, s.c.p, s.u8a.p, s.u8b.p, s.part.p, s.r_jcand.p);
-    sum_parts(c, s.part.p, gL, 1, gL, c.counters.p + 2);
+    sum_parts(c, s.part.p, gJ, 1, gJ, c.counters.p + 2);
     // the leaves that compute hierarchical means, listed (their number stays
     // on the device, at r_jrank[L])
     s.r_jrank.reserve(L + 1);
