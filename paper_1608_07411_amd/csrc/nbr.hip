@@ -114,17 +114,39 @@ struct Heavy {
 
 // Unchanged leaves take their counts from the previous store; the others are
 // listed, in index order, at their rank dpos[i] among the leaves to search.
+// Two leaves per thread (i and i + kBlk of the block's 2 kBlk): the need
+// marks and sources of both are loaded, then the four old offsets of both.
+constexpr int kCleanLeaves = 2;
+
 __global__ void __launch_bounds__(kBlk) k_nbr_count_clean(int64_t L, uint32_t *cnt_p, uint32_t *cnt_m, NbrOld old,
                                                           const uint32_t *dpos, uint32_t *dirty) {
-    const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
-    if (i >= L) return;
-    if (old.need[i]) {
-        dirty[dpos[i]] = (uint32_t)i;
-        return;
+    constexpr int N = kCleanLeaves;
+    int64_t idx[N];
+    bool clean[N];
+    uint32_t j[N];
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        idx[n] = ((int64_t)blockIdx.x * N + n) * kBlk + threadIdx.x;
+        const bool in = idx[n] < L;
+        const bool need = in && old.need[idx[n]];
+        clean[n] = in && !need;
+        j[n] = clean[n] ? old.src[idx[n]] : 0u;
+        if (need) dirty[dpos[idx[n]]] = (uint32_t)idx[n];
     }
-    const uint32_t j = old.src[i];
-    cnt_p[i] = old.off_p[j + 1] - old.off_p[j];
-    cnt_m[i] = old.off_m[j + 1] - old.off_m[j];
+    uint32_t p0[N], p1[N], m0[N], m1[N];
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        p0[n] = old.off_p[j[n]];
+        p1[n] = old.off_p[j[n] + 1];
+        m0[n] = old.off_m[j[n]];
+        m1[n] = old.off_m[j[n] + 1];
+    }
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+        if (clean[n]) {
+            cnt_p[idx[n]] = p1[n] - p0[n];
+            cnt_m[idx[n]] = m1[n] - m0[n];
+        }
 }
 
 // Searched leaves, 8 lanes per leaf (lane f < 6 takes face f), grid-stride
@@ -509,7 +531,8 @@ NbrPending search_begin(Ctx &c, const NbrOld &old, bool need_scanned) {
             scan_exclusive_u32_dev_u8(c, old.need, c.s.e.p, L);
         }
         c.s.dirty.reserve(L);
-        hipLaunchKernelGGL(k_nbr_count_clean, dim3(g), dim3(kBlk), 0, c.stream, L, c.s.a.p, c.s.b.p, old,
+        const unsigned gc = (unsigned)std::max<int64_t>(1, cdiv(L, kCleanLeaves * kBlk));
+        hipLaunchKernelGGL(k_nbr_count_clean, dim3(gc), dim3(kBlk), 0, c.stream, L, c.s.a.p, c.s.b.p, old,
                            (const uint32_t *)c.s.e.p, c.s.dirty.p);
         OTF_LAUNCH_CHECK("k_nbr_count_clean");
         p.dirty = c.s.dirty.p;
