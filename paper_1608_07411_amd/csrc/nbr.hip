@@ -28,8 +28,11 @@ namespace {
 constexpr int kBlk = 256;
 constexpr uint32_t kLight = 32;  // longest range scanned by a single thread
 
-__global__ void k_key_table(const uint32_t *key, int64_t L, int shift, uint32_t nb, uint32_t *table) {
+// (zero, when given: a counter cleared for the count pass that follows)
+__global__ void k_key_table(const uint32_t *key, int64_t L, int shift, uint32_t nb, uint32_t *table,
+                            uint32_t *zero) {
     const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (zero && b == 0) *zero = 0u;
     if (b < nb) table[b] = (uint32_t)find_leaf(key, L, b << shift);
 }
 
@@ -160,7 +163,8 @@ __global__ void __launch_bounds__(kBlk) k_nbr_count_clean(int64_t L, uint32_t *c
 __global__ void __launch_bounds__(kBlk) k_nbr_count(KeyIndex ki, const uint8_t *__restrict__ level, int D,
                                                     uint32_t *cnt_p, uint32_t *cnt_m, uint32_t *fc,
                                                     const uint32_t *dirty, const uint32_t *n_dev, int64_t n_host,
-                                                    Heavy hv, uint32_t *cj, uint32_t *cm) {
+                                                    Heavy hv, uint32_t *cj, uint32_t *cm, uint32_t *zero2) {
+    if (blockIdx.x == 0 && threadIdx.x < 2) zero2[threadIdx.x] = 0u;  // k_heavy_lists' counters
     const uint32_t *__restrict__ key = ki.key;
     const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
     const int face = threadIdx.x & 7;
@@ -478,18 +482,20 @@ KeyIndex key_index(Ctx &c) {
 unsigned grid8(int64_t L) { return (unsigned)std::min<int64_t>(cdiv(8 * L, kBlk), 8192); }
 
 // the count pass (8 lanes per searched leaf, a bounded grid strides over the
-// list), with room for p.cap long ranges; starts the read-back of their number
-uint32_t count_pass(Ctx &c, NbrPending &p) {
+// list), with room for p.cap long ranges; starts the read-back of their number.
+// The long-range counter is cleared here when `clear` (else by the key table
+// launch just before); the pass clears the long-list counters of k_heavy_lists.
+uint32_t count_pass(Ctx &c, NbrPending &p, bool clear) {
     LeafStore &s = c.lv();
     c.s.hv_leaf.reserve(p.cap);
     c.s.hv_lo.reserve(p.cap);
     c.s.hv_hi.reserve(p.cap);
     c.s.hv_face.reserve(p.cap);
     Heavy hv{c.s.hv_leaf.p, c.s.hv_face.p, c.s.hv_lo.p, c.s.hv_hi.p, c.counters.p + 3, p.cap};
-    hipLaunchKernelGGL(k_zero_n, dim3(1), dim3(64), 0, c.stream, c.counters.p + 3, 1);
+    if (clear) hipLaunchKernelGGL(k_zero_n, dim3(1), dim3(64), 0, c.stream, c.counters.p + 3, 1);
     hipLaunchKernelGGL(k_nbr_count, dim3(grid8(c.L)), dim3(kBlk), 0, c.stream, key_index(c), s.level.p,
                        c.prm.max_depth, c.s.a.p, c.s.b.p, c.s.g.p, p.dirty, p.n_dirty_dev, c.L, hv, c.s.nb_j.p,
-                       c.s.nb_m.p);
+                       c.s.nb_m.p, c.counters.p + 14);
     OTF_LAUNCH_CHECK("k_nbr_count");
     return read_back_begin(c, {{c.counters.p + 3, 3}});
 }
@@ -511,13 +517,13 @@ NbrPending search_begin(Ctx &c, const NbrOld &old, bool need_scanned) {
         c.s.key_table.reserve((size_t)nb + nbc);
         uint32_t *tc = c.s.key_table.p + nb;
         hipLaunchKernelGGL(k_key_table, dim3((unsigned)cdiv(nbc, kBlk)), dim3(kBlk), 0, c.stream, s.key.p, L,
-                           shift + kKeyCoarseShift, nbc, tc);
+                           shift + kKeyCoarseShift, nbc, tc, c.counters.p + 3);
         hipLaunchKernelGGL(k_key_table_fine, dim3((unsigned)cdiv(nb, kBlk)), dim3(kBlk), 0, c.stream, s.key.p, L,
                            shift, nb, (const uint32_t *)tc, nbc, c.s.key_table.p);
     } else {
         c.s.key_table.reserve(nb);
         hipLaunchKernelGGL(k_key_table, dim3((unsigned)cdiv(nb, kBlk)), dim3(kBlk), 0, c.stream, s.key.p, L, shift,
-                           nb, c.s.key_table.p);
+                           nb, c.s.key_table.p, c.counters.p + 3);
     }
     OTF_LAUNCH_CHECK("k_key_table");
     NbrPending p{};
@@ -538,7 +544,7 @@ NbrPending search_begin(Ctx &c, const NbrOld &old, bool need_scanned) {
         p.dirty = c.s.dirty.p;
         p.n_dirty_dev = c.s.e.p + L;
     }
-    p.ticket = count_pass(c, p);
+    p.ticket = count_pass(c, p, false);
     return p;
 }
 
@@ -554,7 +560,7 @@ void search_end(Ctx &c, NbrPending &p, void (*overlap)(Ctx &)) {
     uint32_t n_heavy = c.h_counters[3];
     if (n_heavy > p.cap) {  // rare: more long ranges than room; count again with room for all
         p.cap = n_heavy;
-        read_back_wait(c, count_pass(c, p));
+        read_back_wait(c, count_pass(c, p, true));
         n_heavy = c.h_counters[3];
         if (n_heavy > p.cap) fail(OTF_E_DEVICE, "long-range count changed between passes");
     }
@@ -589,7 +595,6 @@ void search_end(Ctx &c, NbrPending &p, void (*overlap)(Ctx &)) {
     // work lists of the leaves with long lists need only the offsets
     s.heavy_p.reserve(L);
     s.heavy_m.reserve(L);
-    hipLaunchKernelGGL(k_zero_n, dim3(1), dim3(64), 0, c.stream, c.counters.p + 14, 2);
     hipLaunchKernelGGL(k_heavy_lists, dim3(g), dim3(kBlk), 0, c.stream, L, (const uint32_t *)s.nbp_off.p,
                        (const uint32_t *)s.nbm_off.p, s.heavy_p.p, s.heavy_m.p, c.counters.p + 14);
     OTF_LAUNCH_CHECK("k_heavy_lists");
