@@ -69,3 +69,16 @@ def test_null_context_is_invalid_before_any_device_work():
     }
     for name, args in calls.items():
         assert getattr(L, name)(*args) == 1, name
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on one GPU; more is refused with a message (exit 2)
+    before anything touches a device."""
+    import json
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
