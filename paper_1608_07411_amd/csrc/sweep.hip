@@ -1,4 +1,5 @@
-// The two leaf sweeps of one primal-dual iteration and the energy reduction.
+// The two leaf sweeps of one primal-dual iteration (single objects and
+// batches), the gradient-descent update sweep, and the energy reduction.
 //
 // Dual sweep (gradient + ascent + unit-ball projection):
 //   g_d = sum_{k in N+_d(n)} c_nk (ubar_k - ubar_n)   ascending key, fma chain
@@ -24,7 +25,6 @@ namespace {
 
 constexpr int kBlk = 256;
 constexpr int kAhead = 8;   // leaves whose observations one wave loads ahead in k_primal
-constexpr int kUnroll = 4;  // list entries per thread in flight while staging a long list
 constexpr int kGather = 4;  // neighbour entries per thread in flight in the short-list sweeps
 
 __device__ inline float rdlane(float v, int l) {
