@@ -54,6 +54,8 @@ def _lib(precision: str):
         lib.orc_prox.restype = C.c_double
         lib.orc_prox.argtypes = [C.c_int, P, P, C.c_double, C.c_double, C.c_double]
         lib.orc_export_state.argtypes = [P, P, C.c_int64, P]
+        lib.orc_restructure_now.argtypes = [P, C.c_float, C.c_float]
+        lib.orc_extract_aux.argtypes = [P, C.c_int64, P, P, P]
         lib.orc_import_state.argtypes = [P, P, C.c_int64]
         _LIBS[precision] = lib
     return _LIBS[precision]
@@ -133,6 +135,23 @@ class Oracle:
         """The paper's gradient descent (lambda on TV, step xi, smoothing eps)."""
         self._check(self.lib.orc_fuse_gd(self.h, int(iterations), lam, xi, eps))
         return self
+
+    def restructure_now(self, lam: float, tau: float):
+        """Split/join of the current state, as the fuse loop runs it after an
+        iteration's primal phase (test hook: only right after a fuse whose last
+        iteration did not restructure)."""
+        self._check(self.lib.orc_restructure_now(self.h, lam, tau))
+        return self
+
+    def extract_aux(self) -> dict:
+        """Per leaf: u' and u_old of the last primal step or split cascade, and
+        the split flag."""
+        n = self.num_leaves()
+        up = np.zeros(n)
+        uo = np.zeros(n)
+        sp = np.zeros(n, np.int32)
+        self._check(self.lib.orc_extract_aux(self.h, n, _ptr(up), _ptr(uo), _ptr(sp)))
+        return dict(uprime=up, uold=uo, split=sp.astype(bool))
 
     def last_counts(self):
         s, j = C.c_int64(0), C.c_int64(0)

@@ -499,54 +499,21 @@ static real coef_div(const orc *o, const unode *m, const unode *n) {
     return (sm * a * a) / (h * sn * sn * sn);
 }
 
-/* ------------------------------------------------------------------------ */
-/* Order of the sums over a leaf's neighbours. The paper leaves it open; here */
-/* a side list (x, y, z neighbours, each in ascending key) of at most        */
-/* LONG_LIST entries is summed as one chain in list order. A longer list is  */
-/* summed in NPART interleaved parts: list entry q goes to part q mod NPART, */
-/* each part a chain from 0 in list order, and the parts are then added in   */
-/* part order. (The + side's three direction sums each have their own parts, */
-/* indexed by the position in the whole side list.)                         */
-/* ------------------------------------------------------------------------ */
-#define LONG_LIST 64
-#define NPART 64
-
 /* Gradient sums of n over its + list (b: direction bounds): g[d] = sum of
  * c_nk (v_k - v_n), C[d] = sum of c_nk over direction d's entries, with v the
- * ubar (field 0) or u (field 1) values. */
+ * ubar (field 0) or u (field 1) values. Every sum is one sequential chain in
+ * list order (ascending neighbour key), however long the list. */
 static void grad_sums(const orc *o, const unode *n, const leafvec *nb, const int64_t b[4], int field, real g[3],
                       real C[3]) {
     const real vn = field ? n->u : n->ubar;
-    if (b[3] <= LONG_LIST) {
-        for (int d = 0; d < 3; ++d) {
-            g[d] = 0;
-            C[d] = 0;
-            for (int64_t q = b[d]; q < b[d + 1]; ++q) {
-                const unode *k = nb->a[q];
-                const real c = coef_grad(o, n, k);
-                g[d] = R_FMA(c, (field ? k->u : k->ubar) - vn, g[d]);
-                C[d] = C[d] + c;
-            }
-        }
-        return;
-    }
-    real pg[3][NPART], pc[3][NPART];
-    for (int d = 0; d < 3; ++d)
-        for (int j = 0; j < NPART; ++j) pg[d][j] = pc[d][j] = 0;
-    for (int d = 0; d < 3; ++d)
-        for (int64_t q = b[d]; q < b[d + 1]; ++q) {
-            const unode *k = nb->a[q];
-            const real c = coef_grad(o, n, k);
-            const int j = (int)(q % NPART);
-            pg[d][j] = R_FMA(c, (field ? k->u : k->ubar) - vn, pg[d][j]);
-            pc[d][j] = pc[d][j] + c;
-        }
     for (int d = 0; d < 3; ++d) {
         g[d] = 0;
         C[d] = 0;
-        for (int j = 0; j < NPART; ++j) {
-            g[d] = g[d] + pg[d][j];
-            C[d] = C[d] + pc[d][j];
+        for (int64_t q = b[d]; q < b[d + 1]; ++q) {
+            const unode *k = nb->a[q];
+            const real c = coef_grad(o, n, k);
+            g[d] = R_FMA(c, (field ? k->u : k->ubar) - vn, g[d]);
+            C[d] = C[d] + c;
         }
     }
 }
@@ -583,23 +550,11 @@ static int div_leaf(const orc *o, unode *n, leafvec *nb, real *out) {
     for (int d = 0; d < 3; ++d) acc = R_FMA(C[d], n->p[d], acc);
     st = side_list(n, -1, nb, b);
     if (st) return st;
-    if (b[3] <= LONG_LIST) {
-        for (int d = 0; d < 3; ++d)
-            for (int64_t q = b[d]; q < b[d + 1]; ++q) {
-                unode *m = nb->a[q];
-                acc = R_FMA(-coef_div(o, m, n), m->p[d], acc);
-            }
-    } else {
-        real part[NPART];
-        for (int j = 0; j < NPART; ++j) part[j] = 0;
-        for (int d = 0; d < 3; ++d)
-            for (int64_t q = b[d]; q < b[d + 1]; ++q) {
-                unode *m = nb->a[q];
-                const int j = (int)(q % NPART);
-                part[j] = R_FMA(-coef_div(o, m, n), m->p[d], part[j]);
-            }
-        for (int j = 0; j < NPART; ++j) acc = acc + part[j];
-    }
+    for (int d = 0; d < 3; ++d)
+        for (int64_t q = b[d]; q < b[d + 1]; ++q) {
+            unode *m = nb->a[q];
+            acc = R_FMA(-coef_div(o, m, n), m->p[d], acc);
+        }
     *out = acc;
     return ORC_OK;
 }
@@ -658,23 +613,17 @@ static int gd_flux_leaf(const orc *o, unode *n, real eps2, leafvec *nb) {
     return ORC_OK;
 }
 
-/* d'(u) for leaf n's observations. Term k (in (F, view) order) is
- * W_k * (r_k / sqrt(r_k^2 + eps^2)), r_k = u - F_k; the terms sit in 64 slots
- * (slots k >= M hold 0) and are summed pairwise: (t0 + t1) + (t2 + t3), then
- * those sums pairwise, and so on (M <= 64 views). */
+/* d'(u) for leaf n's observations: the terms W_k (r_k / sqrt(r_k^2 + eps^2)),
+ * r_k = u - F_k, summed in one sequential chain in (F, view) order, times the
+ * normaliser 1 / (sum W + gamma). */
 static real gd_data_grad(const unode *n, real u, real eps2) {
-    real t[64];
-    for (int k = 0; k < 64; ++k) {
-        t[k] = 0;
-        if (k < n->M) {
-            real r = u - n->F[k];
-            real den = R_SQRT(R_FMA(r, r, eps2));
-            t[k] = n->W[k] * (r / den);
-        }
+    real acc = 0;
+    for (int k = 0; k < n->M; ++k) {
+        real r = u - n->F[k];
+        real den = R_SQRT(R_FMA(r, r, eps2));
+        acc = acc + n->W[k] * (r / den);
     }
-    for (int s = 1; s < 64; s *= 2)
-        for (int k = 0; k < 64; k += 2 * s) t[k] = t[k] + t[k + s];
-    return t[0] * n->inv;
+    return acc * n->inv;
 }
 
 static void set_flags(const orc *o, unode *n) {
@@ -971,6 +920,35 @@ int orc_fuse_gd(orc *o, int iterations, float lam, float xi, float eps) {
     o->sol.gd = 0;
     free(lv.a);
     free(nb.a);
+    return st;
+}
+
+/* Test hook: the restructure of the current state, as the fuse loop runs it
+ * after an iteration's primal phase (split/join flags, u', u_old and u+ from
+ * that phase). Valid only right after an orc_fuse call whose last iteration
+ * did not restructure (restructure_every = 0). */
+int orc_restructure_now(orc *o, float lam, float tau) {
+    if (!o || !o->root) return ORC_E_STATE;
+    const real tl = (real)tau * (real)lam;
+    o->sol.gd = 0;
+    return restructure(o, tl);
+}
+
+/* Test hook: per leaf in key order, u' (the primal step's argument of the
+ * prox; for the gradient descent its divergence), u_old (u before the step)
+ * and the split flag, as the last primal phase or split cascade left them. */
+int orc_extract_aux(const orc *o, int64_t cap, double *uprime, double *uold, int32_t *split) {
+    if (!o || !o->root) return ORC_E_STATE;
+    leafvec lv = {0};
+    int st = collect(o->root, &lv);
+    if (!st && lv.n > cap) st = ORC_E_INVALID;
+    for (int64_t i = 0; i < lv.n && !st; ++i) {
+        unode *n = lv.a[i];
+        if (uprime) uprime[i] = (double)n->uprime;
+        if (uold) uold[i] = (double)n->uold;
+        if (split) split[i] = n->split_flag;
+    }
+    free(lv.a);
     return st;
 }
 

@@ -656,7 +656,7 @@ def test_invalid_arguments_rejected():
 
 
 # ---------------------------------------------------------------------------
-# Long neighbour lists (more than 64 entries), summed in 64 interleaved parts
+# Long neighbour lists (thousands of entries on one face)
 # ---------------------------------------------------------------------------
 def _slab_oracle(D, x0):
     """Half-domain leaves against a refined slab of width 2: the coarse leaves
@@ -675,8 +675,9 @@ def _slab_oracle(D, x0):
 
 @pytest.mark.parametrize("x0", [32, 30])
 def test_adjoint_with_long_lists(x0):
-    """The divergence (long lists in parts) is minus the adjoint of the plain
-    sequential gradient in volume-weighted inner products."""
+    """On lists of 1024 entries the divergence is minus the adjoint of the
+    gradient in volume-weighted inner products (a dropped, duplicated or
+    misweighted entry breaks the identity)."""
     D = 6
     o = _slab_oracle(D, x0)
     ex = o.extract()
@@ -693,8 +694,8 @@ def test_adjoint_with_long_lists(x0):
 @pytest.mark.parametrize("x0", [32, 30])
 def test_step_with_long_lists_matches_plain_gradient(x0):
     """With lambda = 0 the prox returns u', so one iteration is the dual step
-    p1 = proj(p0 + sigma G ubar0) with the plain sequential gradient, then
-    u1 = u0 + tau div p1."""
+    p1 = proj(p0 + sigma G ubar0), then u1 = u0 + tau div p1, on lists of 1024
+    entries."""
     D = 6
     o = _slab_oracle(D, x0)
     o.fuse(3, 0.5, TAU32, TAU32)  # a non-trivial p and ubar
