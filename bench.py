@@ -8,7 +8,8 @@ truncation 3 finest voxels, lambda 0.5, tau = sigma = 1/sqrt(12), split and
 join after every iteration. One step = one primal-dual iteration (dual sweep,
 primal sweep, split/join restructuring) over the whole octree. Inputs are
 resident in HBM before the timed region; the octree build is timed
-separately.
+separately. After the warmup the state is exported; --replays (5) timed runs
+of --steps iterations each start from it, and the median is reported.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -18,7 +19,6 @@ import argparse
 import hashlib
 import json
 import os
-import struct
 import sys
 import time
 
@@ -66,12 +66,13 @@ def parse_args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--replays", type=int, default=5, help="timed replays of --steps iterations from one state")
     ap.add_argument("--workload", default="thin", choices=["thin", "blocks", "sphere", "batch48"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--solver", default="pd", choices=["pd", "gd"],
                     help="pd: primal-dual on the exact energy; gd: the paper's gradient descent (lambda on TV, "
                          "step 0.1 halved every 20 iterations, eps 0.3)")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="oracle CPU-baseline budget")
+    ap.add_argument("--cpu-seconds", type=float, default=25.0, help="oracle CPU-baseline budget (fp32 + fp64)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--eval", action="store_true",
                     help="paper-style evaluation on the sphere workload: Eq. 7 quantisation error against a fully "
@@ -96,76 +97,6 @@ def copy_calibration(mib: int):
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration_bytes_read": 4 * n, "copy_calibration_bytes_written": 4 * n,
                       "launches": 5}), flush=True)
-
-
-# --------------------------------------------------------------------------
-# CPU baseline sample: one aligned sub-cube of the exported GPU state
-# --------------------------------------------------------------------------
-_NODE = np.dtype([("key", "<u4"), ("level", "u1"), ("leaf", "u1"), ("pad", "<u2"), ("S", "<f4"), ("cnt", "<u4")])
-_LEAF = np.dtype([("key", "<u4"), ("level", "u1"), ("pad", "u1", (3,)), ("v", "<f4", (5,))])
-
-
-def crop_state(blob: bytes, cube_level: int, M=None, min_leaves: int = 10000):
-    """State blob of one aligned cube at `cube_level`, re-rooted as a domain of
-    depth D - cube_level: among cubes with at least `min_leaves` leaves, the one
-    whose mean observation count per leaf is closest to the whole octree's
-    (the densest cube if M is not given). A view whose octree has no node for
-    the cube contributes its containing leaf, with the count scaled to the
-    cube's volume (kept >= 1 when observed) so that every leaf keeps its
-    observation count."""
-    D = struct.unpack_from("<i", blob, 8)[0]
-    at = 8 + 40 + 8
-    nv = struct.unpack_from("<i", blob, at)[0]
-    at += 8
-    views = []
-    for _ in range(nv):
-        n = struct.unpack_from("<q", blob, at)[0]
-        at += 8
-        views.append(np.frombuffer(blob, _NODE, n, at))
-        at += n * _NODE.itemsize
-    nl = struct.unpack_from("<q", blob, at)[0]
-    at += 8
-    leaves = np.frombuffer(blob, _LEAF, nl, at)
-    sh = 3 * (D - cube_level)
-    cube_of = leaves["key"].astype(np.int64) >> sh
-    counts = np.bincount(cube_of)
-    best = int(counts.argmax())
-    if M is not None and (counts >= min_leaves).any():
-        msum = np.bincount(cube_of, weights=M.astype(np.float64), minlength=len(counts))
-        ok = counts >= min_leaves
-        mean = np.where(ok, msum / np.maximum(counts, 1), np.inf)
-        best = int(np.argmin(np.abs(mean - M.mean())))
-    sel = leaves[(cube_of == best) & (leaves["level"] >= cube_level)]
-    assert np.sum((1 << (3 * (D - sel["level"].astype(np.int64))))) == (1 << sh), "cube not tiled by leaves"
-    mask = (1 << sh) - 1
-    out = bytearray(blob[:8 + 40 + 8 + 8])
-    struct.pack_into("<i", out, 8, D - cube_level)
-    ckey = best << sh
-    for nodes in views:
-        k = nodes["key"].astype(np.int64)
-        lv = nodes["level"].astype(np.int64)
-        inside = (lv >= cube_level) & ((k >> sh) == best)
-        if inside.any():
-            sub = nodes[inside].copy()
-            sub["level"] -= cube_level
-            sub["key"] = (sub["key"].astype(np.int64) & mask).astype(np.uint32)
-        else:
-            # deepest stored node containing the cube (a leaf above cube_level)
-            cont = (lv < cube_level) & ((k >> (3 * (D - lv))) == (ckey >> (3 * (D - lv))))
-            src = nodes[np.nonzero(cont)[0][lv[cont].argmax()]]
-            sub = np.zeros(1, _NODE)
-            scale = 8 ** (cube_level - int(src["level"]))
-            cnt = int(src["cnt"])
-            c2 = 0 if cnt == 0 else max(1, int(round(cnt / scale)))
-            sub["leaf"] = 1
-            sub["cnt"] = c2
-            sub["S"] = np.float32(float(src["S"]) / cnt * c2) if cnt else 0.0
-        out += struct.pack("<q", len(sub)) + sub.tobytes()
-    cl = sel.copy()
-    cl["level"] -= cube_level
-    cl["key"] = (cl["key"].astype(np.int64) & mask).astype(np.uint32)
-    out += struct.pack("<q", len(cl)) + cl.tobytes()
-    return bytes(out), len(cl), best
 
 
 GD_LAMBDA, GD_STEP0, GD_EPS, GD_HALVE = 0.5, 0.1, 0.3, 20
@@ -195,19 +126,21 @@ class Stepper:
             n -= k
 
 
-def cpu_baseline(blob: bytes, M, w, budget_s: float, solver: str = "pd", t0_iter: int = 0):
-    import oracle
+def host_cpu() -> dict:
+    """The host's CPU model and core counts."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "nproc": len(os.sched_getaffinity(0)), "cpu_count": os.cpu_count()}
 
-    for level in (3, 2, 4, 1):
-        try:
-            sub, nleaves, cube = crop_state(blob, level, M)
-        except AssertionError:
-            continue
-        if 2000 <= nleaves <= 400000:
-            break
-    t0 = time.perf_counter()
-    o = oracle.Oracle("f32").import_state(sub)
-    t_import = time.perf_counter() - t0
+
+def _oracle_rate(oracle, sub: bytes, w, budget_s: float, precision: str, solver: str, t0_iter: int):
+    o = oracle.Oracle(precision).import_state(sub)
     updates, iters = 0, 0
     st = Stepper(solver, w)
     st.t = t0_iter
@@ -220,14 +153,109 @@ def cpu_baseline(blob: bytes, M, w, budget_s: float, solver: str = "pd", t0_iter
         el = time.perf_counter() - t0
         if el >= budget_s or iters >= 1000:
             break
-    rate = updates / el
+    return updates / el, iters, el
+
+
+def cpu_baseline(blob: bytes, M, w, budget_s: float, solver: str = "pd", t0_iter: int = 0):
+    """The oracle (single-threaded C, pinned to one core) on one aligned cube of
+    the GPU state after warmup, cut exactly (every observation mean and weight
+    kept) and re-rooted as its own domain: fp32 (the canonical arithmetic the
+    GPU follows) and fp64, each for part of the budget."""
+    import oracle
+    from paper_1608_07411_amd import state
+
+    sub = None
+    for level in (3, 4, 2, 1):
+        try:
+            sub, nleaves, cube = state.crop(blob, level, M=M, min_leaves=2000, max_leaves=400000)
+            break
+        except ValueError:
+            continue
+    if sub is None:
+        return None
+    cpu = host_cpu()
+    old = os.sched_getaffinity(0)
+    core = min(old)
+    os.sched_setaffinity(0, {core})
+    try:
+        r32, it32, el32 = _oracle_rate(oracle, sub, w, 0.6 * budget_s, "f32", solver, t0_iter)
+        r64, it64, el64 = _oracle_rate(oracle, sub, w, 0.4 * budget_s, "f64", solver, t0_iter)
+    finally:
+        os.sched_setaffinity(0, old)
     return {
-        "value": rate, "unit": "leaf-updates/s", "cores": 1, "kind": "oracle",
-        "sample": (f"oracle fp32 (single-threaded C, pointer octree) on level-{level} cube #{cube} of the GPU "
-                   f"state after warmup ({nleaves} leaves at start, mean observations per leaf closest to the "
-                   f"whole octree's {float(M.mean()):.1f}), re-rooted as its own domain; {iters} iterations with "
-                   f"split/join in {el:.1f} s (state import {t_import:.1f} s excluded)"),
+        "value": r32, "unit": "leaf-updates/s", "cores": 1, "kind": "oracle",
+        "fp64_value": r64, "host_cpu": cpu["model"], "nproc": cpu["nproc"], "cpu_count": cpu["cpu_count"],
+        "sample": (f"oracle (single-threaded C, pointer octree) pinned to core {core} of {cpu['nproc']} "
+                   f"({cpu['model']}), on level-{level} cube #{cube} of the GPU state after warmup ({nleaves} "
+                   f"leaves at start, cut exactly: every view stores a node for the cube or a leaf whose count "
+                   f"divides by the volume ratio; the cube whose mean observations per leaf is closest to the "
+                   f"whole octree's {float(np.mean(M)):.1f}), re-rooted as its own domain, split/join every "
+                   f"iteration; fp32 {it32} iterations in {el32:.1f} s, fp64 {it64} iterations in {el64:.1f} s"),
     }
+
+
+def fp64_check(iterations: int = 200) -> dict:
+    """Converged error of the GPU (fp32) against the fp64 oracle on the sphere
+    workload (depth 6, 8 range maps 160x120), both from the GPU's built state,
+    `iterations` with split/join: structure equality, relative energy
+    difference (Eq. 3 with the normaliser of Eq. 5), and |u_gpu - u_f64| on the
+    finest grid (mean, sum over voxels, max)."""
+    import oracle
+    from paper_1608_07411_amd import otf, synth
+
+    w = synth.workload(1)
+    g = otf.Context(0).build_octree(w.depth, w.cams, w.params)
+    o = oracle.Oracle("f64").import_state(g.export_state())
+    g.fuse(iterations, w.lam, w.tau, w.sigma)
+    o.fuse(iterations, w.lam, w.tau, w.sigma)
+    G = 1 << w.max_depth
+    dg = g.dense_field()
+    eo = o.extract()
+    do = np.zeros(G ** 3)
+    x, y, z = oracle.morton_decode(eo["keys"])
+    s = 1 << (w.max_depth - eo["levels"].astype(np.int64))
+    dense = do.reshape(G, G, G)
+    for i in range(len(s)):
+        dense[z[i]:z[i] + s[i], y[i]:y[i] + s[i], x[i]:x[i] + s[i]] = eo["u"][i]
+    diff = np.abs(np.asarray(dg, np.float64).reshape(-1) - do)
+    tg, dag = g.energy()
+    to, dao = o.energy()
+    Eg, Eo = tg + w.lam * dag, to + w.lam * dao
+    eg = g.extract()
+    g.close()
+    return {"workload": "sphere: depth 6, 8 range maps 160x120, split/join every iteration",
+            "iterations": iterations, "leaves": int(eg["keys"].size),
+            "same_structure": bool(np.array_equal(eg["keys"], eo["keys"])
+                                   and np.array_equal(eg["levels"], eo["levels"])),
+            "rel_energy": abs(Eg - Eo) / abs(Eo), "u_l1_mean": float(diff.mean()), "u_l1_sum": float(diff.sum()),
+            "u_linf": float(diff.max())}
+
+
+def stream_ceiling(gib: float = 2.0) -> dict:
+    """Plain copy and read rates of this GPU in the same run: a 2 GiB fp32
+    buffer copied and summed 5 times each (torch kernels)."""
+    import torch
+
+    n = int(gib * (1 << 30)) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    x.sum()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    t_copy = (time.perf_counter() - t0) / 5
+    t0 = time.perf_counter()
+    for _ in range(5):
+        x.sum()
+    torch.cuda.synchronize()
+    t_read = (time.perf_counter() - t0) / 5
+    del x, y
+    torch.cuda.empty_cache()
+    return {"copy_GBs": 2 * 4 * n / t_copy / 1e9, "read_GBs": 4 * n / t_read / 1e9, "buffer_GiB": gib,
+            "note": "torch copy_ (read + write bytes) and sum (read bytes) over a buffer far larger than the caches"}
 
 
 # --------------------------------------------------------------------------
@@ -454,48 +482,73 @@ def main():
     torch.cuda.synchronize()
     log(f"[bench] warmup {args.warmup} iterations {time.perf_counter() - t0:.2f} s, {ctx.num_leaves()} leaves, "
         f"last split/join {ctx.last_counts()}")
-    blob_for_cpu = None if args.no_cpu else ctx.export_state()
-    M_for_cpu = None if args.no_cpu else ctx.obs_counts()
+    # every replay starts from this state
+    blob0 = ctx.export_state()
+    M0 = ctx.obs_counts()
 
-    # timed region: kernel events are recorded on the library's stream as it runs
-    ctx.reset_counters(profile=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    chunk = max(1, args.steps // 10)
-    done = 0
-    while done < args.steps:
-        n = min(chunk, args.steps - done)
-        stepper.run(ctx, n)
-        done += n
-        log(f"[bench] {done}/{args.steps} iterations, {ctx.num_leaves()} leaves")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = ctx.profile_read()
+    def timed_replay(r: int):
+        """K iterations from the warmed-up state (re-imported for r > 0); kernel
+        events are recorded on the library's stream as it runs."""
+        if r > 0:
+            ctx.import_state(blob0)
+        st = Stepper(args.solver, w)
+        st.t = args.warmup
+        ctx.reset_counters(profile=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        chunk = max(1, args.steps // 5)
+        done = 0
+        while done < args.steps:
+            n = min(chunk, args.steps - done)
+            st.run(ctx, n)
+            done += n
+            log(f"[bench] replay {r + 1}/{args.replays}: {done}/{args.steps} iterations, {ctx.num_leaves()} leaves")
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        prof = ctx.profile_read()
+        return dict(elapsed=elapsed, prof=prof, value=prof["leaf_updates"] / elapsed, L_end=ctx.num_leaves())
+
+    reps = [timed_replay(r) for r in range(args.replays)]
+    order = sorted(range(len(reps)), key=lambda r: reps[r]["value"])
+    med = reps[order[len(order) // 2]]
+    elapsed, prof = med["elapsed"], med["prof"]
     updates = prof["leaf_updates"]
-    value = updates / elapsed
-    L1 = ctx.num_leaves()
+    value = med["value"]
+    L1 = med["L_end"]
 
-    kern = {}
-    for kind in ("dual", "primal"):
-        n = prof[kind]["launches"]
-        avg_ms = prof[kind]["ms"] / max(n, 1)
-        bytes_per_launch = prof["bytes"][kind] / max(n, 1)
-        kern[kind] = dict(avg_ms=avg_ms, bytes=bytes_per_launch, gbs=bytes_per_launch / (avg_ms * 1e-3) / 1e9)
-    dom = max(kern, key=lambda k: kern[k]["avg_ms"])
-    ratio = traffic_ratio(f"k_{dom}", f"{w.name}_depth{w.max_depth}") if args.solver == "pd" else None
-    kname = f"k_{dom}" if args.solver == "pd" else {"dual": "k_dual (flux)", "primal": "k_gd_update"}[dom]
+    def per_launch(kind):
+        n = max(prof[kind]["launches"], 1)
+        ms = prof[kind]["ms"] / n
+        mb = prof["method_bytes"][kind] / n
+        ib = prof["bytes"][kind] / n
+        return dict(avg_ms=ms, method_bytes=mb, impl_bytes=ib, method_GBs=mb / (ms * 1e-3) / 1e9,
+                    impl_GBs=ib / (ms * 1e-3) / 1e9)
+
+    kern = {k: per_launch(k) for k in ("dual", "primal")}
+    sweep_s = (kern["dual"]["avg_ms"] + kern["primal"]["avg_ms"]) * 1e-3
+    sweep_bytes = kern["dual"]["method_bytes"] + kern["primal"]["method_bytes"]
+    ratio = traffic_ratio("leaf_sweep", f"{w.name}_depth{w.max_depth}") if args.solver == "pd" else None
+    names = {"pd": "k_dual + k_primal", "gd": "k_dual (flux) + k_gd_update"}
+    achieved = sweep_bytes / sweep_s / 1e9
     roofline = {
-        "bound": "hbm", "kernel": kname, "achieved": kern[dom]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": kern[dom]["gbs"] / HBM_PEAK_GBS,
-        "traffic": None if ratio is None else ratio * kern[dom]["bytes"],
-        "traffic_note": ("hardware bytes per launch = profiled FETCH/WRITE-to-algorithmic ratio x this run's "
-                         "algorithmic bytes" if ratio is not None else "no profile of the current kernel source"),
-        "algorithmic_bytes_per_launch": kern[dom]["bytes"], "avg_launch_ms": kern[dom]["avg_ms"],
+        "bound": "hbm", "kernel": f"leaf sweep: {names[args.solver]} (one dual and one primal launch)",
+        "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+        "traffic": None if ratio is None else ratio * sweep_bytes,
+        "traffic_note": ("hardware bytes per sweep = profiled (FETCH_SIZE, WRITE_SIZE)-to-algorithmic ratio x "
+                         "this run's algorithmic bytes" if ratio is not None
+                         else "no counter profile of the current sweep source"),
+        "algorithmic_bytes_per_launch": sweep_bytes, "avg_launch_ms": 1e3 * sweep_s,
+        "bytes_definition": ("per leaf-update 40 (u, ubar, p read and written) + 4 per face-adjacency entry + 8 "
+                             "(observation offset, normaliser) + 4 per observation + 4 per prefix weight of a "
+                             "leaf with fractional weights"),
+        "kernels": {f"k_{k}" if args.solver == "pd" else {"dual": "k_dual (flux)", "primal": "k_gd_update"}[k]: v
+                    for k, v in kern.items()},
     }
     phase_ms = {k: prof[k]["ms"] for k in ("dual", "primal", "restructure")}
     sweep_ms = phase_ms["dual"] + phase_ms["primal"]
-    log(f"[bench] {updates} leaf-updates in {elapsed:.3f} s -> {value:.4g}/s; phases (ms) {phase_ms}")
-    log(f"[bench] dual {kern['dual']}, primal {kern['primal']}")
+    log(f"[bench] median replay: {updates} leaf-updates in {elapsed:.3f} s -> {value:.4g}/s; phases (ms) {phase_ms}")
+    log(f"[bench] sweep {achieved:.0f} GB/s ({achieved / HBM_PEAK_GBS:.3f} of peak); dual {kern['dual']}, "
+        f"primal {kern['primal']}")
 
     result = {
         "metric": "leaf-updates/sec (depth-9 octree)", "value": value, "unit": "leaf-updates/s",
@@ -513,15 +566,24 @@ def main():
             "inputs_md5": hashlib.md5(w.depth.tobytes()).hexdigest(),
         },
         "roofline": roofline,
+        "replays": {"n": args.replays, "statistic": "median", "from": "one exported state after warmup",
+                    "values": [r["value"] for r in reps]},
         "sweep_only": {"value": updates / (sweep_ms * 1e-3) if sweep_ms > 0 else None, "unit": "leaf-updates/s",
                        "note": "dual + primal kernel time only (events), restructuring excluded"},
         "phase_ms": phase_ms, "build_s": build_s,
     }
-    if blob_for_cpu is not None:
+    ctx.close()
+    result["stream_ceiling"] = stream_ceiling()
+    log(f"[bench] stream ceiling {result['stream_ceiling']}")
+    if not args.no_cpu:
         log("[bench] CPU baseline (oracle) ...")
-        result["cpu_baseline"] = cpu_baseline(blob_for_cpu, M_for_cpu, w, args.cpu_seconds, args.solver,
-                                              args.warmup)
-        log(f"[bench] CPU baseline {result['cpu_baseline']['value']:.4g} leaf-updates/s")
+        result["cpu_baseline"] = cpu_baseline(blob0, M0, w, args.cpu_seconds, args.solver, args.warmup)
+        if result["cpu_baseline"]:
+            log(f"[bench] CPU baseline {result['cpu_baseline']['value']:.4g} leaf-updates/s (fp32), "
+                f"{result['cpu_baseline']['fp64_value']:.4g} (fp64)")
+        log("[bench] fp64 check (sphere workload, 200 iterations) ...")
+        result["fp64_check"] = fp64_check()
+        log(f"[bench] fp64 check {result['fp64_check']}")
     else:
         result["cpu_baseline"] = None
     print(json.dumps(result), flush=True)

@@ -174,8 +174,15 @@ otf_status otf_import_state(otf_ctx *ctx, const void *buf, int64_t n_bytes);
  * Kinds: 0 dual sweep, 1 primal sweep, 2 restructure (all its kernels,
  * including the observation gather and the adjacency rebuild), 3 energy.
  * otf_profile_read fills ms[4] (summed milliseconds) and launches[4], and
- * leaf_updates (sum over iterations of the leaf count) and bytes[2]
- * (algorithmic bytes of the dual and primal sweeps, summed). */
+ * leaf_updates (sum over iterations of the leaf count) and bytes[4], summed
+ * over the iterations: [0] and [1] the bytes the dual and the primal sweep
+ * move as implemented (level bytes, the divergence hand-over, flags and the
+ * whole observation header included); [2] and [3] the method's own bytes of
+ * one leaf sweep, per leaf-update 40 (u, ubar and p read and written) + 4 per
+ * face-adjacency entry + 8 (observation offset and normaliser) + 4 per
+ * observation value + 4 per prefix weight of a leaf with fractional weights,
+ * attributed to the dual ([2]: ubar and p read, p written, the + list) and
+ * the primal ([3]: the rest). Any pointer may be NULL. */
 otf_status otf_profile(otf_ctx *ctx, int32_t enable);
 otf_status otf_profile_read(otf_ctx *ctx, double *ms, int64_t *launches, int64_t *leaf_updates, double *bytes);
 
@@ -187,6 +194,24 @@ otf_status otf_profile_read(otf_ctx *ctx, double *ms, int64_t *launches, int64_t
  * (0: all equal). Needs no fused state. Errors: OTF_E_INVALID (null, n < 0 or
  * n > 2^28), OTF_E_NOMEM, OTF_E_DEVICE. */
 otf_status otf_selftest_scan(otf_ctx *ctx, int64_t n, uint64_t seed, int64_t *mismatches);
+
+/* Test hook: the after-th device allocation made by later calls on this
+ * context fails as if the device were out of memory, so that the call returns
+ * OTF_E_NOMEM (after = 0 turns the hook off; it fires once). The context stays
+ * destroyable and frees everything it holds; a failed fuse leaves no valid
+ * state (OTF_E_STATE until the next build or import). Errors: OTF_E_INVALID
+ * (null, after < 0). */
+otf_status otf_debug_fail_allocations(otf_ctx *ctx, int64_t after);
+
+/* Test hook of the bounds-checked build (compiled with OTF_DEBUG_BOUNDS, where
+ * the sweeps check every adjacency range, neighbour index, level code and
+ * observation index they read, redirect a bad read to index 0 and report it:
+ * the solver call then fails with OTF_E_DEVICE): points the first + entry of
+ * `leaf` past the last leaf, so that the next fuse must report it. The
+ * default build rejects it with OTF_E_INVALID and changes nothing. Errors:
+ * OTF_E_INVALID (null, leaf out of range, no + neighbour, default build),
+ * OTF_E_STATE. */
+otf_status otf_debug_corrupt_adjacency(otf_ctx *ctx, int64_t leaf);
 
 /* Message of the last failure on this context (empty if none). Valid until the
  * next call on the context. */

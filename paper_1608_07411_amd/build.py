@@ -12,6 +12,10 @@ CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 OBJDIR = os.path.join(HERE, "lib", "obj")
 LIB = os.path.join(LIBDIR, "libotf.so")
+# variant name -> (library file, extra flags): the default build, and the
+# bounds-checked one (every adjacency and observation index the sweeps read
+# is checked on the device)
+VARIANTS = {"default": ("libotf.so", []), "bounds": ("libotf_bounds.so", ["-DOTF_DEBUG_BOUNDS"])}
 SOURCES = ["api.hip", "batch.hip", "build.hip", "gather.hip", "mesh.hip", "mlp.hip", "nbr.hip", "restructure.hip", "scan.hip", "sweep.hip"]
 
 ARCH = os.environ.get("OTF_OFFLOAD_ARCH", "gfx950")
@@ -33,13 +37,16 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False, jobs: int = 8) -> str:
-    os.makedirs(OBJDIR, exist_ok=True)
+def build(verbose: bool = False, jobs: int = 8, variant: str = "default") -> str:
+    name, extra = VARIANTS[variant]
+    objdir = OBJDIR if variant == "default" else os.path.join(OBJDIR, variant)
+    lib = os.path.join(LIBDIR, name)
+    os.makedirs(objdir, exist_ok=True)
     hipcc = _hipcc()
 
     def compile_one(src):
-        obj = os.path.join(OBJDIR, src.replace(".hip", ".o"))
-        cmd = [hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        obj = os.path.join(objdir, src.replace(".hip", ".o"))
+        cmd = [hipcc, *HIPCC_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)
@@ -49,16 +56,17 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
 
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(compile_one, SOURCES))
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    for v in VARIANTS:
+        print(build(verbose=True, variant=v))

@@ -198,33 +198,71 @@ void setup_after_structure(Ctx &c, bool init_values) {
 
 }  // namespace
 
-// Algorithmic bytes of one dual sweep: every leaf reads its level, ubar and p
-// and its + adjacency (offset and entries), writes p and ds; a neighbour's
-// ubar is counted once per leaf, not per entry (a Morton sweep reuses it).
+// Bytes the two leaf sweeps of one iteration move as implemented, per sweep.
+// Dual: every leaf reads its level, ubar and p and its + adjacency (offset
+// and entries), writes p and ds; a neighbour's ubar is counted once per
+// leaf, not per entry (a Morton sweep reuses it).
 double dual_bytes(const Ctx &c) {
     const double L = (double)c.L;
     return L * (1 + 4 + 12 + 4) + 4.0 * (double)c.leaves[c.cur].n_nbp + L * (12 + 4);
 }
 
-// Algorithmic bytes of one primal sweep: level, ds, u, the - adjacency, p
-// once per leaf, the observation header (offset, count, normaliser, total
-// weight); writes u, ubar and the flag byte. The observation segments (F,
-// plus P for leaves with fractional weights, 4 bytes each: with unit weights
-// P_k = k is implied, although the kernel reads it too) are added from the
-// device-side accumulator when read.
+// Primal: level, ds, u, the - adjacency, p once per leaf, the observation
+// header (offset, count, normaliser, total weight); writes u, ubar and the
+// flag byte. The observation segments (F, plus P for leaves with fractional
+// weights, 4 bytes each) are added from the device-side accumulator when
+// read.
 double primal_bytes(const Ctx &c) {
     const double L = (double)c.L;
     return L * (1 + 4 + 4 + 12) + 4.0 * (double)c.leaves[c.cur].n_nbm + L * (4 + 1 + 4 + 4) + L * (4 + 4 + 1);
 }
 
+// The method's own bytes per leaf-update of one whole leaf sweep, with no
+// reuse across iterations: u, ubar and p each read and written (40), 4 per
+// face-adjacency entry of both lists, the observation header (segment offset
+// and normaliser, 8), 4 per sorted observation value and 4 per prefix weight
+// of a leaf with fractional weights (the latter two from the device-side
+// accumulator when read). Attributed to the kernel that moves them: the dual
+// reads ubar and p, writes p and reads the + list (28 + 4 E+); the primal
+// reads u, writes u and ubar, reads the header and the - list
+// (20 + 4 E- + observations).
+double dual_method_bytes(const Ctx &c) {
+    return 28.0 * (double)c.L + 4.0 * (double)c.leaves[c.cur].n_nbp;
+}
+
+double primal_method_bytes(const Ctx &c) {
+    return 20.0 * (double)c.L + 4.0 * (double)c.leaves[c.cur].n_nbm;
+}
+
+void count_sweep_bytes(Ctx &c) {
+    c.alg_bytes[0] += dual_bytes(c);
+    c.alg_bytes[1] += primal_bytes(c);
+    c.alg_bytes[2] += dual_method_bytes(c);
+    c.alg_bytes[3] += primal_method_bytes(c);
+}
+
+}  // namespace otf
+
+namespace otf {
+thread_local int64_t *t_alloc_countdown = nullptr;
 }  // namespace otf
 
 using namespace otf;
 
 namespace {
 
+// Points the allocation-failure countdown at the context for one call.
+struct AllocHook {
+    int64_t *saved;
+    explicit AllocHook(otf_ctx *ctx) : saved(t_alloc_countdown) {
+        t_alloc_countdown = ctx ? &ctx->c.fail_alloc_after : nullptr;
+    }
+    ~AllocHook() { t_alloc_countdown = saved; }
+};
+
 template <class F>
 otf_status guard(otf_ctx *ctx, bool invalidates, F &&f) {
+    AllocHook hook(ctx);
     if (ctx) {
         if (hipSetDevice(ctx->c.device) != hipSuccess) {
             (void)hipGetLastError();
@@ -391,8 +429,7 @@ otf_status otf_fuse(otf_ctx *ctx, int32_t iterations, float lambda, float tau, f
             prof_end(c, kProfPrimal);
             count_flags(c);
             c.leaf_updates += c.L;
-            c.alg_bytes[0] += dual_bytes(c);
-            c.alg_bytes[1] += primal_bytes(c);
+            count_sweep_bytes(c);
             accumulate_obs(c);
             c.last_splits = c.last_joins = 0;
             if (c.prm.restructure_every > 0 && c.iteration % c.prm.restructure_every == 0) {
@@ -430,8 +467,7 @@ otf_status otf_fuse_gd(otf_ctx *ctx, int32_t iterations, float lambda, float ste
             count_flags(c);
             c.leaf_updates += c.L;
             // same bytes as the primal-dual sweeps, with W in place of P for every observation
-            c.alg_bytes[0] += dual_bytes(c);
-            c.alg_bytes[1] += primal_bytes(c);
+            count_sweep_bytes(c);
             accumulate_obs(c, true);
             c.last_splits = c.last_joins = 0;
             if (c.prm.restructure_every > 0 && c.iteration % c.prm.restructure_every == 0) {
@@ -698,6 +734,35 @@ otf_status otf_energy(otf_ctx *ctx, double *tv, double *data) {
     });
 }
 
+otf_status otf_debug_corrupt_adjacency(otf_ctx *ctx, int64_t leaf) {
+#ifdef OTF_DEBUG_BOUNDS
+    if (!ctx || leaf < 0) return OTF_E_INVALID;
+    if (!ctx->c.valid) return OTF_E_STATE;
+    if (leaf >= ctx->c.L) return OTF_E_INVALID;
+    return guard(ctx, false, [&] {
+        Ctx &c = ctx->c;
+        LeafStore &s = c.lv();
+        uint32_t off[2];
+        OTF_HIP(hipMemcpy(off, s.nbp_off.p + leaf, sizeof off, hipMemcpyDeviceToHost));
+        if (off[1] == off[0]) fail(OTF_E_INVALID, "the leaf has no + neighbour");
+        uint32_t e = 0;
+        OTF_HIP(hipMemcpy(&e, s.nbp.p + off[0], sizeof e, hipMemcpyDeviceToHost));
+        e = (e & ~kIdxMask) | (uint32_t)(c.L + 1);  // past the last leaf, inside the index field
+        OTF_HIP(hipMemcpy(s.nbp.p + off[0], &e, sizeof e, hipMemcpyHostToDevice));
+    });
+#else
+    (void)leaf;
+    if (ctx) ctx->c.err = "only the bounds-checked build corrupts an adjacency entry";
+    return OTF_E_INVALID;
+#endif
+}
+
+otf_status otf_debug_fail_allocations(otf_ctx *ctx, int64_t after) {
+    if (!ctx || after < 0) return OTF_E_INVALID;
+    ctx->c.fail_alloc_after = after;
+    return OTF_OK;
+}
+
 otf_status otf_energy_eps(otf_ctx *ctx, double epsilon, double *tv, double *data) {
     if (!ctx || !tv || !data || !std::isfinite(epsilon) || !(epsilon > 0.0)) return OTF_E_INVALID;
     if (!ctx->c.valid) return OTF_E_STATE;
@@ -943,7 +1008,7 @@ otf_status otf_profile(otf_ctx *ctx, int32_t enable) {
             c.prof_n[k] = 0;
         }
         c.leaf_updates = 0;
-        c.alg_bytes[0] = c.alg_bytes[1] = 0.0;
+        for (double &b : c.alg_bytes) b = 0.0;
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, c.stream, c.counters.p + 16, 2);
         OTF_HIP(hipStreamSynchronize(c.stream));
     });
@@ -965,6 +1030,8 @@ otf_status otf_profile_read(otf_ctx *ctx, double *ms, int64_t *launches, int64_t
             std::memcpy(&obs_acc, c.h_counters + 16, 8);
             bytes[0] = c.alg_bytes[0];
             bytes[1] = c.alg_bytes[1] + 4.0 * (double)obs_acc;
+            bytes[2] = c.alg_bytes[2];
+            bytes[3] = c.alg_bytes[3] + 4.0 * (double)obs_acc;
         }
     });
 }

@@ -92,8 +92,7 @@ bool after_sweeps(otf_batch *bt, float tl) {
     for (Ctx *c : bt->b.objs) {
         c->iteration++;
         c->leaf_updates += c->L;
-        c->alg_bytes[0] += dual_bytes(*c);
-        c->alg_bytes[1] += primal_bytes(*c);
+        count_sweep_bytes(*c);
         c->last_splits = c->last_joins = 0;
         if (c->prm.restructure_every > 0 && c->iteration % c->prm.restructure_every == 0) {
             restructure(*c, tl);

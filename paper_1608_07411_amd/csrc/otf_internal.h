@@ -33,6 +33,14 @@ struct Failure {
 };
 
 [[noreturn]] void fail(otf_status st, const std::string &msg);
+
+// Allocation-failure injection (a test hook): while an entry point runs on a
+// context, this points at the context's countdown; the allocation that takes
+// it from 1 to 0 fails as if the device were out of memory.
+extern thread_local int64_t *t_alloc_countdown;
+inline bool alloc_fault_due() {
+    return t_alloc_countdown && *t_alloc_countdown > 0 && --*t_alloc_countdown == 0;
+}
 void hip_check(hipError_t e, const char *what);
 #define OTF_HIP(x) ::otf::hip_check((x), #x)
 #define OTF_LAUNCH_CHECK(name) ::otf::hip_check(hipGetLastError(), name)
@@ -60,6 +68,7 @@ struct DBuf {
         if (count <= n && p) return;
         release();
         size_t c = count ? count + count / 4 + 64 : 1;
+        if (alloc_fault_due()) fail(OTF_E_NOMEM, "device allocation failed (injected)");
         hipError_t e = hipMalloc((void **)&p, c * sizeof(T));
         if (e != hipSuccess) {
             p = nullptr;
@@ -330,6 +339,7 @@ struct Solver {
 
 struct Ctx {
     int device = 0;
+    int64_t fail_alloc_after = 0;  // allocation-failure injection countdown (0: off)
     Solver sol;
     hipStream_t stream = nullptr;
     // a second stream of the library's own (default priority) with fork and
@@ -375,7 +385,9 @@ struct Ctx {
     double prof_ms[kProfKinds] = {0, 0, 0, 0};
     int64_t prof_n[kProfKinds] = {0, 0, 0, 0};
     int64_t leaf_updates = 0;     // sum over iterations of the leaf count (always counted)
-    double alg_bytes[2] = {0, 0};  // algorithmic bytes of the dual and primal sweeps (always counted)
+    // bytes of the dual and primal sweeps (always counted): as implemented
+    // [0, 1], and the method's own per leaf-update [2, 3]
+    double alg_bytes[4] = {0, 0, 0, 0};
     // structure sizes for the algorithmic byte counts
 
     std::string err;
@@ -427,6 +439,9 @@ struct OnSideStream {
 };
 // all work on the stream finished (stream synchronised), scan health checked
 void finish(Ctx &c);
+// Bounds-checked build: the sweeps' violation flags since the last call
+// (cleared); 0 in the default build.
+uint32_t take_bounds_flag();
 // scans over n elements; the total is returned to the host (synchronises)
 uint32_t scan_exclusive_u8(Ctx &c, const uint8_t *in, uint32_t *out, int64_t n);
 uint32_t scan_exclusive_u32(Ctx &c, const uint32_t *in, uint32_t *out, int64_t n);
@@ -555,6 +570,7 @@ void batch_upload(hipStream_t st, BatchState &b, float sigma, float tau, float t
 void batch_sweeps(hipStream_t st, BatchState &b);
 double dual_bytes(const Ctx &c);
 double primal_bytes(const Ctx &c);
+void count_sweep_bytes(Ctx &c);  // one iteration's sweep bytes into alg_bytes
 
 }  // namespace otf
 

@@ -240,29 +240,13 @@ __global__ void k_cascade_prox(int64_t nc, int stride, const float *tF, const fl
     const float *F = tF + j * (int64_t)stride, *W = tW + j * (int64_t)stride;
     float val;
     if (sol.gd) {
-        // data gradient terms in 64 slots summed pairwise (a binary counter:
-        // slot k closes the blocks its trailing one bits end), as the sweep's
-        // butterfly does
+        // data gradient terms in one sequential chain in (F, view) order
         const int M = tM[j];
-        float stk[6];
         float x = 0.0f;
-#pragma unroll
-        for (int k = 0; k < 64; ++k) {
-            x = 0.0f;
-            if (k < M) {
-                const float r = uo - F[k];
-                const float den = sqrtf(__fmaf_rn(r, r, sol.eps2));
-                x = W[k] * (r / den);
-            }
-#pragma unroll
-            for (int b = 0; b < 6; ++b) {
-                if ((k >> b) & 1) {
-                    x = stk[b] + x;
-                } else {
-                    stk[b] = x;
-                    break;
-                }
-            }
+        for (int k = 0; k < M; ++k) {
+            const float r = uo - F[k];
+            const float den = sqrtf(__fmaf_rn(r, r, sol.eps2));
+            x = x + W[k] * (r / den);
         }
         val = __fmaf_rn(sol.xi, __fmaf_rn(sol.lam, up, -(x * tInv[j])), uo);
         cu[j] = val;

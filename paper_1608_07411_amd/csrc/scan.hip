@@ -473,6 +473,8 @@ void read_back(Ctx &c, std::initializer_list<ReadItem> items) { read_back_wait(c
 void finish(Ctx &c) {
     read_back(c, {});
     OTF_HIP(hipStreamSynchronize(c.stream));
+    if (const uint32_t b = take_bounds_flag())
+        fail(OTF_E_DEVICE, "index out of range in a sweep (bounds-checked build), flags " + std::to_string(b));
 }
 
 namespace {

@@ -13,11 +13,10 @@
 //         max(u' - t S_k, F_(k)) (the median of the 2M+1 values)
 //   ubar = 2 u+ - u,  u = u+
 //   flags: split if |u+| < tau_s below max depth, joinable if |u+| > tau_j.
-// Every floating-point operation is a single IEEE operation in a fixed order.
-// Sums over a + or - list of at most kLongList entries are one chain in list
-// order (x, y, z neighbours, each in ascending key); a longer list is summed
-// in 64 interleaved parts (entry q to part q mod 64, each part a chain from 0
-// in list order), the parts then added in part order.
+// Every floating-point operation is a single IEEE operation in a fixed order,
+// and every sum is one sequential chain: over a + or - list in list order (x,
+// y, z neighbours, each in ascending key), however long the list; over a
+// leaf's observations in (F, view) order.
 #include "otf_internal.h"
 
 namespace otf {
@@ -26,6 +25,36 @@ namespace {
 constexpr int kBlk = 256;
 constexpr int kAhead = 8;   // leaves whose observations one wave loads ahead in k_primal
 constexpr int kGather = 4;  // neighbour entries per thread in flight in the short-list sweeps
+
+#ifdef OTF_DEBUG_BOUNDS
+// Bounds-checked build: every adjacency entry (list range, neighbour index,
+// level code) and every observation index the sweeps read is checked. A
+// violation sets a bit of this flag, which the host reads and clears after
+// each solver call, and the read goes to index 0 instead (no fault).
+static __device__ uint32_t bounds_flag;
+__device__ inline uint32_t chk(uint32_t i, int64_t n, uint32_t bit) {
+    if ((int64_t)i >= n) {
+        atomicOr(&bounds_flag, bit);
+        return 0u;
+    }
+    return i;
+}
+#define OTF_NB(v, L) chk((v) & kIdxMask, (L), 1u)
+#define OTF_LV(v) chk((v) >> (kIdxBits + 2), kMaxDepth + 1, 2u)
+#define OTF_OBS(e, n) chk((e), (n), 4u)
+#define OTF_SEG(e0, e1, n)                                                 \
+    do {                                                                   \
+        if ((int64_t)(e1) > (n) || (e0) > (e1)) {                          \
+            atomicOr(&bounds_flag, 8u);                                    \
+            (e0) = (e1) = 0u;                                              \
+        }                                                                  \
+    } while (0)
+#else
+#define OTF_NB(v, L) ((v) & kIdxMask)
+#define OTF_LV(v) ((v) >> (kIdxBits + 2))
+#define OTF_OBS(e, n) (e)
+#define OTF_SEG(e0, e1, n) ((void)0)
+#endif
 
 __device__ inline float rdlane(float v, int l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
@@ -38,6 +67,7 @@ struct DualArgs {
     const float *ubar;  // the field differenced: ubar (primal-dual) or u (gradient descent)
     const uint32_t *off;
     const uint32_t *ent;
+    int64_t n_ent;  // entries of the list (bounds-checked build)
     float *p;
     float *ds;
     float sigma;
@@ -81,7 +111,8 @@ __device__ inline void dual_finish(const DualArgs &a, int64_t i, float gx, float
 // Dual update of leaf i (one thread); a leaf with a long + list is left to
 // dual_long_wave.
 __device__ inline void dual_leaf(const DualArgs &a, const Coef &cf, int64_t i) {
-    const uint32_t e0 = a.off[i], e1 = a.off[i + 1];
+    uint32_t e0 = a.off[i], e1 = a.off[i + 1];
+    OTF_SEG(e0, e1, a.n_ent);
     if (e1 - e0 > kLongList) return;
     const int ln = a.level[i];
     const float ub = a.ubar[i];
@@ -93,12 +124,12 @@ __device__ inline void dual_leaf(const DualArgs &a, const Coef &cf, int64_t i) {
 #pragma unroll
         for (int r = 0; r < kGather; ++r) v[r] = e + r < e1 ? a.ent[e + r] : 0u;
 #pragma unroll
-        for (int r = 0; r < kGather; ++r) ubk[r] = e + r < e1 ? a.ubar[v[r] & kIdxMask] : 0.0f;
+        for (int r = 0; r < kGather; ++r) ubk[r] = e + r < e1 ? a.ubar[OTF_NB(v[r], a.L)] : 0.0f;
 #pragma unroll
         for (int r = 0; r < kGather; ++r) {
             if (e + r >= e1) break;
             const int d = (v[r] >> kIdxBits) & 3;
-            const float c = cf.c[ln][v[r] >> (kIdxBits + 2)];
+            const float c = cf.c[ln][OTF_LV(v[r])];
             const float diff = ubk[r] - ub;
             if (d == 0) {
                 gx = __fmaf_rn(c, diff, gx);
@@ -148,6 +179,7 @@ __device__ inline void dual_leaves(const DualArgs &a, const Coef &cf, const int6
         const int64_t i = on[n] ? idx[n] : 0;
         e0[n] = a.off[i];
         e1[n] = a.off[i + 1];
+        OTF_SEG(e0[n], e1[n], a.n_ent);
         ln[n] = a.level[i];
         ub[n] = a.ubar[i];
 #pragma unroll
@@ -179,7 +211,7 @@ __device__ inline void dual_leaves(const DualArgs &a, const Coef &cf, const int6
         for (int n = 0; n < N; ++n)
 #pragma unroll
             for (int r = 0; r < kGather; ++r)
-                ubk[n][r] = a.ubar[e0[n] + k + r < e1[n] ? (v[n][r] & kIdxMask) : 0u];
+                ubk[n][r] = a.ubar[e0[n] + k + r < e1[n] ? OTF_NB(v[n][r], a.L) : 0u];
         // entries folded in list order; selects rather than branches, so that
         // no load is deferred into a conditional block
 #pragma unroll
@@ -188,7 +220,7 @@ __device__ inline void dual_leaves(const DualArgs &a, const Coef &cf, const int6
             for (int r = 0; r < kGather; ++r) {
                 const bool ok = e0[n] + k + r < e1[n];
                 const int d = ok ? (int)((v[n][r] >> kIdxBits) & 3) : 3;
-                const float c = cf.c[ln[n]][v[n][r] >> (kIdxBits + 2)];
+                const float c = cf.c[ln[n]][OTF_LV(v[n][r])];
                 const float diff = ubk[n][r] - ub[n];
 #pragma unroll
                 for (int x = 0; x < 3; ++x) {
@@ -224,56 +256,81 @@ __device__ inline void dual_leaves(const DualArgs &a, const Coef &cf, const int6
 }
 
 
-// Leaves whose + list is longer than kLongList, one wave each. Such a list is
-// summed in 64 interleaved parts: lane j folds the entries at list positions
-// j, j + 64, j + 128, ... (an fma chain from 0 in list order, one per
-// direction, with the coefficient sums alongside), then the 64 parts of each
-// sum are added in lane order. Lane j's loads of kLongUnroll entries are in
-// flight together; the wave's loads are coalesced.
+// Leaves whose + list is longer than kLongList, one wave each. The wave loads
+// the list in chunks of 64 entries (coalesced, kLongUnroll chunks in flight
+// per lane), stages each chunk in LDS as (coefficient, operand) pairs and
+// folds it into the sequential chains in list order: every lane runs the
+// same chain on the same LDS words (broadcast reads), so the result is on
+// every lane. The list is sorted by direction, so the entries of direction d
+// in a chunk form one run, found by a ballot.
 constexpr int kLongUnroll = 4;
 constexpr int kWavesPerBlock = kBlk / 64;
 
-// sum of the 64 lanes' v, added in lane order (the same value on every lane)
-__device__ inline float lane_order_sum(float v) {
-    float s = 0.0f;
-    // (partly unrolled: a full unroll would hold all 64 values in scalar
-    // registers and lower the occupancy of the sweeps that include it)
-#pragma unroll 8
-    for (int j = 0; j < 64; ++j) s = s + rdlane(v, j);
-    return s;
+// LDS of one wave: a staged chunk (64 pairs), or kAhead rows of 64
+// observation terms (row pitch 65 words, so that lane g reading row g
+// touches distinct banks).
+constexpr int kTermPitch = 65;
+constexpr int kStageWords = kAhead * kTermPitch;
+static_assert(kStageWords >= 128, "a chunk of 64 pairs must fit the stage");
+
+// LDS writes of a wave's lanes before reads by other lanes of the same wave.
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ void dual_long_wave(const DualArgs &a, const Coef &cf, int64_t i, int lane) {
-    const uint32_t e0 = a.off[i], ne = a.off[i + 1] - e0;
+// Run [k0, k1) of a chunk whose lanes hold direction d (mask of the lanes).
+__device__ inline void run_of(uint64_t m, int &k0, int &k1) {
+    k0 = m ? (int)__builtin_ctzll(m) : 0;
+    k1 = k0 + (int)__popcll(m);
+}
+
+// g = fma(c, x, g), C = C + c over the staged pairs [k0, k1), in order.
+__device__ inline void fold_grad(const float2 *st, int k0, int k1, float &g, float &C) {
+    for (int k = k0; k < k1; ++k) {
+        const float2 e = st[k];
+        g = __fmaf_rn(e.x, e.y, g);
+        C = C + e.x;
+    }
+}
+
+__device__ void dual_long_wave(const DualArgs &a, const Coef &cf, int64_t i, int lane, float *lds) {
+    float2 *st = reinterpret_cast<float2 *>(lds);
+    uint32_t e0 = a.off[i], e1 = a.off[i + 1];
+    OTF_SEG(e0, e1, a.n_ent);
+    const uint32_t ne = e1 - e0;
     const int ln = a.level[i];
     const float ub = a.ubar[i];
     float g[3] = {0.0f, 0.0f, 0.0f}, C[3] = {0.0f, 0.0f, 0.0f};
-    for (uint32_t q0 = lane; q0 < ne; q0 += 64 * kLongUnroll) {
+    for (uint32_t q0 = 0; q0 < ne; q0 += 64 * kLongUnroll) {
         uint32_t v[kLongUnroll];
         float u[kLongUnroll];
 #pragma unroll
         for (int r = 0; r < kLongUnroll; ++r) {
-            const uint32_t q = q0 + 64 * r;
+            const uint32_t q = q0 + 64 * r + lane;
             v[r] = a.ent[e0 + (q < ne ? q : 0u)];
         }
 #pragma unroll
-        for (int r = 0; r < kLongUnroll; ++r) u[r] = a.ubar[q0 + 64 * r < ne ? (v[r] & kIdxMask) : 0u];
+        for (int r = 0; r < kLongUnroll; ++r) u[r] = a.ubar[q0 + 64 * r + lane < ne ? OTF_NB(v[r], a.L) : 0u];
 #pragma unroll
         for (int r = 0; r < kLongUnroll; ++r) {
-            const int d = q0 + 64 * r < ne ? (int)((v[r] >> kIdxBits) & 3) : 3;
-            const float c = cf.c[ln][v[r] >> (kIdxBits + 2)];
-            const float diff = u[r] - ub;
-#pragma unroll
-            for (int x = 0; x < 3; ++x) {
-                const float gn = __fmaf_rn(c, diff, g[x]), Cn = C[x] + c;
-                g[x] = d == x ? gn : g[x];
-                C[x] = d == x ? Cn : C[x];
-            }
+            if (q0 + 64 * r >= ne) break;  // uniform
+            const int d = q0 + 64 * r + lane < ne ? (int)((v[r] >> kIdxBits) & 3) : 3;
+            const uint64_t m0 = __ballot(d == 0), m1 = __ballot(d == 1), m2 = __ballot(d == 2);
+            st[lane] = make_float2(cf.c[ln][OTF_LV(v[r])], u[r] - ub);
+            wave_lds_sync();
+            int k0, k1;
+            run_of(m0, k0, k1);
+            fold_grad(st, k0, k1, g[0], C[0]);
+            run_of(m1, k0, k1);
+            fold_grad(st, k0, k1, g[1], C[1]);
+            run_of(m2, k0, k1);
+            fold_grad(st, k0, k1, g[2], C[2]);
+            wave_lds_sync();
         }
     }
-    const float gx = lane_order_sum(g[0]), gy = lane_order_sum(g[1]), gz = lane_order_sum(g[2]);
-    const float Cx = lane_order_sum(C[0]), Cy = lane_order_sum(C[1]), Cz = lane_order_sum(C[2]);
-    if (lane == 0) dual_finish(a, i, gx, gy, gz, Cx, Cy, Cz);
+    if (lane == 0) dual_finish(a, i, g[0], g[1], g[2], C[0], C[1], C[2]);
 }
 
 // Dual sweep in one launch: the first long_blocks blocks take the leaves with
@@ -286,8 +343,9 @@ k_dual(DualArgs a, Coef cf, uint32_t n_long, const uint32_t *long_list, uint32_t
     __shared__ Coef scf;
     const Coef &lcf = stage_coef(cf, scf);
     if (blockIdx.x < long_blocks) {
+        __shared__ float lds[kWavesPerBlock][128];
         const uint32_t item = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-        if (item < n_long) dual_long_wave(a, lcf, long_list[item], threadIdx.x & 63);
+        if (item < n_long) dual_long_wave(a, lcf, long_list[item], threadIdx.x & 63, lds[threadIdx.x >> 6]);
         return;
     }
     const int64_t base = (int64_t)(blockIdx.x - long_blocks) * (kDualLeaves * kBlk) + threadIdx.x;
@@ -304,6 +362,7 @@ struct PrimalArgs {
     const float *p;
     const uint32_t *off;
     const uint32_t *ent;
+    int64_t n_ent, n_obs;  // entries of the list and of the observation pool (bounds-checked build)
     const uint32_t *obs_off;
     const uint8_t *obs_m, *obs_unit;
     const float *inv, *wtot;
@@ -322,33 +381,40 @@ struct PrimalArgs {
     const float *W;
 };
 
-// Divergence of a leaf with a long - list, one wave: the incoming terms in 64
-// interleaved parts as in dual_long_wave, added to ds in lane order (the same
-// value on every lane).
-__device__ float long_divergence(const PrimalArgs &a, const Coef &cf, int64_t i, int lane) {
-    const uint32_t e0 = a.off[i], ne = a.off[i + 1] - e0;
+// Divergence of a leaf with a long - list, one wave: ds, then the incoming
+// terms fma(-c', p_m, acc) in list order, one chain, chunks staged in LDS as
+// in dual_long_wave (the same value on every lane).
+__device__ float long_divergence(const PrimalArgs &a, const Coef &cf, int64_t i, int lane, float *lds) {
+    float2 *st = reinterpret_cast<float2 *>(lds);
+    uint32_t e0 = a.off[i], e1 = a.off[i + 1];
+    OTF_SEG(e0, e1, a.n_ent);
+    const uint32_t ne = e1 - e0;
     const int ln = a.level[i];
-    float part = 0.0f;
-    for (uint32_t q0 = lane; q0 < ne; q0 += 64 * kLongUnroll) {
+    float acc = a.ds[i];
+    for (uint32_t q0 = 0; q0 < ne; q0 += 64 * kLongUnroll) {
         uint32_t v[kLongUnroll];
         float pm[kLongUnroll];
 #pragma unroll
         for (int r = 0; r < kLongUnroll; ++r) {
-            const uint32_t q = q0 + 64 * r;
+            const uint32_t q = q0 + 64 * r + lane;
             v[r] = a.ent[e0 + (q < ne ? q : 0u)];
         }
 #pragma unroll
         for (int r = 0; r < kLongUnroll; ++r)
-            pm[r] = a.p[q0 + 64 * r < ne ? (int64_t)((v[r] >> kIdxBits) & 3) * a.cap + (v[r] & kIdxMask) : 0];
+            pm[r] = a.p[q0 + 64 * r + lane < ne ? (int64_t)((v[r] >> kIdxBits) & 3) * a.cap + OTF_NB(v[r], a.L) : 0];
 #pragma unroll
         for (int r = 0; r < kLongUnroll; ++r) {
-            const float nx = __fmaf_rn(-cf.cp[v[r] >> (kIdxBits + 2)][ln], pm[r], part);
-            part = q0 + 64 * r < ne ? nx : part;
+            if (q0 + 64 * r >= ne) break;  // uniform
+            const int n = (int)min(64u, ne - (q0 + 64 * r));
+            st[lane] = make_float2(-cf.cp[OTF_LV(v[r])][ln], pm[r]);
+            wave_lds_sync();
+            for (int k = 0; k < n; ++k) {
+                const float2 e = st[k];
+                acc = __fmaf_rn(e.x, e.y, acc);
+            }
+            wave_lds_sync();
         }
     }
-    float acc = a.ds[i];
-#pragma unroll 8
-    for (int j = 0; j < 64; ++j) acc = acc + rdlane(part, j);
     return acc;
 }
 
@@ -356,8 +422,8 @@ __device__ float long_divergence(const PrimalArgs &a, const Coef &cf, int64_t i,
 // a separate launch precedes the tiles: long units inside the persistent
 // blocks would hold their tiles at the block's barriers); u' replaces ds for
 // primal_wave<true>.
-__device__ void primal_long_wave(const PrimalArgs &a, const Coef &cf, int64_t i, int lane) {
-    const float acc = long_divergence(a, cf, i, lane);
+__device__ void primal_long_wave(const PrimalArgs &a, const Coef &cf, int64_t i, int lane, float *lds) {
+    const float acc = long_divergence(a, cf, i, lane, lds);
     if (lane == 0) a.ds[i] = __fmaf_rn(a.tau, acc, a.u_in[i]);
 }
 
@@ -375,10 +441,10 @@ __device__ inline float divergence(const PrimalArgs &a, const Coef &cf, uint32_t
         for (int r = 0; r < kGather; ++r) v[r] = a.ent[e + r < e1 ? e + r : e0];
 #pragma unroll
         for (int r = 0; r < kGather; ++r)
-            pm[r] = a.p[e + r < e1 ? (int64_t)((v[r] >> kIdxBits) & 3) * a.cap + (v[r] & kIdxMask) : 0];
+            pm[r] = a.p[e + r < e1 ? (int64_t)((v[r] >> kIdxBits) & 3) * a.cap + OTF_NB(v[r], a.L) : 0];
 #pragma unroll
         for (int r = 0; r < kGather; ++r) {
-            const float nx = __fmaf_rn(-cf.cp[v[r] >> (kIdxBits + 2)][ln], pm[r], acc);
+            const float nx = __fmaf_rn(-cf.cp[OTF_LV(v[r])][ln], pm[r], acc);
             acc = e + r < e1 ? nx : acc;
         }
     }
@@ -452,7 +518,8 @@ __device__ inline void primal_wave(const PrimalArgs &a, const Coef &cf, int64_t 
         // dependent list loads
         ln = a.level[i];
         un = a.u_in[i];
-        const uint32_t e0 = a.off[i], e1 = a.off[i + 1];
+        uint32_t e0 = a.off[i], e1 = a.off[i + 1];
+        OTF_SEG(e0, e1, a.n_ent);
         const float dsi = a.ds[i];
         M = a.obs_m[i];
         oo = a.obs_off[i];
@@ -481,7 +548,7 @@ __device__ inline void primal_wave(const PrimalArgs &a, const Coef &cf, int64_t 
             const int l = min(l0 + g, 63);
             const int Ml = rdlane_i(M, l);
             const uint32_t ool = (uint32_t)rdlane_i((int)oo, l);
-            const uint32_t e = ool + (lane < Ml ? (uint32_t)lane : 0u);
+            const uint32_t e = OTF_OBS(ool + (lane < Ml ? (uint32_t)lane : 0u), a.n_obs);
             Fr[g] = a.F[e];
             Pr[g] = a.P[e];
         }
@@ -528,16 +595,16 @@ __device__ inline void block_flag_counts(uint32_t n_split, uint32_t n_join, uint
 // The whole primal update of a leaf with a long - list, one wave: its own
 // loads, u' = u + tau div (long_divergence), the prox of its observations
 // (lane k: breakpoint k) and its outputs. The flags are returned on every lane.
-__device__ void primal_long_full(const PrimalArgs &a, const Coef &cf, int64_t i, int lane, bool &split,
+__device__ void primal_long_full(const PrimalArgs &a, const Coef &cf, int64_t i, int lane, float *lds, bool &split,
                                  bool &join) {
     const int ln = a.level[i];
     const float un = a.u_in[i];
     const int M = a.obs_m[i];
     const uint32_t oo = a.obs_off[i];
     const float inv = a.inv[i], wt = a.wtot[i];
-    const uint32_t e = oo + (lane < M ? (uint32_t)lane : 0u);
+    const uint32_t e = OTF_OBS(oo + (lane < M ? (uint32_t)lane : 0u), a.n_obs);
     const float Fk = a.F[e], Pk = a.P[e];
-    const float up = __fmaf_rn(a.tau, long_divergence(a, cf, i, lane), un);
+    const float up = __fmaf_rn(a.tau, long_divergence(a, cf, i, lane, lds), un);
     const float v = wave_prox(Fk, Pk, up, a.tl * inv, wt, M, lane);
     primal_flags(a, v, ln, split, join);
     if (lane == 0) primal_store(a, i, v, un, up, split, join);
@@ -554,10 +621,11 @@ k_primal(PrimalArgs a, Coef cf, uint32_t n_long, const uint32_t *long_list, uint
     const Coef &lcf = stage_coef(cf, scf);
     uint32_t ns = 0, nj = 0;
     if (blockIdx.x < long_blocks) {
+        __shared__ float lds[kWavesPerBlock][128];
         const uint32_t item = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
         if (item < n_long) {
             bool split, join;
-            primal_long_full(a, lcf, long_list[item], threadIdx.x & 63, split, join);
+            primal_long_full(a, lcf, long_list[item], threadIdx.x & 63, lds[threadIdx.x >> 6], split, join);
             ns = split ? 1u : 0u;
             nj = join ? 1u : 0u;
         }
@@ -569,26 +637,30 @@ k_primal(PrimalArgs a, Coef cf, uint32_t n_long, const uint32_t *long_list, uint
 
 // Gradient descent (the paper's solver). Divergence per thread, then the
 // data gradient cooperatively as in k_primal: the wave takes its 64 leaves in
-// turn, lane k loads observation k (coalesced) and forms
-//   t_k = W_k (r_k / sqrt(r_k^2 + eps^2)),  r_k = u - F_k  (0 for k >= M),
-// and a butterfly over the 64 lanes sums them pairwise: (t0 + t1) + (t2 + t3)
-// and so on, the same order as a plain pairwise sum over 64 slots. Then
+// groups of kAhead, lane k loads observation k of each leaf (coalesced) and
+// forms
+//   t_k = W_k (r_k / sqrt(r_k^2 + eps^2)),  r_k = u - F_k  (0 for k >= M);
+// the group's terms go to LDS, one row per leaf, and lane g adds row g in
+// one sequential chain in observation order (the zero terms past M leave the
+// sum unchanged: a chain started at +0 never holds -0). Then
 //   u <- u + xi (lam div - d'),  d' = sum * inv.
 // The divergence is kept (uprime) so that split children take the same step
 // with their own data term.
-// Sum of the 64 lanes' t by a butterfly (the same value on every lane: each
-// step adds two equal pairs, and the addition commutes).
-__device__ inline float butterfly_sum(float t) {
-#pragma unroll
-    for (int sh = 1; sh < 64; sh <<= 1) t = t + __shfl_xor(t, sh, 64);
-    return t;
-}
 
 // Data-gradient term of observation k on lane k (0 at or past M).
 __device__ inline float gd_term(float u, float Fk, float Wk, float eps2, int Ml, int lane) {
     const float r = u - Fk;
     const float den = sqrtf(__fmaf_rn(r, r, eps2));  // > 0: eps > 0
     return lane < Ml ? Wk * (r / den) : 0.0f;
+}
+
+// Sequential sum of the n terms of LDS row `row` (every lane may call it; a
+// lane reads its own row).
+__device__ inline float row_sum(const float *lds, int row, int n) {
+    const float *r = lds + row * kTermPitch;
+    float acc = 0.0f;
+    for (int k = 0; k < n; ++k) acc = acc + r[k];
+    return acc;
 }
 
 // Update, flags and stores of a leaf from its divergence dv and data-gradient
@@ -612,7 +684,8 @@ __device__ inline void gd_store(const PrimalArgs &a, int64_t i, float un, float 
 // The wave's 64 consecutive leaves, as primal_wave; a leaf with a long -
 // list is left to its own wave in the same launch (kept in the loop, not
 // stored).
-__device__ inline void gd_wave(const PrimalArgs &a, const Coef &cf, int64_t i, uint32_t &n_split, uint32_t &n_join) {
+__device__ inline void gd_wave(const PrimalArgs &a, const Coef &cf, int64_t i, float *lds, uint32_t &n_split,
+                               uint32_t &n_join) {
     const int lane = threadIdx.x & 63;
     const bool valid = i < a.L;
     bool own = valid;
@@ -623,7 +696,8 @@ __device__ inline void gd_wave(const PrimalArgs &a, const Coef &cf, int64_t i, u
         // the leaf's own loads first, then the divergence's dependent ones
         ln = a.level[i];
         un = a.u_in[i];
-        const uint32_t e0 = a.off[i], e1 = a.off[i + 1];
+        uint32_t e0 = a.off[i], e1 = a.off[i + 1];
+        OTF_SEG(e0, e1, a.n_ent);
         const float dsi = a.ds[i];
         M = a.obs_m[i];
         oo = a.obs_off[i];
@@ -641,17 +715,24 @@ __device__ inline void gd_wave(const PrimalArgs &a, const Coef &cf, int64_t i, u
             const int l = min(l0 + g, 63);
             const int Ml = rdlane_i(M, l);
             const uint32_t ool = (uint32_t)rdlane_i((int)oo, l);
-            const uint32_t e = ool + (lane < Ml ? (uint32_t)lane : 0u);
+            const uint32_t e = OTF_OBS(ool + (lane < Ml ? (uint32_t)lane : 0u), a.n_obs);
             Fr[g] = a.F[e];
             Wr[g] = a.W[e];
         }
+        int nmax = 0;
 #pragma unroll
         for (int g = 0; g < kAhead; ++g) {
-            const int l = l0 + g;
-            const int lc = min(l, 63);
-            const float t = butterfly_sum(gd_term(rdlane(un, lc), Fr[g], Wr[g], a.eps2, rdlane_i(M, lc), lane));
-            mysum = (lane == l && l < nact) ? t : mysum;
+            const int lc = min(l0 + g, 63);
+            const int Ml = rdlane_i(M, lc);
+            nmax = max(nmax, Ml);
+            lds[g * kTermPitch + lane] = gd_term(rdlane(un, lc), Fr[g], Wr[g], a.eps2, Ml, lane);
         }
+        wave_lds_sync();
+        // lane g < kAhead sums leaf l0 + g; the sums reach their leaves' lanes
+        const float sg = row_sum(lds, lane & (kAhead - 1), nmax);
+        const float mine = __shfl(sg, (lane - l0) & (kAhead - 1), 64);
+        mysum = (lane >= l0 && lane < l0 + kAhead) ? mine : mysum;
+        wave_lds_sync();
     }
     bool split = false, join = false;
     if (own) gd_store(a, i, un, dv, mysum, inv, ln, split, join);
@@ -659,19 +740,24 @@ __device__ inline void gd_wave(const PrimalArgs &a, const Coef &cf, int64_t i, u
     n_join = (uint32_t)__popcll(__ballot(join));
 }
 
-// The whole update of a leaf with a long - list, one wave: its divergence in
-// 64 interleaved parts (long_divergence), the data gradient with lane k on
-// observation k, and its stores. The flags are returned on every lane.
-__device__ void gd_long_full(const PrimalArgs &a, const Coef &cf, int64_t i, int lane, bool &split, bool &join) {
+// The whole update of a leaf with a long - list, one wave: its divergence
+// (long_divergence), the data gradient with lane k on observation k summed
+// in one chain from LDS, and its stores. The flags are returned on every
+// lane.
+__device__ void gd_long_full(const PrimalArgs &a, const Coef &cf, int64_t i, int lane, float *lds, bool &split,
+                             bool &join) {
     const int ln = a.level[i];
     const float un = a.u_in[i];
     const int M = a.obs_m[i];
     const uint32_t oo = a.obs_off[i];
     const float inv = a.inv[i];
-    const uint32_t e = oo + (lane < M ? (uint32_t)lane : 0u);
+    const uint32_t e = OTF_OBS(oo + (lane < M ? (uint32_t)lane : 0u), a.n_obs);
     const float Fk = a.F[e], Wk = a.W[e];
-    const float dv = long_divergence(a, cf, i, lane);
-    const float sum = butterfly_sum(gd_term(un, Fk, Wk, a.eps2, M, lane));
+    const float dv = long_divergence(a, cf, i, lane, lds);
+    lds[lane] = gd_term(un, Fk, Wk, a.eps2, M, lane);
+    wave_lds_sync();
+    const float sum = row_sum(lds, 0, M);
+    wave_lds_sync();
     // the stores on lane 0, the flags (from the same values) on every lane
     const float v = __fmaf_rn(a.xi, __fmaf_rn(a.lam, dv, -(sum * inv)), un);
     const float av = fabsf(v);
@@ -689,18 +775,20 @@ __device__ void gd_long_full(const PrimalArgs &a, const Coef &cf, int64_t i, int
 __global__ void __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(8, 8)))
 k_gd_update(PrimalArgs a, Coef cf_arg, uint32_t n_long, const uint32_t *long_list, uint32_t long_blocks) {
     __shared__ Coef scf;
+    __shared__ float lds[kWavesPerBlock][kStageWords];
     const Coef &cf = stage_coef(cf_arg, scf);
+    float *wl = lds[threadIdx.x >> 6];
     uint32_t ns = 0, nj = 0;
     if (blockIdx.x < long_blocks) {
         const uint32_t item = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
         if (item < n_long) {
             bool split, join;
-            gd_long_full(a, cf, long_list[item], threadIdx.x & 63, split, join);
+            gd_long_full(a, cf, long_list[item], threadIdx.x & 63, wl, split, join);
             ns = split ? 1u : 0u;
             nj = join ? 1u : 0u;
         }
     } else {
-        gd_wave(a, cf, (int64_t)(blockIdx.x - long_blocks) * kBlk + threadIdx.x, ns, nj);
+        gd_wave(a, cf, (int64_t)(blockIdx.x - long_blocks) * kBlk + threadIdx.x, wl, ns, nj);
     }
     block_flag_counts<kBlk>(ns, nj, a.part, a.part_stride, blockIdx.x);
 }
@@ -842,7 +930,9 @@ __global__ void __launch_bounds__(kBlk) k_dual_long_b(const ObjDev *objs, int no
     const uint32_t t = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     if (t >= n) return;
     const int j = find_obj(begin, nobj, t);
-    dual_long_wave(objs[j].d, coefs[objs[j].D], objs[j].heavy_p[t - begin[j]], threadIdx.x & 63);
+    __shared__ float lds[kWavesPerBlock][128];
+    dual_long_wave(objs[j].d, coefs[objs[j].D], objs[j].heavy_p[t - begin[j]], threadIdx.x & 63,
+                   lds[threadIdx.x >> 6]);
 }
 
 __global__ void __launch_bounds__(kBlk) k_primal_long_b(const ObjDev *objs, int nobj, const uint32_t *begin,
@@ -850,7 +940,9 @@ __global__ void __launch_bounds__(kBlk) k_primal_long_b(const ObjDev *objs, int 
     const uint32_t t = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     if (t >= n) return;
     const int j = find_obj(begin, nobj, t);
-    primal_long_wave(objs[j].p, coefs[objs[j].D], objs[j].heavy_m[t - begin[j]], threadIdx.x & 63);
+    __shared__ float lds[kWavesPerBlock][128];
+    primal_long_wave(objs[j].p, coefs[objs[j].D], objs[j].heavy_m[t - begin[j]], threadIdx.x & 63,
+                     lds[threadIdx.x >> 6]);
 }
 
 // Object j's split and join flag counts from its tiles' partials (block j),
@@ -892,7 +984,7 @@ __global__ void __launch_bounds__(kBlk) k_batch_counts(const ObjDev *objs, const
 
 DualArgs dual_args(Ctx &c, float sigma) {
     LeafStore &s = c.lv();
-    return DualArgs{c.L, s.cap, s.level.p, s.ubar.p, s.nbp_off.p, s.nbp.p, s.p.p, s.ds.p, sigma, 0, 0.0f};
+    return DualArgs{c.L, s.cap, s.level.p, s.ubar.p, s.nbp_off.p, s.nbp.p, s.n_nbp, s.p.p, s.ds.p, sigma, 0, 0.0f};
 }
 
 PrimalArgs primal_args(Ctx &c, float tau, float tl) {
@@ -905,6 +997,8 @@ PrimalArgs primal_args(Ctx &c, float tau, float tl) {
     a.p = s.p.p;
     a.off = s.nbm_off.p;
     a.ent = s.nbm.p;
+    a.n_ent = s.n_nbm;
+    a.n_obs = (int64_t)c.op().F.n;  // the allocation: a leaf without observations reads its slot
     a.obs_off = s.obs_off.p;
     a.obs_m = s.obs_m.p;
     a.obs_unit = s.obs_unit.p;
@@ -1038,6 +1132,17 @@ void energy(Ctx &c, double *tv, double *data, double eps) {
     }
     *tv = t;
     *data = d;
+}
+
+uint32_t take_bounds_flag() {
+#ifdef OTF_DEBUG_BOUNDS
+    uint32_t h = 0, z = 0;
+    OTF_HIP(hipMemcpyFromSymbol(&h, HIP_SYMBOL(bounds_flag), sizeof h));
+    if (h) OTF_HIP(hipMemcpyToSymbol(HIP_SYMBOL(bounds_flag), &z, sizeof z));
+    return h;
+#else
+    return 0;
+#endif
 }
 
 BatchState::~BatchState() {

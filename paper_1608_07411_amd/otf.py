@@ -15,6 +15,9 @@ from .synth import CAMERA_DTYPE
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "lib", "libotf.so")
+# the bounds-checked build (OTF_DEBUG_BOUNDS): every adjacency index and
+# observation segment the sweeps read is checked on the device
+BOUNDS_LIB_PATH = os.path.join(HERE, "lib", "libotf_bounds.so")
 
 PARAMS_DTYPE = np.dtype([
     ("max_depth", "<i4"), ("delta", "<f4"), ("eta", "<f4"), ("spread_tau", "<f4"),
@@ -26,7 +29,7 @@ STATUS = {0: "OTF_OK", 1: "OTF_E_INVALID", 2: "OTF_E_NOMEM", 3: "OTF_E_CAPACITY"
           5: "OTF_E_STATE"}
 PROFILE_KINDS = ("dual", "primal", "restructure", "energy")
 
-_lib = None
+_libs: dict = {}
 
 
 class OtfError(RuntimeError):
@@ -35,12 +38,12 @@ class OtfError(RuntimeError):
         self.status = status
 
 
-def lib():
-    """Load libotf.so (raises if it was not built)."""
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            raise OSError(f"libotf.so not found at {LIB_PATH}; build it with paper_1608_07411_amd.build.build()")
+def lib(path: str = LIB_PATH):
+    """Load libotf.so, or another build of it at `path` (raises if it was not built)."""
+    if path not in _libs:
+        if not os.path.exists(path):
+            raise OSError(f"{os.path.basename(path)} not found at {path}; build it with "
+                          f"paper_1608_07411_amd.build.build()")
         # PyTorch, when present, brings its own HIP runtime library: load it
         # first, so that this library binds to the same runtime instead of
         # loading a second one into the process
@@ -48,7 +51,7 @@ def lib():
             import torch  # noqa: F401
         except ImportError:
             pass
-        L = C.CDLL(LIB_PATH)
+        L = C.CDLL(path)
         P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
         sig = {
             "otf_create": [C.c_int, P, P],
@@ -60,6 +63,8 @@ def lib():
             "otf_extract_obs": [P, I64, P, P, P, I64, P, P, P],
             "otf_extract_neighbours": [P, I64, P, I64, P, P],
             "otf_energy": [P, P, P],
+            "otf_debug_fail_allocations": [P, C.c_int64],
+            "otf_debug_corrupt_adjacency": [P, C.c_int64],
             "otf_fuse_gd": [P, I32, C.c_float, C.c_float, C.c_float],
             "otf_dense_field": [P, P, I32, I64],
             "otf_mesh": [P, C.c_float, I64, P, P, P],
@@ -102,8 +107,8 @@ def lib():
         L.otf_mlp_last_error.restype = C.c_char_p
         L.otf_mlp_num_params.argtypes = []
         L.otf_mlp_num_params.restype = I64
-        _lib = L
-    return _lib
+        _libs[path] = L
+    return _libs[path]
 
 
 def _ptr(a):
@@ -132,8 +137,8 @@ def _stream_handle(stream):
 class Context:
     """One fused octree on one GPU (otf_ctx)."""
 
-    def __init__(self, device: int = 0, stream=None):
-        self._lib = lib()
+    def __init__(self, device: int = 0, stream=None, library: str = LIB_PATH):
+        self._lib = lib(library)
         self.h = C.c_void_p()
         self._D = None
         self._check(self._lib.otf_create(device, _stream_handle(stream), C.byref(self.h)), "otf_create")
@@ -370,6 +375,14 @@ class Context:
         self._check(self._lib.otf_energy(self.h, C.byref(tv), C.byref(data)), "otf_energy")
         return tv.value, data.value
 
+    def debug_fail_allocations(self, after: int):
+        """Test hook: the after-th later device allocation on this context fails (0: off)."""
+        self._check(self._lib.otf_debug_fail_allocations(self.h, int(after)), "otf_debug_fail_allocations")
+
+    def debug_corrupt_adjacency(self, leaf: int):
+        """Test hook of the bounds-checked build: point leaf's first + entry past the last leaf."""
+        self._check(self._lib.otf_debug_corrupt_adjacency(self.h, int(leaf)), "otf_debug_corrupt_adjacency")
+
     # profiling --------------------------------------------------------------
     def profile(self, enable: bool = True):
         self._check(self._lib.otf_profile(self.h, 1 if enable else 0), "otf_profile")
@@ -378,11 +391,12 @@ class Context:
         ms = np.zeros(4)
         n = np.zeros(4, np.int64)
         lu = C.c_int64(0)
-        by = np.zeros(2)
+        by = np.zeros(4)
         self._check(self._lib.otf_profile_read(self.h, _ptr(ms), _ptr(n), C.byref(lu), _ptr(by)), "otf_profile_read")
         out = {k: dict(ms=float(ms[i]), launches=int(n[i])) for i, k in enumerate(PROFILE_KINDS)}
         out["leaf_updates"] = lu.value
         out["bytes"] = dict(dual=float(by[0]), primal=float(by[1]))
+        out["method_bytes"] = dict(dual=float(by[2]), primal=float(by[3]))
         return out
 
     def reset_counters(self, profile: bool):

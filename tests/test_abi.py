@@ -32,12 +32,12 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
-def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+def test_binding_fails_loudly_without_library(tmp_path):
     from paper_1608_07411_amd import otf
-    monkeypatch.setattr(otf, "LIB_PATH", str(tmp_path / "missing.so"))
-    monkeypatch.setattr(otf, "_lib", None)
     with pytest.raises(OSError):
-        otf.lib()
+        otf.lib(str(tmp_path / "missing.so"))
+    with pytest.raises(OSError):
+        otf.Context(0, library=str(tmp_path / "missing.so"))
 
 
 def test_record_layouts():

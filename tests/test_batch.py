@@ -130,3 +130,36 @@ def test_batch_errors():
     batch.close()
     torch.cuda.synchronize()
     c.close()
+
+
+def test_batch_at_object_shapes_matches_solo_runs_and_oracle():
+    """The first 12 objects of the 48-object batched workload (spheres of max
+    depth 6-9 with 14-59 views 160x120, split/join every iteration): the
+    autotuner's 9 iterations and 7 eager ones, every member bit for bit
+    against its solo run; the depth-6 member also against the fp32 oracle.
+    Some members' adjacency has lists longer than 64 entries (the long-list
+    waves run)."""
+    ws = synth.batch_workloads(12, restructure_every=1)
+    depths = sorted({w.max_depth for w in ws})
+    assert depths == [6, 7, 8, 9]
+    solo, members = _pair(ws)
+    k6 = next(k for k, w in enumerate(ws) if w.max_depth == 6)
+    o = Oracle("f32").import_state(members[k6].export_state())
+    n_long = 0
+    for c in members:
+        counts, _ = c.extract_neighbours()
+        n_long += int(np.count_nonzero((counts[:, :3].sum(1) > 64) | (counts[:, 3:].sum(1) > 64)))
+    assert n_long > 0
+    batch = otf.Batch(0)
+    for m in members:
+        batch.add(m)
+    for n in (9, 7):
+        for c in solo:
+            c.fuse(n, LAM, TAU32, TAU32)
+        batch.fuse(n, LAM, TAU32, TAU32)
+        o.fuse(n, LAM, TAU32, TAU32)
+        torch.cuda.synchronize()
+        _assert_same(solo, members, f"after {n} more iterations")
+        assert members[k6].export_state() == o.export_state(), "depth-6 member differs from the oracle"
+    assert batch.config()["tuned"]
+    batch.close()

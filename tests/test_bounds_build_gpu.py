@@ -1,0 +1,76 @@
+"""The bounds-checked build (libotf_bounds.so, OTF_DEBUG_BOUNDS): the sweeps
+check every adjacency range, neighbour index, level code and observation
+index they read. On valid states it must report nothing and give the same
+results as the oracle bit for bit (sphere workload with split/join, long
+adjacency lists); an entry pointed past the last leaf from the host (a test
+hook of that build only) must be reported as OTF_E_DEVICE, with the bad read
+sent to index 0 so that every kernel still ends normally. The default build
+refuses the hook."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from paper_1608_07411_amd import synth
+from tests.helpers import TAU32, base_params
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - the GPU suite runs on the MI355X machine
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1608_07411_amd import otf  # noqa: E402
+
+
+def _bounds_ctx():
+    return otf.Context(0, library=otf.BOUNDS_LIB_PATH)
+
+
+def test_bounds_build_reports_nothing_and_matches_oracle():
+    w = synth.sphere_workload(max_depth=5, n_views=4, W=80, H=60, f=75.0)
+    g = _bounds_ctx().build_octree(w.depth, w.cams, w.params)
+    o = Oracle("f32").build(w.depth, w.cams, w.params)
+    for _ in range(3):
+        g.fuse(10, w.lam, w.tau, w.sigma)
+        o.fuse(10, w.lam, w.tau, w.sigma)
+        assert g.export_state() == o.export_state()
+    g.fuse_gd(5, 0.5, 0.05, 0.3)
+    o.fuse_gd(5, 0.5, 0.05, 0.3)
+    assert g.export_state() == o.export_state()
+    g.close()
+    # long lists (thousands of entries): the long-list waves' reads
+    D, G = 6, 64
+    rng = np.random.default_rng(0)
+    f = np.ones((2, G, G, G), np.float32)
+    f[:, :, :, 32:34] = rng.uniform(-1, 1, (2, G, G, 2)).astype(np.float32)
+    o = Oracle("f32").build_volumes(f, np.ones((2, G, G, G), np.uint8), base_params(D))
+    g = _bounds_ctx().import_state(o.export_state())
+    g.fuse(4, 0.5, TAU32, TAU32)
+    o.fuse(4, 0.5, TAU32, TAU32)
+    assert g.export_state() == o.export_state()
+    g.close()
+
+
+def test_bounds_build_reports_a_bad_index():
+    # no restructuring: only the sweeps (which check and redirect) read the
+    # corrupted entry
+    w = synth.sphere_workload(max_depth=5, n_views=4, W=80, H=60, f=75.0, restructure_every=0)
+    g = _bounds_ctx().build_octree(w.depth, w.cams, w.params)
+    g.fuse(2, w.lam, w.tau, w.sigma)
+    counts, _ = g.extract_neighbours()
+    leaf = int(np.nonzero(counts[:, :3].sum(1) > 0)[0][0])
+    g.debug_corrupt_adjacency(leaf)
+    with pytest.raises(otf.OtfError) as e:
+        g.fuse(1, w.lam, w.tau, w.sigma)
+    assert e.value.status == 4 and "bounds-checked" in str(e.value)
+    g.close()
+    # the default build refuses the hook and keeps its state
+    d = otf.Context(0).build_octree(w.depth, w.cams, w.params)
+    before = d.export_state()
+    with pytest.raises(otf.OtfError) as e:
+        d.debug_corrupt_adjacency(leaf)
+    assert e.value.status == 1
+    assert d.export_state() == before
+    d.close()

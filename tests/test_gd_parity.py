@@ -93,3 +93,23 @@ def test_gd_invalid_arguments():
     with pytest.raises(otf.OtfError) as e:
         empty.fuse_gd(1, 0.5, 0.1, 0.1)
     assert e.value.status == 5
+
+
+@pytest.mark.parametrize("D,x0", [(6, 32), (6, 30), (7, 62)])
+def test_gd_long_adjacency_lists_parity(D, x0):
+    """Gradient descent on half-domain leaves against a refined slab: the flux
+    sweep's long + lists and the update's long - lists (thousands of entries,
+    several chunks) in the canonical sequential order."""
+    G = 1 << D
+    rng = np.random.default_rng(1)
+    f = np.ones((2, G, G, G), np.float32)
+    f[:, :, :, x0:x0 + 2] = rng.uniform(-1, 1, (2, G, G, 2)).astype(np.float32)
+    w = np.ones((2, G, G, G), np.uint8)
+    o = Oracle("f32").build_volumes(f, w, base_params(D))
+    counts, _ = o.neighbours()
+    assert max(counts[:, :3].sum(1).max(), counts[:, 3:].sum(1).max()) > 64
+    g = otf.Context(0).import_state(o.export_state())
+    for k in range(3):
+        g.fuse_gd(2, 0.5, 0.05, 0.3)
+        o.fuse_gd(2, 0.5, 0.05, 0.3)
+        assert g.export_state() == o.export_state(), f"after {2 * (k + 1)} steps"

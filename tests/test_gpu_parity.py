@@ -286,17 +286,3 @@ def test_long_adjacency_lists_parity(D, x0):
         o.fuse(2, 0.5, TAU32, TAU32)
         g.fuse(2, 0.5, TAU32, TAU32)
         assert g.export_state() == o.export_state()
-
-
-def test_blocks_workload_parity():
-    """The depth-8 workload of 6 spheres and 4 boxes, 32 views 640x480 with
-    outliers: build and two iterations with split/join, bit for bit."""
-    w = synth.workload(2)
-    g = _ctx().build_octree(w.depth, w.cams, w.params)
-    o = Oracle("f32").build(w.depth, w.cams, w.params)
-    assert g.export_state() == o.export_state()
-    for _ in range(2):
-        g.fuse(1, w.lam, w.tau, w.sigma)
-        o.fuse(1, w.lam, w.tau, w.sigma)
-        assert g.last_counts() == o.last_counts()
-        assert g.export_state() == o.export_state()

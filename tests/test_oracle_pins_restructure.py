@@ -184,3 +184,23 @@ def test_primal_step_with_fractional_weights_is_exact_prox():
         assert abs(pre["u"][i] - u_bf) < 1e-9
         assert abs(pre["ubar"][i] - (2.0 * pre["u"][i] - before["u"][i])) < 1e-12
     assert n_frac > len(x) // 10
+
+
+def test_initial_structure_is_union_of_view_structures():
+    """The fused octree starts as the union of the view octrees: its inner
+    nodes (the proper ancestors of its leaves) are exactly the nodes that some
+    view splits."""
+    D = 5
+    f, w = plane_volumes(3, D, 11, p_unobs=0.2)
+    o = Oracle("f64").build_volumes(f, w, base_params(D))
+    views, leaves = parse_views(o.export_state())
+    split = set()
+    for nodes in views:
+        for n in nodes[nodes["leaf"] == 0]:
+            split.add((int(n["level"]), int(n["key"])))
+    inner = set()
+    for k, lv in zip(leaves["key"].tolist(), leaves["level"].tolist()):
+        for L in range(lv):
+            inner.add((L, k & ~((1 << (3 * (D - L))) - 1)))
+    assert len(split) > 50
+    assert inner == split

@@ -9,6 +9,14 @@ properties that hold at any size.
   the second context yields each leaf's u'. For 4096 sampled leaves the
   oracle's prox of their observations (fetched from the device) at that u'
   must equal the first context's u bit for bit.
+* A cube of the full-size state: after 5 iterations with split and join a
+  level-3 cube (64^3 finest voxels) is cut out of the exported state with
+  every observation mean and weight kept exactly, and re-rooted as its own
+  domain. Its leaves' observations fetched by the oracle from the cut view
+  octrees equal those the GPU fetched at full size; then one iteration with
+  split and join on the GPU and in the fp32 oracle from that state (the
+  dual step, divergence, prox, split/join decisions and the fetch of new
+  leaves) and 5 more, bit for bit.
 * Structure and dual feasibility after iterations with split and join: the
   leaves tile the domain in Morton order, every p has norm at most 1 (up to
   one rounding), and every leaf has |u| >= tau_s or lies at the maximum depth
@@ -19,7 +27,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_1608_07411_amd import synth
+from paper_1608_07411_amd import state, synth
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -95,3 +103,43 @@ def test_full_size_structure_after_split_join(work):
         assert ok.all(), f"{np.count_nonzero(~ok)} leaves below tau_s above max depth"
     assert sum(c.last_counts()) > 0
     c.close()
+
+
+def test_full_size_cube_parity(work):
+    w = work
+    dev = torch.from_numpy(w.depth).cuda()
+    c = otf.Context(0).build_octree(dev, w.cams, w.params)
+    c.fuse(5, w.lam, w.tau, w.sigma)
+    blob = c.export_state()
+    M = c.obs_counts()
+    sub = None
+    for level in (3, 4, 2):
+        try:
+            sub, n, cube = state.crop(blob, level, M=M, min_leaves=20000, max_leaves=400000)
+            break
+        except ValueError:
+            continue
+    assert sub is not None, "no cube can be cut exactly"
+    print(f"level-{level} cube #{cube}: {n} leaves", flush=True)
+    D = w.max_depth
+    keys = state.parse(blob)[2]["key"]
+    idx = np.nonzero((keys.astype(np.int64) >> (3 * (D - level))) == cube)[0]
+    full = c.extract_obs_at(idx)
+    c.close()
+    del blob
+    o = oracle.Oracle("f32").import_state(sub)
+    ob = o.leaf_obs()
+    assert np.array_equal(ob["M"], full["M"])
+    assert np.array_equal(ob["F"], full["F"].astype(np.float64))
+    assert np.array_equal(ob["W"], full["W"].astype(np.float64))
+    assert np.array_equal(ob["inv"], full["inv"].astype(np.float64))
+    g = otf.Context(0).import_state(sub)
+    assert g.export_state() == o.export_state()
+    for it in range(6):
+        g.fuse(1, w.lam, w.tau, w.sigma)
+        o.fuse(1, w.lam, w.tau, w.sigma)
+        assert g.last_counts() == o.last_counts(), f"iteration {it + 1}: split/join counts"
+        if it in (0, 5):
+            assert g.export_state() == o.export_state(), f"state after {it + 1} iterations"
+    print(f"cube: 6 iterations identical, {g.num_leaves()} leaves", flush=True)
+    g.close()
