@@ -257,21 +257,24 @@ __device__ inline void dual_leaves(const DualArgs &a, const Coef &cf, const int6
 
 
 // Leaves whose + list is longer than kLongList, one wave each. The wave loads
-// the list in chunks of 64 entries (coalesced, kLongUnroll chunks in flight
-// per lane), stages each chunk in LDS as (coefficient, operand) pairs and
-// folds it into the sequential chains in list order: every lane runs the
-// same chain on the same LDS words (broadcast reads), so the result is on
-// every lane. The list is sorted by direction, so the entries of direction d
-// in a chunk form one run, found by a ballot.
+// the list in windows of kWin entries (coalesced, kLongUnroll entries per
+// lane), stages each window in LDS as (coefficient, operand) pairs in list
+// order and folds it into the sequential chains: every lane runs the same
+// chain on the same LDS words (broadcast reads), so the result is on every
+// lane. The next window's entries and operands are loaded while the current
+// one is folded. The list is sorted by direction, so the entries of one
+// direction in a window form one run; ballots count them.
 constexpr int kLongUnroll = 4;
+constexpr int kWin = 64 * kLongUnroll;  // list entries staged per window
 constexpr int kWavesPerBlock = kBlk / 64;
+constexpr int kWinWords = 2 * kWin;     // one wave's LDS for a staged window
 
-// LDS of one wave: a staged chunk (64 pairs), or kAhead rows of 64
+// LDS of one wave in k_gd_update: a staged window, or kAhead rows of 64
 // observation terms (row pitch 65 words, so that lane g reading row g
 // touches distinct banks).
 constexpr int kTermPitch = 65;
 constexpr int kStageWords = kAhead * kTermPitch;
-static_assert(kStageWords >= 128, "a chunk of 64 pairs must fit the stage");
+static_assert(kStageWords >= kWinWords, "a staged window must fit the stage");
 
 // LDS writes of a wave's lanes before reads by other lanes of the same wave.
 __device__ inline void wave_lds_sync() {
@@ -280,19 +283,72 @@ __device__ inline void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Run [k0, k1) of a chunk whose lanes hold direction d (mask of the lanes).
-__device__ inline void run_of(uint64_t m, int &k0, int &k1) {
-    k0 = m ? (int)__builtin_ctzll(m) : 0;
-    k1 = k0 + (int)__popcll(m);
-}
-
-// g = fma(c, x, g), C = C + c over the staged pairs [k0, k1), in order.
+// g = fma(c, x, g), C = C + c over the staged pairs [k0, k1), in order; the
+// LDS reads of the next 8 pairs are issued before the current 8 are folded.
 __device__ inline void fold_grad(const float2 *st, int k0, int k1, float &g, float &C) {
-    for (int k = k0; k < k1; ++k) {
+    int k = k0;
+    if (k1 - k >= 8) {
+        float2 e[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) e[r] = st[k + r];
+        for (k += 8; k + 8 <= k1; k += 8) {
+            float2 nx[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) nx[r] = st[k + r];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                g = __fmaf_rn(e[r].x, e[r].y, g);
+                C = C + e[r].x;
+            }
+#pragma unroll
+            for (int r = 0; r < 8; ++r) e[r] = nx[r];
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            g = __fmaf_rn(e[r].x, e[r].y, g);
+            C = C + e[r].x;
+        }
+    }
+    for (; k < k1; ++k) {
         const float2 e = st[k];
         g = __fmaf_rn(e.x, e.y, g);
         C = C + e.x;
     }
+}
+
+// acc = fma(c, x, acc) over the staged pairs [k0, k1), in order (pipelined
+// as fold_grad).
+__device__ inline float fold_chain(const float2 *st, int k0, int k1, float acc) {
+    int k = k0;
+    if (k1 - k >= 8) {
+        float2 e[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) e[r] = st[k + r];
+        for (k += 8; k + 8 <= k1; k += 8) {
+            float2 nx[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) nx[r] = st[k + r];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) acc = __fmaf_rn(e[r].x, e[r].y, acc);
+#pragma unroll
+            for (int r = 0; r < 8; ++r) e[r] = nx[r];
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r) acc = __fmaf_rn(e[r].x, e[r].y, acc);
+    }
+    for (; k < k1; ++k) {
+        const float2 e = st[k];
+        acc = __fmaf_rn(e.x, e.y, acc);
+    }
+    return acc;
+}
+
+// Positions [lo, hi) of a staged window whose direction runs are [0, n0),
+// [n0, n01) and [n01, ...): each part folded into its direction's chains.
+__device__ inline void fold_runs(const float2 *st, int n0, int n01, int lo, int hi, float (&g)[3], float (&C)[3]) {
+    fold_grad(st, lo, min(hi, n0), g[0], C[0]);
+    fold_grad(st, max(lo, n0), min(hi, n01), g[1], C[1]);
+    fold_grad(st, max(lo, n01), hi, g[2], C[2]);
 }
 
 __device__ void dual_long_wave(const DualArgs &a, const Coef &cf, int64_t i, int lane, float *lds) {
@@ -303,32 +359,42 @@ __device__ void dual_long_wave(const DualArgs &a, const Coef &cf, int64_t i, int
     const int ln = a.level[i];
     const float ub = a.ubar[i];
     float g[3] = {0.0f, 0.0f, 0.0f}, C[3] = {0.0f, 0.0f, 0.0f};
-    for (uint32_t q0 = 0; q0 < ne; q0 += 64 * kLongUnroll) {
-        uint32_t v[kLongUnroll];
-        float u[kLongUnroll];
+    uint32_t v[kLongUnroll];
+    float u[kLongUnroll];
+#pragma unroll
+    for (int r = 0; r < kLongUnroll; ++r) {
+        const uint32_t q = 64 * r + lane;
+        v[r] = a.ent[e0 + (q < ne ? q : 0u)];
+    }
+#pragma unroll
+    for (int r = 0; r < kLongUnroll; ++r) u[r] = a.ubar[64 * r + lane < ne ? OTF_NB(v[r], a.L) : 0u];
+    for (uint32_t q0 = 0; q0 < ne; q0 += kWin) {
+        // stage the window in list order; count its x and y entries
+        int n0 = 0, n1 = 0;
 #pragma unroll
         for (int r = 0; r < kLongUnroll; ++r) {
-            const uint32_t q = q0 + 64 * r + lane;
-            v[r] = a.ent[e0 + (q < ne ? q : 0u)];
-        }
-#pragma unroll
-        for (int r = 0; r < kLongUnroll; ++r) u[r] = a.ubar[q0 + 64 * r + lane < ne ? OTF_NB(v[r], a.L) : 0u];
-#pragma unroll
-        for (int r = 0; r < kLongUnroll; ++r) {
-            if (q0 + 64 * r >= ne) break;  // uniform
             const int d = q0 + 64 * r + lane < ne ? (int)((v[r] >> kIdxBits) & 3) : 3;
-            const uint64_t m0 = __ballot(d == 0), m1 = __ballot(d == 1), m2 = __ballot(d == 2);
-            st[lane] = make_float2(cf.c[ln][OTF_LV(v[r])], u[r] - ub);
-            wave_lds_sync();
-            int k0, k1;
-            run_of(m0, k0, k1);
-            fold_grad(st, k0, k1, g[0], C[0]);
-            run_of(m1, k0, k1);
-            fold_grad(st, k0, k1, g[1], C[1]);
-            run_of(m2, k0, k1);
-            fold_grad(st, k0, k1, g[2], C[2]);
-            wave_lds_sync();
+            n0 += (int)__popcll(__ballot(d == 0));
+            n1 += (int)__popcll(__ballot(d == 1));
+            st[64 * r + lane] = make_float2(cf.c[ln][OTF_LV(v[r])], u[r] - ub);
         }
+        const int nw = (int)min((uint32_t)kWin, ne - q0);
+        const uint32_t q1 = q0 + kWin;
+        if (q1 < ne) {  // the next window's entries (uniform)
+#pragma unroll
+            for (int r = 0; r < kLongUnroll; ++r) {
+                const uint32_t q = q1 + 64 * r + lane;
+                v[r] = a.ent[e0 + (q < ne ? q : 0u)];
+            }
+        }
+        wave_lds_sync();
+        fold_runs(st, n0, n0 + n1, 0, nw / 2, g, C);
+        if (q1 < ne) {  // and their neighbours' ubar
+#pragma unroll
+            for (int r = 0; r < kLongUnroll; ++r) u[r] = a.ubar[q1 + 64 * r + lane < ne ? OTF_NB(v[r], a.L) : 0u];
+        }
+        fold_runs(st, n0, n0 + n1, nw / 2, nw, g, C);
+        wave_lds_sync();
     }
     if (lane == 0) dual_finish(a, i, g[0], g[1], g[2], C[0], C[1], C[2]);
 }
@@ -343,7 +409,7 @@ k_dual(DualArgs a, Coef cf, uint32_t n_long, const uint32_t *long_list, uint32_t
     __shared__ Coef scf;
     const Coef &lcf = stage_coef(cf, scf);
     if (blockIdx.x < long_blocks) {
-        __shared__ float lds[kWavesPerBlock][128];
+        __shared__ float lds[kWavesPerBlock][kWinWords];
         const uint32_t item = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
         if (item < n_long) dual_long_wave(a, lcf, long_list[item], threadIdx.x & 63, lds[threadIdx.x >> 6]);
         return;
@@ -382,8 +448,8 @@ struct PrimalArgs {
 };
 
 // Divergence of a leaf with a long - list, one wave: ds, then the incoming
-// terms fma(-c', p_m, acc) in list order, one chain, chunks staged in LDS as
-// in dual_long_wave (the same value on every lane).
+// terms fma(-c', p_m, acc) in list order, one chain over LDS-staged windows
+// as in dual_long_wave (the same value on every lane).
 __device__ float long_divergence(const PrimalArgs &a, const Coef &cf, int64_t i, int lane, float *lds) {
     float2 *st = reinterpret_cast<float2 *>(lds);
     uint32_t e0 = a.off[i], e1 = a.off[i + 1];
@@ -391,29 +457,38 @@ __device__ float long_divergence(const PrimalArgs &a, const Coef &cf, int64_t i,
     const uint32_t ne = e1 - e0;
     const int ln = a.level[i];
     float acc = a.ds[i];
-    for (uint32_t q0 = 0; q0 < ne; q0 += 64 * kLongUnroll) {
-        uint32_t v[kLongUnroll];
-        float pm[kLongUnroll];
+    uint32_t v[kLongUnroll];
+    float pm[kLongUnroll];
 #pragma unroll
-        for (int r = 0; r < kLongUnroll; ++r) {
-            const uint32_t q = q0 + 64 * r + lane;
-            v[r] = a.ent[e0 + (q < ne ? q : 0u)];
-        }
+    for (int r = 0; r < kLongUnroll; ++r) {
+        const uint32_t q = 64 * r + lane;
+        v[r] = a.ent[e0 + (q < ne ? q : 0u)];
+    }
 #pragma unroll
-        for (int r = 0; r < kLongUnroll; ++r)
-            pm[r] = a.p[q0 + 64 * r + lane < ne ? (int64_t)((v[r] >> kIdxBits) & 3) * a.cap + OTF_NB(v[r], a.L) : 0];
+    for (int r = 0; r < kLongUnroll; ++r)
+        pm[r] = a.p[64 * r + lane < ne ? (int64_t)((v[r] >> kIdxBits) & 3) * a.cap + OTF_NB(v[r], a.L) : 0];
+    for (uint32_t q0 = 0; q0 < ne; q0 += kWin) {
 #pragma unroll
-        for (int r = 0; r < kLongUnroll; ++r) {
-            if (q0 + 64 * r >= ne) break;  // uniform
-            const int n = (int)min(64u, ne - (q0 + 64 * r));
-            st[lane] = make_float2(-cf.cp[OTF_LV(v[r])][ln], pm[r]);
-            wave_lds_sync();
-            for (int k = 0; k < n; ++k) {
-                const float2 e = st[k];
-                acc = __fmaf_rn(e.x, e.y, acc);
+        for (int r = 0; r < kLongUnroll; ++r) st[64 * r + lane] = make_float2(-cf.cp[OTF_LV(v[r])][ln], pm[r]);
+        const int nw = (int)min((uint32_t)kWin, ne - q0);
+        const uint32_t q1 = q0 + kWin;
+        if (q1 < ne) {  // the next window's entries (uniform)
+#pragma unroll
+            for (int r = 0; r < kLongUnroll; ++r) {
+                const uint32_t q = q1 + 64 * r + lane;
+                v[r] = a.ent[e0 + (q < ne ? q : 0u)];
             }
-            wave_lds_sync();
         }
+        wave_lds_sync();
+        acc = fold_chain(st, 0, nw / 2, acc);
+        if (q1 < ne) {  // and their p
+#pragma unroll
+            for (int r = 0; r < kLongUnroll; ++r)
+                pm[r] = a.p[q1 + 64 * r + lane < ne ? (int64_t)((v[r] >> kIdxBits) & 3) * a.cap + OTF_NB(v[r], a.L)
+                                                   : 0];
+        }
+        acc = fold_chain(st, nw / 2, nw, acc);
+        wave_lds_sync();
     }
     return acc;
 }
@@ -621,7 +696,7 @@ k_primal(PrimalArgs a, Coef cf, uint32_t n_long, const uint32_t *long_list, uint
     const Coef &lcf = stage_coef(cf, scf);
     uint32_t ns = 0, nj = 0;
     if (blockIdx.x < long_blocks) {
-        __shared__ float lds[kWavesPerBlock][128];
+        __shared__ float lds[kWavesPerBlock][kWinWords];
         const uint32_t item = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
         if (item < n_long) {
             bool split, join;
@@ -930,7 +1005,7 @@ __global__ void __launch_bounds__(kBlk) k_dual_long_b(const ObjDev *objs, int no
     const uint32_t t = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     if (t >= n) return;
     const int j = find_obj(begin, nobj, t);
-    __shared__ float lds[kWavesPerBlock][128];
+    __shared__ float lds[kWavesPerBlock][kWinWords];
     dual_long_wave(objs[j].d, coefs[objs[j].D], objs[j].heavy_p[t - begin[j]], threadIdx.x & 63,
                    lds[threadIdx.x >> 6]);
 }
@@ -940,7 +1015,7 @@ __global__ void __launch_bounds__(kBlk) k_primal_long_b(const ObjDev *objs, int 
     const uint32_t t = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     if (t >= n) return;
     const int j = find_obj(begin, nobj, t);
-    __shared__ float lds[kWavesPerBlock][128];
+    __shared__ float lds[kWavesPerBlock][kWinWords];
     primal_long_wave(objs[j].p, coefs[objs[j].D], objs[j].heavy_m[t - begin[j]], threadIdx.x & 63,
                      lds[threadIdx.x >> 6]);
 }

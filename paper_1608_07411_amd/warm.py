@@ -77,32 +77,37 @@ def energy(c, lam: float) -> float:
     return tv + lam * data
 
 
-def time_to_tolerance(c, w, e_target: float, max_iter: int, chunk: int = 10, warm_net=None,
-                      alphas=(1.0, 0.5, 0.25)):
-    """Iterations, solver seconds (warm start included) and the warm start's
-    step until E <= e_target, checking every `chunk` iterations. The warm
-    start is guarded by the energy: the network's prediction is kept at the
-    step (alphas, or none) that lowers the energy most."""
-    import torch
-
-    torch.cuda.synchronize()
-    t = 0.0
+def iterations_to_tolerance(c, w, e_target: float, max_iter: int, warm_net=None, alphas=(1.0, 0.5, 0.25)):
+    """Iterations until E <= e_target, the energy checked after every
+    iteration (not timed), from the plain start or the guarded warm start (the
+    network's prediction kept at the step, alphas or none, that lowers the
+    energy most). Returns (iterations, reached, alpha)."""
     alpha = None
     if warm_net is not None:
-        t0 = time.perf_counter()
         alpha, _ = c.warm_start_guarded(warm_net, w.lam, alphas)
-        torch.cuda.synchronize()
-        t += time.perf_counter() - t0
-    it = 0
-    while it < max_iter:
-        t0 = time.perf_counter()
-        c.fuse(chunk, w.lam, w.tau, w.sigma)
-        torch.cuda.synchronize()
-        t += time.perf_counter() - t0
-        it += chunk
+    for it in range(1, max_iter + 1):
+        c.fuse(1, w.lam, w.tau, w.sigma)
         if energy(c, w.lam) <= e_target:
-            return it, t, True, alpha
-    return it, t, False, alpha
+            return it, True, alpha
+    return max_iter, False, alpha
+
+
+def timed_solve(depth, w, iterations: int, warm_net=None, alphas=(1.0, 0.5, 0.25)) -> float:
+    """Seconds of the solver from a fresh build (not timed): the guarded warm
+    start (if a network is given) and `iterations` iterations, no energy
+    checks in between."""
+    import torch
+
+    c = otf.Context(0).build_octree(depth, w.cams, w.params)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if warm_net is not None:
+        c.warm_start_guarded(warm_net, w.lam, alphas)
+    c.fuse(iterations, w.lam, w.tau, w.sigma)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    c.close()
+    return t
 
 
 def distance_to_solution(net, scenes, iterations: int):
@@ -128,6 +133,11 @@ def distance_to_solution(net, scenes, iterations: int):
 
 
 def evaluate(net, scenes, ref_iterations: int, tol: float = 1e-4, log=print):
+    """Per scene: E_ref, the plain solver's energy after ref_iterations; then,
+    from the plain start and from the guarded warm start, the iterations until
+    E <= E_ref (1 + tol) (the energy checked after every iteration) and the
+    seconds of a separate run of exactly that many iterations (warm start
+    included, no energy checks)."""
     import torch
 
     out = []
@@ -140,22 +150,19 @@ def evaluate(net, scenes, ref_iterations: int, tol: float = 1e-4, log=print):
         leaves = ref.num_leaves()
         ref.close()
         target = e_ref * (1.0 + tol)
-        res = {"scene": w.name, "leaves": leaves, "E_start": e0, "E_ref": e_ref, "ref_iterations": ref_iterations}
+        res = {"scene": w.name, "leaves_at_end": leaves, "E_start": e0, "E_ref": e_ref,
+               "ref_iterations": ref_iterations}
         for name, nn in (("plain", None), ("warm", net)):
             c = otf.Context(0).build_octree(depth, w.cams, w.params)
-            if nn is not None:
-                e_w = None
-            it, t, ok, alpha = time_to_tolerance(c, w, target, 3 * ref_iterations, warm_net=nn)
-            res[name] = {"iterations": it, "seconds": t, "reached": ok}
+            it, ok, alpha = iterations_to_tolerance(c, w, target, 3 * ref_iterations, warm_net=nn)
+            c.close()
+            res[name] = {"iterations": it, "reached": ok, "seconds": timed_solve(depth, w, it, warm_net=nn)}
             if nn is not None:
                 res[name]["alpha"] = alpha
-            if nn is not None:
                 c2 = otf.Context(0).build_octree(depth, w.cams, w.params)
-                c2.warm_start(nn)
-                e_w = energy(c2, w.lam)
+                res[name]["E_after_warm_start"] = (c2.warm_start_guarded(nn, w.lam)[1])
                 c2.close()
-                res[name]["E_after_warm_start"] = e_w
-            c.close()
+        res["speedup"] = res["plain"]["seconds"] / res["warm"]["seconds"]
         log(f"[warm] {w.name}: {res}")
         out.append(res)
     return out

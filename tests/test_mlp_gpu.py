@@ -28,32 +28,95 @@ def _data(rows, seed):
     return X, T
 
 
-def test_forward_matches_oracle():
+def _hidden_outputs(theta, X, layer):
+    """The GPU's hidden activations of `layer` (1..3), exactly: the layers
+    after it pass their input through (identity weights, zero bias: one exact
+    product per sum, and ReLU and bf16 leave a non-negative bf16 value
+    unchanged) and the output layer selects 4 units at a time."""
+    sizes = om.SIZES
+    parts = om.unpack(theta)
+    Xd = torch.from_numpy(X).cuda()
     net = otf.Mlp(0)
+    H = np.zeros((X.shape[0], sizes[layer]), np.float64)
+    for s0 in range(0, sizes[layer], 4):
+        vec = []
+        for li, (W, b) in enumerate(parts):
+            if li < layer:
+                vec += [W.ravel(), b]
+            elif li < len(parts) - 1:
+                vec += [np.eye(sizes[li], dtype=np.float32).ravel(), np.zeros(sizes[li + 1], np.float32)]
+            else:
+                sel = np.zeros((sizes[li], 4), np.float32)
+                sel[np.arange(s0, s0 + 4), np.arange(4)] = 1.0
+                vec += [sel.ravel(), np.zeros(4, np.float32)]
+        net.set_params(np.concatenate(vec).astype(np.float32))
+        H[:, s0:s0 + 4] = net.forward(Xd).cpu().numpy()
+    net.close()
+    return H
+
+
+def _device_layers(theta, X):
+    """bf16(X), the GPU's three hidden activations and its outputs."""
+    net = otf.Mlp(0)
+    net.set_params(theta)
+    Y = net.forward(torch.from_numpy(X).cuda()).cpu().numpy()
+    net.close()
+    return [om.bf16(X).astype(np.float64)] + [_hidden_outputs(theta, X, l) for l in (1, 2, 3)], Y
+
+
+def test_forward_matches_oracle_per_element():
+    """Layer by layer from the GPU's own inputs to that layer: every hidden
+    activation lies in the interval of bf16 values that a sum of the same
+    fp32 products in any order can round to (per element), and every output
+    within that sum's rounding bound; the two sides differ only where the
+    order of the fp32 sum decides a bf16 rounding."""
     theta = om.init_params(5)
+    net = otf.Mlp(0)
     net.set_params(theta)
     assert np.array_equal(net.get_params(), theta)
+    net.close()
+    parts = om.unpack(theta)
     for rows in (1, 17, 1000):
         X, _ = _data(rows, rows)
-        Y = net.forward(torch.from_numpy(X).cuda()).cpu().numpy()
+        acts, Y = _device_layers(theta, X)
+        flips = 0
+        for li in range(3):
+            v, lo, hi = om.layer_interval(acts[li], *parts[li], hidden=True)
+            dev = acts[li + 1]
+            assert np.all((dev >= lo) & (dev <= hi)), (rows, li)
+            flips += int(np.count_nonzero(dev != v))
+        z, lo, hi = om.layer_interval(acts[3], *parts[3], hidden=False)
+        Y = Y.astype(np.float64)
+        assert np.all((Y >= lo) & (Y <= hi)), rows
         R, _ = om.forward(theta, X)
-        assert np.max(np.abs(Y - R)) <= 2e-2 * (1.0 + np.max(np.abs(R))), rows
+        print(f"{rows} rows: {flips} hidden values differ in their bf16 rounding; outputs within "
+              f"{np.max(np.abs(Y - z)):.3g} of the oracle given the same inputs (bound {np.max(hi - z):.3g}), "
+              f"{np.max(np.abs(Y - R)):.3g} from the oracle's own forward", flush=True)
 
 
-def test_gradient_matches_oracle():
-    net = otf.Mlp(0)
+def test_gradient_matches_oracle_per_element():
+    """Every gradient element within its own bound: from the GPU's activations
+    and outputs, the oracle forms the device's dZ exactly, and bounds each
+    product sum over the rows and each bf16 rounding of the backward pass
+    (per element, tight where no rounding is in doubt)."""
     theta = om.init_params(7)
-    net.set_params(theta)
     X, T = _data(6000, 1)  # long enough for the split reduction over rows
+    acts, Y = _device_layers(theta, X)
+    net = otf.Mlp(0)
+    net.set_params(theta)
     loss, g = net.gradient(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda())
-    rl, rg = om.loss_and_grad(theta, X, T)
-    assert abs(loss - rl) <= 1e-2 * rl
-    at = 0
-    for a, b in zip(om.SIZES[:-1], om.SIZES[1:]):
-        for n in (a * b, b):
-            seg, ref = g[at:at + n], rg[at:at + n]
-            assert np.max(np.abs(seg - ref)) <= 3e-2 * np.max(np.abs(ref)) + 1e-6, (a, b, n)
-            at += n
+    net.close()
+    want, bound = om.grad_bound(theta, X, T, acts=acts, Y=Y)
+    dev = np.abs(g.astype(np.float64) - want)
+    assert np.all(dev <= bound), np.argmax(dev - bound)
+    rel = np.median(bound / np.maximum(np.abs(want), 1e-12))
+    ratio = np.max(np.where(bound > 0, dev / np.where(bound > 0, bound, 1.0), 0.0))
+    print(f"gradient: max deviation {dev.max():.3g}, max deviation / bound {ratio:.3g}, "
+          f"median bound / |gradient| {rel:.3g}", flush=True)
+    assert rel < 1e-2
+    # the loss from the GPU's own outputs: fp32 differences, squares summed in double
+    d = (Y.astype(np.float32) - T.astype(np.float32)).astype(np.float64)
+    assert abs(loss - np.mean(d * d)) <= 1e-12 * loss
 
 
 def test_training_lowers_the_loss():
