@@ -149,6 +149,17 @@ otf_status otf_extract_neighbours(const otf_ctx *ctx, int64_t cap_leaves, int32_
  * E = tv + lambda * data. Accumulated in double. */
 otf_status otf_energy(otf_ctx *ctx, double *tv, double *data);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the energy
+ * of otf_energy, bit for bit, computed without any allocation. Its block
+ * partial sums and totals live in a static device array of the library
+ * (4 MiB per device, held until the process ends; enough for the 2^26-leaf
+ * limit). Every call on one device shares that array, so calls that overlap
+ * on one device race; no call leaves anything in it that a later call reads.
+ * Errors: OTF_E_INVALID (null), OTF_E_STATE (no state), OTF_E_CAPACITY (more
+ * leaves than the array holds), OTF_E_DEVICE. */
+otf_status otf_energy_noalloc(otf_ctx *ctx, double *tv, double *data);
+
 /* Splits and joins made by the last restructuring step of the last fuse. */
 otf_status otf_last_counts(const otf_ctx *ctx, int64_t *splits, int64_t *joins);
 

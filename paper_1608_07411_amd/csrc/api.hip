@@ -763,6 +763,12 @@ otf_status otf_debug_fail_allocations(otf_ctx *ctx, int64_t after) {
     return OTF_OK;
 }
 
+otf_status otf_energy_noalloc(otf_ctx *ctx, double *tv, double *data) {
+    if (!ctx || !tv || !data) return OTF_E_INVALID;
+    if (!ctx->c.valid) return OTF_E_STATE;
+    return guard(ctx, false, [&] { energy_noalloc(ctx->c, tv, data); });
+}
+
 otf_status otf_energy_eps(otf_ctx *ctx, double epsilon, double *tv, double *data) {
     if (!ctx || !tv || !data || !std::isfinite(epsilon) || !(epsilon > 0.0)) return OTF_E_INVALID;
     if (!ctx->c.valid) return OTF_E_STATE;

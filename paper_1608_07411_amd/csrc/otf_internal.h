@@ -531,6 +531,8 @@ int64_t marching_cubes(Ctx &c, float iso, int64_t cap, float *h_xyz, unsigned lo
 double quantisation_error(Ctx &c, const float *dense_dev);
 // energy terms in double; eps > 0: the smoothed terms of the gradient-descent energy
 void energy(Ctx &c, double *tv, double *data, double eps = 0.0);
+// energy() without device allocation: partials in a static device array
+void energy_noalloc(Ctx &c, double *tv, double *data);
 // split / join; returns true when the structure changed
 bool restructure(Ctx &c, float tl);
 

@@ -17,6 +17,8 @@
 // and every sum is one sequential chain: over a + or - list in list order (x,
 // y, z neighbours, each in ascending key), however long the list; over a
 // leaf's observations in (F, view) order.
+#include <mutex>
+
 #include "otf_internal.h"
 
 namespace otf {
@@ -1207,6 +1209,69 @@ void energy(Ctx &c, double *tv, double *data, double eps) {
     }
     *tv = t;
     *data = d;
+}
+
+// ------------------------------------------- energy without allocation
+// For callers that cannot allocate device memory (graph capture, serving
+// loops): the block partial sums and the two totals live in a static device
+// array of the library instead of context scratch. Each device holds its own
+// copy until the process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns on that device (the array's name on the host is
+// a stand-in, not a device address). Calls on one device share the array:
+// overlapping calls race.
+constexpr int64_t kEnergyScratchBlocks = kLeafLimit / kBlk;  // 2^26 leaves at most
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double energy_scratch[2 * kEnergyScratchBlocks + 2];
+
+namespace {
+// Totals of the partials in block order, the same order as the host sum of
+// energy(), so the result is bit-identical.
+__global__ void k_energy_total(const double *partial, int64_t blocks, double *out) {
+    if (threadIdx.x != 0) return;
+    double t = 0.0, d = 0.0;
+    for (int64_t b = 0; b < blocks; ++b) {
+        t += partial[2 * b];
+        d += partial[2 * b + 1];
+    }
+    out[0] = t;
+    out[1] = d;
+}
+
+std::mutex g_energy_scratch_mu;
+double *g_energy_scratch[kMaxDevices] = {};
+
+// The array's device address on the current device, looked up once per device.
+double *energy_scratch_on(int device) {
+    if (device < 0 || device >= kMaxDevices) fail(OTF_E_INVALID, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_energy_scratch_mu);
+    if (!g_energy_scratch[device]) {
+        void *p = nullptr;
+        OTF_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(energy_scratch)));
+        g_energy_scratch[device] = static_cast<double *>(p);
+    }
+    return g_energy_scratch[device];
+}
+}  // namespace
+
+void energy_noalloc(Ctx &c, double *tv, double *data) {
+    const int64_t blocks = cdiv(c.L, kBlk);
+    if (blocks > kEnergyScratchBlocks) fail(OTF_E_CAPACITY, "more leaves than the static energy scratch holds (2^26)");
+    double *scr = energy_scratch_on(c.device);
+    double h[2] = {0.0, 0.0};
+    if (blocks > 0) {
+        LeafStore &s = c.lv();
+        hipLaunchKernelGGL(k_energy, dim3((unsigned)blocks), dim3(kBlk), 0, c.stream, c.L, c.prm.max_depth,
+                           s.level.p, s.u.p, s.nbp_off.p, s.nbp.p, s.obs_off.p, s.obs_m.p, s.inv.p, c.op().F.p,
+                           c.op().W.p, c.coef, 0.0, scr);
+        OTF_LAUNCH_CHECK("k_energy");
+        hipLaunchKernelGGL(k_energy_total, dim3(1), dim3(64), 0, c.stream, (const double *)scr, blocks,
+                           scr + 2 * kEnergyScratchBlocks);
+        OTF_LAUNCH_CHECK("k_energy_total");
+        OTF_HIP(hipMemcpyAsync(h, scr + 2 * kEnergyScratchBlocks, sizeof h, hipMemcpyDeviceToHost, c.stream));
+        OTF_HIP(hipStreamSynchronize(c.stream));
+    }
+    *tv = h[0];
+    *data = h[1];
 }
 
 uint32_t take_bounds_flag() {

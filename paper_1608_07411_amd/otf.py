@@ -63,6 +63,7 @@ def lib(path: str = LIB_PATH):
             "otf_extract_obs": [P, I64, P, P, P, I64, P, P, P],
             "otf_extract_neighbours": [P, I64, P, I64, P, P],
             "otf_energy": [P, P, P],
+            "otf_energy_noalloc": [P, P, P],
             "otf_debug_fail_allocations": [P, C.c_int64],
             "otf_debug_corrupt_adjacency": [P, C.c_int64],
             "otf_fuse_gd": [P, I32, C.c_float, C.c_float, C.c_float],
@@ -382,6 +383,12 @@ class Context:
     def debug_corrupt_adjacency(self, leaf: int):
         """Test hook of the bounds-checked build: point leaf's first + entry past the last leaf."""
         self._check(self._lib.otf_debug_corrupt_adjacency(self.h, int(leaf)), "otf_debug_corrupt_adjacency")
+
+    def energy_noalloc(self):
+        """otf_energy without device allocation (static library scratch)."""
+        tv, data = C.c_double(0), C.c_double(0)
+        self._check(self._lib.otf_energy_noalloc(self.h, C.byref(tv), C.byref(data)), "otf_energy_noalloc")
+        return tv.value, data.value
 
     # profiling --------------------------------------------------------------
     def profile(self, enable: bool = True):

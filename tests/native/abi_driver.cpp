@@ -44,6 +44,7 @@ int main() {
     INVALID(otf_extract_neighbours(nullptr, 0, nullptr, 0, nullptr, nullptr));
     INVALID(otf_obs_pool_stats(nullptr, &n, &n, &n));
     INVALID(otf_energy(nullptr, &d0, &d1));
+    INVALID(otf_energy_noalloc(nullptr, &d0, &d1));
     INVALID(otf_energy_eps(nullptr, 0.3, &d0, &d1));
     INVALID(otf_export_state(nullptr, nullptr, 0, &n));
     INVALID(otf_import_state(nullptr, &f, 4));
