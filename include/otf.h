@@ -19,11 +19,18 @@
  *     read or written during the call; pointers marked "device" are device
  *     memory on the context's device, owned by the caller;
  *   - the context owns every device buffer it allocates and frees them in
- *     otf_destroy; all device work is issued on the stream given at creation;
+ *     otf_destroy; device work is issued on the stream given at creation,
+ *     except that a restructuring step (otf_fuse, otf_fuse_gd with split/join)
+ *     runs its new leaves' observation fetch on a second stream that the
+ *     context creates (default priority) and joins back into the given stream
+ *     with an event before anything reads the result; every entry point
+ *     returns after its work on both streams has finished;
  *   - after a failure other than OTF_E_INVALID the fused state is unspecified
  *     and OTF_E_STATE is returned by fuse/extract/energy/export until the next
  *     successful build or import; the context can always be destroyed;
- *   - one context per host thread; contexts share no mutable state.
+ *   - one context per host thread; contexts share no mutable state;
+ *   - a context that is a member of a batch (below) refuses otf_fuse,
+ *     otf_fuse_gd, otf_build_octree and otf_import_state with OTF_E_STATE.
  *
  * Geometry: the reconstruction domain is the unit cube [0,1]^3 split into
  * G^3 finest voxels, G = 2^max_depth. A leaf at level L has side
@@ -73,7 +80,7 @@ typedef struct {
     float split_tau, join_tau; /* tau_s, tau_j of the split and join rules (Sec. 3.2); split_tau <= join_tau;
                                   split_tau = 0 never splits, join_tau > 1 never joins (Sec. 4.2) */
     int32_t restructure_every; /* restructure after iteration t when t % restructure_every == 0; 0 = never */
-    int64_t max_leaves;        /* leaf capacity limit; 0 = no limit beyond device memory */
+    int64_t max_leaves;        /* leaf capacity limit; 0 = none below the 2^26 index limit and device memory */
 } otf_params;
 
 /* Create a context on HIP device `device`. `hip_stream` is a hipStream_t
@@ -356,10 +363,12 @@ otf_status otf_energy_eps(otf_ctx *ctx, double epsilon, double *tv, double *data
  * observations and split/join parameters, and a batch iteration performs one
  * iteration of every member, with results bit-identical to otf_fuse on each
  * member alone. Members must have been created with the batch's device and
- * stream and hold a built or imported octree; the caller keeps them alive,
- * does not call otf_fuse, otf_build_octree or otf_import_state on them while
- * they are members, and destroys the batch before them. Inspection calls
- * (otf_extract, otf_energy, ...) on members are allowed between batch calls.
+ * stream and hold a built or imported octree. While a context is a member,
+ * otf_fuse, otf_fuse_gd, otf_build_octree and otf_import_state on it return
+ * OTF_E_STATE (the batch holds its store pointers); destroying a member
+ * removes it from its batches, and destroying a batch releases its members.
+ * Inspection calls (otf_extract, otf_energy, ...) on members are allowed
+ * between batch calls.
  *
  * The first iterations of a batch double as an autotuner: each runs the
  * sweeps with another launch shape (threads per block and persistent grid

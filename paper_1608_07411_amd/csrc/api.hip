@@ -346,6 +346,7 @@ otf_status otf_destroy(otf_ctx *ctx) {
     if (!ctx) return OTF_E_INVALID;
     (void)hipSetDevice(ctx->c.device);
     (void)hipStreamSynchronize(ctx->c.stream);
+    for (otf_batch *bt : std::vector<otf_batch *>(ctx->c.batches)) batch_forget(bt, &ctx->c);
     if (ctx->c.side) {
         (void)hipStreamSynchronize(ctx->c.side);
         (void)hipStreamDestroy(ctx->c.side);
@@ -360,9 +361,18 @@ otf_status otf_destroy(otf_ctx *ctx) {
 
 const char *otf_last_error(const otf_ctx *ctx) { return ctx ? ctx->c.err.c_str() : "null context"; }
 
+// A batch member is swept, restructured and replaced only through its batch
+// (the batch's table holds its store pointers).
+static bool batch_member(otf_ctx *ctx) {
+    if (ctx->c.batches.empty()) return false;
+    ctx->c.err = "the context is a batch member: fuse it through the batch, or destroy the batch first";
+    return true;
+}
+
 otf_status otf_build_octree(otf_ctx *ctx, const float *depth, int32_t depth_is_device, int32_t n_views,
                             const otf_camera *cams, const otf_params *prm) {
     if (!ctx) return OTF_E_INVALID;
+    if (batch_member(ctx)) return OTF_E_STATE;
     return guard(ctx, true, [&] {
         Ctx &c = ctx->c;
         check_params(prm);
@@ -406,6 +416,7 @@ otf_status otf_build_octree(otf_ctx *ctx, const float *depth, int32_t depth_is_d
 
 otf_status otf_fuse(otf_ctx *ctx, int32_t iterations, float lambda, float tau, float sigma) {
     if (!ctx) return OTF_E_INVALID;
+    if (batch_member(ctx)) return OTF_E_STATE;
     if (iterations < 0 || !std::isfinite(lambda) || !std::isfinite(tau) || !std::isfinite(sigma) || lambda < 0.0f ||
         !(tau > 0.0f) || !(sigma > 0.0f)) {
         ctx->c.err = "bad fuse arguments";
@@ -444,6 +455,7 @@ otf_status otf_fuse(otf_ctx *ctx, int32_t iterations, float lambda, float tau, f
 
 otf_status otf_fuse_gd(otf_ctx *ctx, int32_t iterations, float lambda, float step, float epsilon) {
     if (!ctx) return OTF_E_INVALID;
+    if (batch_member(ctx)) return OTF_E_STATE;
     if (iterations < 0 || !std::isfinite(lambda) || !std::isfinite(step) || !std::isfinite(epsilon) ||
         lambda < 0.0f || !(step > 0.0f) || !(epsilon > 0.0f)) {
         ctx->c.err = "bad fuse arguments";
@@ -883,6 +895,7 @@ otf_status otf_export_state(const otf_ctx *cctx, void *buf, int64_t cap, int64_t
 
 otf_status otf_import_state(otf_ctx *ctx, const void *buf, int64_t n_bytes) {
     if (!ctx || !buf || n_bytes < 0) return OTF_E_INVALID;
+    if (batch_member(ctx)) return OTF_E_STATE;
     return guard(ctx, true, [&] {
         Ctx &c = ctx->c;
         Reader r{(const uint8_t *)buf, n_bytes};

@@ -170,9 +170,11 @@ otf_status otf_batch_destroy(otf_batch *bt) {
     if (!bt) return OTF_E_INVALID;
     (void)hipSetDevice(bt->device);
     (void)hipStreamSynchronize(bt->stream);
+    for (Ctx *c : bt->b.objs) c->batches.erase(std::remove(c->batches.begin(), c->batches.end(), bt), c->batches.end());
     delete bt;
     return OTF_OK;
 }
+
 
 otf_status otf_batch_add(otf_batch *bt, otf_ctx *ctx) {
     if (!bt || !ctx) return OTF_E_INVALID;
@@ -191,6 +193,7 @@ otf_status otf_batch_add(otf_batch *bt, otf_ctx *ctx) {
         }
     return bguard(bt, [&] {
         bt->b.objs.push_back(&ctx->c);
+        ctx->c.batches.push_back(bt);
         bt->table_ok = false;
         if (bt->exec) {
             OTF_HIP(hipGraphExecDestroy(bt->exec));
@@ -278,3 +281,15 @@ otf_status otf_batch_config(const otf_batch *bt, int32_t *block, int32_t *grid, 
 const char *otf_batch_last_error(const otf_batch *bt) { return bt ? bt->err.c_str() : "null batch"; }
 
 }  // extern "C"
+
+namespace otf {
+void batch_forget(otf_batch *bt, Ctx *c) {
+    (void)hipStreamSynchronize(bt->stream);
+    bt->b.objs.erase(std::remove(bt->b.objs.begin(), bt->b.objs.end(), c), bt->b.objs.end());
+    bt->table_ok = false;
+    if (bt->exec) {
+        (void)hipGraphExecDestroy(bt->exec);
+        bt->exec = nullptr;
+    }
+}
+}  // namespace otf

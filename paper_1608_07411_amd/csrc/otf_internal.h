@@ -340,6 +340,7 @@ struct Solver {
 struct Ctx {
     int device = 0;
     int64_t fail_alloc_after = 0;  // allocation-failure injection countdown (0: off)
+    std::vector<otf_batch *> batches;  // batches that hold this context as a member
     Solver sol;
     hipStream_t stream = nullptr;
     // a second stream of the library's own (default priority) with fork and
@@ -579,3 +580,9 @@ void count_sweep_bytes(Ctx &c);  // one iteration's sweep bytes into alg_bytes
 struct otf_ctx {
     otf::Ctx c;
 };
+
+namespace otf {
+// A member context being destroyed leaves its batches (their tables and
+// captured graphs are dropped).
+void batch_forget(otf_batch *bt, Ctx *c);
+}  // namespace otf

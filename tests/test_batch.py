@@ -163,3 +163,29 @@ def test_batch_at_object_shapes_matches_solo_runs_and_oracle():
         assert members[k6].export_state() == o.export_state(), "depth-6 member differs from the oracle"
     assert batch.config()["tuned"]
     batch.close()
+
+
+def test_batch_members_refuse_solo_calls_and_leave_when_destroyed():
+    ws = _workloads(restructure_every=1)[:3]
+    solo, members = _pair(ws)
+    batch = otf.Batch(0)
+    for m in members:
+        batch.add(m)
+    blob = members[0].export_state()
+    w = ws[0]
+    for call in (lambda c: c.fuse(1, LAM, TAU32, TAU32), lambda c: c.fuse_gd(1, 0.5, 0.05, 0.3),
+                 lambda c: c.build_octree(w.depth, w.cams, w.params), lambda c: c.import_state(blob)):
+        with pytest.raises(otf.OtfError) as e:
+            call(members[0])
+        assert e.value.status == 5 and "batch member" in str(e.value)
+    assert members[0].export_state() == blob
+    # a destroyed member leaves the batch; the others go on as before
+    members[1].close()
+    batch.fuse(3, LAM, TAU32, TAU32)
+    for k in (0, 2):
+        solo[k].fuse(3, LAM, TAU32, TAU32)
+    torch.cuda.synchronize()
+    for k in (0, 2):
+        assert members[k].export_state() == solo[k].export_state()
+    batch.close()
+    members[0].fuse(1, LAM, TAU32, TAU32)  # free again once the batch is gone
