@@ -77,12 +77,17 @@ def parse_args():
     ap.add_argument("--eval", action="store_true",
                     help="paper-style evaluation on the sphere workload: Eq. 7 quantisation error against a fully "
                          "refined solve for three split/join threshold pairs, and mesh-to-sphere distances")
+    ap.add_argument("--convergence", action="store_true",
+                    help="per-iteration log (leaf count, splits, joins) and the energy every --log-every iterations "
+                         "on the chosen workload (the leaf-count curve the paper plots over the iterations)")
+    ap.add_argument("--log-every", type=int, default=10)
     ap.add_argument("--eval-gammas", default="0.01,0.1,1.0",
                     help="--eval: the gamma values (normaliser of Eq. 5) to evaluate")
     ap.add_argument("--warm", action="store_true",
                     help="learned warm start: train the per-leaf network on sphere scenes, then seconds to the plain "
                          "solver's final energy (1e-4 relative) from the plain and the warm start on held-out scenes")
     ap.add_argument("--warm-scenes", type=int, default=2000, help="--warm: training scenes")
+    ap.add_argument("--warm-seeds", type=int, default=10, help="--warm: held-out multi-object scenes (seeds from 10000)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized buffer on the GPU 5 times (reference for hardware byte counters)")
     return ap.parse_args()
@@ -449,7 +454,7 @@ def run_warm(args):
     losses, t_train = warm.train(net, X, T, epochs, 32768, 1e-3, log=log)
     rows = int(len(X))
     del X, T
-    seeds = list(range(10000, 10010))
+    seeds = list(range(10000, 10000 + args.warm_seeds))
     res_frozen = warm.evaluate(net, [synth.blocks_workload(seed=s, restructure_every=0) for s in seeds], 1500, log=log)
     res_split = warm.evaluate(net, [synth.blocks_workload(seed=s, restructure_every=1) for s in seeds], 1500, log=log)
     held_sphere = [synth.warm_training_workload(100000 + k) for k in range(2)]
@@ -464,7 +469,8 @@ def run_warm(args):
                 "structure)", "higher_is_better": True,
         "n_gpus": 1, "steps": None, "dtype": "bf16 network, f32 solver", "data": "synthetic",
         "config": {"workload": (f"train: {n_scenes} sphere scenes (depth 6, 8 views), frozen structure, 300 plain "
-                                f"iterations as targets; evaluate: multi-object scenes seeds 10000-10009 (depth 8, "
+                                f"iterations as targets; evaluate: multi-object scenes seeds 10000-"
+                                f"{10000 + args.warm_seeds - 1} (depth 8, "
                                 f"32 views 640x480) frozen and with split/join every iteration, and 2 held-out "
                                 f"spheres; tolerance 1e-4 on the energy after 1500 plain iterations, checked every "
                                 f"iteration; the warm start guarded by the energy (steps 1, 0.5, 0.25 or none)"),
@@ -476,8 +482,39 @@ def run_warm(args):
     print(json.dumps(result), flush=True)
 
 
+def run_convergence(args):
+    """Leaf count, splits and joins after every iteration, and the energy of
+    Eq. 3 with the normaliser of Eq. 5 every --log-every iterations, over
+    --steps iterations of the chosen workload with split/join every
+    iteration."""
+    import torch
+    from paper_1608_07411_amd import otf, synth
+
+    maker = {"thin": synth.thin_workload, "blocks": synth.blocks_workload, "sphere": synth.sphere_workload}
+    w = maker[args.workload](seed=args.seed)
+    depth = torch.from_numpy(w.depth).cuda()
+    ctx = otf.Context(0).build_octree(depth, w.cams, w.params)
+    tv, da = ctx.energy()
+    log_rows = [dict(iteration=0, leaves=ctx.num_leaves(), splits=0, joins=0, energy=tv + w.lam * da, tv=tv, data=da)]
+    for it in range(1, args.steps + 1):
+        ctx.fuse(1, w.lam, w.tau, w.sigma)
+        s_, j_ = ctx.last_counts()
+        row = dict(iteration=it, leaves=ctx.num_leaves(), splits=s_, joins=j_)
+        if it % args.log_every == 0 or it == args.steps:
+            tv, da = ctx.energy()
+            row.update(energy=tv + w.lam * da, tv=tv, data=da)
+            log(f"[convergence] {row}")
+        log_rows.append(row)
+    result = {"metric": "convergence log", "workload": f"{w.name}: depth {w.max_depth}, {w.depth.shape[0]} views",
+              "steps": args.steps, "log_every": args.log_every, "rows": log_rows}
+    print(json.dumps(result), flush=True)
+
+
 def main():
     args = parse_args()
+    if args.convergence:
+        run_convergence(args)
+        return
     if args.warm:
         run_warm(args)
         return

@@ -5,7 +5,7 @@
 //
 // Network: 32 features -> 128 -> 128 -> 128 -> 4 (change of u, px, py, pz), ReLU on the
 // hidden layers. Weights and activations are bfloat16, products accumulate in
-// fp32 on the matrix cores (v_mfma_f32_16x16x16 bf16), biases and the master
+// fp32 on the matrix cores (v_mfma_f32_16x16x32 bf16), biases and the master
 // weights (Adam) are fp32. Parameter vector: per layer W (in x out,
 // row-major) then b.
 //
@@ -26,8 +26,13 @@ constexpr int kBlk = 256;
 constexpr int kIn = 32, kHid = 128, kOut = 4, kLayers = 4;
 constexpr int kSizes[kLayers + 1] = {kIn, kHid, kHid, kHid, kOut};
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// 8 consecutive bf16 values (16 bytes, 16-byte aligned) as an MFMA operand
+__device__ inline bf16x8 ld8(const uint16_t *p) {
+    return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(p));
+}
 
 __device__ inline uint16_t f2bf(float f) {
     uint32_t u = __float_as_uint(f);
@@ -37,46 +42,100 @@ __device__ inline uint16_t f2bf(float f) {
 __device__ inline float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
 // C(m, n) = sum_k A(m, k) B(k, n); A(m, k) = A[m sam + k sak], B(k, n) =
-// B[k sbk + n sbn] (the strides express transposes). A wave computes one
-// 16x16 tile with MFMA, 4 waves per block along n. With gridDim.z > 1 the
-// k range is split: block z writes its partial sum to C + z M N and
-// k_sum_splits adds them. Epilogue (one split): + bias[n], then ReLU, or the
-// ReLU mask of a stored activation (v = mask(m, n) > 0 ? v : 0); fp32 to C
-// and/or bf16 to Cb (row-major M x N).
+// B[k sbk + n sbn] (the strides express transposes). A block computes a
+// 64 x 64 tile of C: per step of 32 over k it stages the 64 x 32 slices of A
+// and of B^T in LDS (coalesced: along k when k is the contiguous index,
+// else along the rows), and each of its 4 waves multiplies a 32 x 32 quarter
+// as 2 x 2 v_mfma_f32_16x16x32 bf16 steps (lane l: row or column l % 16,
+// k = 8 (l / 16) .. + 7). With gridDim.z > 1 the k range is split: block z
+// writes its partial sum to C + z M N and k_sum_splits adds them. Epilogue
+// (one split): + bias[n], then ReLU, or the ReLU mask of a stored activation
+// (v = mask(m, n) > 0 ? v : 0); fp32 to C and/or bf16 to Cb (row-major M x N).
+constexpr int kTM = 64, kTN = 64, kTK = 32;
+constexpr int kTP = kTK + 8;  // LDS row pitch (bf16 elements): 16-byte aligned rows
+
+// Rows [r0, r0 + 64) x k [k0, k0 + 32) of X(r, k) = X[r sr + k sk] into
+// t[r][k] (zeros outside R x [k0, ke)).
+__device__ inline void stage_slice(const uint16_t *X, int R, int64_t ke, int64_t sr, int64_t sk, int r0, int64_t k0,
+                                   uint16_t *t) {
+    const int tid = threadIdx.x;
+    uint16_t v[8];
+    if (sk == 1) {  // k contiguous: 8 consecutive k of one row per thread
+        const int r = tid >> 2, kc = (tid & 3) * 8;
+        const int64_t row = r0 + r, k = k0 + kc;
+        const uint16_t *src = X + row * sr + k;
+        if (row < R && k + 8 <= ke && ((uintptr_t)src & 15) == 0) {
+            *reinterpret_cast<uint4 *>(t + r * kTP + kc) = *reinterpret_cast<const uint4 *>(src);
+            return;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = (row < R && k + j < ke) ? src[j] : (uint16_t)0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) t[r * kTP + kc + j] = v[j];
+    } else {  // rows contiguous: 8 consecutive rows of one k per thread
+        const int kk = tid >> 3, rc = (tid & 7) * 8;
+        const int64_t k = k0 + kk;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int64_t row = r0 + rc + j;
+            v[j] = (row < R && k < ke) ? X[row * sr + k * sk] : (uint16_t)0;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) t[(rc + j) * kTP + kk] = v[j];
+    }
+}
+
 __global__ void __launch_bounds__(kBlk) k_gemm(int M, int N, int64_t K, const uint16_t *A, int64_t sam, int64_t sak,
                                                const uint16_t *B, int64_t sbk, int64_t sbn, float *C, uint16_t *Cb,
                                                int64_t kchunk, const float *bias, int relu, const uint16_t *mask) {
+    __shared__ __align__(16) uint16_t ta[kTM * kTP];
+    __shared__ __align__(16) uint16_t tb[kTN * kTP];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int m0 = blockIdx.x * 16, n0 = (blockIdx.y * 4 + w) * 16;
-    if (n0 >= N) return;  // whole wave
+    const int m0 = blockIdx.x * kTM, n0 = blockIdx.y * kTN;
+    const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
     const int64_t kb = (int64_t)blockIdx.z * kchunk, ke = min(K, kb + kchunk);
-    const int mr = m0 + (lane & 15), nc = n0 + (lane & 15), kq = 4 * (lane >> 4);
-    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    for (int64_t k0 = kb; k0 < ke; k0 += 16) {
-        bf16x4 a, b;
+    const int r16 = lane & 15, kq = 8 * (lane >> 4);
+    f32x4 acc[2][2];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t k = k0 + kq + j;
-            a[j] = (mr < M && k < ke) ? (short)A[mr * sam + k * sak] : (short)0;
-            b[j] = (nc < N && k < ke) ? (short)B[k * sbk + nc * sbn] : (short)0;
-        }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int64_t k0 = kb; k0 < ke; k0 += kTK) {
+        stage_slice(A, M, ke, sam, sak, m0, k0, ta);
+        stage_slice(B, N, ke, sbn, sbk, n0, k0, tb);  // B^T(n, k) = B(k, n)
+        __syncthreads();
+        bf16x8 a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i] = ld8(ta + (wm + 16 * i + r16) * kTP + kq);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = ld8(tb + (wn + 16 * j + r16) * kTP + kq);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int row = m0 + kq + r;
-        if (row >= M || nc >= N) continue;
-        float v = acc[r];
-        if (gridDim.z > 1) {
-            C[(int64_t)blockIdx.z * M * N + (int64_t)row * N + nc] = v;
-            continue;
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int nc = n0 + wn + 16 * j + r16;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+                if (row >= M || nc >= N) continue;
+                float v = acc[i][j][r];
+                if (gridDim.z > 1) {
+                    C[(int64_t)blockIdx.z * M * N + (int64_t)row * N + nc] = v;
+                    continue;
+                }
+                if (bias) v = v + bias[nc];
+                if (relu) v = fmaxf(v, 0.0f);
+                if (mask && !(bf2f(mask[(int64_t)row * N + nc]) > 0.0f)) v = 0.0f;
+                if (C) C[(int64_t)row * N + nc] = v;
+                if (Cb) Cb[(int64_t)row * N + nc] = f2bf(v);
+            }
         }
-        if (bias) v = v + bias[nc];
-        if (relu) v = fmaxf(v, 0.0f);
-        if (mask && !(bf2f(mask[(int64_t)row * N + nc]) > 0.0f)) v = 0.0f;
-        if (C) C[(int64_t)row * N + nc] = v;
-        if (Cb) Cb[(int64_t)row * N + nc] = f2bf(v);
-    }
 }
 
 __global__ void k_sum_splits(const float *part, int splits, int64_t n, float *out) {
@@ -221,10 +280,10 @@ __global__ void k_apply_warm_alpha(int64_t L, int64_t cap, const float *Y, const
 // stores). Operands, the order of the MFMA steps over k and the epilogue
 // (+ bias, ReLU, bf16 rounding) are k_gemm's, so the outputs equal the
 // layered forward's bit for bit; only the features are read and the 4
-// outputs written. Row pitches of 4 extra elements keep the 8-byte operand
-// reads of the 16 lanes of a row group on different banks.
+// outputs written. Row pitches of 8 extra elements keep the 16-byte operand
+// reads aligned.
 constexpr int kFusedWaves = 4;
-constexpr int kPitchIn = kIn + 4, kPitchHid = kHid + 4;
+constexpr int kPitchIn = kIn + 8, kPitchHid = kHid + 8;  // 16-byte aligned rows
 struct __align__(16) FusedLds {
     uint16_t w0[kHid * kPitchIn];
     uint16_t w1[kHid * kPitchHid];
@@ -245,19 +304,19 @@ __device__ inline void stage_wt(const uint16_t *W, int K, int N, uint16_t *wt, i
 template <int K, int NT>
 __device__ inline void fused_layer(const uint16_t *in, int pin, const uint16_t *wt, int pw, const float *bias,
                                    uint16_t *out, int pout, int lane) {
-    const int r16 = lane & 15, kq = 4 * (lane >> 4);
+    const int r16 = lane & 15, kq = 8 * (lane >> 4), rq = 4 * (lane >> 4);
     for (int t = 0; t < NT; ++t) {
         f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int k0 = 0; k0 < K; k0 += 16) {
-            const bf16x4 a = *reinterpret_cast<const bf16x4 *>(in + r16 * pin + k0 + kq);
-            const bf16x4 b = *reinterpret_cast<const bf16x4 *>(wt + (t * 16 + r16) * pw + k0 + kq);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+        for (int k0 = 0; k0 < K; k0 += 32) {
+            const bf16x8 a = ld8(in + r16 * pin + k0 + kq);
+            const bf16x8 b = ld8(wt + (t * 16 + r16) * pw + k0 + kq);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const float v = fmaxf(acc[r] + bias[t * 16 + r16], 0.0f);
-            out[(kq + r) * pout + t * 16 + r16] = f2bf(v);
+            out[(rq + r) * pout + t * 16 + r16] = f2bf(v);
         }
     }
 }
@@ -300,19 +359,19 @@ __global__ void __launch_bounds__(64 * kFusedWaves) k_mlp_forward(const float *X
         fused_layer<kHid, kHid / 16>(s.h[wv][1], kPitchHid, s.w2, kPitchHid, s.b + 2 * kHid, s.h[wv][0], kPitchHid,
                                      lane);
         __syncthreads();
-        {  // output layer: fp32, no ReLU; lane holds column r16 of rows kq..kq+3
-            const int r16 = lane & 15, kq = 4 * (lane >> 4);
+        {  // output layer: fp32, no ReLU; lane holds column r16 of rows rq..rq+3
+            const int r16 = lane & 15, kq = 8 * (lane >> 4), rq = 4 * (lane >> 4);
             f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-            for (int k0 = 0; k0 < kHid; k0 += 16) {
-                const bf16x4 a = *reinterpret_cast<const bf16x4 *>(s.h[wv][0] + r16 * kPitchHid + k0 + kq);
-                const bf16x4 b = *reinterpret_cast<const bf16x4 *>(s.w3 + r16 * kPitchHid + k0 + kq);
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+            for (int k0 = 0; k0 < kHid; k0 += 32) {
+                const bf16x8 a = ld8(s.h[wv][0] + r16 * kPitchHid + k0 + kq);
+                const bf16x8 b = ld8(s.w3 + r16 * kPitchHid + k0 + kq);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
             }
             if (r16 < kOut)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int64_t row = m0 + kq + r;
+                    const int64_t row = m0 + rq + r;
                     if (row < rows) Y[row * kOut + r16] = acc[r] + s.b[3 * kHid + r16];
                 }
         }
@@ -355,7 +414,7 @@ struct Mlp {
     // C = A B with the epilogue of k_gemm; split over k when K is long
     void gemm(int M, int N, int64_t K, const uint16_t *A, int64_t sam, int64_t sak, const uint16_t *B, int64_t sbk,
               int64_t sbn, float *C, uint16_t *Cb, const float *bias, int relu, const uint16_t *mask) {
-        const unsigned gx = (unsigned)cdiv(M, 16), gy = (unsigned)cdiv(N, 64);
+        const unsigned gx = (unsigned)cdiv(M, kTM), gy = (unsigned)cdiv(N, kTN);
         int splits = 1;
         if ((int64_t)gx * gy < 256 && K > 4096) splits = (int)std::min<int64_t>(512, cdiv(K, 2048));
         if (splits == 1) {
@@ -364,7 +423,7 @@ struct Mlp {
             OTF_LAUNCH_CHECK("k_gemm");
             return;
         }
-        const int64_t chunk = ((cdiv(K, splits) + 15) / 16) * 16;
+        const int64_t chunk = ((cdiv(K, splits) + kTK - 1) / kTK) * kTK;
         splits = (int)cdiv(K, chunk);
         part.reserve((size_t)splits * M * N);
         hipLaunchKernelGGL(k_gemm, dim3(gx, gy, (unsigned)splits), dim3(kBlk), 0, stream, M, N, K, A, sam, sak, B, sbk,
