@@ -138,22 +138,50 @@ __global__ void __launch_bounds__(kBlk) k_gemm(int M, int N, int64_t K, const ui
         }
 }
 
+// out[e] = sum over z < splits of part[z n + e]: one wave per element, lane
+// l adding partials l, l + 64, ... in order, then a fixed shuffle tree (a
+// deterministic order; the split partials of a long reduction are many, so
+// they are spread over the lanes rather than walked by one thread)
 __global__ void k_sum_splits(const float *part, int splits, int64_t n, float *out) {
-    const int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x;
-    if (i >= n) return;
+    const int64_t e = (int64_t)blockIdx.x * (kBlk / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (e >= n) return;  // the whole wave
     float s = 0.0f;
-    for (int z = 0; z < splits; ++z) s = s + part[(int64_t)z * n + i];
-    out[i] = s;
+    for (int z = lane; z < splits; z += 64) s = s + part[(int64_t)z * n + e];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s = s + __shfl_down(s, o, 64);
+    if (lane == 0) out[e] = s;
 }
 
-// per-block column sums of a bf16 matrix (rows x N, N <= kBlk) in row order
-__global__ void k_colsum(const uint16_t *Z, int64_t rows, int N, int64_t chunk, float *part) {
-    const int t = threadIdx.x;
-    if (t >= N) return;
+// Per-block column sums of a bf16 matrix (rows x N, N <= kBlk) over `chunk`
+// rows: with G = kBlk / N row phases, thread t sums column t % N over rows
+// r0 + t / N, r0 + t / N + G, ... (a wave's loads cover whole rows), then
+// the G phase sums of each column are added in phase order.
+constexpr int kColRows = 16;  // rows per thread and block
+__global__ void __launch_bounds__(kBlk) k_colsum(const uint16_t *Z, int64_t rows, int N, int64_t chunk,
+                                                 float *part) {
+    __shared__ float sh[kBlk];
+    const int t = threadIdx.x, G = kBlk / N, c = t % N, g = t / N;
     const int64_t r0 = (int64_t)blockIdx.x * chunk, r1 = min(rows, r0 + chunk);
     float s = 0.0f;
-    for (int64_t r = r0; r < r1; ++r) s = s + bf2f(Z[r * N + t]);
-    part[(int64_t)blockIdx.x * N + t] = s;
+    if (g < G) {
+        float v[kColRows];
+#pragma unroll
+        for (int k = 0; k < kColRows; ++k) {
+            const int64_t r = r0 + g + (int64_t)k * G;
+            v[k] = r < r1 ? bf2f(Z[r * N + c]) : 0.0f;
+        }
+#pragma unroll
+        for (int k = 0; k < kColRows; ++k) s = s + v[k];
+        for (int64_t r = r0 + g + (int64_t)kColRows * G; r < r1; r += G) s = s + bf2f(Z[r * N + c]);
+    }
+    sh[t] = s;
+    __syncthreads();
+    if (t < N) {
+        float acc = 0.0f;
+        for (int k = 0; k < G; ++k) acc = acc + sh[k * N + t];
+        part[(int64_t)blockIdx.x * N + t] = acc;
+    }
 }
 
 __global__ void k_to_bf16(const float *x, int64_t n, uint16_t *y) {
@@ -416,7 +444,7 @@ struct Mlp {
               int64_t sbn, float *C, uint16_t *Cb, const float *bias, int relu, const uint16_t *mask) {
         const unsigned gx = (unsigned)cdiv(M, kTM), gy = (unsigned)cdiv(N, kTN);
         int splits = 1;
-        if ((int64_t)gx * gy < 256 && K > 4096) splits = (int)std::min<int64_t>(512, cdiv(K, 2048));
+        if ((int64_t)gx * gy < 256 && K > 4096) splits = (int)std::min<int64_t>(512, cdiv(K, 256));
         if (splits == 1) {
             hipLaunchKernelGGL(k_gemm, dim3(gx, gy, 1), dim3(kBlk), 0, stream, M, N, K, A, sam, sak, B, sbk, sbn, C, Cb,
                                K, bias, relu, mask);
@@ -430,7 +458,7 @@ struct Mlp {
                            sbn, part.p, (uint16_t *)nullptr, chunk, (const float *)nullptr, 0,
                            (const uint16_t *)nullptr);
         OTF_LAUNCH_CHECK("k_gemm split");
-        hipLaunchKernelGGL(k_sum_splits, dim3(g1((int64_t)M * N)), dim3(kBlk), 0, stream, part.p, splits,
+        hipLaunchKernelGGL(k_sum_splits, dim3(g1((int64_t)M * N * 64)), dim3(kBlk), 0, stream, part.p, splits,
                            (int64_t)M * N, C);
         OTF_LAUNCH_CHECK("k_sum_splits");
     }
@@ -481,11 +509,12 @@ struct Mlp {
             // dW = H_in^T dZ (in x out), reduced over the rows
             gemm(in, out, rows, hin, 1, in, dz, out, 1, grad.p + off_w[l], nullptr, nullptr, 0, nullptr);
             // db = column sums of dZ
-            const int64_t chunk = 4096, nbk = cdiv(rows, chunk);
+            const int64_t chunk = (int64_t)kColRows * (kBlk / out), nbk = cdiv(rows, chunk);
             part.reserve((size_t)std::max<int64_t>(nbk * out, 1));
             hipLaunchKernelGGL(k_colsum, dim3((unsigned)nbk), dim3(kBlk), 0, stream, dz, rows, out, chunk, part.p);
             OTF_LAUNCH_CHECK("k_colsum");
-            hipLaunchKernelGGL(k_sum_splits, dim3(g1(out)), dim3(kBlk), 0, stream, part.p, (int)nbk, (int64_t)out,
+            hipLaunchKernelGGL(k_sum_splits, dim3(g1((int64_t)out * 64)), dim3(kBlk), 0, stream, part.p, (int)nbk,
+                               (int64_t)out,
                                grad.p + off_b[l]);
             OTF_LAUNCH_CHECK("bias gradient");
             if (l > 0) {

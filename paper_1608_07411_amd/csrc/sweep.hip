@@ -406,7 +406,7 @@ __device__ void dual_long_wave(const DualArgs &a, const Coef &cf, int64_t i, int
 // per thread: such a block covers kDualLeaves * kBlk consecutive leaves,
 // thread t takes t, t + kBlk, ... (each group coalesced; long-list leaves are
 // skipped). The two kinds of blocks touch disjoint leaves.
-__global__ void __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(8, 8)))
+__global__ void __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(6, 8)))
 k_dual(DualArgs a, Coef cf, uint32_t n_long, const uint32_t *long_list, uint32_t long_blocks) {
     __shared__ Coef scf;
     const Coef &lcf = stage_coef(cf, scf);
