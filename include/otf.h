@@ -23,8 +23,10 @@
  *     except that a restructuring step (otf_fuse, otf_fuse_gd with split/join)
  *     runs its new leaves' observation fetch on a second stream that the
  *     context creates (default priority) and joins back into the given stream
- *     with an event before anything reads the result; every entry point
- *     returns after its work on both streams has finished;
+ *     with an event before anything reads the result, and a frozen-structure
+ *     fuse records a graph on a third stream of its own (nothing runs there;
+ *     see otf_fuse_graph_iterations); every entry point returns after its
+ *     work on these streams has finished;
  *   - after a failure other than OTF_E_INVALID the fused state is unspecified
  *     and OTF_E_STATE is returned by fuse/extract/energy/export until the next
  *     successful build or import; the context can always be destroyed;
@@ -120,6 +122,18 @@ otf_status otf_build_octree(otf_ctx *ctx, const float *depth, int32_t depth_is_d
  * primal and dual steps (tau * sigma * 12 <= 1 guarantees convergence on a
  * fixed structure). All finite. */
 otf_status otf_fuse(otf_ctx *ctx, int32_t iterations, float lambda, float tau, float sigma);
+
+/* Iterations of the last otf_fuse or otf_fuse_gd call that were replayed from
+ * a recorded HIP graph. With restructure_every = 0 (a frozen structure),
+ * kernel timing off (otf_profile) and more than 16 iterations, a call runs
+ * one iteration as usual, records the device work of 8 iterations (the two
+ * sweeps and their flag and observation totals) into a graph once, launches
+ * that graph for as many whole chunks as remain and runs the rest as usual:
+ * fewer host launches per iteration, identical results. *n = 0 otherwise.
+ * The graph is recorded on a capture stream of the library's own (default
+ * priority; recording runs nothing), launched on the context's stream and
+ * destroyed before the call returns. */
+otf_status otf_fuse_graph_iterations(const otf_ctx *ctx, int64_t *n);
 
 /* Number of leaves of the fused octree. */
 otf_status otf_num_leaves(const otf_ctx *ctx, int64_t *n);

@@ -97,6 +97,17 @@ void prof_end(Ctx &c, ProfKind k) {
     c.prof_open = nullptr;
 }
 
+// Records one event that ends the open interval (credited to kind k, or to
+// nothing for k < 0) and opens the next one: consecutive phases share their
+// boundary event, so an iteration records one event per phase.
+void prof_mark(Ctx &c, int k) {
+    if (!c.prof) return;
+    hipEvent_t b = next_event(c);
+    OTF_HIP(hipEventRecord(b, c.stream));
+    if (c.prof_open && k >= 0) c.prof_recs.push_back(Ctx::ProfRec{k, c.prof_open, b});
+    c.prof_open = b;
+}
+
 // Sum the recorded event pairs into the per-kind totals and recycle the events.
 void prof_collect(Ctx &c) {
     if (c.prof_recs.empty()) return;
@@ -109,6 +120,7 @@ void prof_collect(Ctx &c) {
     }
     c.prof_recs.clear();
     c.ev_used = 0;
+    c.prof_open = nullptr;
 }
 
 namespace {
@@ -351,6 +363,7 @@ otf_status otf_destroy(otf_ctx *ctx) {
         (void)hipStreamSynchronize(ctx->c.side);
         (void)hipStreamDestroy(ctx->c.side);
     }
+    if (ctx->c.capture) (void)hipStreamDestroy(ctx->c.capture);
     if (ctx->c.ev_fork) (void)hipEventDestroy(ctx->c.ev_fork);
     if (ctx->c.ev_join) (void)hipEventDestroy(ctx->c.ev_join);
     if (ctx->c.h_counters) (void)hipHostFree(ctx->c.h_counters);
@@ -414,6 +427,94 @@ otf_status otf_build_octree(otf_ctx *ctx, const float *depth, int32_t depth_is_d
     });
 }
 
+namespace {
+// Iterations recorded per graph when the structure is frozen.
+constexpr int kFuseGraphChunk = 8;
+
+// The device work of one frozen iteration (no restructure): the two sweeps,
+// the flag totals and the observation totals, on c.stream.
+void sweep_work(Ctx &c, const Solver &sol, float sigma, float tau, float tl) {
+    if (sol.gd) {
+        launch_gd_flux(c, sol.eps2);
+        launch_gd_update(c, sol.lam, sol.xi, sol.eps2);
+    } else {
+        launch_dual(c, sigma);
+        launch_primal(c, tau, tl);
+    }
+    count_flags(c);
+    accumulate_obs(c, sol.gd != 0);
+}
+
+// Host bookkeeping of one iteration whose device work is already queued.
+void sweep_books(Ctx &c) {
+    c.iteration++;
+    c.leaf_updates += c.L;
+    count_sweep_bytes(c);
+    c.last_splits = c.last_joins = 0;
+}
+
+// Records `chunk` frozen iterations into an executable graph. Run after an
+// eager iteration of the same structure, so that every scratch buffer the
+// sweeps use already has its size (nothing is allocated while recording).
+hipGraphExec_t record_sweeps(Ctx &c, int chunk, const Solver &sol, float sigma, float tau, float tl) {
+    if (!c.capture) OTF_HIP(hipStreamCreateWithFlags(&c.capture, hipStreamNonBlocking));
+    hipStream_t own = c.stream;
+    hipGraph_t g = nullptr;
+    OTF_HIP(hipStreamBeginCapture(c.capture, hipStreamCaptureModeThreadLocal));
+    c.stream = c.capture;
+    try {
+        for (int k = 0; k < chunk; ++k) sweep_work(c, sol, sigma, tau, tl);
+    } catch (...) {
+        c.stream = own;
+        (void)hipStreamEndCapture(c.capture, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    c.stream = own;
+    OTF_HIP(hipStreamEndCapture(c.capture, &g));
+    hipGraphExec_t e = nullptr;
+    const hipError_t r = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    OTF_HIP(r);
+    return e;
+}
+
+// A frozen structure (restructure_every = 0) without kernel timing: one
+// eager iteration, then chunks of kFuseGraphChunk iterations replayed from
+// one recorded graph, then the rest eagerly. Returns the iterations done.
+int fuse_frozen(Ctx &c, int iterations, float sigma, float tau, float tl) {
+    const Solver sol = c.sol;
+    sweep_work(c, sol, sigma, tau, tl);
+    sweep_books(c);
+    int done = 1;
+    const int reps = (iterations - done) / kFuseGraphChunk;
+    hipGraphExec_t e = record_sweeps(c, kFuseGraphChunk, sol, sigma, tau, tl);
+    try {
+        for (int r = 0; r < reps; ++r) {
+            OTF_HIP(hipGraphLaunch(e, c.stream));
+            for (int k = 0; k < kFuseGraphChunk; ++k) sweep_books(c);
+        }
+        OTF_HIP(hipStreamSynchronize(c.stream));
+    } catch (...) {
+        (void)hipStreamSynchronize(c.stream);
+        (void)hipGraphExecDestroy(e);
+        throw;
+    }
+    (void)hipGraphExecDestroy(e);
+    done += reps * kFuseGraphChunk;
+    c.graph_iterations = (int64_t)reps * kFuseGraphChunk;
+    for (; done < iterations; ++done) {
+        sweep_work(c, sol, sigma, tau, tl);
+        sweep_books(c);
+    }
+    return done;
+}
+
+bool graph_replay_applies(const Ctx &c, int iterations) {
+    return c.prm.restructure_every == 0 && !c.prof && iterations > 2 * kFuseGraphChunk;
+}
+}  // namespace
+
 otf_status otf_fuse(otf_ctx *ctx, int32_t iterations, float lambda, float tau, float sigma) {
     if (!ctx) return OTF_E_INVALID;
     if (batch_member(ctx)) return OTF_E_STATE;
@@ -430,25 +531,33 @@ otf_status otf_fuse(otf_ctx *ctx, int32_t iterations, float lambda, float tau, f
         Ctx &c = ctx->c;
         const float tl = tau * lambda;
         c.sol = Solver{};
+        c.graph_iterations = 0;
+        if (graph_replay_applies(c, iterations)) {
+            fuse_frozen(c, iterations, sigma, tau, tl);
+            finish(c);
+            return;
+        }
+        prof_mark(c, -1);
         for (int it = 0; it < iterations; ++it) {
             c.iteration++;
-            prof_begin(c);
             launch_dual(c, sigma);
-            prof_end(c, kProfDual);
-            prof_begin(c);
+            prof_mark(c, kProfDual);
             launch_primal(c, tau, tl);
-            prof_end(c, kProfPrimal);
+            prof_mark(c, kProfPrimal);
             count_flags(c);
             c.leaf_updates += c.L;
             count_sweep_bytes(c);
             accumulate_obs(c);
             c.last_splits = c.last_joins = 0;
+            // the flag totals and the restructure form one timed phase
             if (c.prm.restructure_every > 0 && c.iteration % c.prm.restructure_every == 0) {
-                prof_begin(c);
                 restructure(c, tl);
-                prof_end(c, kProfRestructure);
+                prof_mark(c, kProfRestructure);
+            } else {
+                prof_mark(c, -1);
             }
         }
+        c.prof_open = nullptr;
         finish(c);  // synchronises and checks the scan health flag
     });
 }
@@ -468,14 +577,20 @@ otf_status otf_fuse_gd(otf_ctx *ctx, int32_t iterations, float lambda, float ste
     return guard(ctx, true, [&] {
         Ctx &c = ctx->c;
         c.sol = Solver{1, lambda, step, epsilon * epsilon};
+        c.graph_iterations = 0;
+        if (graph_replay_applies(c, iterations)) {
+            fuse_frozen(c, iterations, 0.0f, 1.0f, 0.0f);
+            c.sol = Solver{};
+            finish(c);
+            return;
+        }
+        prof_mark(c, -1);
         for (int it = 0; it < iterations; ++it) {
             c.iteration++;
-            prof_begin(c);
             launch_gd_flux(c, c.sol.eps2);
-            prof_end(c, kProfDual);
-            prof_begin(c);
+            prof_mark(c, kProfDual);
             launch_gd_update(c, c.sol.lam, c.sol.xi, c.sol.eps2);
-            prof_end(c, kProfPrimal);
+            prof_mark(c, kProfPrimal);
             count_flags(c);
             c.leaf_updates += c.L;
             // same bytes as the primal-dual sweeps, with W in place of P for every observation
@@ -483,11 +598,13 @@ otf_status otf_fuse_gd(otf_ctx *ctx, int32_t iterations, float lambda, float ste
             accumulate_obs(c, true);
             c.last_splits = c.last_joins = 0;
             if (c.prm.restructure_every > 0 && c.iteration % c.prm.restructure_every == 0) {
-                prof_begin(c);
                 restructure(c, 0.0f);
-                prof_end(c, kProfRestructure);
+                prof_mark(c, kProfRestructure);
+            } else {
+                prof_mark(c, -1);
             }
         }
+        c.prof_open = nullptr;
         c.sol = Solver{};
         finish(c);
     });
@@ -1014,6 +1131,12 @@ otf_status otf_import_state(otf_ctx *ctx, const void *buf, int64_t n_bytes) {
         setup_after_structure(c, false);
         c.valid = true;
     });
+}
+
+otf_status otf_fuse_graph_iterations(const otf_ctx *ctx, int64_t *n) {
+    if (!ctx || !n) return OTF_E_INVALID;
+    *n = ctx->c.graph_iterations;
+    return OTF_OK;
 }
 
 otf_status otf_profile(otf_ctx *ctx, int32_t enable) {

@@ -348,6 +348,11 @@ struct Ctx {
     // adjacency search; every use is joined back into `stream`
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // frozen structure: a stream on which chunks of iterations are recorded
+    // into a graph (recording runs nothing; the graph is launched on
+    // `stream`), and how many iterations of the last fuse call were replayed
+    hipStream_t capture = nullptr;
+    int64_t graph_iterations = 0;
     otf_params prm{};
     int n_views = 0;
     int64_t iteration = 0;

@@ -58,6 +58,7 @@ def lib(path: str = LIB_PATH):
             "otf_destroy": [P],
             "otf_build_octree": [P, P, I32, I32, P, P],
             "otf_fuse": [P, I32, C.c_float, C.c_float, C.c_float],
+            "otf_fuse_graph_iterations": [P, P],
             "otf_num_leaves": [P, P],
             "otf_extract": [P, I64, P, P, P, P, P, P],
             "otf_extract_obs": [P, I64, P, P, P, I64, P, P, P],
@@ -200,6 +201,12 @@ class Context:
     def fuse(self, iterations: int, lam: float, tau: float, sigma: float):
         self._check(self._lib.otf_fuse(self.h, int(iterations), lam, tau, sigma), "otf_fuse")
         return self
+
+    def graph_iterations(self) -> int:
+        """Iterations of the last fuse call replayed from a recorded graph."""
+        n = C.c_int64(0)
+        self._check(self._lib.otf_fuse_graph_iterations(self.h, C.byref(n)), "otf_fuse_graph_iterations")
+        return n.value
 
     def fuse_gd(self, iterations: int, lam: float, step: float, eps: float):
         """The paper's gradient descent (lambda on TV, step, smoothing eps)."""
