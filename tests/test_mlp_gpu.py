@@ -245,3 +245,41 @@ def test_guarded_warm_start_keeps_the_lowest_energy(scale):
         want = np.clip(np.float32(0.5) * Y[:, 0] + st["u"], -1.0, 1.0)
         assert np.array_equal(lv["u"], want.astype(np.float32)) and e < min(e_plain, e_one)
     g.fuse(5, lam, TAU32, TAU32)  # the solver runs from the kept state
+
+
+def _small_trained_network():
+    from paper_1608_07411_amd import warm
+
+    X, T = warm.training_set(24, 300, log=lambda *a: None)
+    net = otf.Mlp(0)
+    net.set_params(om.init_params(0))
+    warm.train(net, X, T, 6, 16384, 1e-3, log=lambda *a: None)
+    return net
+
+
+def test_warm_start_reaches_the_tolerance_sooner_on_held_out_spheres():
+    """Time to the plain solver's energy (1e-4 relative, the energy checked
+    every iteration) from the guarded warm start against the plain start, on
+    held-out spheres of the training family: fewer iterations."""
+    from paper_1608_07411_amd import warm
+
+    net = _small_trained_network()
+    scenes = [synth.warm_training_workload(100000 + k) for k in range(2)]
+    for r in warm.evaluate(net, scenes, 1500, log=lambda *a: None):
+        assert r["plain"]["reached"] and r["warm"]["reached"], r
+        assert r["warm"]["iterations"] < r["plain"]["iterations"], r
+
+
+@pytest.mark.xfail(strict=False, reason="a measured negative result: the network trained on sphere scenes does "
+                                        "not shorten the solve of held-out multi-object scenes (0.89x the plain "
+                                        "solver's speed over ten such scenes with the full training set)")
+def test_warm_start_is_faster_on_a_held_out_multi_object_scene():
+    """The same on a held-out multi-object scene (depth 8, 32 views, frozen
+    structure): the warm start should take fewer seconds than the plain start
+    to the plain solver's energy after 300 iterations."""
+    from paper_1608_07411_amd import warm
+
+    net = _small_trained_network()
+    r = warm.evaluate(net, [synth.blocks_workload(seed=10000, restructure_every=0)], 300, log=lambda *a: None)[0]
+    assert r["plain"]["reached"] and r["warm"]["reached"], r
+    assert r["speedup"] > 1.0, r
