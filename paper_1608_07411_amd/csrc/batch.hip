@@ -6,6 +6,7 @@
 // iteration is one primal-dual iteration of every member, bit-identical to
 // otf_fuse on the member alone (per-leaf arithmetic does not depend on the
 // tiling or the launch shape).
+#include <array>
 #include <algorithm>
 #include <cmath>
 #include <new>
@@ -33,7 +34,9 @@ struct otf_batch {
     hipGraphExec_t exec = nullptr;
     hipStream_t capture = nullptr;  // private stream the graph is recorded on (the caller's may be the null stream)
     int graph_iters = 0;
-    const void *graph_table = nullptr;
+    // what the recorded launches baked in: the table's device buffers and
+    // the launch sizes (a change of any of them records the graph again)
+    std::array<uintptr_t, 12> graph_key{};
     int last_graph_iters = 0;
     ~otf_batch() {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -120,6 +123,13 @@ void finish_tuning(otf_batch *bt) {
     bt->table_ok = false;  // tiles depend on the block size
 }
 
+std::array<uintptr_t, 12> graph_key(const otf_batch *bt) {
+    const BatchState &b = bt->b;
+    return {(uintptr_t)b.table.p,    (uintptr_t)b.tile_obj.p, (uintptr_t)b.tile_begin.p, (uintptr_t)b.part.p,
+            (uintptr_t)b.hp_begin.p, (uintptr_t)b.hm_begin.p, (uintptr_t)b.coefs.p,     (uintptr_t)b.ntiles,
+            (uintptr_t)b.n_hp,       (uintptr_t)b.n_hm,       (uintptr_t)b.cfg.blk,     (uintptr_t)b.cfg.grid};
+}
+
 void build_graph(otf_batch *bt, int iters) {
     if (bt->exec) {
         OTF_HIP(hipGraphExecDestroy(bt->exec));
@@ -141,7 +151,7 @@ void build_graph(otf_batch *bt, int iters) {
     (void)hipGraphDestroy(g);
     OTF_HIP(e);
     bt->graph_iters = iters;
-    bt->graph_table = bt->b.table.p;
+    bt->graph_key = graph_key(bt);
 }
 
 }  // namespace
@@ -249,7 +259,7 @@ otf_status otf_batch_fuse(otf_batch *bt, int32_t iterations, float lambda, float
                 ensure_table(bt, sigma, tau, tl);
                 const int reps = (iterations - it) / kGraphChunk;  // the rest (< kGraphChunk) runs eagerly
                 if (reps > 0) {
-                    if (!bt->exec || bt->graph_table != (const void *)bt->b.table.p) build_graph(bt, kGraphChunk);
+                    if (!bt->exec || bt->graph_key != graph_key(bt)) build_graph(bt, kGraphChunk);
                     for (int r = 0; r < reps; ++r) {
                         OTF_HIP(hipGraphLaunch(bt->exec, bt->stream));
                         for (int k = 0; k < kGraphChunk; ++k) after_sweeps(bt, tl);

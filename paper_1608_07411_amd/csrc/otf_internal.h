@@ -562,6 +562,7 @@ struct BatchState {
     uint32_t ntiles = 0, n_hp = 0, n_hm = 0;  // tiles; long + and - lists over all objects
     DBuf<unsigned char> table;                 // per-object sweep arguments
     DBuf<uint32_t> tile_begin, hp_begin, hm_begin, part;
+    DBuf<uint32_t> tile_obj;                   // the member of each tile
     DBuf<Coef> coefs;                          // coupling tables by max depth
     unsigned char *h_stage = nullptr;          // pinned staging for the table uploads
     size_t h_cap = 0;

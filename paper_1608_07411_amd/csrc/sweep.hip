@@ -977,11 +977,13 @@ __device__ inline int find_obj(const uint32_t *begin, int nobj, uint32_t t) {
     return lo;
 }
 
+// tile_obj[t] is the member of tile t (one load instead of a binary search
+// over the members' tile prefix at every tile's start).
 template <int BLK>
-__global__ void __launch_bounds__(BLK) k_dual_b(const ObjDev *objs, int nobj, const uint32_t *tile_begin,
-                                                uint32_t ntiles, const Coef *coefs) {
+__global__ void __launch_bounds__(BLK) k_dual_b(const ObjDev *objs, const uint32_t *tile_obj,
+                                                const uint32_t *tile_begin, uint32_t ntiles, const Coef *coefs) {
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const int j = find_obj(tile_begin, nobj, t);
+        const int j = (int)tile_obj[t];
         const DualArgs a = objs[j].d;
         const int64_t i = (int64_t)(t - tile_begin[j]) * BLK + threadIdx.x;
         if (i < a.L) dual_leaf(a, coefs[objs[j].D], i);
@@ -989,10 +991,11 @@ __global__ void __launch_bounds__(BLK) k_dual_b(const ObjDev *objs, int nobj, co
 }
 
 template <int BLK>
-__global__ void __launch_bounds__(BLK) k_primal_b(const ObjDev *objs, int nobj, const uint32_t *tile_begin,
-                                                  uint32_t ntiles, const Coef *coefs, uint32_t *part) {
+__global__ void __launch_bounds__(BLK) k_primal_b(const ObjDev *objs, const uint32_t *tile_obj,
+                                                  const uint32_t *tile_begin, uint32_t ntiles, const Coef *coefs,
+                                                  uint32_t *part) {
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const int j = find_obj(tile_begin, nobj, t);
+        const int j = (int)tile_obj[t];
         const PrimalArgs a = objs[j].p;
         uint32_t ns, nj;
         primal_wave<true>(a, coefs[objs[j].D], (int64_t)(t - tile_begin[j]) * BLK + threadIdx.x, ns, nj);
@@ -1108,8 +1111,8 @@ void launch_batch(hipStream_t st, BatchState &b) {
     const ObjDev *objs = reinterpret_cast<const ObjDev *>(b.table.p);
     const int nobj = (int)b.objs.size();
     const unsigned grid = (unsigned)(b.cfg.grid > 0 ? std::min<uint32_t>(b.cfg.grid, b.ntiles) : b.ntiles);
-    hipLaunchKernelGGL(k_dual_b<BLK>, dim3(grid), dim3(BLK), 0, st, objs, nobj, (const uint32_t *)b.tile_begin.p,
-                       b.ntiles, (const Coef *)b.coefs.p);
+    hipLaunchKernelGGL(k_dual_b<BLK>, dim3(grid), dim3(BLK), 0, st, objs, (const uint32_t *)b.tile_obj.p,
+                       (const uint32_t *)b.tile_begin.p, b.ntiles, (const Coef *)b.coefs.p);
     OTF_LAUNCH_CHECK("k_dual_b");
     if (b.n_hp > 0) {
         hipLaunchKernelGGL(k_dual_long_b, dim3((unsigned)cdiv(b.n_hp, kWavesPerBlock)), dim3(kBlk), 0, st, objs,
@@ -1121,8 +1124,8 @@ void launch_batch(hipStream_t st, BatchState &b) {
                            nobj, (const uint32_t *)b.hm_begin.p, (uint32_t)b.n_hm, (const Coef *)b.coefs.p);
         OTF_LAUNCH_CHECK("k_primal_long_b");
     }
-    hipLaunchKernelGGL(k_primal_b<BLK>, dim3(grid), dim3(BLK), 0, st, objs, nobj, (const uint32_t *)b.tile_begin.p,
-                       b.ntiles, (const Coef *)b.coefs.p, b.part.p);
+    hipLaunchKernelGGL(k_primal_b<BLK>, dim3(grid), dim3(BLK), 0, st, objs, (const uint32_t *)b.tile_obj.p,
+                       (const uint32_t *)b.tile_begin.p, b.ntiles, (const Coef *)b.coefs.p, b.part.p);
     OTF_LAUNCH_CHECK("k_primal_b");
     hipLaunchKernelGGL(k_batch_counts, dim3((unsigned)nobj), dim3(kBlk), 0, st, objs,
                        (const uint32_t *)b.tile_begin.p, b.ntiles, (const uint32_t *)b.part.p);
@@ -1300,7 +1303,11 @@ void batch_upload(hipStream_t st, BatchState &b, float sigma, float tau, float t
         OTF_HIP(hipMemcpy(b.coefs.p, cf.data(), cf.size() * sizeof(Coef), hipMemcpyHostToDevice));
     }
     const size_t tbytes = (size_t)nobj * sizeof(ObjDev), ibytes = (size_t)(nobj + 1) * sizeof(uint32_t);
-    const size_t need = tbytes + 3 * ibytes;
+    size_t ntiles = 0;
+    for (int j = 0; j < nobj; ++j) ntiles += (size_t)cdiv(b.objs[j]->L, blk);
+    if (ntiles >= (size_t)UINT32_MAX) fail(OTF_E_CAPACITY, "too many batch tiles");
+    const size_t obytes = std::max<size_t>(ntiles, 1) * sizeof(uint32_t);
+    const size_t need = tbytes + 3 * ibytes + obytes;
     if (b.staged) OTF_HIP(hipEventSynchronize(b.staged));  // the previous upload has left the staging area
     else OTF_HIP(hipEventCreateWithFlags(&b.staged, hipEventDisableTiming));
     if (need > b.h_cap) {
@@ -1312,6 +1319,7 @@ void batch_upload(hipStream_t st, BatchState &b, float sigma, float tau, float t
     ObjDev *rec = reinterpret_cast<ObjDev *>(b.h_stage);
     uint32_t *tb = reinterpret_cast<uint32_t *>(b.h_stage + tbytes);
     uint32_t *hp = tb + (nobj + 1), *hm = hp + (nobj + 1);
+    uint32_t *to = hm + (nobj + 1);  // member of each tile
     tb[0] = hp[0] = hm[0] = 0;
     for (int j = 0; j < nobj; ++j) {
         Ctx &c = *b.objs[j];
@@ -1323,6 +1331,7 @@ void batch_upload(hipStream_t st, BatchState &b, float sigma, float tau, float t
         rec[j].counters = c.counters.p;
         rec[j].D = c.prm.max_depth;
         tb[j + 1] = tb[j] + (uint32_t)cdiv(c.L, blk);
+        for (uint32_t t = tb[j]; t < tb[j + 1]; ++t) to[t] = (uint32_t)j;
         hp[j + 1] = hp[j] + (uint32_t)s.n_heavy_p;
         hm[j + 1] = hm[j] + (uint32_t)s.n_heavy_m;
     }
@@ -1334,7 +1343,9 @@ void batch_upload(hipStream_t st, BatchState &b, float sigma, float tau, float t
     b.hp_begin.reserve(nobj + 1);
     b.hm_begin.reserve(nobj + 1);
     b.part.reserve(2 * (size_t)b.ntiles);
+    b.tile_obj.reserve(std::max<size_t>(b.ntiles, 1));
     OTF_HIP(hipMemcpyAsync(b.table.p, rec, tbytes, hipMemcpyHostToDevice, st));
+    OTF_HIP(hipMemcpyAsync(b.tile_obj.p, to, (size_t)b.ntiles * sizeof(uint32_t), hipMemcpyHostToDevice, st));
     OTF_HIP(hipMemcpyAsync(b.tile_begin.p, tb, ibytes, hipMemcpyHostToDevice, st));
     OTF_HIP(hipMemcpyAsync(b.hp_begin.p, hp, ibytes, hipMemcpyHostToDevice, st));
     OTF_HIP(hipMemcpyAsync(b.hm_begin.p, hm, ibytes, hipMemcpyHostToDevice, st));
