@@ -978,15 +978,18 @@ __device__ inline int find_obj(const uint32_t *begin, int nobj, uint32_t t) {
 }
 
 // tile_obj[t] is the member of tile t (one load instead of a binary search
-// over the members' tile prefix at every tile's start).
+// over the members' tile prefix at every tile's start). The dual runs BLK / 2
+// threads per tile of BLK leaves, two leaves per thread as in k_dual.
 template <int BLK>
-__global__ void __launch_bounds__(BLK) k_dual_b(const ObjDev *objs, const uint32_t *tile_obj,
-                                                const uint32_t *tile_begin, uint32_t ntiles, const Coef *coefs) {
+__global__ void __launch_bounds__(BLK / 2) k_dual_b(const ObjDev *objs, const uint32_t *tile_obj,
+                                                    const uint32_t *tile_begin, uint32_t ntiles, const Coef *coefs) {
+    static_assert(kDualLeaves == 2, "two leaves per thread");
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int j = (int)tile_obj[t];
         const DualArgs a = objs[j].d;
-        const int64_t i = (int64_t)(t - tile_begin[j]) * BLK + threadIdx.x;
-        if (i < a.L) dual_leaf(a, coefs[objs[j].D], i);
+        const int64_t base = (int64_t)(t - tile_begin[j]) * BLK + threadIdx.x;
+        const int64_t idx[kDualLeaves] = {base, base + BLK / 2};
+        dual_leaves(a, coefs[objs[j].D], idx);
     }
 }
 
@@ -1111,7 +1114,7 @@ void launch_batch(hipStream_t st, BatchState &b) {
     const ObjDev *objs = reinterpret_cast<const ObjDev *>(b.table.p);
     const int nobj = (int)b.objs.size();
     const unsigned grid = (unsigned)(b.cfg.grid > 0 ? std::min<uint32_t>(b.cfg.grid, b.ntiles) : b.ntiles);
-    hipLaunchKernelGGL(k_dual_b<BLK>, dim3(grid), dim3(BLK), 0, st, objs, (const uint32_t *)b.tile_obj.p,
+    hipLaunchKernelGGL(k_dual_b<BLK>, dim3(grid), dim3(BLK / 2), 0, st, objs, (const uint32_t *)b.tile_obj.p,
                        (const uint32_t *)b.tile_begin.p, b.ntiles, (const Coef *)b.coefs.p);
     OTF_LAUNCH_CHECK("k_dual_b");
     if (b.n_hp > 0) {
