@@ -286,3 +286,80 @@ def test_long_adjacency_lists_parity(D, x0):
         o.fuse(2, 0.5, TAU32, TAU32)
         g.fuse(2, 0.5, TAU32, TAU32)
         assert g.export_state() == o.export_state()
+
+
+# ---------------------------------------------------------------- edge cases
+def _run_both(w, prm, steps, chunk):
+    g = _ctx().build_octree(w.depth, w.cams, prm)
+    o = Oracle("f32").build(w.depth, w.cams, prm)
+    assert g.export_state() == o.export_state(), "built states differ"
+    done = 0
+    while done < steps:
+        g.fuse(chunk, w.lam, w.tau, w.sigma)
+        o.fuse(chunk, w.lam, w.tau, w.sigma)
+        done += chunk
+        _same_leaves(g.extract(), o.extract(), f"after {done} iterations")
+        assert g.last_counts() == o.last_counts()
+    assert g.export_state() == o.export_state()
+    return g, o
+
+
+def test_no_observations_parity():
+    """Every range-map pixel invalid: no leaf has an observation and every
+    view octree is its root, so the fused octree starts as one leaf with
+    u = 0; |u| < tau_s flags it to split, and the split cascade refines the
+    whole domain to the maximum depth, where u stays 0 (a degenerate case of
+    the split rule) and no join applies."""
+    w = _small_sphere()
+    w.depth[:] = 0.0
+    g, o = _run_both(w, w.params, 10, 5)
+    e = g.extract()
+    assert len(e["keys"]) == 8 ** w.max_depth and np.all(e["u"] == 0.0)
+    assert g.energy() == (0.0, 0.0)
+
+
+@pytest.mark.parametrize("n_views", [1, 64])
+def test_view_count_extremes_parity(n_views):
+    """One view and the 64-view maximum (the fetch's segment of 64 lanes, one
+    per view), on small range maps: build, then iterations with split/join.
+    The solid band is 3 delta: at depth 5 the workload's 10 delta spans the
+    whole domain, and with many views every leaf then starts solid."""
+    w = synth.sphere_workload(max_depth=5, n_views=n_views, W=64, H=48, f=60.0)
+    prm = dict(w.params, eta=3 * w.params["delta"])
+    g, _ = _run_both(w, prm, 20, 5)
+    u = g.extract()["u"]
+    assert (u < 0).any() and (u > 0).any()
+
+
+@pytest.mark.parametrize("max_depth", [1, 2, 3])
+def test_tiny_trees_parity(max_depth):
+    """The smallest trees (2^3 to 8^3 finest voxels): leaves at the domain
+    boundary on most faces, lists of one or two entries, splits capped at the
+    maximum depth right away."""
+    w = synth.sphere_workload(max_depth=max_depth, n_views=4, W=32, H=24, f=30.0)
+    _run_both(w, w.params, 12, 4)
+
+
+def test_build_argument_limits():
+    """Arguments outside the documented limits are rejected before any device
+    work (OTF_E_INVALID), and the context stays usable."""
+    w = _small_sphere(n_views=2)
+    g = _ctx()
+    bad_params = [dict(max_depth=0), dict(max_depth=11), dict(gamma=0.0), dict(gamma=-1.0),
+                  dict(eta=0.5 * w.params["delta"]), dict(delta=0.0), dict(split_tau=0.95, join_tau=0.9)]
+    for over in bad_params:
+        with pytest.raises(otf.OtfError) as e:
+            g.build_octree(w.depth, w.cams, dict(w.params, **over))
+        assert e.value.status == 1, over
+    for n in (0, 65):
+        depth = np.zeros((n, w.depth.shape[1], w.depth.shape[2]), np.float32)
+        cams = np.resize(w.cams, n) if n else w.cams[:0]
+        with pytest.raises(otf.OtfError) as e:
+            g.build_octree(depth, cams, w.params)
+        assert e.value.status == 1, n
+    g.build_octree(w.depth, w.cams, w.params)
+    with pytest.raises(otf.OtfError) as e:
+        g.fuse(-1, w.lam, w.tau, w.sigma)
+    assert e.value.status == 1
+    g.fuse(0, w.lam, w.tau, w.sigma)  # zero iterations: nothing happens
+    g.fuse(2, w.lam, w.tau, w.sigma)
