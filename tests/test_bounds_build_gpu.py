@@ -53,6 +53,23 @@ def test_bounds_build_reports_nothing_and_matches_oracle():
     g.close()
 
 
+def test_bounds_build_at_the_timed_workload_size():
+    """The depth-9 workload (~1.3e7 leaves, 64 range maps 640x480, lists up to
+    thousands of entries) for 6 iterations with split/join under the checked
+    build: no index is reported, and the state equals the default build's."""
+    w = synth.thin_workload(seed=0)
+    depth = torch.from_numpy(w.depth).cuda()
+    g = _bounds_ctx().build_octree(depth, w.cams, w.params)
+    d = otf.Context(0).build_octree(depth, w.cams, w.params)
+    for _ in range(2):
+        g.fuse(3, w.lam, w.tau, w.sigma)
+        d.fuse(3, w.lam, w.tau, w.sigma)
+        assert g.num_leaves() == d.num_leaves() and g.last_counts() == d.last_counts()
+    assert g.export_state() == d.export_state()
+    g.close()
+    d.close()
+
+
 def test_bounds_build_reports_a_bad_index():
     # no restructuring: only the sweeps (which check and redirect) read the
     # corrupted entry
