@@ -11,7 +11,7 @@ import pytest
 import oracle
 from oracle import Oracle
 from paper_1608_07411_amd import synth
-from tests.helpers import TAU32, base_params, blob_set, blob_volumes, parse_views, plane_volumes
+from tests.helpers import TAU32, base_params, blob_set, blob_set_leaves, blob_volumes, parse_views, plane_volumes
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -317,6 +317,33 @@ def test_no_observations_parity():
     assert len(e["keys"]) == 8 ** w.max_depth and np.all(e["u"] == 0.0)
     assert g.energy() == (0.0, 0.0)
 
+
+
+@pytest.mark.parametrize("lam_scale", [0.0, 1.0])
+def test_subnormal_values_parity(lam_scale):
+    """Leaf values in the fp32 subnormal range (integers times 2^-140) go through
+    the sweep unflushed: bit-identical to the oracle, and with lambda = 0 every
+    u and nearly every p is still a nonzero subnormal afterwards. With the
+    workload's lambda every leaf here is observed, so the first prox steps
+    start from subnormal u and end at range values."""
+    w = _small_sphere(restructure_every=0)
+    blob = Oracle("f32").build(w.depth, w.cams, w.params).export_state()
+    n = len(Oracle("f32").import_state(blob).extract()["u"])
+    u = (np.random.default_rng(1).integers(-1000, 1001, n) * 2.0 ** -140).astype(np.float32)
+    blob = blob_set_leaves(blob, u=u, ubar=u, p=np.zeros((n, 3), np.float32))
+    g, o = _ctx().import_state(blob), Oracle("f32").import_state(blob)
+    lam = lam_scale * w.lam
+    for done in (3, 6):
+        g.fuse(3, lam, w.tau, w.sigma)
+        o.fuse(3, lam, w.tau, w.sigma)
+        _same_leaves(g.extract(), o.extract(), f"after {done} iterations")
+    e = g.extract()
+    tiny = np.finfo(np.float32).tiny
+    sub_u = (e["u"] != 0) & (np.abs(e["u"]) < tiny)
+    sub_p = (e["p"] != 0) & (np.abs(e["p"]) < tiny)
+    if lam_scale == 0.0:
+        assert sub_u.all() and sub_p.mean() > 0.99
+    assert g.export_state() == o.export_state()
 
 @pytest.mark.parametrize("n_views", [1, 64])
 def test_view_count_extremes_parity(n_views):

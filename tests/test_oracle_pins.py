@@ -14,8 +14,8 @@ import pytest
 import oracle
 from oracle import Oracle, morton_decode
 from paper_1608_07411_amd import synth
-from tests.helpers import (TAU32, base_params, blob_volumes, blob_get, blob_set, leaf_boxes, parse_views, plane_volumes,
-                           to_dense)
+from tests.helpers import (TAU32, base_params, blob_volumes, blob_get, blob_set, blob_set_leaves, leaf_boxes, parse_views,
+                           plane_volumes, to_dense)
 
 
 # ---------------------------------------------------------------------------
@@ -490,6 +490,37 @@ def test_fixed_point_residual_non_increasing():
     assert np.all(res[1:] <= res[:-1] * (1 + 1e-9) + 1e-15)
     assert res[-1] < res[0]
 
+
+
+def test_subnormal_values_survive_the_iteration():
+    """Denormals are kept, not flushed. With lambda = 0 the prox is the identity
+    and, while every |p| stays far below 1, the projection is too, so the
+    primal-dual step (Sec. 3) is linear in (u, p): the same start scaled by
+    2^-100 must give the same result scaled by 2^-100. Starting from u in the
+    subnormal range (integers times 2^-140), the fp32 oracle therefore has to
+    agree with its own normal-range run to within a few units of the smallest
+    subnormal, 2^-149, per value; flushing to zero would be off by up to 5e5
+    of them."""
+    w = synth.sphere_workload(max_depth=5, n_views=4, W=80, H=60, f=75.0, restructure_every=0)
+    blob = Oracle("f32").build(w.depth, w.cams, w.params).export_state()
+    n = len(Oracle("f32").import_state(blob).extract()["u"])
+    k = np.random.default_rng(1).integers(-1000, 1001, n).astype(np.float64)
+
+    def run(scale):
+        u = (k * scale).astype(np.float32)
+        assert np.array_equal(u.astype(np.float64), k * scale)
+        o = Oracle("f32").import_state(blob_set_leaves(blob, u=u, ubar=u, p=np.zeros((n, 3), np.float32)))
+        o.fuse(6, 0.0, w.tau, w.sigma)
+        return o.extract()
+
+    sub, nrm = run(2.0 ** -140), run(2.0 ** -40)
+    q = 2.0 ** -149
+    tiny = np.finfo(np.float32).tiny
+    for key in ("u", "p"):
+        assert np.abs(nrm[key]).max() < 1e-6  # the projection never acts
+        a = sub[key]
+        assert np.all(np.abs(a) < tiny) and np.mean(a != 0) > 0.99, key
+        assert np.abs(a - nrm[key] * 2.0 ** -100).max() <= 16 * q, key
 
 def _dp_1d(Fx, lam_x, cands):
     """Exact minimum of sum_x lam_x * sum_i |u_x - F_i(x)| + sum_x |u_{x+1} - u_x|
