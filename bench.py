@@ -30,15 +30,16 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 SWEEP_SOURCES = ("paper_1608_07411_amd/csrc/sweep.hip",)  # the sweep kernels' source
+MESH_SOURCES = ("paper_1608_07411_amd/csrc/mesh.hip",)  # the evaluation kernels' source
 
 
-def traffic_ratio(kernel: str, workload: str):
+def traffic_ratio(kernel: str, workload: str, sources=SWEEP_SOURCES):
     """Hardware-to-algorithmic byte ratio of a kernel from its committed profile.
 
     The profile records FETCH_SIZE/WRITE_SIZE (scaled by a plain copy's
     reading) over algorithmic bytes for the same dispatches, and a hash of the
-    sweep sources; a hash that no longer matches means the kernel has changed
-    since the counters were taken, and no ratio is returned.
+    kernel's sources; a hash that no longer matches means the kernel has
+    changed since the counters were taken, and no ratio is returned.
     """
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
     if not os.path.exists(path):
@@ -48,7 +49,7 @@ def traffic_ratio(kernel: str, workload: str):
         if " " in line:
             k, v = line.split(" ", 1)
             rec[k] = v.strip()
-    src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in SWEEP_SOURCES)
+    src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in sources)
     if rec.get("source_sha256_16") != hashlib.sha256(src).hexdigest()[:16]:
         return None
     try:
@@ -88,6 +89,9 @@ def parse_args():
                          "solver's final energy (1e-4 relative) from the plain and the warm start on held-out scenes")
     ap.add_argument("--warm-scenes", type=int, default=2000, help="--warm: training scenes")
     ap.add_argument("--warm-seeds", type=int, default=10, help="--warm: held-out multi-object scenes (seeds from 10000)")
+    ap.add_argument("--mesh", action="store_true",
+                    help="meshing and Eq. 7 at the finest grid of the chosen workload after --warmup + --steps "
+                         "iterations: finest-grid field, quantisation error, marching cubes, --replays times")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized buffer on the GPU 5 times (reference for hardware byte counters)")
     return ap.parse_args()
@@ -510,8 +514,88 @@ def run_convergence(args):
     print(json.dumps(result), flush=True)
 
 
+def run_mesh(args):
+    """Meshing and Eq. 7 at the finest grid (512^3 voxels on the depth-9 thin
+    workload): after --warmup iterations the finest-grid field is kept as the
+    reference, --steps more iterations run, then --replays repetitions of the
+    finest-grid field (into a device tensor), the quantisation error of Eq. 7
+    against the reference field, and marching cubes at iso 0 (the count call,
+    then the call that copies the triangles to the host). The field and Eq. 7
+    are timed with events on the library's stream (torch's current stream);
+    marching cubes, whose output is host memory, by the host clock."""
+    import torch
+
+    from paper_1608_07411_amd import otf, synth
+
+    maker = {"thin": synth.thin_workload, "blocks": synth.blocks_workload, "sphere": synth.sphere_workload}
+    w = maker[args.workload](seed=args.seed)
+    D = w.max_depth
+    nvox = 1 << (3 * D)
+    ctx = otf.Context(0).build_octree(torch.from_numpy(w.depth).cuda(), w.cams, w.params)
+    ctx.fuse(args.warmup, w.lam, w.tau, w.sigma)
+    ref = ctx.dense_field(torch.empty(nvox, dtype=torch.float32, device="cuda")).clone()
+    ctx.fuse(args.steps, w.lam, w.tau, w.sigma)
+    L = ctx.num_leaves()
+    out = torch.empty(nvox, dtype=torch.float32, device="cuda")
+    log(f"[mesh] {w.name} depth {D}: {L} leaves after {args.warmup} + {args.steps} iterations")
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, r
+
+    def event_timed(fn):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        r = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return 1e-3 * e0.elapsed_time(e1), r
+
+    event_timed(lambda: ctx.dense_field(out))  # first call: the library's scratch grows
+    rows = []
+    for r in range(max(1, args.replays)):
+        t_dense, _ = event_timed(lambda: ctx.dense_field(out))
+        t_q, q = event_timed(lambda: ctx.quantisation_error(ref))
+        t_mesh, (xyz, ed) = timed(lambda: ctx.mesh(0.0))
+        rows.append(dict(dense_ms=1e3 * t_dense, eq7_ms=1e3 * t_q, mesh_ms=1e3 * t_mesh, eq7=q, triangles=len(xyz)))
+        log(f"[mesh] replay {r + 1}: {rows[-1]}")
+    med = {k: float(np.median([row[k] for row in rows])) for k in ("dense_ms", "eq7_ms", "mesh_ms")}
+    ntri = rows[-1]["triangles"]
+    # the finest-grid field: written once (4 B per voxel), every leaf's u and
+    # key read once
+    dense_bytes = 4 * nvox + 8 * L
+    achieved = dense_bytes / (med["dense_ms"] * 1e-3) / 1e9
+    ratio = traffic_ratio("dense_field", f"{w.name}_depth{D}", MESH_SOURCES)
+    result = {
+        "metric": "finest voxels meshed per second", "value": nvox / (med["mesh_ms"] * 1e-3), "unit": "voxels/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{w.name}: marching cubes and Eq. 7 on the {1 << D}^3 finest grid after "
+                               f"{args.warmup} + {args.steps} iterations (split/join every iteration)",
+                   "leaves": L, "triangles": ntri, "voxels": nvox},
+        "median_ms": med, "eq7": rows[-1]["eq7"],
+        "roofline": {"bound": "hbm", "kernel": "k_dense (finest-grid field; with the chunk-range launch before it)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None if ratio is None else ratio * dense_bytes,
+                     "algorithmic_bytes_per_launch": dense_bytes, "avg_launch_ms": med["dense_ms"],
+                     "bytes_definition": "4 per finest voxel written + 8 per leaf (u and key) read"},
+        "mesh_note": ("mesh_ms: the count call and the call that copies the triangles (36 B of vertices and "
+                      "24 B of edge ids each) to the host; each call resamples the field"),
+        "replays": rows,
+    }
+    ctx.close()
+    print(json.dumps(result), flush=True)
+
+
 def main():
     args = parse_args()
+    if args.mesh:
+        run_mesh(args)
+        return
     if args.convergence:
         run_convergence(args)
         return
@@ -602,7 +686,7 @@ def main():
     kern = {k: per_launch(k) for k in ("dual", "primal")}
     sweep_s = (kern["dual"]["avg_ms"] + kern["primal"]["avg_ms"]) * 1e-3
     sweep_bytes = kern["dual"]["method_bytes"] + kern["primal"]["method_bytes"]
-    ratio = traffic_ratio("leaf_sweep", f"{w.name}_depth{w.max_depth}") if args.solver == "pd" else None
+    ratio = traffic_ratio({"pd": "leaf_sweep", "gd": "gd_sweep"}[args.solver], f"{w.name}_depth{w.max_depth}")
     names = {"pd": "k_dual + k_primal", "gd": "k_dual (flux) + k_gd_update"}
     achieved = sweep_bytes / sweep_s / 1e9
     roofline = {

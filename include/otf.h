@@ -270,7 +270,7 @@ otf_status otf_dense_field(otf_ctx *ctx, float *out, int32_t out_is_device, int6
  * of the edge's lower voxel (equal ids = the same vertex). Host arrays of
  * `capacity` triangles; *n_tris = the count. Errors: OTF_E_INVALID,
  * OTF_E_STATE, OTF_E_CAPACITY (capacity too small or null arrays; *n_tris is
- * set, nothing copied). Needs 9 bytes of device memory per finest voxel. */
+ * set, nothing copied). Needs 4 bytes of device memory per finest voxel. */
 otf_status otf_mesh(otf_ctx *ctx, float iso, int64_t capacity, float *xyz, uint64_t *edges, int64_t *n_tris);
 
 /* Eq. 7: sum over leaves n of |u(n) - mean of `dense` over the finest voxels

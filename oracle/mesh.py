@@ -32,21 +32,49 @@ def dense_from_leaves(keys, levels, u, D: int) -> np.ndarray:
     return out
 
 
-def crossing_vertices(dense: np.ndarray, iso: float, D: int):
+def _morton_encode(x, y, z) -> np.ndarray:
+    x, y, z = (np.asarray(a, dtype=np.uint64) for a in (x, y, z))
+    k = np.zeros(np.broadcast(x, y, z).shape, np.uint64)
+    for b in range(10):
+        k |= ((x >> np.uint64(b)) & np.uint64(1)) << np.uint64(3 * b)
+        k |= ((y >> np.uint64(b)) & np.uint64(1)) << np.uint64(3 * b + 1)
+        k |= ((z >> np.uint64(b)) & np.uint64(1)) << np.uint64(3 * b + 2)
+    return k
+
+
+def dense_box(keys, levels, u, D: int, origin, shape) -> np.ndarray:
+    """The finest-grid field on the box of `shape` (nz, ny, nx) voxels at
+    `origin` (x, y, z): every voxel takes u of the leaf containing it, the
+    last leaf in Morton order whose key is at most the voxel's code."""
+    ox, oy, oz = origin
+    nz, ny, nx = shape
+    zz, yy, xx = np.meshgrid(np.arange(oz, oz + nz), np.arange(oy, oy + ny), np.arange(ox, ox + nx),
+                             indexing="ij")
+    code = _morton_encode(xx, yy, zz)
+    i = np.searchsorted(np.asarray(keys, dtype=np.uint64), code, side="right") - 1
+    return np.asarray(u, dtype=np.float32)[i]
+
+
+def crossing_vertices(dense: np.ndarray, iso: float, D: int, origin=(0, 0, 0)):
     """Edge ids (3 * ((z G + y) G + x) + axis of the lower voxel), sorted, and
-    their vertex positions (N, 3) float32 in world coordinates."""
+    their vertex positions (N, 3) float32 in world coordinates, of the edges
+    whose two voxels lie in `dense`: the whole finest grid (G^3), or a box of
+    it whose first voxel is `origin` (x, y, z)."""
     G = 1 << D
     h = np.float32(2.0 ** -D)
     iso = np.float32(iso)
     below = dense < iso
+    nz, ny, nx = dense.shape
+    ox, oy, oz = origin
+    zz, yy, xx = np.meshgrid(np.arange(oz, oz + nz), np.arange(oy, oy + ny), np.arange(ox, ox + nx),
+                             indexing="ij")
     ids, pos = [], []
-    zz, yy, xx = np.meshgrid(np.arange(G), np.arange(G), np.arange(G), indexing="ij")
     for axis in range(3):
         sl_lo = [slice(None)] * 3
         sl_hi = [slice(None)] * 3
         ax = 2 - axis  # array axis of the grid axis (arrays are [z, y, x])
-        sl_lo[ax] = slice(0, G - 1)
-        sl_hi[ax] = slice(1, G)
+        sl_lo[ax] = slice(0, dense.shape[ax] - 1)
+        sl_hi[ax] = slice(1, dense.shape[ax])
         lo, hi = tuple(sl_lo), tuple(sl_hi)
         m = below[lo] != below[hi]
         v0 = dense[lo][m]

@@ -314,6 +314,7 @@ struct Scratch {
     DBuf<uint32_t> nb_j, nb_m;                          // faces located by the count pass, for the fill
     DBuf<uint32_t> part;                                // per-block partial counts
     DBuf<unsigned char> mc_table;                       // marching-cubes case table (device)
+    DBuf<uint32_t> mesh_first;                          // first leaf of each chunk of the finest grid
     // restructure temporaries (grow-only: an allocation or free per iteration
     // would synchronise the device)
     DBuf<uint8_t> r_sf, r_tM, r_tU, r_isnew, r_Mt;

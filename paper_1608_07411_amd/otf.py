@@ -136,6 +136,23 @@ def _stream_handle(stream):
     return C.c_void_p(0)
 
 
+def _host_arrays(*specs):
+    """Host arrays of the given (shape, dtype) for device-to-host copies: in
+    page-locked memory when torch has a GPU (a copy into pageable memory is
+    staged by the runtime at a fraction of the rate), else plain numpy."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            out = []
+            for shape, dt in specs:
+                t = torch.empty(int(np.prod(shape)) * np.dtype(dt).itemsize, dtype=torch.uint8, pin_memory=True)
+                out.append(t.numpy().view(dt).reshape(shape))
+            return out
+    except ImportError:
+        pass
+    return [np.empty(shape, dt) for shape, dt in specs]
+
+
 class Context:
     """One fused octree on one GPU (otf_ctx)."""
 
@@ -237,8 +254,7 @@ class Context:
         st = self._lib.otf_mesh(self.h, iso, 0, None, None, C.byref(n))
         if st not in (0, 3):
             self._check(st, "otf_mesh")
-        xyz = np.zeros((max(n.value, 1), 3, 3), np.float32)
-        ed = np.zeros((max(n.value, 1), 3), np.uint64)
+        xyz, ed = _host_arrays(((max(n.value, 1), 3, 3), np.float32), ((max(n.value, 1), 3), np.uint64))
         if n.value > 0:
             self._check(self._lib.otf_mesh(self.h, iso, n.value, _ptr(xyz), _ptr(ed), C.byref(n)), "otf_mesh")
         return xyz[:n.value], ed[:n.value]

@@ -9,9 +9,10 @@ from collections import Counter
 import numpy as np
 import pytest
 
+from oracle import Oracle
 from oracle import mesh as om
 from paper_1608_07411_amd import synth
-from tests.helpers import TAU32
+from tests.helpers import TAU32, base_params, blob_volumes
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -128,3 +129,32 @@ def test_quantisation_error_matches_oracle():
     dev = torch.from_numpy(ref_field).cuda()
     assert g.quantisation_error(dev) == e
     assert g.quantisation_error(g.dense_field()) == 0.0
+
+
+@pytest.mark.parametrize("D", [3, 5, 7])
+def test_eval_on_unbalanced_trees_matches_oracle(D):
+    """The field, Eq. 7 and the vertex set on trees built from volumes: one
+    chunk of the finest grid holding many leaves (depth 3), several chunks
+    (depth 5), and leaves larger than a chunk (depth 7). The field and the
+    vertex set bit for bit; Eq. 7 against a random reference field to 1e-9
+    (double sums in another order), and exactly 0 against the own field."""
+    f, wv = blob_volumes(3, D, seed=D)
+    o = Oracle("f32").build_volumes(f, wv, base_params(D))
+    g = otf.Context(0).import_state(o.export_state())
+    g.fuse(3, 0.5, TAU32, TAU32)
+    lv = g.extract()
+    if D == 7:
+        assert (lv["levels"] < D - 4).any(), "no leaf larger than a chunk"
+    ref = om.dense_from_leaves(lv["keys"], lv["levels"], lv["u"], D)
+    assert np.array_equal(g.dense_field(), ref)
+    rnd = np.random.default_rng(D).standard_normal(ref.shape).astype(np.float32)
+    e, e_ref = g.quantisation_error(rnd), om.quantisation_error(lv["keys"], lv["levels"], lv["u"], rnd, D)
+    assert abs(e - e_ref) <= 1e-9 * max(1.0, e_ref)
+    assert g.quantisation_error(ref) == 0.0
+    xyz, ed = g.mesh(0.0)
+    uid, first = np.unique(ed.reshape(-1), return_index=True)
+    ref_ids, ref_pos = om.crossing_vertices(ref, 0.0, D)
+    assert len(ref_ids) > 0
+    assert np.array_equal(uid, ref_ids)
+    assert np.array_equal(xyz.reshape(-1, 3)[first], ref_pos)
+    _topology(ed)

@@ -68,3 +68,33 @@ def test_quantisation_error_of_fields_built_from_the_leaves():
     e = om.quantisation_error(lv["keys"], lv["levels"], lv["u"], shifted, D)
     # |u - (u + 0.25)| per leaf, up to the float32 rounding of u + 0.25
     assert abs(e - 0.25 * len(lv["u"])) < 1e-6 * len(lv["u"])
+
+
+def test_box_forms_agree_with_the_whole_grid():
+    """The box forms of the resampling and of the vertex set, used where the
+    grid is too large for the whole-grid forms, restrict them exactly: the
+    field of a box is that box of the whole field, and the box's vertices are
+    the whole grid's vertices whose edge has both voxels in the box."""
+    lv, D = _small()
+    G = 1 << D
+    full = om.dense_from_leaves(lv["keys"], lv["levels"], lv["u"], D)
+    ids, pos = om.crossing_vertices(full, 0.0, D)
+    assert len(ids) > 50
+    vox, axis = ids // 3, ids % 3
+    vx, vy, vz = vox % G, (vox // G) % G, vox // (G * G)
+    # boxes around two vertices' voxels
+    a, b = len(ids) // 3, 2 * len(ids) // 3
+    def at(i, back, shape):  # a box inside the grid, from `back` voxels before vertex i's voxel
+        return tuple(min(max(0, int(v[i]) - back), G - n) for v, n in zip((vx, vy, vz), shape[::-1]))
+
+    boxes = (((0, 0, 0), (G, G, G)), (at(a, 2, (5, 6, 7)), (5, 6, 7)), (at(b, 1, (7, 4, 5)), (7, 4, 5)))
+    for k, (origin, shape) in enumerate(boxes):
+        (ox, oy, oz), (nz, ny, nx) = origin, shape
+        box = om.dense_box(lv["keys"], lv["levels"], lv["u"], D, origin, shape)
+        assert np.array_equal(box, full[oz:oz + nz, oy:oy + ny, ox:ox + nx])
+        bi, bp = om.crossing_vertices(box, 0.0, D, origin)
+        ex, ey, ez = vx + (axis == 0), vy + (axis == 1), vz + (axis == 2)
+        inside = ((vx >= ox) & (ex < ox + nx) & (vy >= oy) & (ey < oy + ny) & (vz >= oz) & (ez < oz + nz))
+        assert np.array_equal(bi, ids[inside])
+        assert np.array_equal(bp, pos[inside])
+        assert k == 0 or 0 < inside.sum() < len(ids)

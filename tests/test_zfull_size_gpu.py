@@ -17,6 +17,11 @@ properties that hold at any size.
   split and join on the GPU and in the fp32 oracle from that state (the
   dual step, divergence, prox, split/join decisions and the fetch of new
   leaves) and 5 more, bit for bit.
+* Evaluation at full size (the 512^3 finest grid): the field and the
+  marching-cubes vertex set on sampled boxes around mesh vertices against the
+  oracle's box forms, bit for bit; Eq. 7 is 0 against the own field and,
+  against the field of the same leaves with perturbed values u', equals the
+  sum of |u - u'| (the mean of a constant over a leaf is exact).
 * Structure and dual feasibility after iterations with split and join: the
   leaves tile the domain in Morton order, every p has norm at most 1 (up to
   one rounding), and every leaf has |u| >= tau_s or lies at the maximum depth
@@ -27,7 +32,9 @@ import numpy as np
 import pytest
 
 import oracle
+from oracle import mesh as om
 from paper_1608_07411_amd import state, synth
+from tests.helpers import blob_set_leaves
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -143,3 +150,48 @@ def test_full_size_cube_parity(work):
             assert g.export_state() == o.export_state(), f"state after {it + 1} iterations"
     print(f"cube: 6 iterations identical, {g.num_leaves()} leaves", flush=True)
     g.close()
+
+
+def test_full_size_evaluation_on_sampled_boxes(work):
+    w = work
+    D = w.max_depth
+    G = 1 << D
+    c = otf.Context(0).build_octree(torch.from_numpy(w.depth).cuda(), w.cams, w.params)
+    c.fuse(4, w.lam, w.tau, w.sigma)
+    lv = c.extract()
+    L = lv["keys"].size
+    field = c.dense_field(torch.empty(G ** 3, dtype=torch.float32, device="cuda")).view(G, G, G)
+    xyz, ed = c.mesh(0.0)
+    print(f"full-size evaluation: {L} leaves, {len(xyz)} triangles", flush=True)
+    assert len(xyz) > 10000
+    ids = ed.reshape(-1)
+    pts = xyz.reshape(-1, 3)
+    rng = np.random.default_rng(7)
+    n = 24
+    for k in rng.choice(ids.size, 4, replace=False):
+        vox = int(ids[k]) // 3
+        v = (vox % G, (vox // G) % G, vox // (G * G))
+        origin = tuple(min(max(0, int(a) - n // 2), G - n) for a in v)
+        ox, oy, oz = origin
+        box = om.dense_box(lv["keys"], lv["levels"], lv["u"], D, origin, (n, n, n))
+        assert np.array_equal(field[oz:oz + n, oy:oy + n, ox:ox + n].cpu().numpy(), box)
+        bid, bpos = om.crossing_vertices(box, 0.0, D, origin)
+        vv, ax = ids // 3, ids % 3
+        vx, vy, vz = vv % G, (vv // G) % G, vv // (G * G)
+        inside = ((vx >= ox) & (vx + (ax == 0) < ox + n) & (vy >= oy) & (vy + (ax == 1) < oy + n)
+                  & (vz >= oz) & (vz + (ax == 2) < oz + n))
+        gid, first = np.unique(ids[inside], return_index=True)
+        assert len(bid) > 0
+        assert np.array_equal(gid, bid)
+        assert np.array_equal(pts[inside][first], bpos)
+    assert c.quantisation_error(field.view(-1)) == 0.0
+    # the same leaves with values moved by multiples of 2^-12 in [-0.5, 0.5]
+    d = (rng.integers(-2048, 2049, L) * 2.0 ** -12).astype(np.float32)
+    u2 = (lv["u"] + d).astype(np.float32)
+    other = otf.Context(0).import_state(blob_set_leaves(c.export_state(), u=u2))
+    field2 = other.dense_field(torch.empty(G ** 3, dtype=torch.float32, device="cuda"))
+    other.close()
+    e = c.quantisation_error(field2)
+    e_ref = float(np.sum(np.abs(lv["u"].astype(np.float64) - u2.astype(np.float64))))
+    assert abs(e - e_ref) <= 1e-12 * e_ref
+    c.close()
