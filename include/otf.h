@@ -218,6 +218,14 @@ otf_status otf_import_state(otf_ctx *ctx, const void *buf, int64_t n_bytes);
 otf_status otf_profile(otf_ctx *ctx, int32_t enable);
 otf_status otf_profile_read(otf_ctx *ctx, double *ms, int64_t *launches, int64_t *leaf_updates, double *bytes);
 
+/* The evaluation's kernels timed the same way while otf_profile is enabled
+ * (Sec. 3.2 meshing, Eq. 7): ms[4] (summed milliseconds) and launches[4] for
+ * 0 the finest-grid field kernel of otf_dense_field, otf_mesh and
+ * otf_quantisation_error, 1 the Eq. 7 kernels, 2 the marching-cubes count
+ * kernel, 3 the marching-cubes emit kernel. Reset by otf_profile; either
+ * pointer may be NULL. */
+otf_status otf_profile_read_eval(otf_ctx *ctx, double *ms, int64_t *launches);
+
 /* Self-test of the device prefix scans every compaction above relies on:
  * n pseudo-random elements (splitmix64 from seed) are scanned on the context's
  * device (exclusive sums of bytes and of words, two scans sharing a launch,

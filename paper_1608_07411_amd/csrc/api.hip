@@ -1161,7 +1161,7 @@ otf_status otf_profile_read(otf_ctx *ctx, double *ms, int64_t *launches, int64_t
     return guard(ctx, false, [&] {
         Ctx &c = ctx->c;
         prof_collect(c);
-        for (int k = 0; k < kProfKinds; ++k) {
+        for (int k = 0; k < kProfSolverKinds; ++k) {
             if (ms) ms[k] = c.prof_ms[k];
             if (launches) launches[k] = c.prof_n[k];
         }
@@ -1174,6 +1174,18 @@ otf_status otf_profile_read(otf_ctx *ctx, double *ms, int64_t *launches, int64_t
             bytes[1] = c.alg_bytes[1] + 4.0 * (double)obs_acc;
             bytes[2] = c.alg_bytes[2];
             bytes[3] = c.alg_bytes[3] + 4.0 * (double)obs_acc;
+        }
+    });
+}
+
+otf_status otf_profile_read_eval(otf_ctx *ctx, double *ms, int64_t *launches) {
+    if (!ctx) return OTF_E_INVALID;
+    return guard(ctx, false, [&] {
+        Ctx &c = ctx->c;
+        prof_collect(c);
+        for (int k = 0; k < kProfKinds - kProfSolverKinds; ++k) {
+            if (ms) ms[k] = c.prof_ms[kProfSolverKinds + k];
+            if (launches) launches[k] = c.prof_n[kProfSolverKinds + k];
         }
     });
 }

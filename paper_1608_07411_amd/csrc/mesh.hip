@@ -558,8 +558,10 @@ void dense_field(Ctx &c, float *dense) {
     const Chunking ck = chunking(c.prm.max_depth);
     const uint32_t *first = chunk_first(c, ck);
     LeafStore &s = c.lv();
+    prof_begin(c);
     hipLaunchKernelGGL(k_dense, dim3((unsigned)(ck.n / ck.pair)), dim3(kBlk * ck.pair), 0, c.stream, s.key.p,
                        s.level.p, s.u.p, first, ck, dense);
+    prof_end(c, kProfField);
     OTF_LAUNCH_CHECK("k_dense");
 }
 
@@ -580,7 +582,9 @@ int64_t marching_cubes(Ctx &c, float iso, int64_t cap, float *h_xyz, unsigned lo
     cnt.reserve((size_t)rows);
     first.reserve((size_t)rows + 1);
     const unsigned blocks = (unsigned)cdiv(rows, kBlk / 64);
+    prof_begin(c);
     hipLaunchKernelGGL(k_mc_count, dim3(blocks), dim3(kBlk), 0, c.stream, dense.p, D, iso, tab, cnt.p);
+    prof_end(c, kProfMcCount);
     OTF_LAUNCH_CHECK("k_mc_count");
     // a row holds at most 12 triangles per cell; past 2^32 in all, the 32-bit
     // offsets would wrap
@@ -599,8 +603,10 @@ int64_t marching_cubes(Ctx &c, float iso, int64_t cap, float *h_xyz, unsigned lo
     DBuf<unsigned long long> edge;
     xyz.reserve((size_t)(9 * ntri));
     edge.reserve((size_t)(3 * ntri));
+    prof_begin(c);
     hipLaunchKernelGGL(k_mc_emit, dim3(blocks), dim3(kBlk), 0, c.stream, dense.p, D, iso, tab, first.p, xyz.p,
                        edge.p);
+    prof_end(c, kProfMcEmit);
     OTF_LAUNCH_CHECK("k_mc_emit");
     OTF_HIP(hipMemcpyAsync(h_xyz, xyz.p, sizeof(float) * 9 * ntri, hipMemcpyDeviceToHost, c.stream));
     OTF_HIP(hipMemcpyAsync(h_edge, edge.p, sizeof(unsigned long long) * 3 * ntri, hipMemcpyDeviceToHost, c.stream));
@@ -622,6 +628,7 @@ double quantisation_error(Ctx &c, const float *dense_dev) {
     part.reserve((size_t)(ck.n + nb));
     LeafStore &s = c.lv();
     const uint32_t *first = chunk_first(c, ck);
+    prof_begin(c);
     hipLaunchKernelGGL(k_quant_chunk, dim3((unsigned)(ck.n / ck.pair)), dim3(kBlk * ck.pair), 0, c.stream, s.key.p,
                        s.level.p, s.u.p, first, ck, dense_dev, csum.p, part.p);
     OTF_LAUNCH_CHECK("k_quant_chunk");
@@ -639,6 +646,7 @@ double quantisation_error(Ctx &c, const float *dense_dev) {
     OTF_LAUNCH_CHECK("k_pyr_up");
     hipLaunchKernelGGL(k_quant_coarse, dim3((unsigned)nb), dim3(kBlk), 0, c.stream, L, D, q0, s.key.p, s.level.p,
                        s.u.p, pl, part.p + ck.n);
+    prof_end(c, kProfEq7);
     OTF_LAUNCH_CHECK("k_quant_coarse");
     std::vector<double> h((size_t)(ck.n + nb));
     OTF_HIP(hipMemcpyAsync(h.data(), part.p, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c.stream));

@@ -329,7 +329,20 @@ struct Scratch {
     }
 };
 
-enum ProfKind { kProfDual = 0, kProfPrimal = 1, kProfRestructure = 2, kProfEnergy = 3, kProfKinds = 4 };
+// Timed kinds: the solver's (read by otf_profile_read) and the evaluation's
+// (read by otf_profile_read_eval).
+enum ProfKind {
+    kProfDual = 0,
+    kProfPrimal = 1,
+    kProfRestructure = 2,
+    kProfEnergy = 3,
+    kProfSolverKinds = 4,
+    kProfField = 4,    // the finest-grid field kernel
+    kProfEq7 = 5,      // the Eq. 7 kernels
+    kProfMcCount = 6,  // the marching-cubes count kernel
+    kProfMcEmit = 7,   // the marching-cubes emit kernel
+    kProfKinds = 8
+};
 
 // Solver of the running fuse call: primal-dual, or the paper's gradient
 // descent (TV weight lam, step xi, smoothing eps^2); split children follow it.
@@ -389,8 +402,8 @@ struct Ctx {
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     hipEvent_t prof_open = nullptr;
-    double prof_ms[kProfKinds] = {0, 0, 0, 0};
-    int64_t prof_n[kProfKinds] = {0, 0, 0, 0};
+    double prof_ms[kProfKinds] = {};
+    int64_t prof_n[kProfKinds] = {};
     int64_t leaf_updates = 0;     // sum over iterations of the leaf count (always counted)
     // bytes of the dual and primal sweeps (always counted): as implemented
     // [0, 1], and the method's own per leaf-update [2, 3]

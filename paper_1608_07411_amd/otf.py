@@ -88,6 +88,7 @@ def lib(path: str = LIB_PATH):
             "otf_import_state": [P, P, I64],
             "otf_profile": [P, I32],
             "otf_profile_read": [P, P, P, P, P],
+            "otf_profile_read_eval": [P, P, P],
             "otf_batch_create": [C.c_int, P, P],
             "otf_batch_destroy": [P],
             "otf_batch_add": [P, P],
@@ -428,6 +429,14 @@ class Context:
         out["bytes"] = dict(dual=float(by[0]), primal=float(by[1]))
         out["method_bytes"] = dict(dual=float(by[2]), primal=float(by[3]))
         return out
+
+    def profile_read_eval(self) -> dict:
+        """Event-timed evaluation kernels: field, eq7, mc_count, mc_emit."""
+        ms = np.zeros(4)
+        n = np.zeros(4, np.int64)
+        self._check(self._lib.otf_profile_read_eval(self.h, _ptr(ms), _ptr(n)), "otf_profile_read_eval")
+        return {k: dict(ms=float(ms[i]), launches=int(n[i]))
+                for i, k in enumerate(("field", "eq7", "mc_count", "mc_emit"))}
 
     def reset_counters(self, profile: bool):
         """Zero the leaf-update and byte counters; enable or disable kernel timing."""

@@ -158,3 +158,20 @@ def test_eval_on_unbalanced_trees_matches_oracle(D):
     assert np.array_equal(uid, ref_ids)
     assert np.array_equal(xyz.reshape(-1, 3)[first], ref_pos)
     _topology(ed)
+
+
+def test_evaluation_kernel_timing():
+    """otf_profile_read_eval counts and times the evaluation kernels while
+    profiling is on, and otf_profile resets them."""
+    g, D = _fused(D=5, iters=3, eta=0.28125)
+    g.reset_counters(profile=True)
+    field = g.dense_field()
+    g.quantisation_error(field)
+    g.mesh(0.0)  # the count call, then the call that emits
+    k = g.profile_read_eval()
+    # the field: once by dense_field, once by each mesh call
+    assert {n: v["launches"] for n, v in k.items()} == {"field": 3, "eq7": 1, "mc_count": 2, "mc_emit": 1}
+    assert all(v["ms"] > 0 for v in k.values())
+    g.reset_counters(profile=False)
+    g.dense_field()
+    assert all(v["launches"] == 0 for v in g.profile_read_eval().values())
