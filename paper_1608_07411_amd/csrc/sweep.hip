@@ -581,6 +581,23 @@ __device__ inline void primal_store(const PrimalArgs &a, int64_t i, float v, flo
 // (primal_long_full in the same launch): then it stays in the wave's prox
 // loop, with a value that is not stored. Returns the wave's split and join
 // flag counts (the same on every lane).
+// wave_prox for two leaves at once, one per half-wave (segment s: lanes
+// 32 s .. 32 s + 31, lane sl of the segment holding breakpoint sl), for
+// leaves of at most 32 observations: per half the same operations and values.
+__device__ inline float half_prox(float Fk, float Pk, float upl, float tl_, float wtl, int Ml, int sl, int seg) {
+    const float S = __fmaf_rn(2.0f, Pk, -wtl);
+    const float pk = __fmaf_rn(-tl_, S, upl);
+    const bool pred = sl < Ml && pk > Fk;
+    const int ks = __popc((uint32_t)(__ballot(pred) >> (32 * seg)));
+    const float pend = __fmaf_rn(-tl_, wtl, upl);
+    const float pkk = __shfl(pk, 32 * seg + min(ks, 31), 64);
+    const float Fp = __shfl(Fk, 32 * seg + max(ks - 1, 0), 64);
+    const float pks = (ks < Ml) ? pkk : pend;
+    float v = (ks > 0) ? ((pks >= Fp) ? pks : Fp) : pks;
+    v = (Ml > 0) ? v : upl;
+    return v + 0.0f;
+}
+
 template <bool kLongInDs>
 __device__ inline void primal_wave(const PrimalArgs &a, const Coef &cf, int64_t i, uint32_t &n_split,
                                    uint32_t &n_join) {
@@ -615,7 +632,38 @@ __device__ inline void primal_wave(const PrimalArgs &a, const Coef &cf, int64_t 
     // bytes in flight per wave.
     const int nact = __popcll(__ballot(valid));
     float myv = 0.0f;
-    for (int l0 = 0; l0 < nact; l0 += kAhead) {
+    int mx = valid ? M : 0;  // the wave's largest observation count
+    for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+    if (mx <= 32) {
+        // two leaves per step, one per half-wave: leaves l0 + 2 g (lanes
+        // 0-31) and l0 + 2 g + 1 (lanes 32-63)
+        const int seg = lane >> 5, sl = lane & 31;
+        constexpr int kSteps = kAhead / 2;  // kAhead leaves in flight, as below
+        for (int l0 = 0; l0 < nact; l0 += 2 * kSteps) {
+            float Fr[kSteps], Pr[kSteps];
+            int Mg[kSteps];
+#pragma unroll
+            for (int g = 0; g < kSteps; ++g) {
+                const int l = min(l0 + 2 * g + seg, 63);
+                Mg[g] = __shfl(M, l, 64);
+                const uint32_t ool = (uint32_t)__shfl((int)oo, l, 64);
+                const uint32_t e = OTF_OBS(ool + (sl < Mg[g] ? (uint32_t)sl : 0u), a.n_obs);
+                Fr[g] = a.F[e];
+                Pr[g] = a.P[e];
+            }
+#pragma unroll
+            for (int g = 0; g < kSteps; ++g) {
+                const int lc = min(l0 + 2 * g + seg, 63);
+                const float upl = __shfl(up, lc, 64), tl_ = __shfl(t, lc, 64), wtl = __shfl(wt, lc, 64);
+                const float v = half_prox(Fr[g], Pr[g], upl, tl_, wtl, Mg[g], sl, seg);
+                const float v0 = rdlane(v, 0), v1 = rdlane(v, 32);
+                const int la = l0 + 2 * g;
+                myv = (lane == la && la < nact) ? v0 : myv;
+                myv = (lane == la + 1 && la + 1 < nact) ? v1 : myv;
+            }
+        }
+    }
+    for (int l0 = 0; mx > 32 && l0 < nact; l0 += kAhead) {
         float Fr[kAhead], Pr[kAhead];
         // unconditional loads (lanes past a segment's end, and leaves past
         // the wave's last, read its first entry, inside the pool's
