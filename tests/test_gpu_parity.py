@@ -345,6 +345,26 @@ def test_subnormal_values_parity(lam_scale):
         assert sub_u.all() and sub_p.mean() > 0.99
     assert g.export_state() == o.export_state()
 
+
+@pytest.mark.parametrize("n_views", [32, 33])
+def test_prox_wave_segment_boundary_parity(n_views):
+    """Leaves of 23 to 32 observations (32 views: every wave takes the prox of
+    two leaves per step on half-waves, up to all 32 lanes of a half) and up to
+    33 (33 views: a wave holding a leaf of 33 observations takes whole waves,
+    the others half-waves): bit-identical to the oracle through iterations
+    with split/join."""
+    f, wv = blob_volumes(n_views, 4, seed=n_views, p_unobs=0.1)
+    o = Oracle("f32").build_volumes(f, wv, base_params(4))
+    M = o.leaf_obs()["M"]
+    assert M.max() == n_views and M.min() < 32
+    g = _ctx().import_state(o.export_state())
+    for done in (5, 10):
+        g.fuse(5, 0.5, TAU32, TAU32)
+        o.fuse(5, 0.5, TAU32, TAU32)
+        _same_leaves(g.extract(), o.extract(), f"after {done} iterations")
+        assert g.last_counts() == o.last_counts()
+    assert g.export_state() == o.export_state()
+
 @pytest.mark.parametrize("n_views", [1, 64])
 def test_view_count_extremes_parity(n_views):
     """One view and the 64-view maximum (the fetch's segment of 64 lanes, one
