@@ -622,7 +622,7 @@ otf_status otf_selftest_scan(otf_ctx *ctx, int64_t n, uint64_t seed, int64_t *mi
             z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
             return z ^ (z >> 31);
         };
-        std::vector<uint8_t> a(n), b(n), f(n);
+        std::vector<uint8_t> a(n), b(n), f(n), e(n);
         std::vector<uint32_t> x(n), y(n);
         for (int64_t i = 0; i < n; ++i) {
             const uint64_t r = next();
@@ -633,15 +633,18 @@ otf_status otf_selftest_scan(otf_ctx *ctx, int64_t n, uint64_t seed, int64_t *mi
             f[i] = (uint8_t)((i > 0 && ((r >> 5) & 7) != 0 ? (f[i - 1] & 6) : jb) | ((r >> 8) & 1));
             x[i] = (uint32_t)((r >> 16) & 0xFFF);
             y[i] = (uint32_t)(r >> 40) & 0x3FF;
+            e[i] = (uint8_t)(((r >> 60) & 7) == 0);  // sparse flags, 1 in 8
         }
-        DBuf<uint8_t> da, db, df;
-        DBuf<uint32_t> dx, dy, o1, o2, o3, o4, o5, o6, o7;
+        DBuf<uint8_t> da, db, df, de;
+        DBuf<uint32_t> dx, dy, o1, o2, o3, o4, o5, o6, o7, l1, l2, l3, l4, t4;
         const int64_t m = n > 0 ? n : 1;
-        da.reserve(m); db.reserve(m); df.reserve(m); dx.reserve(m); dy.reserve(m);
-        for (DBuf<uint32_t> *o : {&o1, &o2, &o3, &o4, &o5, &o6, &o7}) o->reserve(m + 1);
+        da.reserve(m); db.reserve(m); df.reserve(m); de.reserve(m); dx.reserve(m); dy.reserve(m);
+        for (DBuf<uint32_t> *o : {&o1, &o2, &o3, &o4, &o5, &o6, &o7, &l1, &l2, &l3, &l4}) o->reserve(m + 1);
+        t4.reserve(4);
         upload(c, da.p, a);
         upload(c, db.p, b);
         upload(c, df.p, f);
+        upload(c, de.p, e);
         upload(c, dx.p, x);
         upload(c, dy.p, y);
         scan_exclusive_u32_dev_u8(c, da.p, o1.p, n);
@@ -649,6 +652,15 @@ otf_status otf_selftest_scan(otf_ctx *ctx, int64_t n, uint64_t seed, int64_t *mi
         scan_exclusive_pair_u32(c, dx.p, o4.p, dy.p, o5.p, n);
         scan_run_starts(c, df.p, o6.p, n);
         scan_exclusive_flag_bits(c, df.p, 1u, o7.p, n);
+        // compaction: whole lists, a pair of them, and a list cut at half its length
+        uint32_t nb = 0, ne = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            nb += b[i];
+            ne += e[i];
+        }
+        scan_compact_u8(c, de.p, l1.p, (uint32_t)m, t4.p, n);
+        scan_compact_pair_u8(c, db.p, l2.p, (uint32_t)m, t4.p + 1, de.p, l3.p, (uint32_t)m, t4.p + 2, n);
+        scan_compact_u8(c, db.p, l4.p, nb / 2, t4.p + 3, n);
         finish(c);
         auto g1 = download(c, o1.p, n + 1), g2 = download(c, o2.p, n + 1), g3 = download(c, o3.p, n + 1);
         auto g4 = download(c, o4.p, n + 1), g5 = download(c, o5.p, n + 1), g6 = download(c, o6.p, n);
@@ -671,6 +683,26 @@ otf_status otf_selftest_scan(otf_ctx *ctx, int64_t n, uint64_t seed, int64_t *mi
             sx += x[i];
             sy += y[i];
             sf += f[i] & 1u;
+        }
+        auto h1 = download(c, l1.p, m), h2 = download(c, l2.p, m), h3 = download(c, l3.p, m);
+        auto h4 = download(c, l4.p, m), ht = download(c, t4.p, 4);
+        finish(c);
+        bad += ht[0] != ne;
+        bad += ht[1] != nb;
+        bad += ht[2] != ne;
+        bad += ht[3] != nb;
+        uint32_t kb = 0, ke = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            if (b[i]) {
+                bad += h2[kb] != (uint32_t)i;
+                if (kb < nb / 2) bad += h4[kb] != (uint32_t)i;
+                ++kb;
+            }
+            if (e[i]) {
+                bad += h1[ke] != (uint32_t)i;
+                bad += h3[ke] != (uint32_t)i;
+                ++ke;
+            }
         }
         *mismatches = bad;
     });

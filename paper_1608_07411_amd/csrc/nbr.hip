@@ -121,8 +121,7 @@ struct Heavy {
 // marks and sources of both are loaded, then the four old offsets of both.
 constexpr int kCleanLeaves = 2;
 
-__global__ void __launch_bounds__(kBlk) k_nbr_count_clean(int64_t L, uint32_t *cnt_p, uint32_t *cnt_m, NbrOld old,
-                                                          const uint32_t *dpos, uint32_t *dirty) {
+__global__ void __launch_bounds__(kBlk) k_nbr_count_clean(int64_t L, uint32_t *cnt_p, uint32_t *cnt_m, NbrOld old) {
     constexpr int N = kCleanLeaves;
     int64_t idx[N];
     bool clean[N];
@@ -134,7 +133,6 @@ __global__ void __launch_bounds__(kBlk) k_nbr_count_clean(int64_t L, uint32_t *c
         const bool need = in && old.need[idx[n]];
         clean[n] = in && !need;
         j[n] = clean[n] ? old.src[idx[n]] : 0u;
-        if (need) dirty[dpos[idx[n]]] = (uint32_t)idx[n];
     }
     uint32_t p0[N], p1[N], m0[N], m1[N];
 #pragma unroll
@@ -530,19 +528,19 @@ NbrPending search_begin(Ctx &c, const NbrOld &old, bool need_scanned) {
     p.old = old;
     p.cap = (uint32_t)std::min<int64_t>(6 * L, std::max<int64_t>(4096, L / 8));
     // leaves to search: all of them, or (after a restructure) those marked in
-    // need, listed at their rank dpos[i]; their number dpos[L] stays on the device
+    // need, listed in dirty by a compacting scan; their number e[0] stays on
+    // the device
     if (old.need) {
         if (!need_scanned) {
-            c.s.e.reserve(L + 1);
-            scan_exclusive_u32_dev_u8(c, old.need, c.s.e.p, L);
+            c.s.e.reserve(1);
+            c.s.dirty.reserve(L);
+            scan_compact_u8(c, old.need, c.s.dirty.p, (uint32_t)L, c.s.e.p, L);
         }
-        c.s.dirty.reserve(L);
         const unsigned gc = (unsigned)std::max<int64_t>(1, cdiv(L, kCleanLeaves * kBlk));
-        hipLaunchKernelGGL(k_nbr_count_clean, dim3(gc), dim3(kBlk), 0, c.stream, L, c.s.a.p, c.s.b.p, old,
-                           (const uint32_t *)c.s.e.p, c.s.dirty.p);
+        hipLaunchKernelGGL(k_nbr_count_clean, dim3(gc), dim3(kBlk), 0, c.stream, L, c.s.a.p, c.s.b.p, old);
         OTF_LAUNCH_CHECK("k_nbr_count_clean");
         p.dirty = c.s.dirty.p;
-        p.n_dirty_dev = c.s.e.p + L;
+        p.n_dirty_dev = c.s.e.p;
     }
     p.ticket = count_pass(c, p, false);
     return p;

@@ -468,6 +468,11 @@ uint32_t scan_exclusive_u32(Ctx &c, const uint32_t *in, uint32_t *out, int64_t n
 // exclusive scan without a host read-back: out has n+1 entries, out[n] = total
 void scan_exclusive_u32_dev(Ctx &c, const uint32_t *in, uint32_t *out, int64_t n);
 void scan_exclusive_u32_dev_u8(Ctx &c, const uint8_t *in, uint32_t *out, int64_t n);
+// Compaction of 0/1 flags: list[r] = i for the r-th flagged i (r < cap), the
+// number of flags at *total_dev (device); the pair form in one launch.
+void scan_compact_u8(Ctx &c, const uint8_t *flags, uint32_t *list, uint32_t cap, uint32_t *total_dev, int64_t n);
+void scan_compact_pair_u8(Ctx &c, const uint8_t *a, uint32_t *list_a, uint32_t cap_a, uint32_t *total_a,
+                          const uint8_t *b, uint32_t *list_b, uint32_t cap_b, uint32_t *total_b, int64_t n);
 void scan_inclusive_max_u32(Ctx &c, const uint32_t *in, uint32_t *out, int64_t n);
 // two exclusive scans of the same length in one launch (out arrays of n+1)
 void scan_exclusive_pair_u8(Ctx &c, const uint8_t *a, uint32_t *out_a, const uint8_t *b, uint32_t *out_b, int64_t n);
@@ -529,8 +534,8 @@ struct NbrPending {
     uint32_t ticket, cap;
     const uint32_t *dirty, *n_dirty_dev;
 };
-// need_scanned: the exclusive scan of the new store's need flags (L+1
-// entries) is already in the scratch array s.e
+// need_scanned: the new store's need flags are already listed in the
+// scratch array s.dirty, their number at s.e[0]
 NbrPending build_neighbours_begin(Ctx &c, const LeafStore &old, const uint32_t *remap, bool need_scanned);
 void build_neighbours_end(Ctx &c, NbrPending &p, void (*overlap)(Ctx &));
 // sweeps

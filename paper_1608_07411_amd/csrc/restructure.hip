@@ -478,15 +478,6 @@ __global__ void k_zero_u32(int64_t n, uint32_t *a) {
     if (i < n) a[i] = 0u;
 }
 
-// idx[rank[i]] = i for flagged i; ranks at or above cap are dropped (the
-// host checks the total against cap)
-__global__ void k_compact_idx(int64_t n, const uint8_t *flag, const uint32_t *rank, uint32_t *idx, uint32_t cap) {
-    const int64_t i = TID();
-    if (i >= n || !flag[i]) return;
-    const uint32_t r = rank[i];
-    if (r < cap) idx[r] = (uint32_t)i;
-}
-
 // New leaves' observations from their rows (target t: row t * stride, Mt[t]
 // entries) to the pool at base + (off_t ? off_t[t] : off_leaf[tidx[t]]), one
 // wave per target; the segment offset goes into the leaf header.
@@ -586,13 +577,11 @@ void join_analysis(Ctx &c) {
     hipLaunchKernelGGL(k_join_target, dim3(gJ), dim3(kBlk), 0, c.stream, L, c.prm.max_depth, os.flag.p, os.key.p,
                        os.level.p, s.b.p, s.c.p, s.u8a.p, s.u8b.p, s.part.p, s.r_jcand.p);
     sum_parts(c, s.part.p, gJ, 1, gJ, c.counters.p + 2);
-    // the leaves that compute hierarchical means, listed (their number stays
-    // on the device, at r_jrank[L])
-    s.r_jrank.reserve(L + 1);
+    // the leaves that compute hierarchical means, listed by one compacting
+    // scan (their number stays on the device, at r_jrank[0])
+    s.r_jrank.reserve(1);
     s.r_jlist.reserve(L);
-    scan_exclusive_u32_dev_u8(c, s.r_jcand.p, s.r_jrank.p, L);
-    hipLaunchKernelGGL(k_compact_idx, dim3(gL), dim3(kBlk), 0, c.stream, L, s.r_jcand.p, s.r_jrank.p, s.r_jlist.p,
-                       (uint32_t)L);
+    scan_compact_u8(c, s.r_jcand.p, s.r_jlist.p, (uint32_t)L, s.r_jrank.p, L);
     OTF_LAUNCH_CHECK("join analysis");
 }
 
@@ -623,7 +612,7 @@ void join_values(Ctx &c, const uint8_t *jt, int &next, int count) {
             const int q = D - next;  // levels D-1 .. 0
             const unsigned gq = (unsigned)std::min<int64_t>(grid(L), 2048);
             hipLaunchKernelGGL(k_jval_level, dim3(gq), dim3(kBlk), 0, c.stream, (const uint32_t *)c.s.r_jlist.p,
-                               (const uint32_t *)c.s.r_jrank.p + L, L, D, q, jt, os.key.p, os.level.p, val.p, L);
+                               (const uint32_t *)c.s.r_jrank.p, L, D, q, jt, os.key.p, os.level.p, val.p, L);
         }
     }
     OTF_LAUNCH_CHECK("join means");
@@ -800,17 +789,17 @@ bool restructure(Ctx &c, float tl) {
 
     // ---- observations of the new leaves (append to the pool, or compact)
     DBuf<uint32_t> &nrank = s.r_nrank, &tidx = s.r_tidx, &moff = s.r_moff;
-    nrank.reserve(Lnew + 1);
-    // ranks of the new leaves, and of the leaves whose adjacency is searched
-    // again (for the adjacency pass), in one launch
-    s.e.reserve(Lnew + 1);
-    scan_exclusive_pair_u8(c, isnew.p, nrank.p, ns.need.p, s.e.p, Lnew);
+    // the new leaves (tidx, their number at nrank[0]) and the leaves whose
+    // adjacency is searched again (the adjacency pass's list, its length at
+    // e[0]), listed by one compacting scan of the two flag arrays
+    nrank.reserve(1);
+    s.e.reserve(1);
+    s.dirty.reserve(Lnew);
     tidx.reserve(n_new);
     // cleared first, so that every entry is a valid leaf index even if the
     // two counts of new leaves were to disagree (checked below)
     hipLaunchKernelGGL(k_zero_u32, dim3(grid(n_new)), dim3(kBlk), 0, c.stream, (int64_t)n_new, tidx.p);
-    hipLaunchKernelGGL(k_compact_idx, dim3(grid(Lnew)), dim3(kBlk), 0, c.stream, Lnew, isnew.p, nrank.p, tidx.p,
-                       n_new);
+    scan_compact_pair_u8(c, isnew.p, tidx.p, n_new, nrank.p, ns.need.p, s.dirty.p, (uint32_t)Lnew, s.e.p, Lnew);
     // one fetch pass: sorted observations into rows of n_views (headers
     // written into the new store), placed into the pool once its offsets are
     // known. It runs on the second stream, beside the new store's adjacency
@@ -839,7 +828,7 @@ bool restructure(Ctx &c, float tl) {
                     ns.obs_unit.p, ns.inv.p, ns.wtot.p);
         scan_exclusive_u32_dev_u8(c, Mt.p, moff.p, n_new);
         count_obs(c);
-        t_obs = read_back_begin_side(c, {{moff.p + n_new, 19}, {c.counters.p + 4, 20}, {nrank.p + Lnew, 21}});
+        t_obs = read_back_begin_side(c, {{moff.p + n_new, 19}, {c.counters.p + 4, 20}, {nrank.p, 21}});
         OTF_HIP(hipEventRecord(c.ev_join, c.side));
     }
     NbrPending nbr = build_neighbours_begin(c, os, out_off, true);

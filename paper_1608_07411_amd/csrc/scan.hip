@@ -220,21 +220,28 @@ __device__ inline uint64_t pack_state(uint32_t epoch, uint32_t status, uint32_t 
 
 // Two scans of the same length can share one launch: blocks [ntiles,
 // 2 ntiles) scan (in2, out2) with their own tile states.
+//
+// Compaction (bit 0 of `compact` for the first scan, bit 1 for the second;
+// inputs of 0 and 1 only, AddOp): instead of the ranks, out[r] = i for the
+// r-th element i that is 1 (r < cap), in index order; the total as usual.
 template <class In, class Op>
 __global__ void __launch_bounds__(kThreads) k_scan(In in, int64_t n, uint32_t *out, Op op, int exclusive,
                                                    int vec, uint32_t *total_out, unsigned long long *state,
                                                    uint32_t epoch, int64_t ntiles, uint32_t *health, In in2,
-                                                   uint32_t *out2, uint32_t *total_out2) {
+                                                   uint32_t *out2, uint32_t *total_out2, int compact, uint32_t cap,
+                                                   uint32_t cap2) {
     __shared__ uint32_t smem[kWaves];
     __shared__ uint32_t s_tile[kTileLds];
     __shared__ uint32_t s_prefix;
     const bool second = (int64_t)blockIdx.x >= ntiles;
     const int64_t tile = (int64_t)blockIdx.x - (second ? ntiles : 0);
+    const bool cmp = (compact & (second ? 2 : 1)) != 0;  // block-uniform
     if (second) {
         in = in2;
         out = out2;
         total_out = total_out2;
         state += ntiles;
+        cap = cap2;
     }
     const int64_t first = tile * kTile + (int64_t)threadIdx.x * kItems;
     uint32_t v[kItems];
@@ -296,6 +303,15 @@ __global__ void __launch_bounds__(kThreads) k_scan(In in, int64_t n, uint32_t *o
     __syncthreads();
     const uint32_t tp = tile > 0 ? s_prefix : 0u;
     uint32_t run = op(tp, excl);
+    if (cmp) {
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            if (v[k] != 0u && run < cap) out[run] = (uint32_t)(first + k);
+            run += v[k];
+        }
+        if (total_out && tile == ntiles - 1 && threadIdx.x == 0) *total_out = op(tp, total);
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         const uint32_t x = v[k];
@@ -332,7 +348,8 @@ __global__ void fill_u64(unsigned long long *p, int64_t n) {
 
 template <class In, class Op>
 void scan_any(Ctx &c, In in, uint32_t *out, int64_t n, Op op, bool exclusive, uint32_t *total_dev, In in2 = In{},
-              uint32_t *out2 = nullptr, uint32_t *total_dev2 = nullptr) {
+              uint32_t *out2 = nullptr, uint32_t *total_dev2 = nullptr, int compact = 0, uint32_t cap = 0,
+              uint32_t cap2 = 0) {
     const bool pair = out2 != nullptr;
     if (n <= 0) {
         if (total_dev) hipLaunchKernelGGL(fill_u32, dim3(1), dim3(64), 0, c.stream, total_dev, (int64_t)1, 0u);
@@ -360,7 +377,7 @@ void scan_any(Ctx &c, In in, uint32_t *out, int64_t n, Op op, bool exclusive, ui
     hipLaunchKernelGGL((k_scan<In, Op>), dim3((unsigned)nstate), dim3(kThreads), 0, c.stream, in, n, out, op,
                        exclusive ? 1 : 0, vec, total_dev, ss.state.p, ss.epoch, tiles,
                        c.counters.p + kScanHealthSlot, pair ? in2 : in, pair ? out2 : out,
-                       pair ? total_dev2 : total_dev);
+                       pair ? total_dev2 : total_dev, compact, cap, pair ? cap2 : cap);
     OTF_LAUNCH_CHECK("k_scan");
 }
 
@@ -496,6 +513,15 @@ void scan_exclusive_u32_dev(Ctx &c, const uint32_t *in, uint32_t *out, int64_t n
 
 void scan_exclusive_u32_dev_u8(Ctx &c, const uint8_t *in, uint32_t *out, int64_t n) {
     scan_any(c, in, out, n, AddOp{}, true, out + n);
+}
+
+void scan_compact_u8(Ctx &c, const uint8_t *flags, uint32_t *list, uint32_t cap, uint32_t *total_dev, int64_t n) {
+    scan_any(c, flags, list, n, AddOp{}, true, total_dev, (const uint8_t *)nullptr, nullptr, nullptr, 1, cap, 0u);
+}
+
+void scan_compact_pair_u8(Ctx &c, const uint8_t *a, uint32_t *list_a, uint32_t cap_a, uint32_t *total_a,
+                          const uint8_t *b, uint32_t *list_b, uint32_t cap_b, uint32_t *total_b, int64_t n) {
+    scan_any(c, a, list_a, n, AddOp{}, true, total_a, b, list_b, total_b, 3, cap_a, cap_b);
 }
 
 void sum_parts(Ctx &c, const uint32_t *part, int64_t nblocks, int k, int64_t stride, uint32_t *dst) {
