@@ -57,6 +57,30 @@ __global__ void k_key_table_fine(const uint32_t *key, int64_t L, int shift, uint
     table[b] = (uint32_t)lo;
 }
 
+// The table of a restructured store from the previous store's table (in
+// place): bucket b's old containing leaf j was emitted at remap[j] (its first
+// child if split, the collapsed leaf if it headed a collapse) or removed (an
+// absorbed leaf: the collapsed leaf is the last one emitted before it), and
+// the old leaf after j starts beyond the bucket's first key, so the new
+// containing leaf lies in [remap[j] - 1, remap[j + 1]) (remap[L_old] = L):
+// a search of one or two steps for an unchanged leaf.
+__global__ void k_key_table_remap(const uint32_t *key, int shift, uint32_t nb, const uint32_t *remap,
+                                  uint32_t *table, uint32_t *zero) {
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (zero && b == 0) *zero = 0u;
+    if (b >= nb) return;
+    const uint32_t j = table[b], k = b << shift;
+    const uint32_t r = remap[j];
+    int64_t lo = r > 0 ? (int64_t)r - 1 : 0;
+    int64_t hi = remap[j + 1];
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (key[mid] <= k) lo = mid;
+        else hi = mid;
+    }
+    table[b] = (uint32_t)lo;
+}
+
 // first i with key[i] >= k (k may be the end of the domain)
 __device__ inline int64_t lower_bound(const KeyIndex &ki, uint64_t k, uint64_t domain) {
     if (k >= domain) return ki.L;
@@ -510,7 +534,10 @@ NbrPending search_begin(Ctx &c, const NbrOld &old, bool need_scanned) {
     c.s.nb_m.reserve(6 * L);
     const int shift = std::max(0, 3 * D - 20);
     const uint32_t nb = 1u << (3 * D - shift);
-    if (nb >= 4 * kKeyCoarse) {  // coarse table first (its entries after the fine ones), then the fine one
+    if (old.remap) {  // after a restructure: the previous store's table, remapped
+        hipLaunchKernelGGL(k_key_table_remap, dim3((unsigned)cdiv(nb, kBlk)), dim3(kBlk), 0, c.stream, s.key.p,
+                           shift, nb, old.remap, c.s.key_table.p, c.counters.p + 3);
+    } else if (nb >= 4 * kKeyCoarse) {  // coarse table first (its entries after the fine ones), then the fine one
         const uint32_t nbc = nb / kKeyCoarse;
         c.s.key_table.reserve((size_t)nb + nbc);
         uint32_t *tc = c.s.key_table.p + nb;

@@ -525,7 +525,8 @@ struct NbrOld {  // previous store, for leaves that copy their lists
     const uint8_t *need;      // new leaf: 1 = search its lists, 0 = copy them
     const uint32_t *src;      // new leaf -> old index (kept leaves)
     const uint32_t *off_p, *off_m, *ent_p, *ent_m;
-    const uint32_t *remap;    // old index -> new index of a kept leaf
+    const uint32_t *remap;    // old index -> its emission offset in the new store (the new index of a
+                              // kept leaf), remap[L_old] = L; null for a store built from scratch
     const uint32_t *heavy_p, *heavy_m;  // old leaves with a long + / - list
     uint32_t n_heavy_p, n_heavy_m;
 };
