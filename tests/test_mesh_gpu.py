@@ -175,3 +175,43 @@ def test_evaluation_kernel_timing():
     g.reset_counters(profile=False)
     g.dense_field()
     assert all(v["launches"] == 0 for v in g.profile_read_eval().values())
+
+
+def test_evaluation_at_the_maximum_depth():
+    """Depth 10 (1024^3 finest voxels, the deepest octree the library takes):
+    the field and the vertex set on sampled 24^3 boxes around mesh vertices
+    against the oracle's box forms bit for bit (the triangle count bound of
+    this grid exceeds 32 bits, so the per-row counts are summed in 64 bits
+    before the offsets), and Eq. 7 exactly 0 against the own field. Splitting
+    is off (tau_s = 0): with 4 views much of the domain is unobserved, and the
+    split rule would refine it past the 2^26-leaf limit."""
+    w = synth.sphere_workload(max_depth=10, n_views=4, split_tau=0.0)
+    D = w.max_depth
+    G = 1 << D
+    g = otf.Context(0).build_octree(torch.from_numpy(w.depth).cuda(), w.cams, w.params)
+    g.fuse(2, w.lam, w.tau, w.sigma)
+    lv = g.extract()
+    field = g.dense_field(torch.empty(G ** 3, dtype=torch.float32, device="cuda")).view(G, G, G)
+    xyz, ed = g.mesh(0.0)
+    print(f"depth 10: {lv['keys'].size} leaves, {len(xyz)} triangles", flush=True)
+    assert len(xyz) > 1000
+    ids = ed.reshape(-1)
+    pts = xyz.reshape(-1, 3)
+    vv, ax = ids // 3, ids % 3
+    vx, vy, vz = vv % G, (vv // G) % G, vv // (G * G)
+    rng = np.random.default_rng(10)
+    n = 24
+    for k in rng.choice(ids.size, 3, replace=False):
+        origin = tuple(min(max(0, int(a[k]) - n // 2), G - n) for a in (vx, vy, vz))
+        ox, oy, oz = origin
+        box = om.dense_box(lv["keys"], lv["levels"], lv["u"], D, origin, (n, n, n))
+        assert np.array_equal(field[oz:oz + n, oy:oy + n, ox:ox + n].cpu().numpy(), box)
+        bid, bpos = om.crossing_vertices(box, 0.0, D, origin)
+        inside = ((vx >= ox) & (vx + (ax == 0) < ox + n) & (vy >= oy) & (vy + (ax == 1) < oy + n)
+                  & (vz >= oz) & (vz + (ax == 2) < oz + n))
+        gid, first = np.unique(ids[inside], return_index=True)
+        assert len(bid) > 0
+        assert np.array_equal(gid, bid)
+        assert np.array_equal(pts[inside][first], bpos)
+    assert g.quantisation_error(field.view(-1)) == 0.0
+    g.close()
