@@ -70,6 +70,26 @@ def test_bounds_build_at_the_timed_workload_size():
     d.close()
 
 
+def test_bounds_build_at_the_maximum_depth():
+    """Depth 10, the deepest octree the library takes (30-bit keys, the
+    coupling tables' deepest levels; splitting off, since with 4 views the
+    split rule would refine the unobserved space past the leaf limit): 4
+    iterations with joins and the paper's gradient descent for 2 under the
+    checked build report no index and give the default build's state."""
+    w = synth.sphere_workload(max_depth=10, n_views=4, split_tau=0.0)
+    depth = torch.from_numpy(w.depth).cuda()
+    g = _bounds_ctx().build_octree(depth, w.cams, w.params)
+    d = otf.Context(0).build_octree(depth, w.cams, w.params)
+    for c in (g, d):
+        c.fuse(4, w.lam, w.tau, w.sigma)
+        c.fuse_gd(2, 0.5, 0.05, 0.3)
+    print(f"depth 10: {d.num_leaves()} leaves, last split/join {d.last_counts()}", flush=True)
+    assert g.num_leaves() == d.num_leaves()
+    assert g.export_state() == d.export_state()
+    g.close()
+    d.close()
+
+
 def test_bounds_build_reports_a_bad_index():
     # no restructuring: only the sweeps (which check and redirect) read the
     # corrupted entry
