@@ -253,6 +253,19 @@ otf_status otf_debug_fail_allocations(otf_ctx *ctx, int64_t after);
  * OTF_E_STATE. */
 otf_status otf_debug_corrupt_adjacency(otf_ctx *ctx, int64_t leaf);
 
+/* Test hook of the bounds-checked build, where every device buffer is followed
+ * by a guard zone of known bytes (checked when the buffer is freed and after
+ * every call on a context: a changed byte fails that call with OTF_E_DEVICE,
+ * naming where the buffer was reserved), and every adjacency slot is checked
+ * after each neighbour search (one that no search wrote, or that holds an
+ * index past the last leaf or a level past the maximum depth, fails the call
+ * the same way). Changes one byte of the guard zone after the current +
+ * adjacency list, so that the next call on the context must report it. The
+ * default build rejects it with OTF_E_INVALID and changes nothing. Errors:
+ * OTF_E_INVALID (null, default build), OTF_E_STATE (no octree),
+ * OTF_E_DEVICE. */
+otf_status otf_debug_poke_guard(otf_ctx *ctx);
+
 /* Message of the last failure on this context (empty if none). Valid until the
  * next call on the context. */
 const char *otf_last_error(const otf_ctx *ctx);

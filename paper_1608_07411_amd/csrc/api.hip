@@ -2,12 +2,86 @@
 // state blob, inspection copies, and the iteration driver.
 #include <cmath>
 #include <new>
+#ifdef OTF_DEBUG_BOUNDS
+#include <map>
+#include <mutex>
+#endif
 
 #include "otf_internal.h"
 
 namespace otf {
 
 void fail(otf_status st, const std::string &msg) { throw Failure{st, msg}; }
+
+#ifdef OTF_DEBUG_BOUNDS
+namespace {
+struct GuardSite {
+    size_t bytes;
+    const char *file;
+    int line;
+    bool reported;  // damage already reported (each zone once)
+};
+// live buffers of every context (never destroyed: buffers may be freed at exit)
+std::map<uintptr_t, GuardSite> &guard_table() {
+    static auto *t = new std::map<uintptr_t, GuardSite>();
+    return *t;
+}
+std::mutex &guard_mutex() {
+    static auto *m = new std::mutex();
+    return *m;
+}
+std::string g_guard_err;  // the first damaged zone not yet reported
+
+void guard_inspect(uintptr_t p, GuardSite &g, const char *when) {
+    if (g.reported) return;
+    std::vector<uint8_t> h(kGuardBytes);
+    if (hipMemcpy(h.data(), reinterpret_cast<const char *>(p) + g.bytes, kGuardBytes, hipMemcpyDeviceToHost) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    for (size_t k = 0; k < kGuardBytes; ++k)
+        if (h[k] != kGuardByte) {
+            if (g_guard_err.empty()) {
+                const char *f = std::strrchr(g.file, '/');
+                g_guard_err = "write past the end of a device buffer (bounds-checked build): " +
+                              std::to_string(g.bytes) + " bytes reserved at " + (f ? f + 1 : g.file) + ":" +
+                              std::to_string(g.line) + ", guard byte " + std::to_string(k) + " changed, found " +
+                              when;
+            }
+            g.reported = true;
+            return;
+        }
+}
+}  // namespace
+
+void guard_register(void *p, size_t bytes, const char *file, int line) {
+    OTF_HIP(hipMemset(static_cast<char *>(p) + bytes, kGuardByte, kGuardBytes));
+    OTF_HIP(hipDeviceSynchronize());
+    std::lock_guard<std::mutex> lk(guard_mutex());
+    guard_table()[reinterpret_cast<uintptr_t>(p)] = GuardSite{bytes, file, line, false};
+}
+
+void guard_release(void *p) {
+    (void)hipDeviceSynchronize();  // as hipFree: the buffer's last users have finished
+    std::lock_guard<std::mutex> lk(guard_mutex());
+    auto it = guard_table().find(reinterpret_cast<uintptr_t>(p));
+    if (it == guard_table().end()) return;
+    guard_inspect(it->first, it->second, "when it was freed");
+    guard_table().erase(it);
+}
+
+void guard_check_all() {
+    OTF_HIP(hipDeviceSynchronize());
+    std::string err;
+    {
+        std::lock_guard<std::mutex> lk(guard_mutex());
+        for (auto &kv : guard_table()) guard_inspect(kv.first, kv.second, "after the call");
+        err.swap(g_guard_err);
+    }
+    if (!err.empty()) fail(OTF_E_DEVICE, err);
+}
+#endif
 
 void hip_check(hipError_t e, const char *what) {
     if (e != hipSuccess) {
@@ -289,6 +363,9 @@ otf_status guard(otf_ctx *ctx, bool invalidates, F &&f) {
     };
     try {
         f();
+#ifdef OTF_DEBUG_BOUNDS
+        guard_check_all();
+#endif
         if (ctx) ctx->c.err.clear();
         return OTF_OK;
     } catch (const Failure &e) {
@@ -914,6 +991,29 @@ otf_status otf_debug_corrupt_adjacency(otf_ctx *ctx, int64_t leaf) {
 #else
     (void)leaf;
     if (ctx) ctx->c.err = "only the bounds-checked build corrupts an adjacency entry";
+    return OTF_E_INVALID;
+#endif
+}
+
+otf_status otf_debug_poke_guard(otf_ctx *ctx) {
+#ifdef OTF_DEBUG_BOUNDS
+    if (!ctx) return OTF_E_INVALID;
+    if (!ctx->c.valid) return OTF_E_STATE;
+    // not through guard(): the damage is for the next call to find
+    LeafStore &s = ctx->c.lv();
+    if (hipSetDevice(ctx->c.device) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        (void)hipGetLastError();
+        return OTF_E_DEVICE;
+    }
+    const uint8_t b = (uint8_t)(kGuardByte ^ 0xFF);
+    char *zone = reinterpret_cast<char *>(s.nbp.p) + s.nbp.n * sizeof(uint32_t);
+    if (hipMemcpy(zone + 3, &b, 1, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        return OTF_E_DEVICE;
+    }
+    return OTF_OK;
+#else
+    if (ctx) ctx->c.err = "only the bounds-checked build has guard zones";
     return OTF_E_INVALID;
 #endif
 }

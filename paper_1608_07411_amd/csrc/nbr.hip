@@ -507,6 +507,50 @@ unsigned grid8(int64_t L) { return (unsigned)std::min<int64_t>(cdiv(8 * L, kBlk)
 // list), with room for p.cap long ranges; starts the read-back of their number.
 // The long-range counter is cleared here when `clear` (else by the key table
 // launch just before); the pass clears the long-list counters of k_heavy_lists.
+#ifdef OTF_DEBUG_BOUNDS
+// Bounds-checked build: the lists are filled with kUnwritten before the fill
+// kernels, and afterwards every slot must hold an entry of a leaf at a level
+// up to D. bad[0] counts the bad slots, bad[1] keeps the smallest, bad[2] the
+// value of a bad slot (of the smallest unless two race).
+constexpr uint32_t kUnwritten = 0xFFFFFFFFu;
+__global__ void k_adj_mark(int64_t n, uint32_t *ent, uint32_t *bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) ent[i] = kUnwritten;
+    if (i == 0) {
+        bad[0] = 0;
+        bad[1] = 0xFFFFFFFFu;
+        bad[2] = 0;
+    }
+}
+__global__ void k_adj_check(int64_t n, const uint32_t *ent, int64_t L, int D, uint32_t *bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t v = ent[i];
+    if (v == kUnwritten || (int64_t)(v & kIdxMask) >= L || (int)(v >> (kIdxBits + 2)) > D) {
+        atomicAdd(bad, 1u);
+        if (atomicMin(bad + 1, (uint32_t)i) > (uint32_t)i) atomicExch(bad + 2, v);
+    }
+}
+void adj_mark(Ctx &c, int64_t n, uint32_t *ent, uint32_t *bad) {
+    hipLaunchKernelGGL(k_adj_mark, dim3((unsigned)cdiv(std::max<int64_t>(n, 1), kBlk)), dim3(kBlk), 0, c.stream, n,
+                       ent, bad);
+    OTF_LAUNCH_CHECK("k_adj_mark");
+}
+void adj_check(Ctx &c, const char *side, int64_t n, const uint32_t *ent, uint32_t *bad) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_adj_check, dim3((unsigned)cdiv(n, kBlk)), dim3(kBlk), 0, c.stream, n, ent, c.L,
+                           c.prm.max_depth, bad);
+    OTF_LAUNCH_CHECK("k_adj_check");
+    uint32_t h[3];
+    OTF_HIP(hipMemcpyAsync(h, bad, sizeof h, hipMemcpyDeviceToHost, c.stream));
+    OTF_HIP(hipStreamSynchronize(c.stream));
+    if (h[0])
+        fail(OTF_E_DEVICE, std::string("adjacency check (bounds-checked build): ") + std::to_string(h[0]) + " of " +
+                               std::to_string(n) + " " + side + " slots bad, the first " + std::to_string(h[1]) +
+                               (h[2] == kUnwritten ? ", written by no search" : ", one holds " + std::to_string(h[2])));
+}
+#endif
+
 uint32_t count_pass(Ctx &c, NbrPending &p, bool clear) {
     LeafStore &s = c.lv();
     c.s.hv_leaf.reserve(p.cap);
@@ -633,6 +677,11 @@ void search_end(Ctx &c, NbrPending &p, void (*overlap)(Ctx &)) {
     s.n_heavy_m = c.h_counters[15];
     s.nbp.reserve(s.n_nbp);
     s.nbm.reserve(s.n_nbm);
+#ifdef OTF_DEBUG_BOUNDS
+    c.s.adj_bad.reserve(6);
+    adj_mark(c, s.n_nbp, s.nbp.p, c.s.adj_bad.p);
+    adj_mark(c, s.n_nbm, s.nbm.p, c.s.adj_bad.p + 3);
+#endif
     if (old.need) {
         const int64_t n_long = (int64_t)old.n_heavy_p + old.n_heavy_m;
         const int64_t lb = cdiv(n_long * 64, kBlk);
@@ -647,6 +696,10 @@ void search_end(Ctx &c, NbrPending &p, void (*overlap)(Ctx &)) {
                        (const uint32_t *)s.nbm_off.p, s.nbp.p, s.nbm.p, p.dirty, p.n_dirty_dev, L,
                        (const uint32_t *)c.s.nb_j.p, (const uint32_t *)c.s.nb_m.p);
     OTF_LAUNCH_CHECK("k_nbr_fill");
+#ifdef OTF_DEBUG_BOUNDS
+    adj_check(c, "+", s.n_nbp, s.nbp.p, c.s.adj_bad.p);
+    adj_check(c, "-", s.n_nbm, s.nbm.p, c.s.adj_bad.p + 3);
+#endif
 }
 
 }  // namespace

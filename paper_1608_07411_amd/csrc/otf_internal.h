@@ -48,6 +48,24 @@ void hip_check(hipError_t e, const char *what);
 // ---------------------------------------------------------------------------
 // device buffer (hipMalloc / hipFree), grows on demand
 // ---------------------------------------------------------------------------
+#ifdef OTF_DEBUG_BOUNDS
+// Bounds-checked build: every buffer is followed by a guard zone of
+// kGuardBytes filled with kGuardByte, registered with the place that reserved
+// it. A zone is checked when its buffer is freed and after every call on a
+// context (guard_check_all); a changed byte means a write past the end of the
+// buffer, and the call fails naming the buffer's reserve site.
+constexpr size_t kGuardBytes = 65536;
+constexpr uint8_t kGuardByte = 0xA5;
+void guard_register(void *p, size_t bytes, const char *file, int line);
+void guard_release(void *p);
+void guard_check_all();
+#define OTF_RESERVE_SITE , const char *site_file = __builtin_FILE(), int site_line = __builtin_LINE()
+constexpr size_t kGuardAlloc = kGuardBytes;
+#else
+#define OTF_RESERVE_SITE
+constexpr size_t kGuardAlloc = 0;
+#endif
+
 template <class T>
 struct DBuf {
     T *p = nullptr;
@@ -57,25 +75,33 @@ struct DBuf {
     DBuf &operator=(const DBuf &) = delete;
     ~DBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) {
+#ifdef OTF_DEBUG_BOUNDS
+            guard_release(p);
+#endif
+            (void)hipFree(p);
+        }
         p = nullptr;
         n = 0;
     }
     // ensure capacity for `count` elements; contents are discarded on growth,
     // which leaves a quarter of headroom so that slowly growing sizes do not
     // reallocate (and synchronise) on every call
-    void reserve(size_t count) {
+    void reserve(size_t count OTF_RESERVE_SITE) {
         if (count <= n && p) return;
         release();
         size_t c = count ? count + count / 4 + 64 : 1;
         if (alloc_fault_due()) fail(OTF_E_NOMEM, "device allocation failed (injected)");
-        hipError_t e = hipMalloc((void **)&p, c * sizeof(T));
+        hipError_t e = hipMalloc((void **)&p, c * sizeof(T) + kGuardAlloc);
         if (e != hipSuccess) {
             p = nullptr;
             (void)hipGetLastError();
             fail(OTF_E_NOMEM, "hipMalloc of " + std::to_string(c * sizeof(T)) + " bytes failed");
         }
         n = c;
+#ifdef OTF_DEBUG_BOUNDS
+        guard_register(p, c * sizeof(T), site_file, site_line);
+#endif
     }
     void swap(DBuf &o) {
         std::swap(p, o.p);
@@ -303,6 +329,7 @@ struct ScanState {
 // Scratch reused across phases.
 struct Scratch {
     DBuf<uint32_t> a, b, c, d, e, f, g;
+    DBuf<uint32_t> adj_bad;  // adjacency check of the bounds-checked build
     DBuf<uint8_t> u8a, u8b;
     DBuf<float> fa, fb, fc, fd, fe;
     ScanState scan;

@@ -67,6 +67,7 @@ def lib(path: str = LIB_PATH):
             "otf_energy_noalloc": [P, P, P],
             "otf_debug_fail_allocations": [P, C.c_int64],
             "otf_debug_corrupt_adjacency": [P, C.c_int64],
+            "otf_debug_poke_guard": [P],
             "otf_fuse_gd": [P, I32, C.c_float, C.c_float, C.c_float],
             "otf_dense_field": [P, P, I32, I64],
             "otf_mesh": [P, C.c_float, I64, P, P, P],
@@ -407,6 +408,10 @@ class Context:
     def debug_corrupt_adjacency(self, leaf: int):
         """Test hook of the bounds-checked build: point leaf's first + entry past the last leaf."""
         self._check(self._lib.otf_debug_corrupt_adjacency(self.h, int(leaf)), "otf_debug_corrupt_adjacency")
+
+    def debug_poke_guard(self):
+        """Test hook of the bounds-checked build: damage the guard zone after the + adjacency list."""
+        self._check(self._lib.otf_debug_poke_guard(self.h), "otf_debug_poke_guard")
 
     def energy_noalloc(self):
         """otf_energy without device allocation (static library scratch)."""

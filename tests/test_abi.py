@@ -66,6 +66,7 @@ def test_null_context_is_invalid_before_any_device_work():
         "otf_warm_start_guarded": (None, None, 0.5, 1, None, None, None),
         "otf_export_state": (None, None, 0, None),
         "otf_selftest_scan": (None, 0, 0, None),
+        "otf_debug_poke_guard": (None,),
     }
     for name, args in calls.items():
         assert getattr(L, name)(*args) == 1, name

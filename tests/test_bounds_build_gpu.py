@@ -1,11 +1,14 @@
 """The bounds-checked build (libotf_bounds.so, OTF_DEBUG_BOUNDS): the sweeps
 check every adjacency range, neighbour index, level code and observation
-index they read. On valid states it must report nothing and give the same
-results as the oracle bit for bit (sphere workload with split/join, long
-adjacency lists); an entry pointed past the last leaf from the host (a test
-hook of that build only) must be reported as OTF_E_DEVICE, with the bad read
-sent to index 0 so that every kernel still ends normally. The default build
-refuses the hook."""
+index they read; every device buffer is followed by a guard zone checked when
+the buffer is freed and after every call; every adjacency slot is checked
+after each neighbour search (written, neighbour index and level in range). On
+valid states it must report nothing and give the same results as the oracle
+bit for bit (sphere workload with split/join, long adjacency lists); an entry
+pointed past the last leaf from the host (a test hook of that build only) must
+be reported as OTF_E_DEVICE, with the bad read sent to index 0 so that every
+kernel still ends normally, and so must a guard byte changed from the host.
+The default build refuses both hooks."""
 from __future__ import annotations
 
 import numpy as np
@@ -110,4 +113,28 @@ def test_bounds_build_reports_a_bad_index():
         d.debug_corrupt_adjacency(leaf)
     assert e.value.status == 1
     assert d.export_state() == before
+    d.close()
+
+
+def test_bounds_build_reports_a_damaged_guard_zone():
+    """One byte changed from the host in the guard zone after the + adjacency
+    list: the next call fails with OTF_E_DEVICE and names the place that
+    reserved the list; the default build refuses the hook."""
+    w = synth.sphere_workload(max_depth=5, n_views=4, W=80, H=60, f=75.0, restructure_every=0)
+    g = _bounds_ctx().build_octree(w.depth, w.cams, w.params)
+    g.fuse(1, w.lam, w.tau, w.sigma)
+    g.debug_poke_guard()
+    with pytest.raises(otf.OtfError) as e:
+        g.fuse(1, w.lam, w.tau, w.sigma)
+    assert e.value.status == 4
+    assert "past the end of a device buffer" in str(e.value) and "nbr.hip" in str(e.value)
+    g.close()
+    # the zone was reported once: a new context on the checked build runs clean
+    h = _bounds_ctx().build_octree(w.depth, w.cams, w.params)
+    h.fuse(2, w.lam, w.tau, w.sigma)
+    h.close()
+    d = otf.Context(0).build_octree(w.depth, w.cams, w.params)
+    with pytest.raises(otf.OtfError) as e:
+        d.debug_poke_guard()
+    assert e.value.status == 1
     d.close()
