@@ -181,6 +181,30 @@ otf_status otf_energy(otf_ctx *ctx, double *tv, double *data);
  * leaves than the array holds), OTF_E_DEVICE. */
 otf_status otf_energy_noalloc(otf_ctx *ctx, double *tv, double *data);
 
+/* Per-iteration metrics: the state after one iteration of otf_fuse or
+ * otf_fuse_gd, the measures the paper tracks over its runs (the leaf count
+ * of Fig. 9, the split and join counts of section 3.3, the energy of Eq. 3). */
+typedef struct otf_iter_record {
+    int64_t iteration; /* the context's iteration count after it */
+    int64_t leaves;    /* leaves after its restructure */
+    int64_t splits;    /* leaves split by its restructure (0 without one) */
+    int64_t joins;     /* collapses of its restructure (0 without one) */
+    double tv, data;   /* as otf_energy, of the state after it */
+} otf_iter_record;
+
+/* Arms the per-iteration log: after every iteration of later otf_fuse /
+ * otf_fuse_gd calls whose iteration count is a multiple of k, one record is
+ * written to records[n] (host memory owned by the caller, which must stay
+ * valid while armed) and n is counted up, until n reaches capacity. Each
+ * record costs one energy reduction and a synchronisation; while armed, the
+ * solver calls do not replay recorded graphs. A new call restarts n at 0;
+ * k = 0 or capacity = 0 disarms. Errors: OTF_E_INVALID (null context, k < 0,
+ * capacity < 0, null records with k and capacity above 0). */
+otf_status otf_log_every(otf_ctx *ctx, int32_t k, otf_iter_record *records, int64_t capacity);
+
+/* Records written since the log was armed. Errors: OTF_E_INVALID (null). */
+otf_status otf_log_count(const otf_ctx *ctx, int64_t *n);
+
 /* Splits and joins made by the last restructuring step of the last fuse. */
 otf_status otf_last_counts(const otf_ctx *ctx, int64_t *splits, int64_t *joins);
 

@@ -588,7 +588,19 @@ int fuse_frozen(Ctx &c, int iterations, float sigma, float tau, float tl) {
 }
 
 bool graph_replay_applies(const Ctx &c, int iterations) {
-    return c.prm.restructure_every == 0 && !c.prof && iterations > 2 * kFuseGraphChunk;
+    return c.prm.restructure_every == 0 && !c.prof && c.log_every == 0 && iterations > 2 * kFuseGraphChunk;
+}
+
+// the per-iteration record of the state after an iteration (otf_log_every)
+void log_iteration(Ctx &c) {
+    if (c.log_every <= 0 || c.iteration % c.log_every != 0 || c.log_n >= c.log_cap) return;
+    otf_iter_record r{};
+    r.iteration = c.iteration;
+    r.leaves = c.L;
+    r.splits = c.last_splits;
+    r.joins = c.last_joins;
+    energy(c, &r.tv, &r.data);
+    c.log_buf[c.log_n++] = r;
 }
 }  // namespace
 
@@ -633,10 +645,27 @@ otf_status otf_fuse(otf_ctx *ctx, int32_t iterations, float lambda, float tau, f
             } else {
                 prof_mark(c, -1);
             }
+            log_iteration(c);
         }
         c.prof_open = nullptr;
         finish(c);  // synchronises and checks the scan health flag
     });
+}
+
+otf_status otf_log_every(otf_ctx *ctx, int32_t k, otf_iter_record *records, int64_t capacity) {
+    if (!ctx || k < 0 || capacity < 0 || (k > 0 && capacity > 0 && !records)) return OTF_E_INVALID;
+    Ctx &c = ctx->c;
+    c.log_every = capacity > 0 ? k : 0;
+    c.log_buf = c.log_every > 0 ? records : nullptr;
+    c.log_cap = c.log_every > 0 ? capacity : 0;
+    c.log_n = 0;
+    return OTF_OK;
+}
+
+otf_status otf_log_count(const otf_ctx *ctx, int64_t *n) {
+    if (!ctx || !n) return OTF_E_INVALID;
+    *n = ctx->c.log_n;
+    return OTF_OK;
 }
 
 otf_status otf_fuse_gd(otf_ctx *ctx, int32_t iterations, float lambda, float step, float epsilon) {
@@ -680,6 +709,7 @@ otf_status otf_fuse_gd(otf_ctx *ctx, int32_t iterations, float lambda, float ste
             } else {
                 prof_mark(c, -1);
             }
+            log_iteration(c);
         }
         c.prof_open = nullptr;
         c.sol = Solver{};

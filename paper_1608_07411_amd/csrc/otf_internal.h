@@ -394,6 +394,11 @@ struct Ctx {
     // `stream`), and how many iterations of the last fuse call were replayed
     hipStream_t capture = nullptr;
     int64_t graph_iterations = 0;
+    // per-iteration log (otf_log_every): every log_every-th iteration appends
+    // a record to the caller's host array while log_n < log_cap
+    int32_t log_every = 0;
+    otf_iter_record *log_buf = nullptr;
+    int64_t log_cap = 0, log_n = 0;
     otf_params prm{};
     int n_views = 0;
     int64_t iteration = 0;

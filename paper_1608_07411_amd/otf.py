@@ -25,6 +25,11 @@ PARAMS_DTYPE = np.dtype([
     ("restructure_every", "<i4"), ("max_leaves", "<i8"),
 ])
 
+# otf_iter_record: one per logged iteration (otf_log_every)
+ITER_RECORD_DTYPE = np.dtype([
+    ("iteration", "<i8"), ("leaves", "<i8"), ("splits", "<i8"), ("joins", "<i8"), ("tv", "<f8"), ("data", "<f8"),
+])
+
 STATUS = {0: "OTF_OK", 1: "OTF_E_INVALID", 2: "OTF_E_NOMEM", 3: "OTF_E_CAPACITY", 4: "OTF_E_DEVICE",
           5: "OTF_E_STATE"}
 PROFILE_KINDS = ("dual", "primal", "restructure", "energy")
@@ -68,6 +73,8 @@ def lib(path: str = LIB_PATH):
             "otf_debug_fail_allocations": [P, C.c_int64],
             "otf_debug_corrupt_adjacency": [P, C.c_int64],
             "otf_debug_poke_guard": [P],
+            "otf_log_every": [P, C.c_int32, P, C.c_int64],
+            "otf_log_count": [P, P],
             "otf_fuse_gd": [P, I32, C.c_float, C.c_float, C.c_float],
             "otf_dense_field": [P, P, I32, I64],
             "otf_mesh": [P, C.c_float, I64, P, P, P],
@@ -408,6 +415,19 @@ class Context:
     def debug_corrupt_adjacency(self, leaf: int):
         """Test hook of the bounds-checked build: point leaf's first + entry past the last leaf."""
         self._check(self._lib.otf_debug_corrupt_adjacency(self.h, int(leaf)), "otf_debug_corrupt_adjacency")
+
+    def log_every(self, k: int, capacity: int):
+        """Arm the per-iteration log (every k-th iteration, up to capacity records)."""
+        self._log = np.zeros(max(int(capacity), 0), ITER_RECORD_DTYPE)
+        ptr = self._log.ctypes.data if self._log.size else None
+        self._check(self._lib.otf_log_every(self.h, int(k), ptr, int(capacity)), "otf_log_every")
+        return self
+
+    def log(self):
+        """The records written since log_every (a structured array)."""
+        n = C.c_int64(0)
+        self._check(self._lib.otf_log_count(self.h, C.byref(n)), "otf_log_count")
+        return self._log[: n.value].copy()
 
     def debug_poke_guard(self):
         """Test hook of the bounds-checked build: damage the guard zone after the + adjacency list."""

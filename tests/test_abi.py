@@ -46,6 +46,7 @@ def test_record_layouts():
     assert otf.PARAMS_DTYPE.itemsize == 40
     import oracle
     assert oracle.PARAMS_DTYPE == otf.PARAMS_DTYPE
+    assert otf.ITER_RECORD_DTYPE.itemsize == 48
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libotf.so not built")
@@ -67,6 +68,8 @@ def test_null_context_is_invalid_before_any_device_work():
         "otf_export_state": (None, None, 0, None),
         "otf_selftest_scan": (None, 0, 0, None),
         "otf_debug_poke_guard": (None,),
+        "otf_log_every": (None, 1, None, 0),
+        "otf_log_count": (None, None),
     }
     for name, args in calls.items():
         assert getattr(L, name)(*args) == 1, name
