@@ -290,6 +290,14 @@ otf_status otf_debug_corrupt_adjacency(otf_ctx *ctx, int64_t leaf);
  * OTF_E_DEVICE. */
 otf_status otf_debug_poke_guard(otf_ctx *ctx);
 
+/* Test hook of the bounds-checked build: the next neighbour search (a build,
+ * an import, or the restructure of a solver call) leaves the first + slot as
+ * if no search had written it, so that its adjacency check must fail that
+ * call with OTF_E_DEVICE before any kernel reads the slot. The default build
+ * rejects it with OTF_E_INVALID and changes nothing. Errors: OTF_E_INVALID
+ * (null, default build), OTF_E_STATE (no octree). */
+otf_status otf_debug_unwritten_slot(otf_ctx *ctx);
+
 /* Message of the last failure on this context (empty if none). Valid until the
  * next call on the context. */
 const char *otf_last_error(const otf_ctx *ctx);

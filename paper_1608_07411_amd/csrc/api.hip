@@ -1048,6 +1048,18 @@ otf_status otf_debug_poke_guard(otf_ctx *ctx) {
 #endif
 }
 
+otf_status otf_debug_unwritten_slot(otf_ctx *ctx) {
+#ifdef OTF_DEBUG_BOUNDS
+    if (!ctx) return OTF_E_INVALID;
+    if (!ctx->c.valid) return OTF_E_STATE;
+    ctx->c.debug_unwritten_slot = true;
+    return OTF_OK;
+#else
+    if (ctx) ctx->c.err = "only the bounds-checked build checks the adjacency slots";
+    return OTF_E_INVALID;
+#endif
+}
+
 otf_status otf_debug_fail_allocations(otf_ctx *ctx, int64_t after) {
     if (!ctx || after < 0) return OTF_E_INVALID;
     ctx->c.fail_alloc_after = after;

@@ -697,6 +697,12 @@ void search_end(Ctx &c, NbrPending &p, void (*overlap)(Ctx &)) {
                        (const uint32_t *)c.s.nb_j.p, (const uint32_t *)c.s.nb_m.p);
     OTF_LAUNCH_CHECK("k_nbr_fill");
 #ifdef OTF_DEBUG_BOUNDS
+    if (c.debug_unwritten_slot && s.n_nbp > 0) {  // test hook: as if no search had written + slot 0
+        c.debug_unwritten_slot = false;
+        const uint32_t m = kUnwritten;
+        OTF_HIP(hipMemcpyAsync(s.nbp.p, &m, sizeof m, hipMemcpyHostToDevice, c.stream));
+        OTF_HIP(hipStreamSynchronize(c.stream));
+    }
     adj_check(c, "+", s.n_nbp, s.nbp.p, c.s.adj_bad.p);
     adj_check(c, "-", s.n_nbm, s.nbm.p, c.s.adj_bad.p + 3);
 #endif

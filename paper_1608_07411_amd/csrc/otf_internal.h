@@ -396,6 +396,7 @@ struct Ctx {
     int64_t graph_iterations = 0;
     // per-iteration log (otf_log_every): every log_every-th iteration appends
     // a record to the caller's host array while log_n < log_cap
+    bool debug_unwritten_slot = false;  // checked build: the next search leaves + slot 0 unwritten
     int32_t log_every = 0;
     otf_iter_record *log_buf = nullptr;
     int64_t log_cap = 0, log_n = 0;

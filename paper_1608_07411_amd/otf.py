@@ -73,6 +73,7 @@ def lib(path: str = LIB_PATH):
             "otf_debug_fail_allocations": [P, C.c_int64],
             "otf_debug_corrupt_adjacency": [P, C.c_int64],
             "otf_debug_poke_guard": [P],
+            "otf_debug_unwritten_slot": [P],
             "otf_log_every": [P, C.c_int32, P, C.c_int64],
             "otf_log_count": [P, P],
             "otf_fuse_gd": [P, I32, C.c_float, C.c_float, C.c_float],
@@ -428,6 +429,10 @@ class Context:
         n = C.c_int64(0)
         self._check(self._lib.otf_log_count(self.h, C.byref(n)), "otf_log_count")
         return self._log[: n.value].copy()
+
+    def debug_unwritten_slot(self):
+        """Test hook of the bounds-checked build: the next neighbour search leaves + slot 0 unwritten."""
+        self._check(self._lib.otf_debug_unwritten_slot(self.h), "otf_debug_unwritten_slot")
 
     def debug_poke_guard(self):
         """Test hook of the bounds-checked build: damage the guard zone after the + adjacency list."""

@@ -68,6 +68,7 @@ def test_null_context_is_invalid_before_any_device_work():
         "otf_export_state": (None, None, 0, None),
         "otf_selftest_scan": (None, 0, 0, None),
         "otf_debug_poke_guard": (None,),
+        "otf_debug_unwritten_slot": (None,),
         "otf_log_every": (None, 1, None, 0),
         "otf_log_count": (None, None),
     }

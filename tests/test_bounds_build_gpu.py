@@ -7,8 +7,9 @@ valid states it must report nothing and give the same results as the oracle
 bit for bit (sphere workload with split/join, long adjacency lists); an entry
 pointed past the last leaf from the host (a test hook of that build only) must
 be reported as OTF_E_DEVICE, with the bad read sent to index 0 so that every
-kernel still ends normally, and so must a guard byte changed from the host.
-The default build refuses both hooks."""
+kernel still ends normally, and so must a guard byte changed from the host
+and an adjacency slot left as no search had written it. The default build
+refuses the hooks."""
 from __future__ import annotations
 
 import numpy as np
@@ -136,5 +137,27 @@ def test_bounds_build_reports_a_damaged_guard_zone():
     d = otf.Context(0).build_octree(w.depth, w.cams, w.params)
     with pytest.raises(otf.OtfError) as e:
         d.debug_poke_guard()
+    assert e.value.status == 1
+    d.close()
+
+
+def test_bounds_build_reports_an_unwritten_adjacency_slot():
+    """The next neighbour search (the restructure of the next solver call)
+    leaves + slot 0 unwritten: its adjacency check fails that call with
+    OTF_E_DEVICE before any sweep reads the slot; the default build refuses
+    the hook."""
+    w = synth.sphere_workload(max_depth=5, n_views=4, W=80, H=60, f=75.0)
+    g = _bounds_ctx().build_octree(w.depth, w.cams, w.params)
+    g.fuse(1, w.lam, w.tau, w.sigma)
+    g.debug_unwritten_slot()
+    with pytest.raises(otf.OtfError) as e:
+        for _ in range(20):  # until a restructure searches again
+            g.fuse(1, w.lam, w.tau, w.sigma)
+    assert e.value.status == 4
+    assert "adjacency check" in str(e.value) and "written by no search" in str(e.value)
+    g.close()
+    d = otf.Context(0).build_octree(w.depth, w.cams, w.params)
+    with pytest.raises(otf.OtfError) as e:
+        d.debug_unwritten_slot()
     assert e.value.status == 1
     d.close()
