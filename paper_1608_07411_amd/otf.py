@@ -477,8 +477,9 @@ class Batch:
     """Many contexts swept by the same launches (otf_batch). Members stay owned
     by the caller and must outlive the batch."""
 
-    def __init__(self, device: int = 0, stream=None):
-        self._lib = lib()
+    def __init__(self, device: int = 0, stream=None, library: str = LIB_PATH):
+        # members must come from the same build (library) as the batch
+        self._lib = lib(library)
         self.h = C.c_void_p()
         self.members = []
         st = self._lib.otf_batch_create(device, _stream_handle(stream), C.byref(self.h))

@@ -161,3 +161,31 @@ def test_bounds_build_reports_an_unwritten_adjacency_slot():
         d.debug_unwritten_slot()
     assert e.value.status == 1
     d.close()
+
+
+def test_bounds_build_batch_reports_nothing_and_matches_solo_runs():
+    """The batched sweeps under the checked build (members of uneven depth,
+    split/join every iteration, through the autotuner's iterations and eager
+    ones; then frozen members through graph replays): no index is reported,
+    no guard zone or adjacency slot is bad, and every member equals its solo
+    run on the default build."""
+    from tests.helpers import TAU32
+    for every, steps in ((1, (5, 6, 3)), (0, (9, 40))):
+        ws = [synth.sphere_workload(seed=k, max_depth=D, n_views=V, W=80, H=60, f=75.0, restructure_every=every)
+              for k, (D, V) in enumerate([(4, 3), (5, 4), (6, 2)])]
+        solo = [otf.Context(0).build_octree(w.depth, w.cams, w.params) for w in ws]
+        members = [_bounds_ctx().build_octree(w.depth, w.cams, w.params) for w in ws]
+        batch = otf.Batch(0, library=otf.BOUNDS_LIB_PATH)
+        for m in members:
+            batch.add(m)
+        for n in steps:
+            for c in solo:
+                c.fuse(n, 0.5, TAU32, TAU32)
+            batch.fuse(n, 0.5, TAU32, TAU32)
+            for a, b in zip(solo, members):
+                assert a.export_state() == b.export_state() and a.last_counts() == b.last_counts()
+        if every == 0:
+            assert batch.config()["graph_iterations"] > 0
+        batch.close()
+        for c in solo + members:
+            c.close()
